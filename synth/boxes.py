@@ -1,0 +1,54 @@
+"""Seeded oriented boxes.
+
+A box is (center[3], axes[3][3], half[3]); row k of ``axes`` is the unit local
+axis k in world coordinates (right handed).  Packed as 15 float32 values in the
+order center, axes (row major), half -- the layout of ``obbv_box``.
+"""
+import numpy as np
+
+
+def quat_to_axes(q):
+    """Rotation of a unit quaternion (x, y, z, w); returns axes with rows = R[:, k]."""
+    x, y, z, w = (float(t) for t in q)
+    R = np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+    return R.T.copy()
+
+
+def _uniform_quaternions(rng, n):
+    """Uniform random unit quaternions (Shoemake, Graphics Gems III, 1992)."""
+    u1, u2, u3 = rng.uniform(size=(3, n))
+    a, b = np.sqrt(1.0 - u1), np.sqrt(u1)
+    return np.stack([a * np.sin(2 * np.pi * u2), a * np.cos(2 * np.pi * u2),
+                     b * np.sin(2 * np.pi * u3), b * np.cos(2 * np.pi * u3)], axis=-1)
+
+
+def random_boxes(n, seed, center_range=1.2, half_range=(0.1, 0.8)):
+    """n boxes: centers U[-c, c]^3, half extents U[lo, hi]^3, uniform rotations.
+
+    Returns float32 arrays center [n,3], axes [n,3,3], half [n,3].
+    """
+    rng = np.random.default_rng(seed)
+    center = rng.uniform(-center_range, center_range, size=(n, 3))
+    half = rng.uniform(half_range[0], half_range[1], size=(n, 3))
+    qs = _uniform_quaternions(rng, n)
+    axes = np.stack([quat_to_axes(q) for q in qs]) if n else np.zeros((0, 3, 3))
+    return (center.astype(np.float32), axes.astype(np.float32), half.astype(np.float32))
+
+
+def axis_aligned_box(center, half):
+    c = np.asarray(center, dtype=np.float32).reshape(1, 3)
+    h = np.asarray(half, dtype=np.float32).reshape(1, 3)
+    return c, np.eye(3, dtype=np.float32)[None], h
+
+
+def boxes_to_array(center, axes, half):
+    """Pack into the [n, 15] float32 layout (center, axes row major, half)."""
+    center = np.asarray(center, dtype=np.float32).reshape(-1, 3)
+    n = center.shape[0]
+    axes = np.asarray(axes, dtype=np.float32).reshape(n, 9)
+    half = np.asarray(half, dtype=np.float32).reshape(n, 3)
+    return np.ascontiguousarray(np.concatenate([center, axes, half], axis=1))
