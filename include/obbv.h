@@ -1,0 +1,181 @@
+/*
+ * obbv.h -- C ABI of libobbv, the MI355X (gfx950) outer-volume engine for
+ * variational hierarchical oriented bounding boxes (Wang, Hua, Xu, Huo, Bao,
+ * "Variational Hierarchical Directed Bounding Box Construction for Solid Mesh
+ * Models", arXiv 2203.10521).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Return value: OBBV_OK (0) or a negative OBBV_ERR_* code.  No C++ exception
+ *   crosses this boundary.  obbv_last_error() returns a thread-local message for
+ *   the last failing call of the calling thread.
+ * - "device" pointers are HIP device allocations (for example torch tensors on
+ *   cuda:0 under ROCm); "host" pointers are ordinary host memory.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *   are stream ordered and asynchronous unless marked "synchronous".
+ * - The caller owns every buffer it passes and the library never frees caller
+ *   memory.  Scratch memory is a per-device library pool, grown on demand and
+ *   returned to HIP by obbv_release().
+ * - Meshes are closed, consistently oriented triangle meshes (Sec. 6 of the paper:
+ *   the method handles solid models only): every directed edge (a, b) occurs
+ *   once and its reverse (b, a) once; triangles are counter-clockwise seen from
+ *   outside.  Vertices are float32 xyz triples, triangles int32 index triples.
+ * - A box is (center, axes, half): row k of `axes` is the unit local axis k in
+ *   world coordinates (right handed); local coordinates are x' = axes (x - center);
+ *   the box is { |x'_k| <= half[k] }.  These are the 6 free parameters (centre
+ *   and axes) plus the enclosure-determined extents of Sec. 4.2.1.
+ */
+#ifndef OBBV_H
+#define OBBV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define OBBV_OK 0
+#define OBBV_ERR_INVALID_ARG (-1)     /* bad pointer, size, count, NaN parameter */
+#define OBBV_ERR_MESH_NOT_CLOSED (-2) /* a directed edge lacks its reverse       */
+#define OBBV_ERR_MESH_NOT_ORIENTED (-3) /* a directed edge occurs twice, or the
+                                           enclosed volume is not positive       */
+#define OBBV_ERR_DEGENERATE (-4)      /* nothing to compute (e.g. empty cluster) */
+#define OBBV_ERR_WORKSPACE (-5)       /* scratch limit exceeded                  */
+#define OBBV_ERR_OOM (-6)             /* hipMalloc failed                        */
+#define OBBV_ERR_HIP (-7)             /* a HIP runtime call failed               */
+#define OBBV_ERR_UNSUPPORTED (-8)     /* option not available on this device     */
+
+/* ---- device status word bits (obbv_status) ---------------------------- */
+#define OBBV_STATUS_NAN_BOX 0x1u      /* a box had a non-finite parameter        */
+#define OBBV_STATUS_BAD_INDEX 0x2u    /* a triangle index was out of range       */
+
+/* ---- data types -------------------------------------------------------- */
+typedef struct {
+  const float* vertices;    /* device, [n_vertices][3] float32              */
+  const int32_t* triangles; /* device, [n_triangles][3] int32, CCW outward  */
+  int32_t n_vertices;
+  int32_t n_triangles;
+} obbv_mesh;
+
+typedef struct {
+  float center[3];
+  float axes[9]; /* row major; row k = local axis k */
+  float half[3];
+} obbv_box;      /* 60 bytes, 4-byte aligned, no padding */
+
+/* Options of the outer-volume estimator (Sec. 4.1; see obbv_outer_volume). */
+typedef struct {
+  int32_t R;          /* rays per face edge: R x R rays per cast axis, 1..32767 */
+  uint32_t axis_mask; /* bit w set: cast along local axis w; 0 means 7 (all) */
+  uint64_t seed;      /* SplitMix64 seed of the ray jitter                   */
+  int32_t tile;       /* ray tile edge: 8 or 16; 0 = library choice          */
+  uint32_t flags;     /* reserved, must be 0                                 */
+} obbv_ov_params;
+
+/* ---- library ------------------------------------------------------------ */
+
+/* Version string, static storage. */
+const char* obbv_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* obbv_last_error(void);
+
+/* Synchronous.  Waits for `stream`, reads and clears the device status word
+ * (OBBV_STATUS_* bits) of the current device into *out_flags (host, nullable). */
+int obbv_status(void* stream, uint32_t* out_flags);
+
+/* Synchronous.  Frees the scratch pool of every device. */
+int obbv_release(void);
+
+/* ---- mesh staging ------------------------------------------------------ */
+
+/* Synchronous.  Validates a mesh for the closed-solid requirement (Sec. 6):
+ * indices in [0, n_vertices), every directed edge once with its reverse once,
+ * enclosed volume sum(det[a, b, c]) / 6 > 0.
+ * out_report (host, nullable, 4 entries): [0] number of directed edges without
+ * exactly one reverse, [1] number of repeated directed edges, [2] number of
+ * out-of-range indices, [3] unused (0).  *out_volume (host, nullable): the
+ * signed enclosed volume (float64).
+ * Returns OBBV_OK, OBBV_ERR_MESH_NOT_CLOSED, OBBV_ERR_MESH_NOT_ORIENTED or
+ * OBBV_ERR_INVALID_ARG. */
+int obbv_validate_mesh(const obbv_mesh* mesh, int32_t* out_report, double* out_volume,
+                       void* stream);
+
+/* ---- outer volume (the hot path) ----------------------------------------- */
+
+/* Outer volume OBV(X, O) of every box (Sec. 3, Eq. 4: the volume of the box
+ * outside the solid), by the jittered parallel-ray estimator of Sec. 4.1:
+ * for each cast axis w in axis_mask, an R x R grid of cells on the face
+ * [-h_u, h_u] x [-h_v, h_v] ((u, v) = the other two local axes in cyclic
+ * order), one ray per cell at (-h_u + (i + xi) du, -h_v + (j + eta) dv) parallel
+ * to axis w, with (xi, eta) drawn by SplitMix64 from
+ * (seed, box_key[b], w, i, j); the inside length of [-h_w, h_w] on each ray is
+ * integrated from its signed crossings (Eq. 9 generalised to a line), and
+ * OBV = V_box - mean_w sum_rays L du dv with V_box = 8 h0 h1 h2.
+ *
+ * meshes     host array of n_meshes mesh descriptors (device data), n_meshes >= 1
+ * boxes      device, [n_boxes] obbv_box
+ * box_mesh   device, [n_boxes] int32 mesh index per box; NULL = all mesh 0
+ * box_key    device, [n_boxes] uint32 jitter key per box; NULL = box index
+ * params     host; R in [1, 32767]
+ * out_obv    device, [n_boxes] float64 outer volume per box
+ * A box with a zero extent gets OBV 0; a box with a non-finite parameter gets
+ * NaN and sets OBBV_STATUS_NAN_BOX (read it with obbv_status).  n_boxes = 0 is
+ * a no-op.  The call synchronises the stream once to size its scratch memory.
+ */
+int obbv_outer_volume(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                      const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                      const obbv_ov_params* params, double* out_obv, void* stream);
+
+/* As obbv_outer_volume, with optional extra outputs (each nullable, device):
+ * out_vin_axis  [n_boxes][3] float64 inside volume per cast axis (0 if not cast)
+ * out_ray_q     [n_boxes][3][R][R] int32 per-ray inside fraction of the slab,
+ *               in units of 2^-22 (L / (2 h_w) * 2^22, rounded per crossing)
+ * out_ray_hits  [n_boxes][3][R][R] int32 crossings counted on each ray
+ * out_side      [n_boxes][3] int32: 0 = crossings above the slab bottom were
+ *               used, 1 = crossings below the slab top (mirrored cast)
+ * The per-ray outputs are meant for tests and need n_boxes * 3 * R * R entries. */
+int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                         const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                         const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
+                         int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side,
+                         void* stream);
+
+/* ---- measurement ----------------------------------------------------------- */
+
+/* Host.  enable != 0: every later obbv_outer_volume* call records a pair of HIP
+ * events around its ray-test kernel (k_test) on the call's stream and adds the
+ * number of ray-triangle tests it performs (rays x binned triangles of each
+ * tile) to a device counter.  enable == 0 stops recording. */
+int obbv_profile_enable(int enable);
+
+/* Synchronous.  Sums the elapsed time of the recorded k_test launches and
+ * returns it with the launch count and the test count, then clears the record.
+ * Outputs are host pointers, each nullable. */
+int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests);
+
+/* ---- covariance OBB fit -------------------------------------------------- */
+
+/* Area-weighted covariance box of every triangle cluster: the box axes are the
+ * principal directions of the cluster's surface (continuous-surface covariance,
+ * the PCA split of top-down builders, Sec. 2), decreasing eigenvalue, e2 = e0 x e1,
+ * largest-|component| of e0 and of e1 positive; the extents enclose the cluster's
+ * vertices tightly (Sec. 4.2.1: the extents follow from the centre and axes).
+ * The 3x3 eigenproblem is solved in float64 by cyclic Jacobi.
+ *
+ * mesh         host descriptor (device data)
+ * tri_cluster  device, [n_triangles] int32 cluster id in [0, n_clusters) or -1 (ignored)
+ * out_boxes    device, [n_clusters] obbv_box; an empty cluster gets center 0,
+ *              identity axes, half 0
+ * out_eigvals  device, [n_clusters][3] float64 (decreasing), nullable
+ */
+int obbv_fit(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters,
+             obbv_box* out_boxes, double* out_eigvals, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OBBV_H */

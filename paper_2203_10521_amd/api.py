@@ -1,0 +1,150 @@
+"""Python binding of libobbv: argument marshalling only.
+
+Every function takes torch tensors on the HIP device (``cuda:0`` under ROCm),
+checks dtypes and shapes, and calls the C entry point of the same name on the
+current torch stream.  All arithmetic runs in the library's HIP kernels.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+BOX_FLOATS = 15  # center[3], axes[9] (row k = local axis k), half[3]
+
+
+class ObbvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libobbv error {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != 0:
+        raise ObbvError(code, _lib.lib().obbv_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name, shape_tail=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [n, {', '.join(map(str, shape_tail))}]")
+    return t
+
+
+def mesh_struct(V, F):
+    _dev(V, torch.float32, "vertices", (3,))
+    _dev(F, torch.int32, "triangles", (3,))
+    return _lib.ObbvMesh(V.data_ptr(), F.data_ptr(), V.shape[0], F.shape[0])
+
+
+def version():
+    return _lib.lib().obbv_version().decode()
+
+
+def status(stream=None):
+    flags = ctypes.c_uint32(0)
+    _check(_lib.lib().obbv_status(_stream(stream), ctypes.byref(flags)))
+    return flags.value
+
+
+def release():
+    _check(_lib.lib().obbv_release())
+
+
+def validate_mesh(V, F, stream=None):
+    """(code, report[4], volume) -- code 0 means a closed, outward oriented solid."""
+    m = mesh_struct(V, F)
+    rep = (ctypes.c_int32 * 4)()
+    vol = ctypes.c_double(0.0)
+    code = _lib.lib().obbv_validate_mesh(ctypes.byref(m), rep, ctypes.byref(vol), _stream(stream))
+    return code, list(rep), vol.value
+
+
+def _params(R, seed, axis_mask, tile):
+    return _lib.ObbvOvParams(int(R), int(axis_mask), int(seed) & ((1 << 64) - 1), int(tile), 0)
+
+
+def outer_volume(V, F, boxes, R, seed=0, axis_mask=7, tile=0, box_key=None, out=None, stream=None):
+    """OBV of every box against the mesh (V, F); float64 tensor [n_boxes]."""
+    return outer_volume_ex(V, F, boxes, R, seed, axis_mask, tile, box_key, out=out, stream=stream)["obv"]
+
+
+def outer_volume_ex(V, F, boxes, R, seed=0, axis_mask=7, tile=0, box_key=None, rays=False,
+                    out=None, stream=None, meshes=None, box_mesh=None):
+    """Outer volume with the optional per-axis and per-ray outputs of obbv_outer_volume_ex.
+
+    ``meshes`` (list of (V, F)) with ``box_mesh`` (int32 [n_boxes]) evaluates boxes
+    against several meshes in one call; then V and F are ignored.
+    """
+    _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
+    n = boxes.shape[0]
+    dev = boxes.device
+    if meshes is None:
+        meshes = [(V, F)]
+    structs = (_lib.ObbvMesh * len(meshes))(*[mesh_struct(v, f) for v, f in meshes])
+    if box_mesh is not None:
+        _dev(box_mesh, torch.int32, "box_mesh")
+    if box_key is not None:
+        _dev(box_key, torch.int32, "box_key")
+    obv = out if out is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    _dev(obv, torch.float64, "out")
+    vin = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    side = torch.empty((n, 3), dtype=torch.int32, device=dev)
+    rq = rh = None
+    if rays:
+        rq = torch.empty((n, 3, R, R), dtype=torch.int32, device=dev)
+        rh = torch.empty((n, 3, R, R), dtype=torch.int32, device=dev)
+    p = _params(R, seed, axis_mask, tile)
+    _check(_lib.lib().obbv_outer_volume_ex(structs, len(meshes), _ptr(boxes), _ptr(box_mesh), _ptr(box_key),
+                                           n, ctypes.byref(p), _ptr(obv), _ptr(vin), _ptr(rq), _ptr(rh),
+                                           _ptr(side), _stream(stream)))
+    return {"obv": obv, "vin_axis": vin, "ray_q": rq, "ray_hits": rh, "side": side}
+
+
+def outer_volume_raw(meshes_struct, n_meshes, boxes, box_mesh, box_key, n, params, out, stream=None):
+    """Direct obbv_outer_volume call on prepared structs (used by the timing loop)."""
+    _check(_lib.lib().obbv_outer_volume(meshes_struct, n_meshes, _ptr(boxes), _ptr(box_mesh), _ptr(box_key),
+                                        n, ctypes.byref(params), _ptr(out), _stream(stream)))
+
+
+def fit(V, F, tri_cluster, n_clusters, stream=None):
+    """Covariance OBB per cluster: (boxes float32 [n, 15], eigenvalues float64 [n, 3])."""
+    m = mesh_struct(V, F)
+    _dev(tri_cluster, torch.int32, "tri_cluster")
+    if tri_cluster.shape[0] != F.shape[0]:
+        raise ValueError("tri_cluster needs one entry per triangle")
+    boxes = torch.empty((n_clusters, BOX_FLOATS), dtype=torch.float32, device=V.device)
+    eig = torch.empty((n_clusters, 3), dtype=torch.float64, device=V.device)
+    _check(_lib.lib().obbv_fit(ctypes.byref(m), _ptr(tri_cluster), int(n_clusters), _ptr(boxes), _ptr(eig),
+                               _stream(stream)))
+    return boxes, eig
+
+
+def profile_enable(enable=True):
+    """Record HIP events around every later ray-test kernel launch (and count its tests)."""
+    _check(_lib.lib().obbv_profile_enable(1 if enable else 0))
+
+
+def profile_read():
+    """(total k_test milliseconds, launches, ray-triangle tests) since the last read."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    t = ctypes.c_int64(0)
+    _check(_lib.lib().obbv_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(t)))
+    return ms.value, n.value, t.value

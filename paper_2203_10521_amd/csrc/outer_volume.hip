@@ -1,0 +1,753 @@
+// Outer volume OBV(X, O) of oriented boxes against a closed mesh
+// (Sec. 3, Eq. 4), by jittered parallel rays on each box face and the signed
+// crossing sum along each ray (Sec. 4.1, Eq. 9 generalised to a line).
+//
+// Pipeline per call (all on one stream):
+//   k_box_chunks + scan  work list of (box, 256-triangle chunk) items
+//   k_cull_count         per (box, cast axis): triangles in the half prism above
+//                        the slab bottom and below the slab top (ballot counts)
+//   k_choose_side        keep the half prism with fewer triangles (mirror flag)
+//   k_tile_count         per (box, axis, ray tile): number of binned triangles
+//   scans                record offsets, bin offsets  (one host sync: sizes)
+//   k_write              per kept triangle: a 64-byte test record (edge and depth
+//                        planes, fixed point) + its index in every tile bin
+//   k_test               one wave per ray tile: every ray against its bin
+//   k_finalize           float64 OBV per box
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace obbv {
+namespace {
+
+constexpr int kCullThreads = 256;
+constexpr int kTestThreads = 64;
+
+struct BoxRegs {
+  float Q[9];
+  float c[3];
+  float h[3];
+};
+
+__device__ inline BoxRegs load_box(const obbv_box* __restrict__ boxes, int b) {
+  BoxRegs r;
+  const float* p = reinterpret_cast<const float*>(boxes + b);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.c[k] = p[k];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r.Q[k] = p[3 + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.h[k] = p[12 + k];
+  return r;
+}
+
+// 0 = computable box, 1 = zero extent (OBV 0, nothing to cast), 2 = invalid (NaN / negative)
+__device__ inline int box_state(const BoxRegs& B) {
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) finite = finite && isfinite(B.Q[k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) finite = finite && isfinite(B.c[k]) && isfinite(B.h[k]);
+  if (!finite) return 2;
+  if (B.h[0] < 0.f || B.h[1] < 0.f || B.h[2] < 0.f) return 2;
+  if (B.h[0] == 0.f || B.h[1] == 0.f || B.h[2] == 0.f) return 1;
+  return 0;
+}
+
+// Workgroup k is dispatched to XCD k % 8; give every XCD a contiguous range of
+// logical ids so that tiles of one (box, axis) share that XCD's L2.
+__device__ inline int xcd_remap(int bid, int n) {
+  const int nx = 8;
+  const int q = n / nx, r = n % nx;
+  const int x = bid % nx, k = bid / nx;
+  return x * q + min(x, r) + k;
+}
+
+// Cast frame of one (box, axis): face axes (ua, va), half extents, cell sizes.
+struct CastFrame {
+  int ua, va;
+  float hu, hv, hw;
+  double du, dv;
+  float eu, ev;  // bounding-box margins for binning
+};
+
+__device__ inline CastFrame cast_frame(const BoxRegs& B, int w, int R) {
+  CastFrame f;
+  f.ua = (w + 1) % 3;
+  f.va = (w + 2) % 3;
+  f.hu = B.h[f.ua];
+  f.hv = B.h[f.va];
+  f.hw = B.h[w];
+  f.du = __ddiv_rn(__dmul_rn(2.0, (double)f.hu), (double)R);
+  f.dv = __ddiv_rn(__dmul_rn(2.0, (double)f.hv), (double)R);
+  f.eu = 1e-6f * f.hu;
+  f.ev = 1e-6f * f.hv;
+  return f;
+}
+
+// The triangle in the cast frame of axis w, optionally mirrored (z -> -z).
+struct CastTri {
+  float u[3], v[3], z[3];
+  double A2;  // twice the signed projected area (float64 of the float coordinates)
+};
+
+__device__ inline CastTri cast_tri(const float P[3][3], int w, const CastFrame& f, bool mirror) {
+  CastTri t;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    t.u[k] = P[k][f.ua];
+    t.v[k] = P[k][f.va];
+    t.z[k] = mirror ? -P[k][w] : P[k][w];
+  }
+  const double x1 = (double)t.u[1] - (double)t.u[0], y1 = (double)t.v[1] - (double)t.v[0];
+  const double x2 = (double)t.u[2] - (double)t.u[0], y2 = (double)t.v[2] - (double)t.v[0];
+  t.A2 = __dsub_rn(__dmul_rn(x1, y2), __dmul_rn(y1, x2));
+  return t;
+}
+
+// Rectangle overlap of the projected bounding box (with margins) and a
+// non-degenerate projection: the part of the test shared by both sides.
+__device__ inline bool projects_into_face(const CastTri& t, const CastFrame& f) {
+  const float umin = fminf(fminf(t.u[0], t.u[1]), t.u[2]);
+  const float umax = fmaxf(fmaxf(t.u[0], t.u[1]), t.u[2]);
+  const float vmin = fminf(fminf(t.v[0], t.v[1]), t.v[2]);
+  const float vmax = fmaxf(fmaxf(t.v[0], t.v[1]), t.v[2]);
+  return t.A2 != 0.0 && umax >= -f.hu - f.eu && umin <= f.hu + f.eu && vmax >= -f.hv - f.ev &&
+         vmin <= f.hv + f.ev;
+}
+
+// Tile range of the cells whose rays can hit the triangle (conservative).
+__device__ inline void tile_range(const CastTri& t, const CastFrame& f, int R, int TE, int& ti0,
+                                  int& ti1, int& tj0, int& tj1) {
+  const float umin = fminf(fminf(t.u[0], t.u[1]), t.u[2]);
+  const float umax = fmaxf(fmaxf(t.u[0], t.u[1]), t.u[2]);
+  const float vmin = fminf(fminf(t.v[0], t.v[1]), t.v[2]);
+  const float vmax = fmaxf(fmaxf(t.v[0], t.v[1]), t.v[2]);
+  const double hu = f.hu, hv = f.hv;
+  int i0 = (int)floor(((double)umin - f.eu + hu) / f.du);
+  int i1 = (int)floor(((double)umax + f.eu + hu) / f.du);
+  int j0 = (int)floor(((double)vmin - f.ev + hv) / f.dv);
+  int j1 = (int)floor(((double)vmax + f.ev + hv) / f.dv);
+  i0 = max(0, min(R - 1, i0));
+  i1 = max(0, min(R - 1, i1));
+  j0 = max(0, min(R - 1, j0));
+  j1 = max(0, min(R - 1, j1));
+  ti0 = i0 / TE;
+  ti1 = i1 / TE;
+  tj0 = j0 / TE;
+  tj1 = j1 / TE;
+}
+
+// Load triangle t of mesh M in the box frame.  Returns false (and flags the
+// status word) on an out-of-range index.
+__device__ inline bool load_tri_local(const MeshDev& M, int t, const BoxRegs& B, float P[3][3],
+                                      uint32_t* status) {
+  const int32_t* f = M.F + 3 * (int64_t)t;
+  const int a = f[0], b = f[1], c = f[2];
+  if ((unsigned)a >= (unsigned)M.nv || (unsigned)b >= (unsigned)M.nv || (unsigned)c >= (unsigned)M.nv) {
+    atomicOr(status, OBBV_STATUS_BAD_INDEX);
+    return false;
+  }
+  const int idx[3] = {a, b, c};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float* p = M.V + 3 * (int64_t)idx[k];
+    to_local(B.Q, B.c, p[0], p[1], p[2], P[k]);
+  }
+  return true;
+}
+
+// item -> (box, chunk) by binary search over the per-box chunk offsets
+__device__ inline int item_box(const int64_t* __restrict__ chunk_off, int n_boxes, int64_t item) {
+  int lo = 0, hi = n_boxes;  // chunk_off[lo] <= item < chunk_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (chunk_off[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+struct CullArgs {
+  const obbv_box* boxes;
+  const int32_t* box_mesh;
+  const MeshDev* meshes;
+  const int64_t* chunk_off;
+  int n_boxes;
+  int R;
+  int TE;
+  int tpe;  // tiles per face edge
+  uint32_t axis_mask;
+  uint32_t* status;
+};
+
+__global__ void k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ meshes,
+                             int n_meshes, int n_boxes, int32_t* __restrict__ nch, uint32_t* status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_boxes) return;
+  const int m = box_mesh ? box_mesh[b] : 0;
+  if (m < 0 || m >= n_meshes) {  // out-of-range mesh index: the box sees no triangles
+    atomicOr(status, OBBV_STATUS_BAD_INDEX);
+    nch[b] = 0;
+    return;
+  }
+  nch[b] = (meshes[m].nt + kCullThreads - 1) / kCullThreads;
+}
+
+// Which prism(s) the triangle belongs to, per cast axis.
+//   above: projects into the face and reaches above the slab bottom (z_max > -h)
+//   below: projects into the face and reaches below the slab top   (z_min <  h)
+__global__ void __launch_bounds__(kCullThreads)
+k_cull_count(CullArgs a, int32_t* __restrict__ side_cnt) {
+  const int64_t total = a.chunk_off[a.n_boxes];
+  const int lane = threadIdx.x & 63;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int b = item_box(a.chunk_off, a.n_boxes, item);
+    const BoxRegs B = load_box(a.boxes, b);
+    if (box_state(B) != 0) continue;
+    const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
+    const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
+    float P[3][3];
+    const bool ok = t < M.nt && load_tri_local(M, t, B, P, a.status);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      if (!((a.axis_mask >> w) & 1u)) continue;
+      const CastFrame f = cast_frame(B, w, a.R);
+      bool ka = false, kb = false;
+      if (ok) {
+        const CastTri tr = cast_tri(P, w, f, false);
+        if (projects_into_face(tr, f)) {
+          const float zmin = fminf(fminf(tr.z[0], tr.z[1]), tr.z[2]);
+          const float zmax = fmaxf(fmaxf(tr.z[0], tr.z[1]), tr.z[2]);
+          ka = zmax > -f.hw;
+          kb = zmin < f.hw;
+        }
+      }
+      const uint64_t ma = __ballot(ka), mb = __ballot(kb);
+      if (lane == 0) {
+        if (ma) atomicAdd(&side_cnt[(b * 3 + w) * 2 + 0], (int)__popcll(ma));
+        if (mb) atomicAdd(&side_cnt[(b * 3 + w) * 2 + 1], (int)__popcll(mb));
+      }
+    }
+  }
+}
+
+__global__ void k_choose_side(const int32_t* __restrict__ side_cnt, int nbw, int32_t* __restrict__ side,
+                              int32_t* __restrict__ rec_cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbw) return;
+  const int up = side_cnt[2 * i + 0], dn = side_cnt[2 * i + 1];
+  const int mirror = dn < up ? 1 : 0;
+  side[i] = mirror;
+  rec_cnt[i] = mirror ? dn : up;
+}
+
+// Is the triangle kept on the chosen side?  (Mirrored frames flip z, so the
+// kept half prism is always "above the slab bottom" in the cast frame.)
+__device__ inline bool kept(const CastTri& tr, const CastFrame& f) {
+  if (!projects_into_face(tr, f)) return false;
+  const float zmax = fmaxf(fmaxf(tr.z[0], tr.z[1]), tr.z[2]);
+  return zmax > -f.hw;
+}
+
+__global__ void __launch_bounds__(kCullThreads)
+k_tile_count(CullArgs a, const int32_t* __restrict__ side, int32_t* __restrict__ tile_cnt) {
+  const int64_t total = a.chunk_off[a.n_boxes];
+  const int TT = a.tpe * a.tpe;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int b = item_box(a.chunk_off, a.n_boxes, item);
+    const BoxRegs B = load_box(a.boxes, b);
+    if (box_state(B) != 0) continue;
+    const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
+    const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
+    float P[3][3];
+    if (!(t < M.nt && load_tri_local(M, t, B, P, a.status))) continue;
+    for (int w = 0; w < 3; ++w) {
+      if (!((a.axis_mask >> w) & 1u)) continue;
+      const int bw = b * 3 + w;
+      const CastFrame f = cast_frame(B, w, a.R);
+      const CastTri tr = cast_tri(P, w, f, side[bw] != 0);
+      if (!kept(tr, f)) continue;
+      int ti0, ti1, tj0, tj1;
+      tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
+      int32_t* base = tile_cnt + (int64_t)bw * TT;
+      for (int tj = tj0; tj <= tj1; ++tj)
+        for (int ti = ti0; ti <= ti1; ++ti) atomicAdd(&base[tj * a.tpe + ti], 1);
+    }
+  }
+}
+
+// The 64-byte test record of a kept triangle in its cast frame.
+//   [0..8]   edge functions E_k(u, v) = A_k u + B_k v + C_k, k = edge (k -> k+1),
+//            oriented so that the inside of the projected triangle is E >= 0
+//   [9..11]  depth plane in fixed point: y(u, v) = D u + E v + F equals
+//            kMagic + s (w(u, v) + h) 2^21 / h, s = crossing sign
+//   [12..13] clamp of y to the part of the triangle inside the slab
+// The edge coefficients of an edge shared by two triangles are exact
+// negatives of each other (or equal, when one of them is flipped), so the two
+// triangles classify every ray consistently: the test is watertight.
+__device__ inline void make_record(const CastTri& t, bool mirror, float hw, float4* __restrict__ out) {
+  const int sa = t.A2 > 0.0 ? 1 : -1;
+  const int s = mirror ? -sa : sa;
+  float A[3], Bc[3], C[3];
+  double Ad[3], Bd[3], Cd[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int i = k, j = (k + 1) % 3;
+    A[k] = __fsub_rn(t.v[i], t.v[j]);
+    Bc[k] = __fsub_rn(t.u[j], t.u[i]);
+    Ad[k] = __dsub_rn((double)t.v[i], (double)t.v[j]);
+    Bd[k] = __dsub_rn((double)t.u[j], (double)t.u[i]);
+    Cd[k] = __dsub_rn(__dmul_rn((double)t.u[i], (double)t.v[j]), __dmul_rn((double)t.v[i], (double)t.u[j]));
+    C[k] = (float)Cd[k];
+    if (sa < 0) {
+      A[k] = __fsub_rn(0.0f, A[k]);
+      Bc[k] = __fsub_rn(0.0f, Bc[k]);
+      C[k] = __fsub_rn(0.0f, C[k]);
+    }
+  }
+  // barycentric weight of vertex 0 is E_1 / A2, of vertex 1 is E_2 / A2, of vertex 2 is E_0 / A2
+  const double D = (Ad[1] * t.z[0] + Ad[2] * t.z[1] + Ad[0] * t.z[2]) / t.A2;
+  const double E = (Bd[1] * t.z[0] + Bd[2] * t.z[1] + Bd[0] * t.z[2]) / t.A2;
+  const double F = (Cd[1] * t.z[0] + Cd[2] * t.z[1] + Cd[0] * t.z[2]) / t.A2;
+  const double h = hw;
+  const double K = (double)s * kHalfQ / h;
+  const double zmin = fmin(fmin((double)t.z[0], (double)t.z[1]), (double)t.z[2]);
+  const double zmax = fmax(fmax((double)t.z[0], (double)t.z[1]), (double)t.z[2]);
+  const double zlo = fmin(fmax(-h, zmin), h);
+  const double zhi = fmax(fmin(h, zmax), -h);
+  double lo = K * (zlo + h) + (double)kMagic;
+  double hi = K * (zhi + h) + (double)kMagic;
+  if (s < 0) {
+    const double tmp = lo;
+    lo = hi;
+    hi = tmp;
+  }
+  out[0] = make_float4(A[0], Bc[0], C[0], A[1]);
+  out[1] = make_float4(Bc[1], C[1], A[2], Bc[2]);
+  out[2] = make_float4(C[2], (float)(K * D), (float)(K * E), (float)(K * (F + h) + (double)kMagic));
+  out[3] = make_float4((float)lo, (float)hi, 0.0f, 0.0f);
+}
+
+__global__ void __launch_bounds__(kCullThreads)
+k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict__ rec_off,
+        const int32_t* __restrict__ rec_cnt, int32_t* __restrict__ rec_cur, const int64_t* __restrict__ bin_off,
+        int32_t* __restrict__ bin_cur, float4* __restrict__ recs, int32_t* __restrict__ bins) {
+  const int64_t total = a.chunk_off[a.n_boxes];
+  const int TT = a.tpe * a.tpe;
+  const int lane = threadIdx.x & 63;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int b = item_box(a.chunk_off, a.n_boxes, item);
+    const BoxRegs B = load_box(a.boxes, b);
+    if (box_state(B) != 0) continue;
+    const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
+    const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
+    float P[3][3];
+    const bool ok = t < M.nt && load_tri_local(M, t, B, P, a.status);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      if (!((a.axis_mask >> w) & 1u)) continue;
+      const int bw = b * 3 + w;
+      const bool mirror = side[bw] != 0;
+      const CastFrame f = cast_frame(B, w, a.R);
+      CastTri tr;
+      bool keep = false;
+      if (ok) {
+        tr = cast_tri(P, w, f, mirror);
+        keep = kept(tr, f);
+      }
+      // wave-aggregated slot reservation: ballot + prefix popcount, one atomic per wave
+      const uint64_t m = __ballot(keep);
+      if (m == 0) continue;
+      int base = 0;
+      if (lane == __ffsll((long long)m) - 1) base = atomicAdd(&rec_cur[bw], (int)__popcll(m));
+      base = __shfl(base, __ffsll((long long)m) - 1);
+      if (!keep) continue;
+      const int rank = (int)__popcll(m & ((1ull << lane) - 1ull));
+      if (base + rank >= rec_cnt[bw]) {  // count and write passes disagree: never expected
+        atomicOr(a.status, OBBV_STATUS_BAD_INDEX);
+        continue;
+      }
+      const int64_t slot = rec_off[bw] + base + rank;
+      make_record(tr, mirror, f.hw, recs + 4 * slot);
+      int ti0, ti1, tj0, tj1;
+      tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
+      const int64_t tbase = (int64_t)bw * TT;
+      for (int tj = tj0; tj <= tj1; ++tj)
+        for (int ti = ti0; ti <= ti1; ++ti) {
+          const int64_t tl = tbase + tj * a.tpe + ti;
+          const int pos = atomicAdd(&bin_cur[tl], 1);
+          if (bin_off[tl] + pos < bin_off[tl + 1])
+            bins[bin_off[tl] + pos] = (int32_t)slot;
+          else
+            atomicOr(a.status, OBBV_STATUS_BAD_INDEX);
+        }
+    }
+  }
+}
+
+struct TestArgs {
+  const obbv_box* boxes;
+  const uint32_t* box_key;
+  const int64_t* bin_off;
+  const int32_t* bins;
+  const float4* recs;
+  unsigned long long* acc;  // [nbw] per-(box, axis) sum of q
+  int32_t* ray_q;           // nullable [nbw][R][R]
+  int32_t* ray_hits;        // nullable [nbw][R][R]
+  unsigned long long* test_counter;  // nullable: += rays x binned triangles per tile
+  uint64_t seed;
+  int n_boxes;
+  int n_rec;
+  int R;
+  int tpe;
+  uint32_t axis_mask;
+};
+
+// One wave per TE x TE ray tile of one (box, axis); RPL = (TE/8)^2 rays per lane.
+// Every ray is tested against every record in the tile's bin:
+//   E_k = A_k u + B_k v + C_k (3 x 2 FMA), inside iff min E_k >= 0,
+//   y = D u + E v + F (2 FMA), clamped to the triangle's slab part (med3),
+//   acc += inside ? bits(y) : kMagicBits   -- exact integer accumulation.
+template <int TE, bool STATS>
+__global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
+  constexpr int NB = TE / 8;
+  constexpr int RPL = NB * NB;
+  const int TT = a.tpe * a.tpe;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int bw = bid / TT;
+  const int tile = bid - bw * TT;
+  const int b = bw / 3, w = bw - 3 * (bw / 3);
+  if (!((a.axis_mask >> w) & 1u)) return;
+  const BoxRegs B = load_box(a.boxes, b);
+  if (box_state(B) != 0) return;
+  const int ua = (w + 1) % 3, va = (w + 2) % 3;
+  const double hu = B.h[ua], hv = B.h[va];
+  const double du = __ddiv_rn(__dmul_rn(2.0, hu), (double)a.R);
+  const double dv = __ddiv_rn(__dmul_rn(2.0, hv), (double)a.R);
+  const uint32_t key = a.box_key ? a.box_key[b] : (uint32_t)b;
+  const int ti = tile % a.tpe, tj = tile / a.tpe;
+  const int lane = threadIdx.x;
+
+  float ru[RPL], rv[RPL];
+  uint32_t acc[RPL];
+  int hits[RPL];
+  bool valid[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = ti * TE + (r % NB) * 8 + (lane & 7);
+    const int j = tj * TE + (r / NB) * 8 + (lane >> 3);
+    valid[r] = i < a.R && j < a.R;
+    acc[r] = 0u;
+    hits[r] = 0;
+    ru[r] = 0.f;
+    rv[r] = 0.f;
+    if (valid[r]) {
+      const uint64_t n = ray_counter(key, w, i, j);
+      const double xi = u24(splitmix64_at(a.seed, n));
+      const double eta = u24(splitmix64_at(a.seed, n + 1));
+      ru[r] = (float)__dadd_rn(-hu, __dmul_rn(__dadd_rn((double)i, xi), du));
+      rv[r] = (float)__dadd_rn(-hv, __dmul_rn(__dadd_rn((double)j, eta), dv));
+    }
+  }
+
+  const int64_t k0 = a.bin_off[(int64_t)bw * TT + tile];
+  const int64_t k1 = a.bin_off[(int64_t)bw * TT + tile + 1];
+  for (int64_t k = k0; k < k1; ++k) {
+    const int idx = a.bins[k];
+    if ((unsigned)idx >= (unsigned)a.n_rec) continue;  // only after a flagged write-pass mismatch
+    const float4 r0 = a.recs[4 * (int64_t)idx + 0];
+    const float4 r1 = a.recs[4 * (int64_t)idx + 1];
+    const float4 r2 = a.recs[4 * (int64_t)idx + 2];
+    const float4 r3 = a.recs[4 * (int64_t)idx + 3];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const float u = ru[r], v = rv[r];
+      const float e0 = __fmaf_rn(r0.x, u, __fmaf_rn(r0.y, v, r0.z));
+      const float e1 = __fmaf_rn(r0.w, u, __fmaf_rn(r1.x, v, r1.y));
+      const float e2 = __fmaf_rn(r1.z, u, __fmaf_rn(r1.w, v, r2.x));
+      const float m = fminf(fminf(e0, e1), e2);
+      const float y = __fmaf_rn(r2.y, u, __fmaf_rn(r2.z, v, r2.w));
+      const float c = __builtin_amdgcn_fmed3f(y, r3.x, r3.y);
+      const bool in = m >= 0.0f;
+      acc[r] += in ? __float_as_uint(c) : kMagicBits;
+      if (STATS) hits[r] += in ? 1 : 0;
+    }
+  }
+  const uint32_t nbias = (uint32_t)(k1 - k0) * kMagicBits;
+  if (a.test_counter && lane == 0) {
+    const int ni = min(TE, a.R - ti * TE), nj = min(TE, a.R - tj * TE);
+    atomicAdd(a.test_counter, (unsigned long long)((k1 - k0) * (int64_t)(ni * nj)));
+  }
+  int64_t lane_sum = 0;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int32_t q = valid[r] ? (int32_t)(acc[r] - nbias) : 0;
+    lane_sum += q;
+    if (STATS && valid[r]) {
+      const int i = ti * TE + (r % NB) * 8 + (lane & 7);
+      const int j = tj * TE + (r / NB) * 8 + (lane >> 3);
+      const int64_t o = ((int64_t)bw * a.R + i) * a.R + j;
+      if (a.ray_q) a.ray_q[o] = q;
+      if (a.ray_hits) a.ray_hits[o] = hits[r];
+    }
+  }
+  // wave reduction of the 64 lane sums, one 64-bit atomic per wave
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lane_sum += __shfl_xor(lane_sum, off);
+  if (lane == 0 && lane_sum != 0) atomicAdd(&a.acc[bw], (unsigned long long)lane_sum);
+}
+
+__global__ void k_finalize(const obbv_box* __restrict__ boxes, int n_boxes, int R, uint32_t axis_mask,
+                           const unsigned long long* __restrict__ acc, double* __restrict__ out_obv,
+                           double* __restrict__ out_vin_axis, uint32_t* status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_boxes) return;
+  const BoxRegs B = load_box(boxes, b);
+  const int st = box_state(B);
+  if (st == 2) {
+    out_obv[b] = __longlong_as_double(0x7ff8000000000000ll);
+    atomicOr(status, OBBV_STATUS_NAN_BOX);
+    if (out_vin_axis)
+      for (int w = 0; w < 3; ++w) out_vin_axis[3 * b + w] = __longlong_as_double(0x7ff8000000000000ll);
+    return;
+  }
+  const double vbox = 8.0 * (double)B.h[0] * (double)B.h[1] * (double)B.h[2];
+  const double denom = kQOne * (double)R * (double)R;
+  double sum = 0.0;
+  int n = 0;
+  for (int w = 0; w < 3; ++w) {
+    double vin = 0.0;
+    if ((axis_mask >> w) & 1u) {
+      vin = st == 0 ? vbox * ((double)(long long)acc[3 * b + w] / denom) : 0.0;
+      sum += vin;
+      ++n;
+    }
+    if (out_vin_axis) out_vin_axis[3 * b + w] = vin;
+  }
+  out_obv[b] = vbox - (n ? sum / n : 0.0);
+}
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct HostPinned {
+  int64_t* p = nullptr;
+};
+HostPinned g_pinned[64];
+
+int pinned_totals(int64_t** out) {
+  int dev = 0;
+  OBBV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return OBBV_ERR_UNSUPPORTED;
+  if (!g_pinned[dev].p) {
+    void* q = nullptr;
+    OBBV_HIP(hipHostMalloc(&q, 64, hipHostMallocDefault));
+    g_pinned[dev].p = (int64_t*)q;
+  }
+  *out = g_pinned[dev].p;
+  return OBBV_OK;
+}
+
+template <int TE>
+int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, hipStream_t s) {
+  if (stats)
+    hipLaunchKernelGGL((k_test<TE, true>), dim3((unsigned)nblocks), dim3(kTestThreads), 0, s, ta);
+  else
+    hipLaunchKernelGGL((k_test<TE, false>), dim3((unsigned)nblocks), dim3(kTestThreads), 0, s, ta);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+}  // namespace
+
+int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                      const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                      const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
+                      int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s) {
+  OBBV_ARG(params != nullptr, "params is NULL");
+  OBBV_ARG(n_boxes >= 0, "n_boxes < 0");
+  if (n_boxes == 0) return OBBV_OK;
+  OBBV_ARG(meshes != nullptr && n_meshes >= 1, "need at least one mesh");
+  OBBV_ARG(boxes != nullptr && out_obv != nullptr, "boxes / out_obv is NULL");
+  OBBV_ARG(n_meshes == 1 || box_mesh != nullptr, "box_mesh is required with several meshes");
+  OBBV_ARG(params->R >= 1 && params->R <= 32767, "R must be in [1, 32767]");
+  OBBV_ARG(params->flags == 0, "flags must be 0");
+  OBBV_ARG(params->tile == 0 || params->tile == 8 || params->tile == 16, "tile must be 0, 8 or 16");
+  const uint32_t mask = params->axis_mask ? params->axis_mask : 7u;
+  OBBV_ARG(mask <= 7u, "axis_mask has bits above 2");
+  OBBV_ARG((int64_t)n_boxes * 3 < (1ll << 31) / 2, "too many boxes");
+  int max_nt = 0;
+  std::vector<MeshDev> mh((size_t)n_meshes);
+  for (int m = 0; m < n_meshes; ++m) {
+    OBBV_ARG(meshes[m].n_triangles >= 0 && meshes[m].n_vertices >= 0, "negative mesh size");
+    OBBV_ARG(meshes[m].n_triangles == 0 || (meshes[m].triangles && meshes[m].vertices),
+             "mesh pointers are NULL");
+    mh[m] = MeshDev{meshes[m].vertices, meshes[m].triangles, meshes[m].n_vertices, meshes[m].n_triangles};
+    max_nt = std::max(max_nt, meshes[m].n_triangles);
+  }
+  const int R = params->R;
+  const int TE = params->tile ? params->tile : (R >= 48 ? 16 : 8);
+  const int tpe = ceil_div(R, TE);
+  const int64_t TT = (int64_t)tpe * tpe;
+  const int64_t nbw = (int64_t)n_boxes * 3;
+  OBBV_ARG(nbw * TT < (1ll << 31), "R too large for this many boxes in one call");
+
+  uint32_t* status = nullptr;
+  OBBV_RET(status_word(&status));
+
+  // ---- meta scratch layout ----
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t o_mesh = take(sizeof(MeshDev) * n_meshes);
+  const size_t o_nch = take(4 * (size_t)n_boxes);
+  const size_t o_choff = take(8 * (size_t)(n_boxes + 1));
+  const size_t o_side = take(4 * (size_t)nbw);
+  const size_t o_reccnt = take(4 * (size_t)nbw);
+  const size_t o_recoff = take(8 * (size_t)(nbw + 1));
+  const size_t o_binoff = take(8 * (size_t)(nbw * TT + 1));
+  const size_t o_zero0 = off;  // zero-initialised block
+  const size_t o_sidecnt = take(4 * (size_t)nbw * 2);
+  const size_t o_reccur = take(4 * (size_t)nbw);
+  const size_t o_tilecnt = take(4 * (size_t)(nbw * TT));
+  const size_t o_bincur = take(4 * (size_t)(nbw * TT));
+  const size_t o_acc = take(8 * (size_t)nbw);
+  const size_t o_zero1 = off;
+  const size_t scan_bytes =
+      std::max(exclusive_scan_scratch_bytes(nbw * TT), exclusive_scan_scratch_bytes(std::max<int64_t>(nbw, n_boxes)));
+  const size_t o_scan = take(scan_bytes);
+  void* meta_v = nullptr;
+  OBBV_RET(pool_get(kPoolMeta, off, &meta_v));
+  char* meta = (char*)meta_v;
+  MeshDev* d_mesh = (MeshDev*)(meta + o_mesh);
+  int32_t* d_nch = (int32_t*)(meta + o_nch);
+  int64_t* d_choff = (int64_t*)(meta + o_choff);
+  int32_t* d_side = (int32_t*)(meta + o_side);
+  int32_t* d_reccnt = (int32_t*)(meta + o_reccnt);
+  int64_t* d_recoff = (int64_t*)(meta + o_recoff);
+  int64_t* d_binoff = (int64_t*)(meta + o_binoff);
+  int32_t* d_sidecnt = (int32_t*)(meta + o_sidecnt);
+  int32_t* d_reccur = (int32_t*)(meta + o_reccur);
+  int32_t* d_tilecnt = (int32_t*)(meta + o_tilecnt);
+  int32_t* d_bincur = (int32_t*)(meta + o_bincur);
+  unsigned long long* d_acc = (unsigned long long*)(meta + o_acc);
+  void* d_scan = meta + o_scan;
+
+  OBBV_HIP(hipMemcpyAsync(d_mesh, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
+  OBBV_HIP(hipMemsetAsync(meta + o_zero0, 0, o_zero1 - o_zero0, s));
+
+  hipLaunchKernelGGL(k_box_chunks, dim3(ceil_div(n_boxes, 256)), dim3(256), 0, s, box_mesh, d_mesh,
+                     n_meshes, n_boxes, d_nch, status);
+  OBBV_HIP(hipGetLastError());
+  OBBV_RET(exclusive_scan_i32_to_i64(d_nch, d_choff, n_boxes, d_scan, scan_bytes, s));
+
+  CullArgs ca;
+  ca.boxes = boxes;
+  ca.box_mesh = box_mesh;
+  ca.meshes = d_mesh;
+  ca.chunk_off = d_choff;
+  ca.n_boxes = n_boxes;
+  ca.R = R;
+  ca.TE = TE;
+  ca.tpe = tpe;
+  ca.axis_mask = mask;
+  ca.status = status;
+  const int64_t items_bound = (int64_t)n_boxes * ceil_div(std::max(max_nt, 1), kCullThreads);
+  const unsigned cull_grid = (unsigned)std::min<int64_t>(items_bound, 256 * 16);
+
+  hipLaunchKernelGGL(k_cull_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_sidecnt);
+  OBBV_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_choose_side, dim3(ceil_div(nbw, 256)), dim3(256), 0, s, d_sidecnt, (int)nbw,
+                     d_side, d_reccnt);
+  OBBV_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_tile_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_tilecnt);
+  OBBV_HIP(hipGetLastError());
+  OBBV_RET(exclusive_scan_i32_to_i64(d_reccnt, d_recoff, nbw, d_scan, scan_bytes, s));
+  OBBV_RET(exclusive_scan_i32_to_i64(d_tilecnt, d_binoff, nbw * TT, d_scan, scan_bytes, s));
+
+  int64_t* pin = nullptr;
+  OBBV_RET(pinned_totals(&pin));
+  OBBV_HIP(hipMemcpyAsync(pin + 0, d_recoff + nbw, 8, hipMemcpyDeviceToHost, s));
+  OBBV_HIP(hipMemcpyAsync(pin + 1, d_binoff + nbw * TT, 8, hipMemcpyDeviceToHost, s));
+  OBBV_HIP(hipStreamSynchronize(s));
+  const int64_t n_rec = pin[0], n_bin = pin[1];
+  OBBV_ARG(n_rec < (1ll << 31), "more than 2^31 triangle records in one call; split the boxes");
+
+  if (n_rec > 0) {
+    void* recs_v = nullptr;
+    void* bins_v = nullptr;
+    OBBV_RET(pool_get(kPoolRecords, (size_t)n_rec * 64, &recs_v));
+    OBBV_RET(pool_get(kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
+    hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
+                       d_reccnt, d_reccur, d_binoff, d_bincur, (float4*)recs_v, (int32_t*)bins_v);
+    OBBV_HIP(hipGetLastError());
+    TestArgs ta;
+    ta.boxes = boxes;
+    ta.box_key = box_key;
+    ta.bin_off = d_binoff;
+    ta.bins = (const int32_t*)bins_v;
+    ta.recs = (const float4*)recs_v;
+    ta.acc = d_acc;
+    ta.ray_q = out_ray_q;
+    ta.ray_hits = out_ray_hits;
+    ta.test_counter = nullptr;
+    void* prof_token = nullptr;
+    if (profiling_enabled()) {
+      OBBV_RET(profile_counter(&ta.test_counter));
+      OBBV_RET(profile_record_begin(s, &prof_token));
+    }
+    ta.seed = params->seed;
+    ta.n_boxes = n_boxes;
+    ta.n_rec = (int)n_rec;
+    ta.R = R;
+    ta.tpe = tpe;
+    ta.axis_mask = mask;
+    const bool stats = out_ray_q || out_ray_hits;
+    if (stats) {
+      const size_t per = (size_t)nbw * R * R * 4;
+      if (out_ray_q) OBBV_HIP(hipMemsetAsync(out_ray_q, 0, per, s));
+      if (out_ray_hits) OBBV_HIP(hipMemsetAsync(out_ray_hits, 0, per, s));
+    }
+    if (TE == 8)
+      OBBV_RET(launch_test<8>(ta, nbw * TT, stats, s));
+    else
+      OBBV_RET(launch_test<16>(ta, nbw * TT, stats, s));
+    if (prof_token != nullptr || profiling_enabled()) OBBV_RET(profile_record_end(s, prof_token));
+  } else if (out_ray_q || out_ray_hits) {
+    const size_t per = (size_t)nbw * R * R * 4;
+    if (out_ray_q) OBBV_HIP(hipMemsetAsync(out_ray_q, 0, per, s));
+    if (out_ray_hits) OBBV_HIP(hipMemsetAsync(out_ray_hits, 0, per, s));
+  }
+  if (out_side) OBBV_HIP(hipMemcpyAsync(out_side, d_side, 4 * nbw, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_finalize, dim3(ceil_div(n_boxes, 128)), dim3(128), 0, s, boxes, n_boxes, R, mask,
+                     d_acc, out_obv, out_vin_axis, status);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+}  // namespace obbv
+
+extern "C" int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                    const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                                    const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
+                                    int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side,
+                                    void* stream) {
+  obbv::clear_error();
+  return obbv::outer_volume_impl(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, params, out_obv,
+                                 out_vin_axis, out_ray_q, out_ray_hits, out_side, (hipStream_t)stream);
+}
+
+extern "C" int obbv_outer_volume(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                 const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                                 const obbv_ov_params* params, double* out_obv, void* stream) {
+  obbv::clear_error();
+  return obbv::outer_volume_impl(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, params, out_obv,
+                                 nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream);
+}

@@ -1,0 +1,394 @@
+// Host runtime of libobbv: errors, per-device scratch pool, status word,
+// device exclusive scan, mesh validation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace obbv {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+// ---------------------------------------------------------------------------
+// scratch pool
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kMaxDevices = 64;
+struct DevicePool {
+  void* ptr[kPoolCount] = {};
+  size_t cap[kPoolCount] = {};
+  uint32_t* status = nullptr;
+};
+DevicePool g_pools[kMaxDevices];
+std::mutex g_pool_mutex;
+}  // namespace
+
+int pool_get(int slot, size_t bytes, void** out) {
+  int dev = 0;
+  OBBV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index out of range");
+    return OBBV_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_pool_mutex);
+  DevicePool& p = g_pools[dev];
+  if (bytes == 0) bytes = 256;
+  if (p.cap[slot] < bytes) {
+    if (p.ptr[slot]) {
+      // kernels of earlier calls may still read the old block
+      OBBV_HIP(hipDeviceSynchronize());
+      OBBV_HIP(hipFree(p.ptr[slot]));
+      p.ptr[slot] = nullptr;
+      p.cap[slot] = 0;
+    }
+    size_t want = std::max(bytes + bytes / 4, (size_t)1 << 20);
+    void* q = nullptr;
+    if (hipMalloc(&q, want) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hipMalloc of " + std::to_string(want) + " bytes of scratch failed");
+      return OBBV_ERR_OOM;
+    }
+    p.ptr[slot] = q;
+    p.cap[slot] = want;
+  }
+  *out = p.ptr[slot];
+  return OBBV_OK;
+}
+
+int status_word(uint32_t** out) {
+  int dev = 0;
+  OBBV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index out of range");
+    return OBBV_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_pool_mutex);
+  DevicePool& p = g_pools[dev];
+  if (!p.status) {
+    void* q = nullptr;
+    OBBV_HIP(hipMalloc(&q, 256));
+    OBBV_HIP(hipMemset(q, 0, 256));
+    p.status = (uint32_t*)q;
+  }
+  *out = p.status;
+  return OBBV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan int32 -> int64 (three kernels per level, recursive on block sums)
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanBlock = kScanThreads * kScanItems;  // elements per block
+
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_block(const T* __restrict__ in, int64_t* __restrict__ out, int64_t* __restrict__ sums,
+             int64_t n) {
+  __shared__ int64_t sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t run = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    v[k] = idx < n ? (int64_t)in[idx] : 0;
+    run += v[k];
+  }
+  sh[threadIdx.x] = run;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread totals
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int64_t add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t excl = sh[threadIdx.x] - run;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    if (idx < n) out[idx] = excl;
+    excl += v[k];
+  }
+  if (threadIdx.x == kScanThreads - 1 && sums) sums[blockIdx.x] = sh[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_add(int64_t* __restrict__ out, const int64_t* __restrict__ offs, int64_t n) {
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  const int64_t add = offs[blockIdx.x];
+  for (int k = threadIdx.x; k < kScanBlock; k += kScanThreads) {
+    const int64_t idx = base + k;
+    if (idx < n) out[idx] += add;
+  }
+}
+
+__global__ void k_write_total(const int64_t* __restrict__ excl, const int32_t* __restrict__ last_in,
+                              int64_t* __restrict__ total_out) {
+  *total_out = *excl + (int64_t)*last_in;
+}
+
+template <typename T>
+int scan_level(const T* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb <= 1) {
+    hipLaunchKernelGGL(k_scan_block<T>, dim3(1), dim3(kScanThreads), 0, s, in, out,
+                       (int64_t*)nullptr, n);
+    OBBV_HIP(hipGetLastError());
+    return OBBV_OK;
+  }
+  int64_t* sums = scratch;
+  int64_t* sums_scan = scratch + nb;
+  hipLaunchKernelGGL(k_scan_block<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, sums,
+                     n);
+  OBBV_HIP(hipGetLastError());
+  OBBV_RET(scan_level<int64_t>(sums, sums_scan, nb, scratch + 2 * nb, s));
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, out, sums_scan, n);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+}  // namespace
+
+size_t exclusive_scan_scratch_bytes(int64_t n) {
+  size_t total = 0;
+  int64_t m = n;
+  while (m > kScanBlock) {
+    m = (m + kScanBlock - 1) / kScanBlock;
+    total += 2 * (size_t)m;
+  }
+  return (total + 8) * sizeof(int64_t);
+}
+
+int exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* scratch,
+                              size_t scratch_bytes, hipStream_t s) {
+  if (n <= 0) {
+    OBBV_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+    return OBBV_OK;
+  }
+  if (scratch_bytes < exclusive_scan_scratch_bytes(n)) {
+    set_error("scan scratch too small");
+    return OBBV_ERR_WORKSPACE;
+  }
+  OBBV_RET(scan_level<int32_t>(in, out, n, (int64_t*)scratch, s));
+  hipLaunchKernelGGL(k_write_total, dim3(1), dim3(1), 0, s, out + (n - 1), in + (n - 1), out + n);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// measurement: event pairs around k_test launches, device test counter
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfState {
+  bool enabled = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  unsigned long long* counter = nullptr;
+  int counter_dev = -1;
+};
+ProfState g_prof;
+std::mutex g_prof_mutex;
+}  // namespace
+
+bool profiling_enabled() { return g_prof.enabled; }
+
+int profile_counter(unsigned long long** out) {
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  int dev = 0;
+  OBBV_HIP(hipGetDevice(&dev));
+  if (!g_prof.counter || g_prof.counter_dev != dev) {
+    void* q = nullptr;
+    OBBV_HIP(hipMalloc(&q, 256));
+    OBBV_HIP(hipMemset(q, 0, 256));
+    g_prof.counter = (unsigned long long*)q;
+    g_prof.counter_dev = dev;
+  }
+  *out = g_prof.counter;
+  return OBBV_OK;
+}
+
+int profile_record_begin(hipStream_t s, void** token) {
+  hipEvent_t a, b;
+  OBBV_HIP(hipEventCreate(&a));
+  OBBV_HIP(hipEventCreate(&b));
+  OBBV_HIP(hipEventRecord(a, s));
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  g_prof.events.emplace_back(a, b);
+  *token = (void*)(g_prof.events.size() - 1);
+  return OBBV_OK;
+}
+
+int profile_record_end(hipStream_t s, void* token) {
+  hipEvent_t b;
+  {
+    std::lock_guard<std::mutex> lock(g_prof_mutex);
+    b = g_prof.events[(size_t)token].second;
+  }
+  OBBV_HIP(hipEventRecord(b, s));
+  return OBBV_OK;
+}
+
+}  // namespace obbv
+
+using namespace obbv;
+
+extern "C" int obbv_profile_enable(int enable) {
+  clear_error();
+  g_prof.enabled = enable != 0;
+  if (g_prof.enabled) {
+    unsigned long long* c = nullptr;
+    OBBV_RET(profile_counter(&c));
+  }
+  return OBBV_OK;
+}
+
+extern "C" int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests) {
+  clear_error();
+  std::lock_guard<std::mutex> lock(g_prof_mutex);
+  double total = 0.0;
+  for (auto& e : g_prof.events) {
+    OBBV_HIP(hipEventSynchronize(e.second));
+    float ms = 0.f;
+    OBBV_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+    total += ms;
+    OBBV_HIP(hipEventDestroy(e.first));
+    OBBV_HIP(hipEventDestroy(e.second));
+  }
+  const int64_t n = (int64_t)g_prof.events.size();
+  g_prof.events.clear();
+  unsigned long long tests = 0;
+  if (g_prof.counter) {
+    OBBV_HIP(hipDeviceSynchronize());
+    OBBV_HIP(hipMemcpy(&tests, g_prof.counter, 8, hipMemcpyDeviceToHost));
+    OBBV_HIP(hipMemset(g_prof.counter, 0, 8));
+  }
+  if (out_test_ms) *out_test_ms = total;
+  if (out_launches) *out_launches = n;
+  if (out_tests) *out_tests = (int64_t)tests;
+  return OBBV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: library
+// ---------------------------------------------------------------------------
+extern "C" const char* obbv_version(void) { return "obbv 0.1.0 (gfx950)"; }
+
+extern "C" const char* obbv_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int obbv_status(void* stream, uint32_t* out_flags) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* st = nullptr;
+  OBBV_RET(status_word(&st));
+  uint32_t host = 0;
+  OBBV_HIP(hipMemcpyAsync(&host, st, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  OBBV_HIP(hipMemsetAsync(st, 0, sizeof(uint32_t), s));
+  OBBV_HIP(hipStreamSynchronize(s));
+  if (out_flags) *out_flags = host;
+  return OBBV_OK;
+}
+
+extern "C" int obbv_release(void) {
+  clear_error();
+  int cur = 0;
+  OBBV_HIP(hipGetDevice(&cur));
+  std::lock_guard<std::mutex> lock(g_pool_mutex);
+  for (int d = 0; d < kMaxDevices; ++d) {
+    DevicePool& p = g_pools[d];
+    bool any = p.status != nullptr;
+    for (int k = 0; k < kPoolCount; ++k) any = any || p.ptr[k];
+    if (!any) continue;
+    OBBV_HIP(hipSetDevice(d));
+    for (int k = 0; k < kPoolCount; ++k) {
+      if (p.ptr[k]) OBBV_HIP(hipFree(p.ptr[k]));
+      p.ptr[k] = nullptr;
+      p.cap[k] = 0;
+    }
+    if (p.status) OBBV_HIP(hipFree(p.status));
+    p.status = nullptr;
+  }
+  OBBV_HIP(hipSetDevice(cur));
+  return OBBV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: mesh validation (synchronous, host side)
+// ---------------------------------------------------------------------------
+extern "C" int obbv_validate_mesh(const obbv_mesh* mesh, int32_t* out_report, double* out_volume,
+                                  void* stream) {
+  clear_error();
+  OBBV_ARG(mesh != nullptr, "mesh is NULL");
+  OBBV_ARG(mesh->n_triangles >= 0 && mesh->n_vertices >= 0, "negative mesh size");
+  OBBV_ARG(mesh->n_triangles == 0 || (mesh->triangles && mesh->vertices), "mesh pointers are NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nt = mesh->n_triangles, nv = mesh->n_vertices;
+  std::vector<int32_t> F((size_t)nt * 3);
+  std::vector<float> V((size_t)nv * 3);
+  if (nt) OBBV_HIP(hipMemcpyAsync(F.data(), mesh->triangles, F.size() * 4, hipMemcpyDeviceToHost, s));
+  if (nv) OBBV_HIP(hipMemcpyAsync(V.data(), mesh->vertices, V.size() * 4, hipMemcpyDeviceToHost, s));
+  OBBV_HIP(hipStreamSynchronize(s));
+  int32_t bad_index = 0;
+  for (int32_t x : F)
+    if (x < 0 || x >= nv) ++bad_index;
+  int32_t report[4] = {0, 0, bad_index, 0};
+  double vol = 0.0;
+  if (bad_index == 0 && nt > 0) {
+    std::vector<uint64_t> e;
+    e.reserve((size_t)nt * 3);
+    for (int64_t t = 0; t < nt; ++t)
+      for (int k = 0; k < 3; ++k) {
+        uint32_t a = (uint32_t)F[3 * t + k], b = (uint32_t)F[3 * t + (k + 1) % 3];
+        e.push_back(((uint64_t)a << 32) | b);
+      }
+    std::sort(e.begin(), e.end());
+    int32_t repeated = 0, unmatched = 0;
+    for (size_t i = 0; i < e.size(); ++i) {
+      if (i + 1 < e.size() && e[i + 1] == e[i]) ++repeated;
+      uint64_t rev = (e[i] << 32) | (e[i] >> 32);
+      auto range = std::equal_range(e.begin(), e.end(), rev);
+      if (range.second - range.first != 1) ++unmatched;
+    }
+    report[0] = unmatched;
+    report[1] = repeated;
+    for (int64_t t = 0; t < nt; ++t) {
+      const float* a = &V[3 * (size_t)F[3 * t + 0]];
+      const float* b = &V[3 * (size_t)F[3 * t + 1]];
+      const float* c = &V[3 * (size_t)F[3 * t + 2]];
+      double bc0 = (double)b[1] * c[2] - (double)b[2] * c[1];
+      double bc1 = (double)b[2] * c[0] - (double)b[0] * c[2];
+      double bc2 = (double)b[0] * c[1] - (double)b[1] * c[0];
+      vol += (double)a[0] * bc0 + (double)a[1] * bc1 + (double)a[2] * bc2;
+    }
+    vol /= 6.0;
+  }
+  if (out_report) std::memcpy(out_report, report, sizeof(report));
+  if (out_volume) *out_volume = vol;
+  if (bad_index) {
+    set_error("triangle index out of range");
+    return OBBV_ERR_INVALID_ARG;
+  }
+  if (report[1]) {
+    set_error("a directed edge occurs more than once (inconsistent orientation)");
+    return OBBV_ERR_MESH_NOT_ORIENTED;
+  }
+  if (report[0]) {
+    set_error("a directed edge has no reverse edge (mesh not closed)");
+    return OBBV_ERR_MESH_NOT_CLOSED;
+  }
+  if (nt > 0 && !(vol > 0.0)) {
+    set_error("enclosed volume is not positive (triangles not outward oriented)");
+    return OBBV_ERR_MESH_NOT_ORIENTED;
+  }
+  return OBBV_OK;
+}

@@ -1,0 +1,65 @@
+"""The C ABI library loads, exports every symbol of include/obbv.h, and rejects
+bad arguments before touching the device (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "obbv.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(obbv_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2203_10521_amd import _lib
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported_and_bound(L):
+    from paper_2203_10521_amd import _lib
+    names = _declared()
+    assert "obbv_outer_volume" in names and "obbv_fit" in names
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in _lib.SIGNATURES, n
+
+
+def test_struct_layouts_match_header():
+    from paper_2203_10521_amd import _lib
+    assert ctypes.sizeof(_lib.ObbvOvParams) == 24
+    assert _lib.ObbvOvParams.seed.offset == 8
+    assert ctypes.sizeof(_lib.ObbvMesh) == 24
+
+
+def test_argument_errors_before_any_device_call(L):
+    from paper_2203_10521_amd import _lib
+    m = _lib.ObbvMesh(0, 0, 0, 0)
+    p = _lib.ObbvOvParams(32, 7, 1, 0, 0)
+    # n_boxes == 0 is a no-op
+    assert L.obbv_outer_volume(ctypes.byref(m), 1, None, None, None, 0, ctypes.byref(p), None, None) == 0
+    # NULL params, bad R, bad tile, bad mask, flags != 0, several meshes without box_mesh
+    assert L.obbv_outer_volume(ctypes.byref(m), 1, None, None, None, 1, None, None, None) == -1
+    for R, mask, tile, flags in [(0, 7, 0, 0), (40000, 7, 0, 0), (32, 7, 12, 0), (32, 9, 0, 0), (32, 7, 0, 1)]:
+        bad = _lib.ObbvOvParams(R, mask, 1, tile, flags)
+        rc = L.obbv_outer_volume(ctypes.byref(m), 1, ctypes.c_void_p(16), None, None, 1, ctypes.byref(bad),
+                                 ctypes.c_void_p(16), None)
+        assert rc == -1
+        assert len(L.obbv_last_error()) > 0
+    two = (_lib.ObbvMesh * 2)()
+    rc = L.obbv_outer_volume(two, 2, ctypes.c_void_p(16), None, None, 1, ctypes.byref(p), ctypes.c_void_p(16),
+                             None)
+    assert rc == -1
+    assert L.obbv_fit(ctypes.byref(m), None, -1, None, None, None) == -1
+    assert L.obbv_fit(ctypes.byref(m), None, 0, None, None, None) == 0
+    assert L.obbv_validate_mesh(None, None, None, None) == -1
+
+
+def test_version(L):
+    assert L.obbv_version().startswith(b"obbv")
