@@ -174,6 +174,80 @@ int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_t
 int obbv_fit(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters,
              obbv_box* out_boxes, double* out_eigvals, void* stream);
 
+/* ---- same-layer Lloyd clustering (Sec. 4.2.1) ----------------------------- */
+
+typedef struct obbv_lloyd obbv_lloyd; /* opaque state, created and destroyed in pairs */
+
+typedef struct {
+  int32_t R;              /* rays per face edge of every outer-volume evaluation */
+  int32_t tile;           /* ray tile edge (0 = library choice, 8 or 16)          */
+  uint64_t seed;          /* SplitMix64 seed of the ray jitter                    */
+  int32_t pops_per_round; /* K: frontier triangles taken per group per round; 1 = the
+                             serial flood of the paper                            */
+  int32_t reserved;       /* must be 0                                            */
+  double delta;           /* rotation step (radians) of the parameter update      */
+} obbv_lloyd_params;
+
+/* Synchronous.  Copies the mesh to the host (the flood's queue and adjacency
+ * live there; every outer volume is evaluated on the device) and creates a state.
+ * The mesh's device arrays must stay valid while the state exists. */
+int obbv_lloyd_create(const obbv_mesh* mesh, const obbv_lloyd_params* params, obbv_lloyd** out);
+
+/* Host.  Defines the groups of one layer: tri_group[t] (host, [n_triangles]) is
+ * the group of triangle t or -1; box b belongs to group box_group[b] (host,
+ * [n_boxes]) and starts with centre and axes from boxes[b] (host, [n_boxes][15],
+ * obbv_box layout; the half extents are ignored); box_slot[b] (host, nullable)
+ * is its ray-jitter key (default b).  The boxes of a group partition its
+ * triangles (Eq. 11). */
+int obbv_lloyd_set_groups(obbv_lloyd* st, int32_t n_boxes, const int32_t* tri_group, const int32_t* box_group,
+                          const float* boxes, const uint32_t* box_slot);
+
+/* Synchronous.  One Lloyd iteration of every group: the flooding partition
+ * (Sec. 4.2.1 step 1, Eq. 12-13) with the current centres and axes fixed, then
+ * the parameter update of every box (step 2: tight box, finite-difference
+ * rotation gradient, line search, kept if OBV drops). */
+int obbv_lloyd_step(obbv_lloyd* st, void* stream);
+
+/* Host.  Results of the last step (each output nullable, host):
+ * tri_box [n_triangles] box of each triangle (-1 = none), boxes [n_boxes][15],
+ * obv [n_boxes], *layer_error = sum of OBV (Eq. 6), counters [4] = outer-volume
+ * evaluations, flood rounds, candidates that needed no evaluation, moves. */
+int obbv_lloyd_get(obbv_lloyd* st, int32_t* tri_box, float* boxes, double* obv, double* layer_error,
+                   int64_t* counters);
+
+int obbv_lloyd_destroy(obbv_lloyd* st);
+
+/* ---- hierarchy (Sec. 4.2.2) ---------------------------------------------- */
+
+typedef struct {
+  int32_t levels;         /* layers including the root, 1..12                    */
+  int32_t branching;      /* children per node, fixed in advance                  */
+  int32_t iters;          /* Lloyd iterations per layer and pass                  */
+  int32_t sweeps;         /* bottom-up / top-down sweeps after the first top-down */
+  int32_t R;
+  int32_t tile;
+  int32_t pops_per_round;
+  int32_t reserved;       /* must be 0 */
+  uint64_t seed;          /* ray jitter and seed-triangle draws                   */
+  double delta;
+} obbv_hier_params;
+
+/* Synchronous.  Builds the hierarchy: the root is the covariance box of the mesh
+ * refined by parameter updates; each lower layer splits every node's triangles
+ * among `branching` children by same-layer Lloyd (top-down decomposition); each
+ * sweep then merges layers bottom-up with the child boxes as units and keeps a
+ * merge only if the hierarchy error e (Eq. 7, layer weight = number of layers to
+ * the leaves, leaf = 1, Sec. 5) drops, and re-solves the layers below top-down,
+ * again keeping only improvements.  Node numbering is level-major:
+ * n_nodes = sum_l branching^l.  Outputs (host, each nullable):
+ * out_boxes [n_nodes][15]; out_obv [n_nodes]; out_parent [n_nodes] (-1 root);
+ * out_tri_node [levels][n_triangles] node of every triangle per layer;
+ * out_e [1 + sweeps] e after the top-down pass and after every sweep;
+ * out_counters [4] as obbv_lloyd_get. */
+int obbv_build_hierarchy(const obbv_mesh* mesh, const obbv_hier_params* params, float* out_boxes, double* out_obv,
+                         int32_t* out_parent, int32_t* out_tri_node, double* out_e, int64_t* out_counters,
+                         void* stream);
+
 #ifdef __cplusplus
 }
 #endif

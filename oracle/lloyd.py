@@ -1,0 +1,365 @@
+"""Same-layer Lloyd clustering of triangles into boxes (Sec. 4.2.1) and the
+layer weights of the hierarchy error (Sec. 3, Eq. 7; Sec. 5) -- float64 oracle.
+
+A box O_i of a layer has a centre c_i and axes Q_i (its 6 free parameters); its
+half extents S_i follow from enclosing its triangle set F_i.  During the
+partition the centre stays fixed, so the box is symmetric about c_i:
+h_i = max over the vertices v of F_i of |Q_i (v - c_i)|.
+
+Partition (flooding, Sec. 4.2.1 step 1), in the paper's order:
+  * every triangle t of the group gets the key |m_t - c_nearest| (centroid to the
+    nearest box centre); each box starts from the triangle nearest its centre;
+  * repeatedly take t_min, the frontier triangle with the smallest key; for every
+    box O_i compute dOBV_i = |OBV(O_i(S_i')) - OBV(O_i(S_i))| (Eq. 12) where S_i'
+    encloses F_i and t_min; give t_min to the box with the smallest dOBV (Eq. 13;
+    ties: nearer centre, then lower index); put its unassigned neighbours in the
+    queue.  A box that already contains t_min has dOBV = 0, so when one exists
+    t_min goes to the nearest such box without evaluating the others.
+  * bulk-synchronous rounds take the K smallest frontier triangles at once and
+    evaluate them all against the boxes of the round start (K = 1 is the serial
+    flood); triangles no flood reaches (other components) are assigned one by
+    one by the same rule at the end.
+Parameter update (step 2): tight box for the current axes, then a finite
+difference gradient of OBV over the three rotation angles (+-delta about each
+local axis) and a steepest-descent line search; the best candidate is kept if
+it lowers OBV.
+
+Boxes are stored as float32 (centre and axes rounded to nearest, half extents
+rounded up so the box still encloses), as the HIP path stores them; OBV values
+come from an evaluator callable (the ray-grid oracle in the tests).
+"""
+import heapq
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# float32 box storage
+# ---------------------------------------------------------------------------
+def f32_up(x):
+    """Round float64 values up to float32."""
+    x = np.asarray(x, dtype=np.float64)
+    y = x.astype(np.float32)
+    lo = y.astype(np.float64) < x
+    y = np.where(lo, np.nextafter(y, np.float32(np.inf)), y)
+    return y.astype(np.float32)
+
+
+def make_box(c, Q, h):
+    return (np.asarray(c, np.float64).astype(np.float32), np.asarray(Q, np.float64).astype(np.float32),
+            f32_up(h))
+
+
+def project(P, Q):
+    """Local coordinates Q p of points P [n,3] (float64), summed in axis order."""
+    P = np.asarray(P, np.float64)
+    Q = np.asarray(Q, np.float64)
+    return np.stack([(P[:, 0] * Q[r, 0] + P[:, 1] * Q[r, 1]) + P[:, 2] * Q[r, 2] for r in range(3)], axis=1)
+
+
+def tri_extent(V, F, t, c, Q):
+    """max over the vertices of triangle t of |Q (v - c)| per local axis (float64)."""
+    P = project(V[F[t]].astype(np.float64) - np.asarray(c, np.float64), Q)
+    return np.abs(P).max(axis=0)
+
+
+def tight_box(V, F, tris, Q):
+    """Tightest box with axes Q (float32) around the vertices of triangles `tris`."""
+    Q32 = np.asarray(Q, np.float32)
+    Q64 = Q32.astype(np.float64)
+    idx = np.unique(F[np.asarray(tris)].reshape(-1))
+    proj = project(V[idx].astype(np.float64), Q64)
+    lo, hi = proj.min(0), proj.max(0)
+    mid = 0.5 * (lo + hi)
+    c = np.array([(Q64[0, k] * mid[0] + Q64[1, k] * mid[1]) + Q64[2, k] * mid[2] for k in range(3)])
+    c32 = c.astype(np.float32)
+    # extents about the stored (rounded) centre so the float32 box encloses
+    P = project(V[idx].astype(np.float64) - c32.astype(np.float64), Q64)
+    return c32, Q32, f32_up(np.abs(P).max(axis=0))
+
+
+def adjacency(F):
+    """Edge-adjacent triangles (sharing an undirected edge)."""
+    edges = {}
+    for t, (a, b, c) in enumerate(np.asarray(F).tolist()):
+        for u, v in ((a, b), (b, c), (c, a)):
+            edges.setdefault((min(u, v), max(u, v)), []).append(t)
+    nb = [[] for _ in range(len(F))]
+    for ts in edges.values():
+        for x in ts:
+            for y in ts:
+                if x != y:
+                    nb[x].append(y)
+    return [sorted(set(n)) for n in nb]
+
+
+# ---------------------------------------------------------------------------
+# partition
+# ---------------------------------------------------------------------------
+def _centroids(V, F):
+    T = V[F].astype(np.float64)
+    return ((T[:, 0] + T[:, 1]) + T[:, 2]) / 3.0
+
+
+def flood_partition(V, F, adj, group, centers, axes, slots, evaluate, K=32):
+    """Bulk-synchronous flood of the triangles `group` into len(centers) boxes.
+
+    evaluate(list of (slot, c, Q, h)) -> float64 array of OBV.
+    Returns (assign: dict t -> box index, boxes: list of (c, Q, h), obv array,
+    counters dict).
+    """
+    V = np.asarray(V)
+    F = np.asarray(F)
+    b = len(centers)
+    group = [int(t) for t in group]
+    in_group = set(group)
+    m = _centroids(V, F)
+    C = np.asarray(centers, np.float32).astype(np.float64)
+    dist = {t: np.linalg.norm(m[t] - C, axis=1) for t in group}
+    key = {t: float(dist[t].min()) for t in group}
+    assign = {}
+    boxes = []
+    chosen = set()
+    for i in range(b):
+        cand = [t for t in group if t not in chosen]
+        s = min(cand, key=lambda t: (float(dist[t][i]), t))
+        chosen.add(s)
+        assign[s] = i
+        boxes.append(make_box(centers[i], axes[i], tri_extent(V, F, s, np.float32(centers[i]),
+                                                              np.float32(axes[i]))))
+    obv = np.array(evaluate([(slots[i], *boxes[i]) for i in range(b)]), dtype=np.float64)
+    counters = {"rounds": 0, "evals": b, "trivial": 0, "moves": 0}
+    heap = []
+    queued = set(assign)
+    for s in list(assign):
+        for n in adj[s]:
+            if n in in_group and n not in queued:
+                queued.add(n)
+                heapq.heappush(heap, (key[n], n))
+
+    def decide(pops):
+        """Evaluate the (t, box) candidates of this round against the current boxes.
+
+        A box that already contains t has dOBV = 0, the smallest possible value,
+        so when one exists t goes to the nearest such box and the other boxes
+        of t need no evaluation.
+        """
+        grown = {}
+        req = []
+        for t in pops:
+            trivial_any = False
+            for i in range(b):
+                c, Q, h = boxes[i]
+                h2 = f32_up(np.maximum(h.astype(np.float64), tri_extent(V, F, t, c, Q)))
+                grown[(t, i)] = h2
+                if np.array_equal(h2, h):
+                    counters["trivial"] += 1
+                    trivial_any = True
+            if not trivial_any:
+                req += [(t, i) for i in range(b)]
+        vals = evaluate([(slots[i], boxes[i][0], boxes[i][1], grown[(t, i)]) for t, i in req]) if req else []
+        counters["evals"] += len(req)
+        dval = {k: v for k, v in zip(req, vals)}
+        choice = {}
+        for t in pops:
+            best = None
+            for i in range(b):
+                if (t, i) in dval:
+                    d = abs(dval[(t, i)] - obv[i])
+                elif np.array_equal(grown[(t, i)], boxes[i][2]):
+                    d = 0.0
+                else:
+                    continue          # not evaluated: another box contains t
+                k = (d, float(dist[t][i]), i)
+                if best is None or k < best:
+                    best = k
+            choice[t] = best[2]
+        return choice, grown, dval
+
+    def apply(choice, grown, dval):
+        per_box = {}
+        for t, i in choice.items():
+            assign[t] = i
+            per_box.setdefault(i, []).append(t)
+            counters["moves"] += 1
+        extra = []
+        for i, ts in per_box.items():
+            c, Q, h = boxes[i]
+            hs = [grown[(t, i)] for t in ts]
+            hn = hs[0]
+            for x in hs[1:]:
+                hn = np.maximum(hn, x)
+            if np.array_equal(hn, h):
+                continue
+            boxes[i] = (c, Q, hn)
+            same = [t for t in ts if np.array_equal(grown[(t, i)], hn) and (t, i) in dval]
+            if same:
+                obv[i] = dval[(same[0], i)]
+            else:
+                extra.append(i)
+        if extra:
+            vals = evaluate([(slots[i], *boxes[i]) for i in extra])
+            counters["evals"] += len(extra)
+            for i, v in zip(extra, vals):
+                obv[i] = v
+
+    while heap:
+        pops = []
+        while heap and len(pops) < K:
+            _, t = heapq.heappop(heap)
+            if t not in assign:
+                pops.append(t)
+        if not pops:
+            break
+        counters["rounds"] += 1
+        choice, grown, dval = decide(pops)
+        apply(choice, grown, dval)
+        for t in pops:
+            for n in adj[t]:
+                if n in in_group and n not in assign and n not in queued:
+                    queued.add(n)
+                    heapq.heappush(heap, (key[n], n))
+    # triangles the flood cannot reach
+    for t in sorted(group):
+        if t not in assign:
+            choice, grown, dval = decide([t])
+            apply(choice, grown, dval)
+    return assign, boxes, obv, counters
+
+
+def serial_flood(V, F, adj, group, centers, axes, slots, evaluate):
+    """The paper's serial flood: one t_min at a time (reference for K = 1)."""
+    V = np.asarray(V)
+    F = np.asarray(F)
+    b = len(centers)
+    in_group = set(int(t) for t in group)
+    m = _centroids(V, F)
+    C = np.asarray(centers, np.float32).astype(np.float64)
+    boxes, assign, chosen = [], {}, set()
+    for i in range(b):
+        s = min((t for t in in_group if t not in chosen),
+                key=lambda t: (float(np.linalg.norm(m[t] - C[i])), t))
+        chosen.add(s)
+        assign[s] = i
+        boxes.append(make_box(centers[i], axes[i],
+                              tri_extent(V, F, s, np.float32(centers[i]), np.float32(axes[i]))))
+    obv = [float(v) for v in evaluate([(slots[i], *boxes[i]) for i in range(b)])]
+    heap = []
+    seen = set(assign)
+
+    def push_neighbours(t):
+        for n in adj[t]:
+            if n in in_group and n not in seen:
+                seen.add(n)
+                heapq.heappush(heap, (float(np.linalg.norm(m[n] - C, axis=1).min()), n))
+
+    for s in list(assign):
+        push_neighbours(s)
+
+    def take(t):
+        best, best_h, best_v = None, None, None
+        grown = []
+        for i in range(b):
+            c, Q, h = boxes[i]
+            grown.append(f32_up(np.maximum(h.astype(np.float64), tri_extent(V, F, t, c, Q))))
+        inside = [i for i in range(b) if np.array_equal(grown[i], boxes[i][2])]
+        for i in (inside if inside else range(b)):
+            c, Q, h = boxes[i]
+            h2 = grown[i]
+            if inside:
+                d, v = 0.0, obv[i]
+            else:
+                v = float(evaluate([(slots[i], c, Q, h2)])[0])
+                d = abs(v - obv[i])
+            k = (d, float(np.linalg.norm(m[t] - C[i])), i)
+            if best is None or k < best:
+                best, best_h, best_v = k, h2, v
+        i = best[2]
+        assign[t] = i
+        boxes[i] = (boxes[i][0], boxes[i][1], best_h)
+        obv[i] = best_v
+
+    while heap:
+        _, t = heapq.heappop(heap)
+        if t in assign:
+            continue
+        take(t)
+        push_neighbours(t)
+    for t in sorted(in_group):
+        if t not in assign:
+            take(t)
+    return assign, boxes, np.array(obv)
+
+
+# ---------------------------------------------------------------------------
+# parameter update
+# ---------------------------------------------------------------------------
+def rot_local(k, theta):
+    """Rotation by theta about local axis k, acting on the local axis frame."""
+    cth, sth = np.cos(theta), np.sin(theta)
+    R = np.eye(3)
+    a, b = (k + 1) % 3, (k + 2) % 3
+    R[a, a], R[a, b], R[b, a], R[b, b] = cth, -sth, sth, cth
+    return R
+
+
+def rodrigues(r):
+    th = float(np.linalg.norm(r))
+    if th == 0.0:
+        return np.eye(3)
+    k = np.asarray(r, np.float64) / th
+    Kx = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + np.sin(th) * Kx + (1 - np.cos(th)) * (Kx @ Kx)
+
+
+def update_box(V, F, tris, Q, slot, evaluate, delta=0.02, steps=(8.0, 4.0, 2.0, 1.0, 0.5)):
+    """Step 2 of the Lloyd iteration for one box: tight box, FD gradient over the
+    three rotation angles, line search along -gradient; returns (box, obv, accepted)."""
+    Q = np.asarray(Q, np.float32).astype(np.float64)
+    base = tight_box(V, F, tris, Q)
+    cands = [base]
+    for k in range(3):
+        for sgn in (+1.0, -1.0):
+            cands.append(tight_box(V, F, tris, rot_local(k, sgn * delta) @ Q))
+    vals = np.asarray(evaluate([(slot, *bx) for bx in cands]), dtype=np.float64)
+    g = np.array([(vals[1 + 2 * k] - vals[2 + 2 * k]) / (2 * delta) for k in range(3)])
+    gn = float(np.linalg.norm(g))
+    if gn == 0.0:
+        return base, float(vals[0]), False
+    d = -g / gn
+    line = [tight_box(V, F, tris, rodrigues(s * delta * d) @ Q) for s in steps]
+    lv = np.asarray(evaluate([(slot, *bx) for bx in line]), dtype=np.float64)
+    j = int(np.argmin(lv))
+    if lv[j] < vals[0]:
+        return line[j], float(lv[j]), True
+    return base, float(vals[0]), False
+
+
+# ---------------------------------------------------------------------------
+# one Lloyd iteration of a group, and the hierarchy weights
+# ---------------------------------------------------------------------------
+def lloyd_iteration(V, F, adj, group, centers, axes, slots, evaluate, K=32):
+    """Partition then update every box; returns (clusters, boxes, obv, layer error)."""
+    assign, boxes, obv, cnt = flood_partition(V, F, adj, group, centers, axes, slots, evaluate, K)
+    b = len(centers)
+    clusters = [[t for t, i in assign.items() if i == k] for k in range(b)]
+    out_boxes, out_obv = [], []
+    for k in range(b):
+        if not clusters[k]:
+            out_boxes.append(boxes[k])
+            out_obv.append(float(obv[k]))
+            continue
+        bx, v, _ = update_box(V, F, clusters[k], boxes[k][1], slots[k], evaluate)
+        out_boxes.append(bx)
+        out_obv.append(v)
+    return clusters, out_boxes, np.array(out_obv), float(np.sum(out_obv)), cnt
+
+
+def layer_weights(n_levels):
+    """Sec. 5: omega = number of layers from the layer to the leaves, leaf = 1."""
+    return [float(n_levels - l) for l in range(n_levels)]
+
+
+def hierarchy_error(level_obv, weights):
+    """Eq. 7 with each layer's OMV replaced by its sum of OBV (Eq. 6)."""
+    return float(sum(w * float(np.sum(o)) for w, o in zip(weights, level_obv)))

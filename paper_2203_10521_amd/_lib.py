@@ -31,6 +31,17 @@ class ObbvOvParams(ctypes.Structure):
                 ("tile", c_int32), ("flags", c_uint32)]
 
 
+class ObbvLloydParams(ctypes.Structure):
+    _fields_ = [("R", c_int32), ("tile", c_int32), ("seed", c_uint64), ("pops_per_round", c_int32),
+                ("reserved", c_int32), ("delta", ctypes.c_double)]
+
+
+class ObbvHierParams(ctypes.Structure):
+    _fields_ = [("levels", c_int32), ("branching", c_int32), ("iters", c_int32), ("sweeps", c_int32),
+                ("R", c_int32), ("tile", c_int32), ("pops_per_round", c_int32), ("reserved", c_int32),
+                ("seed", c_uint64), ("delta", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/obbv.h
 SIGNATURES = {
     "obbv_version": (ctypes.c_char_p, []),
@@ -46,6 +57,15 @@ SIGNATURES = {
     "obbv_profile_enable": (c_int32, [c_int32]),
     "obbv_profile_read": (c_int32, [c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "obbv_fit": (c_int32, [ctypes.POINTER(ObbvMesh), c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "obbv_lloyd_create": (c_int32, [ctypes.POINTER(ObbvMesh), ctypes.POINTER(ObbvLloydParams),
+                                    ctypes.POINTER(c_void_p)]),
+    "obbv_lloyd_set_groups": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "obbv_lloyd_step": (c_int32, [c_void_p, c_void_p]),
+    "obbv_lloyd_get": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double_p,
+                                 ctypes.POINTER(ctypes.c_int64)]),
+    "obbv_lloyd_destroy": (c_int32, [c_void_p]),
+    "obbv_build_hierarchy": (c_int32, [ctypes.POINTER(ObbvMesh), ctypes.POINTER(ObbvHierParams), c_void_p,
+                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
 }
 
 _lib = None

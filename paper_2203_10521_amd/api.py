@@ -6,6 +6,7 @@ current torch stream.  All arithmetic runs in the library's HIP kernels.
 """
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -148,3 +149,83 @@ def profile_read():
     t = ctypes.c_int64(0)
     _check(_lib.lib().obbv_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(t)))
     return ms.value, n.value, t.value
+
+
+def _host_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else ctypes.c_void_p(0)
+
+
+class Lloyd:
+    """Same-layer Lloyd clustering state (obbv_lloyd_*); host arrays are numpy."""
+
+    def __init__(self, V, F, R, seed=0, pops_per_round=32, delta=0.02, tile=0, stream=None):
+        self._mesh = mesh_struct(V, F)
+        self._keep = (V, F)
+        self.n_triangles = F.shape[0]
+        p = _lib.ObbvLloydParams(int(R), int(tile), int(seed) & ((1 << 64) - 1), int(pops_per_round), 0,
+                                 float(delta))
+        self._h = ctypes.c_void_p(0)
+        _check(_lib.lib().obbv_lloyd_create(ctypes.byref(self._mesh), ctypes.byref(p), ctypes.byref(self._h)))
+        self.n_boxes = 0
+        self._stream = stream
+
+    def set_groups(self, tri_group, box_group, boxes, box_slot=None):
+        tri_group = np.ascontiguousarray(tri_group, dtype=np.int32)
+        box_group = np.ascontiguousarray(box_group, dtype=np.int32)
+        boxes = np.ascontiguousarray(boxes, dtype=np.float32).reshape(-1, BOX_FLOATS)
+        slot = None if box_slot is None else np.ascontiguousarray(box_slot, dtype=np.uint32)
+        self.n_boxes = boxes.shape[0]
+        _check(_lib.lib().obbv_lloyd_set_groups(self._h, self.n_boxes, _host_ptr(tri_group), _host_ptr(box_group),
+                                                _host_ptr(boxes), _host_ptr(slot)))
+
+    def step(self):
+        _check(_lib.lib().obbv_lloyd_step(self._h, _stream(self._stream)))
+
+    def get(self):
+        tri_box = np.empty(self.n_triangles, np.int32)
+        boxes = np.empty((self.n_boxes, BOX_FLOATS), np.float32)
+        obv = np.empty(self.n_boxes, np.float64)
+        e = ctypes.c_double(0.0)
+        cnt = (ctypes.c_int64 * 4)()
+        _check(_lib.lib().obbv_lloyd_get(self._h, _host_ptr(tri_box), _host_ptr(boxes), _host_ptr(obv),
+                                         ctypes.byref(e), cnt))
+        return {"tri_box": tri_box, "boxes": boxes, "obv": obv, "layer_error": e.value,
+                "counters": dict(zip(("evals", "rounds", "trivial", "moves"), list(cnt)))}
+
+    def close(self):
+        if self._h:
+            _lib.lib().obbv_lloyd_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_hierarchy(V, F, levels, branching, iters, sweeps, R, seed=0, pops_per_round=32, delta=0.02, tile=0,
+                    stream=None):
+    """obbv_build_hierarchy; returns numpy outputs (boxes, obv, parent, tri_node, e, counters)."""
+    m = mesh_struct(V, F)
+    p = _lib.ObbvHierParams(int(levels), int(branching), int(iters), int(sweeps), int(R), int(tile),
+                            int(pops_per_round), 0, int(seed) & ((1 << 64) - 1), float(delta))
+    n_nodes = sum(branching ** level for level in range(levels))
+    nt = F.shape[0]
+    boxes = np.zeros((n_nodes, BOX_FLOATS), np.float32)
+    obv = np.zeros(n_nodes, np.float64)
+    parent = np.zeros(n_nodes, np.int32)
+    tri_node = np.zeros((levels, nt), np.int32)
+    e = np.zeros(1 + sweeps, np.float64)
+    cnt = np.zeros(4, np.int64)
+    _check(_lib.lib().obbv_build_hierarchy(ctypes.byref(m), ctypes.byref(p), _host_ptr(boxes), _host_ptr(obv),
+                                           _host_ptr(parent), _host_ptr(tri_node), _host_ptr(e), _host_ptr(cnt),
+                                           _stream(stream)))
+    return {"boxes": boxes, "obv": obv, "parent": parent, "tri_node": tri_node, "e": e,
+            "counters": dict(zip(("evals", "rounds", "trivial", "moves"), cnt.tolist()))}

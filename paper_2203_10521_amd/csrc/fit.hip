@@ -30,6 +30,56 @@ struct FitScratch {
   uint64_t* hi;   // [n][3]
 };
 
+// Adds vals[0..N) of every lane into base[N * cluster + k]: lanes with the same
+// cluster are summed across the wave first, then one lane per cluster does the
+// atomics (triangles of one cluster are mostly contiguous, so a wave usually
+// holds one or two clusters).  Lanes with c < 0 contribute nothing.
+template <int N>
+__device__ inline void wave_cluster_add(double* base, int c, const double (&vals)[N]) {
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(c >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lc = __shfl(c, leader);
+    const bool mine = c == lc;
+    const uint64_t mask = __ballot(mine);
+    for (int k = 0; k < N; ++k) {
+      double v = mine ? vals[k] : 0.0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == leader) atomicAdd(&base[N * lc + k], v);
+    }
+    todo &= ~mask;
+  }
+}
+
+template <int N>
+__device__ inline void wave_cluster_minmax(uint64_t* lo, uint64_t* hi, int c, const uint64_t (&kl)[N],
+                                           const uint64_t (&kh)[N]) {
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(c >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lc = __shfl(c, leader);
+    const bool mine = c == lc;
+    const uint64_t mask = __ballot(mine);
+    for (int k = 0; k < N; ++k) {
+      unsigned long long a = mine ? kl[k] : ~0ull, b = mine ? kh[k] : 0ull;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long a2 = __shfl_xor(a, off), b2 = __shfl_xor(b, off);
+        a = a2 < a ? a2 : a;
+        b = b2 > b ? b2 : b;
+      }
+      if (lane == leader) {
+        atomicMin((unsigned long long*)&lo[N * lc + k], a);
+        atomicMax((unsigned long long*)&hi[N * lc + k], b);
+      }
+    }
+    todo &= ~mask;
+  }
+}
+
 __device__ inline bool tri_cluster_of(const int32_t* __restrict__ cl, int t, int n, int& c) {
   c = cl[t];
   return c >= 0 && c < n;
@@ -58,39 +108,45 @@ __device__ inline double tri_area(const double p[3][3]) {
 __global__ void __launch_bounds__(kFitThreads)
 k_fit_mean(MeshDev M, const int32_t* __restrict__ cl, int n, FitScratch s, uint32_t* status) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= M.nt) return;
-  int c;
-  if (!tri_cluster_of(cl, t, n, c)) return;
+  int c = -1;
   double p[3][3];
-  if (!load_tri(M, t, p, status)) return;
-  const double A = tri_area(p);
-  atomicAdd(&s.S[c], A);
-  for (int d = 0; d < 3; ++d) atomicAdd(&s.M[3 * c + d], A * (p[0][d] + p[1][d] + p[2][d]) / 3.0);
+  if (t < M.nt && tri_cluster_of(cl, t, n, c) && !load_tri(M, t, p, status)) c = -1;
+  if (t >= M.nt) c = -1;
+  double a1[1] = {0.0}, m3[3] = {0.0, 0.0, 0.0};
+  if (c >= 0) {
+    const double A = tri_area(p);
+    a1[0] = A;
+    for (int d = 0; d < 3; ++d) m3[d] = A * (p[0][d] + p[1][d] + p[2][d]) / 3.0;
+  }
+  wave_cluster_add<1>(s.S, c, a1);
+  wave_cluster_add<3>(s.M, c, m3);
 }
 
 __global__ void __launch_bounds__(kFitThreads)
 k_fit_cov(MeshDev M, const int32_t* __restrict__ cl, int n, FitScratch s, uint32_t* status) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= M.nt) return;
-  int c;
-  if (!tri_cluster_of(cl, t, n, c)) return;
+  int c = -1;
   double p[3][3];
-  if (!load_tri(M, t, p, status)) return;
-  const double A = tri_area(p);
-  const double S = s.S[c];
-  if (!(S > 0.0)) return;
-  double mu[3], m[3];
-  for (int d = 0; d < 3; ++d) mu[d] = s.M[3 * c + d] / S;
-  for (int k = 0; k < 3; ++k)
-    for (int d = 0; d < 3; ++d) p[k][d] -= mu[d];
-  for (int d = 0; d < 3; ++d) m[d] = (p[0][d] + p[1][d] + p[2][d]) / 3.0;
-  const int ii[6] = {0, 1, 2, 0, 0, 1};
-  const int jj[6] = {0, 1, 2, 1, 2, 2};
-  for (int e = 0; e < 6; ++e) {
-    const int i = ii[e], j = jj[e];
-    const double E = (9.0 * m[i] * m[j] + p[0][i] * p[0][j] + p[1][i] * p[1][j] + p[2][i] * p[2][j]) / 12.0;
-    atomicAdd(&s.C[6 * c + e], A * E);
+  if (t < M.nt && tri_cluster_of(cl, t, n, c) && !load_tri(M, t, p, status)) c = -1;
+  if (t >= M.nt) c = -1;
+  if (c >= 0 && !(s.S[c] > 0.0)) c = -1;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  if (c >= 0) {
+    const double A = tri_area(p);
+    const double S = s.S[c];
+    double mu[3], m[3];
+    for (int d = 0; d < 3; ++d) mu[d] = s.M[3 * c + d] / S;
+    for (int k = 0; k < 3; ++k)
+      for (int d = 0; d < 3; ++d) p[k][d] -= mu[d];
+    for (int d = 0; d < 3; ++d) m[d] = (p[0][d] + p[1][d] + p[2][d]) / 3.0;
+    const int ii[6] = {0, 1, 2, 0, 0, 1};
+    const int jj[6] = {0, 1, 2, 1, 2, 2};
+    for (int e = 0; e < 6; ++e) {
+      const int i = ii[e], j = jj[e];
+      acc[e] = A * ((9.0 * m[i] * m[j] + p[0][i] * p[0][j] + p[1][i] * p[1][j] + p[2][i] * p[2][j]) / 12.0);
+    }
   }
+  wave_cluster_add<6>(s.C, c, acc);
 }
 
 // Cyclic Jacobi on a symmetric 3x3 matrix a (float64, in place); v = eigenvectors (columns).
@@ -194,22 +250,26 @@ __global__ void __launch_bounds__(kFitThreads)
 k_fit_extent(MeshDev M, const int32_t* __restrict__ cl, int n, const obbv_box* __restrict__ boxes, FitScratch s,
              uint32_t* status) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= M.nt) return;
-  int c;
-  if (!tri_cluster_of(cl, t, n, c)) return;
+  int c = -1;
   double p[3][3];
-  if (!load_tri(M, t, p, status)) return;
-  const float* ax = reinterpret_cast<const float*>(boxes + c) + 3;
-  for (int r = 0; r < 3; ++r) {
-    double lo = 1e300, hi = -1e300;
-    for (int k = 0; k < 3; ++k) {
-      const double x = (double)ax[3 * r] * p[k][0] + (double)ax[3 * r + 1] * p[k][1] + (double)ax[3 * r + 2] * p[k][2];
-      lo = fmin(lo, x);
-      hi = fmax(hi, x);
+  if (t < M.nt && tri_cluster_of(cl, t, n, c) && !load_tri(M, t, p, status)) c = -1;
+  if (t >= M.nt) c = -1;
+  uint64_t kl[3] = {~0ull, ~0ull, ~0ull}, kh[3] = {0ull, 0ull, 0ull};
+  if (c >= 0) {
+    const float* ax = reinterpret_cast<const float*>(boxes + c) + 3;
+    for (int r = 0; r < 3; ++r) {
+      double lo = 1e300, hi = -1e300;
+      for (int k = 0; k < 3; ++k) {
+        const double x =
+            (double)ax[3 * r] * p[k][0] + (double)ax[3 * r + 1] * p[k][1] + (double)ax[3 * r + 2] * p[k][2];
+        lo = fmin(lo, x);
+        hi = fmax(hi, x);
+      }
+      kl[r] = ordered_key(lo);
+      kh[r] = ordered_key(hi);
     }
-    atomicMin((unsigned long long*)&s.lo[3 * c + r], (unsigned long long)ordered_key(lo));
-    atomicMax((unsigned long long*)&s.hi[3 * c + r], (unsigned long long)ordered_key(hi));
   }
+  wave_cluster_minmax<3>(s.lo, s.hi, c, kl, kh);
 }
 
 __global__ void k_fit_box(int n, FitScratch s, obbv_box* __restrict__ out) {

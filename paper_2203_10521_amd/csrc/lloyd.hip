@@ -1,0 +1,1095 @@
+// Same-layer Lloyd clustering (Sec. 4.2.1) and the multigrid-like hierarchy
+// (Sec. 4.2.2) on top of the outer-volume kernels.
+//
+// The flood's decisions need a priority queue and mesh adjacency; they run on
+// the host.  Every outer-volume value they need -- grown candidate boxes of a
+// round of every group of a level, union boxes, parameter-update candidates --
+// is evaluated by one batched obbv outer-volume launch sequence per round, so the
+// device sees a few large batches per round instead of one box at a time.
+//
+// Reading of the paper (shared with the CPU oracle):
+//   * a box has fixed centre c and axes Q during the partition; its half extents
+//     enclose its elements symmetrically: h = max |Q (v - c)| over the vertices;
+//   * boxes are stored as float32: centre and axes rounded to nearest, half
+//     extents rounded up;
+//   * key of an element = distance from its centroid to the nearest centre of its
+//     group; each box starts from the element nearest its centre;
+//   * a round pops the K smallest-key frontier elements of every group; for each
+//     (element, box) the grown box is evaluated unless it equals the current box;
+//     dOBV = |OBV(grown) - OBV(current)| (Eq. 12); argmin with ties to the nearer
+//     centre, then the lower index (Eq. 13); boxes grow to the union of what they
+//     received; unreachable elements are assigned one by one at the end;
+//   * parameter update: tight box for the axes, +-delta rotations about each
+//     local axis, gradient, line search at {8, 4, 2, 1, 0.5} delta along -g,
+//     keep the best if it lowers OBV.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <numeric>
+#include <queue>
+#include <vector>
+
+#include "common.h"
+
+namespace obbv {
+
+int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                      const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                      const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
+                      int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s);
+int fit_impl(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters, obbv_box* out_boxes,
+             double* out_eigvals, hipStream_t st);
+
+namespace {
+
+struct HBox {
+  float c[3];
+  float Q[9];
+  float h[3];
+};
+
+inline float f32_up(double x) {
+  float y = (float)x;
+  if ((double)y < x) y = nextafterf(y, INFINITY);
+  return y;
+}
+
+inline bool same_h(const float a[3], const float b[3]) { return a[0] == b[0] && a[1] == b[1] && a[2] == b[2]; }
+
+// ---------------------------------------------------------------------------
+// batched outer-volume evaluation on the device
+// ---------------------------------------------------------------------------
+struct Evaluator {
+  obbv_mesh mesh{};
+  obbv_ov_params params{};
+  hipStream_t stream = nullptr;
+  char* dbuf = nullptr;
+  size_t cap = 0;
+  std::vector<obbv_box> hb;
+  std::vector<uint32_t> hk;
+  int64_t evals = 0;
+  int64_t calls = 0;
+
+  ~Evaluator() {
+    if (dbuf) (void)hipFree(dbuf);
+  }
+
+  int eval(const std::vector<HBox>& boxes, const std::vector<uint32_t>& keys, std::vector<double>& out) {
+    const size_t n = boxes.size();
+    out.assign(n, 0.0);
+    if (n == 0) return OBBV_OK;
+    const size_t need = n * (sizeof(obbv_box) + 8 + 8) + 1024;
+    if (need > cap) {
+      if (dbuf) {
+        OBBV_HIP(hipStreamSynchronize(stream));
+        OBBV_HIP(hipFree(dbuf));
+        dbuf = nullptr;
+      }
+      cap = std::max(need * 2, (size_t)1 << 16);
+      if (hipMalloc((void**)&dbuf, cap) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = 0;
+        set_error("hipMalloc failed for the Lloyd evaluation buffer");
+        return OBBV_ERR_OOM;
+      }
+    }
+    hb.resize(n);
+    hk.assign(keys.begin(), keys.end());
+    for (size_t i = 0; i < n; ++i) {
+      std::memcpy(hb[i].center, boxes[i].c, 12);
+      std::memcpy(hb[i].axes, boxes[i].Q, 36);
+      std::memcpy(hb[i].half, boxes[i].h, 12);
+    }
+    obbv_box* db = (obbv_box*)dbuf;
+    size_t off = (n * sizeof(obbv_box) + 255) & ~(size_t)255;
+    uint32_t* dk = (uint32_t*)(dbuf + off);
+    off += (n * 4 + 255) & ~(size_t)255;
+    double* dout = (double*)(dbuf + off);
+    OBBV_HIP(hipMemcpyAsync(db, hb.data(), n * sizeof(obbv_box), hipMemcpyHostToDevice, stream));
+    OBBV_HIP(hipMemcpyAsync(dk, hk.data(), n * 4, hipMemcpyHostToDevice, stream));
+    OBBV_RET(outer_volume_impl(&mesh, 1, db, nullptr, dk, (int32_t)n, &params, dout, nullptr, nullptr, nullptr,
+                               nullptr, stream));
+    OBBV_HIP(hipMemcpyAsync(out.data(), dout, n * 8, hipMemcpyDeviceToHost, stream));
+    OBBV_HIP(hipStreamSynchronize(stream));
+    evals += (int64_t)n;
+    ++calls;
+    return OBBV_OK;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// host copy of the mesh: vertices, triangles, centroids, edge adjacency
+// ---------------------------------------------------------------------------
+struct HostMesh {
+  std::vector<float> V;
+  std::vector<int32_t> F;
+  int nv = 0, nt = 0;
+  std::vector<double> cen;            // [nt][3]
+  std::vector<int32_t> adj_off, adj;  // CSR of edge-adjacent triangles (sorted)
+
+  int load(const obbv_mesh* m, hipStream_t s) {
+    nv = m->n_vertices;
+    nt = m->n_triangles;
+    V.resize((size_t)nv * 3);
+    F.resize((size_t)nt * 3);
+    if (nv) OBBV_HIP(hipMemcpyAsync(V.data(), m->vertices, V.size() * 4, hipMemcpyDeviceToHost, s));
+    if (nt) OBBV_HIP(hipMemcpyAsync(F.data(), m->triangles, F.size() * 4, hipMemcpyDeviceToHost, s));
+    OBBV_HIP(hipStreamSynchronize(s));
+    for (int32_t x : F)
+      if (x < 0 || x >= nv) {
+        set_error("triangle index out of range");
+        return OBBV_ERR_INVALID_ARG;
+      }
+    cen.resize((size_t)nt * 3);
+    for (int t = 0; t < nt; ++t)
+      for (int d = 0; d < 3; ++d) {
+        const double a = V[3 * F[3 * t + 0] + d], b = V[3 * F[3 * t + 1] + d], c = V[3 * F[3 * t + 2] + d];
+        cen[3 * t + d] = ((a + b) + c) / 3.0;
+      }
+    // adjacency through sorted undirected edge keys
+    std::vector<std::pair<uint64_t, int32_t>> e;
+    e.reserve((size_t)nt * 3);
+    for (int t = 0; t < nt; ++t)
+      for (int k = 0; k < 3; ++k) {
+        uint32_t a = (uint32_t)F[3 * t + k], b = (uint32_t)F[3 * t + (k + 1) % 3];
+        if (a > b) std::swap(a, b);
+        e.emplace_back(((uint64_t)a << 32) | b, t);
+      }
+    std::sort(e.begin(), e.end());
+    std::vector<std::vector<int32_t>> nb((size_t)nt);
+    for (size_t i = 0; i < e.size();) {
+      size_t j = i;
+      while (j < e.size() && e[j].first == e[i].first) ++j;
+      for (size_t x = i; x < j; ++x)
+        for (size_t y = i; y < j; ++y)
+          if (e[x].second != e[y].second) nb[e[x].second].push_back(e[y].second);
+      i = j;
+    }
+    adj_off.assign((size_t)nt + 1, 0);
+    for (int t = 0; t < nt; ++t) {
+      auto& v = nb[t];
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+      adj_off[t + 1] = adj_off[t] + (int32_t)v.size();
+    }
+    adj.resize(adj_off[nt]);
+    for (int t = 0; t < nt; ++t) std::copy(nb[t].begin(), nb[t].end(), adj.begin() + adj_off[t]);
+    return OBBV_OK;
+  }
+
+  // local coordinates Q (v - c), summed in axis order (float64)
+  inline void local(int vi, const float c[3], const double Q[9], double out[3]) const {
+    const double p0 = (double)V[3 * vi + 0] - (double)c[0];
+    const double p1 = (double)V[3 * vi + 1] - (double)c[1];
+    const double p2 = (double)V[3 * vi + 2] - (double)c[2];
+    for (int r = 0; r < 3; ++r) out[r] = (p0 * Q[3 * r + 0] + p1 * Q[3 * r + 1]) + p2 * Q[3 * r + 2];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// flood elements: single triangles, or units made of several triangles
+// ---------------------------------------------------------------------------
+struct Elements {
+  int n = 0;
+  std::vector<int32_t> tri_off, tris;  // CSR: triangles of each element
+  std::vector<double> cen;             // [n][3] element centroid
+  std::vector<int32_t> adj_off, adj;   // CSR: adjacent elements
+
+  static Elements triangles(const HostMesh& M) {
+    Elements E;
+    E.n = M.nt;
+    E.tri_off.resize((size_t)M.nt + 1);
+    E.tris.resize((size_t)M.nt);
+    for (int t = 0; t <= M.nt; ++t) E.tri_off[t] = t;
+    std::iota(E.tris.begin(), E.tris.end(), 0);
+    E.cen = M.cen;
+    E.adj_off = M.adj_off;
+    E.adj = M.adj;
+    return E;
+  }
+};
+
+// per-axis max over the element's vertices of |Q (v - c)|
+void element_extent(const HostMesh& M, const Elements& E, int e, const HBox& b, double out[3]) {
+  double Q[9];
+  for (int k = 0; k < 9; ++k) Q[k] = b.Q[k];
+  out[0] = out[1] = out[2] = 0.0;
+  for (int x = E.tri_off[e]; x < E.tri_off[e + 1]; ++x) {
+    const int t = E.tris[x];
+    for (int k = 0; k < 3; ++k) {
+      double p[3];
+      M.local(M.F[3 * t + k], b.c, Q, p);
+      for (int r = 0; r < 3; ++r) out[r] = std::max(out[r], std::fabs(p[r]));
+    }
+  }
+}
+
+inline double dist3(const double* a, const float* c) {
+  const double d0 = a[0] - (double)c[0], d1 = a[1] - (double)c[1], d2 = a[2] - (double)c[2];
+  return std::sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+}
+
+// ---------------------------------------------------------------------------
+// one partition step for many groups in lockstep
+// ---------------------------------------------------------------------------
+struct Group {
+  std::vector<int32_t> elems;  // sorted element ids
+  std::vector<int32_t> boxes;  // global box ids; local index = position
+};
+
+struct Counters {
+  int64_t evals = 0, rounds = 0, trivial = 0, moves = 0;
+};
+
+struct PartitionIO {
+  std::vector<HBox>* boxes;        // in: centres / axes; out: grown boxes
+  std::vector<double>* obv;        // out: OBV of the grown boxes
+  std::vector<uint32_t>* slot;     // jitter key per box
+  std::vector<int32_t>* elem_box;  // out: box of each element (-1 = none)
+};
+
+int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Group>& groups, PartitionIO io,
+                    int K, Evaluator& ev, Counters& cnt) {
+  std::vector<HBox>& boxes = *io.boxes;
+  std::vector<double>& obv = *io.obv;
+  std::vector<int32_t>& eb = *io.elem_box;
+  const std::vector<uint32_t>& slot = *io.slot;
+  const int G = (int)groups.size();
+  eb.assign((size_t)E.n, -1);
+  std::vector<int32_t> elem_group((size_t)E.n, -1);
+  for (int g = 0; g < G; ++g)
+    for (int e : groups[g].elems) elem_group[e] = g;
+  using QE = std::pair<double, int32_t>;
+  std::vector<std::priority_queue<QE, std::vector<QE>, std::greater<QE>>> heap((size_t)G);
+  std::vector<char> queued((size_t)E.n, 0);
+  std::vector<double> key((size_t)E.n, 0.0);
+
+  // keys, seeds, initial boxes
+  std::vector<HBox> req_boxes;
+  std::vector<uint32_t> req_keys;
+  std::vector<int32_t> req_box;
+  for (int g = 0; g < G; ++g) {
+    const Group& gr = groups[g];
+    const int b = (int)gr.boxes.size();
+    if (gr.elems.empty() || b == 0) continue;
+    for (int e : gr.elems) {
+      double k = INFINITY;
+      for (int i = 0; i < b; ++i) k = std::min(k, dist3(&E.cen[3 * e], boxes[gr.boxes[i]].c));
+      key[e] = k;
+    }
+    std::vector<char> chosen;  // small: membership via eb
+    for (int i = 0; i < b && i < (int)gr.elems.size(); ++i) {
+      const int bi = gr.boxes[i];
+      int best = -1;
+      double bd = INFINITY;
+      for (int e : gr.elems) {
+        if (eb[e] >= 0) continue;
+        const double d = dist3(&E.cen[3 * e], boxes[bi].c);
+        if (d < bd || (d == bd && e < best)) {
+          bd = d;
+          best = e;
+        }
+      }
+      eb[best] = bi;
+      double ext[3];
+      element_extent(M, E, best, boxes[bi], ext);
+      for (int r = 0; r < 3; ++r) boxes[bi].h[r] = f32_up(ext[r]);
+      req_boxes.push_back(boxes[bi]);
+      req_keys.push_back(slot[bi]);
+      req_box.push_back(bi);
+    }
+  }
+  std::vector<double> vals;
+  OBBV_RET(ev.eval(req_boxes, req_keys, vals));
+  cnt.evals += (int64_t)vals.size();
+  for (size_t x = 0; x < vals.size(); ++x) obv[req_box[x]] = vals[x];
+  for (int g = 0; g < G; ++g)
+    for (int e : groups[g].elems)
+      if (eb[e] >= 0) queued[e] = 1;
+  auto push_neighbours = [&](int e) {
+    const int g = elem_group[e];
+    for (int x = E.adj_off[e]; x < E.adj_off[e + 1]; ++x) {
+      const int n = E.adj[x];
+      if (elem_group[n] == g && eb[n] < 0 && !queued[n]) {
+        queued[n] = 1;
+        heap[g].push({key[n], n});
+      }
+    }
+  };
+  for (int g = 0; g < G; ++g)
+    for (int e : groups[g].elems)
+      if (eb[e] >= 0) push_neighbours(e);
+
+  // one decision round over the given pops of every group
+  struct Cand {
+    int e, g, li;  // element, group, local box index
+    float h[3];
+    bool trivial;
+    double val;
+  };
+  auto round = [&](const std::vector<std::vector<int32_t>>& pops) -> int {
+    std::vector<Cand> cands;
+    req_boxes.clear();
+    req_keys.clear();
+    std::vector<int32_t> req_idx;
+    // a box that already contains the element has dOBV = 0, the minimum: then the
+    // element's other candidates need no evaluation
+    for (int g = 0; g < G; ++g) {
+      const Group& gr = groups[g];
+      const int b = (int)gr.boxes.size();
+      for (int e : pops[g]) {
+        const size_t first = cands.size();
+        bool any_trivial = false;
+        for (int i = 0; i < b; ++i) {
+          const HBox& bx = boxes[gr.boxes[i]];
+          Cand c;
+          c.e = e;
+          c.g = g;
+          c.li = i;
+          double ext[3];
+          element_extent(M, E, e, bx, ext);
+          for (int r = 0; r < 3; ++r) c.h[r] = f32_up(std::max((double)bx.h[r], ext[r]));
+          c.trivial = same_h(c.h, bx.h);
+          c.val = 0.0;
+          if (c.trivial) {
+            ++cnt.trivial;
+            any_trivial = true;
+          }
+          cands.push_back(c);
+        }
+        if (any_trivial) continue;
+        for (int i = 0; i < b; ++i) {
+          HBox gb = boxes[gr.boxes[i]];
+          std::memcpy(gb.h, cands[first + i].h, 12);
+          req_boxes.push_back(gb);
+          req_keys.push_back(slot[gr.boxes[i]]);
+          req_idx.push_back((int32_t)(first + i));
+        }
+      }
+    }
+    std::vector<char> evaluated(cands.size(), 0);
+    for (int32_t x : req_idx) evaluated[x] = 1;
+    OBBV_RET(ev.eval(req_boxes, req_keys, vals));
+    cnt.evals += (int64_t)vals.size();
+    for (size_t x = 0; x < vals.size(); ++x) cands[req_idx[x]].val = vals[x];
+    // decisions
+    std::vector<std::vector<int32_t>> got((size_t)boxes.size());  // candidate index per receiving box
+    std::vector<int32_t> touched;
+    size_t ci = 0;
+    for (int g = 0; g < G; ++g) {
+      const Group& gr = groups[g];
+      const int b = (int)gr.boxes.size();
+      for (int e : pops[g]) {
+        int best = -1;
+        double bd = 0.0, bdist = 0.0;
+        for (int i = 0; i < b; ++i) {
+          const Cand& c = cands[ci + i];
+          const int bi = gr.boxes[i];
+          if (!c.trivial && !evaluated[ci + i]) continue;  // another box contains the element
+          const double d = c.trivial ? 0.0 : std::fabs(c.val - obv[bi]);
+          const double dd = dist3(&E.cen[3 * e], boxes[bi].c);
+          if (best < 0 || d < bd || (d == bd && (dd < bdist || (dd == bdist && i < best)))) {
+            best = i;
+            bd = d;
+            bdist = dd;
+          }
+        }
+        const int bi = gr.boxes[best];
+        eb[e] = bi;
+        ++cnt.moves;
+        if (got[bi].empty()) touched.push_back(bi);
+        got[bi].push_back((int32_t)(ci + best));
+        ci += b;
+      }
+    }
+    // grow the receiving boxes to the union
+    req_boxes.clear();
+    req_keys.clear();
+    std::vector<int32_t> extra;
+    for (int bi : touched) {
+      float hn[3];
+      std::memcpy(hn, cands[got[bi][0]].h, 12);
+      for (size_t x = 1; x < got[bi].size(); ++x)
+        for (int r = 0; r < 3; ++r) hn[r] = std::max(hn[r], cands[got[bi][x]].h[r]);
+      if (same_h(hn, boxes[bi].h)) continue;
+      std::memcpy(boxes[bi].h, hn, 12);
+      bool found = false;
+      for (int cx : got[bi])
+        if (evaluated[cx] && same_h(cands[cx].h, hn)) {
+          obv[bi] = cands[cx].val;
+          found = true;
+          break;
+        }
+      if (!found) {
+        extra.push_back(bi);
+        req_boxes.push_back(boxes[bi]);
+        req_keys.push_back(slot[bi]);
+      }
+    }
+    if (!extra.empty()) {
+      OBBV_RET(ev.eval(req_boxes, req_keys, vals));
+      cnt.evals += (int64_t)vals.size();
+      for (size_t x = 0; x < extra.size(); ++x) obv[extra[x]] = vals[x];
+    }
+    return OBBV_OK;
+  };
+
+  std::vector<std::vector<int32_t>> pops((size_t)G);
+  for (;;) {
+    bool any = false;
+    for (int g = 0; g < G; ++g) {
+      pops[g].clear();
+      while (!heap[g].empty() && (int)pops[g].size() < K) {
+        const int e = heap[g].top().second;
+        heap[g].pop();
+        if (eb[e] < 0) pops[g].push_back(e);
+      }
+      any = any || !pops[g].empty();
+    }
+    if (!any) break;
+    ++cnt.rounds;
+    OBBV_RET(round(pops));
+    for (int g = 0; g < G; ++g)
+      for (int e : pops[g]) push_neighbours(e);
+  }
+  // elements no flood reached: one by one, in index order, all groups in lockstep
+  std::vector<std::vector<int32_t>> left((size_t)G);
+  size_t maxleft = 0;
+  for (int g = 0; g < G; ++g) {
+    if (groups[g].boxes.empty()) continue;
+    for (int e : groups[g].elems)
+      if (eb[e] < 0) left[g].push_back(e);
+    maxleft = std::max(maxleft, left[g].size());
+  }
+  for (size_t p = 0; p < maxleft; ++p) {
+    for (int g = 0; g < G; ++g) {
+      pops[g].clear();
+      if (p < left[g].size()) pops[g].push_back(left[g][p]);
+    }
+    ++cnt.rounds;
+    OBBV_RET(round(pops));
+  }
+  return OBBV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// parameter update
+// ---------------------------------------------------------------------------
+void mat3_mul(const double A[9], const double B[9], double C[9]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = (A[3 * i + 0] * B[0 + j] + A[3 * i + 1] * B[3 + j]) + A[3 * i + 2] * B[6 + j];
+}
+
+void rot_local(int k, double th, double R[9]) {
+  for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  const int a = (k + 1) % 3, b = (k + 2) % 3;
+  const double c = std::cos(th), s = std::sin(th);
+  R[3 * a + a] = c;
+  R[3 * a + b] = -s;
+  R[3 * b + a] = s;
+  R[3 * b + b] = c;
+}
+
+void rodrigues(const double r[3], double R[9]) {
+  const double th = std::sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+  for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  if (th == 0.0) return;
+  const double k[3] = {r[0] / th, r[1] / th, r[2] / th};
+  const double Kx[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+  double K2[9];
+  mat3_mul(Kx, Kx, K2);
+  const double s = std::sin(th), c1 = 1.0 - std::cos(th);
+  for (int i = 0; i < 9; ++i) R[i] = (R[i] + s * Kx[i]) + c1 * K2[i];
+}
+
+// tightest box with axes Q (rounded to float32) around the given vertices
+HBox tight_box(const HostMesh& M, const std::vector<int32_t>& verts, const double Qd[9]) {
+  HBox b;
+  double Q[9];
+  for (int k = 0; k < 9; ++k) {
+    b.Q[k] = (float)Qd[k];
+    Q[k] = (double)b.Q[k];
+  }
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  const float zero[3] = {0.f, 0.f, 0.f};
+  for (int v : verts) {
+    double p[3];
+    M.local(v, zero, Q, p);
+    for (int r = 0; r < 3; ++r) {
+      lo[r] = std::min(lo[r], p[r]);
+      hi[r] = std::max(hi[r], p[r]);
+    }
+  }
+  double mid[3];
+  for (int r = 0; r < 3; ++r) mid[r] = 0.5 * (lo[r] + hi[r]);
+  for (int k = 0; k < 3; ++k) b.c[k] = (float)((Q[0 + k] * mid[0] + Q[3 + k] * mid[1]) + Q[6 + k] * mid[2]);
+  double ext[3] = {0, 0, 0};
+  for (int v : verts) {
+    double p[3];
+    M.local(v, b.c, Q, p);
+    for (int r = 0; r < 3; ++r) ext[r] = std::max(ext[r], std::fabs(p[r]));
+  }
+  for (int r = 0; r < 3; ++r) b.h[r] = f32_up(ext[r]);
+  return b;
+}
+
+// Update every box with a non-empty vertex set; returns the accepted OBV per box.
+int update_boxes(const HostMesh& M, const std::vector<std::vector<int32_t>>& verts, std::vector<HBox>& boxes,
+                 std::vector<double>& obv, const std::vector<uint32_t>& slot, const std::vector<int32_t>& which,
+                 double delta, Evaluator& ev, Counters& cnt) {
+  const double steps[5] = {8.0, 4.0, 2.0, 1.0, 0.5};
+  std::vector<HBox> req;
+  std::vector<uint32_t> keys;
+  for (int bi : which) {
+    double Q[9];
+    for (int k = 0; k < 9; ++k) Q[k] = (double)boxes[bi].Q[k];
+    req.push_back(tight_box(M, verts[bi], Q));
+    keys.push_back(slot[bi]);
+    for (int k = 0; k < 3; ++k)
+      for (int sg = 0; sg < 2; ++sg) {
+        double R[9], Q2[9];
+        rot_local(k, sg == 0 ? delta : -delta, R);
+        mat3_mul(R, Q, Q2);
+        req.push_back(tight_box(M, verts[bi], Q2));
+        keys.push_back(slot[bi]);
+      }
+  }
+  std::vector<double> v1;
+  OBBV_RET(ev.eval(req, keys, v1));
+  cnt.evals += (int64_t)v1.size();
+  std::vector<HBox> req2;
+  std::vector<uint32_t> keys2;
+  std::vector<int32_t> has_line;
+  for (size_t x = 0; x < which.size(); ++x) {
+    const double* v = &v1[7 * x];
+    double g[3];
+    for (int k = 0; k < 3; ++k) g[k] = (v[1 + 2 * k] - v[2 + 2 * k]) / (2.0 * delta);
+    const double gn = std::sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
+    if (gn == 0.0) {
+      has_line.push_back(0);
+      continue;
+    }
+    has_line.push_back(1);
+    double Q[9];
+    for (int k = 0; k < 9; ++k) Q[k] = (double)boxes[which[x]].Q[k];
+    for (double s : steps) {
+      const double r[3] = {s * delta * (-g[0] / gn), s * delta * (-g[1] / gn), s * delta * (-g[2] / gn)};
+      double R[9], Q2[9];
+      rodrigues(r, R);
+      mat3_mul(R, Q, Q2);
+      req2.push_back(tight_box(M, verts[which[x]], Q2));
+      keys2.push_back(slot[which[x]]);
+    }
+  }
+  std::vector<double> v2;
+  OBBV_RET(ev.eval(req2, keys2, v2));
+  cnt.evals += (int64_t)v2.size();
+  size_t li = 0;
+  for (size_t x = 0; x < which.size(); ++x) {
+    const int bi = which[x];
+    HBox best = req[7 * x];
+    double bv = v1[7 * x];
+    if (has_line[x]) {
+      int j = 0;
+      for (int s = 1; s < 5; ++s)
+        if (v2[li + s] < v2[li + j]) j = s;
+      if (v2[li + j] < bv) {
+        best = req2[li + j];
+        bv = v2[li + j];
+      }
+      li += 5;
+    }
+    boxes[bi] = best;
+    obv[bi] = bv;
+  }
+  return OBBV_OK;
+}
+
+std::vector<int32_t> vertex_set(const HostMesh& M, const std::vector<int32_t>& tris, std::vector<char>& mark) {
+  std::vector<int32_t> v;
+  for (int t : tris)
+    for (int k = 0; k < 3; ++k) {
+      const int x = M.F[3 * t + k];
+      if (!mark[x]) {
+        mark[x] = 1;
+        v.push_back(x);
+      }
+    }
+  for (int x : v) mark[x] = 0;
+  std::sort(v.begin(), v.end());
+  return v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Lloyd state behind the C ABI
+// ---------------------------------------------------------------------------
+struct LloydState {
+  HostMesh M;
+  Elements E;
+  Evaluator ev;
+  int K = 32;
+  double delta = 0.02;
+  std::vector<Group> groups;
+  std::vector<HBox> boxes;
+  std::vector<double> obv;
+  std::vector<uint32_t> slot;
+  std::vector<int32_t> tri_box;
+  Counters cnt;
+  double layer_error = 0.0;
+};
+
+// One Lloyd iteration (partition + parameter update) of every group.
+static int lloyd_iterate(LloydState& S) {
+  std::vector<int32_t> eb;
+  PartitionIO io{&S.boxes, &S.obv, &S.slot, &eb};
+  // groups with a single box: every element goes to it, the update fits the tight box
+  std::vector<Group> flood_groups;
+  for (const Group& g : S.groups)
+    if (g.boxes.size() > 1) flood_groups.push_back(g);
+  OBBV_RET(flood_partition(S.M, S.E, flood_groups, io, S.K, S.ev, S.cnt));
+  for (const Group& g : S.groups)
+    if (g.boxes.size() == 1)
+      for (int e : g.elems) eb[e] = g.boxes[0];
+  // triangles of each box
+  std::vector<std::vector<int32_t>> tris(S.boxes.size());
+  S.tri_box.assign((size_t)S.M.nt, -1);
+  for (int e = 0; e < S.E.n; ++e)
+    if (eb[e] >= 0)
+      for (int x = S.E.tri_off[e]; x < S.E.tri_off[e + 1]; ++x) {
+        tris[eb[e]].push_back(S.E.tris[x]);
+        S.tri_box[S.E.tris[x]] = eb[e];
+      }
+  std::vector<std::vector<int32_t>> verts(S.boxes.size());
+  std::vector<char> mark((size_t)S.M.nv, 0);
+  std::vector<int32_t> which;
+  for (size_t b = 0; b < S.boxes.size(); ++b)
+    if (!tris[b].empty()) {
+      verts[b] = vertex_set(S.M, tris[b], mark);
+      which.push_back((int32_t)b);
+    }
+  OBBV_RET(update_boxes(S.M, verts, S.boxes, S.obv, S.slot, which, S.delta, S.ev, S.cnt));
+  S.layer_error = 0.0;
+  for (size_t b = 0; b < S.boxes.size(); ++b) S.layer_error += tris[b].empty() ? 0.0 : S.obv[b];
+  return OBBV_OK;
+}
+
+}  // namespace obbv
+
+using namespace obbv;
+
+extern "C" int obbv_lloyd_create(const obbv_mesh* mesh, const obbv_lloyd_params* p, obbv_lloyd** out) {
+  clear_error();
+  OBBV_ARG(mesh && p && out, "NULL argument");
+  OBBV_ARG(p->R >= 1 && p->R <= 32767, "R must be in [1, 32767]");
+  OBBV_ARG(p->pops_per_round >= 1, "pops_per_round must be >= 1");
+  OBBV_ARG(p->delta > 0.0, "delta must be positive");
+  OBBV_ARG(mesh->n_triangles > 0 && mesh->triangles && mesh->vertices, "empty mesh");
+  LloydState* S = new LloydState();
+  S->ev.mesh = *mesh;
+  S->ev.params.R = p->R;
+  S->ev.params.axis_mask = 7;
+  S->ev.params.seed = p->seed;
+  S->ev.params.tile = p->tile;
+  S->ev.params.flags = 0;
+  S->ev.stream = nullptr;
+  S->K = p->pops_per_round;
+  S->delta = p->delta;
+  int rc = S->M.load(mesh, nullptr);
+  if (rc != OBBV_OK) {
+    delete S;
+    return rc;
+  }
+  S->E = Elements::triangles(S->M);
+  *out = reinterpret_cast<obbv_lloyd*>(S);
+  return OBBV_OK;
+}
+
+extern "C" int obbv_lloyd_set_groups(obbv_lloyd* st, int32_t n_boxes, const int32_t* tri_group,
+                                     const int32_t* box_group, const float* boxes, const uint32_t* box_slot) {
+  clear_error();
+  OBBV_ARG(st && tri_group && box_group && boxes, "NULL argument");
+  OBBV_ARG(n_boxes >= 1, "n_boxes must be >= 1");
+  LloydState& S = *reinterpret_cast<LloydState*>(st);
+  int32_t ng = 0;
+  for (int b = 0; b < n_boxes; ++b) {
+    OBBV_ARG(box_group[b] >= 0, "box_group must be >= 0");
+    ng = std::max(ng, box_group[b] + 1);
+  }
+  S.groups.assign((size_t)ng, Group{});
+  for (int b = 0; b < n_boxes; ++b) S.groups[box_group[b]].boxes.push_back(b);
+  for (int t = 0; t < S.M.nt; ++t) {
+    const int g = tri_group[t];
+    OBBV_ARG(g < ng, "tri_group beyond the last group");
+    if (g >= 0) S.groups[g].elems.push_back(t);
+  }
+  S.boxes.resize((size_t)n_boxes);
+  S.obv.assign((size_t)n_boxes, 0.0);
+  S.slot.resize((size_t)n_boxes);
+  for (int b = 0; b < n_boxes; ++b) {
+    std::memcpy(S.boxes[b].c, boxes + 15 * b, 12);
+    std::memcpy(S.boxes[b].Q, boxes + 15 * b + 3, 36);
+    std::memcpy(S.boxes[b].h, boxes + 15 * b + 12, 12);
+    S.slot[b] = box_slot ? box_slot[b] : (uint32_t)b;
+  }
+  S.tri_box.assign((size_t)S.M.nt, -1);
+  return OBBV_OK;
+}
+
+extern "C" int obbv_lloyd_step(obbv_lloyd* st, void* stream) {
+  clear_error();
+  OBBV_ARG(st, "NULL state");
+  LloydState& S = *reinterpret_cast<LloydState*>(st);
+  OBBV_ARG(!S.groups.empty(), "obbv_lloyd_set_groups was not called");
+  S.ev.stream = (hipStream_t)stream;
+  return lloyd_iterate(S);
+}
+
+extern "C" int obbv_lloyd_get(obbv_lloyd* st, int32_t* tri_box, float* boxes, double* obv, double* layer_error,
+                              int64_t* counters) {
+  clear_error();
+  OBBV_ARG(st, "NULL state");
+  LloydState& S = *reinterpret_cast<LloydState*>(st);
+  if (tri_box) std::memcpy(tri_box, S.tri_box.data(), 4 * (size_t)S.M.nt);
+  if (boxes)
+    for (size_t b = 0; b < S.boxes.size(); ++b) {
+      std::memcpy(boxes + 15 * b, S.boxes[b].c, 12);
+      std::memcpy(boxes + 15 * b + 3, S.boxes[b].Q, 36);
+      std::memcpy(boxes + 15 * b + 12, S.boxes[b].h, 12);
+    }
+  if (obv) std::memcpy(obv, S.obv.data(), 8 * S.obv.size());
+  if (layer_error) *layer_error = S.layer_error;
+  if (counters) {
+    counters[0] = S.cnt.evals;
+    counters[1] = S.cnt.rounds;
+    counters[2] = S.cnt.trivial;
+    counters[3] = S.cnt.moves;
+  }
+  return OBBV_OK;
+}
+
+extern "C" int obbv_lloyd_destroy(obbv_lloyd* st) {
+  clear_error();
+  delete reinterpret_cast<LloydState*>(st);
+  return OBBV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// hierarchy: top-down levels, then multigrid-like up / down sweeps (Sec. 4.2.2)
+// ---------------------------------------------------------------------------
+namespace obbv {
+namespace {
+
+constexpr uint64_t kSeedSalt = 0x243F6A8885A308D3ull;
+
+struct Level {
+  std::vector<HBox> box;
+  std::vector<double> obv;
+  std::vector<int32_t> parent;    // level-local index of the parent node (-1 at the root)
+  std::vector<uint32_t> slot;     // global node id = jitter key
+  std::vector<int32_t> tri_node;  // [nt] level-local node of every triangle
+};
+
+struct Tree {
+  int L = 1, b = 1;
+  std::vector<Level> lv;
+  double error() const {  // Eq. 7 with omega = layers to the leaves (leaf = 1)
+    double e = 0.0;
+    for (int l = 0; l < L; ++l) {
+      double s = 0.0;
+      for (size_t j = 0; j < lv[l].obv.size(); ++j) s += lv[l].obv[j];
+      e += (double)(L - l) * s;
+    }
+    return e;
+  }
+};
+
+// seed triangles of group (level, parent): draws from SplitMix64, duplicates rejected
+std::vector<int32_t> random_seeds(const std::vector<int32_t>& G, int count, uint64_t seed, int level, int parent) {
+  std::vector<int32_t> out;
+  uint64_t draw = 0;
+  while ((int)out.size() < count) {
+    const uint64_t n = ((uint64_t)level << 48) | ((uint64_t)parent << 20) | draw++;
+    const int32_t t = G[(size_t)(splitmix64_at(seed ^ kSeedSalt, n) % (uint64_t)G.size())];
+    if (std::find(out.begin(), out.end(), t) == out.end()) out.push_back(t);
+  }
+  return out;
+}
+
+// run `iters` Lloyd iterations of level l with its current parents; children of a
+// parent are the level-l nodes pointing at it
+int solve_level(LloydState& S, Tree& T, int l, int iters) {
+  Level& C = T.lv[l];
+  const Level& P = T.lv[l - 1];
+  const int np = (int)P.box.size();
+  S.groups.assign((size_t)np, Group{});
+  for (int t = 0; t < S.M.nt; ++t) S.groups[P.tri_node[t]].elems.push_back(t);
+  for (int j = 0; j < (int)C.box.size(); ++j)
+    if (C.parent[j] >= 0 && C.box[j].h[0] >= 0.f) S.groups[C.parent[j]].boxes.push_back(j);
+  // a group keeps at most as many boxes as it has triangles
+  for (auto& g : S.groups)
+    if (g.boxes.size() > g.elems.size()) g.boxes.resize(g.elems.size());
+  S.E = Elements::triangles(S.M);
+  S.boxes = C.box;
+  S.obv = C.obv;
+  S.slot = C.slot;
+  for (int it = 0; it < iters; ++it) OBBV_RET(lloyd_iterate(S));
+  C.box = S.boxes;
+  // nodes that kept no triangles become empty boxes
+  std::vector<char> used(C.box.size(), 0);
+  for (int t = 0; t < S.M.nt; ++t)
+    if (S.tri_box[t] >= 0) used[S.tri_box[t]] = 1;
+  for (size_t j = 0; j < C.box.size(); ++j) {
+    C.obv[j] = used[j] ? S.obv[j] : 0.0;
+    if (!used[j]) C.box[j].h[0] = C.box[j].h[1] = C.box[j].h[2] = 0.f;
+  }
+  for (int t = 0; t < S.M.nt; ++t) C.tri_node[t] = S.tri_box[t];
+  return OBBV_OK;
+}
+
+// bottom-up merge of level l: the level-(l+1) boxes are the units of a Lloyd
+// iteration that re-groups them under the level-l boxes of each grandparent
+int merge_level(LloydState& S, Tree& T, int l) {
+  Level& A = T.lv[l];          // merged level
+  Level& U = T.lv[l + 1];      // units
+  const Level& G = T.lv[l - 1];
+  const int nu = (int)U.box.size();
+  // elements = units with triangles
+  Elements E;
+  std::vector<int32_t> unit_of_elem, elem_of_unit((size_t)nu, -1);
+  std::vector<std::vector<int32_t>> ut((size_t)nu);
+  for (int t = 0; t < S.M.nt; ++t)
+    if (U.tri_node[t] >= 0) ut[U.tri_node[t]].push_back(t);
+  E.tri_off.push_back(0);
+  for (int u = 0; u < nu; ++u) {
+    if (ut[u].empty()) continue;
+    elem_of_unit[u] = E.n++;
+    unit_of_elem.push_back(u);
+    for (int t : ut[u]) E.tris.push_back(t);
+    E.tri_off.push_back((int32_t)E.tris.size());
+    for (int k = 0; k < 3; ++k) E.cen.push_back((double)U.box[u].c[k]);
+  }
+  // unit adjacency: a mesh edge joins triangles of the two units
+  std::vector<std::vector<int32_t>> nb((size_t)E.n);
+  for (int t = 0; t < S.M.nt; ++t) {
+    const int a = U.tri_node[t] >= 0 ? elem_of_unit[U.tri_node[t]] : -1;
+    if (a < 0) continue;
+    for (int x = S.M.adj_off[t]; x < S.M.adj_off[t + 1]; ++x) {
+      const int u2 = U.tri_node[S.M.adj[x]];
+      const int c = u2 >= 0 ? elem_of_unit[u2] : -1;
+      if (c >= 0 && c != a) nb[a].push_back(c);
+    }
+  }
+  E.adj_off.assign((size_t)E.n + 1, 0);
+  for (int e = 0; e < E.n; ++e) {
+    std::sort(nb[e].begin(), nb[e].end());
+    nb[e].erase(std::unique(nb[e].begin(), nb[e].end()), nb[e].end());
+    E.adj_off[e + 1] = E.adj_off[e] + (int32_t)nb[e].size();
+    for (int c : nb[e]) E.adj.push_back(c);
+  }
+  // groups: grandparents; their boxes are the level-l nodes under them
+  const int ng = (int)G.box.size();
+  S.groups.assign((size_t)ng, Group{});
+  for (int e = 0; e < E.n; ++e) {
+    const int u = unit_of_elem[e];
+    const int a = U.parent[u];
+    S.groups[A.parent[a]].elems.push_back(e);
+  }
+  for (int j = 0; j < (int)A.box.size(); ++j)
+    if (A.parent[j] >= 0 && A.obv.size() && (A.box[j].h[0] > 0.f || A.box[j].h[1] > 0.f))
+      S.groups[A.parent[j]].boxes.push_back(j);
+  for (auto& g : S.groups)
+    if (g.boxes.size() > g.elems.size()) g.boxes.resize(g.elems.size());
+  S.E = std::move(E);
+  S.boxes = A.box;
+  S.obv = A.obv;
+  S.slot = A.slot;
+  std::vector<int32_t> eb;
+  PartitionIO io{&S.boxes, &S.obv, &S.slot, &eb};
+  std::vector<Group> fg;
+  for (const Group& g : S.groups)
+    if (g.boxes.size() > 1) fg.push_back(g);
+  OBBV_RET(flood_partition(S.M, S.E, fg, io, S.K, S.ev, S.cnt));
+  for (const Group& g : S.groups)
+    if (g.boxes.size() == 1)
+      for (int e : g.elems) eb[e] = g.boxes[0];
+  // new parents of the units, triangles of the merged boxes, box update
+  std::vector<std::vector<int32_t>> tris(A.box.size());
+  for (int e = 0; e < S.E.n; ++e) {
+    if (eb[e] < 0) continue;
+    U.parent[unit_of_elem[e]] = eb[e];
+    for (int x = S.E.tri_off[e]; x < S.E.tri_off[e + 1]; ++x) tris[eb[e]].push_back(S.E.tris[x]);
+  }
+  std::vector<std::vector<int32_t>> verts(A.box.size());
+  std::vector<char> mark((size_t)S.M.nv, 0);
+  std::vector<int32_t> which;
+  for (size_t j = 0; j < A.box.size(); ++j)
+    if (!tris[j].empty()) {
+      verts[j] = vertex_set(S.M, tris[j], mark);
+      which.push_back((int32_t)j);
+    }
+  OBBV_RET(update_boxes(S.M, verts, S.boxes, S.obv, S.slot, which, S.delta, S.ev, S.cnt));
+  A.box = S.boxes;
+  for (size_t j = 0; j < A.box.size(); ++j) {
+    A.obv[j] = tris[j].empty() ? 0.0 : S.obv[j];
+    if (tris[j].empty()) A.box[j].h[0] = A.box[j].h[1] = A.box[j].h[2] = 0.f;
+  }
+  for (int t = 0; t < S.M.nt; ++t) A.tri_node[t] = U.tri_node[t] >= 0 ? U.parent[U.tri_node[t]] : -1;
+  return OBBV_OK;
+}
+
+}  // namespace
+}  // namespace obbv
+
+extern "C" int obbv_build_hierarchy(const obbv_mesh* mesh, const obbv_hier_params* p, float* out_boxes,
+                                    double* out_obv, int32_t* out_parent, int32_t* out_tri_node, double* out_e,
+                                    int64_t* out_counters, void* stream) {
+  clear_error();
+  OBBV_ARG(mesh && p, "NULL argument");
+  OBBV_ARG(p->levels >= 1 && p->levels <= 12, "levels must be in [1, 12]");
+  OBBV_ARG(p->branching >= 1, "branching must be >= 1");
+  OBBV_ARG(p->iters >= 1 && p->sweeps >= 0, "iters >= 1 and sweeps >= 0");
+  int64_t n_nodes = 0, w = 1;
+  for (int l = 0; l < p->levels; ++l, w *= p->branching) n_nodes += w;
+  OBBV_ARG(n_nodes < (1 << 24), "too many nodes");
+  obbv_lloyd_params lp{p->R, p->tile, p->seed, p->pops_per_round, 0, p->delta};
+  obbv_lloyd* handle = nullptr;
+  OBBV_RET(obbv_lloyd_create(mesh, &lp, &handle));
+  std::unique_ptr<LloydState> S(reinterpret_cast<LloydState*>(handle));
+  hipStream_t s = (hipStream_t)stream;
+  S->ev.stream = s;
+  const int nt = S->M.nt;
+  Tree T;
+  T.L = p->levels;
+  T.b = p->branching;
+  T.lv.resize((size_t)T.L);
+  // root: covariance fit of all triangles, then parameter updates
+  {
+    Level& R0 = T.lv[0];
+    int32_t* dcl = nullptr;
+    obbv_box* dbox = nullptr;
+    OBBV_HIP(hipMalloc(&dcl, 4 * (size_t)nt));
+    OBBV_HIP(hipMalloc(&dbox, sizeof(obbv_box)));
+    OBBV_HIP(hipMemsetAsync(dcl, 0, 4 * (size_t)nt, s));
+    int rc = fit_impl(mesh, dcl, 1, dbox, nullptr, s);
+    obbv_box hb;
+    if (rc == OBBV_OK) rc = hipMemcpyAsync(&hb, dbox, sizeof(hb), hipMemcpyDeviceToHost, s) == hipSuccess ? 0 : OBBV_ERR_HIP;
+    if (rc == OBBV_OK) rc = hipStreamSynchronize(s) == hipSuccess ? 0 : OBBV_ERR_HIP;
+    (void)hipFree(dcl);
+    (void)hipFree(dbox);
+    OBBV_RET(rc);
+    HBox rb;
+    std::memcpy(rb.c, hb.center, 12);
+    std::memcpy(rb.Q, hb.axes, 36);
+    std::memcpy(rb.h, hb.half, 12);
+    R0.box = {rb};
+    R0.obv = {0.0};
+    R0.parent = {-1};
+    R0.slot = {0u};
+    R0.tri_node.assign((size_t)nt, 0);
+    S->groups.assign(1, Group{});
+    for (int t = 0; t < nt; ++t) S->groups[0].elems.push_back(t);
+    S->groups[0].boxes = {0};
+    S->boxes = R0.box;
+    S->obv = R0.obv;
+    S->slot = R0.slot;
+    for (int it = 0; it < p->iters; ++it) OBBV_RET(lloyd_iterate(*S));
+    R0.box = S->boxes;
+    R0.obv = S->obv;
+  }
+  // top-down: each level splits every parent's triangles among `branching` children
+  uint32_t node_base = 1;
+  for (int l = 1; l < T.L; ++l) {
+    const Level& P = T.lv[l - 1];
+    Level& C = T.lv[l];
+    const int np = (int)P.box.size();
+    const int nc = np * T.b;
+    C.box.assign((size_t)nc, HBox{});
+    C.obv.assign((size_t)nc, 0.0);
+    C.parent.assign((size_t)nc, -1);
+    C.slot.resize((size_t)nc);
+    C.tri_node.assign((size_t)nt, -1);
+    std::vector<std::vector<int32_t>> G((size_t)np);
+    for (int t = 0; t < nt; ++t) G[P.tri_node[t]].push_back(t);
+    for (int q = 0; q < np; ++q) {
+      const int nseed = std::min<int>(T.b, (int)G[q].size());
+      std::vector<int32_t> seeds = nseed ? random_seeds(G[q], nseed, p->seed, l, q) : std::vector<int32_t>{};
+      for (int k = 0; k < T.b; ++k) {
+        const int j = q * T.b + k;
+        C.parent[j] = q;
+        C.slot[j] = node_base + (uint32_t)j;
+        HBox& bx = C.box[j];
+        std::memcpy(bx.Q, P.box[q].Q, 36);
+        if (k < nseed) {
+          for (int d = 0; d < 3; ++d) bx.c[d] = (float)S->M.cen[3 * seeds[k] + d];
+          bx.h[0] = bx.h[1] = bx.h[2] = 0.f;
+        } else {  // more children than triangles: an empty node
+          std::memcpy(bx.c, P.box[q].c, 12);
+          bx.h[0] = bx.h[1] = bx.h[2] = -1.f;
+        }
+      }
+    }
+    OBBV_RET(solve_level(*S, T, l, p->iters));
+    for (auto& bx : C.box)
+      if (bx.h[0] < 0.f) bx.h[0] = bx.h[1] = bx.h[2] = 0.f;
+    node_base += (uint32_t)nc;
+  }
+  double e = T.error();
+  if (out_e) out_e[0] = e;
+  // sweeps: bottom-up merges while Eq. 7 improves, then top-down re-solves
+  for (int sw = 0; sw < p->sweeps; ++sw) {
+    int top = T.L;  // highest level changed by the up pass
+    for (int l = T.L - 2; l >= 1; --l) {
+      const Tree saved = T;
+      OBBV_RET(merge_level(*S, T, l));
+      const double e2 = T.error();
+      if (e2 < e) {
+        e = e2;
+        top = l;
+      } else {
+        T = saved;
+        break;
+      }
+    }
+    for (int l = std::max(1, top + 1); l < T.L; ++l) {
+      const Tree saved = T;
+      OBBV_RET(solve_level(*S, T, l, p->iters));
+      const double e2 = T.error();
+      if (e2 < e)
+        e = e2;
+      else
+        T = saved;
+    }
+    if (out_e) out_e[1 + sw] = e;
+  }
+  // outputs, level-major global node numbering
+  int64_t g0 = 0;
+  for (int l = 0; l < T.L; ++l) {
+    const Level& Lv = T.lv[l];
+    const int64_t pbase = l > 0 ? g0 - (int64_t)T.lv[l - 1].box.size() : 0;
+    for (size_t j = 0; j < Lv.box.size(); ++j) {
+      const int64_t g = g0 + (int64_t)j;
+      if (out_boxes) {
+        std::memcpy(out_boxes + 15 * g, Lv.box[j].c, 12);
+        std::memcpy(out_boxes + 15 * g + 3, Lv.box[j].Q, 36);
+        std::memcpy(out_boxes + 15 * g + 12, Lv.box[j].h, 12);
+      }
+      if (out_obv) out_obv[g] = Lv.obv[j];
+      if (out_parent) out_parent[g] = Lv.parent[j] >= 0 ? (int32_t)(pbase + Lv.parent[j]) : -1;
+    }
+    if (out_tri_node)
+      for (int t = 0; t < nt; ++t)
+        out_tri_node[(int64_t)l * nt + t] = Lv.tri_node[t] >= 0 ? (int32_t)(g0 + Lv.tri_node[t]) : -1;
+    g0 += (int64_t)Lv.box.size();
+  }
+  if (out_counters) {
+    out_counters[0] = S->cnt.evals;
+    out_counters[1] = S->cnt.rounds;
+    out_counters[2] = S->cnt.trivial;
+    out_counters[3] = S->cnt.moves;
+  }
+  return OBBV_OK;
+}

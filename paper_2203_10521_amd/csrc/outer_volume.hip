@@ -15,6 +15,7 @@
 //   k_finalize           float64 OBV per box
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "common.h"
@@ -24,6 +25,7 @@ namespace {
 
 constexpr int kCullThreads = 256;
 constexpr int kTestThreads = 64;
+constexpr int kTestChunk = 256;  // records per ray-test work item
 
 struct BoxRegs {
   float Q[9];
@@ -246,6 +248,16 @@ __global__ void k_choose_side(const int32_t* __restrict__ side_cnt, int nbw, int
   rec_cnt[i] = mirror ? dn : up;
 }
 
+// Work items of the test pass: every non-empty tile bin is cut into chunks of at
+// most `chunk` records, so no wave walks a much longer list than the others.
+__global__ void k_chunk_count(const int64_t* __restrict__ bin_off, int64_t n_tiles, int chunk,
+                              int32_t* __restrict__ nchunk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int64_t n = bin_off[t + 1] - bin_off[t];
+  nchunk[t] = (int32_t)((n + chunk - 1) / chunk);
+}
+
 // Is the triangle kept on the chosen side?  (Mirrored frames flip z, so the
 // kept half prism is always "above the slab bottom" in the cast frame.)
 __device__ inline bool kept(const CastTri& tr, const CastFrame& f) {
@@ -254,29 +266,51 @@ __device__ inline bool kept(const CastTri& tr, const CastFrame& f) {
   return zmax > -f.hw;
 }
 
+// Tile counters of one work item (one box, 256 triangles, three axes) are
+// aggregated in LDS when they fit (3 * TT <= kLdsTiles) and flushed with one
+// global atomic per non-zero tile.
+constexpr int kLdsTiles = 3 * 1024;
+
 __global__ void __launch_bounds__(kCullThreads)
 k_tile_count(CullArgs a, const int32_t* __restrict__ side, int32_t* __restrict__ tile_cnt) {
+  __shared__ int32_t cnt[kLdsTiles];
   const int64_t total = a.chunk_off[a.n_boxes];
   const int TT = a.tpe * a.tpe;
+  const bool lds = 3 * TT <= kLdsTiles;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item_box(a.chunk_off, a.n_boxes, item);
     const BoxRegs B = load_box(a.boxes, b);
     if (box_state(B) != 0) continue;
+    if (lds) {
+      for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) cnt[k] = 0;
+      __syncthreads();
+    }
     const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    if (!(t < M.nt && load_tri_local(M, t, B, P, a.status))) continue;
-    for (int w = 0; w < 3; ++w) {
-      if (!((a.axis_mask >> w) & 1u)) continue;
-      const int bw = b * 3 + w;
-      const CastFrame f = cast_frame(B, w, a.R);
-      const CastTri tr = cast_tri(P, w, f, side[bw] != 0);
-      if (!kept(tr, f)) continue;
-      int ti0, ti1, tj0, tj1;
-      tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
-      int32_t* base = tile_cnt + (int64_t)bw * TT;
-      for (int tj = tj0; tj <= tj1; ++tj)
-        for (int ti = ti0; ti <= ti1; ++ti) atomicAdd(&base[tj * a.tpe + ti], 1);
+    if (t < M.nt && load_tri_local(M, t, B, P, a.status)) {
+      for (int w = 0; w < 3; ++w) {
+        if (!((a.axis_mask >> w) & 1u)) continue;
+        const int bw = b * 3 + w;
+        const CastFrame f = cast_frame(B, w, a.R);
+        const CastTri tr = cast_tri(P, w, f, side[bw] != 0);
+        if (!kept(tr, f)) continue;
+        int ti0, ti1, tj0, tj1;
+        tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
+        for (int tj = tj0; tj <= tj1; ++tj)
+          for (int ti = ti0; ti <= ti1; ++ti) {
+            if (lds)
+              atomicAdd(&cnt[w * TT + tj * a.tpe + ti], 1);
+            else
+              atomicAdd(&tile_cnt[(int64_t)bw * TT + tj * a.tpe + ti], 1);
+          }
+      }
+    }
+    if (lds) {
+      __syncthreads();
+      for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads)
+        if (cnt[k]) atomicAdd(&tile_cnt[(int64_t)(b * 3 + k / TT) * TT + (k % TT)], cnt[k]);
+      __syncthreads();
     }
   }
 }
@@ -333,12 +367,19 @@ __device__ inline void make_record(const CastTri& t, bool mirror, float hw, floa
   out[3] = make_float4((float)lo, (float)hi, 0.0f, 0.0f);
 }
 
+// Bin slots: every (tile) of the work item first counts its entries in LDS,
+// then reserves a contiguous range of its bin with one global atomic; the
+// entries then take positions in that range (their order inside a bin does
+// not matter: the ray sums are exact integers).
 __global__ void __launch_bounds__(kCullThreads)
 k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict__ rec_off,
         const int32_t* __restrict__ rec_cnt, int32_t* __restrict__ rec_cur, const int64_t* __restrict__ bin_off,
         int32_t* __restrict__ bin_cur, float4* __restrict__ recs, int32_t* __restrict__ bins) {
+  __shared__ int32_t cnt[kLdsTiles];
+  __shared__ int32_t base_pos[kLdsTiles];
   const int64_t total = a.chunk_off[a.n_boxes];
   const int TT = a.tpe * a.tpe;
+  const bool lds = 3 * TT <= kLdsTiles;
   const int lane = threadIdx.x & 63;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item_box(a.chunk_off, a.n_boxes, item);
@@ -348,6 +389,30 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
     const bool ok = t < M.nt && load_tri_local(M, t, B, P, a.status);
+    if (lds) {
+      // pass 1: count this item's entries per tile
+      for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) cnt[k] = 0;
+      __syncthreads();
+      if (ok)
+        for (int w = 0; w < 3; ++w) {
+          if (!((a.axis_mask >> w) & 1u)) continue;
+          const CastFrame f = cast_frame(B, w, a.R);
+          const CastTri tr = cast_tri(P, w, f, side[b * 3 + w] != 0);
+          if (!kept(tr, f)) continue;
+          int ti0, ti1, tj0, tj1;
+          tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
+          for (int tj = tj0; tj <= tj1; ++tj)
+            for (int ti = ti0; ti <= ti1; ++ti) atomicAdd(&cnt[w * TT + tj * a.tpe + ti], 1);
+        }
+      __syncthreads();
+      // reserve one range per non-zero tile
+      for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) {
+        const int c = cnt[k];
+        base_pos[k] = c ? atomicAdd(&bin_cur[(int64_t)(b * 3 + k / TT) * TT + (k % TT)], c) : 0;
+        cnt[k] = 0;
+      }
+      __syncthreads();
+    }
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       if (!((a.axis_mask >> w) & 1u)) continue;
@@ -380,13 +445,15 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
       for (int tj = tj0; tj <= tj1; ++tj)
         for (int ti = ti0; ti <= ti1; ++ti) {
           const int64_t tl = tbase + tj * a.tpe + ti;
-          const int pos = atomicAdd(&bin_cur[tl], 1);
+          const int lt = w * TT + tj * a.tpe + ti;
+          const int pos = lds ? base_pos[lt] + atomicAdd(&cnt[lt], 1) : atomicAdd(&bin_cur[tl], 1);
           if (bin_off[tl] + pos < bin_off[tl + 1])
             bins[bin_off[tl] + pos] = (int32_t)slot;
           else
             atomicOr(a.status, OBBV_STATUS_BAD_INDEX);
         }
     }
+    if (lds) __syncthreads();  // cnt / base_pos are reused by the next item
   }
 }
 
@@ -394,6 +461,9 @@ struct TestArgs {
   const obbv_box* boxes;
   const uint32_t* box_key;
   const int64_t* bin_off;
+  const int64_t* chunk_off;  // [nbw * TT + 1] first work item of each tile
+  int64_t n_tiles;
+  int chunk;
   const int32_t* bins;
   const float4* recs;
   unsigned long long* acc;  // [nbw] per-(box, axis) sum of q
@@ -413,14 +483,24 @@ struct TestArgs {
 //   E_k = A_k u + B_k v + C_k (3 x 2 FMA), inside iff min E_k >= 0,
 //   y = D u + E v + F (2 FMA), clamped to the triangle's slab part (med3),
 //   acc += inside ? bits(y) : kMagicBits   -- exact integer accumulation.
-template <int TE, bool STATS>
+template <int TE, bool STATS, bool STAGE>
 __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
   constexpr int NB = TE / 8;
   constexpr int RPL = NB * NB;
   const int TT = a.tpe * a.tpe;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int bw = bid / TT;
-  const int tile = bid - bw * TT;
+  const int64_t item = xcd_remap(blockIdx.x, gridDim.x);
+  // tile of this work item: chunk_off[g] <= item < chunk_off[g + 1]
+  int64_t lo = 0, hi = a.n_tiles;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a.chunk_off[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int64_t g = lo;
+  const int bw = (int)(g / TT);
+  const int tile = (int)(g - (int64_t)bw * TT);
   const int b = bw / 3, w = bw - 3 * (bw / 3);
   if (!((a.axis_mask >> w) & 1u)) return;
   const BoxRegs B = load_box(a.boxes, b);
@@ -455,15 +535,10 @@ __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
     }
   }
 
-  const int64_t k0 = a.bin_off[(int64_t)bw * TT + tile];
-  const int64_t k1 = a.bin_off[(int64_t)bw * TT + tile + 1];
-  for (int64_t k = k0; k < k1; ++k) {
-    const int idx = a.bins[k];
-    if ((unsigned)idx >= (unsigned)a.n_rec) continue;  // only after a flagged write-pass mismatch
-    const float4 r0 = a.recs[4 * (int64_t)idx + 0];
-    const float4 r1 = a.recs[4 * (int64_t)idx + 1];
-    const float4 r2 = a.recs[4 * (int64_t)idx + 2];
-    const float4 r3 = a.recs[4 * (int64_t)idx + 3];
+  const int64_t kb = a.bin_off[g] + (item - a.chunk_off[g]) * a.chunk;
+  const int64_t k0 = kb;
+  const int64_t k1 = min(a.bin_off[g + 1], kb + a.chunk);
+  auto test_record = [&](const float4 r0, const float4 r1, const float4 r2, const float4 r3) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const float u = ru[r], v = rv[r];
@@ -476,6 +551,40 @@ __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
       const bool in = m >= 0.0f;
       acc[r] += in ? __float_as_uint(c) : kMagicBits;
       if (STATS) hits[r] += in ? 1 : 0;
+    }
+  };
+  if (STAGE) {
+    // 64 records at a time: one coalesced record load per lane into LDS, then
+    // every lane reads each record from LDS (same address for the whole wave)
+    __shared__ float4 srec[kTestThreads * 4];
+    for (int64_t base = k0; base < k1; base += kTestThreads) {
+      const int n = (int)min((int64_t)kTestThreads, k1 - base);
+      if (lane < n) {
+        const int idx = a.bins[base + lane];
+        if ((unsigned)idx < (unsigned)a.n_rec) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) srec[4 * lane + q] = a.recs[4 * (int64_t)idx + q];
+        } else {  // a record no ray is inside of (only after a flagged write-pass mismatch)
+          srec[4 * lane + 0] = make_float4(0.f, 0.f, -1.f, 0.f);
+          srec[4 * lane + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+          srec[4 * lane + 2] = make_float4(0.f, 0.f, 0.f, kMagic);
+          srec[4 * lane + 3] = make_float4(kMagic, kMagic, 0.f, 0.f);
+        }
+      }
+      __syncthreads();
+      for (int j = 0; j < n; ++j) test_record(srec[4 * j + 0], srec[4 * j + 1], srec[4 * j + 2], srec[4 * j + 3]);
+      __syncthreads();
+    }
+  } else {
+    for (int64_t k = k0; k < k1; ++k) {
+      const int idx = a.bins[k];
+      if ((unsigned)idx >= (unsigned)a.n_rec) {  // only after a flagged write-pass mismatch
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[r] += kMagicBits;
+        continue;
+      }
+      test_record(a.recs[4 * (int64_t)idx + 0], a.recs[4 * (int64_t)idx + 1], a.recs[4 * (int64_t)idx + 2],
+                  a.recs[4 * (int64_t)idx + 3]);
     }
   }
   const uint32_t nbias = (uint32_t)(k1 - k0) * kMagicBits;
@@ -492,8 +601,8 @@ __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
       const int i = ti * TE + (r % NB) * 8 + (lane & 7);
       const int j = tj * TE + (r / NB) * 8 + (lane >> 3);
       const int64_t o = ((int64_t)bw * a.R + i) * a.R + j;
-      if (a.ray_q) a.ray_q[o] = q;
-      if (a.ray_hits) a.ray_hits[o] = hits[r];
+      if (a.ray_q) atomicAdd(&a.ray_q[o], q);
+      if (a.ray_hits) atomicAdd(&a.ray_hits[o], hits[r]);
     }
   }
   // wave reduction of the 64 lane sums, one 64-bit atomic per wave
@@ -553,13 +662,26 @@ int pinned_totals(int64_t** out) {
 }
 
 template <int TE>
-int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, hipStream_t s) {
-  if (stats)
-    hipLaunchKernelGGL((k_test<TE, true>), dim3((unsigned)nblocks), dim3(kTestThreads), 0, s, ta);
+int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hipStream_t s) {
+  const dim3 g((unsigned)nblocks), b(kTestThreads);
+  if (stats && stage)
+    hipLaunchKernelGGL((k_test<TE, true, true>), g, b, 0, s, ta);
+  else if (stats)
+    hipLaunchKernelGGL((k_test<TE, true, false>), g, b, 0, s, ta);
+  else if (stage)
+    hipLaunchKernelGGL((k_test<TE, false, true>), g, b, 0, s, ta);
   else
-    hipLaunchKernelGGL((k_test<TE, false>), dim3((unsigned)nblocks), dim3(kTestThreads), 0, s, ta);
+    hipLaunchKernelGGL((k_test<TE, false, false>), g, b, 0, s, ta);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
+}
+
+// Record loading of the ray-test loop: 1 = LDS staging (default), 0 = scalar
+// loads.  OBBV_TEST_STAGE overrides it (used to compare the two on a device).
+bool test_stage_choice() {
+  const char* e = getenv("OBBV_TEST_STAGE");
+  if (e && *e) return atoi(e) != 0;
+  return true;
 }
 
 }  // namespace
@@ -613,6 +735,8 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
   const size_t o_reccnt = take(4 * (size_t)nbw);
   const size_t o_recoff = take(8 * (size_t)(nbw + 1));
   const size_t o_binoff = take(8 * (size_t)(nbw * TT + 1));
+  const size_t o_nchunk = take(4 * (size_t)(nbw * TT));
+  const size_t o_chunkoff = take(8 * (size_t)(nbw * TT + 1));
   const size_t o_zero0 = off;  // zero-initialised block
   const size_t o_sidecnt = take(4 * (size_t)nbw * 2);
   const size_t o_reccur = take(4 * (size_t)nbw);
@@ -633,6 +757,8 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
   int32_t* d_reccnt = (int32_t*)(meta + o_reccnt);
   int64_t* d_recoff = (int64_t*)(meta + o_recoff);
   int64_t* d_binoff = (int64_t*)(meta + o_binoff);
+  int32_t* d_nchunk = (int32_t*)(meta + o_nchunk);
+  int64_t* d_chunkoff = (int64_t*)(meta + o_chunkoff);
   int32_t* d_sidecnt = (int32_t*)(meta + o_sidecnt);
   int32_t* d_reccur = (int32_t*)(meta + o_reccur);
   int32_t* d_tilecnt = (int32_t*)(meta + o_tilecnt);
@@ -671,13 +797,20 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
   OBBV_HIP(hipGetLastError());
   OBBV_RET(exclusive_scan_i32_to_i64(d_reccnt, d_recoff, nbw, d_scan, scan_bytes, s));
   OBBV_RET(exclusive_scan_i32_to_i64(d_tilecnt, d_binoff, nbw * TT, d_scan, scan_bytes, s));
+  const int chunk = kTestChunk;
+  hipLaunchKernelGGL(k_chunk_count, dim3(ceil_div(nbw * TT, 256)), dim3(256), 0, s, d_binoff, nbw * TT,
+                     chunk, d_nchunk);
+  OBBV_HIP(hipGetLastError());
+  OBBV_RET(exclusive_scan_i32_to_i64(d_nchunk, d_chunkoff, nbw * TT, d_scan, scan_bytes, s));
 
   int64_t* pin = nullptr;
   OBBV_RET(pinned_totals(&pin));
   OBBV_HIP(hipMemcpyAsync(pin + 0, d_recoff + nbw, 8, hipMemcpyDeviceToHost, s));
   OBBV_HIP(hipMemcpyAsync(pin + 1, d_binoff + nbw * TT, 8, hipMemcpyDeviceToHost, s));
+  OBBV_HIP(hipMemcpyAsync(pin + 2, d_chunkoff + nbw * TT, 8, hipMemcpyDeviceToHost, s));
   OBBV_HIP(hipStreamSynchronize(s));
-  const int64_t n_rec = pin[0], n_bin = pin[1];
+  const int64_t n_rec = pin[0], n_bin = pin[1], n_items = pin[2];
+  OBBV_ARG(n_items < (1ll << 31), "too many ray-test work items in one call; split the boxes");
   OBBV_ARG(n_rec < (1ll << 31), "more than 2^31 triangle records in one call; split the boxes");
 
   if (n_rec > 0) {
@@ -692,6 +825,9 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
     ta.boxes = boxes;
     ta.box_key = box_key;
     ta.bin_off = d_binoff;
+    ta.chunk_off = d_chunkoff;
+    ta.n_tiles = nbw * TT;
+    ta.chunk = chunk;
     ta.bins = (const int32_t*)bins_v;
     ta.recs = (const float4*)recs_v;
     ta.acc = d_acc;
@@ -715,10 +851,13 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
       if (out_ray_q) OBBV_HIP(hipMemsetAsync(out_ray_q, 0, per, s));
       if (out_ray_hits) OBBV_HIP(hipMemsetAsync(out_ray_hits, 0, per, s));
     }
-    if (TE == 8)
-      OBBV_RET(launch_test<8>(ta, nbw * TT, stats, s));
-    else
-      OBBV_RET(launch_test<16>(ta, nbw * TT, stats, s));
+    if (n_items > 0) {
+      const bool stage = test_stage_choice();
+      if (TE == 8)
+        OBBV_RET(launch_test<8>(ta, n_items, stats, stage, s));
+      else
+        OBBV_RET(launch_test<16>(ta, n_items, stats, stage, s));
+    }
     if (prof_token != nullptr || profiling_enabled()) OBBV_RET(profile_record_end(s, prof_token));
   } else if (out_ray_q || out_ray_hits) {
     const size_t per = (size_t)nbw * R * R * 4;

@@ -1,0 +1,114 @@
+"""HIP-evaluated Lloyd step and hierarchy vs the CPU oracle (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lloyd as olloyd
+from oracle import raygrid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2203_10521_amd import api as A
+    return A
+
+
+def _dev(V, F):
+    import torch
+    return torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+
+
+def _raygrid_eval(V, F, R, seed):
+    def ev(items):
+        return [raygrid.raygrid_obv(V, F, c, Q, h, R, seed, int(slot))["obv"] for slot, c, Q, h in items]
+    return ev
+
+
+def _pack(centers, axes):
+    n = len(centers)
+    return synth.boxes_to_array(centers, axes, np.zeros((n, 3), np.float32))
+
+
+@pytest.mark.parametrize("K", [1, 4])
+def test_one_lloyd_iteration_matches_the_oracle(api, K):
+    """Same input state, one iteration (flood + parameter update): identical
+    partition and boxes, OBV within 1e-5 of the box volume."""
+    V, F = synth.noisy_cube_sphere(4, seed=5)
+    adj = olloyd.adjacency(F)
+    centers = np.array([[0.8, 0.2, 0.1], [-0.6, 0.5, -0.2], [0.0, -0.7, 0.6]], np.float32)
+    _, ax, _ = synth.random_boxes(3, seed=9)
+    R, seed = 8, 3
+    clusters, boxes, obv, e, _ = olloyd.lloyd_iteration(V, F, adj, range(len(F)), centers, ax, [10, 11, 12],
+                                                        _raygrid_eval(V, F, R, seed), K=K)
+    Vt, Ft = _dev(V, F)
+    with api.Lloyd(Vt, Ft, R=R, seed=seed, pops_per_round=K) as L:
+        L.set_groups(np.zeros(len(F), np.int32), np.zeros(3, np.int32), _pack(centers, ax), [10, 11, 12])
+        L.step()
+        out = L.get()
+    ref_box = np.full(len(F), -1)
+    for k, ts in enumerate(clusters):
+        ref_box[ts] = k
+    assert np.array_equal(out["tri_box"], ref_box)
+    for k in range(3):
+        c, Q, h = boxes[k]
+        got = out["boxes"][k]
+        assert np.allclose(got[:3], c, atol=1e-6) and np.allclose(got[3:12], Q.reshape(-1), atol=1e-6)
+        assert np.allclose(got[12:], h, atol=1e-6)
+        vb = 8 * np.prod(h.astype(np.float64))
+        assert abs(out["obv"][k] - obv[k]) <= 1e-5 * vb
+    assert out["counters"]["evals"] > 0
+
+
+def test_disjoint_cuboids_reach_zero(api):
+    V, F, comp, params = synth.disjoint_cuboids(3, seed=7)
+    centers = np.array([p[0] for p in params], np.float32)
+    axes = np.array([p[1] for p in params], np.float32)
+    Vt, Ft = _dev(V, F)
+    with api.Lloyd(Vt, Ft, R=16, seed=1, pops_per_round=8) as L:
+        L.set_groups(np.zeros(len(F), np.int32), np.zeros(3, np.int32), _pack(centers, axes))
+        L.step()
+        out = L.get()
+    for k in range(3):
+        assert set(np.nonzero(out["tri_box"] == k)[0]) == set(np.nonzero(comp == k)[0])
+    vb = sum(8 * np.prod(p[2]) for p in params)
+    assert out["layer_error"] <= 1e-5 * vb
+
+
+def test_hierarchy_structure_enclosure_and_error(api):
+    """Small hierarchy: every triangle has a node per layer, a node's triangles
+    lie in its parent's, every box encloses its triangles (F_i in O_i), the
+    root covers the mesh (Definition 1), e never increases over the sweeps and
+    equals Eq. 7 recomputed from the returned boxes."""
+    import torch
+    V, F = synth.noisy_cube_sphere(6, seed=8)
+    Vt, Ft = _dev(V, F)
+    L, b, R, seed = 3, 2, 8, 5
+    out = api.build_hierarchy(Vt, Ft, levels=L, branching=b, iters=2, sweeps=2, R=R, seed=seed,
+                              pops_per_round=8)
+    boxes, obv, parent, tri_node, e = out["boxes"], out["obv"], out["parent"], out["tri_node"], out["e"]
+    n_nodes = 1 + b + b * b
+    assert boxes.shape == (n_nodes, 15)
+    assert np.all(tri_node[0] == 0) and np.all(tri_node >= 0)
+    for lv in range(1, L):
+        assert np.array_equal(parent[tri_node[lv]], tri_node[lv - 1])
+    for node in range(n_nodes):
+        tris = np.nonzero((tri_node == node).any(axis=0))[0]
+        if len(tris) == 0:
+            continue
+        bx = boxes[node].astype(np.float64)
+        idx = np.unique(F[tris])
+        loc = (V[idx].astype(np.float64) - bx[:3]) @ bx[3:12].reshape(3, 3).T
+        assert np.all(np.abs(loc) <= bx[12:] * (1 + 1e-6) + 1e-6), node
+    assert np.all(np.diff(e) <= 0)
+    # Eq. 7 with omega = layers to the leaves, from OBVs recomputed on the device
+    key = torch.from_numpy(np.arange(n_nodes, dtype=np.int32)).cuda()
+    re = api.outer_volume(Vt, Ft, torch.from_numpy(boxes).cuda(), R, seed=seed, box_key=key).cpu().numpy()
+    level = np.concatenate([[lv] * b ** lv for lv in range(L)])
+    used = np.array([(tri_node == n).any() for n in range(n_nodes)])
+    assert np.allclose(re[used], obv[used], rtol=0, atol=1e-12)
+    w = (L - level).astype(np.float64)
+    assert abs(np.sum(w * obv) - e[-1]) <= 1e-9 * max(1.0, e[-1])
