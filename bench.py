@@ -4,16 +4,19 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
 Workload (the hierarchy configuration the headline metric is quoted on): the
 noisy torus (R = 1, r = 0.35, 256 x 128 quads = 65,536 triangles, radial
-displacement 0.02 x a smooth 8 x 8-mode Fourier field, seed 21), a four-level
-hierarchy with branching 4 (1 / 4 / 16 / 64 boxes), 128 x 128 rays per box face.
-One step fits the box of every cluster of the four levels (covariance OBB) and
-evaluates the outer volume of all 85 boxes.
+displacement 0.02 x a smooth 8 x 8-mode Fourier field, seed 21); a 4-layer
+hierarchy with branching 4 (1 / 4 / 16 / 64 boxes), 20 Lloyd iterations per
+layer, 2 multigrid-like up / down sweeps, 128 x 128 rays per box face, K = 32
+flood pops per group per round.  One step = one complete obbv_build_hierarchy.
 
-Prints one JSON line.  `value` is box outer-volume evaluations per second;
-the roofline object describes the ray-test kernel (k_test): algorithmic FP32
-FLOP (16 per ray-triangle test) over its average launch time, measured with
-HIP events on the library's stream.  `cpu_baseline` times the CPU oracle on a
-bounded sample of the same boxes.
+`value` is box outer-volume evaluations per second over the build; `moves_per_s`
+the Lloyd moves (triangle assignments) decided per second (exact evaluation
+only).  The roofline object describes the ray-test kernel (k_test): algorithmic
+FP32 FLOP (16 per ray-triangle test) over its average launch time, measured with
+HIP events on the library's stream.  `saturated` repeats the measurement on one
+large evaluation (the 85 boxes of the built hierarchy plus 4,011 perturbed
+copies) for context.  `cpu_baseline` times the CPU oracle on a bounded sample of
+the hierarchy's boxes.
 """
 import argparse
 import json
@@ -30,61 +33,71 @@ METRIC = ("box outer-volume evals/s + ray-tri tests/s (% FP32 peak); "
           "Lloyd moves/s surrogate vs exact")
 FP32_PEAK_TFLOPS = 157.3
 FLOP_PER_TEST = 16          # 3 edge functions x 2 FMA + depth plane 2 FMA
-R_RAYS = 128
-SEED_MESH, SEED_RAYS = 21, 23
+HIER = dict(levels=4, branching=4, iters=20, sweeps=2, R=128, seed=23, pops_per_round=32)
+SEED_MESH = 21
 
 
-def level_clusters(n_u, n_v, k):
-    """Cluster id per triangle: k angular sectors of the torus grid (triangle t
-    lies in quad (i, j) = (t // (2 n_v), ...), sector = i * k // n_u)."""
-    t = np.arange(2 * n_u * n_v)
-    i = t // (2 * n_v)
-    return (i * k // n_u).astype(np.int32)
+def roofline(test_ms, launches, tests):
+    avg_ms = test_ms / max(launches, 1)
+    per_launch = tests / max(launches, 1)
+    achieved = per_launch * FLOP_PER_TEST / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    return avg_ms, per_launch, achieved
 
 
-def build_workload(torch):
-    import synth
-    V, F = synth.noisy_torus(seed=SEED_MESH)
-    Vt = torch.from_numpy(V).cuda()
-    Ft = torch.from_numpy(F).cuda()
-    levels = [1, 4, 16, 64]
-    clusters = [torch.from_numpy(level_clusters(256, 128, k)).cuda() for k in levels]
-    return {"V": V, "F": F, "Vt": Vt, "Ft": Ft, "levels": levels, "clusters": clusters}
+def saturated(api, torch, Vt, Ft, boxes, R, seed):
+    """One large evaluation: the hierarchy's boxes plus perturbed copies (4,096 boxes)."""
+    g = np.random.default_rng(5)
+    B = np.repeat(boxes, 4096 // len(boxes) + 1, axis=0)[:4096].copy()
+    B[len(boxes):, :3] += g.normal(0, 0.05, size=(4096 - len(boxes), 3)).astype(np.float32)
+    B[len(boxes):, 12:] *= g.uniform(0.8, 1.2, size=(4096 - len(boxes), 3)).astype(np.float32)
+    Bt = torch.from_numpy(B).cuda()
+    api.outer_volume(Vt, Ft, Bt, R, seed=seed)
+    torch.cuda.synchronize()
+    api.profile_enable(True)
+    api.profile_read()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        api.outer_volume(Vt, Ft, Bt, R, seed=seed)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, n, tests = api.profile_read()
+    api.profile_enable(False)
+    avg_ms, per_launch, achieved = roofline(ms, n, tests)
+    return {"n_boxes": int(len(B)), "evals_per_s": len(B) * reps / dt, "k_test_avg_ms": avg_ms,
+            "tests_per_launch": per_launch, "tests_per_s": tests / (ms * 1e-3),
+            "achieved_tflops": achieved, "frac": achieved / FP32_PEAK_TFLOPS}
 
 
-def step(api, torch, wl):
-    boxes = [api.fit(wl["Vt"], wl["Ft"], cl, k)[0] for cl, k in zip(wl["clusters"], wl["levels"])]
-    B = torch.cat(boxes, 0).contiguous()
-    obv = api.outer_volume(wl["Vt"], wl["Ft"], B, R_RAYS, seed=SEED_RAYS)
-    return B, obv
-
-
-def cpu_baseline(wl, boxes_np, budget_s=20.0):
-    """The CPU oracle (float64 NumPy, one process) on a bounded sample of the same
-    boxes: evaluate boxes in a fixed order until about budget_s seconds pass."""
+def cpu_baseline(V, F, boxes, R, seed, budget_s=20.0):
+    """The CPU oracle (float64 NumPy, one process) on a bounded sample of the
+    hierarchy's boxes: evaluate boxes in a fixed order until about budget_s."""
     from oracle import raygrid
     order = [0, 1, 5, 21, 2, 6, 22, 40, 3, 7, 60, 84]
     done = 0
     t0 = time.perf_counter()
     for b in order:
-        bx = boxes_np[b].astype(np.float64)
-        raygrid.raygrid_obv(wl["V"], wl["F"], bx[:3], bx[3:12].reshape(3, 3).astype(np.float32),
-                            bx[12:15].astype(np.float32), R_RAYS, SEED_RAYS, b)
+        bx = boxes[b]
+        if not np.all(bx[12:] > 0):
+            continue
+        raygrid.raygrid_obv(V, F, bx[:3], bx[3:12].reshape(3, 3), bx[12:15], R, seed, b)
         done += 1
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "box evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of the 85 hierarchy boxes (levels 0-3 in order), R={R_RAYS}, "
-                      f"float64 NumPy ray-grid oracle, {dt:.1f} s"}
+            "sample": f"{done} boxes of the built torus hierarchy (layers 0-3, fixed order), R={R}, "
+                      f"float64 NumPy ray-grid oracle, one process, {dt:.1f} s"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-saturated", action="store_true")
+    ap.add_argument("--iters", type=int, default=HIER["iters"], help="Lloyd iterations per layer")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -92,56 +105,68 @@ def main():
         sys.exit(2)
 
     import torch
+
+    import synth
     from paper_2203_10521_amd import api
 
-    wl = build_workload(torch)
+    hp = dict(HIER, iters=args.iters)
+    V, F = synth.noisy_torus(seed=SEED_MESH)
+    Vt, Ft = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+    # create the library's scratch pools before the timed region
+    api.outer_volume(Vt, Ft, torch.zeros((1, 15), dtype=torch.float32, device="cuda") + 0.5, 8)
+    torch.cuda.synchronize()
     for _ in range(args.warmup):
-        step(api, torch, wl)
+        api.build_hierarchy(Vt, Ft, **hp)
     torch.cuda.synchronize()
 
     api.profile_enable(True)
-    api.profile_read()  # clear
-    torch.cuda.synchronize()
+    api.profile_read()
+    evals = moves = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        B, obv = step(api, torch, wl)
+        out = api.build_hierarchy(Vt, Ft, **hp)
+        evals += out["counters"]["evals"]
+        moves += out["counters"]["moves"]
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    dt = time.perf_counter() - t0
     test_ms, launches, tests = api.profile_read()
     api.profile_enable(False)
+    avg_ms, per_launch, achieved = roofline(test_ms, launches, tests)
 
-    n_boxes = int(B.shape[0])
-    dt = t1 - t0
-    ms_per_step = 1e3 * dt / args.steps
-    evals_per_s = n_boxes * args.steps / dt
-    avg_launch_ms = test_ms / max(launches, 1)
-    tests_per_launch = tests / max(launches, 1)
-    achieved_tflops = tests_per_launch * FLOP_PER_TEST / (avg_launch_ms * 1e-3) / 1e12
-    out = {
+    result = {
         "metric": METRIC,
-        "value": evals_per_s,
+        "value": evals / dt,
         "unit": "box evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * dt / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "noisy torus 65,536 triangles; 1/4/16/64-box hierarchy levels; "
-                               "128x128 rays per box face; covariance fit + outer volume of 85 boxes",
-                   "n_boxes": n_boxes, "R": R_RAYS, "n_triangles": int(wl["F"].shape[0])},
-        "tests_per_s": tests * 1.0 / (test_ms * 1e-3) if test_ms > 0 else None,
-        "k_test_avg_ms": avg_launch_ms,
-        "tests_per_launch": tests_per_launch,
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": None},
+        "config": {"workload": "noisy torus 65,536 triangles; hierarchy 1/4/16/64 boxes (4 layers, "
+                               "branching 4); 20 Lloyd iterations per layer; 2 up/down sweeps; "
+                               "128x128 rays per box face; K=32 pops per group per round",
+                   "levels": hp["levels"], "branching": hp["branching"], "iters": hp["iters"],
+                   "sweeps": hp["sweeps"], "R": hp["R"], "pops_per_round": hp["pops_per_round"],
+                   "n_triangles": int(F.shape[0])},
+        "evals_per_step": evals / args.steps,
+        "moves_per_s": moves / dt,
+        "hierarchy_error": out["e"].tolist(),
+        "tests_per_s": tests / (test_ms * 1e-3) if test_ms > 0 else None,
+        "k_test_avg_ms": avg_ms,
+        "k_test_launches": launches,
+        "tests_per_launch": per_launch,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None},
     }
+    if not args.no_saturated:
+        result["saturated"] = saturated(api, torch, Vt, Ft, out["boxes"], hp["R"], hp["seed"])
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, B.cpu().numpy())
-    print(json.dumps(out), flush=True)
+        result["cpu_baseline"] = cpu_baseline(V, F, out["boxes"], hp["R"], hp["seed"])
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":
