@@ -178,6 +178,19 @@ int obbv_fit(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_cluste
 
 typedef struct obbv_lloyd obbv_lloyd; /* opaque state, created and destroyed in pairs */
 
+/* Learned ranking of flood candidates (all pointers device, owned by the caller). */
+typedef struct {
+  const float* mlp_params; /* [obbv_mlp_param_count()] trained ranker            */
+  const float* volume;     /* [N][N][N] occupancy volume (obbv_occupancy_volume)  */
+  const float* frame;      /* [10] frame of the volume                            */
+  int32_t N;               /* volume edge (8 nb)                                  */
+  int32_t verify_top;      /* candidates per popped triangle evaluated exactly    */
+  float max_error;         /* mean |predicted - exact| outer fraction of the
+                              verified candidates above which the state returns to
+                              exact evaluation of every candidate                 */
+  int32_t reserved;        /* must be 0                                           */
+} obbv_surrogate;
+
 typedef struct {
   int32_t R;              /* rays per face edge of every outer-volume evaluation */
   int32_t tile;           /* ray tile edge (0 = library choice, 8 or 16)          */
@@ -208,10 +221,20 @@ int obbv_lloyd_set_groups(obbv_lloyd* st, int32_t n_boxes, const int32_t* tri_gr
  * rotation gradient, line search, kept if OBV drops). */
 int obbv_lloyd_step(obbv_lloyd* st, void* stream);
 
+/* Host.  With a non-NULL surrogate, later steps rank the candidate boxes of a
+ * popped triangle that no box contains by the ranker's predicted dOBV
+ * (|f * V(grown) - OBV(current)|, f = predicted outer fraction) and evaluate
+ * only the verify_top best exactly; the triangle goes to the verified box with
+ * the smallest exact dOBV.  NULL returns to exact evaluation of every candidate.
+ * The structure is copied; its device arrays must stay valid. */
+int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* surrogate);
+
 /* Host.  Results of the last step (each output nullable, host):
  * tri_box [n_triangles] box of each triangle (-1 = none), boxes [n_boxes][15],
  * obv [n_boxes], *layer_error = sum of OBV (Eq. 6), counters [4] = outer-volume
- * evaluations, flood rounds, candidates that needed no evaluation, moves. */
+ * evaluations, flood rounds, candidates that needed no evaluation, moves,
+ * ranker predictions, ranker fallbacks to exact evaluation (counters has 6
+ * entries, cumulative over the state's steps). */
 int obbv_lloyd_get(obbv_lloyd* st, int32_t* tri_box, float* boxes, double* obv, double* layer_error,
                    int64_t* counters);
 
@@ -230,6 +253,7 @@ typedef struct {
   int32_t reserved;       /* must be 0 */
   uint64_t seed;          /* ray jitter and seed-triangle draws                   */
   double delta;
+  const obbv_surrogate* surrogate; /* host pointer, NULL = exact evaluation only   */
 } obbv_hier_params;
 
 /* Synchronous.  Builds the hierarchy: the root is the covariance box of the mesh
@@ -243,10 +267,59 @@ typedef struct {
  * out_boxes [n_nodes][15]; out_obv [n_nodes]; out_parent [n_nodes] (-1 root);
  * out_tri_node [levels][n_triangles] node of every triangle per layer;
  * out_e [1 + sweeps] e after the top-down pass and after every sweep;
- * out_counters [4] as obbv_lloyd_get. */
+ * out_counters [6] as obbv_lloyd_get. */
 int obbv_build_hierarchy(const obbv_mesh* mesh, const obbv_hier_params* params, float* out_boxes, double* out_obv,
                          int32_t* out_parent, int32_t* out_tri_node, double* out_e, int64_t* out_counters,
                          void* stream);
+
+/* ---- learned ranker of candidate boxes -------------------------------------- */
+
+/* Occupancy features of boxes: for every box, 8 x 8 rays along local axis 2
+ * (one jittered ray per cell, SplitMix64 seed `seed`, jitter key = box index),
+ * and on each ray the inside length within each of the 8 equal sub-slabs of
+ * [-h2, h2] divided by the sub-slab length (Sec. 4.1 integration on a coarse
+ * grid).  Output row b of out_X (device, [n_boxes][544] float32):
+ * [0..2] (centre - frame centre) / frame diagonal, [3..11] axes,
+ * [12..14] log(half / frame diagonal), [15..526] occupancy (x-major, then y,
+ * then z), [527..543] 0.  mesh_frame (device, [n_meshes][4]) = bounding-box
+ * centre xyz and diagonal of each mesh. */
+int obbv_box_features(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes, const int32_t* box_mesh,
+                      int32_t n_boxes, const float* mesh_frame, uint64_t seed, float* out_X, void* stream);
+
+/* Occupancy volume of a mesh: an (8 nb)^3 grid of voxels over the box
+ * frame[0..2] + [0, 8 nb) * frame[3..5] (origin, voxel size; device frame [10]),
+ * filled with the sub-slab inside fractions of nb^3 axis-aligned tiling boxes
+ * (obbv_box_features occupancy, jitter key = tiling box index).  out_volume:
+ * device [8 nb][8 nb][8 nb] float32, index [z][y][x].  frame[6..9] (bounding-box
+ * centre xyz and diagonal) is used by obbv_sample_features. */
+int obbv_occupancy_volume(const obbv_mesh* mesh, int32_t nb, const float* frame, uint64_t seed, float* out_volume,
+                          void* stream);
+
+/* Ranker input rows sampled from an occupancy volume (the fast path used inside
+ * the Lloyd flood): [0..14] as obbv_box_features (normalised by frame[6..9]);
+ * [15..526] the volume at the 8 x 8 x 8 sub-cell centres of the box (trilinear,
+ * voxel centres at origin + (i + 1/2) voxel, 0 outside), x-major then y then z. */
+int obbv_sample_features(const float* volume, int32_t N, const float* frame, const obbv_box* boxes, int32_t n_boxes,
+                         float* out_X, void* stream);
+
+/* Number of float32 parameters of the ranker MLP (544 -> 256 -> 256 -> 1):
+ * W1 [544][256], b1 [256], W2 [256][256], b2 [256], w3 [256], b3 [1], in this
+ * order; W[i][o] multiplies input i into output o. */
+int64_t obbv_mlp_param_count(void);
+
+/* Predicted outer fraction OBV / V_box = sigmoid(MLP(X)) of n rows (device
+ * X [n][544], out_f [n]); n a multiple of 32.  Products on bfloat16 MFMA with
+ * float32 accumulation. */
+int obbv_mlp_forward(const float* params, const float* X, int32_t n, float* out_f, void* stream);
+
+/* One training step on n rows (multiple of 32): forward, mean squared error
+ * against target (device [n]), backward, Adam update (lr > 0; step counts from
+ * 1; adam_m / adam_v device [param_count], zero before the first step).
+ * out_loss (device [1], nullable) receives the loss before the update;
+ * out_grad (device [param_count], nullable) the gradient.  lr = 0 computes the
+ * gradient without updating. */
+int obbv_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, const float* X, const float* target,
+                        int32_t n, float lr, float* out_loss, float* out_grad, void* stream);
 
 #ifdef __cplusplus
 }

@@ -55,6 +55,38 @@ def parity_inside_length(depths, h):
     return L
 
 
+def parity_inside_length_interval(depths, a, b):
+    """Inside length of [a, b] on one line from its crossing depths (parity rule)."""
+    d = np.sort(np.asarray(depths, dtype=np.float64))
+    inside = (int(np.sum(d < a)) % 2) == 1
+    pos, L = a, 0.0
+    for t in d[(d >= a) & (d <= b)]:
+        if inside:
+            L += t - pos
+        pos = t
+        inside = not inside
+    if inside:
+        L += b - pos
+    return L
+
+
+def occupancy(V, F, center, axes, half, seed, box_key=0):
+    """8 x 8 x 8 inside fractions of a box: 8 x 8 jittered rays along local axis 2,
+    inside length within each of the 8 equal sub-slabs of [-h2, h2] / sub-slab length."""
+    P = to_local(V, center, axes)
+    h = np.asarray(half, dtype=np.float64).reshape(3)
+    res = cast_axis(P, np.asarray(F, np.int64), h, 2, 8, seed, box_key, keep_depths=True)
+    occ = np.zeros((8, 8, 8))
+    step = 2.0 * h[2] / 8
+    for i in range(8):
+        for j in range(8):
+            d = res["depths"][i * 8 + j]
+            for k in range(8):
+                a = -h[2] + k * step
+                occ[i, j, k] = parity_inside_length_interval(d, a, a + step) / step
+    return occ
+
+
 def signed_inside_length(depths, signs, h):
     """sum_k s_k (clamp(w_k, -h, h) + h) with s_k = +1 when the line leaves the solid."""
     d = np.clip(np.asarray(depths, dtype=np.float64), -h, h)
@@ -75,7 +107,7 @@ def eq9_outside_length(t_hits, signs, t_e):
     return float(t_e - np.sum(s[keep] * np.minimum(t[keep], t_e)))
 
 
-def cast_axis(P, F, half, w, R, seed, box_key, tol=1e-6):
+def cast_axis(P, F, half, w, R, seed, box_key, tol=1e-6, keep_depths=False):
     """All rays of one cast axis.  Returns a dict of per-ray [R, R] arrays."""
     ua, va = face_axes(w)
     hu, hv, hw = float(half[ua]), float(half[va]), float(half[w])
@@ -155,6 +187,7 @@ def cast_axis(P, F, half, w, R, seed, box_key, tol=1e-6):
     n_above = np.zeros(R * R, dtype=np.int64)
     near_slab = np.zeros(R * R, dtype=bool)
     bounds = np.searchsorted(hr, np.arange(R * R + 1))
+    depths = [hwv[bounds[r]:bounds[r + 1]] for r in range(R * R)] if keep_depths else None
     for r in np.nonzero(bounds[1:] > bounds[:-1])[0]:
         d = hwv[bounds[r]:bounds[r + 1]]
         sg = hs[bounds[r]:bounds[r + 1]]
@@ -171,7 +204,7 @@ def cast_axis(P, F, half, w, R, seed, box_key, tol=1e-6):
         "n_below": n_below.reshape(R, R), "n_in": n_in.reshape(R, R),
         "n_above": n_above.reshape(R, R),
         "near_edge": near_edge, "near_slab": near_slab.reshape(R, R),
-        "u": u, "v": v,
+        "u": u, "v": v, "depths": depths,
     }
 
 

@@ -36,10 +36,15 @@ class ObbvLloydParams(ctypes.Structure):
                 ("reserved", c_int32), ("delta", ctypes.c_double)]
 
 
+class ObbvSurrogate(ctypes.Structure):
+    _fields_ = [("mlp_params", c_void_p), ("volume", c_void_p), ("frame", c_void_p), ("N", c_int32),
+                ("verify_top", c_int32), ("max_error", ctypes.c_float), ("reserved", c_int32)]
+
+
 class ObbvHierParams(ctypes.Structure):
     _fields_ = [("levels", c_int32), ("branching", c_int32), ("iters", c_int32), ("sweeps", c_int32),
                 ("R", c_int32), ("tile", c_int32), ("pops_per_round", c_int32), ("reserved", c_int32),
-                ("seed", c_uint64), ("delta", ctypes.c_double)]
+                ("seed", c_uint64), ("delta", ctypes.c_double), ("surrogate", ctypes.POINTER(ObbvSurrogate))]
 
 
 # name -> (restype, argtypes); every symbol declared in include/obbv.h
@@ -57,10 +62,19 @@ SIGNATURES = {
     "obbv_profile_enable": (c_int32, [c_int32]),
     "obbv_profile_read": (c_int32, [c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "obbv_fit": (c_int32, [ctypes.POINTER(ObbvMesh), c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "obbv_box_features": (c_int32, [ctypes.POINTER(ObbvMesh), c_int32, c_void_p, c_void_p, c_int32, c_void_p,
+                                    c_uint64, c_void_p, c_void_p]),
+    "obbv_occupancy_volume": (c_int32, [ctypes.POINTER(ObbvMesh), c_int32, c_void_p, c_uint64, c_void_p, c_void_p]),
+    "obbv_sample_features": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "obbv_mlp_param_count": (ctypes.c_int64, []),
+    "obbv_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "obbv_mlp_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32,
+                                      ctypes.c_float, c_void_p, c_void_p, c_void_p]),
     "obbv_lloyd_create": (c_int32, [ctypes.POINTER(ObbvMesh), ctypes.POINTER(ObbvLloydParams),
                                     ctypes.POINTER(c_void_p)]),
     "obbv_lloyd_set_groups": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "obbv_lloyd_step": (c_int32, [c_void_p, c_void_p]),
+    "obbv_lloyd_set_surrogate": (c_int32, [c_void_p, ctypes.POINTER(ObbvSurrogate)]),
     "obbv_lloyd_get": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double_p,
                                  ctypes.POINTER(ctypes.c_int64)]),
     "obbv_lloyd_destroy": (c_int32, [c_void_p]),

@@ -186,11 +186,17 @@ class Lloyd:
         boxes = np.empty((self.n_boxes, BOX_FLOATS), np.float32)
         obv = np.empty(self.n_boxes, np.float64)
         e = ctypes.c_double(0.0)
-        cnt = (ctypes.c_int64 * 4)()
+        cnt = (ctypes.c_int64 * 6)()
         _check(_lib.lib().obbv_lloyd_get(self._h, _host_ptr(tri_box), _host_ptr(boxes), _host_ptr(obv),
                                          ctypes.byref(e), cnt))
         return {"tri_box": tri_box, "boxes": boxes, "obv": obv, "layer_error": e.value,
-                "counters": dict(zip(("evals", "rounds", "trivial", "moves"), list(cnt)))}
+                "counters": dict(zip(COUNTERS, list(cnt)))}
+
+    def set_surrogate(self, surrogate):
+        """A Surrogate (or None for exact evaluation of every candidate)."""
+        self._sur = surrogate
+        _check(_lib.lib().obbv_lloyd_set_surrogate(
+            self._h, ctypes.byref(surrogate.struct()) if surrogate is not None else None))
 
     def close(self):
         if self._h:
@@ -210,12 +216,29 @@ class Lloyd:
             pass
 
 
+COUNTERS = ("evals", "rounds", "trivial", "moves", "predicted", "fallbacks")
+
+
+class Surrogate:
+    """Device arrays of a trained ranker (obbv_surrogate)."""
+
+    def __init__(self, mlp_params, volume, frame, verify_top=1, max_error=0.05):
+        self.mlp_params, self.volume, self.frame = mlp_params, volume, frame
+        self.verify_top, self.max_error = int(verify_top), float(max_error)
+
+    def struct(self):
+        self._s = _lib.ObbvSurrogate(self.mlp_params.data_ptr(), self.volume.data_ptr(), self.frame.data_ptr(),
+                                     self.volume.shape[0], self.verify_top, self.max_error, 0)
+        return self._s
+
+
 def build_hierarchy(V, F, levels, branching, iters, sweeps, R, seed=0, pops_per_round=32, delta=0.02, tile=0,
-                    stream=None):
+                    surrogate=None, stream=None):
     """obbv_build_hierarchy; returns numpy outputs (boxes, obv, parent, tri_node, e, counters)."""
     m = mesh_struct(V, F)
+    sp = ctypes.pointer(surrogate.struct()) if surrogate is not None else None
     p = _lib.ObbvHierParams(int(levels), int(branching), int(iters), int(sweeps), int(R), int(tile),
-                            int(pops_per_round), 0, int(seed) & ((1 << 64) - 1), float(delta))
+                            int(pops_per_round), 0, int(seed) & ((1 << 64) - 1), float(delta), sp)
     n_nodes = sum(branching ** level for level in range(levels))
     nt = F.shape[0]
     boxes = np.zeros((n_nodes, BOX_FLOATS), np.float32)
@@ -223,9 +246,104 @@ def build_hierarchy(V, F, levels, branching, iters, sweeps, R, seed=0, pops_per_
     parent = np.zeros(n_nodes, np.int32)
     tri_node = np.zeros((levels, nt), np.int32)
     e = np.zeros(1 + sweeps, np.float64)
-    cnt = np.zeros(4, np.int64)
+    cnt = np.zeros(6, np.int64)
     _check(_lib.lib().obbv_build_hierarchy(ctypes.byref(m), ctypes.byref(p), _host_ptr(boxes), _host_ptr(obv),
                                            _host_ptr(parent), _host_ptr(tri_node), _host_ptr(e), _host_ptr(cnt),
                                            _stream(stream)))
     return {"boxes": boxes, "obv": obv, "parent": parent, "tri_node": tri_node, "e": e,
-            "counters": dict(zip(("evals", "rounds", "trivial", "moves"), cnt.tolist()))}
+            "counters": dict(zip(COUNTERS, cnt.tolist()))}
+
+
+def mesh_frame(V):
+    """[4] float32: bounding-box centre xyz and diagonal of a vertex tensor."""
+    lo = V.min(dim=0).values
+    hi = V.max(dim=0).values
+    return torch.cat([(lo + hi) / 2, torch.linalg.norm(hi - lo).reshape(1)]).to(torch.float32).contiguous()
+
+
+def box_features(boxes, seed=0, meshes=None, box_mesh=None, frames=None, stream=None):
+    """[n, 544] float32 ranker inputs (obbv_box_features)."""
+    _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
+    n = boxes.shape[0]
+    structs = (_lib.ObbvMesh * len(meshes))(*[mesh_struct(v, f) for v, f in meshes])
+    if frames is None:
+        frames = torch.stack([mesh_frame(v) for v, _ in meshes]).contiguous()
+    _dev(frames, torch.float32, "frames", (4,))
+    if box_mesh is not None:
+        _dev(box_mesh, torch.int32, "box_mesh")
+    X = torch.empty((n, 544), dtype=torch.float32, device=boxes.device)
+    _check(_lib.lib().obbv_box_features(structs, len(meshes), _ptr(boxes), _ptr(box_mesh), n, _ptr(frames),
+                                        int(seed) & ((1 << 64) - 1), _ptr(X), _stream(stream)))
+    return X
+
+
+def mlp_param_count():
+    return int(_lib.lib().obbv_mlp_param_count())
+
+
+def mlp_pack(p):
+    """Pack a dict of numpy parameters (W1, b1, W2, b2, w3, b3) into the float32 vector."""
+    return np.concatenate([np.asarray(p[k], np.float64).reshape(-1) for k in ("W1", "b1", "W2", "b2", "w3", "b3")]
+                          ).astype(np.float32)
+
+
+def mlp_unpack(v):
+    v = np.asarray(v, np.float64)
+    sizes = [("W1", (544, 256)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)), ("w3", (256,)), ("b3", (1,))]
+    out, o = {}, 0
+    for k, shp in sizes:
+        n = int(np.prod(shp))
+        out[k] = v[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+def mlp_forward(params, X, stream=None):
+    _dev(params, torch.float32, "params")
+    _dev(X, torch.float32, "X", (544,))
+    f = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(_lib.lib().obbv_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(f), _stream(stream)))
+    return f
+
+
+def mlp_train_step(params, m, v, step, X, target, lr, want_grad=False, stream=None):
+    """One Adam step in place; returns (loss tensor [1], gradient tensor or None)."""
+    for t, name in ((params, "params"), (m, "adam_m"), (v, "adam_v"), (target, "target")):
+        _dev(t, torch.float32, name)
+    _dev(X, torch.float32, "X", (544,))
+    loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+    grad = torch.empty_like(params) if want_grad else None
+    _check(_lib.lib().obbv_mlp_train_step(_ptr(params), _ptr(m), _ptr(v), int(step), _ptr(X), _ptr(target),
+                                          X.shape[0], float(lr), _ptr(loss), _ptr(grad), _stream(stream)))
+    return loss, grad
+
+
+def volume_frame(V, nb, margin=0.02):
+    """[10] float32 frame of an occupancy volume: origin xyz, voxel size xyz (the
+    bounding box grown by `margin` of its diagonal), bounding-box centre, diagonal."""
+    lo = V.min(dim=0).values.double()
+    hi = V.max(dim=0).values.double()
+    diag = torch.linalg.norm(hi - lo)
+    lo2, hi2 = lo - margin * diag, hi + margin * diag
+    vox = (hi2 - lo2) / (8 * nb)
+    return torch.cat([lo2, vox, (lo + hi) / 2, diag.reshape(1)]).to(torch.float32).contiguous()
+
+
+def occupancy_volume(V, F, nb=16, seed=0, frame=None, stream=None):
+    """(volume [8nb, 8nb, 8nb] float32 indexed [z, y, x], frame [10])."""
+    m = mesh_struct(V, F)
+    if frame is None:
+        frame = volume_frame(V, nb)
+    N = 8 * nb
+    vol = torch.empty((N, N, N), dtype=torch.float32, device=V.device)
+    _check(_lib.lib().obbv_occupancy_volume(ctypes.byref(m), int(nb), _ptr(frame), int(seed) & ((1 << 64) - 1),
+                                            _ptr(vol), _stream(stream)))
+    return vol, frame
+
+
+def sample_features(volume, frame, boxes, stream=None):
+    _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
+    X = torch.empty((boxes.shape[0], 544), dtype=torch.float32, device=boxes.device)
+    _check(_lib.lib().obbv_sample_features(_ptr(volume), volume.shape[0], _ptr(frame), _ptr(boxes), boxes.shape[0],
+                                           _ptr(X), _stream(stream)))
+    return X

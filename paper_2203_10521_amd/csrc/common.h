@@ -42,7 +42,15 @@ void clear_error();
 // ---------------------------------------------------------------------------
 // per-device scratch: a few independently growing buffers and the status word
 // ---------------------------------------------------------------------------
-enum PoolSlot { kPoolMeta = 0, kPoolRecords = 1, kPoolBins = 2, kPoolFit = 3, kPoolCount = 4 };
+enum PoolSlot {
+  kPoolMeta = 0,
+  kPoolRecords = 1,
+  kPoolBins = 2,
+  kPoolFit = 3,
+  kPoolMlp = 4,
+  kPoolFeat = 5,
+  kPoolCount = 6
+};
 
 // Ensures slot `slot` of the current device holds at least `bytes` and returns it.
 // Growing frees the old block (hipFree waits for the device), so call it only

@@ -38,9 +38,11 @@ namespace obbv {
 int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                       const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
                       const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
-                      int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s);
+                      int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s,
+                      float* out_occ);
 int fit_impl(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters, obbv_box* out_boxes,
              double* out_eigvals, hipStream_t st);
+int mlp_forward_impl(const float* params, const float* X, int32_t n, float* out_f, hipStream_t s);
 
 namespace {
 
@@ -110,11 +112,71 @@ struct Evaluator {
     OBBV_HIP(hipMemcpyAsync(db, hb.data(), n * sizeof(obbv_box), hipMemcpyHostToDevice, stream));
     OBBV_HIP(hipMemcpyAsync(dk, hk.data(), n * 4, hipMemcpyHostToDevice, stream));
     OBBV_RET(outer_volume_impl(&mesh, 1, db, nullptr, dk, (int32_t)n, &params, dout, nullptr, nullptr, nullptr,
-                               nullptr, stream));
+                               nullptr, stream, nullptr));
     OBBV_HIP(hipMemcpyAsync(out.data(), dout, n * 8, hipMemcpyDeviceToHost, stream));
     OBBV_HIP(hipStreamSynchronize(stream));
     evals += (int64_t)n;
     ++calls;
+    return OBBV_OK;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// learned ranker: sampled occupancy features + MLP, batched on the device
+// ---------------------------------------------------------------------------
+struct Predictor {
+  obbv_surrogate cfg{};
+  bool on = false;
+  hipStream_t stream = nullptr;
+  char* dbuf = nullptr;
+  size_t cap = 0;
+  std::vector<obbv_box> hb;
+  std::vector<float> hf;
+  double err_sum = 0.0;
+  int64_t err_n = 0, predicted = 0, fallbacks = 0;
+
+  ~Predictor() {
+    if (dbuf) (void)hipFree(dbuf);
+  }
+
+  int predict(const std::vector<HBox>& boxes, std::vector<float>& out) {
+    const size_t n = boxes.size();
+    const size_t np = (n + 31) / 32 * 32;
+    out.assign(n, 0.f);
+    if (n == 0) return OBBV_OK;
+    const size_t need = np * (sizeof(obbv_box) + 544 * 4 + 4) + 1024;
+    if (need > cap) {
+      if (dbuf) {
+        OBBV_HIP(hipStreamSynchronize(stream));
+        OBBV_HIP(hipFree(dbuf));
+        dbuf = nullptr;
+      }
+      cap = std::max(need * 2, (size_t)1 << 20);
+      if (hipMalloc((void**)&dbuf, cap) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = 0;
+        set_error("hipMalloc failed for the ranker buffer");
+        return OBBV_ERR_OOM;
+      }
+    }
+    hb.assign(np, obbv_box{});
+    for (size_t i = 0; i < n; ++i) {
+      std::memcpy(hb[i].center, boxes[i].c, 12);
+      std::memcpy(hb[i].axes, boxes[i].Q, 36);
+      std::memcpy(hb[i].half, boxes[i].h, 12);
+    }
+    obbv_box* db = (obbv_box*)dbuf;
+    float* X = (float*)(dbuf + ((np * sizeof(obbv_box) + 255) & ~(size_t)255));
+    float* f = X + np * 544;
+    OBBV_HIP(hipMemcpyAsync(db, hb.data(), np * sizeof(obbv_box), hipMemcpyHostToDevice, stream));
+    const int rc = obbv_sample_features(cfg.volume, cfg.N, cfg.frame, db, (int32_t)np, X, stream);
+    if (rc != OBBV_OK) return rc;
+    OBBV_RET(mlp_forward_impl(cfg.mlp_params, X, (int32_t)np, f, stream));
+    hf.resize(np);
+    OBBV_HIP(hipMemcpyAsync(hf.data(), f, np * 4, hipMemcpyDeviceToHost, stream));
+    OBBV_HIP(hipStreamSynchronize(stream));
+    std::copy(hf.begin(), hf.begin() + n, out.begin());
+    predicted += (int64_t)n;
     return OBBV_OK;
   }
 };
@@ -251,7 +313,7 @@ struct PartitionIO {
 };
 
 int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Group>& groups, PartitionIO io,
-                    int K, Evaluator& ev, Counters& cnt) {
+                    int K, Evaluator& ev, Counters& cnt, Predictor* pred) {
   std::vector<HBox>& boxes = *io.boxes;
   std::vector<double>& obv = *io.obv;
   std::vector<int32_t>& eb = *io.elem_box;
@@ -369,11 +431,65 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         }
       }
     }
+    // learned ranking: keep the verify_top candidates of each element with the
+    // smallest predicted dOBV for exact evaluation
+    std::vector<float> fpred;
+    std::vector<int32_t> kept_pred;  // candidate -> index into fpred (for the error check)
+    if (pred && pred->on && !req_idx.empty()) {
+      OBBV_RET(pred->predict(req_boxes, fpred));
+      std::vector<HBox> rb;
+      std::vector<uint32_t> rk;
+      std::vector<int32_t> ri;
+      kept_pred.clear();
+      size_t x = 0;
+      while (x < req_idx.size()) {
+        size_t y = x;
+        while (y < req_idx.size() && cands[req_idx[y]].e == cands[req_idx[x]].e &&
+               cands[req_idx[y]].g == cands[req_idx[x]].g)
+          ++y;
+        std::vector<std::pair<double, size_t>> score;
+        for (size_t z = x; z < y; ++z) {
+          const Cand& c = cands[req_idx[z]];
+          const int bi = groups[c.g].boxes[c.li];
+          const double vb = 8.0 * (double)c.h[0] * (double)c.h[1] * (double)c.h[2];
+          score.push_back({std::fabs((double)fpred[z] * vb - obv[bi]), z});
+        }
+        std::sort(score.begin(), score.end());
+        const size_t keep = std::min<size_t>(score.size(), (size_t)std::max(1, pred->cfg.verify_top));
+        std::vector<size_t> sel;
+        for (size_t q = 0; q < keep; ++q) sel.push_back(score[q].second);
+        std::sort(sel.begin(), sel.end());
+        for (size_t z : sel) {
+          rb.push_back(req_boxes[z]);
+          rk.push_back(req_keys[z]);
+          ri.push_back(req_idx[z]);
+          kept_pred.push_back((int32_t)z);
+        }
+        x = y;
+      }
+      req_boxes.swap(rb);
+      req_keys.swap(rk);
+      req_idx.swap(ri);
+    }
     std::vector<char> evaluated(cands.size(), 0);
     for (int32_t x : req_idx) evaluated[x] = 1;
     OBBV_RET(ev.eval(req_boxes, req_keys, vals));
     cnt.evals += (int64_t)vals.size();
     for (size_t x = 0; x < vals.size(); ++x) cands[req_idx[x]].val = vals[x];
+    if (!kept_pred.empty()) {  // the exact kernel judges the ranker
+      for (size_t x = 0; x < vals.size(); ++x) {
+        const HBox& bx = req_boxes[x];
+        const double vb = 8.0 * (double)bx.h[0] * (double)bx.h[1] * (double)bx.h[2];
+        if (vb > 0.0) {
+          pred->err_sum += std::fabs((double)fpred[kept_pred[x]] - vals[x] / vb);
+          ++pred->err_n;
+        }
+      }
+      if (pred->err_n >= 64 && pred->err_sum / (double)pred->err_n > (double)pred->cfg.max_error) {
+        pred->on = false;
+        ++pred->fallbacks;
+      }
+    }
     // decisions
     std::vector<std::vector<int32_t>> got((size_t)boxes.size());  // candidate index per receiving box
     std::vector<int32_t> touched;
@@ -640,6 +756,7 @@ struct LloydState {
   std::vector<int32_t> tri_box;
   Counters cnt;
   double layer_error = 0.0;
+  Predictor pred;
 };
 
 // One Lloyd iteration (partition + parameter update) of every group.
@@ -650,7 +767,7 @@ static int lloyd_iterate(LloydState& S) {
   std::vector<Group> flood_groups;
   for (const Group& g : S.groups)
     if (g.boxes.size() > 1) flood_groups.push_back(g);
-  OBBV_RET(flood_partition(S.M, S.E, flood_groups, io, S.K, S.ev, S.cnt));
+  OBBV_RET(flood_partition(S.M, S.E, flood_groups, io, S.K, S.ev, S.cnt, &S.pred));
   for (const Group& g : S.groups)
     if (g.boxes.size() == 1)
       for (int e : g.elems) eb[e] = g.boxes[0];
@@ -745,11 +862,31 @@ extern "C" int obbv_lloyd_step(obbv_lloyd* st, void* stream) {
   LloydState& S = *reinterpret_cast<LloydState*>(st);
   OBBV_ARG(!S.groups.empty(), "obbv_lloyd_set_groups was not called");
   S.ev.stream = (hipStream_t)stream;
+  S.pred.stream = (hipStream_t)stream;
   return lloyd_iterate(S);
+}
+
+extern "C" int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* sur) {
+  clear_error();
+  OBBV_ARG(st, "NULL state");
+  LloydState& S = *reinterpret_cast<LloydState*>(st);
+  if (!sur) {
+    S.pred.on = false;
+    return OBBV_OK;
+  }
+  OBBV_ARG(sur->mlp_params && sur->volume && sur->frame, "surrogate arrays are NULL");
+  OBBV_ARG(sur->N >= 1 && sur->verify_top >= 1 && sur->reserved == 0, "bad surrogate sizes");
+  S.pred.cfg = *sur;
+  S.pred.on = true;
+  S.pred.err_sum = 0.0;
+  S.pred.err_n = 0;
+  return OBBV_OK;
 }
 
 extern "C" int obbv_lloyd_get(obbv_lloyd* st, int32_t* tri_box, float* boxes, double* obv, double* layer_error,
                               int64_t* counters) {
+  // counters: [0] evaluations, [1] rounds, [2] no-evaluation candidates, [3] moves,
+  // [4] ranker predictions, [5] ranker fallbacks
   clear_error();
   OBBV_ARG(st, "NULL state");
   LloydState& S = *reinterpret_cast<LloydState*>(st);
@@ -767,6 +904,8 @@ extern "C" int obbv_lloyd_get(obbv_lloyd* st, int32_t* tri_box, float* boxes, do
     counters[1] = S.cnt.rounds;
     counters[2] = S.cnt.trivial;
     counters[3] = S.cnt.moves;
+    counters[4] = S.pred.predicted;
+    counters[5] = S.pred.fallbacks;
   }
   return OBBV_OK;
 }
@@ -912,7 +1051,7 @@ int merge_level(LloydState& S, Tree& T, int l) {
   std::vector<Group> fg;
   for (const Group& g : S.groups)
     if (g.boxes.size() > 1) fg.push_back(g);
-  OBBV_RET(flood_partition(S.M, S.E, fg, io, S.K, S.ev, S.cnt));
+  OBBV_RET(flood_partition(S.M, S.E, fg, io, S.K, S.ev, S.cnt, &S.pred));
   for (const Group& g : S.groups)
     if (g.boxes.size() == 1)
       for (int e : g.elems) eb[e] = g.boxes[0];
@@ -956,11 +1095,14 @@ extern "C" int obbv_build_hierarchy(const obbv_mesh* mesh, const obbv_hier_param
   for (int l = 0; l < p->levels; ++l, w *= p->branching) n_nodes += w;
   OBBV_ARG(n_nodes < (1 << 24), "too many nodes");
   obbv_lloyd_params lp{p->R, p->tile, p->seed, p->pops_per_round, 0, p->delta};
+  OBBV_ARG(p->reserved == 0, "reserved must be 0");
   obbv_lloyd* handle = nullptr;
   OBBV_RET(obbv_lloyd_create(mesh, &lp, &handle));
   std::unique_ptr<LloydState> S(reinterpret_cast<LloydState*>(handle));
   hipStream_t s = (hipStream_t)stream;
   S->ev.stream = s;
+  S->pred.stream = s;
+  if (p->surrogate) OBBV_RET(obbv_lloyd_set_surrogate(handle, p->surrogate));
   const int nt = S->M.nt;
   Tree T;
   T.L = p->levels;
@@ -1090,6 +1232,8 @@ extern "C" int obbv_build_hierarchy(const obbv_mesh* mesh, const obbv_hier_param
     out_counters[1] = S->cnt.rounds;
     out_counters[2] = S->cnt.trivial;
     out_counters[3] = S->cnt.moves;
+    out_counters[4] = S->pred.predicted;
+    out_counters[5] = S->pred.fallbacks;
   }
   return OBBV_OK;
 }

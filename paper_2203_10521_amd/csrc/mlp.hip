@@ -1,0 +1,256 @@
+// Surrogate ranker MLP: 544 -> 256 (ReLU) -> 256 (ReLU) -> 1 (sigmoid), trained
+// on (box, outer fraction) pairs from the exact outer-volume kernel.
+//
+// Every matrix product runs on MFMA (v_mfma_f32_32x32x8bf16_1k): operands are
+// rounded to bfloat16 (round to nearest even) as they are loaded, products are
+// accumulated in float32.  Activations, gradients and the master weights stay in
+// float32 memory; the bfloat16 rounding points are the inputs, the weights, the
+// hidden activations and the back-propagated gradients entering each product.
+//
+// Parameter vector (float32, kMlpParams entries):
+//   W1 [544][256] | b1 [256] | W2 [256][256] | b2 [256] | w3 [256] | b3 [1]
+// (W[i][o] multiplies input i into output o).
+#include <cmath>
+
+#include "common.h"
+
+namespace obbv {
+namespace {
+
+constexpr int kIn = 544, kH = 256;
+constexpr int64_t oW1 = 0, ob1 = oW1 + (int64_t)kIn * kH, oW2 = ob1 + kH, ob2 = oW2 + (int64_t)kH * kH,
+                  ow3 = ob2 + kH, ob3 = ow3 + kH, kParams = ob3 + 1;
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ inline short f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ inline float bf(float x) { return __uint_as_float(((uint32_t)(uint16_t)f2bf(x)) << 16); }
+
+// C[m, n] (+)= sum_k bf16(A[m, k]) bf16(B[k, n]) with arbitrary element strides.
+// One wave per 32 x 32 tile of C; M, N multiples of 32, K a multiple of 8.
+// MFMA 32x32x8 operand layout: lane l holds A[l % 32][4 (l / 32) + j] and
+// B[4 (l / 32) + j][l % 32], j = 0..3; result register r of lane l is
+// C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+__global__ void __launch_bounds__(64)
+k_gemm(const float* __restrict__ A, int64_t sam, int64_t sak, const float* __restrict__ B, int64_t sbk,
+       int64_t sbn, float* __restrict__ C, int64_t scm, int64_t scn, int M, int N, int K, int accumulate) {
+  const int tiles_n = N / 32;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - (blockIdx.x / tiles_n) * tiles_n;
+  const int lane = threadIdx.x;
+  const int r = lane & 31, kq = (lane >> 5) * 4;
+  const int64_t m = (int64_t)tm * 32 + r, n = (int64_t)tn * 32 + r;
+  v16f acc;
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    v4s a, b;
+    for (int j = 0; j < 4; ++j) {
+      const int64_t k = k0 + kq + j;
+      a[j] = f2bf(A[m * sam + k * sak]);
+      b[j] = f2bf(B[k * sbk + n * sbn]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  for (int rr = 0; rr < 16; ++rr) {
+    const int64_t row = (int64_t)tm * 32 + 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4);
+    const int64_t col = (int64_t)tn * 32 + (lane & 31);
+    float* c = C + row * scm + col * scn;
+    *c = accumulate ? *c + acc[rr] : acc[rr];
+  }
+}
+
+int gemm(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C, int64_t scm,
+         int64_t scn, int M, int N, int K, bool accumulate, hipStream_t s) {
+  if (M % 32 || N % 32 || K % 8) {
+    set_error("MLP product sizes must be multiples of 32 (M, N) and 8 (K)");
+    return OBBV_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_gemm, dim3((unsigned)((M / 32) * (N / 32))), dim3(64), 0, s, A, sam, sak, B, sbk, sbn, C, scm,
+                     scn, M, N, K, accumulate ? 1 : 0);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+// H = relu(Z + b) in place, rows of width w
+__global__ void k_bias_relu(float* __restrict__ Z, const float* __restrict__ b, int64_t n, int w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * w) return;
+  Z[i] = fmaxf(Z[i] + b[i % w], 0.f);
+}
+
+// z = bf16(H2) . bf16(w3) + b3; f = sigmoid(z); with targets: dz and the loss
+__global__ void k_head(const float* __restrict__ H2, const float* __restrict__ P, int n, float* __restrict__ f,
+                       const float* __restrict__ t, float* __restrict__ dz, float* __restrict__ loss) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const float* h = H2 + (int64_t)row * kH;
+  float z = 0.f;
+  for (int c = 0; c < kH; ++c) z = fmaf(bf(h[c]), bf(P[ow3 + c]), z);
+  z += P[ob3];
+  const float fr = 1.f / (1.f + expf(-z));
+  f[row] = fr;
+  if (t) {
+    const float e = fr - t[row];
+    dz[row] = 2.f * e * fr * (1.f - fr) / (float)n;
+    atomicAdd(loss, e * e / (float)n);
+  }
+}
+
+// dw3[c] = sum_r bf16(H2[r][c]) bf16(dz[r]); db3 = sum_r dz[r]  (one thread per column)
+__global__ void k_dw3(const float* __restrict__ H2, const float* __restrict__ dz, int n, float* __restrict__ G) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > kH) return;
+  float acc = 0.f;
+  if (c < kH) {
+    for (int r = 0; r < n; ++r) acc = fmaf(bf(H2[(int64_t)r * kH + c]), bf(dz[r]), acc);
+    G[ow3 + c] = acc;
+  } else {
+    for (int r = 0; r < n; ++r) acc += dz[r];
+    G[ob3] = acc;
+  }
+}
+
+// dH2[r][c] = bf16(dz[r]) bf16(w3[c]) [H2 > 0]
+__global__ void k_dh2(const float* __restrict__ dz, const float* __restrict__ P, const float* __restrict__ H2, int n,
+                      float* __restrict__ dH2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * kH) return;
+  const int r = (int)(i / kH), c = (int)(i % kH);
+  dH2[i] = H2[i] > 0.f ? bf(dz[r]) * bf(P[ow3 + c]) : 0.f;
+}
+
+__global__ void k_relu_mask(float* __restrict__ G, const float* __restrict__ H, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(H[i] > 0.f)) G[i] = 0.f;
+}
+
+// out[c] = sum_r X[r][c]  (unrounded gradient sums for the biases)
+__global__ void k_colsum(const float* __restrict__ X, int n, int w, float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= w) return;
+  float acc = 0.f;
+  for (int r = 0; r < n; ++r) acc += X[(int64_t)r * w + c];
+  out[c] = acc;
+}
+
+// Adam (Kingma and Ba, 2015) with bias correction, float32 master weights
+__global__ void k_adam(float* __restrict__ P, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ G,
+                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = G[i];
+  const float mi = b1 * m[i] + (1.f - b1) * g;
+  const float vi = b2 * v[i] + (1.f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+struct MlpScratch {
+  float* H1;
+  float* H2;
+  float* f;
+  float* dz;
+  float* dH2;
+  float* dH1;
+  float* G;
+  float* loss;
+};
+
+int mlp_scratch(int n, MlpScratch& S) {
+  const size_t bytes = ((size_t)n * kH * 4 + (size_t)n * 2 + (size_t)kParams + 64) * sizeof(float);
+  void* p = nullptr;
+  OBBV_RET(pool_get(kPoolMlp, bytes, &p));
+  float* q = (float*)p;
+  S.H1 = q;
+  q += (size_t)n * kH;
+  S.H2 = q;
+  q += (size_t)n * kH;
+  S.dH2 = q;
+  q += (size_t)n * kH;
+  S.dH1 = q;
+  q += (size_t)n * kH;
+  S.f = q;
+  q += n;
+  S.dz = q;
+  q += n;
+  S.loss = q;
+  q += 16;
+  S.G = q;
+  return OBBV_OK;
+}
+
+inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+int forward(const float* P, const float* X, int n, MlpScratch& S, float* out_f, const float* t, hipStream_t s) {
+  OBBV_RET(gemm(X, kIn, 1, P + oW1, kH, 1, S.H1, kH, 1, n, kH, kIn, false, s));
+  hipLaunchKernelGGL(k_bias_relu, dim3(blocks((int64_t)n * kH, 256)), dim3(256), 0, s, S.H1, P + ob1, (int64_t)n, kH);
+  OBBV_RET(gemm(S.H1, kH, 1, P + oW2, kH, 1, S.H2, kH, 1, n, kH, kH, false, s));
+  hipLaunchKernelGGL(k_bias_relu, dim3(blocks((int64_t)n * kH, 256)), dim3(256), 0, s, S.H2, P + ob2, (int64_t)n, kH);
+  if (t) OBBV_HIP(hipMemsetAsync(S.loss, 0, 4, s));
+  hipLaunchKernelGGL(k_head, dim3(blocks(n, 256)), dim3(256), 0, s, S.H2, P, n, out_f, t, S.dz, S.loss);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+}  // namespace
+
+int mlp_forward_impl(const float* params, const float* X, int32_t n, float* out_f, hipStream_t s) {
+  OBBV_ARG(params && X && out_f, "NULL argument");
+  OBBV_ARG(n >= 0 && n % 32 == 0, "n must be a non-negative multiple of 32");
+  if (n == 0) return OBBV_OK;
+  MlpScratch S;
+  OBBV_RET(mlp_scratch(n, S));
+  return forward(params, X, n, S, out_f, nullptr, s);
+}
+
+}  // namespace obbv
+
+using namespace obbv;
+
+extern "C" int obbv_mlp_forward(const float* params, const float* X, int32_t n, float* out_f, void* stream) {
+  clear_error();
+  return mlp_forward_impl(params, X, n, out_f, (hipStream_t)stream);
+}
+
+extern "C" int obbv_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, const float* X,
+                                   const float* target, int32_t n, float lr, float* out_loss, float* out_grad,
+                                   void* stream) {
+  clear_error();
+  OBBV_ARG(params && adam_m && adam_v && X && target, "NULL argument");
+  OBBV_ARG(n > 0 && n % 32 == 0, "n must be a positive multiple of 32");
+  OBBV_ARG(step >= 1, "step counts from 1");
+  hipStream_t s = (hipStream_t)stream;
+  MlpScratch S;
+  OBBV_RET(mlp_scratch(n, S));
+  OBBV_RET(forward(params, X, n, S, S.f, target, s));
+  float* G = out_grad ? out_grad : S.G;
+  const float* P = params;
+  // head
+  hipLaunchKernelGGL(k_dw3, dim3(blocks(kH + 1, 64)), dim3(64), 0, s, S.H2, S.dz, n, G);
+  hipLaunchKernelGGL(k_dh2, dim3(blocks((int64_t)n * kH, 256)), dim3(256), 0, s, S.dz, P, S.H2, n, S.dH2);
+  OBBV_HIP(hipGetLastError());
+  // layer 2: dW2 = H1^T dH2, db2 = colsum dH2, dH1 = (dH2 W2^T) [H1 > 0]
+  OBBV_RET(gemm(S.H1, 1, kH, S.dH2, kH, 1, G + oW2, kH, 1, kH, kH, n, false, s));
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(kH, 64)), dim3(64), 0, s, S.dH2, n, kH, G + ob2);
+  OBBV_RET(gemm(S.dH2, kH, 1, P + oW2, 1, kH, S.dH1, kH, 1, n, kH, kH, false, s));
+  hipLaunchKernelGGL(k_relu_mask, dim3(blocks((int64_t)n * kH, 256)), dim3(256), 0, s, S.dH1, S.H1, (int64_t)n * kH);
+  // layer 1: dW1 = X^T dH1, db1 = colsum dH1
+  OBBV_RET(gemm(X, 1, kIn, S.dH1, kH, 1, G + oW1, kH, 1, kIn, kH, n, false, s));
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(kH, 64)), dim3(64), 0, s, S.dH1, n, kH, G + ob1);
+  OBBV_HIP(hipGetLastError());
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  if (lr > 0.f)
+    hipLaunchKernelGGL(k_adam, dim3(blocks(kParams, 256)), dim3(256), 0, s, params, adam_m, adam_v, G, kParams, lr,
+                       b1, b2, 1e-8f, c1, c2);
+  if (out_loss) OBBV_HIP(hipMemcpyAsync(out_loss, S.loss, 4, hipMemcpyDeviceToDevice, s));
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+extern "C" int64_t obbv_mlp_param_count(void) { return kParams; }

@@ -321,6 +321,7 @@ k_tile_count(CullArgs a, const int32_t* __restrict__ side, int32_t* __restrict__
 //   [9..11]  depth plane in fixed point: y(u, v) = D u + E v + F equals
 //            kMagic + s (w(u, v) + h) 2^21 / h, s = crossing sign
 //   [12..13] clamp of y to the part of the triangle inside the slab
+//   [14]     crossing sign s (+1 leaving the solid along +w in the cast frame)
 // The edge coefficients of an edge shared by two triangles are exact
 // negatives of each other (or equal, when one of them is flipped), so the two
 // triangles classify every ray consistently: the test is watertight.
@@ -364,7 +365,7 @@ __device__ inline void make_record(const CastTri& t, bool mirror, float hw, floa
   out[0] = make_float4(A[0], Bc[0], C[0], A[1]);
   out[1] = make_float4(Bc[1], C[1], A[2], Bc[2]);
   out[2] = make_float4(C[2], (float)(K * D), (float)(K * E), (float)(K * (F + h) + (double)kMagic));
-  out[3] = make_float4((float)lo, (float)hi, 0.0f, 0.0f);
+  out[3] = make_float4((float)lo, (float)hi, (float)s, 0.0f);
 }
 
 // Bin slots: every (tile) of the work item first counts its entries in LDS,
@@ -470,6 +471,8 @@ struct TestArgs {
   int32_t* ray_q;           // nullable [nbw][R][R]
   int32_t* ray_hits;        // nullable [nbw][R][R]
   unsigned long long* test_counter;  // nullable: += rays x binned triangles per tile
+  float* occ;                        // nullable [n_boxes][8][8][8]: sub-slab inside fractions (R = 8, axis 2)
+  const int32_t* side;               // [nbw] mirrored cast flags
   uint64_t seed;
   int n_boxes;
   int n_rec;
@@ -483,7 +486,7 @@ struct TestArgs {
 //   E_k = A_k u + B_k v + C_k (3 x 2 FMA), inside iff min E_k >= 0,
 //   y = D u + E v + F (2 FMA), clamped to the triangle's slab part (med3),
 //   acc += inside ? bits(y) : kMagicBits   -- exact integer accumulation.
-template <int TE, bool STATS, bool STAGE>
+template <int TE, bool STATS, bool STAGE, bool OCC>
 __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
   constexpr int NB = TE / 8;
   constexpr int RPL = NB * NB;
@@ -514,6 +517,8 @@ __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
   const int lane = threadIdx.x;
 
   float ru[RPL], rv[RPL];
+  float occ_acc[OCC ? 8 : 1];
+  for (int j = 0; j < (OCC ? 8 : 1); ++j) occ_acc[j] = 0.f;
   uint32_t acc[RPL];
   int hits[RPL];
   bool valid[RPL];
@@ -551,6 +556,15 @@ __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
       const bool in = m >= 0.0f;
       acc[r] += in ? __float_as_uint(c) : kMagicBits;
       if (STATS) hits[r] += in ? 1 : 0;
+      if (OCC && in) {
+        // the same crossing split over 8 equal sub-slabs: position from the slab
+        // bottom in units of 2^-22 of the slab, sub-slab k spans [k 2^19, (k+1) 2^19]
+        const float sg = r3.z;
+        const float yq = (c - kMagic) * sg;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          occ_acc[k] += sg * (fminf(fmaxf(yq, (float)(k << 19)), (float)((k + 1) << 19)) - (float)(k << 19));
+      }
     }
   };
   if (STAGE) {
@@ -604,6 +618,12 @@ __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
       if (a.ray_q) atomicAdd(&a.ray_q[o], q);
       if (a.ray_hits) atomicAdd(&a.ray_hits[o], hits[r]);
     }
+  }
+  if (OCC && valid[0]) {
+    const int i = ti * TE + (lane & 7), j = tj * TE + (lane >> 3);
+    const bool mirror = a.side[bw] != 0;
+    float* o = a.occ + (((int64_t)b * 8 + i) * 8 + j) * 8;
+    for (int k = 0; k < 8; ++k) atomicAdd(&o[mirror ? 7 - k : k], occ_acc[k] * (1.0f / 524288.0f));
   }
   // wave reduction of the 64 lane sums, one 64-bit atomic per wave
 #pragma unroll
@@ -664,14 +684,16 @@ int pinned_totals(int64_t** out) {
 template <int TE>
 int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hipStream_t s) {
   const dim3 g((unsigned)nblocks), b(kTestThreads);
-  if (stats && stage)
-    hipLaunchKernelGGL((k_test<TE, true, true>), g, b, 0, s, ta);
+  if (ta.occ && TE == 8)
+    hipLaunchKernelGGL((k_test<TE, false, true, true>), g, b, 0, s, ta);
+  else if (stats && stage)
+    hipLaunchKernelGGL((k_test<TE, true, true, false>), g, b, 0, s, ta);
   else if (stats)
-    hipLaunchKernelGGL((k_test<TE, true, false>), g, b, 0, s, ta);
+    hipLaunchKernelGGL((k_test<TE, true, false, false>), g, b, 0, s, ta);
   else if (stage)
-    hipLaunchKernelGGL((k_test<TE, false, true>), g, b, 0, s, ta);
+    hipLaunchKernelGGL((k_test<TE, false, true, false>), g, b, 0, s, ta);
   else
-    hipLaunchKernelGGL((k_test<TE, false, false>), g, b, 0, s, ta);
+    hipLaunchKernelGGL((k_test<TE, false, false, false>), g, b, 0, s, ta);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
 }
@@ -689,7 +711,8 @@ bool test_stage_choice() {
 int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                       const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
                       const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
-                      int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s) {
+                      int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s,
+                      float* out_occ) {
   OBBV_ARG(params != nullptr, "params is NULL");
   OBBV_ARG(n_boxes >= 0, "n_boxes < 0");
   if (n_boxes == 0) return OBBV_OK;
@@ -712,7 +735,8 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
     max_nt = std::max(max_nt, meshes[m].n_triangles);
   }
   const int R = params->R;
-  const int TE = params->tile ? params->tile : (R >= 48 ? 16 : 8);
+  const int TE = out_occ ? 8 : (params->tile ? params->tile : (R >= 48 ? 16 : 8));
+  OBBV_ARG(!out_occ || (R == 8 && mask == 4u), "occupancy needs R = 8 and axis_mask = 4");
   const int tpe = ceil_div(R, TE);
   const int64_t TT = (int64_t)tpe * tpe;
   const int64_t nbw = (int64_t)n_boxes * 3;
@@ -834,6 +858,8 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
     ta.ray_q = out_ray_q;
     ta.ray_hits = out_ray_hits;
     ta.test_counter = nullptr;
+    ta.occ = out_occ;
+    ta.side = d_side;
     void* prof_token = nullptr;
     if (profiling_enabled()) {
       OBBV_RET(profile_counter(&ta.test_counter));
@@ -880,7 +906,7 @@ extern "C" int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, c
                                     void* stream) {
   obbv::clear_error();
   return obbv::outer_volume_impl(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, params, out_obv,
-                                 out_vin_axis, out_ray_q, out_ray_hits, out_side, (hipStream_t)stream);
+                                 out_vin_axis, out_ray_q, out_ray_hits, out_side, (hipStream_t)stream, nullptr);
 }
 
 extern "C" int obbv_outer_volume(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
@@ -888,5 +914,178 @@ extern "C" int obbv_outer_volume(const obbv_mesh* meshes, int32_t n_meshes, cons
                                  const obbv_ov_params* params, double* out_obv, void* stream) {
   obbv::clear_error();
   return obbv::outer_volume_impl(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, params, out_obv,
-                                 nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream);
+                                 nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// surrogate input rows: 15 normalised box parameters + 8 x 8 x 8 occupancy
+// ---------------------------------------------------------------------------
+namespace obbv {
+namespace {
+__global__ void k_features(const obbv_box* __restrict__ boxes, const int32_t* __restrict__ box_mesh, int n_meshes,
+                           const float* __restrict__ frame, const float* __restrict__ occ, int n,
+                           float* __restrict__ X) {
+  const int b = blockIdx.x;
+  if (b >= n) return;
+  const float* p = reinterpret_cast<const float*>(boxes + b);
+  int m = box_mesh ? box_mesh[b] : 0;
+  m = (m < 0 || m >= n_meshes) ? 0 : m;
+  const float* fr = frame + 4 * m;
+  float* x = X + (int64_t)b * 544;
+  for (int k = threadIdx.x; k < 544; k += blockDim.x) {
+    float v = 0.f;
+    if (k < 3)
+      v = (p[k] - fr[k]) / fr[3];
+    else if (k < 12)
+      v = p[k];
+    else if (k < 15)
+      v = logf(fmaxf(p[k], 1e-30f) / fr[3]);
+    else if (k < 527)
+      v = occ[(int64_t)b * 512 + (k - 15)];
+    x[k] = v;
+  }
+}
+}  // namespace
+}  // namespace obbv
+
+extern "C" int obbv_box_features(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                 const int32_t* box_mesh, int32_t n_boxes, const float* mesh_frame, uint64_t seed,
+                                 float* out_X, void* stream) {
+  using namespace obbv;
+  clear_error();
+  OBBV_ARG(n_boxes >= 0, "n_boxes < 0");
+  if (n_boxes == 0) return OBBV_OK;
+  OBBV_ARG(mesh_frame && out_X && boxes, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  void* q = nullptr;
+  OBBV_RET(pool_get(kPoolFeat, (size_t)n_boxes * (512 * 4 + 8), &q));
+  float* occ = (float*)q;
+  double* obv = (double*)(occ + (size_t)n_boxes * 512);
+  OBBV_HIP(hipMemsetAsync(occ, 0, (size_t)n_boxes * 512 * 4, s));
+  obbv_ov_params p{8, 4u, seed, 8, 0u};
+  OBBV_RET(outer_volume_impl(meshes, n_meshes, boxes, box_mesh, nullptr, n_boxes, &p, obv, nullptr, nullptr, nullptr,
+                             nullptr, s, occ));
+  hipLaunchKernelGGL(k_features, dim3((unsigned)n_boxes), dim3(128), 0, s, boxes, box_mesh, n_meshes, mesh_frame, occ,
+                     n_boxes, out_X);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// occupancy volume of a mesh and ranker inputs sampled from it
+// ---------------------------------------------------------------------------
+namespace obbv {
+namespace {
+// axis-aligned tiling boxes of the bounding box: nb^3 boxes, box (bx, by, bz) at
+// index (bz * nb + by) * nb + bx
+__global__ void k_tiling_boxes(const float* __restrict__ frame, int nb, obbv_box* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb * nb * nb) return;
+  const int bx = i % nb, by = (i / nb) % nb, bz = i / (nb * nb);
+  float* o = reinterpret_cast<float*>(out + i);
+  const int idx[3] = {bx, by, bz};
+  for (int k = 0; k < 3; ++k) {
+    const float cell = 8.0f * frame[3 + k];
+    o[k] = frame[k] + (idx[k] + 0.5f) * cell;  // centre
+    o[12 + k] = 0.5f * cell;                     // half extent
+  }
+  for (int k = 0; k < 9; ++k) o[3 + k] = (k % 4 == 0) ? 1.f : 0.f;
+}
+
+// occupancy [box][x][y][z] of the tiling boxes -> volume [z][y][x]
+__global__ void k_scatter_volume(const float* __restrict__ occ, int nb, float* __restrict__ vol) {
+  const int64_t n = (int64_t)nb * nb * nb * 512;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t box = t / 512;
+  const int r = (int)(t % 512);
+  const int x = r / 64, y = (r / 8) % 8, z = r % 8;
+  const int bx = (int)(box % nb), by = (int)((box / nb) % nb), bz = (int)(box / ((int64_t)nb * nb));
+  const int64_t N = 8 * nb;
+  vol[((int64_t)(8 * bz + z) * N + (8 * by + y)) * N + (8 * bx + x)] = occ[t];
+}
+
+__device__ inline float vol_at(const float* __restrict__ vol, int N, int x, int y, int z) {
+  if (x < 0 || y < 0 || z < 0 || x >= N || y >= N || z >= N) return 0.f;
+  return vol[((int64_t)z * N + y) * N + x];
+}
+
+// ranker input rows from the occupancy volume: box parameters normalised by the
+// mesh frame, then the volume sampled (trilinear, voxel centres at origin + (i + 1/2) voxel)
+// at the 8 x 8 x 8 sub-cell centres of the box
+__global__ void k_sample_features(const float* __restrict__ vol, int N, const float* __restrict__ frame,
+                                  const obbv_box* __restrict__ boxes, int n, float* __restrict__ X) {
+  const int b = blockIdx.x;
+  if (b >= n) return;
+  const float* p = reinterpret_cast<const float*>(boxes + b);
+  float* x = X + (int64_t)b * 544;
+  for (int k = threadIdx.x; k < 544; k += blockDim.x) {
+    float v = 0.f;
+    if (k < 3) {
+      v = (p[k] - frame[6 + k]) / frame[9];
+    } else if (k < 12) {
+      v = p[k];
+    } else if (k < 15) {
+      v = logf(fmaxf(p[k], 1e-30f) / frame[9]);
+    } else if (k < 527) {
+      const int r = k - 15;
+      const int ix = r / 64, iy = (r / 8) % 8, iz = r % 8;
+      const float l0 = ((ix + 0.5f) / 4.0f - 1.0f) * p[12];
+      const float l1 = ((iy + 0.5f) / 4.0f - 1.0f) * p[13];
+      const float l2 = ((iz + 0.5f) / 4.0f - 1.0f) * p[14];
+      float g[3];
+      for (int d = 0; d < 3; ++d) {
+        const float w = p[d] + l0 * p[3 + d] + l1 * p[6 + d] + l2 * p[9 + d];
+        g[d] = (w - frame[d]) / frame[3 + d] - 0.5f;  // continuous voxel coordinate
+      }
+      const int x0 = (int)floorf(g[0]), y0 = (int)floorf(g[1]), z0 = (int)floorf(g[2]);
+      const float fx = g[0] - x0, fy = g[1] - y0, fz = g[2] - z0;
+      float acc = 0.f;
+      for (int c = 0; c < 8; ++c) {
+        const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+        const float wgt = (dx ? fx : 1.f - fx) * (dy ? fy : 1.f - fy) * (dz ? fz : 1.f - fz);
+        acc += wgt * vol_at(vol, N, x0 + dx, y0 + dy, z0 + dz);
+      }
+      v = acc;
+    }
+    x[k] = v;
+  }
+}
+}  // namespace
+}  // namespace obbv
+
+extern "C" int obbv_occupancy_volume(const obbv_mesh* mesh, int32_t nb, const float* frame, uint64_t seed,
+                                     float* out_volume, void* stream) {
+  using namespace obbv;
+  clear_error();
+  OBBV_ARG(mesh && frame && out_volume, "NULL argument");
+  OBBV_ARG(nb >= 1 && nb <= 64, "nb must be in [1, 64]");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = nb * nb * nb;
+  void* q = nullptr;
+  OBBV_RET(pool_get(kPoolFeat, (size_t)n * (512 * 4 + 8 + sizeof(obbv_box)) + 1024, &q));
+  float* occ = (float*)q;
+  double* obv = (double*)(occ + (size_t)n * 512);
+  obbv_box* tb = (obbv_box*)(obv + n);
+  OBBV_HIP(hipMemsetAsync(occ, 0, (size_t)n * 512 * 4, s));
+  hipLaunchKernelGGL(k_tiling_boxes, dim3(ceil_div(n, 128)), dim3(128), 0, s, frame, nb, tb);
+  OBBV_HIP(hipGetLastError());
+  obbv_ov_params p{8, 4u, seed, 8, 0u};
+  OBBV_RET(outer_volume_impl(mesh, 1, tb, nullptr, nullptr, n, &p, obv, nullptr, nullptr, nullptr, nullptr, s, occ));
+  hipLaunchKernelGGL(k_scatter_volume, dim3(ceil_div((int64_t)n * 512, 256)), dim3(256), 0, s, occ, nb, out_volume);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+extern "C" int obbv_sample_features(const float* volume, int32_t N, const float* frame, const obbv_box* boxes,
+                                    int32_t n_boxes, float* out_X, void* stream) {
+  using namespace obbv;
+  clear_error();
+  OBBV_ARG(n_boxes >= 0 && N >= 1, "bad size");
+  if (n_boxes == 0) return OBBV_OK;
+  OBBV_ARG(volume && frame && boxes && out_X, "NULL argument");
+  hipLaunchKernelGGL(k_sample_features, dim3((unsigned)n_boxes), dim3(128), 0, (hipStream_t)stream, volume, N, frame,
+                     boxes, n_boxes, out_X);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
 }
