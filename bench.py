@@ -11,7 +11,8 @@ flood pops per group per round.  One step = one complete obbv_build_hierarchy.
 
 `value` is box outer-volume evaluations per second over the build; `moves_per_s`
 the Lloyd moves (triangle assignments) decided per second (exact evaluation
-only).  The roofline object describes the ray-test kernel (k_test): algorithmic
+only).  `surrogate` trains the candidate ranker on noisy spheres and rebuilds
+the same hierarchy with ranker-guided floods (moves/s and final error vs exact).  The roofline object describes the ray-test kernel (k_test): algorithmic
 FP32 FLOP (16 per ray-triangle test) over its average launch time, measured with
 HIP events on the library's stream.  `saturated` repeats the measurement on one
 large evaluation (the 85 boxes of the built hierarchy plus 4,011 perturbed
@@ -19,6 +20,7 @@ copies) for context.  `cpu_baseline` times the CPU oracle on a bounded sample of
 the hierarchy's boxes.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +37,28 @@ FP32_PEAK_TFLOPS = 157.3
 FLOP_PER_TEST = 16          # 3 edge functions x 2 FMA + depth plane 2 FMA
 HIER = dict(levels=4, branching=4, iters=20, sweeps=2, R=128, seed=23, pops_per_round=32)
 SEED_MESH = 21
+
+
+# HBM traffic of k_test per launch on this workload, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, summed over the k_test dispatches of one build),
+# each scaled by the same counter's reading for a plain device copy of known size.
+# Valid only for the kernel source it was measured on: any change to the
+# outer-volume source (hash below) reports null until the counters are re-taken.
+K_TEST_TRAFFIC = None
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def traffic_bytes():
+    if K_TEST_TRAFFIC is None:
+        return None
+    src = os.path.join(ROOT, "paper_2203_10521_amd", "csrc", "outer_volume.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != K_TEST_TRAFFIC["source_sha256"]:
+            return None
+    return K_TEST_TRAFFIC["fetch_bytes_per_launch"] + K_TEST_TRAFFIC["write_bytes_per_launch"]
 
 
 def roofline(test_ms, launches, tests):
@@ -69,6 +93,41 @@ def saturated(api, torch, Vt, Ft, boxes, R, seed):
             "achieved_tflops": achieved, "frac": achieved / FP32_PEAK_TFLOPS}
 
 
+def surrogate_comparison(api, torch, Vt, Ft, hp, exact):
+    """Train the ranker on exact outer fractions of noisy spheres (not the torus),
+    then rebuild the same torus hierarchy with ranker-guided floods."""
+    import synth
+    from paper_2203_10521_amd import ranker
+    t0 = time.perf_counter()
+    meshes, boxes = [], []
+    for k in range(8):
+        V, F = synth.noisy_cube_sphere(16 + 6 * k, seed=500 + k)
+        meshes.append((torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()))
+        boxes.append(torch.from_numpy(synth.mixed_boxes(V, 8192, seed=600 + k)).cuda())
+    X, t, _ = ranker.make_dataset(meshes, boxes, R=64, seed=1, nb=16)
+    n_val = 8192
+    P, losses = ranker.train(X[n_val:], t[n_val:], steps=3000, batch=4096, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    val_mae = (ranker.predict(P, X[:n_val]) - t[:n_val]).abs().mean().item()
+    occ_mae = (ranker.occupancy_heuristic(X[:n_val]) - t[:n_val]).abs().mean().item()
+    vol, frame = api.occupancy_volume(Vt, Ft, nb=16, seed=1)
+    sur = api.Surrogate(P, vol, frame, verify_top=1, max_error=0.05)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = api.build_hierarchy(Vt, Ft, surrogate=sur, **hp)
+    dt = time.perf_counter() - t1
+    c = out["counters"]
+    return {"moves_per_s": c["moves"] / dt, "exact_moves_per_s": exact["moves_per_s"],
+            "speedup": (c["moves"] / dt) / exact["moves_per_s"],
+            "final_e": float(out["e"][-1]), "exact_final_e": exact["final_e"],
+            "e_ratio": float(out["e"][-1]) / exact["final_e"],
+            "exact_evals": c["evals"], "exact_evals_without_ranker": exact["evals"],
+            "predictions": c["predicted"], "fallbacks": c["fallbacks"], "build_s": dt,
+            "train": {"samples": int(X.shape[0] - n_val), "steps": 3000, "seconds": train_s,
+                      "final_loss": losses[-1][1], "val_mae": val_mae, "occupancy_mean_val_mae": occ_mae}}
+
+
 def cpu_baseline(V, F, boxes, R, seed, budget_s=20.0):
     """The CPU oracle (float64 NumPy, one process) on a bounded sample of the
     hierarchy's boxes: evaluate boxes in a fixed order until about budget_s."""
@@ -97,8 +156,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-saturated", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--iters", type=int, default=HIER["iters"], help="Lloyd iterations per layer")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the memory-traffic counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        for _ in range(3):
+            y = x.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4, "copies": 3, "ok": bool(y[0].item() == 1.0)}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is described in DESIGN.md and not run.", file=sys.stderr)
@@ -115,8 +185,9 @@ def main():
     # create the library's scratch pools before the timed region
     api.outer_volume(Vt, Ft, torch.zeros((1, 15), dtype=torch.float32, device="cuda") + 0.5, 8)
     torch.cuda.synchronize()
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
         api.build_hierarchy(Vt, Ft, **hp)
+        log(f"warmup step {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
 
     api.profile_enable(True)
@@ -127,6 +198,7 @@ def main():
         out = api.build_hierarchy(Vt, Ft, **hp)
         evals += out["counters"]["evals"]
         moves += out["counters"]["moves"]
+        log(f"timed step done: {out['counters']['evals']} evaluations")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     test_ms, launches, tests = api.profile_read()
@@ -160,11 +232,19 @@ def main():
         "k_test_launches": launches,
         "tests_per_launch": per_launch,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None},
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic_bytes()},
     }
+    log(f"hierarchy: {evals / dt:.0f} evals/s, k_test {avg_ms:.4f} ms avg over {launches} launches")
+    if not args.no_surrogate:
+        log("surrogate comparison: training the ranker, then the guided build")
+        result["surrogate"] = surrogate_comparison(
+            api, torch, Vt, Ft, hp, {"moves_per_s": moves / dt, "final_e": float(out["e"][-1]),
+                                     "evals": evals / args.steps})
     if not args.no_saturated:
+        log("saturated evaluation")
         result["saturated"] = saturated(api, torch, Vt, Ft, out["boxes"], hp["R"], hp["seed"])
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(V, F, out["boxes"], hp["R"], hp["seed"])
     print(json.dumps(result), flush=True)
 

@@ -50,6 +50,8 @@ extern "C" {
 /* ---- device status word bits (obbv_status) ---------------------------- */
 #define OBBV_STATUS_NAN_BOX 0x1u      /* a box had a non-finite parameter        */
 #define OBBV_STATUS_BAD_INDEX 0x2u    /* a triangle index was out of range       */
+#define OBBV_STATUS_OVERFLOW 0x4u     /* a planned launch needed more scratch than
+                                         it was sized for; its results are invalid */
 
 /* ---- data types -------------------------------------------------------- */
 typedef struct {
@@ -155,6 +157,32 @@ int obbv_profile_enable(int enable);
  * returns it with the launch count and the test count, then clears the record.
  * Outputs are host pointers, each nullable. */
 int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests);
+
+/* ---- planned (graph-replayed) evaluations ------------------------------------ */
+
+typedef struct obbv_ov_plan obbv_ov_plan; /* opaque */
+
+/* Synchronous.  Plans repeated evaluations of the same argument pointers (the
+ * contents of `boxes` may change between launches): with params->tile == 0 the
+ * ray tile edge is autotuned (both edges timed; the choice is cached per device,
+ * R and size buckets), one synchronous evaluation sizes the scratch (times
+ * `headroom` >= 1), and one evaluation with fixed scratch, a persistent ray-test
+ * grid and no host round trip is captured into a HIP graph.  The plan owns its
+ * scratch; the caller's arrays must outlive it. */
+int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes, const int32_t* box_mesh,
+                        const uint32_t* box_key, int32_t n_boxes, const obbv_ov_params* params, double* out_obv,
+                        double headroom, void* stream, obbv_ov_plan** out);
+
+/* Asynchronous.  Replays the planned evaluation on `stream` (writes out_obv).  If
+ * the boxes now need more scratch than planned, OBBV_STATUS_OVERFLOW is set
+ * (read with obbv_status) and out_obv is not valid: plan again. */
+int obbv_ov_plan_launch(obbv_ov_plan* plan, void* stream);
+
+/* Host.  Chosen tile edge, capacities [records, bins, work items] and the
+ * autotuner's timings [tile 8, tile 16] in ms (0 when not tuned); each nullable. */
+int obbv_ov_plan_info(obbv_ov_plan* plan, int32_t* out_tile, int64_t* out_caps, float* out_tuned_ms);
+
+int obbv_ov_plan_destroy(obbv_ov_plan* plan);
 
 /* ---- covariance OBB fit -------------------------------------------------- */
 
@@ -307,9 +335,10 @@ int obbv_sample_features(const float* volume, int32_t N, const float* frame, con
  * order; W[i][o] multiplies input i into output o. */
 int64_t obbv_mlp_param_count(void);
 
-/* Predicted outer fraction OBV / V_box = sigmoid(MLP(X)) of n rows (device
- * X [n][544], out_f [n]); n a multiple of 32.  Products on bfloat16 MFMA with
- * float32 accumulation. */
+/* Predicted outer fraction OBV / V_box of n rows (device X [n][544], out_f [n]);
+ * n a multiple of 32.  The network corrects the occupancy estimate:
+ * f = (1 - mean of X[15..526]) + sigmoid(z) - 1/2, z the MLP output.  Products
+ * on bfloat16 MFMA with float32 accumulation. */
 int obbv_mlp_forward(const float* params, const float* X, int32_t n, float* out_f, void* stream);
 
 /* One training step on n rows (multiple of 32): forward, mean squared error

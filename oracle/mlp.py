@@ -2,7 +2,9 @@
 
 A small network predicts the outer fraction OBV / V_box of a candidate box from
 its 15 normalised parameters and an 8 x 8 x 8 occupancy of the box (527 inputs,
-zero-padded to 544): 544 -> 256 (ReLU) -> 256 (ReLU) -> 1 (sigmoid).  The HIP
+zero-padded to 544): 544 -> 256 (ReLU) -> 256 (ReLU) -> 1.  The output is a
+correction of the occupancy estimate h = 1 - mean(occupancy):
+f = h + sigmoid(z) - 1/2.  The HIP
 path multiplies bfloat16 operands with float32 accumulation; this oracle
 computes in float64 and, when ``bf16=True``, rounds to bfloat16
 (round-to-nearest-even) exactly where the HIP path feeds a matrix product:
@@ -24,7 +26,8 @@ def bf16(x):
 
 
 def init_params(seed=0):
-    """He-uniform weights, zero biases (float64); W are [in, out]."""
+    """He-uniform weights, the output layer scaled by 0.1 so that training starts
+    near the occupancy estimate (z close to 0), zero biases (float64); W are [in, out]."""
     g = np.random.default_rng(seed)
 
     def he(n_in, n_out):
@@ -33,7 +36,7 @@ def init_params(seed=0):
     W1 = he(D_PAD, D_H)
     W1[D_IN:] = 0.0
     return {"W1": W1, "b1": np.zeros(D_H), "W2": he(D_H, D_H), "b2": np.zeros(D_H),
-            "w3": he(D_H, 1)[:, 0], "b3": np.zeros(1)}
+            "w3": 0.1 * he(D_H, 1)[:, 0], "b3": np.zeros(1)}
 
 
 def forward(X, p, bf16_points=True):
@@ -46,8 +49,10 @@ def forward(X, p, bf16_points=True):
     H2 = np.maximum(Z2, 0.0)
     H2b = r(H2)
     z = H2b @ r(p["w3"]) + p["b3"][0]
-    f = 1.0 / (1.0 + np.exp(-z))
-    return f, {"Xb": Xb, "Z1": Z1, "H1b": H1b, "Z2": Z2, "H2b": H2b, "z": z}
+    sig = 1.0 / (1.0 + np.exp(-z))
+    h = 1.0 - np.asarray(X, np.float64)[:, 15:D_IN].mean(axis=1)
+    f = h + sig - 0.5
+    return f, {"Xb": Xb, "Z1": Z1, "H1b": H1b, "Z2": Z2, "H2b": H2b, "z": z, "sig": sig}
 
 
 def loss_and_grads(X, t, p, bf16_points=True):
@@ -56,7 +61,7 @@ def loss_and_grads(X, t, p, bf16_points=True):
     f, c = forward(X, p, bf16_points)
     n = X.shape[0]
     loss = float(np.mean((f - t) ** 2))
-    dz = 2.0 * (f - t) * f * (1.0 - f) / n
+    dz = 2.0 * (f - t) * c["sig"] * (1.0 - c["sig"]) / n
     dzb = r(dz)
     g = {"w3": c["H2b"].T @ dzb, "b3": np.array([dz.sum()])}
     dH2 = np.outer(dzb, r(p["w3"])) * (c["Z2"] > 0)

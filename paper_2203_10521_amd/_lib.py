@@ -59,6 +59,13 @@ SIGNATURES = {
     "obbv_outer_volume_ex": (c_int32, [ctypes.POINTER(ObbvMesh), c_int32, c_void_p, c_void_p, c_void_p,
                                        c_int32, ctypes.POINTER(ObbvOvParams), c_void_p, c_void_p,
                                        c_void_p, c_void_p, c_void_p, c_void_p]),
+    "obbv_ov_plan_create": (c_int32, [ctypes.POINTER(ObbvMesh), c_int32, c_void_p, c_void_p, c_void_p, c_int32,
+                                      ctypes.POINTER(ObbvOvParams), c_void_p, ctypes.c_double, c_void_p,
+                                      ctypes.POINTER(c_void_p)]),
+    "obbv_ov_plan_launch": (c_int32, [c_void_p, c_void_p]),
+    "obbv_ov_plan_info": (c_int32, [c_void_p, c_int32_p, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_float)]),
+    "obbv_ov_plan_destroy": (c_int32, [c_void_p]),
     "obbv_profile_enable": (c_int32, [c_int32]),
     "obbv_profile_read": (c_int32, [c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "obbv_fit": (c_int32, [ctypes.POINTER(ObbvMesh), c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),

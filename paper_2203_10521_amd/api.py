@@ -347,3 +347,41 @@ def sample_features(volume, frame, boxes, stream=None):
     _check(_lib.lib().obbv_sample_features(_ptr(volume), volume.shape[0], _ptr(frame), _ptr(boxes), boxes.shape[0],
                                            _ptr(X), _stream(stream)))
     return X
+
+
+class OuterVolumePlan:
+    """obbv_ov_plan_*: an autotuned, graph-captured evaluation of fixed arrays."""
+
+    def __init__(self, boxes, R, seed=0, axis_mask=7, tile=0, meshes=None, box_mesh=None, box_key=None,
+                 headroom=1.25, stream=None):
+        _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
+        self.boxes, self.box_mesh, self.box_key, self._meshes = boxes, box_mesh, box_key, meshes
+        self._structs = (_lib.ObbvMesh * len(meshes))(*[mesh_struct(v, f) for v, f in meshes])
+        self.out = torch.empty(boxes.shape[0], dtype=torch.float64, device=boxes.device)
+        self._p = _params(R, seed, axis_mask, tile)
+        self._h = ctypes.c_void_p(0)
+        _check(_lib.lib().obbv_ov_plan_create(self._structs, len(meshes), _ptr(boxes), _ptr(box_mesh),
+                                              _ptr(box_key), boxes.shape[0], ctypes.byref(self._p), _ptr(self.out),
+                                              float(headroom), _stream(stream), ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        _check(_lib.lib().obbv_ov_plan_launch(self._h, _stream(stream)))
+        return self.out
+
+    def info(self):
+        tile = ctypes.c_int32(0)
+        caps = (ctypes.c_int64 * 3)()
+        tms = (ctypes.c_float * 2)()
+        _check(_lib.lib().obbv_ov_plan_info(self._h, ctypes.byref(tile), caps, tms))
+        return {"tile": tile.value, "caps": list(caps), "tuned_ms": list(tms)}
+
+    def close(self):
+        if self._h:
+            _lib.lib().obbv_ov_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

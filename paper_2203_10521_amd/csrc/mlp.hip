@@ -1,5 +1,6 @@
-// Surrogate ranker MLP: 544 -> 256 (ReLU) -> 256 (ReLU) -> 1 (sigmoid), trained
-// on (box, outer fraction) pairs from the exact outer-volume kernel.
+// Surrogate ranker MLP: 544 -> 256 (ReLU) -> 256 (ReLU) -> 1, trained on (box,
+// outer fraction) pairs from the exact outer-volume kernel.  The output corrects
+// the occupancy estimate: f = (1 - mean occupancy) + sigmoid(z) - 1/2.
 //
 // Every matrix product runs on MFMA (v_mfma_f32_32x32x8bf16_1k): operands are
 // rounded to bfloat16 (round to nearest even) as they are loaded, products are
@@ -82,20 +83,26 @@ __global__ void k_bias_relu(float* __restrict__ Z, const float* __restrict__ b, 
   Z[i] = fmaxf(Z[i] + b[i % w], 0.f);
 }
 
-// z = bf16(H2) . bf16(w3) + b3; f = sigmoid(z); with targets: dz and the loss
-__global__ void k_head(const float* __restrict__ H2, const float* __restrict__ P, int n, float* __restrict__ f,
-                       const float* __restrict__ t, float* __restrict__ dz, float* __restrict__ loss) {
+// z = bf16(H2) . bf16(w3) + b3; the output corrects the occupancy estimate
+// h = 1 - mean(X[15..526]): f = h + sigmoid(z) - 1/2; with targets: dz and the loss
+__global__ void k_head(const float* __restrict__ H2, const float* __restrict__ P, const float* __restrict__ X, int n,
+                       float* __restrict__ f, const float* __restrict__ t, float* __restrict__ dz,
+                       float* __restrict__ loss) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n) return;
-  const float* h = H2 + (int64_t)row * kH;
+  const float* hr = H2 + (int64_t)row * kH;
   float z = 0.f;
-  for (int c = 0; c < kH; ++c) z = fmaf(bf(h[c]), bf(P[ow3 + c]), z);
+  for (int c = 0; c < kH; ++c) z = fmaf(bf(hr[c]), bf(P[ow3 + c]), z);
   z += P[ob3];
-  const float fr = 1.f / (1.f + expf(-z));
+  const float* x = X + (int64_t)row * kIn;
+  float occ = 0.f;
+  for (int c = 15; c < 527; ++c) occ += x[c];
+  const float sig = 1.f / (1.f + expf(-z));
+  const float fr = (1.f - occ / 512.f) + sig - 0.5f;
   f[row] = fr;
   if (t) {
     const float e = fr - t[row];
-    dz[row] = 2.f * e * fr * (1.f - fr) / (float)n;
+    dz[row] = 2.f * e * sig * (1.f - sig) / (float)n;
     atomicAdd(loss, e * e / (float)n);
   }
 }
@@ -192,7 +199,7 @@ int forward(const float* P, const float* X, int n, MlpScratch& S, float* out_f, 
   OBBV_RET(gemm(S.H1, kH, 1, P + oW2, kH, 1, S.H2, kH, 1, n, kH, kH, false, s));
   hipLaunchKernelGGL(k_bias_relu, dim3(blocks((int64_t)n * kH, 256)), dim3(256), 0, s, S.H2, P + ob2, (int64_t)n, kH);
   if (t) OBBV_HIP(hipMemsetAsync(S.loss, 0, 4, s));
-  hipLaunchKernelGGL(k_head, dim3(blocks(n, 256)), dim3(256), 0, s, S.H2, P, n, out_f, t, S.dz, S.loss);
+  hipLaunchKernelGGL(k_head, dim3(blocks(n, 256)), dim3(256), 0, s, S.H2, P, X, n, out_f, t, S.dz, S.loss);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
 }

@@ -185,7 +185,13 @@ struct CullArgs {
   int tpe;  // tiles per face edge
   uint32_t axis_mask;
   uint32_t* status;
+  int64_t rec_cap;  // record / bin capacity of the scratch (planned launches)
+  int64_t bin_cap;
 };
+
+__global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
 
 __global__ void k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ meshes,
                              int n_meshes, int n_boxes, int32_t* __restrict__ nch, uint32_t* status) {
@@ -439,6 +445,10 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
         continue;
       }
       const int64_t slot = rec_off[bw] + base + rank;
+      if (slot >= a.rec_cap) {  // more records than a planned launch was sized for
+        atomicOr(a.status, OBBV_STATUS_OVERFLOW);
+        continue;
+      }
       make_record(tr, mirror, f.hw, recs + 4 * slot);
       int ti0, ti1, tj0, tj1;
       tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
@@ -448,7 +458,9 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
           const int64_t tl = tbase + tj * a.tpe + ti;
           const int lt = w * TT + tj * a.tpe + ti;
           const int pos = lds ? base_pos[lt] + atomicAdd(&cnt[lt], 1) : atomicAdd(&bin_cur[tl], 1);
-          if (bin_off[tl] + pos < bin_off[tl + 1])
+          if (bin_off[tl] + pos >= a.bin_cap)
+            atomicOr(a.status, OBBV_STATUS_OVERFLOW);
+          else if (bin_off[tl] + pos < bin_off[tl + 1])
             bins[bin_off[tl] + pos] = (int32_t)slot;
           else
             atomicOr(a.status, OBBV_STATUS_BAD_INDEX);
@@ -479,6 +491,9 @@ struct TestArgs {
   int R;
   int tpe;
   uint32_t axis_mask;
+  int64_t bin_cap;      // planned launches: bins beyond it were not written
+  int64_t item_cap;     // planned launches: work items beyond it are skipped
+  int persistent;       // 1: grid-stride over the work items counted on the device
 };
 
 // One wave per TE x TE ray tile of one (box, axis); RPL = (TE/8)^2 rays per lane.
@@ -487,11 +502,23 @@ struct TestArgs {
 //   y = D u + E v + F (2 FMA), clamped to the triangle's slab part (med3),
 //   acc += inside ? bits(y) : kMagicBits   -- exact integer accumulation.
 template <int TE, bool STATS, bool STAGE, bool OCC>
+__device__ void test_item(const TestArgs& a, const int64_t item);
+
+template <int TE, bool STATS, bool STAGE, bool OCC>
 __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
+  if (!a.persistent) {
+    test_item<TE, STATS, STAGE, OCC>(a, xcd_remap(blockIdx.x, gridDim.x));
+    return;
+  }
+  const int64_t total = min(a.chunk_off[a.n_tiles], a.item_cap);
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) test_item<TE, STATS, STAGE, OCC>(a, item);
+}
+
+template <int TE, bool STATS, bool STAGE, bool OCC>
+__device__ void test_item(const TestArgs& a, const int64_t item) {
   constexpr int NB = TE / 8;
   constexpr int RPL = NB * NB;
   const int TT = a.tpe * a.tpe;
-  const int64_t item = xcd_remap(blockIdx.x, gridDim.x);
   // tile of this work item: chunk_off[g] <= item < chunk_off[g + 1]
   int64_t lo = 0, hi = a.n_tiles;
   while (hi - lo > 1) {
@@ -543,6 +570,7 @@ __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
   const int64_t kb = a.bin_off[g] + (item - a.chunk_off[g]) * a.chunk;
   const int64_t k0 = kb;
   const int64_t k1 = min(a.bin_off[g + 1], kb + a.chunk);
+  if (k1 > a.bin_cap) return;  // bins past a planned capacity were not written (flagged)
   auto test_record = [&](const float4 r0, const float4 r1, const float4 r2, const float4 r3) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
@@ -681,6 +709,23 @@ int pinned_totals(int64_t** out) {
   return OBBV_OK;
 }
 
+}  // namespace
+
+// How one evaluation is executed: the synchronous path sizes scratch from the
+// device counts (one host round trip); a planned launch uses fixed scratch and
+// never returns to the host, so it can be captured into a HIP graph.
+struct OvExec {
+  bool planned = false;
+  char* meta = nullptr;
+  size_t meta_cap = 0, meta_bytes = 0;
+  float4* recs = nullptr;
+  int32_t* bins = nullptr;
+  int64_t rec_cap = 0, bin_cap = 0, item_cap = 0;
+  int64_t n_rec = 0, n_bin = 0, n_items = 0;  // counts of the last synchronous run
+};
+
+namespace {
+
 template <int TE>
 int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hipStream_t s) {
   const dim3 g((unsigned)nblocks), b(kTestThreads);
@@ -708,11 +753,11 @@ bool test_stage_choice() {
 
 }  // namespace
 
-int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
-                      const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
-                      const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
-                      int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s,
-                      float* out_occ) {
+int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                     const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                     const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
+                     int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s,
+                     float* out_occ, OvExec* ex) {
   OBBV_ARG(params != nullptr, "params is NULL");
   OBBV_ARG(n_boxes >= 0, "n_boxes < 0");
   if (n_boxes == 0) return OBBV_OK;
@@ -736,6 +781,7 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
   }
   const int R = params->R;
   const int TE = out_occ ? 8 : (params->tile ? params->tile : (R >= 48 ? 16 : 8));
+  const bool planned = ex && ex->planned;
   OBBV_ARG(!out_occ || (R == 8 && mask == 4u), "occupancy needs R = 8 and axis_mask = 4");
   const int tpe = ceil_div(R, TE);
   const int64_t TT = (int64_t)tpe * tpe;
@@ -772,7 +818,16 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
       std::max(exclusive_scan_scratch_bytes(nbw * TT), exclusive_scan_scratch_bytes(std::max<int64_t>(nbw, n_boxes)));
   const size_t o_scan = take(scan_bytes);
   void* meta_v = nullptr;
-  OBBV_RET(pool_get(kPoolMeta, off, &meta_v));
+  if (planned) {
+    if (off > ex->meta_cap) {
+      set_error("planned scratch too small for this call");
+      return OBBV_ERR_WORKSPACE;
+    }
+    meta_v = ex->meta;
+  } else {
+    OBBV_RET(pool_get(kPoolMeta, off, &meta_v));
+  }
+  if (ex) ex->meta_bytes = off;
   char* meta = (char*)meta_v;
   MeshDev* d_mesh = (MeshDev*)(meta + o_mesh);
   int32_t* d_nch = (int32_t*)(meta + o_nch);
@@ -790,8 +845,9 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
   unsigned long long* d_acc = (unsigned long long*)(meta + o_acc);
   void* d_scan = meta + o_scan;
 
-  OBBV_HIP(hipMemcpyAsync(d_mesh, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
-  OBBV_HIP(hipMemsetAsync(meta + o_zero0, 0, o_zero1 - o_zero0, s));
+  if (!planned) OBBV_HIP(hipMemcpyAsync(d_mesh, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_fill_zero, dim3(256), dim3(256), 0, s, (uint32_t*)(meta + o_zero0),
+                     (int64_t)((o_zero1 - o_zero0) / 4));
 
   hipLaunchKernelGGL(k_box_chunks, dim3(ceil_div(n_boxes, 256)), dim3(256), 0, s, box_mesh, d_mesh,
                      n_meshes, n_boxes, d_nch, status);
@@ -809,6 +865,8 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
   ca.tpe = tpe;
   ca.axis_mask = mask;
   ca.status = status;
+  ca.rec_cap = planned ? ex->rec_cap : INT64_MAX;
+  ca.bin_cap = planned ? ex->bin_cap : INT64_MAX;
   const int64_t items_bound = (int64_t)n_boxes * ceil_div(std::max(max_nt, 1), kCullThreads);
   const unsigned cull_grid = (unsigned)std::min<int64_t>(items_bound, 256 * 16);
 
@@ -827,21 +885,40 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
   OBBV_HIP(hipGetLastError());
   OBBV_RET(exclusive_scan_i32_to_i64(d_nchunk, d_chunkoff, nbw * TT, d_scan, scan_bytes, s));
 
-  int64_t* pin = nullptr;
-  OBBV_RET(pinned_totals(&pin));
-  OBBV_HIP(hipMemcpyAsync(pin + 0, d_recoff + nbw, 8, hipMemcpyDeviceToHost, s));
-  OBBV_HIP(hipMemcpyAsync(pin + 1, d_binoff + nbw * TT, 8, hipMemcpyDeviceToHost, s));
-  OBBV_HIP(hipMemcpyAsync(pin + 2, d_chunkoff + nbw * TT, 8, hipMemcpyDeviceToHost, s));
-  OBBV_HIP(hipStreamSynchronize(s));
-  const int64_t n_rec = pin[0], n_bin = pin[1], n_items = pin[2];
+  int64_t n_rec, n_bin, n_items;
+  if (planned) {  // no host round trip: capacities were fixed when the launch was planned
+    n_rec = ex->rec_cap;
+    n_bin = ex->bin_cap;
+    n_items = ex->item_cap;
+  } else {
+    int64_t* pin = nullptr;
+    OBBV_RET(pinned_totals(&pin));
+    OBBV_HIP(hipMemcpyAsync(pin + 0, d_recoff + nbw, 8, hipMemcpyDeviceToHost, s));
+    OBBV_HIP(hipMemcpyAsync(pin + 1, d_binoff + nbw * TT, 8, hipMemcpyDeviceToHost, s));
+    OBBV_HIP(hipMemcpyAsync(pin + 2, d_chunkoff + nbw * TT, 8, hipMemcpyDeviceToHost, s));
+    OBBV_HIP(hipStreamSynchronize(s));
+    n_rec = pin[0];
+    n_bin = pin[1];
+    n_items = pin[2];
+    if (ex) {
+      ex->n_rec = n_rec;
+      ex->n_bin = n_bin;
+      ex->n_items = n_items;
+    }
+  }
   OBBV_ARG(n_items < (1ll << 31), "too many ray-test work items in one call; split the boxes");
   OBBV_ARG(n_rec < (1ll << 31), "more than 2^31 triangle records in one call; split the boxes");
 
   if (n_rec > 0) {
     void* recs_v = nullptr;
     void* bins_v = nullptr;
-    OBBV_RET(pool_get(kPoolRecords, (size_t)n_rec * 64, &recs_v));
-    OBBV_RET(pool_get(kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
+    if (planned) {
+      recs_v = ex->recs;
+      bins_v = ex->bins;
+    } else {
+      OBBV_RET(pool_get(kPoolRecords, (size_t)n_rec * 64, &recs_v));
+      OBBV_RET(pool_get(kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
+    }
     hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
                        d_reccnt, d_reccur, d_binoff, d_bincur, (float4*)recs_v, (int32_t*)bins_v);
     OBBV_HIP(hipGetLastError());
@@ -860,8 +937,11 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
     ta.test_counter = nullptr;
     ta.occ = out_occ;
     ta.side = d_side;
+    ta.bin_cap = planned ? ex->bin_cap : INT64_MAX;
+    ta.item_cap = planned ? ex->item_cap : INT64_MAX;
+    ta.persistent = planned ? 1 : 0;
     void* prof_token = nullptr;
-    if (profiling_enabled()) {
+    if (profiling_enabled() && !planned) {
       OBBV_RET(profile_counter(&ta.test_counter));
       OBBV_RET(profile_record_begin(s, &prof_token));
     }
@@ -879,12 +959,13 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
     }
     if (n_items > 0) {
       const bool stage = test_stage_choice();
+      const int64_t grid = planned ? std::min<int64_t>(n_items, 256 * 32) : n_items;
       if (TE == 8)
-        OBBV_RET(launch_test<8>(ta, n_items, stats, stage, s));
+        OBBV_RET(launch_test<8>(ta, grid, stats, stage, s));
       else
-        OBBV_RET(launch_test<16>(ta, n_items, stats, stage, s));
+        OBBV_RET(launch_test<16>(ta, grid, stats, stage, s));
     }
-    if (prof_token != nullptr || profiling_enabled()) OBBV_RET(profile_record_end(s, prof_token));
+    if (profiling_enabled() && !planned) OBBV_RET(profile_record_end(s, prof_token));
   } else if (out_ray_q || out_ray_hits) {
     const size_t per = (size_t)nbw * R * R * 4;
     if (out_ray_q) OBBV_HIP(hipMemsetAsync(out_ray_q, 0, per, s));
@@ -895,6 +976,15 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
                      d_acc, out_obv, out_vin_axis, status);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
+}
+
+int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                      const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                      const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
+                      int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s,
+                      float* out_occ) {
+  return outer_volume_run(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, params, out_obv, out_vin_axis,
+                          out_ray_q, out_ray_hits, out_side, s, out_occ, nullptr);
 }
 
 }  // namespace obbv
@@ -1087,5 +1177,204 @@ extern "C" int obbv_sample_features(const float* volume, int32_t N, const float*
   hipLaunchKernelGGL(k_sample_features, dim3((unsigned)n_boxes), dim3(128), 0, (hipStream_t)stream, volume, N, frame,
                      boxes, n_boxes, out_X);
   OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// planned evaluations: autotuned tile size, fixed scratch, HIP graph replay
+// ---------------------------------------------------------------------------
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+
+namespace obbv {
+namespace {
+
+struct OvPlanState {
+  std::vector<obbv_mesh> meshes;
+  const obbv_box* boxes = nullptr;
+  const int32_t* box_mesh = nullptr;
+  const uint32_t* box_key = nullptr;
+  int32_t n_boxes = 0;
+  obbv_ov_params params{};
+  double* out_obv = nullptr;
+  OvExec ex;
+  void* alloc = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  float tuned_ms[2] = {0.f, 0.f};
+};
+
+// autotuner cache: (device, R, boxes bucket, triangles bucket) -> tile edge
+std::map<std::tuple<int, int, int, int>, int> g_tile_cache;
+std::mutex g_tile_mutex;
+
+inline int bucket(int64_t x) {
+  int b = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+int time_tile(OvPlanState& P, int tile, hipStream_t s, float* ms) {
+  obbv_ov_params p = P.params;
+  p.tile = tile;
+  hipEvent_t a, b;
+  OBBV_HIP(hipEventCreate(&a));
+  OBBV_HIP(hipEventCreate(&b));
+  int rc = outer_volume_impl(P.meshes.data(), (int32_t)P.meshes.size(), P.boxes, P.box_mesh, P.box_key, P.n_boxes,
+                             &p, P.out_obv, nullptr, nullptr, nullptr, nullptr, s, nullptr);  // warm
+  if (rc == OBBV_OK) rc = hipEventRecord(a, s) == hipSuccess ? OBBV_OK : OBBV_ERR_HIP;
+  for (int r = 0; r < 2 && rc == OBBV_OK; ++r)
+    rc = outer_volume_impl(P.meshes.data(), (int32_t)P.meshes.size(), P.boxes, P.box_mesh, P.box_key, P.n_boxes, &p,
+                           P.out_obv, nullptr, nullptr, nullptr, nullptr, s, nullptr);
+  if (rc == OBBV_OK) rc = hipEventRecord(b, s) == hipSuccess ? OBBV_OK : OBBV_ERR_HIP;
+  if (rc == OBBV_OK) rc = hipEventSynchronize(b) == hipSuccess ? OBBV_OK : OBBV_ERR_HIP;
+  if (rc == OBBV_OK) rc = hipEventElapsedTime(ms, a, b) == hipSuccess ? OBBV_OK : OBBV_ERR_HIP;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+}  // namespace
+}  // namespace obbv
+
+extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                   const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                                   const obbv_ov_params* params, double* out_obv, double headroom, void* stream,
+                                   obbv_ov_plan** out) {
+  using namespace obbv;
+  clear_error();
+  OBBV_ARG(out && meshes && params && boxes && out_obv, "NULL argument");
+  OBBV_ARG(n_boxes >= 1 && n_meshes >= 1, "need boxes and meshes");
+  OBBV_ARG(headroom >= 1.0, "headroom must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<OvPlanState> P(new OvPlanState());
+  P->meshes.assign(meshes, meshes + n_meshes);
+  P->boxes = boxes;
+  P->box_mesh = box_mesh;
+  P->box_key = box_key;
+  P->n_boxes = n_boxes;
+  P->params = *params;
+  P->out_obv = out_obv;
+  // autotune the ray tile edge (8: one ray per lane, 16: four rays per lane)
+  if (P->params.tile == 0) {
+    int dev = 0;
+    OBBV_HIP(hipGetDevice(&dev));
+    int64_t ntri = 0;
+    for (int m = 0; m < n_meshes; ++m) ntri += meshes[m].n_triangles;
+    const auto key = std::make_tuple(dev, P->params.R, bucket(n_boxes), bucket(ntri / n_meshes));
+    int tile = 0;
+    {
+      std::lock_guard<std::mutex> lock(g_tile_mutex);
+      auto it = g_tile_cache.find(key);
+      if (it != g_tile_cache.end()) tile = it->second;
+    }
+    if (!tile) {
+      OBBV_RET(time_tile(*P, 8, s, &P->tuned_ms[0]));
+      OBBV_RET(time_tile(*P, 16, s, &P->tuned_ms[1]));
+      tile = P->tuned_ms[0] <= P->tuned_ms[1] ? 8 : 16;
+      std::lock_guard<std::mutex> lock(g_tile_mutex);
+      g_tile_cache[key] = tile;
+    }
+    P->params.tile = tile;
+  }
+  // size the scratch with one synchronous evaluation
+  OvExec probe;
+  OBBV_RET(outer_volume_run(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, &P->params, out_obv, nullptr,
+                            nullptr, nullptr, nullptr, s, nullptr, &probe));
+  OBBV_HIP(hipStreamSynchronize(s));
+  OvExec& ex = P->ex;
+  ex.planned = true;
+  ex.meta_cap = probe.meta_bytes;
+  ex.rec_cap = (int64_t)std::ceil((double)probe.n_rec * headroom) + 1024;
+  ex.bin_cap = (int64_t)std::ceil((double)probe.n_bin * headroom) + 4096;
+  ex.item_cap = (int64_t)std::ceil((double)probe.n_items * headroom) + 64;
+  const size_t bytes = align_up(ex.meta_cap) + align_up((size_t)ex.rec_cap * 64) + align_up((size_t)ex.bin_cap * 4);
+  if (hipMalloc(&P->alloc, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of the planned scratch failed");
+    return OBBV_ERR_OOM;
+  }
+  ex.meta = (char*)P->alloc;
+  ex.recs = (float4*)(ex.meta + align_up(ex.meta_cap));
+  ex.bins = (int32_t*)((char*)ex.recs + align_up((size_t)ex.rec_cap * 64));
+  // the mesh table lives at the start of the meta block (outside the graph)
+  std::vector<MeshDev> mh((size_t)n_meshes);
+  for (int m = 0; m < n_meshes; ++m)
+    mh[m] = MeshDev{meshes[m].vertices, meshes[m].triangles, meshes[m].n_vertices, meshes[m].n_triangles};
+  OBBV_HIP(hipMemcpy(ex.meta, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice));
+  uint32_t* st = nullptr;
+  OBBV_RET(status_word(&st));
+  // capture one evaluation on a private stream
+  hipStream_t cs = nullptr;
+  OBBV_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  OBBV_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  int rc = outer_volume_run(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, &P->params, out_obv, nullptr,
+                            nullptr, nullptr, nullptr, cs, nullptr, &ex);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
+  if (rc != OBBV_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipFree(P->alloc);
+    return rc;
+  }
+  if (ec != hipSuccess) {
+    (void)hipFree(P->alloc);
+    set_error(std::string("graph capture failed: ") + hipGetErrorString(ec));
+    return OBBV_ERR_HIP;
+  }
+  P->graph = g;
+  if (hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    (void)hipFree(P->alloc);
+    set_error("hipGraphInstantiate failed");
+    return OBBV_ERR_HIP;
+  }
+  *out = reinterpret_cast<obbv_ov_plan*>(P.release());
+  return OBBV_OK;
+}
+
+extern "C" int obbv_ov_plan_launch(obbv_ov_plan* plan, void* stream) {
+  using namespace obbv;
+  clear_error();
+  OBBV_ARG(plan, "NULL plan");
+  OvPlanState* P = reinterpret_cast<OvPlanState*>(plan);
+  OBBV_HIP(hipGraphLaunch(P->exec, (hipStream_t)stream));
+  return OBBV_OK;
+}
+
+extern "C" int obbv_ov_plan_info(obbv_ov_plan* plan, int32_t* out_tile, int64_t* out_caps, float* out_tuned_ms) {
+  using namespace obbv;
+  clear_error();
+  OBBV_ARG(plan, "NULL plan");
+  OvPlanState* P = reinterpret_cast<OvPlanState*>(plan);
+  if (out_tile) *out_tile = P->params.tile;
+  if (out_caps) {
+    out_caps[0] = P->ex.rec_cap;
+    out_caps[1] = P->ex.bin_cap;
+    out_caps[2] = P->ex.item_cap;
+  }
+  if (out_tuned_ms) {
+    out_tuned_ms[0] = P->tuned_ms[0];
+    out_tuned_ms[1] = P->tuned_ms[1];
+  }
+  return OBBV_OK;
+}
+
+extern "C" int obbv_ov_plan_destroy(obbv_ov_plan* plan) {
+  using namespace obbv;
+  clear_error();
+  if (!plan) return OBBV_OK;
+  OvPlanState* P = reinterpret_cast<OvPlanState*>(plan);
+  OBBV_HIP(hipDeviceSynchronize());
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->alloc) (void)hipFree(P->alloc);
+  delete P;
   return OBBV_OK;
 }

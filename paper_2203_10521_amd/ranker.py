@@ -1,0 +1,85 @@
+"""Training and evaluation of the candidate-box ranker (learned part of the flood).
+
+Orchestration only: the training targets are outer fractions OBV / V_box from
+the exact kernel (obbv_outer_volume), the inputs come from obbv_sample_features,
+and every forward, backward and Adam step runs in the library's MFMA kernels.
+"""
+import math
+
+import numpy as np
+import torch
+
+from . import api
+
+PARAMS = 544 * 256 + 256 + 256 * 256 + 256 + 256 + 1
+
+
+def init_params(seed=0):
+    """He-uniform weights (first-layer rows past the 527 real inputs zero, the output
+    layer scaled by 0.1 so that training starts near the occupancy estimate), zero biases."""
+    g = np.random.default_rng(seed)
+
+    def he(n_in, n_out):
+        lim = math.sqrt(6.0 / n_in)
+        return g.uniform(-lim, lim, size=(n_in, n_out))
+    W1 = he(544, 256)
+    W1[527:] = 0.0
+    return {"W1": W1, "b1": np.zeros(256), "W2": he(256, 256), "b2": np.zeros(256),
+            "w3": 0.1 * he(256, 1)[:, 0], "b3": np.zeros(1)}
+
+
+def make_dataset(meshes, boxes, R=64, seed=0, nb=16):
+    """Ranker inputs and targets for every (mesh, box set) pair.
+
+    meshes: list of (V, F) device tensors; boxes: list of float32 [n, 15] device
+    tensors.  Returns (X [N, 544], t [N]) on the device and the per-mesh
+    (volume, frame) used for the features.
+    """
+    Xs, ts, vols = [], [], []
+    for (Vt, Ft), B in zip(meshes, boxes):
+        vol, frame = api.occupancy_volume(Vt, Ft, nb=nb, seed=seed)
+        obv = api.outer_volume(Vt, Ft, B, R, seed=seed)
+        vb = 8.0 * B[:, 12].double() * B[:, 13].double() * B[:, 14].double()
+        ok = vb > 0
+        t = torch.zeros_like(obv)
+        t[ok] = (obv[ok] / vb[ok]).clamp(0.0, 1.0)
+        Xs.append(api.sample_features(vol, frame, B))
+        ts.append(t.to(torch.float32))
+        vols.append((vol, frame))
+    return torch.cat(Xs), torch.cat(ts), vols
+
+
+def train(X, t, steps=2000, batch=4096, lr=1e-3, seed=0, log_every=0):
+    """Adam with a cosine learning-rate decay on random mini-batches; returns
+    (float32 parameter vector on the device, list of batch losses)."""
+    P = torch.from_numpy(api.mlp_pack(init_params(seed))).to(X.device)
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    n = X.shape[0]
+    batch = min(batch, n // 32 * 32)
+    gen = torch.Generator(device=X.device)
+    gen.manual_seed(seed)
+    losses = []
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, n, (batch,), device=X.device, generator=gen)
+        rate = lr * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / steps))
+        loss, _ = api.mlp_train_step(P, m, v, step, X[idx].contiguous(), t[idx].contiguous(), rate)
+        if log_every and (step % log_every == 0 or step == 1):
+            losses.append((step, float(loss.item())))
+    if not log_every:
+        losses.append((steps, float(loss.item())))
+    return P, losses
+
+
+def predict(P, X):
+    """Predicted outer fractions of the rows of X (padded to a multiple of 32)."""
+    n = X.shape[0]
+    pad = (-n) % 32
+    if pad:
+        X = torch.cat([X, torch.zeros((pad, X.shape[1]), dtype=X.dtype, device=X.device)])
+    return api.mlp_forward(P, X.contiguous())[:n]
+
+
+def occupancy_heuristic(X):
+    """Outer fraction estimated as 1 - mean of the 512 sampled occupancies."""
+    return 1.0 - X[:, 15:527].mean(dim=1)

@@ -6,11 +6,11 @@ both the CPU oracle and the HIP library receive these arrays as plain inputs.
 """
 from .meshes import (icosahedron, icosphere, cuboid, octahedron, tetrahedron,
                      noisy_torus, noisy_cube_sphere, helix_tube, disjoint_cuboids)
-from .boxes import random_boxes, quat_to_axes, axis_aligned_box, boxes_to_array
+from .boxes import random_boxes, quat_to_axes, axis_aligned_box, boxes_to_array, mixed_boxes
 
 __all__ = [
     "icosahedron", "icosphere", "cuboid", "octahedron", "tetrahedron",
     "noisy_torus", "noisy_cube_sphere", "helix_tube", "disjoint_cuboids",
-    "random_boxes", "quat_to_axes", "axis_aligned_box",
+    "random_boxes", "quat_to_axes", "axis_aligned_box", "mixed_boxes",
     "boxes_to_array",
 ]

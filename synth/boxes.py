@@ -52,3 +52,24 @@ def boxes_to_array(center, axes, half):
     axes = np.asarray(axes, dtype=np.float32).reshape(n, 9)
     half = np.asarray(half, dtype=np.float32).reshape(n, 3)
     return np.ascontiguousarray(np.concatenate([center, axes, half], axis=1))
+
+
+def mixed_boxes(V, n, seed, surface_frac=0.5):
+    """n boxes around a mesh with vertices V: a `surface_frac` share centred near
+    random vertices (half extents U[0.02, 0.3] x diagonal, like boxes grown around
+    surface patches), the rest with centres uniform in the bounding box grown by
+    10% (half extents U[0.03, 0.5] x diagonal); uniform random rotations.
+    Returns float32 [n, 15] rows (center, axes, half)."""
+    rng = np.random.default_rng(seed)
+    V = np.asarray(V, dtype=np.float64)
+    lo, hi = V.min(0), V.max(0)
+    diag = float(np.linalg.norm(hi - lo))
+    ns = int(round(n * surface_frac))
+    c_s = V[rng.integers(0, len(V), ns)] + rng.normal(0, 0.02 * diag, (ns, 3))
+    h_s = rng.uniform(0.02, 0.3, (ns, 3)) * diag
+    span = hi - lo
+    c_r = rng.uniform(lo - 0.1 * span, hi + 0.1 * span, (n - ns, 3))
+    h_r = rng.uniform(0.03, 0.5, (n - ns, 3)) * diag
+    qs = _uniform_quaternions(rng, n)
+    axes = np.stack([quat_to_axes(q) for q in qs]) if n else np.zeros((0, 3, 3))
+    return boxes_to_array(np.vstack([c_s, c_r]), axes, np.vstack([h_s, h_r]))

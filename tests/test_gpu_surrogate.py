@@ -94,8 +94,10 @@ def test_mlp_training_reduces_loss(api):
     g = np.random.default_rng(8)
     n = 512
     X = g.normal(0, 1.0, size=(n, omlp.D_PAD)).astype(np.float32)
+    X[:, 15:omlp.D_IN] = g.uniform(0, 1, size=(n, omlp.D_IN - 15))
     X[:, omlp.D_IN:] = 0
-    t = (1.0 / (1.0 + np.exp(-(X[:, 0] - 0.5 * X[:, 20] + 0.3 * X[:, 100])))).astype(np.float32)
+    h = 1.0 - X[:, 15:omlp.D_IN].mean(axis=1)
+    t = np.clip(h + 0.2 * np.tanh(X[:, 0] - 0.5 * X[:, 5] + 0.3 * X[:, 10]), 0, 1).astype(np.float32)
     P = torch.from_numpy(api.mlp_pack(omlp.init_params(seed=1))).cuda()
     m, v = torch.zeros_like(P), torch.zeros_like(P)
     Xt, tt = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
