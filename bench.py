@@ -94,8 +94,9 @@ def saturated(api, torch, Vt, Ft, boxes, R, seed):
 
 
 def surrogate_comparison(api, torch, Vt, Ft, hp, exact):
-    """Train the ranker on exact outer fractions of noisy spheres (not the torus),
-    then rebuild the same torus hierarchy with ranker-guided floods."""
+    """Train the ranker on exact outer fractions of noisy spheres (not the torus):
+    boxes recorded during exact Lloyd iterations plus random boxes around the
+    surface; then rebuild the same torus hierarchy with ranker-guided floods."""
     import synth
     from paper_2203_10521_amd import ranker
     t0 = time.perf_counter()
@@ -103,16 +104,18 @@ def surrogate_comparison(api, torch, Vt, Ft, hp, exact):
     for k in range(8):
         V, F = synth.noisy_cube_sphere(16 + 6 * k, seed=500 + k)
         meshes.append((torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()))
-        boxes.append(torch.from_numpy(synth.mixed_boxes(V, 8192, seed=600 + k)).cuda())
+        rec = ranker.lloyd_boxes(V, F, R=64, seed=700 + k, n_groups=16, iters=2, cap=8192)
+        mixed = synth.mixed_boxes(V, 16384 - len(rec), seed=600 + k)
+        boxes.append(torch.from_numpy(np.concatenate([rec, mixed])).cuda())
     X, t, _ = ranker.make_dataset(meshes, boxes, R=64, seed=1, nb=16)
-    n_val = 8192
-    P, losses = ranker.train(X[n_val:], t[n_val:], steps=3000, batch=4096, lr=2e-3, seed=0)
+    n_val = boxes[-1].shape[0]          # the last sphere is held out for validation
+    P, losses = ranker.train(X[:-n_val], t[:-n_val], steps=3000, batch=4096, lr=2e-3, seed=0)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    val_mae = (ranker.predict(P, X[:n_val]) - t[:n_val]).abs().mean().item()
-    occ_mae = (ranker.occupancy_heuristic(X[:n_val]) - t[:n_val]).abs().mean().item()
+    val_mae = (ranker.predict(P, X[-n_val:]) - t[-n_val:]).abs().mean().item()
+    occ_mae = (ranker.occupancy_heuristic(X[-n_val:]) - t[-n_val:]).abs().mean().item()
     vol, frame = api.occupancy_volume(Vt, Ft, nb=16, seed=1)
-    sur = api.Surrogate(P, vol, frame, verify_top=1, max_error=0.05)
+    sur = api.Surrogate(P, vol, frame, verify_top=4, max_error=0.05)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     out = api.build_hierarchy(Vt, Ft, surrogate=sur, **hp)

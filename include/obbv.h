@@ -145,6 +145,26 @@ int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_b
                          int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side,
                          void* stream);
 
+/* As obbv_outer_volume for one mesh, for boxes that come in groups sharing a
+ * centre and axes -- the candidate moves of the Lloyd partition (Sec. 4.2.1,
+ * Eq. 12) are such groups: every candidate is its box grown to enclose one more
+ * triangle.  frames[f] is the union of group f (its centre, axes and the
+ * largest half extents of its boxes); box_frame[b] names the group of box b.
+ * The mesh is culled once per group, so each box only walks the triangles that
+ * project into a face of its group's frame.  The result is bitwise the one of
+ * obbv_outer_volume with the same boxes and keys.  A box whose centre or axes
+ * differ (bitwise) from its frame's, or that reaches outside it, or whose
+ * box_frame is out of range, walks the whole mesh instead (same result).
+ *
+ * frames     device, [n_frames] obbv_box, 1 <= n_frames <= n_boxes
+ * box_frame  device, [n_boxes] int32
+ * other arguments as obbv_outer_volume (box_key nullable = box index).
+ * The call synchronises the stream once (scratch sizing), twice when
+ * n_frames x n_triangles exceeds 2^28. */
+int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
+                              int32_t n_boxes, const obbv_ov_params* params, const obbv_box* frames,
+                              const int32_t* box_frame, int32_t n_frames, double* out_obv, void* stream);
+
 /* ---- measurement ----------------------------------------------------------- */
 
 /* Host.  enable != 0: every later obbv_outer_volume* call records a pair of HIP
@@ -212,10 +232,12 @@ typedef struct {
   const float* volume;     /* [N][N][N] occupancy volume (obbv_occupancy_volume)  */
   const float* frame;      /* [10] frame of the volume                            */
   int32_t N;               /* volume edge (8 nb)                                  */
-  int32_t verify_top;      /* candidates per popped triangle evaluated exactly    */
-  float max_error;         /* mean |predicted - exact| outer fraction of the
-                              verified candidates above which the state returns to
-                              exact evaluation of every candidate                 */
+  int32_t verify_top;      /* candidates per receiving box and round evaluated
+                              exactly (the smallest predicted changes)            */
+  float max_error;         /* rolling mean |predicted - exact| outer fraction of
+                              the last 256 verified candidates above which the
+                              rest of the Lloyd iteration evaluates every
+                              candidate exactly                                   */
   int32_t reserved;        /* must be 0                                           */
 } obbv_surrogate;
 
@@ -249,12 +271,18 @@ int obbv_lloyd_set_groups(obbv_lloyd* st, int32_t n_boxes, const int32_t* tri_gr
  * rotation gradient, line search, kept if OBV drops). */
 int obbv_lloyd_step(obbv_lloyd* st, void* stream);
 
-/* Host.  With a non-NULL surrogate, later steps rank the candidate boxes of a
- * popped triangle that no box contains by the ranker's predicted dOBV
- * (|f * V(grown) - OBV(current)|, f = predicted outer fraction) and evaluate
- * only the verify_top best exactly; the triangle goes to the verified box with
- * the smallest exact dOBV.  NULL returns to exact evaluation of every candidate.
- * The structure is copied; its device arrays must stay valid. */
+/* Host.  With a non-NULL surrogate, later flood rounds predict the outer
+ * fraction f of every candidate box (a box grown by a popped triangle that no box
+ * of its group contains) and of the current boxes, with the predicted change
+ * dOBV = max(0, f(grown) V(grown) - f(current) V(current)) (Eq. 12).  Of the
+ * candidates a box receives in one round, only the verify_top with the smallest
+ * predicted change are evaluated exactly; every triangle then goes to the box
+ * with the smallest change, exact where evaluated and predicted elsewhere.  Box
+ * volumes after a round and the parameter update stay exact.  The exact values
+ * judge the ranker: when the rolling error exceeds max_error the rest of that
+ * iteration evaluates every candidate (counted as a fallback).  NULL returns to
+ * exact evaluation of every candidate.  The structure is copied; its device
+ * arrays must stay valid. */
 int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* surrogate);
 
 /* Host.  Results of the last step (each output nullable, host):
@@ -265,6 +293,17 @@ int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* surrogate);
  * entries, cumulative over the state's steps). */
 int obbv_lloyd_get(obbv_lloyd* st, int32_t* tri_box, float* boxes, double* obv, double* layer_error,
                    int64_t* counters);
+
+/* Host.  cap > 0: from now on the state keeps a uniform sample (reservoir of
+ * size cap, drawn with SplitMix64) of the (box, exact outer volume) pairs it
+ * evaluates -- flood candidates, grown boxes and parameter-update trials --
+ * the training pairs of the learned ranker.  cap = 0 stops recording.  Either
+ * call clears the sample. */
+int obbv_lloyd_record(obbv_lloyd* st, int64_t cap);
+
+/* Host.  Copies up to max_n recorded pairs (boxes [n][15] in obbv_box layout,
+ * obv [n] float64; host arrays) and the count to *n_out, then clears the sample. */
+int obbv_lloyd_take_records(obbv_lloyd* st, int64_t max_n, float* boxes, double* obv, int64_t* n_out);
 
 int obbv_lloyd_destroy(obbv_lloyd* st);
 

@@ -59,6 +59,9 @@ SIGNATURES = {
     "obbv_outer_volume_ex": (c_int32, [ctypes.POINTER(ObbvMesh), c_int32, c_void_p, c_void_p, c_void_p,
                                        c_int32, ctypes.POINTER(ObbvOvParams), c_void_p, c_void_p,
                                        c_void_p, c_void_p, c_void_p, c_void_p]),
+    "obbv_outer_volume_grouped": (c_int32, [ctypes.POINTER(ObbvMesh), c_void_p, c_void_p, c_int32,
+                                            ctypes.POINTER(ObbvOvParams), c_void_p, c_void_p, c_int32, c_void_p,
+                                            c_void_p]),
     "obbv_ov_plan_create": (c_int32, [ctypes.POINTER(ObbvMesh), c_int32, c_void_p, c_void_p, c_void_p, c_int32,
                                       ctypes.POINTER(ObbvOvParams), c_void_p, ctypes.c_double, c_void_p,
                                       ctypes.POINTER(c_void_p)]),
@@ -84,6 +87,9 @@ SIGNATURES = {
     "obbv_lloyd_set_surrogate": (c_int32, [c_void_p, ctypes.POINTER(ObbvSurrogate)]),
     "obbv_lloyd_get": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double_p,
                                  ctypes.POINTER(ctypes.c_int64)]),
+    "obbv_lloyd_record": (c_int32, [c_void_p, ctypes.c_int64]),
+    "obbv_lloyd_take_records": (c_int32, [c_void_p, ctypes.c_int64, c_void_p, c_void_p,
+                                          ctypes.POINTER(ctypes.c_int64)]),
     "obbv_lloyd_destroy": (c_int32, [c_void_p]),
     "obbv_build_hierarchy": (c_int32, [ctypes.POINTER(ObbvMesh), ctypes.POINTER(ObbvHierParams), c_void_p,
                                        c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -118,6 +118,26 @@ def outer_volume_ex(V, F, boxes, R, seed=0, axis_mask=7, tile=0, box_key=None, r
     return {"obv": obv, "vin_axis": vin, "ray_q": rq, "ray_hits": rh, "side": side}
 
 
+def outer_volume_grouped(V, F, boxes, R, frames, box_frame, seed=0, axis_mask=7, tile=0, box_key=None,
+                         out=None, stream=None):
+    """obbv_outer_volume_grouped: boxes in groups sharing a centre and axes;
+    frames [n_frames, 15] are the groups' unions, box_frame [n_boxes] int32."""
+    _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
+    _dev(frames, torch.float32, "frames", (BOX_FLOATS,))
+    _dev(box_frame, torch.int32, "box_frame")
+    if box_key is not None:
+        _dev(box_key, torch.int32, "box_key")
+    n = boxes.shape[0]
+    obv = out if out is not None else torch.empty(n, dtype=torch.float64, device=boxes.device)
+    _dev(obv, torch.float64, "out")
+    m = mesh_struct(V, F)
+    p = _params(R, seed, axis_mask, tile)
+    _check(_lib.lib().obbv_outer_volume_grouped(ctypes.byref(m), _ptr(boxes), _ptr(box_key), n, ctypes.byref(p),
+                                                _ptr(frames), _ptr(box_frame), frames.shape[0], _ptr(obv),
+                                                _stream(stream)))
+    return obv
+
+
 def outer_volume_raw(meshes_struct, n_meshes, boxes, box_mesh, box_key, n, params, out, stream=None):
     """Direct obbv_outer_volume call on prepared structs (used by the timing loop)."""
     _check(_lib.lib().obbv_outer_volume(meshes_struct, n_meshes, _ptr(boxes), _ptr(box_mesh), _ptr(box_key),
@@ -197,6 +217,20 @@ class Lloyd:
         self._sur = surrogate
         _check(_lib.lib().obbv_lloyd_set_surrogate(
             self._h, ctypes.byref(surrogate.struct()) if surrogate is not None else None))
+
+    def record(self, cap):
+        """Keep a uniform sample of up to cap evaluated (box, outer volume) pairs."""
+        _check(_lib.lib().obbv_lloyd_record(self._h, int(cap)))
+        self._rec_cap = int(cap)
+
+    def take_records(self):
+        """(boxes float32 [n, 15], obv float64 [n]) of the sample; clears it."""
+        cap = getattr(self, "_rec_cap", 0)
+        boxes = np.empty((max(cap, 1), BOX_FLOATS), np.float32)
+        obv = np.empty(max(cap, 1), np.float64)
+        n = ctypes.c_int64(0)
+        _check(_lib.lib().obbv_lloyd_take_records(self._h, cap, _host_ptr(boxes), _host_ptr(obv), ctypes.byref(n)))
+        return boxes[:n.value].copy(), obv[:n.value].copy()
 
     def close(self):
         if self._h:

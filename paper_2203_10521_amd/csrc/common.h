@@ -49,7 +49,8 @@ enum PoolSlot {
   kPoolFit = 3,
   kPoolMlp = 4,
   kPoolFeat = 5,
-  kPoolCount = 6
+  kPoolLists = 6,
+  kPoolCount = 7
 };
 
 // Ensures slot `slot` of the current device holds at least `bytes` and returns it.

@@ -29,6 +29,8 @@
 #include <memory>
 #include <numeric>
 #include <queue>
+#include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -40,6 +42,9 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
                       const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
                       int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s,
                       float* out_occ);
+int outer_volume_frames(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key, int32_t n_boxes,
+                        const obbv_ov_params* params, const obbv_box* frames, const int32_t* box_frame,
+                        int32_t n_frames, double* out_obv, hipStream_t s);
 int fit_impl(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters, obbv_box* out_boxes,
              double* out_eigvals, hipStream_t st);
 int mlp_forward_impl(const float* params, const float* X, int32_t n, float* out_f, hipStream_t s);
@@ -67,56 +72,124 @@ struct Evaluator {
   obbv_mesh mesh{};
   obbv_ov_params params{};
   hipStream_t stream = nullptr;
-  char* dbuf = nullptr;
+  char* dbuf = nullptr;  // device: boxes, keys, frames, box frames, results
+  char* hbuf = nullptr;  // pinned host staging of the same layout
   size_t cap = 0;
-  std::vector<obbv_box> hb;
-  std::vector<uint32_t> hk;
   int64_t evals = 0;
   int64_t calls = 0;
+  std::vector<HBox> fr;  // frames of the current call (host)
+  // optional uniform sample (reservoir) of the evaluated (box, outer volume) pairs
+  int64_t rec_cap = 0, rec_seen = 0;
+  std::vector<HBox> rec_box;
+  std::vector<double> rec_val;
+
+  void record(const std::vector<HBox>& boxes, const std::vector<double>& vals) {
+    for (size_t i = 0; i < boxes.size(); ++i) {
+      const int64_t k = rec_seen++;
+      if ((int64_t)rec_box.size() < rec_cap) {
+        rec_box.push_back(boxes[i]);
+        rec_val.push_back(vals[i]);
+      } else {
+        const uint64_t j = splitmix64_at(0x5DEECE66Dull, (uint64_t)k) % (uint64_t)(k + 1);
+        if ((int64_t)j < rec_cap) {
+          rec_box[j] = boxes[i];
+          rec_val[j] = vals[i];
+        }
+      }
+    }
+  }
 
   ~Evaluator() {
     if (dbuf) (void)hipFree(dbuf);
+    if (hbuf) (void)hipHostFree(hbuf);
   }
+
+  static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
   int eval(const std::vector<HBox>& boxes, const std::vector<uint32_t>& keys, std::vector<double>& out) {
     const size_t n = boxes.size();
     out.assign(n, 0.0);
     if (n == 0) return OBBV_OK;
-    const size_t need = n * (sizeof(obbv_box) + 8 + 8) + 1024;
+    // Candidates of one box share its centre and axes: group them into frames so
+    // that the mesh is culled once per frame (against the union of its boxes).
+    std::vector<int32_t> box_frame(n);
+    fr.clear();
+    {
+      std::unordered_map<std::string, int32_t> index;
+      std::string key(48, '\0');
+      for (size_t i = 0; i < n; ++i) {
+        std::memcpy(&key[0], boxes[i].c, 12);
+        std::memcpy(&key[12], boxes[i].Q, 36);
+        auto it = index.find(key);
+        if (it == index.end()) {
+          it = index.emplace(key, (int32_t)fr.size()).first;
+          fr.push_back(boxes[i]);
+        } else {
+          HBox& f = fr[it->second];
+          for (int r = 0; r < 3; ++r) f.h[r] = std::fmax(f.h[r], boxes[i].h[r]);
+        }
+        box_frame[i] = it->second;
+      }
+    }
+    const size_t nf = fr.size();
+    const bool shared = 2 * nf <= n;
+    const size_t o_box = 0, o_key = al(n * sizeof(obbv_box)), o_frame = o_key + al(n * 4);
+    const size_t o_bf = o_frame + al(nf * sizeof(obbv_box)), o_out = o_bf + al(n * 4);
+    const size_t need = o_out + al(n * 8);
     if (need > cap) {
       if (dbuf) {
         OBBV_HIP(hipStreamSynchronize(stream));
         OBBV_HIP(hipFree(dbuf));
-        dbuf = nullptr;
-      }
-      cap = std::max(need * 2, (size_t)1 << 16);
-      if (hipMalloc((void**)&dbuf, cap) != hipSuccess) {
-        (void)hipGetLastError();
+        OBBV_HIP(hipHostFree(hbuf));
+        dbuf = hbuf = nullptr;
         cap = 0;
+      }
+      const size_t want = std::max(need * 2, (size_t)1 << 16);
+      if (hipMalloc((void**)&dbuf, want) != hipSuccess) {
+        (void)hipGetLastError();
+        dbuf = nullptr;
         set_error("hipMalloc failed for the Lloyd evaluation buffer");
         return OBBV_ERR_OOM;
       }
+      if (hipHostMalloc((void**)&hbuf, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(dbuf);
+        dbuf = hbuf = nullptr;
+        set_error("hipHostMalloc failed for the Lloyd evaluation buffer");
+        return OBBV_ERR_OOM;
+      }
+      cap = want;
     }
-    hb.resize(n);
-    hk.assign(keys.begin(), keys.end());
-    for (size_t i = 0; i < n; ++i) {
-      std::memcpy(hb[i].center, boxes[i].c, 12);
-      std::memcpy(hb[i].axes, boxes[i].Q, 36);
-      std::memcpy(hb[i].half, boxes[i].h, 12);
+    auto put = [](obbv_box* d, const HBox& b) {
+      std::memcpy(d->center, b.c, 12);
+      std::memcpy(d->axes, b.Q, 36);
+      std::memcpy(d->half, b.h, 12);
+    };
+    obbv_box* hb = (obbv_box*)(hbuf + o_box);
+    for (size_t i = 0; i < n; ++i) put(hb + i, boxes[i]);
+    std::memcpy(hbuf + o_key, keys.data(), n * 4);
+    if (shared) {
+      obbv_box* hf = (obbv_box*)(hbuf + o_frame);
+      for (size_t f = 0; f < nf; ++f) put(hf + f, fr[f]);
+      std::memcpy(hbuf + o_bf, box_frame.data(), n * 4);
     }
-    obbv_box* db = (obbv_box*)dbuf;
-    size_t off = (n * sizeof(obbv_box) + 255) & ~(size_t)255;
-    uint32_t* dk = (uint32_t*)(dbuf + off);
-    off += (n * 4 + 255) & ~(size_t)255;
-    double* dout = (double*)(dbuf + off);
-    OBBV_HIP(hipMemcpyAsync(db, hb.data(), n * sizeof(obbv_box), hipMemcpyHostToDevice, stream));
-    OBBV_HIP(hipMemcpyAsync(dk, hk.data(), n * 4, hipMemcpyHostToDevice, stream));
-    OBBV_RET(outer_volume_impl(&mesh, 1, db, nullptr, dk, (int32_t)n, &params, dout, nullptr, nullptr, nullptr,
-                               nullptr, stream, nullptr));
-    OBBV_HIP(hipMemcpyAsync(out.data(), dout, n * 8, hipMemcpyDeviceToHost, stream));
+    const size_t up = shared ? o_out : o_frame;
+    OBBV_HIP(hipMemcpyAsync(dbuf, hbuf, up, hipMemcpyHostToDevice, stream));
+    double* dout = (double*)(dbuf + o_out);
+    if (shared)
+      OBBV_RET(outer_volume_frames(&mesh, (const obbv_box*)(dbuf + o_box), (const uint32_t*)(dbuf + o_key),
+                                   (int32_t)n, &params, (const obbv_box*)(dbuf + o_frame),
+                                   (const int32_t*)(dbuf + o_bf), (int32_t)nf, dout, stream));
+    else
+      OBBV_RET(outer_volume_impl(&mesh, 1, (const obbv_box*)(dbuf + o_box), nullptr,
+                                 (const uint32_t*)(dbuf + o_key), (int32_t)n, &params, dout, nullptr, nullptr,
+                                 nullptr, nullptr, stream, nullptr));
+    OBBV_HIP(hipMemcpyAsync(hbuf + o_out, dout, n * 8, hipMemcpyDeviceToHost, stream));
     OBBV_HIP(hipStreamSynchronize(stream));
+    std::memcpy(out.data(), hbuf + o_out, n * 8);
     evals += (int64_t)n;
     ++calls;
+    if (rec_cap > 0) record(boxes, out);
     return OBBV_OK;
   }
 };
@@ -132,8 +205,34 @@ struct Predictor {
   size_t cap = 0;
   std::vector<obbv_box> hb;
   std::vector<float> hf;
+  bool paused = false;  // the judge found the ranker off: exact evaluation until the next iteration
   double err_sum = 0.0;
   int64_t err_n = 0, predicted = 0, fallbacks = 0;
+  static constexpr int kWindow = 256;
+
+  // Rolling mean |predicted - exact| outer fraction over the last kWindow verified
+  // candidates; above cfg.max_error (once 64 are in) the ranker pauses.
+  std::vector<double> window;
+  size_t wpos = 0;
+  void judge(double err) {
+    if ((int)window.size() < kWindow) {
+      window.push_back(err);
+    } else {
+      err_sum -= window[wpos];
+      window[wpos] = err;
+      wpos = (wpos + 1) % kWindow;
+    }
+    err_sum += err;
+    err_n = (int64_t)window.size();
+    if (err_n >= 64 && err_sum / (double)err_n > (double)cfg.max_error) {
+      paused = true;
+      ++fallbacks;
+      window.clear();
+      wpos = 0;
+      err_sum = 0.0;
+      err_n = 0;
+    }
+  }
 
   ~Predictor() {
     if (dbuf) (void)hipFree(dbuf);
@@ -384,6 +483,25 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     for (int e : groups[g].elems)
       if (eb[e] >= 0) push_neighbours(e);
 
+  // Boxes that grew at the end of a round to a size none of their evaluated
+  // candidates had: their outer volume is evaluated with the next round's
+  // candidates (one device call per round; the values are the same).
+  std::vector<int32_t> stale;
+  auto flush_stale = [&]() -> int {
+    if (stale.empty()) return OBBV_OK;
+    req_boxes.clear();
+    req_keys.clear();
+    for (int bi : stale) {
+      req_boxes.push_back(boxes[bi]);
+      req_keys.push_back(slot[bi]);
+    }
+    OBBV_RET(ev.eval(req_boxes, req_keys, vals));
+    cnt.evals += (int64_t)vals.size();
+    for (size_t x = 0; x < stale.size(); ++x) obv[stale[x]] = vals[x];
+    stale.clear();
+    return OBBV_OK;
+  };
+
   // one decision round over the given pops of every group
   struct Cand {
     int e, g, li;  // element, group, local box index
@@ -393,9 +511,9 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
   };
   auto round = [&](const std::vector<std::vector<int32_t>>& pops) -> int {
     std::vector<Cand> cands;
-    req_boxes.clear();
-    req_keys.clear();
-    std::vector<int32_t> req_idx;
+    std::vector<HBox> cb;       // candidate boxes to evaluate
+    std::vector<uint32_t> ck;   // their jitter keys
+    std::vector<int32_t> cidx;  // their candidate indices
     // a box that already contains the element has dOBV = 0, the minimum: then the
     // element's other candidates need no evaluation
     for (int g = 0; g < G; ++g) {
@@ -425,69 +543,90 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         for (int i = 0; i < b; ++i) {
           HBox gb = boxes[gr.boxes[i]];
           std::memcpy(gb.h, cands[first + i].h, 12);
-          req_boxes.push_back(gb);
-          req_keys.push_back(slot[gr.boxes[i]]);
-          req_idx.push_back((int32_t)(first + i));
+          cb.push_back(gb);
+          ck.push_back(slot[gr.boxes[i]]);
+          cidx.push_back((int32_t)(first + i));
         }
       }
     }
-    // learned ranking: keep the verify_top candidates of each element with the
-    // smallest predicted dOBV for exact evaluation
-    std::vector<float> fpred;
-    std::vector<int32_t> kept_pred;  // candidate -> index into fpred (for the error check)
-    if (pred && pred->on && !req_idx.empty()) {
-      OBBV_RET(pred->predict(req_boxes, fpred));
+    // Learned ranking.  The ranker predicts the outer fraction of every candidate
+    // and of the current boxes; the predicted change of a move is
+    // f(grown) V(grown) - f(current) V(current) (the two predictions share most of
+    // their error).  For every receiving box only the verify_top candidates with
+    // the smallest predicted change are evaluated exactly; the other candidates
+    // are decided on the prediction.
+    std::vector<double> dpred(cands.size(), 0.0);
+    std::vector<char> predicted_c(cands.size(), 0);
+    std::vector<float> fcand;  // prediction of each kept candidate (judge)
+    if (pred && pred->on && !pred->paused && !cidx.empty()) {
+      std::vector<HBox> pb = cb;
+      std::vector<int32_t> cur_of((size_t)boxes.size(), -1);
+      for (int32_t x : cidx) {
+        const int bi = groups[cands[x].g].boxes[cands[x].li];
+        if (cur_of[bi] < 0) {
+          cur_of[bi] = (int32_t)pb.size();
+          pb.push_back(boxes[bi]);
+        }
+      }
+      std::vector<float> fp;
+      OBBV_RET(pred->predict(pb, fp));
+      std::vector<std::vector<std::pair<double, size_t>>> per_box((size_t)boxes.size());
+      for (size_t z = 0; z < cidx.size(); ++z) {
+        const Cand& c = cands[cidx[z]];
+        const int bi = groups[c.g].boxes[c.li];
+        const HBox& cu = boxes[bi];
+        const double vg = 8.0 * (double)c.h[0] * (double)c.h[1] * (double)c.h[2];
+        const double vc = 8.0 * (double)cu.h[0] * (double)cu.h[1] * (double)cu.h[2];
+        const double d = (double)fp[z] * vg - (double)fp[cur_of[bi]] * vc;
+        dpred[cidx[z]] = std::max(d, 0.0);
+        predicted_c[cidx[z]] = 1;
+        per_box[bi].push_back({dpred[cidx[z]], z});
+      }
+      std::vector<char> keep(cidx.size(), 0);
+      const size_t top = (size_t)std::max(1, pred->cfg.verify_top);
+      for (auto& v : per_box) {
+        if (v.empty()) continue;
+        std::sort(v.begin(), v.end());
+        for (size_t q = 0; q < std::min(top, v.size()); ++q) keep[v[q].second] = 1;
+      }
       std::vector<HBox> rb;
       std::vector<uint32_t> rk;
       std::vector<int32_t> ri;
-      kept_pred.clear();
-      size_t x = 0;
-      while (x < req_idx.size()) {
-        size_t y = x;
-        while (y < req_idx.size() && cands[req_idx[y]].e == cands[req_idx[x]].e &&
-               cands[req_idx[y]].g == cands[req_idx[x]].g)
-          ++y;
-        std::vector<std::pair<double, size_t>> score;
-        for (size_t z = x; z < y; ++z) {
-          const Cand& c = cands[req_idx[z]];
-          const int bi = groups[c.g].boxes[c.li];
-          const double vb = 8.0 * (double)c.h[0] * (double)c.h[1] * (double)c.h[2];
-          score.push_back({std::fabs((double)fpred[z] * vb - obv[bi]), z});
+      for (size_t z = 0; z < cidx.size(); ++z)
+        if (keep[z]) {
+          rb.push_back(cb[z]);
+          rk.push_back(ck[z]);
+          ri.push_back(cidx[z]);
+          fcand.push_back(fp[z]);
         }
-        std::sort(score.begin(), score.end());
-        const size_t keep = std::min<size_t>(score.size(), (size_t)std::max(1, pred->cfg.verify_top));
-        std::vector<size_t> sel;
-        for (size_t q = 0; q < keep; ++q) sel.push_back(score[q].second);
-        std::sort(sel.begin(), sel.end());
-        for (size_t z : sel) {
-          rb.push_back(req_boxes[z]);
-          rk.push_back(req_keys[z]);
-          ri.push_back(req_idx[z]);
-          kept_pred.push_back((int32_t)z);
-        }
-        x = y;
-      }
-      req_boxes.swap(rb);
-      req_keys.swap(rk);
-      req_idx.swap(ri);
+      cb.swap(rb);
+      ck.swap(rk);
+      cidx.swap(ri);
     }
-    std::vector<char> evaluated(cands.size(), 0);
-    for (int32_t x : req_idx) evaluated[x] = 1;
+    // one device call: the stale boxes of the last round, then the candidates
+    const size_t ns = stale.size();
+    req_boxes.clear();
+    req_keys.clear();
+    for (int bi : stale) {
+      req_boxes.push_back(boxes[bi]);
+      req_keys.push_back(slot[bi]);
+    }
+    req_boxes.insert(req_boxes.end(), cb.begin(), cb.end());
+    req_keys.insert(req_keys.end(), ck.begin(), ck.end());
     OBBV_RET(ev.eval(req_boxes, req_keys, vals));
     cnt.evals += (int64_t)vals.size();
-    for (size_t x = 0; x < vals.size(); ++x) cands[req_idx[x]].val = vals[x];
-    if (!kept_pred.empty()) {  // the exact kernel judges the ranker
-      for (size_t x = 0; x < vals.size(); ++x) {
-        const HBox& bx = req_boxes[x];
+    for (size_t x = 0; x < ns; ++x) obv[stale[x]] = vals[x];
+    stale.clear();
+    std::vector<char> evaluated(cands.size(), 0);
+    for (size_t x = 0; x < cidx.size(); ++x) {
+      cands[cidx[x]].val = vals[ns + x];
+      evaluated[cidx[x]] = 1;
+    }
+    if (!fcand.empty()) {  // the exact kernel judges the ranker
+      for (size_t x = 0; x < cidx.size(); ++x) {
+        const HBox& bx = req_boxes[ns + x];
         const double vb = 8.0 * (double)bx.h[0] * (double)bx.h[1] * (double)bx.h[2];
-        if (vb > 0.0) {
-          pred->err_sum += std::fabs((double)fpred[kept_pred[x]] - vals[x] / vb);
-          ++pred->err_n;
-        }
-      }
-      if (pred->err_n >= 64 && pred->err_sum / (double)pred->err_n > (double)pred->cfg.max_error) {
-        pred->on = false;
-        ++pred->fallbacks;
+        if (vb > 0.0) pred->judge(std::fabs((double)fcand[x] - vals[ns + x] / vb));
       }
     }
     // decisions
@@ -503,8 +642,15 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         for (int i = 0; i < b; ++i) {
           const Cand& c = cands[ci + i];
           const int bi = gr.boxes[i];
-          if (!c.trivial && !evaluated[ci + i]) continue;  // another box contains the element
-          const double d = c.trivial ? 0.0 : std::fabs(c.val - obv[bi]);
+          double d;
+          if (c.trivial)
+            d = 0.0;
+          else if (evaluated[ci + i])
+            d = std::fabs(c.val - obv[bi]);
+          else if (predicted_c[ci + i])
+            d = dpred[ci + i];
+          else
+            continue;  // another box contains the element
           const double dd = dist3(&E.cen[3 * e], boxes[bi].c);
           if (best < 0 || d < bd || (d == bd && (dd < bdist || (dd == bdist && i < best)))) {
             best = i;
@@ -521,9 +667,6 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       }
     }
     // grow the receiving boxes to the union
-    req_boxes.clear();
-    req_keys.clear();
-    std::vector<int32_t> extra;
     for (int bi : touched) {
       float hn[3];
       std::memcpy(hn, cands[got[bi][0]].h, 12);
@@ -538,16 +681,7 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
           found = true;
           break;
         }
-      if (!found) {
-        extra.push_back(bi);
-        req_boxes.push_back(boxes[bi]);
-        req_keys.push_back(slot[bi]);
-      }
-    }
-    if (!extra.empty()) {
-      OBBV_RET(ev.eval(req_boxes, req_keys, vals));
-      cnt.evals += (int64_t)vals.size();
-      for (size_t x = 0; x < extra.size(); ++x) obv[extra[x]] = vals[x];
+      if (!found) stale.push_back(bi);
     }
     return OBBV_OK;
   };
@@ -587,7 +721,7 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     ++cnt.rounds;
     OBBV_RET(round(pops));
   }
-  return OBBV_OK;
+  return flush_stale();
 }
 
 // ---------------------------------------------------------------------------
@@ -761,6 +895,7 @@ struct LloydState {
 
 // One Lloyd iteration (partition + parameter update) of every group.
 static int lloyd_iterate(LloydState& S) {
+  S.pred.paused = false;  // a judge fallback lasts for one iteration
   std::vector<int32_t> eb;
   PartitionIO io{&S.boxes, &S.obv, &S.slot, &eb};
   // groups with a single box: every element goes to it, the update fits the tight box
@@ -878,6 +1013,9 @@ extern "C" int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* su
   OBBV_ARG(sur->N >= 1 && sur->verify_top >= 1 && sur->reserved == 0, "bad surrogate sizes");
   S.pred.cfg = *sur;
   S.pred.on = true;
+  S.pred.paused = false;
+  S.pred.window.clear();
+  S.pred.wpos = 0;
   S.pred.err_sum = 0.0;
   S.pred.err_n = 0;
   return OBBV_OK;
@@ -907,6 +1045,37 @@ extern "C" int obbv_lloyd_get(obbv_lloyd* st, int32_t* tri_box, float* boxes, do
     counters[4] = S.pred.predicted;
     counters[5] = S.pred.fallbacks;
   }
+  return OBBV_OK;
+}
+
+extern "C" int obbv_lloyd_record(obbv_lloyd* st, int64_t cap) {
+  clear_error();
+  OBBV_ARG(st, "NULL state");
+  OBBV_ARG(cap >= 0, "cap must be >= 0");
+  LloydState& S = *reinterpret_cast<LloydState*>(st);
+  S.ev.rec_cap = cap;
+  S.ev.rec_seen = 0;
+  S.ev.rec_box.clear();
+  S.ev.rec_val.clear();
+  return OBBV_OK;
+}
+
+extern "C" int obbv_lloyd_take_records(obbv_lloyd* st, int64_t max_n, float* boxes, double* obv, int64_t* n_out) {
+  clear_error();
+  OBBV_ARG(st && n_out, "NULL argument");
+  LloydState& S = *reinterpret_cast<LloydState*>(st);
+  const int64_t n = std::min<int64_t>(max_n, (int64_t)S.ev.rec_box.size());
+  OBBV_ARG(n == 0 || (boxes && obv), "NULL output arrays");
+  for (int64_t i = 0; i < n; ++i) {
+    std::memcpy(boxes + 15 * i, S.ev.rec_box[i].c, 12);
+    std::memcpy(boxes + 15 * i + 3, S.ev.rec_box[i].Q, 36);
+    std::memcpy(boxes + 15 * i + 12, S.ev.rec_box[i].h, 12);
+    obv[i] = S.ev.rec_val[i];
+  }
+  *n_out = n;
+  S.ev.rec_seen = 0;
+  S.ev.rec_box.clear();
+  S.ev.rec_val.clear();
   return OBBV_OK;
 }
 
@@ -1051,6 +1220,7 @@ int merge_level(LloydState& S, Tree& T, int l) {
   std::vector<Group> fg;
   for (const Group& g : S.groups)
     if (g.boxes.size() > 1) fg.push_back(g);
+  S.pred.paused = false;
   OBBV_RET(flood_partition(S.M, S.E, fg, io, S.K, S.ev, S.cnt, &S.pred));
   for (const Group& g : S.groups)
     if (g.boxes.size() == 1)

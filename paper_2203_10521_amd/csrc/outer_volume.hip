@@ -45,6 +45,10 @@ __device__ inline BoxRegs load_box(const obbv_box* __restrict__ boxes, int b) {
   return r;
 }
 
+// element k of a 3-vector held in registers (selects, so the vector never
+// needs addressable private memory)
+__device__ inline float pick3(const float v[3], int k) { return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]); }
+
 // 0 = computable box, 1 = zero extent (OBV 0, nothing to cast), 2 = invalid (NaN / negative)
 __device__ inline int box_state(const BoxRegs& B) {
   bool finite = true;
@@ -79,9 +83,9 @@ __device__ inline CastFrame cast_frame(const BoxRegs& B, int w, int R) {
   CastFrame f;
   f.ua = (w + 1) % 3;
   f.va = (w + 2) % 3;
-  f.hu = B.h[f.ua];
-  f.hv = B.h[f.va];
-  f.hw = B.h[w];
+  f.hu = pick3(B.h, f.ua);
+  f.hv = pick3(B.h, f.va);
+  f.hw = pick3(B.h, w);
   f.du = __ddiv_rn(__dmul_rn(2.0, (double)f.hu), (double)R);
   f.dv = __ddiv_rn(__dmul_rn(2.0, (double)f.hv), (double)R);
   f.eu = 1e-6f * f.hu;
@@ -187,23 +191,109 @@ struct CullArgs {
   uint32_t* status;
   int64_t rec_cap;  // record / bin capacity of the scratch (planned launches)
   int64_t bin_cap;
+  // nullable: the triangles a box can see, as one list per shared frame
+  const int32_t* tri_list;
+  const int64_t* list_off;  // [n_frames + 1]
+  const int32_t* box_list;  // [n_boxes] frame of every box, -1 = the whole mesh
 };
+
+// Number of triangles box b walks, and its t-th triangle.
+__device__ inline int box_ntri(const CullArgs& a, int b, const MeshDev& M) {
+  const int l = a.tri_list ? a.box_list[b] : -1;
+  return l < 0 ? M.nt : (int)(a.list_off[l + 1] - a.list_off[l]);
+}
+__device__ inline int box_tri(const CullArgs& a, int b, int t) {
+  const int l = a.tri_list ? a.box_list[b] : -1;
+  return l < 0 ? t : a.tri_list[a.list_off[l] + t];
+}
 
 __global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+// A box may use its frame's triangle list only if it has the frame's centre and
+// axes (same bits) and lies inside the frame box; otherwise it walks the whole
+// mesh (slower, same result).
+__device__ inline bool inside_frame(const obbv_box& bx, const obbv_box& fr) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(&bx);
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(&fr);
+  bool same = true;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) same = same && p[k] == q[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) same = same && bx.half[k] <= fr.half[k];  // false on NaN
+  return same;
+}
+
 __global__ void k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ meshes,
-                             int n_meshes, int n_boxes, int32_t* __restrict__ nch, uint32_t* status) {
+                             int n_meshes, int n_boxes, const obbv_box* __restrict__ boxes,
+                             const obbv_box* __restrict__ frames, const int32_t* __restrict__ box_frame,
+                             int n_frames, const int64_t* __restrict__ list_off, int32_t* __restrict__ box_list,
+                             int32_t* __restrict__ nch, uint32_t* status) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_boxes) return;
   const int m = box_mesh ? box_mesh[b] : 0;
   if (m < 0 || m >= n_meshes) {  // out-of-range mesh index: the box sees no triangles
     atomicOr(status, OBBV_STATUS_BAD_INDEX);
     nch[b] = 0;
+    if (box_list) box_list[b] = -1;
     return;
   }
-  nch[b] = (meshes[m].nt + kCullThreads - 1) / kCullThreads;
+  int64_t n = meshes[m].nt;
+  if (box_list) {
+    const int f = box_frame[b];
+    const bool use = f >= 0 && f < n_frames && inside_frame(boxes[b], frames[f]);
+    box_list[b] = use ? f : -1;
+    if (use) n = list_off[f + 1] - list_off[f];
+  }
+  nch[b] = (int32_t)((n + kCullThreads - 1) / kCullThreads);
+}
+
+// Shared frames: boxes with the same centre and axes see every triangle at the
+// same local coordinates, and a triangle can matter to one of them only if it
+// projects into a face of their union (the frame box, with the largest half
+// extents).  One pass per (frame, triangle) lists those triangles; with
+// `list_off` NULL it only counts them.  The list order is irrelevant: every
+// later sum is an exact integer.
+__global__ void __launch_bounds__(kCullThreads)
+k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, uint32_t axis_mask, int nch,
+             int32_t* __restrict__ cnt, const int64_t* __restrict__ list_off, int32_t* __restrict__ cur,
+             int32_t* __restrict__ list, uint32_t* status) {
+  const int64_t total = (int64_t)n_frames * nch;
+  const int lane = threadIdx.x & 63;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int fr = (int)(item / nch);
+    const int t = (int)(item - (int64_t)fr * nch) * kCullThreads + threadIdx.x;
+    const BoxRegs B = load_box(frames, fr);
+    if (box_state(B) != 0) continue;
+    float P[3][3];
+    bool keep = false;
+    if (t < M.nt && load_tri_local(M, t, B, P, status)) {
+#pragma unroll
+      for (int w = 0; w < 3; ++w) {
+        if (!((axis_mask >> w) & 1u)) continue;
+        const CastFrame f = cast_frame(B, w, 1);
+        keep = keep || projects_into_face(cast_tri(P, w, f, false), f);
+      }
+    }
+    const uint64_t m = __ballot(keep);
+    if (m == 0) continue;
+    const int leader = __ffsll((long long)m) - 1;
+    if (!list_off) {
+      if (lane == leader) atomicAdd(&cnt[fr], (int)__popcll(m));
+      continue;
+    }
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cur[fr], (int)__popcll(m));
+    base = __shfl(base, leader);
+    if (keep) {
+      const int pos = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+      if (pos < cnt[fr])
+        list[list_off[fr] + pos] = t;
+      else  // count and write passes disagree: never expected
+        atomicOr(status, OBBV_STATUS_BAD_INDEX);
+    }
+  }
 }
 
 // Which prism(s) the triangle belongs to, per cast axis.
@@ -220,7 +310,7 @@ k_cull_count(CullArgs a, int32_t* __restrict__ side_cnt) {
     const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    const bool ok = t < M.nt && load_tri_local(M, t, B, P, a.status);
+    const bool ok = t < box_ntri(a, b, M) && load_tri_local(M, box_tri(a, b, t), B, P, a.status);
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       if (!((a.axis_mask >> w) & 1u)) continue;
@@ -294,7 +384,7 @@ k_tile_count(CullArgs a, const int32_t* __restrict__ side, int32_t* __restrict__
     const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    if (t < M.nt && load_tri_local(M, t, B, P, a.status)) {
+    if (t < box_ntri(a, b, M) && load_tri_local(M, box_tri(a, b, t), B, P, a.status)) {
       for (int w = 0; w < 3; ++w) {
         if (!((a.axis_mask >> w) & 1u)) continue;
         const int bw = b * 3 + w;
@@ -395,7 +485,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
     const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    const bool ok = t < M.nt && load_tri_local(M, t, B, P, a.status);
+    const bool ok = t < box_ntri(a, b, M) && load_tri_local(M, box_tri(a, b, t), B, P, a.status);
     if (lds) {
       // pass 1: count this item's entries per tile
       for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) cnt[k] = 0;
@@ -536,7 +626,7 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
   const BoxRegs B = load_box(a.boxes, b);
   if (box_state(B) != 0) return;
   const int ua = (w + 1) % 3, va = (w + 2) % 3;
-  const double hu = B.h[ua], hv = B.h[va];
+  const double hu = pick3(B.h, ua), hv = pick3(B.h, va);
   const double du = __ddiv_rn(__dmul_rn(2.0, hu), (double)a.R);
   const double dv = __ddiv_rn(__dmul_rn(2.0, hv), (double)a.R);
   const uint32_t key = a.box_key ? a.box_key[b] : (uint32_t)b;
@@ -675,18 +765,19 @@ __global__ void k_finalize(const obbv_box* __restrict__ boxes, int n_boxes, int 
   }
   const double vbox = 8.0 * (double)B.h[0] * (double)B.h[1] * (double)B.h[2];
   const double denom = kQOne * (double)R * (double)R;
-  double sum = 0.0;
+  long long qsum = 0;  // exact: the mean over the cast axes is taken on the integers
   int n = 0;
   for (int w = 0; w < 3; ++w) {
     double vin = 0.0;
     if ((axis_mask >> w) & 1u) {
-      vin = st == 0 ? vbox * ((double)(long long)acc[3 * b + w] / denom) : 0.0;
-      sum += vin;
+      const long long q = st == 0 ? (long long)acc[3 * b + w] : 0ll;
+      vin = vbox * ((double)q / denom);
+      qsum += q;
       ++n;
     }
     if (out_vin_axis) out_vin_axis[3 * b + w] = vin;
   }
-  out_obv[b] = vbox - (n ? sum / n : 0.0);
+  out_obv[b] = vbox - (n ? vbox * ((double)qsum / (denom * n)) : 0.0);
 }
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -753,11 +844,18 @@ bool test_stage_choice() {
 
 }  // namespace
 
+// Boxes grouped by shared centre and axes (device arrays; one mesh only).
+struct SharedFrames {
+  const obbv_box* frames;    // [n_frames] centre, axes and the largest half extents of the group
+  const int32_t* box_frame;  // [n_boxes] group of every box
+  int32_t n_frames;
+};
+
 int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                      const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
                      const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
                      int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s,
-                     float* out_occ, OvExec* ex) {
+                     float* out_occ, OvExec* ex, const SharedFrames* sf = nullptr) {
   OBBV_ARG(params != nullptr, "params is NULL");
   OBBV_ARG(n_boxes >= 0, "n_boxes < 0");
   if (n_boxes == 0) return OBBV_OK;
@@ -783,6 +881,9 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   const int TE = out_occ ? 8 : (params->tile ? params->tile : (R >= 48 ? 16 : 8));
   const bool planned = ex && ex->planned;
   OBBV_ARG(!out_occ || (R == 8 && mask == 4u), "occupancy needs R = 8 and axis_mask = 4");
+  OBBV_ARG(!sf || (n_meshes == 1 && !planned && sf->n_frames >= 1 && sf->n_frames <= n_boxes),
+           "shared frames need one mesh, an unplanned call and 1..n_boxes frames");
+  const int n_frames = sf ? sf->n_frames : 0;
   const int tpe = ceil_div(R, TE);
   const int64_t TT = (int64_t)tpe * tpe;
   const int64_t nbw = (int64_t)n_boxes * 3;
@@ -800,6 +901,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   };
   const size_t o_mesh = take(sizeof(MeshDev) * n_meshes);
   const size_t o_nch = take(4 * (size_t)n_boxes);
+  const size_t o_blist = take(4 * (size_t)(sf ? n_boxes : 0));
   const size_t o_choff = take(8 * (size_t)(n_boxes + 1));
   const size_t o_side = take(4 * (size_t)nbw);
   const size_t o_reccnt = take(4 * (size_t)nbw);
@@ -813,7 +915,10 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   const size_t o_tilecnt = take(4 * (size_t)(nbw * TT));
   const size_t o_bincur = take(4 * (size_t)(nbw * TT));
   const size_t o_acc = take(8 * (size_t)nbw);
+  const size_t o_fcnt = take(4 * (size_t)n_frames);
+  const size_t o_fcur = take(4 * (size_t)n_frames);
   const size_t o_zero1 = off;
+  const size_t o_foff = take(8 * (size_t)(n_frames + 1));
   const size_t scan_bytes =
       std::max(exclusive_scan_scratch_bytes(nbw * TT), exclusive_scan_scratch_bytes(std::max<int64_t>(nbw, n_boxes)));
   const size_t o_scan = take(scan_bytes);
@@ -843,14 +948,43 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   int32_t* d_tilecnt = (int32_t*)(meta + o_tilecnt);
   int32_t* d_bincur = (int32_t*)(meta + o_bincur);
   unsigned long long* d_acc = (unsigned long long*)(meta + o_acc);
+  int32_t* d_blist = sf ? (int32_t*)(meta + o_blist) : nullptr;
+  int32_t* d_fcnt = (int32_t*)(meta + o_fcnt);
+  int32_t* d_fcur = (int32_t*)(meta + o_fcur);
+  int64_t* d_foff = (int64_t*)(meta + o_foff);
   void* d_scan = meta + o_scan;
 
   if (!planned) OBBV_HIP(hipMemcpyAsync(d_mesh, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_fill_zero, dim3(256), dim3(256), 0, s, (uint32_t*)(meta + o_zero0),
                      (int64_t)((o_zero1 - o_zero0) / 4));
 
+  int32_t* d_list = nullptr;
+  if (sf) {  // candidate triangles of every shared frame
+    const int nt = meshes[0].n_triangles;
+    const int nch = ceil_div(std::max(nt, 1), kCullThreads);
+    const unsigned fgrid = (unsigned)std::min<int64_t>((int64_t)n_frames * nch, 256 * 16);
+    hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], mask,
+                       nch, d_fcnt, (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr, status);
+    OBBV_HIP(hipGetLastError());
+    OBBV_RET(exclusive_scan_i32_to_i64(d_fcnt, d_foff, n_frames, d_scan, scan_bytes, s));
+    int64_t bound = (int64_t)n_frames * nt;
+    if (bound * 4 > ((int64_t)1 << 30)) {  // large: size the lists exactly (one host round trip)
+      int64_t* pin = nullptr;
+      OBBV_RET(pinned_totals(&pin));
+      OBBV_HIP(hipMemcpyAsync(pin + 3, d_foff + n_frames, 8, hipMemcpyDeviceToHost, s));
+      OBBV_HIP(hipStreamSynchronize(s));
+      bound = pin[3];
+    }
+    void* lv = nullptr;
+    OBBV_RET(pool_get(kPoolLists, (size_t)std::max<int64_t>(bound, 1) * 4, &lv));
+    d_list = (int32_t*)lv;
+    hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], mask,
+                       nch, d_fcnt, (const int64_t*)d_foff, d_fcur, d_list, status);
+    OBBV_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_box_chunks, dim3(ceil_div(n_boxes, 256)), dim3(256), 0, s, box_mesh, d_mesh,
-                     n_meshes, n_boxes, d_nch, status);
+                     n_meshes, n_boxes, boxes, sf ? sf->frames : nullptr, sf ? sf->box_frame : nullptr, n_frames,
+                     (const int64_t*)d_foff, d_blist, d_nch, status);
   OBBV_HIP(hipGetLastError());
   OBBV_RET(exclusive_scan_i32_to_i64(d_nch, d_choff, n_boxes, d_scan, scan_bytes, s));
 
@@ -867,6 +1001,9 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   ca.status = status;
   ca.rec_cap = planned ? ex->rec_cap : INT64_MAX;
   ca.bin_cap = planned ? ex->bin_cap : INT64_MAX;
+  ca.tri_list = d_list;
+  ca.list_off = sf ? d_foff : nullptr;
+  ca.box_list = d_blist;
   const int64_t items_bound = (int64_t)n_boxes * ceil_div(std::max(max_nt, 1), kCullThreads);
   const unsigned cull_grid = (unsigned)std::min<int64_t>(items_bound, 256 * 16);
 
@@ -978,6 +1115,14 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   return OBBV_OK;
 }
 
+int outer_volume_frames(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key, int32_t n_boxes,
+                        const obbv_ov_params* params, const obbv_box* frames, const int32_t* box_frame,
+                        int32_t n_frames, double* out_obv, hipStream_t s) {
+  const SharedFrames sf{frames, box_frame, n_frames};
+  return outer_volume_run(mesh, 1, boxes, nullptr, box_key, n_boxes, params, out_obv, nullptr, nullptr, nullptr,
+                          nullptr, s, nullptr, nullptr, &sf);
+}
+
 int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                       const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
                       const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
@@ -988,6 +1133,18 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
 }
 
 }  // namespace obbv
+
+extern "C" int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
+                                         int32_t n_boxes, const obbv_ov_params* params, const obbv_box* frames,
+                                         const int32_t* box_frame, int32_t n_frames, double* out_obv,
+                                         void* stream) {
+  obbv::clear_error();
+  OBBV_ARG(mesh && params, "NULL argument");
+  if (n_boxes == 0) return OBBV_OK;
+  OBBV_ARG(frames && box_frame && n_frames >= 1 && n_frames <= n_boxes, "need 1..n_boxes frames");
+  return obbv::outer_volume_frames(mesh, boxes, box_key, n_boxes, params, frames, box_frame, n_frames, out_obv,
+                                   (hipStream_t)stream);
+}
 
 extern "C" int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                                     const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,

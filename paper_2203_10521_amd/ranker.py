@@ -71,6 +71,52 @@ def train(X, t, steps=2000, batch=4096, lr=1e-3, seed=0, log_every=0):
     return P, losses
 
 
+def _kmeans_groups(V, F, k, seed, iters=8):
+    """Triangle groups by k-means of the centroids (host, numpy)."""
+    cen = V.astype(np.float64)[F].mean(axis=1)
+    g = np.random.default_rng(seed)
+    C = cen[g.choice(len(cen), size=k, replace=False)]
+    for _ in range(iters):
+        lab = np.argmin(((cen[:, None, :] - C[None, :, :]) ** 2).sum(-1), axis=1)
+        for j in range(k):
+            sel = lab == j
+            if sel.any():
+                C[j] = cen[sel].mean(axis=0)
+    return np.argmin(((cen[:, None, :] - C[None, :, :]) ** 2).sum(-1), axis=1).astype(np.int32)
+
+
+def lloyd_boxes(V, F, R=64, seed=0, n_groups=16, per_group=4, iters=2, cap=8192, pops_per_round=32):
+    """Boxes the flood meets in use: a uniform sample of the (box, exact outer
+    volume) pairs evaluated by `iters` exact Lloyd iterations of `n_groups`
+    k-means triangle groups with `per_group` boxes each (seeded at random
+    triangles, axes of the group's covariance box).  V, F are host arrays;
+    returns float32 [n, 15] boxes (host)."""
+    Vt, Ft = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+    grp = _kmeans_groups(V, F, n_groups, seed) if n_groups > 1 else np.zeros(F.shape[0], np.int32)
+    fitted, _ = api.fit(Vt, Ft, torch.from_numpy(grp).cuda(), n_groups)
+    fitted = fitted.cpu().numpy()
+    g = np.random.default_rng(seed + 1)
+    cen = V.astype(np.float64)[F].mean(axis=1)
+    boxes, box_group = [], []
+    for j in range(n_groups):
+        tris = np.nonzero(grp == j)[0]
+        if len(tris) < per_group:
+            continue
+        for t in g.choice(tris, size=per_group, replace=False):
+            b = fitted[j].copy()
+            b[:3] = cen[t]
+            b[12:] = 0.0
+            boxes.append(b)
+            box_group.append(j)
+    with api.Lloyd(Vt, Ft, R=R, seed=seed, pops_per_round=pops_per_round) as L:
+        L.set_groups(grp, np.array(box_group, np.int32), np.array(boxes, np.float32))
+        L.record(cap)
+        for _ in range(iters):
+            L.step()
+        B, _ = L.take_records()
+    return B
+
+
 def predict(P, X):
     """Predicted outer fractions of the rows of X (padded to a multiple of 32)."""
     n = X.shape[0]

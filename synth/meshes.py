@@ -189,23 +189,42 @@ def _orient_by_volume(V, F):
     return F
 
 
+def _legendre_normalised(x, lmax):
+    """Orthonormal associated Legendre functions with the Condon-Shortley phase:
+    P[l][m] = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) P_l^m(x), by the standard
+    three-term recurrences in l (stable for all degrees used here)."""
+    s = np.sqrt(np.maximum(1.0 - x * x, 0.0))
+    P = [[None] * (lmax + 1) for _ in range(lmax + 1)]
+    P[0][0] = np.full_like(x, np.sqrt(1.0 / (4.0 * np.pi)))
+    for m in range(1, lmax + 1):
+        P[m][m] = -np.sqrt((2.0 * m + 1.0) / (2.0 * m)) * s * P[m - 1][m - 1]
+    for m in range(0, lmax):
+        P[m + 1][m] = np.sqrt(2.0 * m + 3.0) * x * P[m][m]
+    for m in range(0, lmax + 1):
+        for l in range(m + 2, lmax + 1):
+            a = np.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+            b = np.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+            P[l][m] = a * (x * P[l - 1][m] - b * P[l - 2][m])
+    return P
+
+
 def _real_sph_harm_field(dirs, lmax, rng, decay_plus=1.0):
-    """Seeded real spherical-harmonic field g(d) = sum_{l=1..lmax} sum_m c_lm Y_lm(d)."""
-    from scipy.special import sph_harm_y
+    """Seeded real spherical-harmonic field g(d) = sum_{l=1..lmax} sum_m c_lm Y_lm(d),
+    with Y_l0 = Y_l^0, Y_lm = sqrt(2) Re Y_l^m and Y_l,-m = sqrt(2) Im Y_l^m (m > 0),
+    Y_l^m the complex orthonormal harmonics with the Condon-Shortley phase."""
     x, y, z = dirs[:, 0], dirs[:, 1], dirs[:, 2]
-    theta = np.arccos(np.clip(z, -1.0, 1.0))      # polar
     phi = np.arctan2(y, x)                         # azimuth
+    P = _legendre_normalised(np.clip(z, -1.0, 1.0), lmax)
     g = np.zeros(len(dirs))
     for l in range(1, lmax + 1):
         for m in range(-l, l + 1):
             c = rng.standard_normal() / (l + decay_plus)
-            Y = sph_harm_y(l, abs(m), theta, phi)
             if m < 0:
-                yr = np.sqrt(2.0) * Y.imag
+                yr = np.sqrt(2.0) * P[l][-m] * np.sin(-m * phi)
             elif m == 0:
-                yr = Y.real
+                yr = P[l][0]
             else:
-                yr = np.sqrt(2.0) * Y.real
+                yr = np.sqrt(2.0) * P[l][m] * np.cos(m * phi)
             g += c * yr
     return g
 
@@ -218,44 +237,61 @@ def noisy_cube_sphere(n, amp=0.05, lmax=8, seed=31):
     normalised to max |g| = 1.
     """
     n = int(n)
-    key_to_idx = {}
-    pts = []
-    F = []
-
-    def vid(p):
-        k = (int(p[0]), int(p[1]), int(p[2]))
-        if k not in key_to_idx:
-            key_to_idx[k] = len(pts)
-            pts.append(k)
-        return key_to_idx[k]
-
-    # integer lattice on the cube [-n, n]^3 (step 2), faces with outward CCW order
+    # integer lattice on the cube [-n, n]^3 (step 2), one (n+1)^2 grid per face
+    lin = -n + 2 * np.arange(n + 1)
+    grids, quads = [], []
     for axis in range(3):
         for sgn in (-1, 1):
             a1, a2 = (axis + 1) % 3, (axis + 2) % 3
-            grid = np.empty((n + 1, n + 1), dtype=np.int64)
-            for i in range(n + 1):
-                for j in range(n + 1):
-                    p = [0, 0, 0]
-                    p[axis] = sgn * n
-                    p[a1] = -n + 2 * i
-                    p[a2] = -n + 2 * j
-                    grid[i, j] = vid(p)
-            for i in range(n):
-                for j in range(n):
-                    a, b, c, d = grid[i, j], grid[i + 1, j], grid[i + 1, j + 1], grid[i, j + 1]
-                    # (a1, a2, axis) is right handed, so (a,b,c) is CCW seen from +axis
-                    if sgn > 0:
-                        F += [(a, b, c), (a, c, d)]
-                    else:
-                        F += [(a, c, b), (a, d, c)]
-    P = np.array(pts, dtype=np.float64)
+            p = np.zeros((n + 1, n + 1, 3), dtype=np.int64)
+            p[..., axis] = sgn * n
+            p[..., a1] = lin[:, None]
+            p[..., a2] = lin[None, :]
+            grids.append(p.reshape(-1, 3))
+    keys = np.concatenate(grids)
+    pts, inv = np.unique(keys, axis=0, return_inverse=True)
+    inv = inv.reshape(6, n + 1, n + 1)
+    F = []
+    for f, (axis, sgn) in enumerate([(ax, sg) for ax in range(3) for sg in (-1, 1)]):
+        g = inv[f]
+        a, b, c, d = g[:-1, :-1], g[1:, :-1], g[1:, 1:], g[:-1, 1:]
+        # (a1, a2, axis) is right handed, so (a, b, c) is CCW seen from +axis
+        if sgn > 0:
+            t1, t2 = np.stack([a, b, c], -1), np.stack([a, c, d], -1)
+        else:
+            t1, t2 = np.stack([a, c, b], -1), np.stack([a, d, c], -1)
+        F.append(np.stack([t1, t2], 2).reshape(-1, 3))
+    F = np.concatenate(F)
+    P = pts.astype(np.float64)
     dirs = P / np.linalg.norm(P, axis=1, keepdims=True)
     rng = np.random.default_rng(seed)
     g = _real_sph_harm_field(dirs, lmax, rng)
     g /= np.abs(g).max()
     V = dirs * (1.0 + amp * g)[:, None]
     return V.astype(np.float32), np.array(F, dtype=np.int32)
+
+
+def lognormal_triangle_counts(count, seed, median=20000, sigma=np.log(10.0) / 2, lo=2000, hi=200000):
+    """Triangle-count targets T ~ lognormal(median, sigma), redrawn until in [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    T = np.empty(count)
+    todo = np.arange(count)
+    while len(todo):
+        T[todo] = median * np.exp(sigma * rng.standard_normal(len(todo)))
+        todo = todo[(T[todo] < lo) | (T[todo] > hi)]
+    return T
+
+
+def noisy_sphere_batch(count=256, seed=3, amp=0.05, lmax=8):
+    """A batch of noisy cube-spheres with lognormal triangle counts: mesh m has
+    n = round(sqrt(T_m / 12)) quads per face edge (12 n^2 triangles) and its own
+    spherical-harmonic field (seed 1000 * seed + m).  Returns a list of (V, F)."""
+    T = lognormal_triangle_counts(count, seed)
+    out = []
+    for m in range(count):
+        n = max(1, int(round(np.sqrt(T[m] / 12.0))))
+        out.append(noisy_cube_sphere(n, amp=amp, lmax=lmax, seed=1000 * seed + m))
+    return out
 
 
 def helix_tube(turns=4, radius=1.0, pitch=0.6, tube_r=0.15, noise=0.01,

@@ -1,0 +1,131 @@
+"""Batched evaluation at full size: 256 noisy spheres with lognormal triangle
+counts (2k-200k, median 20k, 8.35 M triangles in all), 64 random boxes per mesh
+(16,384 boxes), 64 x 64 rays per face, one planned (autotuned, graph-replayed)
+evaluation.  Needs an MI355X."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import raygrid
+
+pytestmark = pytest.mark.gpu
+
+R, SEED, PER_MESH, N_MESH = 64, 33, 64, 256
+TOL_BOX = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def batch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2203_10521_amd import api
+    t0 = time.perf_counter()
+    host = synth.noisy_sphere_batch(N_MESH, seed=3)
+    meshes, boxes, bm = [], [], []
+    for m, (V, F) in enumerate(host):
+        meshes.append((torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()))
+        c, a, h = synth.random_boxes(PER_MESH, seed=5000 + m)
+        boxes.append(synth.boxes_to_array(c, a, h))
+        bm += [m] * PER_MESH
+    B = np.concatenate(boxes)
+    Bt = torch.from_numpy(B).cuda()
+    bmt = torch.from_numpy(np.array(bm, np.int32)).cuda()
+    _say(f"batch: {sum(F.shape[0] for _, F in host)} triangles, {len(B)} boxes, "
+         f"generated in {time.perf_counter() - t0:.1f} s")
+    return api, host, meshes, B, Bt, bmt
+
+
+@pytest.fixture(scope="module")
+def planned(batch):
+    import torch
+    api, host, meshes, B, Bt, bmt = batch
+    plan = api.OuterVolumePlan(Bt, R, seed=SEED, meshes=meshes, box_mesh=bmt, headroom=1.25)
+    info = plan.info()
+    _say(f"plan: tile {info['tile']}, caps {info['caps']}, tuned ms {info['tuned_ms']}")
+    out = plan.launch().clone()
+    torch.cuda.synchronize()
+    assert api.status() == 0
+    yield plan, info, out.cpu().numpy()
+    plan.close()
+
+
+def test_config3_planned_launch_equals_eager_and_separate_calls(batch, planned):
+    import torch
+    api, host, meshes, B, Bt, bmt = batch
+    plan, info, got = planned
+    eager = api.outer_volume_ex(None, None, Bt, R, seed=SEED, tile=info["tile"], meshes=meshes,
+                                box_mesh=bmt)["obv"].cpu().numpy()
+    assert api.status() == 0
+    assert np.array_equal(got, eager)
+    again = plan.launch().cpu().numpy()
+    assert np.array_equal(again, got)
+    # one mesh at a time (same jitter keys = global box index) gives the same bits
+    for m in (0, 97, 255):
+        sl = slice(m * PER_MESH, (m + 1) * PER_MESH)
+        key = torch.arange(m * PER_MESH, (m + 1) * PER_MESH, dtype=torch.int32, device="cuda")
+        sep = api.outer_volume(meshes[m][0], meshes[m][1], Bt[sl].contiguous(), R, seed=SEED,
+                               tile=info["tile"], box_key=key).cpu().numpy()
+        assert np.array_equal(sep, got[sl]), m
+
+
+def test_config3_trivial_boxes_exact(batch, planned):
+    """Boxes disjoint from a mesh's bounding ball give exactly V_box; boxes inside
+    a ball the solid contains give exactly 0 (any size, any seed).  The meshes
+    are star-shaped about the origin, so the solid contains the ball whose
+    radius is the smallest distance from the origin to a triangle's plane."""
+    api, host, meshes, B, Bt, bmt = batch
+    _, _, got = planned
+    c, h = B[:, :3].astype(np.float64), B[:, 12:].astype(np.float64)
+    circ = np.linalg.norm(h, axis=1)
+    n_out = n_in = 0
+    for m, (V, F) in enumerate(host):
+        V64 = V.astype(np.float64)
+        r_out = np.linalg.norm(V64, axis=1).max()
+        a, b_, c_ = V64[F[:, 0]], V64[F[:, 1]], V64[F[:, 2]]
+        n = np.cross(b_ - a, c_ - a)
+        r_in = (np.abs(np.einsum("ij,ij->i", n, a)) / np.linalg.norm(n, axis=1)).min()
+        for b in range(m * PER_MESH, (m + 1) * PER_MESH):
+            d = np.linalg.norm(c[b])
+            vb = 8.0 * h[b, 0] * h[b, 1] * h[b, 2]
+            if d - circ[b] > r_out * 1.0001:
+                assert abs(got[b] - vb) <= 1e-15 * vb, b
+                n_out += 1
+            elif d + circ[b] < r_in * 0.9999:
+                assert got[b] == 0.0, b
+                n_in += 1
+    _say(f"exact-trivial boxes: {n_out} disjoint, {n_in} inside")
+    assert n_out > 100
+
+
+def test_config3_sampled_boxes_match_oracle(batch, planned):
+    """Sixteen boxes that meet the surface region (small, median and large
+    meshes) vs the float64 oracle."""
+    api, host, meshes, B, Bt, bmt = batch
+    _, _, got = planned
+    T = np.array([F.shape[0] for _, F in host])
+    order = np.argsort(T, kind="stable")
+    picks = []
+    for m in (order[0], order[1], order[N_MESH // 2], order[-1]):
+        m = int(m)
+        r_out = np.linalg.norm(host[m][0].astype(np.float64), axis=1).max()
+        d = np.linalg.norm(B[m * PER_MESH:(m + 1) * PER_MESH, :3].astype(np.float64), axis=1)
+        circ = np.linalg.norm(B[m * PER_MESH:(m + 1) * PER_MESH, 12:].astype(np.float64), axis=1)
+        near = np.nonzero(d - circ < r_out)[0][:4]
+        picks += [m * PER_MESH + int(k) for k in near]
+    worst = 0.0
+    for b in picks:
+        m = b // PER_MESH
+        V, F = host[m]
+        ref = raygrid.raygrid_obv(V, F, B[b, :3], B[b, 3:12].reshape(3, 3), B[b, 12:15], R, SEED, b)
+        err = abs(got[b] - ref["obv"]) / max(ref["v_box"], 1e-30)
+        worst = max(worst, err)
+        assert err <= TOL_BOX, (b, m, T[m], got[b], ref["obv"])
+    _say(f"sampled boxes: worst |gpu - oracle| / V_box = {worst:.2e}")

@@ -168,6 +168,46 @@ def test_config2_torus_sampled_boxes_full_size(api):
     torch.cuda.synchronize()
 
 
+def test_grouped_candidates_equal_plain_calls(api):
+    """Boxes grouped by shared centre and axes (Lloyd candidates: a box grown in
+    several ways) give bitwise the plain call's results; boxes whose group frame
+    does not contain them (other axes, larger extent, bad index) fall back to
+    the whole mesh and still agree."""
+    import torch
+    V, F = synth.noisy_torus()
+    g = np.random.default_rng(12)
+    c, a, h = synth.random_boxes(8, seed=61, center_range=1.0, half_range=(0.05, 0.3))
+    cand, frame_of = [], []
+    for k in range(8):
+        for _ in range(6):
+            grow = g.uniform(1.0, 1.6, size=3).astype(np.float32)
+            grow[g.integers(0, 3)] = 1.0
+            cand.append((c[k], a[k], (h[k] * grow).astype(np.float32)))
+            frame_of.append(k)
+    B = synth.boxes_to_array(np.array([x[0] for x in cand]), np.array([x[1] for x in cand]),
+                             np.array([x[2] for x in cand]))
+    frames = np.zeros((8, 15), np.float32)
+    for k in range(8):
+        sel = [i for i, f in enumerate(frame_of) if f == k]
+        frames[k] = B[sel[0]]
+        frames[k, 12:] = B[sel, 12:].max(axis=0)
+    bf = np.array(frame_of, np.int32)
+    # fallbacks: wrong frame (other axes), a box larger than its frame, an index out of range
+    bf[5] = 3
+    B[11, 12] = frames[1, 12] * 1.25
+    bf[20] = 99
+    Vt, Ft = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+    Bt = torch.from_numpy(B).cuda()
+    keys = torch.from_numpy((np.arange(len(B)) * 7 + 3).astype(np.int32)).cuda()
+    api.status()
+    for R in (16, 48, 128):
+        plain = api.outer_volume(Vt, Ft, Bt, R, seed=9, box_key=keys).cpu().numpy()
+        grouped = api.outer_volume_grouped(Vt, Ft, Bt, R, torch.from_numpy(frames).cuda(),
+                                           torch.from_numpy(bf).cuda(), seed=9, box_key=keys).cpu().numpy()
+        assert np.array_equal(plain, grouped), (R, np.nonzero(plain != grouped))
+    assert api.status() == 0
+
+
 def test_validate_mesh(api):
     import torch
     V, F = synth.icosphere(2)

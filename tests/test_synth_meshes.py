@@ -34,3 +34,26 @@ def test_workload_sizes():
     assert len(F) == 12 * 41 * 41
     V, F = synth.helix_tube(rings=100, around=128)
     assert len(F) == 99 * 128 * 2 + 256
+
+
+def test_spherical_harmonic_recurrence_matches_scipy():
+    from scipy.special import sph_harm_y
+    from synth.meshes import _legendre_normalised
+    g = np.random.default_rng(0)
+    d = g.normal(size=(500, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    theta = np.arccos(d[:, 2])
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    P = _legendre_normalised(d[:, 2], 8)
+    for l in range(9):
+        for m in range(l + 1):
+            Y = sph_harm_y(l, m, theta, phi)
+            assert np.allclose(P[l][m] * np.cos(m * phi), Y.real, atol=1e-12), (l, m)
+            assert np.allclose(P[l][m] * np.sin(m * phi), Y.imag, atol=1e-12), (l, m)
+
+
+def test_lognormal_counts_range_and_median():
+    T = synth.lognormal_triangle_counts(4096, seed=3)
+    assert T.min() >= 2000 and T.max() <= 200000
+    # truncation at +-2 sigma is nearly symmetric in log space: median stays ~20k
+    assert 17000 < np.median(T) < 23000
