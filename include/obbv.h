@@ -150,8 +150,9 @@ int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_b
  * Eq. 12) are such groups: every candidate is its box grown to enclose one more
  * triangle.  frames[f] is the union of group f (its centre, axes and the
  * largest half extents of its boxes); box_frame[b] names the group of box b.
- * The mesh is culled once per group, so each box only walks the triangles that
- * project into a face of its group's frame.  The result is bitwise the one of
+ * The mesh is culled and transformed once per group, so each box only streams
+ * the frame coordinates of the triangles that project into a face of its
+ * group's frame.  The result is bitwise the one of
  * obbv_outer_volume with the same boxes and keys.  A box whose centre or axes
  * differ (bitwise) from its frame's, or that reaches outside it, or whose
  * box_frame is out of range, walks the whole mesh instead (same result).
@@ -159,8 +160,8 @@ int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_b
  * frames     device, [n_frames] obbv_box, 1 <= n_frames <= n_boxes
  * box_frame  device, [n_boxes] int32
  * other arguments as obbv_outer_volume (box_key nullable = box index).
- * The call synchronises the stream once (scratch sizing), twice when
- * n_frames x n_triangles exceeds 2^28. */
+ * The call synchronises the stream once (scratch sizing), twice when the
+ * frame lists could exceed 2 GiB (48 bytes per frame and triangle). */
 int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
                               int32_t n_boxes, const obbv_ov_params* params, const obbv_box* frames,
                               const int32_t* box_frame, int32_t n_frames, double* out_obv, void* stream);

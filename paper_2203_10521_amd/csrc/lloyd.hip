@@ -111,24 +111,45 @@ struct Evaluator {
     out.assign(n, 0.0);
     if (n == 0) return OBBV_OK;
     // Candidates of one box share its centre and axes: group them into frames so
-    // that the mesh is culled once per frame (against the union of its boxes).
+    // that the mesh is culled and transformed once per frame (against the union
+    // of its boxes).  Boxes of one centre and axes are split into size classes
+    // (a frame grows while the sum of its half extents stays within 1.6 times
+    // that of its smallest box), so small candidates do not walk the triangles
+    // of far-grown ones.
     std::vector<int32_t> box_frame(n);
     fr.clear();
     {
       std::unordered_map<std::string, int32_t> index;
+      std::vector<std::vector<int32_t>> members;
       std::string key(48, '\0');
       for (size_t i = 0; i < n; ++i) {
         std::memcpy(&key[0], boxes[i].c, 12);
         std::memcpy(&key[12], boxes[i].Q, 36);
         auto it = index.find(key);
         if (it == index.end()) {
-          it = index.emplace(key, (int32_t)fr.size()).first;
-          fr.push_back(boxes[i]);
-        } else {
-          HBox& f = fr[it->second];
-          for (int r = 0; r < 3; ++r) f.h[r] = std::fmax(f.h[r], boxes[i].h[r]);
+          it = index.emplace(key, (int32_t)members.size()).first;
+          members.emplace_back();
         }
-        box_frame[i] = it->second;
+        members[it->second].push_back((int32_t)i);
+      }
+      auto size_of = [](const float h[3]) { return (double)h[0] + (double)h[1] + (double)h[2]; };
+      for (auto& mem : members) {
+        std::stable_sort(mem.begin(), mem.end(), [&](int32_t x, int32_t y) {
+          return size_of(boxes[x].h) < size_of(boxes[y].h);
+        });
+        double limit = -1.0;
+        for (int32_t i : mem) {
+          const double si = size_of(boxes[i].h);
+          if (fr.empty() || limit < 0.0 || !(si <= limit)) {  // NaN sizes start their own frame
+            fr.push_back(boxes[i]);
+            limit = 1.6 * si;
+          } else {
+            HBox& f = fr.back();
+            for (int r = 0; r < 3; ++r) f.h[r] = std::fmax(f.h[r], boxes[i].h[r]);
+          }
+          box_frame[i] = (int32_t)fr.size() - 1;
+        }
+        limit = -1.0;
       }
     }
     const size_t nf = fr.size();

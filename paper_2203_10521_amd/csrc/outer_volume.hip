@@ -191,20 +191,38 @@ struct CullArgs {
   uint32_t* status;
   int64_t rec_cap;  // record / bin capacity of the scratch (planned launches)
   int64_t bin_cap;
-  // nullable: the triangles a box can see, as one list per shared frame
-  const int32_t* tri_list;
+  // nullable: the triangles a box can see, one list per shared frame, held as
+  // their frame-local vertex coordinates (3 float4 per triangle)
+  const float4* list_P;
   const int64_t* list_off;  // [n_frames + 1]
   const int32_t* box_list;  // [n_boxes] frame of every box, -1 = the whole mesh
 };
 
-// Number of triangles box b walks, and its t-th triangle.
+// Number of triangles box b walks.
 __device__ inline int box_ntri(const CullArgs& a, int b, const MeshDev& M) {
-  const int l = a.tri_list ? a.box_list[b] : -1;
+  const int l = a.list_P ? a.box_list[b] : -1;
   return l < 0 ? M.nt : (int)(a.list_off[l + 1] - a.list_off[l]);
 }
-__device__ inline int box_tri(const CullArgs& a, int b, int t) {
-  const int l = a.tri_list ? a.box_list[b] : -1;
-  return l < 0 ? t : a.tri_list[a.list_off[l] + t];
+
+// The t-th triangle of box b in the box frame: from its frame's list (the same
+// bits to_local gives: same centre, same axes), else transformed from the mesh.
+__device__ inline bool cull_tri(const CullArgs& a, int b, const MeshDev& M, const BoxRegs& B, int t,
+                                float P[3][3]) {
+  const int l = a.list_P ? a.box_list[b] : -1;
+  if (l < 0) return t < M.nt && load_tri_local(M, t, B, P, a.status);
+  if (t >= (int)(a.list_off[l + 1] - a.list_off[l])) return false;
+  const float4* q = a.list_P + 3 * (a.list_off[l] + t);
+  const float4 x = q[0], y = q[1], z = q[2];
+  P[0][0] = x.x;
+  P[0][1] = x.y;
+  P[0][2] = x.z;
+  P[1][0] = x.w;
+  P[1][1] = y.x;
+  P[1][2] = y.y;
+  P[2][0] = y.z;
+  P[2][1] = y.w;
+  P[2][2] = z.x;
+  return true;
 }
 
 __global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
@@ -258,7 +276,7 @@ __global__ void k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev
 __global__ void __launch_bounds__(kCullThreads)
 k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, uint32_t axis_mask, int nch,
              int32_t* __restrict__ cnt, const int64_t* __restrict__ list_off, int32_t* __restrict__ cur,
-             int32_t* __restrict__ list, uint32_t* status) {
+             float4* __restrict__ list_P, uint32_t* status) {
   const int64_t total = (int64_t)n_frames * nch;
   const int lane = threadIdx.x & 63;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
@@ -288,10 +306,14 @@ k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, uint3
     base = __shfl(base, leader);
     if (keep) {
       const int pos = base + (int)__popcll(m & ((1ull << lane) - 1ull));
-      if (pos < cnt[fr])
-        list[list_off[fr] + pos] = t;
-      else  // count and write passes disagree: never expected
+      if (pos < cnt[fr]) {
+        float4* q = list_P + 3 * (list_off[fr] + pos);
+        q[0] = make_float4(P[0][0], P[0][1], P[0][2], P[1][0]);
+        q[1] = make_float4(P[1][1], P[1][2], P[2][0], P[2][1]);
+        q[2] = make_float4(P[2][2], 0.f, 0.f, 0.f);
+      } else {  // count and write passes disagree: never expected
         atomicOr(status, OBBV_STATUS_BAD_INDEX);
+      }
     }
   }
 }
@@ -310,7 +332,7 @@ k_cull_count(CullArgs a, int32_t* __restrict__ side_cnt) {
     const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    const bool ok = t < box_ntri(a, b, M) && load_tri_local(M, box_tri(a, b, t), B, P, a.status);
+    const bool ok = cull_tri(a, b, M, B, t, P);
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       if (!((a.axis_mask >> w) & 1u)) continue;
@@ -384,7 +406,7 @@ k_tile_count(CullArgs a, const int32_t* __restrict__ side, int32_t* __restrict__
     const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    if (t < box_ntri(a, b, M) && load_tri_local(M, box_tri(a, b, t), B, P, a.status)) {
+    if (cull_tri(a, b, M, B, t, P)) {
       for (int w = 0; w < 3; ++w) {
         if (!((a.axis_mask >> w) & 1u)) continue;
         const int bw = b * 3 + w;
@@ -485,7 +507,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
     const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    const bool ok = t < box_ntri(a, b, M) && load_tri_local(M, box_tri(a, b, t), B, P, a.status);
+    const bool ok = cull_tri(a, b, M, B, t, P);
     if (lds) {
       // pass 1: count this item's entries per tile
       for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) cnt[k] = 0;
@@ -958,17 +980,17 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   hipLaunchKernelGGL(k_fill_zero, dim3(256), dim3(256), 0, s, (uint32_t*)(meta + o_zero0),
                      (int64_t)((o_zero1 - o_zero0) / 4));
 
-  int32_t* d_list = nullptr;
+  float4* d_listP = nullptr;
   if (sf) {  // candidate triangles of every shared frame
     const int nt = meshes[0].n_triangles;
     const int nch = ceil_div(std::max(nt, 1), kCullThreads);
     const unsigned fgrid = (unsigned)std::min<int64_t>((int64_t)n_frames * nch, 256 * 16);
     hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], mask,
-                       nch, d_fcnt, (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr, status);
+                       nch, d_fcnt, (const int64_t*)nullptr, (int32_t*)nullptr, (float4*)nullptr, status);
     OBBV_HIP(hipGetLastError());
     OBBV_RET(exclusive_scan_i32_to_i64(d_fcnt, d_foff, n_frames, d_scan, scan_bytes, s));
     int64_t bound = (int64_t)n_frames * nt;
-    if (bound * 4 > ((int64_t)1 << 30)) {  // large: size the lists exactly (one host round trip)
+    if (bound * 48 > ((int64_t)1 << 31)) {  // large: size the lists exactly (one host round trip)
       int64_t* pin = nullptr;
       OBBV_RET(pinned_totals(&pin));
       OBBV_HIP(hipMemcpyAsync(pin + 3, d_foff + n_frames, 8, hipMemcpyDeviceToHost, s));
@@ -976,10 +998,10 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       bound = pin[3];
     }
     void* lv = nullptr;
-    OBBV_RET(pool_get(kPoolLists, (size_t)std::max<int64_t>(bound, 1) * 4, &lv));
-    d_list = (int32_t*)lv;
+    OBBV_RET(pool_get(kPoolLists, (size_t)std::max<int64_t>(bound, 1) * 48, &lv));
+    d_listP = (float4*)lv;
     hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], mask,
-                       nch, d_fcnt, (const int64_t*)d_foff, d_fcur, d_list, status);
+                       nch, d_fcnt, (const int64_t*)d_foff, d_fcur, d_listP, status);
     OBBV_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_box_chunks, dim3(ceil_div(n_boxes, 256)), dim3(256), 0, s, box_mesh, d_mesh,
@@ -1001,7 +1023,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   ca.status = status;
   ca.rec_cap = planned ? ex->rec_cap : INT64_MAX;
   ca.bin_cap = planned ? ex->bin_cap : INT64_MAX;
-  ca.tri_list = d_list;
+  ca.list_P = d_listP;
   ca.list_off = sf ? d_foff : nullptr;
   ca.box_list = d_blist;
   const int64_t items_bound = (int64_t)n_boxes * ceil_div(std::max(max_nt, 1), kCullThreads);

@@ -65,3 +65,15 @@ def test_feature_row_layout():
     assert np.allclose(x[:3], [0, 0.5, 1.0]) and np.allclose(x[3:12], np.eye(3).reshape(-1))
     assert np.allclose(x[12:15], np.log([0.25, 0.5, 1.0]))
     assert np.array_equal(x[15:527], occ) and not x[527:].any()
+
+
+def test_adam_first_step_is_a_signed_learning_rate_step():
+    """Kingma and Ba (2015): after one step from zero moments the bias-corrected
+    update is lr * g / (|g| + eps) per parameter."""
+    g = np.random.default_rng(9)
+    p = {"a": g.normal(size=7), "b": g.normal(size=(2, 3))}
+    grads = {"a": g.normal(size=7), "b": g.normal(size=(2, 3)) * 1e-3}
+    ref = {k: v - 0.01 * grads[k] / (np.abs(grads[k]) + 1e-8) for k, v in p.items()}
+    out = mlp.adam_step({k: v.copy() for k, v in p.items()}, grads, {}, lr=0.01)
+    for k in p:
+        assert np.allclose(out[k], ref[k], rtol=1e-12, atol=1e-15)

@@ -103,3 +103,26 @@ def test_axes_estimates_agree_with_exact_on_config1_boxes():
         ex = exact.inside_volume(V, F, c[b], a[b], h[b], axis=0)
         # statistical agreement of the 3-axis mean at R = 32
         assert abs(r["v_in"] - ex) <= 2e-2 * r["v_box"]
+
+
+def test_occupancy_cuboid_face_splits_sub_slabs_exactly():
+    """An axis-aligned cuboid whose top face lies on the boundary between the
+    4th and 5th sub-slab of the box (and whose sides contain the box's column):
+    sub-slabs 0-3 are inside (1), 4-7 outside (0), on every ray (up to the
+    rounding of the sub-slab bounds)."""
+    V, F = synth.cuboid((2.0, 2.0, 1.0), center=(0.0, 0.0, -1.0))   # solid z in [-2, 0]
+    occ = raygrid.occupancy(V.astype(np.float64), F, [0.1, -0.2, 0.0], np.eye(3), [0.5, 0.4, 0.8], 3, 7)
+    assert np.abs(occ[:, :, :4] - 1.0).max() <= 1e-12
+    assert np.abs(occ[:, :, 4:]).max() <= 1e-12
+
+
+def test_occupancy_mean_is_the_inside_fraction_of_its_rays():
+    """Summed over the 8 sub-slabs, the occupancy of a ray is its inside length
+    over the slab: the mean over (i, j, k) is V_in along axis 2 / V_box for the
+    same 8 x 8 jittered rays."""
+    V, F = synth.noisy_torus(nu=48, nv=24)
+    c, a, h = synth.random_boxes(3, seed=4, center_range=0.8, half_range=(0.3, 0.7))
+    for b in range(3):
+        occ = raygrid.occupancy(V, F, c[b], a[b], h[b], 11, b)
+        r = raygrid.raygrid_obv(V, F, c[b], a[b], h[b], 8, 11, b, axis_mask=4)
+        assert abs(occ.mean() - r["v_in"] / r["v_box"]) <= 1e-12
