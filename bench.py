@@ -44,7 +44,12 @@ SEED_MESH = 21
 # each scaled by the same counter's reading for a plain device copy of known size.
 # Valid only for the kernel source it was measured on: any change to the
 # outer-volume source (hash below) reports null until the counters are re-taken.
-K_TEST_TRAFFIC = None
+K_TEST_TRAFFIC = {
+    "source_sha256": "9cd2fdd753d3ac49807ff2c90a97df4849e305a97bd24b3956837aa8faa71c0d",
+    "fetch_bytes_per_launch": 67657795,   # 33,037.1 KiB raw x 2.0 (copy calibration)
+    "write_bytes_per_launch": 624150,     # 609.5 KiB raw x 1.0
+    "profile": "profiles/k_test_torus_hierarchy_traffic.md",
+}
 
 
 def log(msg):
@@ -115,7 +120,7 @@ def surrogate_comparison(api, torch, Vt, Ft, hp, exact):
     val_mae = (ranker.predict(P, X[-n_val:]) - t[-n_val:]).abs().mean().item()
     occ_mae = (ranker.occupancy_heuristic(X[-n_val:]) - t[-n_val:]).abs().mean().item()
     vol, frame = api.occupancy_volume(Vt, Ft, nb=16, seed=1)
-    sur = api.Surrogate(P, vol, frame, verify_top=4, max_error=0.05)
+    sur = api.Surrogate(P, vol, frame, verify_top=0, max_error=0.05, judge_every=16)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     out = api.build_hierarchy(Vt, Ft, surrogate=sur, **hp)

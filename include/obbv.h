@@ -233,13 +233,15 @@ typedef struct {
   const float* volume;     /* [N][N][N] occupancy volume (obbv_occupancy_volume)  */
   const float* frame;      /* [10] frame of the volume                            */
   int32_t N;               /* volume edge (8 nb)                                  */
-  int32_t verify_top;      /* candidates per receiving box and round evaluated
-                              exactly (the smallest predicted changes)            */
+  int32_t verify_top;      /* in ordinary rounds, candidates per receiving box
+                              evaluated exactly (smallest predicted change);
+                              0 = decide on the predictions alone                 */
   float max_error;         /* rolling mean |predicted - exact| outer fraction of
-                              the last 256 verified candidates above which the
-                              rest of the Lloyd iteration evaluates every
-                              candidate exactly                                   */
-  int32_t reserved;        /* must be 0                                           */
+                              the last 256 judged candidates above which the rest
+                              of the Lloyd iteration evaluates every candidate
+                              exactly                                             */
+  int32_t judge_every;     /* every judge_every-th flood round evaluates every
+                              candidate exactly and judges the ranker (>= 1)      */
 } obbv_surrogate;
 
 typedef struct {
@@ -275,15 +277,17 @@ int obbv_lloyd_step(obbv_lloyd* st, void* stream);
 /* Host.  With a non-NULL surrogate, later flood rounds predict the outer
  * fraction f of every candidate box (a box grown by a popped triangle that no box
  * of its group contains) and of the current boxes, with the predicted change
- * dOBV = max(0, f(grown) V(grown) - f(current) V(current)) (Eq. 12).  Of the
- * candidates a box receives in one round, only the verify_top with the smallest
- * predicted change are evaluated exactly; every triangle then goes to the box
- * with the smallest change, exact where evaluated and predicted elsewhere.  Box
- * volumes after a round and the parameter update stay exact.  The exact values
- * judge the ranker: when the rolling error exceeds max_error the rest of that
- * iteration evaluates every candidate (counted as a fallback).  NULL returns to
- * exact evaluation of every candidate.  The structure is copied; its device
- * arrays must stay valid. */
+ * dOBV = max(0, f(grown) V(grown) - f(current) V(current)) (Eq. 12).  In an
+ * ordinary round, of the candidates a box receives only the verify_top with the
+ * smallest predicted change are evaluated exactly, and every triangle goes to
+ * the box with the smallest change (exact where evaluated, predicted elsewhere);
+ * a round with nothing to verify makes no outer-volume call at all.  Every
+ * judge_every-th round evaluates every candidate exactly, decides on the exact
+ * values and judges the ranker with them: when the rolling error exceeds
+ * max_error the rest of that iteration is exact (counted as a fallback).  The
+ * outer volumes of grown boxes, the final boxes of the flood and the parameter
+ * update stay exact.  NULL returns to exact evaluation of every candidate.  The
+ * structure is copied; its device arrays must stay valid. */
 int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* surrogate);
 
 /* Host.  Results of the last step (each output nullable, host):

@@ -38,7 +38,7 @@ class ObbvLloydParams(ctypes.Structure):
 
 class ObbvSurrogate(ctypes.Structure):
     _fields_ = [("mlp_params", c_void_p), ("volume", c_void_p), ("frame", c_void_p), ("N", c_int32),
-                ("verify_top", c_int32), ("max_error", ctypes.c_float), ("reserved", c_int32)]
+                ("verify_top", c_int32), ("max_error", ctypes.c_float), ("judge_every", c_int32)]
 
 
 class ObbvHierParams(ctypes.Structure):

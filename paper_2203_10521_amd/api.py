@@ -256,13 +256,13 @@ COUNTERS = ("evals", "rounds", "trivial", "moves", "predicted", "fallbacks")
 class Surrogate:
     """Device arrays of a trained ranker (obbv_surrogate)."""
 
-    def __init__(self, mlp_params, volume, frame, verify_top=1, max_error=0.05):
+    def __init__(self, mlp_params, volume, frame, verify_top=0, max_error=0.05, judge_every=16):
         self.mlp_params, self.volume, self.frame = mlp_params, volume, frame
-        self.verify_top, self.max_error = int(verify_top), float(max_error)
+        self.verify_top, self.max_error, self.judge_every = int(verify_top), float(max_error), int(judge_every)
 
     def struct(self):
         self._s = _lib.ObbvSurrogate(self.mlp_params.data_ptr(), self.volume.data_ptr(), self.frame.data_ptr(),
-                                     self.volume.shape[0], self.verify_top, self.max_error, 0)
+                                     self.volume.shape[0], self.verify_top, self.max_error, self.judge_every)
         return self._s
 
 

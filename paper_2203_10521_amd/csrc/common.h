@@ -50,13 +50,39 @@ enum PoolSlot {
   kPoolMlp = 4,
   kPoolFeat = 5,
   kPoolLists = 6,
-  kPoolCount = 7
+  kPoolItems = 7,
+  kPoolCount = 8
 };
 
 // Ensures slot `slot` of the current device holds at least `bytes` and returns it.
 // Growing frees the old block (hipFree waits for the device), so call it only
 // where no queued kernel still reads that slot.
 int pool_get(int slot, size_t bytes, void** out);
+
+// How one outer-volume evaluation is executed.  Default: scratch is sized from
+// the device counts (one host round trip).  planned: fixed scratch, no round
+// trip, capturable into a HIP graph.  capped: fixed record / bin / work-item
+// capacities for a caller that checks the actual totals afterwards and repeats
+// the call if they exceed the capacities.  `status` (nullable, device) replaces
+// the library status word for the call; with `publish` (nullable, pinned host
+// memory mapped for the device) the call's last kernel writes there the status
+// bits ([0], uint32) and the totals ([1..3], int64: records, bin entries, work
+// items), so the caller reads them after a stream synchronisation without a
+// copy command.
+struct OvExec {
+  bool planned = false;
+  bool capped = false;
+  char* meta = nullptr;
+  size_t meta_cap = 0, meta_bytes = 0;
+  float4* recs = nullptr;
+  int32_t* bins = nullptr;
+  int64_t rec_cap = 0, bin_cap = 0, item_cap = 0;
+  int64_t n_rec = 0, n_bin = 0, n_items = 0;  // counts of the last synchronous run
+  char* items = nullptr;                      // per-cull-item counts and offsets
+  size_t items_cap = 0, items_bytes = 0;
+  uint32_t* status = nullptr;
+  int64_t* publish = nullptr;
+};
 int status_word(uint32_t** out);   // device pointer of this device's status word
 
 // measurement hooks (obbv_profile_enable / obbv_profile_read)

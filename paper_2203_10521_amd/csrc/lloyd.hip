@@ -44,7 +44,10 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
                       float* out_occ);
 int outer_volume_frames(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key, int32_t n_boxes,
                         const obbv_ov_params* params, const obbv_box* frames, const int32_t* box_frame,
-                        int32_t n_frames, double* out_obv, hipStream_t s);
+                        int32_t n_frames, double* out_obv, hipStream_t s, OvExec* ex);
+int outer_volume_exec(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key, int32_t n_boxes,
+                      const obbv_ov_params* params, double* out_obv, hipStream_t s, OvExec* ex);
+int status_or(uint32_t bits, hipStream_t s);
 int fit_impl(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters, obbv_box* out_boxes,
              double* out_eigvals, hipStream_t st);
 int mlp_forward_impl(const float* params, const float* X, int32_t n, float* out_f, hipStream_t s);
@@ -72,28 +75,35 @@ struct Evaluator {
   obbv_mesh mesh{};
   obbv_ov_params params{};
   hipStream_t stream = nullptr;
-  char* dbuf = nullptr;  // device: boxes, keys, frames, box frames, results
+  char* dbuf = nullptr;  // device: boxes, keys, frames, box frames, control words, results
   char* hbuf = nullptr;  // pinned host staging of the same layout
+  char* hdev = nullptr;  // hbuf as mapped for the device (results are written there)
   size_t cap = 0;
+  // Record / bin / work-item scratch of capped calls (no mid-call host round
+  // trip); grown, and the call repeated synchronously, when a call overflows.
+  char* sbuf = nullptr;
+  size_t scap = 0;
+  int64_t rec_cap = 0, bin_cap = 0, item_cap = 0;
+  int64_t overflows = 0;
   int64_t evals = 0;
   int64_t calls = 0;
   std::vector<HBox> fr;  // frames of the current call (host)
   // optional uniform sample (reservoir) of the evaluated (box, outer volume) pairs
-  int64_t rec_cap = 0, rec_seen = 0;
-  std::vector<HBox> rec_box;
-  std::vector<double> rec_val;
+  int64_t smp_cap = 0, smp_seen = 0;
+  std::vector<HBox> smp_box;
+  std::vector<double> smp_val;
 
   void record(const std::vector<HBox>& boxes, const std::vector<double>& vals) {
     for (size_t i = 0; i < boxes.size(); ++i) {
-      const int64_t k = rec_seen++;
-      if ((int64_t)rec_box.size() < rec_cap) {
-        rec_box.push_back(boxes[i]);
-        rec_val.push_back(vals[i]);
+      const int64_t k = smp_seen++;
+      if ((int64_t)smp_box.size() < smp_cap) {
+        smp_box.push_back(boxes[i]);
+        smp_val.push_back(vals[i]);
       } else {
         const uint64_t j = splitmix64_at(0x5DEECE66Dull, (uint64_t)k) % (uint64_t)(k + 1);
-        if ((int64_t)j < rec_cap) {
-          rec_box[j] = boxes[i];
-          rec_val[j] = vals[i];
+        if ((int64_t)j < smp_cap) {
+          smp_box[j] = boxes[i];
+          smp_val[j] = vals[i];
         }
       }
     }
@@ -102,6 +112,35 @@ struct Evaluator {
   ~Evaluator() {
     if (dbuf) (void)hipFree(dbuf);
     if (hbuf) (void)hipHostFree(hbuf);
+    if (sbuf) (void)hipFree(sbuf);
+  }
+
+  // capacities from the totals of a synchronous call, with headroom
+  int grow(int64_t n_rec, int64_t n_bin, int64_t n_items) {
+    const int64_t r = std::max(rec_cap, n_rec + n_rec / 2 + 4096);
+    const int64_t b = std::max(bin_cap, n_bin + n_bin / 2 + 8192);
+    const int64_t it = std::max(item_cap, n_items + n_items / 2 + 256);
+    const size_t need = al((size_t)r * 64) + al((size_t)b * 4);
+    if (need > scap) {
+      if (sbuf) {
+        OBBV_HIP(hipStreamSynchronize(stream));
+        OBBV_HIP(hipFree(sbuf));
+        sbuf = nullptr;
+        scap = 0;
+      }
+      if (hipMalloc((void**)&sbuf, need) != hipSuccess) {
+        (void)hipGetLastError();
+        sbuf = nullptr;
+        rec_cap = bin_cap = item_cap = 0;
+        set_error("hipMalloc failed for the Lloyd evaluation scratch");
+        return OBBV_ERR_OOM;
+      }
+      scap = need;
+    }
+    rec_cap = r;
+    bin_cap = b;
+    item_cap = it;
+    return OBBV_OK;
   }
 
   static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -155,14 +194,14 @@ struct Evaluator {
     const size_t nf = fr.size();
     const bool shared = 2 * nf <= n;
     const size_t o_box = 0, o_key = al(n * sizeof(obbv_box)), o_frame = o_key + al(n * 4);
-    const size_t o_bf = o_frame + al(nf * sizeof(obbv_box)), o_out = o_bf + al(n * 4);
+    const size_t o_bf = o_frame + al(nf * sizeof(obbv_box)), o_ctl = o_bf + al(n * 4), o_out = o_ctl + 256;
     const size_t need = o_out + al(n * 8);
     if (need > cap) {
       if (dbuf) {
         OBBV_HIP(hipStreamSynchronize(stream));
         OBBV_HIP(hipFree(dbuf));
         OBBV_HIP(hipHostFree(hbuf));
-        dbuf = hbuf = nullptr;
+        dbuf = hbuf = hdev = nullptr;
         cap = 0;
       }
       const size_t want = std::max(need * 2, (size_t)1 << 16);
@@ -172,10 +211,12 @@ struct Evaluator {
         set_error("hipMalloc failed for the Lloyd evaluation buffer");
         return OBBV_ERR_OOM;
       }
-      if (hipHostMalloc((void**)&hbuf, want, hipHostMallocDefault) != hipSuccess) {
+      if (hipHostMalloc((void**)&hbuf, want, hipHostMallocDefault) != hipSuccess ||
+          hipHostGetDevicePointer((void**)&hdev, hbuf, 0) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(dbuf);
-        dbuf = hbuf = nullptr;
+        if (hbuf) (void)hipHostFree(hbuf);
+        dbuf = hbuf = hdev = nullptr;
         set_error("hipHostMalloc failed for the Lloyd evaluation buffer");
         return OBBV_ERR_OOM;
       }
@@ -194,23 +235,53 @@ struct Evaluator {
       for (size_t f = 0; f < nf; ++f) put(hf + f, fr[f]);
       std::memcpy(hbuf + o_bf, box_frame.data(), n * 4);
     }
-    const size_t up = shared ? o_out : o_frame;
-    OBBV_HIP(hipMemcpyAsync(dbuf, hbuf, up, hipMemcpyHostToDevice, stream));
-    double* dout = (double*)(dbuf + o_out);
-    if (shared)
-      OBBV_RET(outer_volume_frames(&mesh, (const obbv_box*)(dbuf + o_box), (const uint32_t*)(dbuf + o_key),
+    // control words: the call's private status word (device, zeroed by the
+    // upload); the published status bits and totals (host, written by the device)
+    std::memset(hbuf + o_ctl, 0, 256);
+    OBBV_HIP(hipMemcpyAsync(dbuf, hbuf, o_out, hipMemcpyHostToDevice, stream));
+    double* hout = (double*)(hdev + o_out);  // results go straight to pinned host memory
+    uint32_t* dstatus = (uint32_t*)(dbuf + o_ctl);
+    int64_t* pub = (int64_t*)(hdev + o_ctl + 64);
+    const int64_t* hpub = (const int64_t*)(hbuf + o_ctl + 64);
+    auto run = [&](OvExec* ex) -> int {
+      if (shared)
+        return outer_volume_frames(&mesh, (const obbv_box*)(dbuf + o_box), (const uint32_t*)(dbuf + o_key),
                                    (int32_t)n, &params, (const obbv_box*)(dbuf + o_frame),
-                                   (const int32_t*)(dbuf + o_bf), (int32_t)nf, dout, stream));
-    else
-      OBBV_RET(outer_volume_impl(&mesh, 1, (const obbv_box*)(dbuf + o_box), nullptr,
-                                 (const uint32_t*)(dbuf + o_key), (int32_t)n, &params, dout, nullptr, nullptr,
-                                 nullptr, nullptr, stream, nullptr));
-    OBBV_HIP(hipMemcpyAsync(hbuf + o_out, dout, n * 8, hipMemcpyDeviceToHost, stream));
-    OBBV_HIP(hipStreamSynchronize(stream));
+                                   (const int32_t*)(dbuf + o_bf), (int32_t)nf, hout, stream, ex);
+      return outer_volume_exec(&mesh, (const obbv_box*)(dbuf + o_box), (const uint32_t*)(dbuf + o_key), (int32_t)n,
+                               &params, hout, stream, ex);
+    };
+    bool done = false;
+    if (rec_cap > 0) {  // one pass, no round trip; checked afterwards
+      OvExec ex;
+      ex.capped = true;
+      ex.recs = (float4*)sbuf;
+      ex.bins = (int32_t*)(sbuf + al((size_t)rec_cap * 64));
+      ex.rec_cap = rec_cap;
+      ex.bin_cap = bin_cap;
+      ex.item_cap = item_cap;
+      ex.status = dstatus;
+      ex.publish = pub;
+      OBBV_RET(run(&ex));
+      OBBV_HIP(hipStreamSynchronize(stream));
+      const uint32_t st = (uint32_t)hpub[0];
+      if (!(st & OBBV_STATUS_OVERFLOW) && hpub[1] <= rec_cap && hpub[2] <= bin_cap && hpub[3] <= item_cap) {
+        done = true;
+        if (st) OBBV_RET(status_or(st, stream));
+      } else {
+        ++overflows;
+      }
+    }
+    if (!done) {  // sized from the device counts; then capacities for the next calls
+      OvExec probe;
+      OBBV_RET(run(&probe));
+      OBBV_HIP(hipStreamSynchronize(stream));
+      OBBV_RET(grow(probe.n_rec, probe.n_bin, probe.n_items));
+    }
     std::memcpy(out.data(), hbuf + o_out, n * 8);
     evals += (int64_t)n;
     ++calls;
-    if (rec_cap > 0) record(boxes, out);
+    if (smp_cap > 0) record(boxes, out);
     return OBBV_OK;
   }
 };
@@ -224,8 +295,6 @@ struct Predictor {
   hipStream_t stream = nullptr;
   char* dbuf = nullptr;
   size_t cap = 0;
-  std::vector<obbv_box> hb;
-  std::vector<float> hf;
   bool paused = false;  // the judge found the ranker off: exact evaluation until the next iteration
   double err_sum = 0.0;
   int64_t err_n = 0, predicted = 0, fallbacks = 0;
@@ -255,8 +324,13 @@ struct Predictor {
     }
   }
 
+  char* hbuf = nullptr;  // pinned staging: boxes in, predictions out (written by the device)
+  char* hdev = nullptr;
+  size_t hcap = 0;
+
   ~Predictor() {
     if (dbuf) (void)hipFree(dbuf);
+    if (hbuf) (void)hipHostFree(hbuf);
   }
 
   int predict(const std::vector<HBox>& boxes, std::vector<float>& out) {
@@ -264,38 +338,44 @@ struct Predictor {
     const size_t np = (n + 31) / 32 * 32;
     out.assign(n, 0.f);
     if (n == 0) return OBBV_OK;
-    const size_t need = np * (sizeof(obbv_box) + 544 * 4 + 4) + 1024;
-    if (need > cap) {
-      if (dbuf) {
-        OBBV_HIP(hipStreamSynchronize(stream));
-        OBBV_HIP(hipFree(dbuf));
-        dbuf = nullptr;
-      }
-      cap = std::max(need * 2, (size_t)1 << 20);
-      if (hipMalloc((void**)&dbuf, cap) != hipSuccess) {
+    const size_t o_f = (np * sizeof(obbv_box) + 255) & ~(size_t)255;
+    const size_t hneed = o_f + np * 4;
+    const size_t need = o_f + np * 544 * 4 + 1024;
+    if (need > cap || hneed > hcap) {
+      OBBV_HIP(hipStreamSynchronize(stream));
+      if (dbuf) OBBV_HIP(hipFree(dbuf));
+      if (hbuf) OBBV_HIP(hipHostFree(hbuf));
+      dbuf = hbuf = hdev = nullptr;
+      cap = hcap = 0;
+      const size_t want = std::max(need * 2, (size_t)1 << 20), hwant = std::max(hneed * 2, (size_t)1 << 16);
+      if (hipMalloc((void**)&dbuf, want) != hipSuccess ||
+          hipHostMalloc((void**)&hbuf, hwant, hipHostMallocDefault) != hipSuccess ||
+          hipHostGetDevicePointer((void**)&hdev, hbuf, 0) != hipSuccess) {
         (void)hipGetLastError();
-        cap = 0;
-        set_error("hipMalloc failed for the ranker buffer");
+        set_error("allocation failed for the ranker buffers");
         return OBBV_ERR_OOM;
       }
+      cap = want;
+      hcap = hwant;
     }
-    hb.assign(np, obbv_box{});
-    for (size_t i = 0; i < n; ++i) {
-      std::memcpy(hb[i].center, boxes[i].c, 12);
-      std::memcpy(hb[i].axes, boxes[i].Q, 36);
-      std::memcpy(hb[i].half, boxes[i].h, 12);
+    obbv_box* hb = (obbv_box*)hbuf;
+    for (size_t i = 0; i < np; ++i) {
+      if (i < n) {
+        std::memcpy(hb[i].center, boxes[i].c, 12);
+        std::memcpy(hb[i].axes, boxes[i].Q, 36);
+        std::memcpy(hb[i].half, boxes[i].h, 12);
+      } else {
+        std::memset(&hb[i], 0, sizeof(obbv_box));
+      }
     }
     obbv_box* db = (obbv_box*)dbuf;
-    float* X = (float*)(dbuf + ((np * sizeof(obbv_box) + 255) & ~(size_t)255));
-    float* f = X + np * 544;
-    OBBV_HIP(hipMemcpyAsync(db, hb.data(), np * sizeof(obbv_box), hipMemcpyHostToDevice, stream));
+    float* X = (float*)(dbuf + o_f);
+    OBBV_HIP(hipMemcpyAsync(db, hbuf, np * sizeof(obbv_box), hipMemcpyHostToDevice, stream));
     const int rc = obbv_sample_features(cfg.volume, cfg.N, cfg.frame, db, (int32_t)np, X, stream);
     if (rc != OBBV_OK) return rc;
-    OBBV_RET(mlp_forward_impl(cfg.mlp_params, X, (int32_t)np, f, stream));
-    hf.resize(np);
-    OBBV_HIP(hipMemcpyAsync(hf.data(), f, np * 4, hipMemcpyDeviceToHost, stream));
+    OBBV_RET(mlp_forward_impl(cfg.mlp_params, X, (int32_t)np, (float*)(hdev + o_f), stream));
     OBBV_HIP(hipStreamSynchronize(stream));
-    std::copy(hf.begin(), hf.begin() + n, out.begin());
+    std::memcpy(out.data(), hbuf + o_f, n * 4);
     predicted += (int64_t)n;
     return OBBV_OK;
   }
@@ -505,9 +585,11 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       if (eb[e] >= 0) push_neighbours(e);
 
   // Boxes that grew at the end of a round to a size none of their evaluated
-  // candidates had: their outer volume is evaluated with the next round's
-  // candidates (one device call per round; the values are the same).
+  // candidates had: their outer volume is evaluated with the next round that
+  // evaluates candidates (one device call per round; the values are the same).
   std::vector<int32_t> stale;
+  std::vector<char> is_stale(boxes.size(), 0);
+  int64_t round_no = 0;
   auto flush_stale = [&]() -> int {
     if (stale.empty()) return OBBV_OK;
     req_boxes.clear();
@@ -518,7 +600,10 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     }
     OBBV_RET(ev.eval(req_boxes, req_keys, vals));
     cnt.evals += (int64_t)vals.size();
-    for (size_t x = 0; x < stale.size(); ++x) obv[stale[x]] = vals[x];
+    for (size_t x = 0; x < stale.size(); ++x) {
+      obv[stale[x]] = vals[x];
+      is_stale[stale[x]] = 0;
+    }
     stale.clear();
     return OBBV_OK;
   };
@@ -579,7 +664,10 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     std::vector<double> dpred(cands.size(), 0.0);
     std::vector<char> predicted_c(cands.size(), 0);
     std::vector<float> fcand;  // prediction of each kept candidate (judge)
-    if (pred && pred->on && !pred->paused && !cidx.empty()) {
+    const bool ranked = pred && pred->on && !pred->paused && !cidx.empty();
+    const bool judge_round = ranked && round_no % std::max(1, pred->cfg.judge_every) == 0;
+    ++round_no;
+    if (ranked) {
       std::vector<HBox> pb = cb;
       std::vector<int32_t> cur_of((size_t)boxes.size(), -1);
       for (int32_t x : cidx) {
@@ -603,13 +691,16 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         predicted_c[cidx[z]] = 1;
         per_box[bi].push_back({dpred[cidx[z]], z});
       }
-      std::vector<char> keep(cidx.size(), 0);
-      const size_t top = (size_t)std::max(1, pred->cfg.verify_top);
-      for (auto& v : per_box) {
-        if (v.empty()) continue;
-        std::sort(v.begin(), v.end());
-        for (size_t q = 0; q < std::min(top, v.size()); ++q) keep[v[q].second] = 1;
-      }
+      // a judge round evaluates every candidate; other rounds the verify_top
+      // smallest predicted changes of every receiving box
+      std::vector<char> keep(cidx.size(), judge_round ? 1 : 0);
+      const size_t top = (size_t)std::max(0, pred->cfg.verify_top);
+      if (!judge_round)
+        for (auto& v : per_box) {
+          if (v.empty()) continue;
+          std::sort(v.begin(), v.end());
+          for (size_t q = 0; q < std::min(top, v.size()); ++q) keep[v[q].second] = 1;
+        }
       std::vector<HBox> rb;
       std::vector<uint32_t> rk;
       std::vector<int32_t> ri;
@@ -624,20 +715,27 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       ck.swap(rk);
       cidx.swap(ri);
     }
-    // one device call: the stale boxes of the last round, then the candidates
-    const size_t ns = stale.size();
+    // one device call, if any candidate needs an exact value: the stale boxes
+    // (their exact volumes enter the exact changes), then the candidates
+    const size_t ns = cb.empty() ? 0 : stale.size();
     req_boxes.clear();
     req_keys.clear();
-    for (int bi : stale) {
-      req_boxes.push_back(boxes[bi]);
-      req_keys.push_back(slot[bi]);
+    vals.clear();
+    if (!cb.empty()) {
+      for (int bi : stale) {
+        req_boxes.push_back(boxes[bi]);
+        req_keys.push_back(slot[bi]);
+      }
+      req_boxes.insert(req_boxes.end(), cb.begin(), cb.end());
+      req_keys.insert(req_keys.end(), ck.begin(), ck.end());
+      OBBV_RET(ev.eval(req_boxes, req_keys, vals));
+      cnt.evals += (int64_t)vals.size();
+      for (size_t x = 0; x < ns; ++x) {
+        obv[stale[x]] = vals[x];
+        is_stale[stale[x]] = 0;
+      }
+      stale.clear();
     }
-    req_boxes.insert(req_boxes.end(), cb.begin(), cb.end());
-    req_keys.insert(req_keys.end(), ck.begin(), ck.end());
-    OBBV_RET(ev.eval(req_boxes, req_keys, vals));
-    cnt.evals += (int64_t)vals.size();
-    for (size_t x = 0; x < ns; ++x) obv[stale[x]] = vals[x];
-    stale.clear();
     std::vector<char> evaluated(cands.size(), 0);
     for (size_t x = 0; x < cidx.size(); ++x) {
       cands[cidx[x]].val = vals[ns + x];
@@ -702,7 +800,10 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
           found = true;
           break;
         }
-      if (!found) stale.push_back(bi);
+      if (!found && !is_stale[bi]) {
+        is_stale[bi] = 1;
+        stale.push_back(bi);
+      }
     }
     return OBBV_OK;
   };
@@ -1031,7 +1132,7 @@ extern "C" int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* su
     return OBBV_OK;
   }
   OBBV_ARG(sur->mlp_params && sur->volume && sur->frame, "surrogate arrays are NULL");
-  OBBV_ARG(sur->N >= 1 && sur->verify_top >= 1 && sur->reserved == 0, "bad surrogate sizes");
+  OBBV_ARG(sur->N >= 1 && sur->verify_top >= 0 && sur->judge_every >= 1, "bad surrogate sizes");
   S.pred.cfg = *sur;
   S.pred.on = true;
   S.pred.paused = false;
@@ -1074,10 +1175,10 @@ extern "C" int obbv_lloyd_record(obbv_lloyd* st, int64_t cap) {
   OBBV_ARG(st, "NULL state");
   OBBV_ARG(cap >= 0, "cap must be >= 0");
   LloydState& S = *reinterpret_cast<LloydState*>(st);
-  S.ev.rec_cap = cap;
-  S.ev.rec_seen = 0;
-  S.ev.rec_box.clear();
-  S.ev.rec_val.clear();
+  S.ev.smp_cap = cap;
+  S.ev.smp_seen = 0;
+  S.ev.smp_box.clear();
+  S.ev.smp_val.clear();
   return OBBV_OK;
 }
 
@@ -1085,18 +1186,18 @@ extern "C" int obbv_lloyd_take_records(obbv_lloyd* st, int64_t max_n, float* box
   clear_error();
   OBBV_ARG(st && n_out, "NULL argument");
   LloydState& S = *reinterpret_cast<LloydState*>(st);
-  const int64_t n = std::min<int64_t>(max_n, (int64_t)S.ev.rec_box.size());
+  const int64_t n = std::min<int64_t>(max_n, (int64_t)S.ev.smp_box.size());
   OBBV_ARG(n == 0 || (boxes && obv), "NULL output arrays");
   for (int64_t i = 0; i < n; ++i) {
-    std::memcpy(boxes + 15 * i, S.ev.rec_box[i].c, 12);
-    std::memcpy(boxes + 15 * i + 3, S.ev.rec_box[i].Q, 36);
-    std::memcpy(boxes + 15 * i + 12, S.ev.rec_box[i].h, 12);
-    obv[i] = S.ev.rec_val[i];
+    std::memcpy(boxes + 15 * i, S.ev.smp_box[i].c, 12);
+    std::memcpy(boxes + 15 * i + 3, S.ev.smp_box[i].Q, 36);
+    std::memcpy(boxes + 15 * i + 12, S.ev.smp_box[i].h, 12);
+    obv[i] = S.ev.smp_val[i];
   }
   *n_out = n;
-  S.ev.rec_seen = 0;
-  S.ev.rec_box.clear();
-  S.ev.rec_val.clear();
+  S.ev.smp_seen = 0;
+  S.ev.smp_box.clear();
+  S.ev.smp_val.clear();
   return OBBV_OK;
 }
 

@@ -32,14 +32,16 @@ __device__ inline short f2bf(float x) {
 }
 __device__ inline float bf(float x) { return __uint_as_float(((uint32_t)(uint16_t)f2bf(x)) << 16); }
 
-// C[m, n] (+)= sum_k bf16(A[m, k]) bf16(B[k, n]) with arbitrary element strides.
+// C[m, n] (+)= sum_k bf16(A[m, k]) bf16(B[k, n]) with arbitrary element strides;
+// with `bias` (forward layers) C[m, n] = max(sum + bias[n], 0) instead.
 // One wave per 32 x 32 tile of C; M, N multiples of 32, K a multiple of 8.
 // MFMA 32x32x8 operand layout: lane l holds A[l % 32][4 (l / 32) + j] and
 // B[4 (l / 32) + j][l % 32], j = 0..3; result register r of lane l is
 // C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 __global__ void __launch_bounds__(64)
 k_gemm(const float* __restrict__ A, int64_t sam, int64_t sak, const float* __restrict__ B, int64_t sbk,
-       int64_t sbn, float* __restrict__ C, int64_t scm, int64_t scn, int M, int N, int K, int accumulate) {
+       int64_t sbn, float* __restrict__ C, int64_t scm, int64_t scn, int M, int N, int K, int accumulate,
+       const float* __restrict__ bias) {
   const int tiles_n = N / 32;
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - (blockIdx.x / tiles_n) * tiles_n;
   const int lane = threadIdx.x;
@@ -60,27 +62,23 @@ k_gemm(const float* __restrict__ A, int64_t sam, int64_t sak, const float* __res
     const int64_t row = (int64_t)tm * 32 + 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4);
     const int64_t col = (int64_t)tn * 32 + (lane & 31);
     float* c = C + row * scm + col * scn;
-    *c = accumulate ? *c + acc[rr] : acc[rr];
+    if (bias)
+      *c = fmaxf(acc[rr] + bias[col], 0.f);
+    else
+      *c = accumulate ? *c + acc[rr] : acc[rr];
   }
 }
 
 int gemm(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C, int64_t scm,
-         int64_t scn, int M, int N, int K, bool accumulate, hipStream_t s) {
+         int64_t scn, int M, int N, int K, bool accumulate, hipStream_t s, const float* bias_relu = nullptr) {
   if (M % 32 || N % 32 || K % 8) {
     set_error("MLP product sizes must be multiples of 32 (M, N) and 8 (K)");
     return OBBV_ERR_INVALID_ARG;
   }
   hipLaunchKernelGGL(k_gemm, dim3((unsigned)((M / 32) * (N / 32))), dim3(64), 0, s, A, sam, sak, B, sbk, sbn, C, scm,
-                     scn, M, N, K, accumulate ? 1 : 0);
+                     scn, M, N, K, accumulate ? 1 : 0, bias_relu);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
-}
-
-// H = relu(Z + b) in place, rows of width w
-__global__ void k_bias_relu(float* __restrict__ Z, const float* __restrict__ b, int64_t n, int w) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * w) return;
-  Z[i] = fmaxf(Z[i] + b[i % w], 0.f);
 }
 
 // z = bf16(H2) . bf16(w3) + b3; the output corrects the occupancy estimate
@@ -194,10 +192,8 @@ int mlp_scratch(int n, MlpScratch& S) {
 inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 int forward(const float* P, const float* X, int n, MlpScratch& S, float* out_f, const float* t, hipStream_t s) {
-  OBBV_RET(gemm(X, kIn, 1, P + oW1, kH, 1, S.H1, kH, 1, n, kH, kIn, false, s));
-  hipLaunchKernelGGL(k_bias_relu, dim3(blocks((int64_t)n * kH, 256)), dim3(256), 0, s, S.H1, P + ob1, (int64_t)n, kH);
-  OBBV_RET(gemm(S.H1, kH, 1, P + oW2, kH, 1, S.H2, kH, 1, n, kH, kH, false, s));
-  hipLaunchKernelGGL(k_bias_relu, dim3(blocks((int64_t)n * kH, 256)), dim3(256), 0, s, S.H2, P + ob2, (int64_t)n, kH);
+  OBBV_RET(gemm(X, kIn, 1, P + oW1, kH, 1, S.H1, kH, 1, n, kH, kIn, false, s, P + ob1));
+  OBBV_RET(gemm(S.H1, kH, 1, P + oW2, kH, 1, S.H2, kH, 1, n, kH, kH, false, s, P + ob2));
   if (t) OBBV_HIP(hipMemsetAsync(S.loss, 0, 4, s));
   hipLaunchKernelGGL(k_head, dim3(blocks(n, 256)), dim3(256), 0, s, S.H2, P, X, n, out_f, t, S.dz, S.loss);
   OBBV_HIP(hipGetLastError());

@@ -3,10 +3,14 @@
 // crossing sum along each ray (Sec. 4.1, Eq. 9 generalised to a line).
 //
 // Pipeline per call (all on one stream):
+//   [k_frame_cull x 2]   boxes grouped by shared centre and axes: the frame-local
+//                        coordinates of the triangles each group can see
 //   k_box_chunks + scan  work list of (box, 256-triangle chunk) items
-//   k_cull_count         per (box, cast axis): triangles in the half prism above
-//                        the slab bottom and below the slab top (ballot counts)
-//   k_choose_side        keep the half prism with fewer triangles (mirror flag)
+//   k_cull_count         per item and cast axis: triangles in the half prism above
+//                        the slab bottom and below the slab top (ballot counts
+//                        summed per block; no shared global counters)
+//   k_box_sides          keep the half prism with fewer triangles (mirror flag);
+//                        per-item record offsets (scan over the box's items)
 //   k_tile_count         per (box, axis, ray tile): number of binned triangles
 //   scans                record offsets, bin offsets  (one host sync: sizes)
 //   k_write              per kept triangle: a 64-byte test record (edge and depth
@@ -267,26 +271,31 @@ __global__ void k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev
   nch[b] = (int32_t)((n + kCullThreads - 1) / kCullThreads);
 }
 
+// Per-wave ballot counts of a 256-thread block, summed in LDS: every block
+// writes its own counts (no global atomics on shared counters, which serialise).
+constexpr int kCullWaves = kCullThreads / 64;
+
 // Shared frames: boxes with the same centre and axes see every triangle at the
 // same local coordinates, and a triangle can matter to one of them only if it
 // projects into a face of their union (the frame box, with the largest half
-// extents).  One pass per (frame, triangle) lists those triangles; with
-// `list_off` NULL it only counts them.  The list order is irrelevant: every
-// later sum is an exact integer.
+// extents).  Items are (frame, 256-triangle chunk).  With item_off NULL the pass
+// writes each item's count of such triangles; otherwise it writes their
+// frame-local coordinates at list_off[frame] + item_off[item] + rank (in
+// triangle order).
 __global__ void __launch_bounds__(kCullThreads)
 k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, uint32_t axis_mask, int nch,
-             int32_t* __restrict__ cnt, const int64_t* __restrict__ list_off, int32_t* __restrict__ cur,
-             float4* __restrict__ list_P, uint32_t* status) {
+             int32_t* __restrict__ item_cnt, const int32_t* __restrict__ item_off,
+             const int64_t* __restrict__ list_off, float4* __restrict__ list_P, uint32_t* status) {
+  __shared__ int32_t wc[kCullWaves];
   const int64_t total = (int64_t)n_frames * nch;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int fr = (int)(item / nch);
     const int t = (int)(item - (int64_t)fr * nch) * kCullThreads + threadIdx.x;
     const BoxRegs B = load_box(frames, fr);
-    if (box_state(B) != 0) continue;
     float P[3][3];
     bool keep = false;
-    if (t < M.nt && load_tri_local(M, t, B, P, status)) {
+    if (box_state(B) == 0 && t < M.nt && load_tri_local(M, t, B, P, status)) {
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
         if (!((axis_mask >> w) & 1u)) continue;
@@ -295,18 +304,18 @@ k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, uint3
       }
     }
     const uint64_t m = __ballot(keep);
-    if (m == 0) continue;
-    const int leader = __ffsll((long long)m) - 1;
-    if (!list_off) {
-      if (lane == leader) atomicAdd(&cnt[fr], (int)__popcll(m));
-      continue;
-    }
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&cur[fr], (int)__popcll(m));
-    base = __shfl(base, leader);
-    if (keep) {
-      const int pos = base + (int)__popcll(m & ((1ull << lane) - 1ull));
-      if (pos < cnt[fr]) {
+    if (lane == 0) wc[wave] = (int)__popcll(m);
+    __syncthreads();
+    if (!item_off) {
+      if (threadIdx.x == 0) {
+        int c = 0;
+        for (int v = 0; v < kCullWaves; ++v) c += wc[v];
+        item_cnt[item] = c;
+      }
+    } else if (keep) {
+      int pos = item_off[item] + (int)__popcll(m & ((1ull << lane) - 1ull));
+      for (int v = 0; v < wave; ++v) pos += wc[v];
+      if (pos < item_off[item] + item_cnt[item]) {
         float4* q = list_P + 3 * (list_off[fr] + pos);
         q[0] = make_float4(P[0][0], P[0][1], P[0][2], P[1][0]);
         q[1] = make_float4(P[1][1], P[1][2], P[2][0], P[2][1]);
@@ -315,30 +324,60 @@ k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, uint3
         atomicOr(status, OBBV_STATUS_BAD_INDEX);
       }
     }
+    __syncthreads();
   }
+}
+
+// One wave per group of consecutive items [first(g), first(g + 1)): exclusive
+// scan of the groups' item counts (column `col` of `ncol`) into item_off, and
+// the group total.  Groups are frames (first(g) = g * per) or boxes (first =
+// chunk_off).
+__device__ inline int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(v, off);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+__global__ void k_frame_scan(const int32_t* __restrict__ item_cnt, int n_frames, int per,
+                             int32_t* __restrict__ item_off, int32_t* __restrict__ frame_cnt) {
+  const int g = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= n_frames) return;
+  const int64_t i0 = (int64_t)g * per, i1 = i0 + per;
+  int base = 0;
+  for (int64_t i = i0; i < i1; i += 64) {
+    const int v = i + lane < i1 ? item_cnt[i + lane] : 0;
+    const int inc = wave_incl_scan(v, lane);
+    if (i + lane < i1) item_off[i + lane] = base + inc - v;
+    base += __shfl(inc, 63);
+  }
+  if (lane == 0) frame_cnt[g] = base;
 }
 
 // Which prism(s) the triangle belongs to, per cast axis.
 //   above: projects into the face and reaches above the slab bottom (z_max > -h)
 //   below: projects into the face and reaches below the slab top   (z_min <  h)
 __global__ void __launch_bounds__(kCullThreads)
-k_cull_count(CullArgs a, int32_t* __restrict__ side_cnt) {
+k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt) {
+  __shared__ int32_t wc[kCullWaves][6];
   const int64_t total = a.chunk_off[a.n_boxes];
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item_box(a.chunk_off, a.n_boxes, item);
     const BoxRegs B = load_box(a.boxes, b);
-    if (box_state(B) != 0) continue;
+    const bool valid = box_state(B) == 0;
     const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    const bool ok = cull_tri(a, b, M, B, t, P);
+    const bool ok = valid && cull_tri(a, b, M, B, t, P);
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
-      if (!((a.axis_mask >> w) & 1u)) continue;
-      const CastFrame f = cast_frame(B, w, a.R);
       bool ka = false, kb = false;
-      if (ok) {
+      if (ok && ((a.axis_mask >> w) & 1u)) {
+        const CastFrame f = cast_frame(B, w, a.R);
         const CastTri tr = cast_tri(P, w, f, false);
         if (projects_into_face(tr, f)) {
           const float zmin = fminf(fminf(tr.z[0], tr.z[1]), tr.z[2]);
@@ -349,21 +388,53 @@ k_cull_count(CullArgs a, int32_t* __restrict__ side_cnt) {
       }
       const uint64_t ma = __ballot(ka), mb = __ballot(kb);
       if (lane == 0) {
-        if (ma) atomicAdd(&side_cnt[(b * 3 + w) * 2 + 0], (int)__popcll(ma));
-        if (mb) atomicAdd(&side_cnt[(b * 3 + w) * 2 + 1], (int)__popcll(mb));
+        wc[wave][2 * w + 0] = (int)__popcll(ma);
+        wc[wave][2 * w + 1] = (int)__popcll(mb);
       }
     }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      int c = 0;
+      for (int v = 0; v < kCullWaves; ++v) c += wc[v][threadIdx.x];
+      item_cnt[6 * item + threadIdx.x] = c;
+    }
+    __syncthreads();
   }
 }
 
-__global__ void k_choose_side(const int32_t* __restrict__ side_cnt, int nbw, int32_t* __restrict__ side,
-                              int32_t* __restrict__ rec_cnt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nbw) return;
-  const int up = side_cnt[2 * i + 0], dn = side_cnt[2 * i + 1];
+// One wave per (box, cast axis): the triangle counts of both half prisms, the
+// side with fewer triangles (mirror flag), its record count, and every item's
+// first record within the (box, axis) (exclusive scan over the box's items).
+__global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, const int32_t* __restrict__ item_cnt,
+                            int32_t* __restrict__ side, int32_t* __restrict__ rec_cnt,
+                            int32_t* __restrict__ item_off) {
+  const int bw = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (bw >= 3 * n_boxes) return;
+  const int b = bw / 3, w = bw - 3 * b;
+  const int64_t i0 = chunk_off[b], i1 = chunk_off[b + 1];
+  int up = 0, dn = 0;
+  for (int64_t i = i0 + lane; i < i1; i += 64) {
+    up += item_cnt[6 * i + 2 * w];
+    dn += item_cnt[6 * i + 2 * w + 1];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    up += __shfl_xor(up, off);
+    dn += __shfl_xor(dn, off);
+  }
   const int mirror = dn < up ? 1 : 0;
-  side[i] = mirror;
-  rec_cnt[i] = mirror ? dn : up;
+  if (lane == 0) {
+    side[bw] = mirror;
+    rec_cnt[bw] = mirror ? dn : up;
+  }
+  int base = 0;
+  for (int64_t i = i0; i < i1; i += 64) {
+    const int v = i + lane < i1 ? item_cnt[6 * (i + lane) + 2 * w + mirror] : 0;
+    const int inc = wave_incl_scan(v, lane);
+    if (i + lane < i1) item_off[3 * (i + lane) + w] = base + inc - v;
+    base += __shfl(inc, 63);
+  }
 }
 
 // Work items of the test pass: every non-empty tile bin is cut into chunks of at
@@ -492,38 +563,49 @@ __device__ inline void make_record(const CastTri& t, bool mirror, float hw, floa
 // not matter: the ray sums are exact integers).
 __global__ void __launch_bounds__(kCullThreads)
 k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict__ rec_off,
-        const int32_t* __restrict__ rec_cnt, int32_t* __restrict__ rec_cur, const int64_t* __restrict__ bin_off,
-        int32_t* __restrict__ bin_cur, float4* __restrict__ recs, int32_t* __restrict__ bins) {
+        const int32_t* __restrict__ rec_cnt, const int32_t* __restrict__ item_off,
+        const int64_t* __restrict__ bin_off, int32_t* __restrict__ bin_cur, float4* __restrict__ recs,
+        int32_t* __restrict__ bins) {
   __shared__ int32_t cnt[kLdsTiles];
   __shared__ int32_t base_pos[kLdsTiles];
+  __shared__ int32_t wc[kCullWaves][3];
   const int64_t total = a.chunk_off[a.n_boxes];
   const int TT = a.tpe * a.tpe;
   const bool lds = 3 * TT <= kLdsTiles;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item_box(a.chunk_off, a.n_boxes, item);
     const BoxRegs B = load_box(a.boxes, b);
-    if (box_state(B) != 0) continue;
+    const bool valid = box_state(B) == 0;
     const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    const bool ok = cull_tri(a, b, M, B, t, P);
-    if (lds) {
-      // pass 1: count this item's entries per tile
+    const bool ok = valid && cull_tri(a, b, M, B, t, P);
+    // pass 1: kept flags, per-wave record counts, and (in LDS) per-tile entry counts
+    if (lds)
       for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) cnt[k] = 0;
-      __syncthreads();
-      if (ok)
-        for (int w = 0; w < 3; ++w) {
-          if (!((a.axis_mask >> w) & 1u)) continue;
-          const CastFrame f = cast_frame(B, w, a.R);
-          const CastTri tr = cast_tri(P, w, f, side[b * 3 + w] != 0);
-          if (!kept(tr, f)) continue;
+    __syncthreads();
+    uint32_t keepmask = 0;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      bool keep = false;
+      if (ok && ((a.axis_mask >> w) & 1u)) {
+        const CastFrame f = cast_frame(B, w, a.R);
+        const CastTri tr = cast_tri(P, w, f, side[b * 3 + w] != 0);
+        keep = kept(tr, f);
+        if (keep && lds) {
           int ti0, ti1, tj0, tj1;
           tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
           for (int tj = tj0; tj <= tj1; ++tj)
             for (int ti = ti0; ti <= ti1; ++ti) atomicAdd(&cnt[w * TT + tj * a.tpe + ti], 1);
         }
-      __syncthreads();
+      }
+      keepmask |= keep ? (1u << w) : 0u;
+      const uint64_t m = __ballot(keep);
+      if (lane == 0) wc[wave][w] = (int)__popcll(m);
+    }
+    __syncthreads();
+    if (lds) {
       // reserve one range per non-zero tile
       for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) {
         const int c = cnt[k];
@@ -532,31 +614,23 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
       }
       __syncthreads();
     }
+    // pass 2: records at their deterministic slots, bin entries
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
-      if (!((a.axis_mask >> w) & 1u)) continue;
+      const bool keep = (keepmask >> w) & 1u;
+      const uint64_t m = __ballot(keep);
+      if (!keep) continue;
       const int bw = b * 3 + w;
       const bool mirror = side[bw] != 0;
       const CastFrame f = cast_frame(B, w, a.R);
-      CastTri tr;
-      bool keep = false;
-      if (ok) {
-        tr = cast_tri(P, w, f, mirror);
-        keep = kept(tr, f);
-      }
-      // wave-aggregated slot reservation: ballot + prefix popcount, one atomic per wave
-      const uint64_t m = __ballot(keep);
-      if (m == 0) continue;
-      int base = 0;
-      if (lane == __ffsll((long long)m) - 1) base = atomicAdd(&rec_cur[bw], (int)__popcll(m));
-      base = __shfl(base, __ffsll((long long)m) - 1);
-      if (!keep) continue;
-      const int rank = (int)__popcll(m & ((1ull << lane) - 1ull));
-      if (base + rank >= rec_cnt[bw]) {  // count and write passes disagree: never expected
+      const CastTri tr = cast_tri(P, w, f, mirror);
+      int rank = item_off[3 * item + w] + (int)__popcll(m & ((1ull << lane) - 1ull));
+      for (int v = 0; v < wave; ++v) rank += wc[v][w];
+      if (rank >= rec_cnt[bw]) {  // count and write passes disagree: never expected
         atomicOr(a.status, OBBV_STATUS_BAD_INDEX);
         continue;
       }
-      const int64_t slot = rec_off[bw] + base + rank;
+      const int64_t slot = rec_off[bw] + rank;
       if (slot >= a.rec_cap) {  // more records than a planned launch was sized for
         atomicOr(a.status, OBBV_STATUS_OVERFLOW);
         continue;
@@ -578,7 +652,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
             atomicOr(a.status, OBBV_STATUS_BAD_INDEX);
         }
     }
-    if (lds) __syncthreads();  // cnt / base_pos are reused by the next item
+    __syncthreads();  // cnt / base_pos / wc are reused by the next item
   }
 }
 
@@ -771,6 +845,19 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
   if (lane == 0 && lane_sum != 0) atomicAdd(&a.acc[bw], (unsigned long long)lane_sum);
 }
 
+// The call's status bits and totals, written (vector stores) to the caller's
+// mapped host memory.
+__global__ void k_publish(const int64_t* __restrict__ rec, const int64_t* __restrict__ bin,
+                          const int64_t* __restrict__ items, const uint32_t* __restrict__ status,
+                          int64_t* __restrict__ out) {
+  out[0] = (int64_t)*status;
+  out[1] = *rec;
+  out[2] = *bin;
+  out[3] = *items;
+}
+
+__global__ void k_or_word(uint32_t* __restrict__ w, uint32_t bits) { atomicOr(w, bits); }
+
 __global__ void k_finalize(const obbv_box* __restrict__ boxes, int n_boxes, int R, uint32_t axis_mask,
                            const unsigned long long* __restrict__ acc, double* __restrict__ out_obv,
                            double* __restrict__ out_vin_axis, uint32_t* status) {
@@ -823,19 +910,6 @@ int pinned_totals(int64_t** out) {
 }
 
 }  // namespace
-
-// How one evaluation is executed: the synchronous path sizes scratch from the
-// device counts (one host round trip); a planned launch uses fixed scratch and
-// never returns to the host, so it can be captured into a HIP graph.
-struct OvExec {
-  bool planned = false;
-  char* meta = nullptr;
-  size_t meta_cap = 0, meta_bytes = 0;
-  float4* recs = nullptr;
-  int32_t* bins = nullptr;
-  int64_t rec_cap = 0, bin_cap = 0, item_cap = 0;
-  int64_t n_rec = 0, n_bin = 0, n_items = 0;  // counts of the last synchronous run
-};
 
 namespace {
 
@@ -902,6 +976,8 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   const int R = params->R;
   const int TE = out_occ ? 8 : (params->tile ? params->tile : (R >= 48 ? 16 : 8));
   const bool planned = ex && ex->planned;
+  const bool capped = ex && ex->capped && !planned;
+  const bool fixed = planned || capped;  // scratch capacities fixed: no host round trip
   OBBV_ARG(!out_occ || (R == 8 && mask == 4u), "occupancy needs R = 8 and axis_mask = 4");
   OBBV_ARG(!sf || (n_meshes == 1 && !planned && sf->n_frames >= 1 && sf->n_frames <= n_boxes),
            "shared frames need one mesh, an unplanned call and 1..n_boxes frames");
@@ -913,6 +989,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
 
   uint32_t* status = nullptr;
   OBBV_RET(status_word(&status));
+  if (ex && ex->status) status = ex->status;
 
   // ---- meta scratch layout ----
   size_t off = 0;
@@ -932,14 +1009,11 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   const size_t o_nchunk = take(4 * (size_t)(nbw * TT));
   const size_t o_chunkoff = take(8 * (size_t)(nbw * TT + 1));
   const size_t o_zero0 = off;  // zero-initialised block
-  const size_t o_sidecnt = take(4 * (size_t)nbw * 2);
-  const size_t o_reccur = take(4 * (size_t)nbw);
   const size_t o_tilecnt = take(4 * (size_t)(nbw * TT));
   const size_t o_bincur = take(4 * (size_t)(nbw * TT));
   const size_t o_acc = take(8 * (size_t)nbw);
-  const size_t o_fcnt = take(4 * (size_t)n_frames);
-  const size_t o_fcur = take(4 * (size_t)n_frames);
   const size_t o_zero1 = off;
+  const size_t o_fcnt = take(4 * (size_t)n_frames);
   const size_t o_foff = take(8 * (size_t)(n_frames + 1));
   const size_t scan_bytes =
       std::max(exclusive_scan_scratch_bytes(nbw * TT), exclusive_scan_scratch_bytes(std::max<int64_t>(nbw, n_boxes)));
@@ -965,16 +1039,36 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   int64_t* d_binoff = (int64_t*)(meta + o_binoff);
   int32_t* d_nchunk = (int32_t*)(meta + o_nchunk);
   int64_t* d_chunkoff = (int64_t*)(meta + o_chunkoff);
-  int32_t* d_sidecnt = (int32_t*)(meta + o_sidecnt);
-  int32_t* d_reccur = (int32_t*)(meta + o_reccur);
   int32_t* d_tilecnt = (int32_t*)(meta + o_tilecnt);
   int32_t* d_bincur = (int32_t*)(meta + o_bincur);
   unsigned long long* d_acc = (unsigned long long*)(meta + o_acc);
   int32_t* d_blist = sf ? (int32_t*)(meta + o_blist) : nullptr;
   int32_t* d_fcnt = (int32_t*)(meta + o_fcnt);
-  int32_t* d_fcur = (int32_t*)(meta + o_fcur);
   int64_t* d_foff = (int64_t*)(meta + o_foff);
   void* d_scan = meta + o_scan;
+
+  // per-item counts and offsets of the cull passes (every entry is written)
+  const int64_t items_bound = (int64_t)n_boxes * ceil_div(std::max(max_nt, 1), kCullThreads);
+  const int64_t fitems = sf ? (int64_t)n_frames * ceil_div(std::max(meshes[0].n_triangles, 1), kCullThreads) : 0;
+  const size_t items_bytes = align_up(24 * (size_t)items_bound) + align_up(12 * (size_t)items_bound) +
+                             2 * align_up(4 * (size_t)fitems);
+  char* items = nullptr;
+  if (planned) {
+    if (items_bytes > ex->items_cap) {
+      set_error("planned scratch too small for this call");
+      return OBBV_ERR_WORKSPACE;
+    }
+    items = ex->items;
+  } else {
+    void* iv = nullptr;
+    OBBV_RET(pool_get(kPoolItems, items_bytes, &iv));
+    items = (char*)iv;
+  }
+  if (ex) ex->items_bytes = items_bytes;
+  int32_t* d_icnt = (int32_t*)items;
+  int32_t* d_ioff = (int32_t*)(items + align_up(24 * (size_t)items_bound));
+  int32_t* d_ficnt = (int32_t*)((char*)d_ioff + align_up(12 * (size_t)items_bound));
+  int32_t* d_fioff = (int32_t*)((char*)d_ficnt + align_up(4 * (size_t)fitems));
 
   if (!planned) OBBV_HIP(hipMemcpyAsync(d_mesh, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_fill_zero, dim3(256), dim3(256), 0, s, (uint32_t*)(meta + o_zero0),
@@ -986,7 +1080,10 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     const int nch = ceil_div(std::max(nt, 1), kCullThreads);
     const unsigned fgrid = (unsigned)std::min<int64_t>((int64_t)n_frames * nch, 256 * 16);
     hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], mask,
-                       nch, d_fcnt, (const int64_t*)nullptr, (int32_t*)nullptr, (float4*)nullptr, status);
+                       nch, d_ficnt, (const int32_t*)nullptr, (const int64_t*)nullptr, (float4*)nullptr, status);
+    OBBV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_frame_scan, dim3(ceil_div(n_frames, kCullWaves)), dim3(kCullThreads), 0, s,
+                       (const int32_t*)d_ficnt, n_frames, nch, d_fioff, d_fcnt);
     OBBV_HIP(hipGetLastError());
     OBBV_RET(exclusive_scan_i32_to_i64(d_fcnt, d_foff, n_frames, d_scan, scan_bytes, s));
     int64_t bound = (int64_t)n_frames * nt;
@@ -1001,7 +1098,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     OBBV_RET(pool_get(kPoolLists, (size_t)std::max<int64_t>(bound, 1) * 48, &lv));
     d_listP = (float4*)lv;
     hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], mask,
-                       nch, d_fcnt, (const int64_t*)d_foff, d_fcur, d_listP, status);
+                       nch, d_ficnt, (const int32_t*)d_fioff, (const int64_t*)d_foff, d_listP, status);
     OBBV_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_box_chunks, dim3(ceil_div(n_boxes, 256)), dim3(256), 0, s, box_mesh, d_mesh,
@@ -1021,18 +1118,17 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   ca.tpe = tpe;
   ca.axis_mask = mask;
   ca.status = status;
-  ca.rec_cap = planned ? ex->rec_cap : INT64_MAX;
-  ca.bin_cap = planned ? ex->bin_cap : INT64_MAX;
+  ca.rec_cap = fixed ? ex->rec_cap : INT64_MAX;
+  ca.bin_cap = fixed ? ex->bin_cap : INT64_MAX;
   ca.list_P = d_listP;
   ca.list_off = sf ? d_foff : nullptr;
   ca.box_list = d_blist;
-  const int64_t items_bound = (int64_t)n_boxes * ceil_div(std::max(max_nt, 1), kCullThreads);
   const unsigned cull_grid = (unsigned)std::min<int64_t>(items_bound, 256 * 16);
 
-  hipLaunchKernelGGL(k_cull_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_sidecnt);
+  hipLaunchKernelGGL(k_cull_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_icnt);
   OBBV_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_choose_side, dim3(ceil_div(nbw, 256)), dim3(256), 0, s, d_sidecnt, (int)nbw,
-                     d_side, d_reccnt);
+  hipLaunchKernelGGL(k_box_sides, dim3(ceil_div(nbw, kCullWaves)), dim3(kCullThreads), 0, s,
+                     (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, d_ioff);
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_tile_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_tilecnt);
   OBBV_HIP(hipGetLastError());
@@ -1045,7 +1141,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   OBBV_RET(exclusive_scan_i32_to_i64(d_nchunk, d_chunkoff, nbw * TT, d_scan, scan_bytes, s));
 
   int64_t n_rec, n_bin, n_items;
-  if (planned) {  // no host round trip: capacities were fixed when the launch was planned
+  if (fixed) {  // no host round trip: capacities were fixed beforehand
     n_rec = ex->rec_cap;
     n_bin = ex->bin_cap;
     n_items = ex->item_cap;
@@ -1071,7 +1167,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   if (n_rec > 0) {
     void* recs_v = nullptr;
     void* bins_v = nullptr;
-    if (planned) {
+    if (fixed) {
       recs_v = ex->recs;
       bins_v = ex->bins;
     } else {
@@ -1079,7 +1175,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       OBBV_RET(pool_get(kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
     }
     hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
-                       d_reccnt, d_reccur, d_binoff, d_bincur, (float4*)recs_v, (int32_t*)bins_v);
+                       d_reccnt, (const int32_t*)d_ioff, d_binoff, d_bincur, (float4*)recs_v, (int32_t*)bins_v);
     OBBV_HIP(hipGetLastError());
     TestArgs ta;
     ta.boxes = boxes;
@@ -1096,9 +1192,9 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     ta.test_counter = nullptr;
     ta.occ = out_occ;
     ta.side = d_side;
-    ta.bin_cap = planned ? ex->bin_cap : INT64_MAX;
-    ta.item_cap = planned ? ex->item_cap : INT64_MAX;
-    ta.persistent = planned ? 1 : 0;
+    ta.bin_cap = fixed ? ex->bin_cap : INT64_MAX;
+    ta.item_cap = fixed ? ex->item_cap : INT64_MAX;
+    ta.persistent = fixed ? 1 : 0;
     void* prof_token = nullptr;
     if (profiling_enabled() && !planned) {
       OBBV_RET(profile_counter(&ta.test_counter));
@@ -1118,7 +1214,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     }
     if (n_items > 0) {
       const bool stage = test_stage_choice();
-      const int64_t grid = planned ? std::min<int64_t>(n_items, 256 * 32) : n_items;
+      const int64_t grid = fixed ? std::min<int64_t>(n_items, 256 * 32) : n_items;
       if (TE == 8)
         OBBV_RET(launch_test<8>(ta, grid, stats, stage, s));
       else
@@ -1134,15 +1230,35 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   hipLaunchKernelGGL(k_finalize, dim3(ceil_div(n_boxes, 128)), dim3(128), 0, s, boxes, n_boxes, R, mask,
                      d_acc, out_obv, out_vin_axis, status);
   OBBV_HIP(hipGetLastError());
+  if (ex && ex->publish) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, (const int64_t*)(d_recoff + nbw),
+                       (const int64_t*)(d_binoff + nbw * TT), (const int64_t*)(d_chunkoff + nbw * TT),
+                       (const uint32_t*)status, ex->publish);
+    OBBV_HIP(hipGetLastError());
+  }
   return OBBV_OK;
 }
 
 int outer_volume_frames(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key, int32_t n_boxes,
                         const obbv_ov_params* params, const obbv_box* frames, const int32_t* box_frame,
-                        int32_t n_frames, double* out_obv, hipStream_t s) {
+                        int32_t n_frames, double* out_obv, hipStream_t s, OvExec* ex) {
   const SharedFrames sf{frames, box_frame, n_frames};
   return outer_volume_run(mesh, 1, boxes, nullptr, box_key, n_boxes, params, out_obv, nullptr, nullptr, nullptr,
-                          nullptr, s, nullptr, nullptr, &sf);
+                          nullptr, s, nullptr, ex, &sf);
+}
+
+int outer_volume_exec(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key, int32_t n_boxes,
+                      const obbv_ov_params* params, double* out_obv, hipStream_t s, OvExec* ex) {
+  return outer_volume_run(mesh, 1, boxes, nullptr, box_key, n_boxes, params, out_obv, nullptr, nullptr, nullptr,
+                          nullptr, s, nullptr, ex, nullptr);
+}
+
+int status_or(uint32_t bits, hipStream_t s) {
+  uint32_t* w = nullptr;
+  OBBV_RET(status_word(&w));
+  hipLaunchKernelGGL(k_or_word, dim3(1), dim3(1), 0, s, w, bits);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
 }
 
 int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
@@ -1165,7 +1281,7 @@ extern "C" int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* 
   if (n_boxes == 0) return OBBV_OK;
   OBBV_ARG(frames && box_frame && n_frames >= 1 && n_frames <= n_boxes, "need 1..n_boxes frames");
   return obbv::outer_volume_frames(mesh, boxes, box_key, n_boxes, params, frames, box_frame, n_frames, out_obv,
-                                   (hipStream_t)stream);
+                                   (hipStream_t)stream, nullptr);
 }
 
 extern "C" int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
@@ -1472,7 +1588,9 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   ex.rec_cap = (int64_t)std::ceil((double)probe.n_rec * headroom) + 1024;
   ex.bin_cap = (int64_t)std::ceil((double)probe.n_bin * headroom) + 4096;
   ex.item_cap = (int64_t)std::ceil((double)probe.n_items * headroom) + 64;
-  const size_t bytes = align_up(ex.meta_cap) + align_up((size_t)ex.rec_cap * 64) + align_up((size_t)ex.bin_cap * 4);
+  ex.items_cap = probe.items_bytes;
+  const size_t bytes = align_up(ex.meta_cap) + align_up((size_t)ex.rec_cap * 64) + align_up((size_t)ex.bin_cap * 4) +
+                       align_up(ex.items_cap);
   if (hipMalloc(&P->alloc, bytes) != hipSuccess) {
     (void)hipGetLastError();
     set_error("hipMalloc of the planned scratch failed");
@@ -1481,6 +1599,7 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   ex.meta = (char*)P->alloc;
   ex.recs = (float4*)(ex.meta + align_up(ex.meta_cap));
   ex.bins = (int32_t*)((char*)ex.recs + align_up((size_t)ex.rec_cap * 64));
+  ex.items = (char*)ex.bins + align_up((size_t)ex.bin_cap * 4);
   // the mesh table lives at the start of the meta block (outside the graph)
   std::vector<MeshDev> mh((size_t)n_meshes);
   for (int m = 0; m < n_meshes; ++m)

@@ -85,7 +85,8 @@ int status_word(uint32_t** out) {
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan int32 -> int64 (three kernels per level, recursive on block sums)
+// exclusive scan int32 -> int64 (two kernels per level, recursive on block sums;
+// out[n] = total)
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int kScanThreads = 256;
@@ -95,7 +96,7 @@ constexpr int kScanBlock = kScanThreads * kScanItems;  // elements per block
 template <typename T>
 __global__ void __launch_bounds__(kScanThreads)
 k_scan_block(const T* __restrict__ in, int64_t* __restrict__ out, int64_t* __restrict__ sums,
-             int64_t n) {
+             int64_t n, int64_t* __restrict__ total_out) {
   __shared__ int64_t sh[kScanThreads];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
   int64_t v[kScanItems];
@@ -123,6 +124,7 @@ k_scan_block(const T* __restrict__ in, int64_t* __restrict__ out, int64_t* __res
     excl += v[k];
   }
   if (threadIdx.x == kScanThreads - 1 && sums) sums[blockIdx.x] = sh[threadIdx.x];
+  if (threadIdx.x == kScanThreads - 1 && total_out) *total_out = sh[threadIdx.x];  // single-block level
 }
 
 __global__ void __launch_bounds__(kScanThreads)
@@ -135,26 +137,25 @@ k_scan_add(int64_t* __restrict__ out, const int64_t* __restrict__ offs, int64_t 
   }
 }
 
-__global__ void k_write_total(const int64_t* __restrict__ excl, const int32_t* __restrict__ last_in,
-                              int64_t* __restrict__ total_out) {
-  *total_out = *excl + (int64_t)*last_in;
-}
+__global__ void k_zero_i64(int64_t* __restrict__ p) { *p = 0; }
 
+// Exclusive scan of one level; the single-block top level also writes the
+// grand total to total_out.
 template <typename T>
-int scan_level(const T* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s) {
+int scan_level(const T* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s, int64_t* total_out) {
   const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb <= 1) {
     hipLaunchKernelGGL(k_scan_block<T>, dim3(1), dim3(kScanThreads), 0, s, in, out,
-                       (int64_t*)nullptr, n);
+                       (int64_t*)nullptr, n, total_out);
     OBBV_HIP(hipGetLastError());
     return OBBV_OK;
   }
   int64_t* sums = scratch;
   int64_t* sums_scan = scratch + nb;
   hipLaunchKernelGGL(k_scan_block<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, sums,
-                     n);
+                     n, (int64_t*)nullptr);
   OBBV_HIP(hipGetLastError());
-  OBBV_RET(scan_level<int64_t>(sums, sums_scan, nb, scratch + 2 * nb, s));
+  OBBV_RET(scan_level<int64_t>(sums, sums_scan, nb, scratch + 2 * nb, s, total_out));
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, out, sums_scan, n);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
@@ -173,17 +174,16 @@ size_t exclusive_scan_scratch_bytes(int64_t n) {
 
 int exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* scratch,
                               size_t scratch_bytes, hipStream_t s) {
-  if (n <= 0) {
-    OBBV_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+  if (n <= 0) {  // a kernel, not a memset node, so the call stays capturable
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, out);
+    OBBV_HIP(hipGetLastError());
     return OBBV_OK;
   }
   if (scratch_bytes < exclusive_scan_scratch_bytes(n)) {
     set_error("scan scratch too small");
     return OBBV_ERR_WORKSPACE;
   }
-  OBBV_RET(scan_level<int32_t>(in, out, n, (int64_t*)scratch, s));
-  hipLaunchKernelGGL(k_write_total, dim3(1), dim3(1), 0, s, out + (n - 1), in + (n - 1), out + n);
-  OBBV_HIP(hipGetLastError());
+  OBBV_RET(scan_level<int32_t>(in, out, n, (int64_t*)scratch, s, out + n));
   return OBBV_OK;
 }
 
