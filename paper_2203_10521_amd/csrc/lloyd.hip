@@ -23,6 +23,9 @@
 //     local axis, gradient, line search at {8, 4, 2, 1, 0.5} delta along -g,
 //     keep the best if it lowers OBV.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -60,6 +63,15 @@ struct HBox {
   float h[3];
 };
 
+// Wall-clock accounting of the Lloyd driver, printed to stderr when the
+// environment variable OBBV_LLOYD_TIMING is set (measurement only).
+struct WallTimer {
+  double s = 0.0;
+  std::chrono::steady_clock::time_point t0;
+  void start() { t0 = std::chrono::steady_clock::now(); }
+  void stop() { s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
 inline float f32_up(double x) {
   float y = (float)x;
   if ((double)y < x) y = nextafterf(y, INFINITY);
@@ -85,6 +97,7 @@ struct Evaluator {
   size_t scap = 0;
   int64_t rec_cap = 0, bin_cap = 0, item_cap = 0;
   int64_t overflows = 0;
+  WallTimer t_prep, t_dev;
   int64_t evals = 0;
   int64_t calls = 0;
   std::vector<HBox> fr;  // frames of the current call (host)
@@ -149,6 +162,7 @@ struct Evaluator {
     const size_t n = boxes.size();
     out.assign(n, 0.0);
     if (n == 0) return OBBV_OK;
+    t_prep.start();
     // Candidates of one box share its centre and axes: group them into frames so
     // that the mesh is culled and transformed once per frame (against the union
     // of its boxes).  Boxes of one centre and axes are split into size classes
@@ -238,6 +252,8 @@ struct Evaluator {
     // control words: the call's private status word (device, zeroed by the
     // upload); the published status bits and totals (host, written by the device)
     std::memset(hbuf + o_ctl, 0, 256);
+    t_prep.stop();
+    t_dev.start();
     OBBV_HIP(hipMemcpyAsync(dbuf, hbuf, o_out, hipMemcpyHostToDevice, stream));
     double* hout = (double*)(hdev + o_out);  // results go straight to pinned host memory
     uint32_t* dstatus = (uint32_t*)(dbuf + o_ctl);
@@ -278,6 +294,7 @@ struct Evaluator {
       OBBV_HIP(hipStreamSynchronize(stream));
       OBBV_RET(grow(probe.n_rec, probe.n_bin, probe.n_items));
     }
+    t_dev.stop();
     std::memcpy(out.data(), hbuf + o_out, n * 8);
     evals += (int64_t)n;
     ++calls;
@@ -296,6 +313,7 @@ struct Predictor {
   char* dbuf = nullptr;
   size_t cap = 0;
   bool paused = false;  // the judge found the ranker off: exact evaluation until the next iteration
+  WallTimer t_pred;
   double err_sum = 0.0;
   int64_t err_n = 0, predicted = 0, fallbacks = 0;
   static constexpr int kWindow = 256;
@@ -338,6 +356,7 @@ struct Predictor {
     const size_t np = (n + 31) / 32 * 32;
     out.assign(n, 0.f);
     if (n == 0) return OBBV_OK;
+    t_pred.start();
     const size_t o_f = (np * sizeof(obbv_box) + 255) & ~(size_t)255;
     const size_t hneed = o_f + np * 4;
     const size_t need = o_f + np * 544 * 4 + 1024;
@@ -377,6 +396,7 @@ struct Predictor {
     OBBV_HIP(hipStreamSynchronize(stream));
     std::memcpy(out.data(), hbuf + o_f, n * 4);
     predicted += (int64_t)n;
+    t_pred.stop();
     return OBBV_OK;
   }
 };
@@ -1013,6 +1033,19 @@ struct LloydState {
   Counters cnt;
   double layer_error = 0.0;
   Predictor pred;
+  WallTimer t_flood, t_update, t_life;
+  int64_t n_calls0 = 0;
+
+  LloydState() { t_life.start(); }
+  ~LloydState() {
+    if (!getenv("OBBV_LLOYD_TIMING")) return;
+    t_life.stop();
+    fprintf(stderr,
+            "[obbv lloyd] wall %.3f s: flood %.3f s, parameter update %.3f s; outer-volume calls %lld "
+            "(host prep %.3f s, device incl. launches %.3f s, %lld overflow repeats); ranker %.3f s\n",
+            t_life.s, t_flood.s, t_update.s, (long long)ev.calls, ev.t_prep.s, ev.t_dev.s, (long long)ev.overflows,
+            pred.t_pred.s);
+  }
 };
 
 // One Lloyd iteration (partition + parameter update) of every group.
@@ -1024,7 +1057,9 @@ static int lloyd_iterate(LloydState& S) {
   std::vector<Group> flood_groups;
   for (const Group& g : S.groups)
     if (g.boxes.size() > 1) flood_groups.push_back(g);
+  S.t_flood.start();
   OBBV_RET(flood_partition(S.M, S.E, flood_groups, io, S.K, S.ev, S.cnt, &S.pred));
+  S.t_flood.stop();
   for (const Group& g : S.groups)
     if (g.boxes.size() == 1)
       for (int e : g.elems) eb[e] = g.boxes[0];
@@ -1045,7 +1080,9 @@ static int lloyd_iterate(LloydState& S) {
       verts[b] = vertex_set(S.M, tris[b], mark);
       which.push_back((int32_t)b);
     }
+  S.t_update.start();
   OBBV_RET(update_boxes(S.M, verts, S.boxes, S.obv, S.slot, which, S.delta, S.ev, S.cnt));
+  S.t_update.stop();
   S.layer_error = 0.0;
   for (size_t b = 0; b < S.boxes.size(); ++b) S.layer_error += tris[b].empty() ? 0.0 : S.obv[b];
   return OBBV_OK;
@@ -1362,7 +1399,9 @@ int merge_level(LloydState& S, Tree& T, int l) {
       verts[j] = vertex_set(S.M, tris[j], mark);
       which.push_back((int32_t)j);
     }
+  S.t_update.start();
   OBBV_RET(update_boxes(S.M, verts, S.boxes, S.obv, S.slot, which, S.delta, S.ev, S.cnt));
+  S.t_update.stop();
   A.box = S.boxes;
   for (size_t j = 0; j < A.box.size(); ++j) {
     A.obv[j] = tris[j].empty() ? 0.0 : S.obv[j];

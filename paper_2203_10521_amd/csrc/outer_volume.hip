@@ -5,14 +5,16 @@
 // Pipeline per call (all on one stream):
 //   [k_frame_cull x 2]   boxes grouped by shared centre and axes: the frame-local
 //                        coordinates of the triangles each group can see
-//   k_box_chunks + scan  work list of (box, 256-triangle chunk) items
+//   k_box_chunks         work list of (box, 256-triangle chunk) items (one block,
+//                        scanned in place)
 //   k_cull_count         per item and cast axis: triangles in the half prism above
 //                        the slab bottom and below the slab top (ballot counts
 //                        summed per block; no shared global counters)
 //   k_box_sides          keep the half prism with fewer triangles (mirror flag);
 //                        per-item record offsets (scan over the box's items)
 //   k_tile_count         per (box, axis, ray tile): number of binned triangles
-//   scans                record offsets, bin offsets  (one host sync: sizes)
+//   k_tiles_scan_*       bin, work-item and record offsets (3 kernels); unless the
+//                        scratch is capped or planned, one host sync for sizes
 //   k_write              per kept triangle: a 64-byte test record (edge and depth
 //                        planes, fixed point) + its index in every tile bin
 //   k_test               one wave per ray tile: every ray against its bin
@@ -128,22 +130,29 @@ __device__ inline bool projects_into_face(const CastTri& t, const CastFrame& f) 
          vmin <= f.hv + f.ev;
 }
 
-// Tile range of the cells whose rays can hit the triangle (conservative).
-__device__ inline void tile_range(const CastTri& t, const CastFrame& f, int R, int TE, int& ti0,
-                                  int& ti1, int& tj0, int& tj1) {
+// Range of the cells whose rays can hit the triangle (conservative), and the
+// range of TE x TE ray tiles holding them.
+__device__ inline void cell_range(const CastTri& t, const CastFrame& f, int R, int& i0, int& i1, int& j0,
+                                  int& j1) {
   const float umin = fminf(fminf(t.u[0], t.u[1]), t.u[2]);
   const float umax = fmaxf(fmaxf(t.u[0], t.u[1]), t.u[2]);
   const float vmin = fminf(fminf(t.v[0], t.v[1]), t.v[2]);
   const float vmax = fmaxf(fmaxf(t.v[0], t.v[1]), t.v[2]);
   const double hu = f.hu, hv = f.hv;
-  int i0 = (int)floor(((double)umin - f.eu + hu) / f.du);
-  int i1 = (int)floor(((double)umax + f.eu + hu) / f.du);
-  int j0 = (int)floor(((double)vmin - f.ev + hv) / f.dv);
-  int j1 = (int)floor(((double)vmax + f.ev + hv) / f.dv);
+  i0 = (int)floor(((double)umin - f.eu + hu) / f.du);
+  i1 = (int)floor(((double)umax + f.eu + hu) / f.du);
+  j0 = (int)floor(((double)vmin - f.ev + hv) / f.dv);
+  j1 = (int)floor(((double)vmax + f.ev + hv) / f.dv);
   i0 = max(0, min(R - 1, i0));
   i1 = max(0, min(R - 1, i1));
   j0 = max(0, min(R - 1, j0));
   j1 = max(0, min(R - 1, j1));
+}
+
+__device__ inline void tile_range(const CastTri& t, const CastFrame& f, int R, int TE, int& ti0,
+                                  int& ti1, int& tj0, int& tj1) {
+  int i0, i1, j0, j1;
+  cell_range(t, f, R, i0, i1, j0, j1);
   ti0 = i0 / TE;
   ti1 = i1 / TE;
   tj0 = j0 / TE;
@@ -229,10 +238,6 @@ __device__ inline bool cull_tri(const CullArgs& a, int b, const MeshDev& M, cons
   return true;
 }
 
-__global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
-}
-
 // A box may use its frame's triangle list only if it has the frame's centre and
 // axes (same bits) and lies inside the frame box; otherwise it walks the whole
 // mesh (slower, same result).
@@ -247,28 +252,66 @@ __device__ inline bool inside_frame(const obbv_box& bx, const obbv_box& fr) {
   return same;
 }
 
-__global__ void k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ meshes,
-                             int n_meshes, int n_boxes, const obbv_box* __restrict__ boxes,
-                             const obbv_box* __restrict__ frames, const int32_t* __restrict__ box_frame,
-                             int n_frames, const int64_t* __restrict__ list_off, int32_t* __restrict__ box_list,
-                             int32_t* __restrict__ nch, uint32_t* status) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_boxes) return;
-  const int m = box_mesh ? box_mesh[b] : 0;
-  if (m < 0 || m >= n_meshes) {  // out-of-range mesh index: the box sees no triangles
-    atomicOr(status, OBBV_STATUS_BAD_INDEX);
-    nch[b] = 0;
-    if (box_list) box_list[b] = -1;
-    return;
+// Exclusive scan of one value per thread over a block of kScanBlockThreads;
+// returns the exclusive prefix and the block total (all threads).
+constexpr int kScanBlockThreads = 1024;
+__device__ inline long long block_excl_scan(long long v, long long* wsum, long long& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  long long inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const long long u = __shfl_up(inc, off);
+    if (lane >= off) inc += u;
   }
-  int64_t n = meshes[m].nt;
-  if (box_list) {
-    const int f = box_frame[b];
-    const bool use = f >= 0 && f < n_frames && inside_frame(boxes[b], frames[f]);
-    box_list[b] = use ? f : -1;
-    if (use) n = list_off[f + 1] - list_off[f];
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  long long before = 0;
+  total = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    if (k < wave) before += wsum[k];
+    total += wsum[k];
   }
-  nch[b] = (int32_t)((n + kCullThreads - 1) / kCullThreads);
+  __syncthreads();
+  return before + inc - v;
+}
+
+// One block: the number of 256-triangle items of every box (its frame list, or
+// the whole mesh), their exclusive scan (chunk_off[0..n_boxes]), the frame use
+// of every box, and the per-call counters that must start at zero.
+__global__ void __launch_bounds__(kScanBlockThreads)
+k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ meshes, int n_meshes, int n_boxes,
+             const obbv_box* __restrict__ boxes, const obbv_box* __restrict__ frames,
+             const int32_t* __restrict__ box_frame, int n_frames, const int64_t* __restrict__ list_off,
+             int32_t* __restrict__ box_list, int64_t* __restrict__ chunk_off, uint32_t* __restrict__ done_counter,
+             uint32_t* status) {
+  __shared__ long long wsum[kScanBlockThreads / 64];
+  if (threadIdx.x == 0 && done_counter) *done_counter = 0u;
+  long long base = 0;
+  for (int b0 = 0; b0 < n_boxes; b0 += kScanBlockThreads) {
+    const int b = b0 + (int)threadIdx.x;
+    long long nch = 0;
+    if (b < n_boxes) {
+      const int m = box_mesh ? box_mesh[b] : 0;
+      if (m < 0 || m >= n_meshes) {  // out-of-range mesh index: the box sees no triangles
+        atomicOr(status, OBBV_STATUS_BAD_INDEX);
+        if (box_list) box_list[b] = -1;
+      } else {
+        int64_t n = meshes[m].nt;
+        if (box_list) {
+          const int f = box_frame[b];
+          const bool use = f >= 0 && f < n_frames && inside_frame(boxes[b], frames[f]);
+          box_list[b] = use ? f : -1;
+          if (use) n = list_off[f + 1] - list_off[f];
+        }
+        nch = (n + kCullThreads - 1) / kCullThreads;
+      }
+    }
+    long long total = 0;
+    const long long ex = block_excl_scan(nch, wsum, total);
+    if (b < n_boxes) chunk_off[b] = base + ex;
+    base += total;
+  }
+  if (threadIdx.x == 0) chunk_off[n_boxes] = base;
 }
 
 // Per-wave ballot counts of a 256-thread block, summed in LDS: every block
@@ -342,19 +385,34 @@ __device__ inline int wave_incl_scan(int v, int lane) {
 }
 
 __global__ void k_frame_scan(const int32_t* __restrict__ item_cnt, int n_frames, int per,
-                             int32_t* __restrict__ item_off, int32_t* __restrict__ frame_cnt) {
-  const int g = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+                             int32_t* __restrict__ item_off, int32_t* __restrict__ frame_cnt,
+                             int64_t* __restrict__ frame_off) {
   const int lane = threadIdx.x & 63;
-  if (g >= n_frames) return;
-  const int64_t i0 = (int64_t)g * per, i1 = i0 + per;
-  int base = 0;
-  for (int64_t i = i0; i < i1; i += 64) {
-    const int v = i + lane < i1 ? item_cnt[i + lane] : 0;
-    const int inc = wave_incl_scan(v, lane);
-    if (i + lane < i1) item_off[i + lane] = base + inc - v;
-    base += __shfl(inc, 63);
+  const int waves = (int)(gridDim.x * (blockDim.x >> 6));
+  for (int g = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6); g < n_frames; g += waves) {
+    const int64_t i0 = (int64_t)g * per, i1 = i0 + per;
+    int base = 0;
+    for (int64_t i = i0; i < i1; i += 64) {
+      const int v = i + lane < i1 ? item_cnt[i + lane] : 0;
+      const int inc = wave_incl_scan(v, lane);
+      if (i + lane < i1) item_off[i + lane] = base + inc - v;
+      base += __shfl(inc, 63);
+    }
+    if (lane == 0) frame_cnt[g] = base;
   }
-  if (lane == 0) frame_cnt[g] = base;
+  if (!frame_off) return;
+  // single-block launch: the frames' list offsets as well
+  __shared__ long long wsum[kScanBlockThreads / 64];
+  __syncthreads();
+  long long fb = 0;
+  for (int g0 = 0; g0 < n_frames; g0 += (int)blockDim.x) {
+    const int g = g0 + (int)threadIdx.x;
+    long long total = 0;
+    const long long ex = block_excl_scan(g < n_frames ? (long long)frame_cnt[g] : 0ll, wsum, total);
+    if (g < n_frames) frame_off[g] = fb + ex;
+    fb += total;
+  }
+  if (threadIdx.x == 0) frame_off[n_frames] = fb;
 }
 
 // Which prism(s) the triangle belongs to, per cast axis.
@@ -407,10 +465,17 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt) {
 // first record within the (box, axis) (exclusive scan over the box's items).
 __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, const int32_t* __restrict__ item_cnt,
                             int32_t* __restrict__ side, int32_t* __restrict__ rec_cnt,
-                            int32_t* __restrict__ item_off) {
+                            int32_t* __restrict__ item_off, int TT, int32_t* __restrict__ tile_cnt,
+                            int32_t* __restrict__ bin_cur, unsigned long long* __restrict__ acc) {
   const int bw = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (bw >= 3 * n_boxes) return;
+  // counters of this (box, axis) that later passes accumulate into
+  for (int k = lane; k < TT; k += 64) {
+    tile_cnt[(int64_t)bw * TT + k] = 0;
+    bin_cur[(int64_t)bw * TT + k] = 0;
+  }
+  if (lane == 0) acc[bw] = 0ull;
   const int b = bw / 3, w = bw - 3 * b;
   const int64_t i0 = chunk_off[b], i1 = chunk_off[b + 1];
   int up = 0, dn = 0;
@@ -437,14 +502,72 @@ __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, 
   }
 }
 
-// Work items of the test pass: every non-empty tile bin is cut into chunks of at
-// most `chunk` records, so no wave walks a much longer list than the others.
-__global__ void k_chunk_count(const int64_t* __restrict__ bin_off, int64_t n_tiles, int chunk,
-                              int32_t* __restrict__ nchunk) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const int64_t n = bin_off[t + 1] - bin_off[t];
-  nchunk[t] = (int32_t)((n + chunk - 1) / chunk);
+// Offsets of the tile bins and of the test work items in one scan: every
+// non-empty bin is cut into chunks of at most `chunk` records (so no wave walks
+// a much longer list than the others), and both the bin sizes and the chunk
+// counts are scanned together.  Three kernels: per block of kScanBlockThreads
+// tiles, one block for the block sums (and the per-(box, axis) record counts),
+// then the block offsets.
+__global__ void __launch_bounds__(kScanBlockThreads)
+k_tiles_scan_block(const int32_t* __restrict__ cnt, int64_t n, int chunk, int64_t* __restrict__ bin_off,
+                   int64_t* __restrict__ chunk_off, int64_t* __restrict__ bsum) {
+  __shared__ long long wsum[kScanBlockThreads / 64];
+  const int64_t i = (int64_t)blockIdx.x * kScanBlockThreads + threadIdx.x;
+  const int c = i < n ? cnt[i] : 0;
+  long long tb = 0, tc = 0;
+  const long long eb = block_excl_scan(c, wsum, tb);
+  const long long ec = block_excl_scan((c + chunk - 1) / chunk, wsum, tc);
+  if (i < n) {
+    bin_off[i] = eb;
+    chunk_off[i] = ec;
+  }
+  if (threadIdx.x == 0) {
+    bsum[2 * blockIdx.x] = tb;
+    bsum[2 * blockIdx.x + 1] = tc;
+  }
+}
+
+__global__ void __launch_bounds__(kScanBlockThreads)
+k_tiles_scan_top(int64_t* __restrict__ bsum, int64_t nb, int64_t n, int64_t* __restrict__ bin_off,
+                 int64_t* __restrict__ chunk_off, const int32_t* __restrict__ rec_cnt, int64_t nbw,
+                 int64_t* __restrict__ rec_off) {
+  __shared__ long long wsum[kScanBlockThreads / 64];
+  long long ob = 0, oc = 0;
+  for (int64_t j0 = 0; j0 < nb; j0 += kScanBlockThreads) {
+    const int64_t j = j0 + threadIdx.x;
+    long long tb = 0, tc = 0;
+    const long long eb = block_excl_scan(j < nb ? bsum[2 * j] : 0, wsum, tb);
+    const long long ec = block_excl_scan(j < nb ? bsum[2 * j + 1] : 0, wsum, tc);
+    __syncthreads();  // every thread has read its bsum entries
+    if (j < nb) {
+      bsum[2 * j] = ob + eb;
+      bsum[2 * j + 1] = oc + ec;
+    }
+    ob += tb;
+    oc += tc;
+  }
+  if (threadIdx.x == 0) {
+    bin_off[n] = ob;
+    chunk_off[n] = oc;
+  }
+  long long orr = 0;
+  for (int64_t j0 = 0; j0 < nbw; j0 += kScanBlockThreads) {
+    const int64_t j = j0 + threadIdx.x;
+    long long t = 0;
+    const long long e = block_excl_scan(j < nbw ? rec_cnt[j] : 0, wsum, t);
+    if (j < nbw) rec_off[j] = orr + e;
+    orr += t;
+  }
+  if (threadIdx.x == 0) rec_off[nbw] = orr;
+}
+
+__global__ void __launch_bounds__(kScanBlockThreads)
+k_tiles_scan_add(int64_t n, const int64_t* __restrict__ bsum, int64_t* __restrict__ bin_off,
+                 int64_t* __restrict__ chunk_off) {
+  const int64_t i = (int64_t)blockIdx.x * kScanBlockThreads + threadIdx.x;
+  if (i >= n || blockIdx.x == 0) return;
+  bin_off[i] += bsum[2 * blockIdx.x];
+  chunk_off[i] += bsum[2 * blockIdx.x + 1];
 }
 
 // Is the triangle kept on the chosen side?  (Mirrored frames flip z, so the
@@ -636,18 +759,20 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
         continue;
       }
       make_record(tr, mirror, f.hw, recs + 4 * slot);
-      int ti0, ti1, tj0, tj1;
-      tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
+      int i0, i1, j0, j1;
+      cell_range(tr, f, a.R, i0, i1, j0, j1);
+      const int ti0 = i0 / a.TE, ti1 = i1 / a.TE, tj0 = j0 / a.TE, tj1 = j1 / a.TE;
       const int64_t tbase = (int64_t)bw * TT;
       for (int tj = tj0; tj <= tj1; ++tj)
         for (int ti = ti0; ti <= ti1; ++ti) {
           const int64_t tl = tbase + tj * a.tpe + ti;
           const int lt = w * TT + tj * a.tpe + ti;
           const int pos = lds ? base_pos[lt] + atomicAdd(&cnt[lt], 1) : atomicAdd(&bin_cur[tl], 1);
+          const uint32_t entry = (uint32_t)slot;
           if (bin_off[tl] + pos >= a.bin_cap)
             atomicOr(a.status, OBBV_STATUS_OVERFLOW);
           else if (bin_off[tl] + pos < bin_off[tl + 1])
-            bins[bin_off[tl] + pos] = (int32_t)slot;
+            bins[bin_off[tl] + pos] = (int32_t)entry;
           else
             atomicOr(a.status, OBBV_STATUS_BAD_INDEX);
         }
@@ -845,24 +970,44 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
   if (lane == 0 && lane_sum != 0) atomicAdd(&a.acc[bw], (unsigned long long)lane_sum);
 }
 
-// The call's status bits and totals, written (vector stores) to the caller's
-// mapped host memory.
-__global__ void k_publish(const int64_t* __restrict__ rec, const int64_t* __restrict__ bin,
-                          const int64_t* __restrict__ items, const uint32_t* __restrict__ status,
-                          int64_t* __restrict__ out) {
-  out[0] = (int64_t)*status;
-  out[1] = *rec;
-  out[2] = *bin;
-  out[3] = *items;
-}
-
 __global__ void k_or_word(uint32_t* __restrict__ w, uint32_t bits) { atomicOr(w, bits); }
 
+struct Publish {
+  int64_t* out;  // nullable: mapped host memory [status, records, bin entries, work items]
+  const int64_t* rec;
+  const int64_t* bin;
+  const int64_t* items;
+  uint32_t* done;  // blocks finished (zeroed by k_box_chunks)
+};
+
+__device__ void finalize_box(const obbv_box* __restrict__ boxes, int b, int R, uint32_t axis_mask,
+                             const unsigned long long* __restrict__ acc, double* __restrict__ out_obv,
+                             double* __restrict__ out_vin_axis, uint32_t* status);
+
+// float64 OBV per box; the last block to finish publishes the call's status bits
+// and totals to the caller's mapped host memory.
 __global__ void k_finalize(const obbv_box* __restrict__ boxes, int n_boxes, int R, uint32_t axis_mask,
                            const unsigned long long* __restrict__ acc, double* __restrict__ out_obv,
-                           double* __restrict__ out_vin_axis, uint32_t* status) {
+                           double* __restrict__ out_vin_axis, uint32_t* status, Publish pub) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_boxes) return;
+  if (b < n_boxes) finalize_box(boxes, b, R, axis_mask, acc, out_obv, out_vin_axis, status);
+  if (!pub.out) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(pub.done, 1u) == gridDim.x - 1) {
+      __threadfence();
+      pub.out[0] = (int64_t)atomicOr(status, 0u);
+      pub.out[1] = *pub.rec;
+      pub.out[2] = *pub.bin;
+      pub.out[3] = *pub.items;
+    }
+  }
+}
+
+__device__ void finalize_box(const obbv_box* __restrict__ boxes, int b, int R, uint32_t axis_mask,
+                             const unsigned long long* __restrict__ acc, double* __restrict__ out_obv,
+                             double* __restrict__ out_vin_axis, uint32_t* status) {
   const BoxRegs B = load_box(boxes, b);
   const int st = box_state(B);
   if (st == 2) {
@@ -931,7 +1076,8 @@ int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hip
 }
 
 // Record loading of the ray-test loop: 1 = LDS staging (default), 0 = scalar
-// loads.  OBBV_TEST_STAGE overrides it (used to compare the two on a device).
+// loads in batches of four.  OBBV_TEST_STAGE overrides it (used to compare the
+// two on a device; staging measured faster).
 bool test_stage_choice() {
   const char* e = getenv("OBBV_TEST_STAGE");
   if (e && *e) return atoi(e) != 0;
@@ -999,24 +1145,21 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     return o;
   };
   const size_t o_mesh = take(sizeof(MeshDev) * n_meshes);
-  const size_t o_nch = take(4 * (size_t)n_boxes);
+  const size_t o_done = take(4);
   const size_t o_blist = take(4 * (size_t)(sf ? n_boxes : 0));
   const size_t o_choff = take(8 * (size_t)(n_boxes + 1));
   const size_t o_side = take(4 * (size_t)nbw);
   const size_t o_reccnt = take(4 * (size_t)nbw);
   const size_t o_recoff = take(8 * (size_t)(nbw + 1));
   const size_t o_binoff = take(8 * (size_t)(nbw * TT + 1));
-  const size_t o_nchunk = take(4 * (size_t)(nbw * TT));
   const size_t o_chunkoff = take(8 * (size_t)(nbw * TT + 1));
-  const size_t o_zero0 = off;  // zero-initialised block
-  const size_t o_tilecnt = take(4 * (size_t)(nbw * TT));
-  const size_t o_bincur = take(4 * (size_t)(nbw * TT));
-  const size_t o_acc = take(8 * (size_t)nbw);
-  const size_t o_zero1 = off;
+  const size_t o_tilecnt = take(4 * (size_t)(nbw * TT));  // zeroed by k_box_sides
+  const size_t o_bincur = take(4 * (size_t)(nbw * TT));   // zeroed by k_box_sides
+  const size_t o_acc = take(8 * (size_t)nbw);             // zeroed by k_box_sides
   const size_t o_fcnt = take(4 * (size_t)n_frames);
   const size_t o_foff = take(8 * (size_t)(n_frames + 1));
   const size_t scan_bytes =
-      std::max(exclusive_scan_scratch_bytes(nbw * TT), exclusive_scan_scratch_bytes(std::max<int64_t>(nbw, n_boxes)));
+      std::max({exclusive_scan_scratch_bytes(n_frames), (size_t)16 * (ceil_div(nbw * TT, kScanBlockThreads) + 1)});
   const size_t o_scan = take(scan_bytes);
   void* meta_v = nullptr;
   if (planned) {
@@ -1031,13 +1174,12 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   if (ex) ex->meta_bytes = off;
   char* meta = (char*)meta_v;
   MeshDev* d_mesh = (MeshDev*)(meta + o_mesh);
-  int32_t* d_nch = (int32_t*)(meta + o_nch);
+  uint32_t* d_done = (uint32_t*)(meta + o_done);
   int64_t* d_choff = (int64_t*)(meta + o_choff);
   int32_t* d_side = (int32_t*)(meta + o_side);
   int32_t* d_reccnt = (int32_t*)(meta + o_reccnt);
   int64_t* d_recoff = (int64_t*)(meta + o_recoff);
   int64_t* d_binoff = (int64_t*)(meta + o_binoff);
-  int32_t* d_nchunk = (int32_t*)(meta + o_nchunk);
   int64_t* d_chunkoff = (int64_t*)(meta + o_chunkoff);
   int32_t* d_tilecnt = (int32_t*)(meta + o_tilecnt);
   int32_t* d_bincur = (int32_t*)(meta + o_bincur);
@@ -1071,8 +1213,6 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   int32_t* d_fioff = (int32_t*)((char*)d_ficnt + align_up(4 * (size_t)fitems));
 
   if (!planned) OBBV_HIP(hipMemcpyAsync(d_mesh, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_fill_zero, dim3(256), dim3(256), 0, s, (uint32_t*)(meta + o_zero0),
-                     (int64_t)((o_zero1 - o_zero0) / 4));
 
   float4* d_listP = nullptr;
   if (sf) {  // candidate triangles of every shared frame
@@ -1082,10 +1222,16 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], mask,
                        nch, d_ficnt, (const int32_t*)nullptr, (const int64_t*)nullptr, (float4*)nullptr, status);
     OBBV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_frame_scan, dim3(ceil_div(n_frames, kCullWaves)), dim3(kCullThreads), 0, s,
-                       (const int32_t*)d_ficnt, n_frames, nch, d_fioff, d_fcnt);
-    OBBV_HIP(hipGetLastError());
-    OBBV_RET(exclusive_scan_i32_to_i64(d_fcnt, d_foff, n_frames, d_scan, scan_bytes, s));
+    if ((int64_t)n_frames * nch <= ((int64_t)1 << 20)) {  // one block: item and frame offsets
+      hipLaunchKernelGGL(k_frame_scan, dim3(1), dim3(kScanBlockThreads), 0, s, (const int32_t*)d_ficnt, n_frames,
+                         nch, d_fioff, d_fcnt, d_foff);
+      OBBV_HIP(hipGetLastError());
+    } else {
+      hipLaunchKernelGGL(k_frame_scan, dim3(ceil_div(n_frames, kCullWaves)), dim3(kCullThreads), 0, s,
+                         (const int32_t*)d_ficnt, n_frames, nch, d_fioff, d_fcnt, (int64_t*)nullptr);
+      OBBV_HIP(hipGetLastError());
+      OBBV_RET(exclusive_scan_i32_to_i64(d_fcnt, d_foff, n_frames, d_scan, scan_bytes, s));
+    }
     int64_t bound = (int64_t)n_frames * nt;
     if (bound * 48 > ((int64_t)1 << 31)) {  // large: size the lists exactly (one host round trip)
       int64_t* pin = nullptr;
@@ -1101,11 +1247,10 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
                        nch, d_ficnt, (const int32_t*)d_fioff, (const int64_t*)d_foff, d_listP, status);
     OBBV_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_box_chunks, dim3(ceil_div(n_boxes, 256)), dim3(256), 0, s, box_mesh, d_mesh,
+  hipLaunchKernelGGL(k_box_chunks, dim3(1), dim3(kScanBlockThreads), 0, s, box_mesh, (const MeshDev*)d_mesh,
                      n_meshes, n_boxes, boxes, sf ? sf->frames : nullptr, sf ? sf->box_frame : nullptr, n_frames,
-                     (const int64_t*)d_foff, d_blist, d_nch, status);
+                     (const int64_t*)d_foff, d_blist, d_choff, d_done, status);
   OBBV_HIP(hipGetLastError());
-  OBBV_RET(exclusive_scan_i32_to_i64(d_nch, d_choff, n_boxes, d_scan, scan_bytes, s));
 
   CullArgs ca;
   ca.boxes = boxes;
@@ -1128,17 +1273,29 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   hipLaunchKernelGGL(k_cull_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_icnt);
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_box_sides, dim3(ceil_div(nbw, kCullWaves)), dim3(kCullThreads), 0, s,
-                     (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, d_ioff);
+                     (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, d_ioff, (int)TT,
+                     d_tilecnt, d_bincur, d_acc);
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_tile_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_tilecnt);
   OBBV_HIP(hipGetLastError());
-  OBBV_RET(exclusive_scan_i32_to_i64(d_reccnt, d_recoff, nbw, d_scan, scan_bytes, s));
-  OBBV_RET(exclusive_scan_i32_to_i64(d_tilecnt, d_binoff, nbw * TT, d_scan, scan_bytes, s));
+  // bin and work-item offsets of the tiles, record offsets of the (box, axis) pairs
   const int chunk = kTestChunk;
-  hipLaunchKernelGGL(k_chunk_count, dim3(ceil_div(nbw * TT, 256)), dim3(256), 0, s, d_binoff, nbw * TT,
-                     chunk, d_nchunk);
-  OBBV_HIP(hipGetLastError());
-  OBBV_RET(exclusive_scan_i32_to_i64(d_nchunk, d_chunkoff, nbw * TT, d_scan, scan_bytes, s));
+  {
+    const int64_t nt_all = nbw * TT;
+    const int64_t nb = ceil_div(nt_all, kScanBlockThreads);
+    int64_t* bsum = (int64_t*)d_scan;
+    hipLaunchKernelGGL(k_tiles_scan_block, dim3((unsigned)nb), dim3(kScanBlockThreads), 0, s,
+                       (const int32_t*)d_tilecnt, nt_all, chunk, d_binoff, d_chunkoff, bsum);
+    OBBV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tiles_scan_top, dim3(1), dim3(kScanBlockThreads), 0, s, bsum, nb, nt_all, d_binoff,
+                       d_chunkoff, (const int32_t*)d_reccnt, nbw, d_recoff);
+    OBBV_HIP(hipGetLastError());
+    if (nb > 1) {
+      hipLaunchKernelGGL(k_tiles_scan_add, dim3((unsigned)nb), dim3(kScanBlockThreads), 0, s, nt_all,
+                         (const int64_t*)bsum, d_binoff, d_chunkoff);
+      OBBV_HIP(hipGetLastError());
+    }
+  }
 
   int64_t n_rec, n_bin, n_items;
   if (fixed) {  // no host round trip: capacities were fixed beforehand
@@ -1227,15 +1384,10 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     if (out_ray_hits) OBBV_HIP(hipMemsetAsync(out_ray_hits, 0, per, s));
   }
   if (out_side) OBBV_HIP(hipMemcpyAsync(out_side, d_side, 4 * nbw, hipMemcpyDeviceToDevice, s));
+  Publish pub{ex ? ex->publish : nullptr, d_recoff + nbw, d_binoff + nbw * TT, d_chunkoff + nbw * TT, d_done};
   hipLaunchKernelGGL(k_finalize, dim3(ceil_div(n_boxes, 128)), dim3(128), 0, s, boxes, n_boxes, R, mask,
-                     d_acc, out_obv, out_vin_axis, status);
+                     (const unsigned long long*)d_acc, out_obv, out_vin_axis, status, pub);
   OBBV_HIP(hipGetLastError());
-  if (ex && ex->publish) {
-    hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, (const int64_t*)(d_recoff + nbw),
-                       (const int64_t*)(d_binoff + nbw * TT), (const int64_t*)(d_chunkoff + nbw * TT),
-                       (const uint32_t*)status, ex->publish);
-    OBBV_HIP(hipGetLastError());
-  }
   return OBBV_OK;
 }
 
