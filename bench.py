@@ -12,9 +12,11 @@ flood pops per group per round.  One step = one complete obbv_build_hierarchy.
 `value` is box outer-volume evaluations per second over the build; `moves_per_s`
 the Lloyd moves (triangle assignments) decided per second (exact evaluation
 only).  `surrogate` trains the candidate ranker on noisy spheres and rebuilds
-the same hierarchy with ranker-guided floods (moves/s and final error vs exact).  The roofline object describes the ray-test kernel (k_test): algorithmic
-FP32 FLOP (16 per ray-triangle test) over its average launch time, measured with
-HIP events on the library's stream.  `saturated` repeats the measurement on one
+the same hierarchy with ranker-guided floods (moves/s and final error vs exact).
+The roofline object describes the ray-test kernel: algorithmic FP32 FLOP (16 per
+ray-triangle test the kernel needs: the rays of the cells each triangle covers)
+over its average launch time, measured with HIP events on the library's stream.
+`saturated` repeats the measurement on one
 large evaluation (the 85 boxes of the built hierarchy plus 4,011 perturbed
 copies) for context.  `cpu_baseline` times the CPU oracle on a bounded sample of
 the hierarchy's boxes.
@@ -39,16 +41,16 @@ HIER = dict(levels=4, branching=4, iters=20, sweeps=2, R=128, seed=23, pops_per_
 SEED_MESH = 21
 
 
-# HBM traffic of k_test per launch on this workload, from two rocprofv3 --pmc runs
-# (FETCH_SIZE, then WRITE_SIZE, summed over the k_test dispatches of one build),
+# HBM traffic of the ray-test kernel per launch on this workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, then WRITE_SIZE, over the ray-test dispatches of one build),
 # each scaled by the same counter's reading for a plain device copy of known size.
 # Valid only for the kernel source it was measured on: any change to the
 # outer-volume source (hash below) reports null until the counters are re-taken.
 K_TEST_TRAFFIC = {
-    "source_sha256": "9cd2fdd753d3ac49807ff2c90a97df4849e305a97bd24b3956837aa8faa71c0d",
-    "fetch_bytes_per_launch": 67657795,   # 33,037.1 KiB raw x 2.0 (copy calibration)
-    "write_bytes_per_launch": 624150,     # 609.5 KiB raw x 1.0
-    "profile": "profiles/k_test_torus_hierarchy_traffic.md",
+    "source_sha256": "01b7b06da4c7e2f043e6599f2a45e2d4d1900105720189abe90088b9db19cbb4",
+    "fetch_bytes_per_launch": 86353544,   # 42,166.2 KiB raw x 2.0 (copy calibration)
+    "write_bytes_per_launch": 630878,     # 616.1 KiB raw x 1.0
+    "profile": "profiles/ray_test_torus_hierarchy_traffic.md",
 }
 
 

@@ -51,13 +51,19 @@ enum PoolSlot {
   kPoolFeat = 5,
   kPoolLists = 6,
   kPoolItems = 7,
-  kPoolCount = 8
+  kPoolTiles = 8,
+  kPoolCount = 9
 };
 
 // Ensures slot `slot` of the current device holds at least `bytes` and returns it.
 // Growing frees the old block (hipFree waits for the device), so call it only
 // where no queued kernel still reads that slot.
 int pool_get(int slot, size_t bytes, void** out);
+
+// A ray-test record: 5 float4 = 80 bytes (edge planes, depth plane, clamp,
+// sign, projected bounding box).
+constexpr int kRecF4 = 5;
+constexpr int kRecBytes = 16 * kRecF4;
 
 // How one outer-volume evaluation is executed.  Default: scratch is sized from
 // the device counts (one host round trip).  planned: fixed scratch, no round
@@ -80,6 +86,7 @@ struct OvExec {
   int64_t n_rec = 0, n_bin = 0, n_items = 0;  // counts of the last synchronous run
   char* items = nullptr;                      // per-cull-item counts and offsets
   size_t items_cap = 0, items_bytes = 0;
+  int32_t* itile = nullptr;                   // [item_cap] tile of every ray-test work item
   uint32_t* status = nullptr;
   int64_t* publish = nullptr;
 };

@@ -15,7 +15,7 @@
 //   k_tile_count         per (box, axis, ray tile): number of binned triangles
 //   k_tiles_scan_*       bin, work-item and record offsets (3 kernels); unless the
 //                        scratch is capped or planned, one host sync for sizes
-//   k_write              per kept triangle: a 64-byte test record (edge and depth
+//   k_write              per kept triangle: an 80-byte test record (edge and depth
 //                        planes, fixed point) + its index in every tile bin
 //   k_test               one wave per ray tile: every ray against its bin
 //   k_finalize           float64 OBV per box
@@ -627,13 +627,14 @@ k_tile_count(CullArgs a, const int32_t* __restrict__ side, int32_t* __restrict__
   }
 }
 
-// The 64-byte test record of a kept triangle in its cast frame.
+// The 80-byte test record of a kept triangle in its cast frame.
 //   [0..8]   edge functions E_k(u, v) = A_k u + B_k v + C_k, k = edge (k -> k+1),
 //            oriented so that the inside of the projected triangle is E >= 0
 //   [9..11]  depth plane in fixed point: y(u, v) = D u + E v + F equals
 //            kMagic + s (w(u, v) + h) 2^21 / h, s = crossing sign
 //   [12..13] clamp of y to the part of the triangle inside the slab
 //   [14]     crossing sign s (+1 leaving the solid along +w in the cast frame)
+//   [16..19] projected bounding box: u min, u max, v min, v max
 // The edge coefficients of an edge shared by two triangles are exact
 // negatives of each other (or equal, when one of them is flipped), so the two
 // triangles classify every ray consistently: the test is watertight.
@@ -678,6 +679,8 @@ __device__ inline void make_record(const CastTri& t, bool mirror, float hw, floa
   out[1] = make_float4(Bc[1], C[1], A[2], Bc[2]);
   out[2] = make_float4(C[2], (float)(K * D), (float)(K * E), (float)(K * (F + h) + (double)kMagic));
   out[3] = make_float4((float)lo, (float)hi, (float)s, 0.0f);
+  out[4] = make_float4(fminf(fminf(t.u[0], t.u[1]), t.u[2]), fmaxf(fmaxf(t.u[0], t.u[1]), t.u[2]),
+                       fminf(fminf(t.v[0], t.v[1]), t.v[2]), fmaxf(fmaxf(t.v[0], t.v[1]), t.v[2]));
 }
 
 // Bin slots: every (tile) of the work item first counts its entries in LDS,
@@ -758,7 +761,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
         atomicOr(a.status, OBBV_STATUS_OVERFLOW);
         continue;
       }
-      make_record(tr, mirror, f.hw, recs + 4 * slot);
+      make_record(tr, mirror, f.hw, recs + kRecF4 * slot);
       int i0, i1, j0, j1;
       cell_range(tr, f, a.R, i0, i1, j0, j1);
       const int ti0 = i0 / a.TE, ti1 = i1 / a.TE, tj0 = j0 / a.TE, tj1 = j1 / a.TE;
@@ -804,6 +807,7 @@ struct TestArgs {
   uint32_t axis_mask;
   int64_t bin_cap;      // planned launches: bins beyond it were not written
   int64_t item_cap;     // planned launches: work items beyond it are skipped
+  const int32_t* item_tile;  // [work items] tile of every work item
   int persistent;       // 1: grid-stride over the work items counted on the device
 };
 
@@ -814,6 +818,15 @@ struct TestArgs {
 //   acc += inside ? bits(y) : kMagicBits   -- exact integer accumulation.
 template <int TE, bool STATS, bool STAGE, bool OCC>
 __device__ void test_item(const TestArgs& a, const int64_t item);
+
+// The tile of every work item (one thread per tile writes its chunks' entries).
+__global__ void k_item_tiles(const int64_t* __restrict__ chunk_off, int64_t n_tiles, int32_t* __restrict__ item_tile,
+                             int64_t cap) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int64_t c1 = min(chunk_off[t + 1], cap);
+  for (int64_t c = chunk_off[t]; c < c1; ++c) item_tile[c] = (int32_t)t;
+}
 
 template <int TE, bool STATS, bool STAGE, bool OCC>
 __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
@@ -831,15 +844,7 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
   constexpr int RPL = NB * NB;
   const int TT = a.tpe * a.tpe;
   // tile of this work item: chunk_off[g] <= item < chunk_off[g + 1]
-  int64_t lo = 0, hi = a.n_tiles;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a.chunk_off[mid] <= item)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  const int64_t g = lo;
+  const int64_t g = a.item_tile[item];
   const int bw = (int)(g / TT);
   const int tile = (int)(g - (int64_t)bw * TT);
   const int b = bw / 3, w = bw - 3 * (bw / 3);
@@ -916,7 +921,7 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
         const int idx = a.bins[base + lane];
         if ((unsigned)idx < (unsigned)a.n_rec) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) srec[4 * lane + q] = a.recs[4 * (int64_t)idx + q];
+          for (int q = 0; q < 4; ++q) srec[4 * lane + q] = a.recs[kRecF4 * (int64_t)idx + q];
         } else {  // a record no ray is inside of (only after a flagged write-pass mismatch)
           srec[4 * lane + 0] = make_float4(0.f, 0.f, -1.f, 0.f);
           srec[4 * lane + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -936,8 +941,8 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
         for (int r = 0; r < RPL; ++r) acc[r] += kMagicBits;
         continue;
       }
-      test_record(a.recs[4 * (int64_t)idx + 0], a.recs[4 * (int64_t)idx + 1], a.recs[4 * (int64_t)idx + 2],
-                  a.recs[4 * (int64_t)idx + 3]);
+      test_record(a.recs[kRecF4 * (int64_t)idx + 0], a.recs[kRecF4 * (int64_t)idx + 1],
+                  a.recs[kRecF4 * (int64_t)idx + 2], a.recs[kRecF4 * (int64_t)idx + 3]);
     }
   }
   const uint32_t nbias = (uint32_t)(k1 - k0) * kMagicBits;
@@ -968,6 +973,196 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) lane_sum += __shfl_xor(lane_sum, off);
   if (lane == 0 && lane_sum != 0) atomicAdd(&a.acc[bw], (unsigned long long)lane_sum);
+}
+
+// Rasterising ray test of 16 x 16-ray tiles.  Each lane takes one record and
+// tests only the rays of the cells its projected bounding box covers (the same
+// conservative cell range the binning used); a record covering more than
+// kRasterCells cells of the tile is tested by the whole wave instead, every lane
+// its four rays.  A crossing inside the triangle adds q = bits(y) - 0x4B400000
+// (the fixed-point inside length, as in k_test) to its ray's integer sum in LDS,
+// so the sums are exact and independent of the order.
+constexpr int kRasterCells = 16;
+
+__device__ inline bool ray_hit(float u, float v, const float4& r0, const float4& r1, const float4& r2,
+                               const float4& r3, int32_t& q) {
+  const float e0 = __fmaf_rn(r0.x, u, __fmaf_rn(r0.y, v, r0.z));
+  const float e1 = __fmaf_rn(r0.w, u, __fmaf_rn(r1.x, v, r1.y));
+  const float e2 = __fmaf_rn(r1.z, u, __fmaf_rn(r1.w, v, r2.x));
+  const float mn = fminf(fminf(e0, e1), e2);
+  const float y = __fmaf_rn(r2.y, u, __fmaf_rn(r2.z, v, r2.w));
+  const float c = __builtin_amdgcn_fmed3f(y, r3.x, r3.y);
+  q = (int32_t)(__float_as_uint(c) - kMagicBits);
+  return mn >= 0.0f;
+}
+
+template <bool STATS>
+__device__ void raster_item(const TestArgs& a, const int64_t item) {
+  const int TT = a.tpe * a.tpe;
+  const int64_t g = a.item_tile[item];
+  const int bw = (int)(g / TT);
+  const int tile = (int)(g - (int64_t)bw * TT);
+  const int b = bw / 3, w = bw - 3 * (bw / 3);
+  if (!((a.axis_mask >> w) & 1u)) return;
+  const BoxRegs B = load_box(a.boxes, b);
+  if (box_state(B) != 0) return;
+  const int ua = (w + 1) % 3, va = (w + 2) % 3;
+  const float huf = pick3(B.h, ua), hvf = pick3(B.h, va);
+  const double hu = huf, hv = hvf;
+  const double du = __ddiv_rn(__dmul_rn(2.0, hu), (double)a.R);
+  const double dv = __ddiv_rn(__dmul_rn(2.0, hv), (double)a.R);
+  const float eu = 1e-6f * huf, ev = 1e-6f * hvf;
+  const double idu = 1.0 / du, idv = 1.0 / dv;
+  const uint32_t key = a.box_key ? a.box_key[b] : (uint32_t)b;
+  const int ti = tile % a.tpe, tj = tile / a.tpe;
+  const int ci_lo = ti * 16, cj_lo = tj * 16;
+  const int ci_hi = min(ci_lo + 15, a.R - 1), cj_hi = min(cj_lo + 15, a.R - 1);
+  const int lane = threadIdx.x;
+  __shared__ float2 sray[256];
+  __shared__ int32_t sacc[256];
+  __shared__ int32_t shit[STATS ? 256 : 1];
+  float ru[4], rv[4];
+  bool valid[4];
+  int32_t racc[4];
+  int rhit[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = lane + 64 * k;
+    const int i = ci_lo + (r & 15), j = cj_lo + (r >> 4);
+    valid[k] = i < a.R && j < a.R;
+    ru[k] = rv[k] = 0.f;
+    if (valid[k]) {
+      const uint64_t n = ray_counter(key, w, i, j);
+      const double xi = u24(splitmix64_at(a.seed, n));
+      const double eta = u24(splitmix64_at(a.seed, n + 1));
+      ru[k] = (float)__dadd_rn(-hu, __dmul_rn(__dadd_rn((double)i, xi), du));
+      rv[k] = (float)__dadd_rn(-hv, __dmul_rn(__dadd_rn((double)j, eta), dv));
+    }
+    sray[r] = make_float2(ru[k], rv[k]);
+    sacc[r] = 0;
+    if (STATS) shit[r] = 0;
+    racc[k] = 0;
+    rhit[k] = 0;
+  }
+  __syncthreads();
+  const int64_t kb = a.bin_off[g] + (item - a.chunk_off[g]) * a.chunk;
+  const int64_t k0 = kb;
+  const int64_t k1 = min(a.bin_off[g + 1], kb + a.chunk);
+  int64_t tests = 0;
+  if (k1 <= a.bin_cap) {  // bins past a planned capacity were not written (flagged)
+    for (int64_t base = k0; base < k1; base += kTestThreads) {
+      const int n = (int)min((int64_t)kTestThreads, k1 - base);
+      bool have = lane < n, big = false;
+      float4 q0, q1, q2, q3, q4;
+      if (have) {
+        const int idx = a.bins[base + lane];
+        have = (unsigned)idx < (unsigned)a.n_rec;  // else only after a flagged write-pass mismatch
+        if (have) {
+          const float4* rp = a.recs + kRecF4 * (int64_t)idx;
+          q0 = rp[0];
+          q1 = rp[1];
+          q2 = rp[2];
+          q3 = rp[3];
+          q4 = rp[4];
+        }
+      }
+      if (have) {
+        // the binning's cell range, with reciprocals (the 1e-6 margins dwarf
+        // the difference from dividing)
+        int c0 = (int)floor(((double)q4.x - eu + hu) * idu);
+        int c1 = (int)floor(((double)q4.y + eu + hu) * idu);
+        int d0 = (int)floor(((double)q4.z - ev + hv) * idv);
+        int d1 = (int)floor(((double)q4.w + ev + hv) * idv);
+        c0 = max(ci_lo, max(0, c0));
+        c1 = min(ci_hi, c1);
+        d0 = max(cj_lo, max(0, d0));
+        d1 = min(cj_hi, d1);
+        const int cells = (c1 >= c0 && d1 >= d0) ? (c1 - c0 + 1) * (d1 - d0 + 1) : 0;
+        big = cells > kRasterCells;
+        if (!big) {
+          tests += cells;
+          for (int cj = d0; cj <= d1; ++cj)
+            for (int ci = c0; ci <= c1; ++ci) {
+              const int r = (ci - ci_lo) + 16 * (cj - cj_lo);
+              const float2 p = sray[r];
+              int32_t q;
+              if (ray_hit(p.x, p.y, q0, q1, q2, q3, q)) {
+                atomicAdd(&sacc[r], q);
+                if (STATS) atomicAdd(&shit[r], 1);
+              }
+            }
+        }
+      }
+      // records covering many cells: the whole wave, every lane its own rays
+      uint64_t bm = __ballot(have && big);
+      while (bm) {
+        const int src = __ffsll((long long)bm) - 1;
+        bm &= bm - 1;
+        float4 s0, s1, s2, s3;
+        s0.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.x), src));
+        s0.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.y), src));
+        s0.z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.z), src));
+        s0.w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.w), src));
+        s1.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.x), src));
+        s1.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.y), src));
+        s1.z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.z), src));
+        s1.w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.w), src));
+        s2.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.x), src));
+        s2.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.y), src));
+        s2.z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.z), src));
+        s2.w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.w), src));
+        s3.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q3.x), src));
+        s3.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q3.y), src));
+        s3.z = 0.f;
+        s3.w = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          int32_t q;
+          const bool in = ray_hit(ru[k], rv[k], s0, s1, s2, s3, q);
+          if (valid[k] && in) {
+            racc[k] += q;
+            if (STATS) ++rhit[k];
+          }
+        }
+        tests += lane == 0 ? (int64_t)(ci_hi - ci_lo + 1) * (cj_hi - cj_lo + 1) : 0;
+      }
+    }
+  }
+  __syncthreads();
+  int64_t lane_sum = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!valid[k]) continue;
+    const int r = lane + 64 * k;
+    const int32_t q = sacc[r] + racc[k];
+    lane_sum += q;
+    if (STATS) {
+      const int i = ci_lo + (r & 15), j = cj_lo + (r >> 4);
+      const int64_t o = ((int64_t)bw * a.R + i) * a.R + j;
+      if (a.ray_q) atomicAdd(&a.ray_q[o], q);
+      if (a.ray_hits) atomicAdd(&a.ray_hits[o], shit[r] + rhit[k]);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lane_sum += __shfl_xor(lane_sum, off);
+    tests += __shfl_xor(tests, off);
+  }
+  if (lane == 0 && lane_sum != 0) atomicAdd(&a.acc[bw], (unsigned long long)lane_sum);
+  if (lane == 0 && a.test_counter) atomicAdd(a.test_counter, (unsigned long long)tests);
+}
+
+template <bool STATS>
+__global__ void __launch_bounds__(kTestThreads) k_raster(TestArgs a) {
+  if (!a.persistent) {
+    raster_item<STATS>(a, xcd_remap(blockIdx.x, gridDim.x));
+    return;
+  }
+  const int64_t total = min(a.chunk_off[a.n_tiles], a.item_cap);
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    raster_item<STATS>(a, item);
+    __syncthreads();  // LDS of the next item
+  }
 }
 
 __global__ void k_or_word(uint32_t* __restrict__ w, uint32_t bits) { atomicOr(w, bits); }
@@ -1058,10 +1253,17 @@ int pinned_totals(int64_t** out) {
 
 namespace {
 
+bool test_raster_choice();
+
 template <int TE>
 int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hipStream_t s) {
   const dim3 g((unsigned)nblocks), b(kTestThreads);
-  if (ta.occ && TE == 8)
+  if (TE == 16 && !ta.occ && test_raster_choice()) {
+    if (stats)
+      hipLaunchKernelGGL((k_raster<true>), g, b, 0, s, ta);
+    else
+      hipLaunchKernelGGL((k_raster<false>), g, b, 0, s, ta);
+  } else if (ta.occ && TE == 8)
     hipLaunchKernelGGL((k_test<TE, false, true, true>), g, b, 0, s, ta);
   else if (stats && stage)
     hipLaunchKernelGGL((k_test<TE, true, true, false>), g, b, 0, s, ta);
@@ -1078,6 +1280,14 @@ int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hip
 // Record loading of the ray-test loop: 1 = LDS staging (default), 0 = scalar
 // loads in batches of four.  OBBV_TEST_STAGE overrides it (used to compare the
 // two on a device; staging measured faster).
+// Ray tests of 16 x 16 tiles: 1 = rasterising kernel (default), 0 = every ray of
+// the tile against every record.  OBBV_TEST_RASTER overrides it.
+bool test_raster_choice() {
+  const char* e = getenv("OBBV_TEST_RASTER");
+  if (e && *e) return atoi(e) != 0;
+  return true;
+}
+
 bool test_stage_choice() {
   const char* e = getenv("OBBV_TEST_STAGE");
   if (e && *e) return atoi(e) != 0;
@@ -1328,7 +1538,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       recs_v = ex->recs;
       bins_v = ex->bins;
     } else {
-      OBBV_RET(pool_get(kPoolRecords, (size_t)n_rec * 64, &recs_v));
+      OBBV_RET(pool_get(kPoolRecords, (size_t)n_rec * kRecBytes, &recs_v));
       OBBV_RET(pool_get(kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
     }
     hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
@@ -1351,6 +1561,15 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     ta.side = d_side;
     ta.bin_cap = fixed ? ex->bin_cap : INT64_MAX;
     ta.item_cap = fixed ? ex->item_cap : INT64_MAX;
+    int32_t* itile = nullptr;
+    if (fixed) {
+      itile = ex->itile;
+    } else {
+      void* tv = nullptr;
+      OBBV_RET(pool_get(kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * 4, &tv));
+      itile = (int32_t*)tv;
+    }
+    ta.item_tile = itile;
     ta.persistent = fixed ? 1 : 0;
     void* prof_token = nullptr;
     if (profiling_enabled() && !planned) {
@@ -1370,6 +1589,9 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       if (out_ray_hits) OBBV_HIP(hipMemsetAsync(out_ray_hits, 0, per, s));
     }
     if (n_items > 0) {
+      hipLaunchKernelGGL(k_item_tiles, dim3((unsigned)ceil_div(nbw * TT, 256)), dim3(256), 0, s,
+                         (const int64_t*)d_chunkoff, nbw * TT, itile, n_items);
+      OBBV_HIP(hipGetLastError());
       const bool stage = test_stage_choice();
       const int64_t grid = fixed ? std::min<int64_t>(n_items, 256 * 32) : n_items;
       if (TE == 8)
@@ -1741,8 +1963,8 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   ex.bin_cap = (int64_t)std::ceil((double)probe.n_bin * headroom) + 4096;
   ex.item_cap = (int64_t)std::ceil((double)probe.n_items * headroom) + 64;
   ex.items_cap = probe.items_bytes;
-  const size_t bytes = align_up(ex.meta_cap) + align_up((size_t)ex.rec_cap * 64) + align_up((size_t)ex.bin_cap * 4) +
-                       align_up(ex.items_cap);
+  const size_t bytes = align_up(ex.meta_cap) + align_up((size_t)ex.rec_cap * kRecBytes) + align_up((size_t)ex.bin_cap * 4) +
+                       align_up(ex.items_cap) + align_up((size_t)ex.item_cap * 4);
   if (hipMalloc(&P->alloc, bytes) != hipSuccess) {
     (void)hipGetLastError();
     set_error("hipMalloc of the planned scratch failed");
@@ -1750,8 +1972,9 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   }
   ex.meta = (char*)P->alloc;
   ex.recs = (float4*)(ex.meta + align_up(ex.meta_cap));
-  ex.bins = (int32_t*)((char*)ex.recs + align_up((size_t)ex.rec_cap * 64));
+  ex.bins = (int32_t*)((char*)ex.recs + align_up((size_t)ex.rec_cap * kRecBytes));
   ex.items = (char*)ex.bins + align_up((size_t)ex.bin_cap * 4);
+  ex.itile = (int32_t*)(ex.items + align_up(ex.items_cap));
   // the mesh table lives at the start of the meta block (outside the graph)
   std::vector<MeshDev> mh((size_t)n_meshes);
   for (int m = 0; m < n_meshes; ++m)
