@@ -54,6 +54,10 @@ int status_or(uint32_t bits, hipStream_t s);
 int fit_impl(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters, obbv_box* out_boxes,
              double* out_eigvals, hipStream_t st);
 int mlp_forward_impl(const float* params, const float* X, int32_t n, float* out_f, hipStream_t s);
+int mlp_pack_impl(const float* params, short* packed, hipStream_t s);
+int64_t mlp_packed_entries();
+int mlp_infer_packed(const float* params, const short* packed, const float* X, int32_t n, float* out_f,
+                     hipStream_t s);
 
 namespace {
 
@@ -346,10 +350,13 @@ struct Predictor {
   char* hbuf = nullptr;  // pinned staging: boxes in, predictions out (written by the device)
   char* hdev = nullptr;
   size_t hcap = 0;
+  short* packed = nullptr;  // bfloat16 transposed weights of cfg.mlp_params
+  bool packed_ready = false;
 
   ~Predictor() {
     if (dbuf) (void)hipFree(dbuf);
     if (hbuf) (void)hipHostFree(hbuf);
+    if (packed) (void)hipFree(packed);
   }
 
   int predict(const std::vector<HBox>& boxes, std::vector<float>& out) {
@@ -393,7 +400,19 @@ struct Predictor {
     OBBV_HIP(hipMemcpyAsync(db, hbuf, np * sizeof(obbv_box), hipMemcpyHostToDevice, stream));
     const int rc = obbv_sample_features(cfg.volume, cfg.N, cfg.frame, db, (int32_t)np, X, stream);
     if (rc != OBBV_OK) return rc;
-    OBBV_RET(mlp_forward_impl(cfg.mlp_params, X, (int32_t)np, (float*)(hdev + o_f), stream));
+    if (!packed) {
+      if (hipMalloc((void**)&packed, (size_t)mlp_packed_entries() * 2) != hipSuccess) {
+        (void)hipGetLastError();
+        packed = nullptr;
+        set_error("allocation failed for the ranker weights");
+        return OBBV_ERR_OOM;
+      }
+    }
+    if (!packed_ready) {
+      OBBV_RET(mlp_pack_impl(cfg.mlp_params, packed, stream));
+      packed_ready = true;
+    }
+    OBBV_RET(mlp_infer_packed(cfg.mlp_params, packed, X, (int32_t)np, (float*)(hdev + o_f), stream));
     OBBV_HIP(hipStreamSynchronize(stream));
     std::memcpy(out.data(), hbuf + o_f, n * 4);
     predicted += (int64_t)n;
@@ -1172,6 +1191,7 @@ extern "C" int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* su
   OBBV_ARG(sur->mlp_params && sur->volume && sur->frame, "surrogate arrays are NULL");
   OBBV_ARG(sur->N >= 1 && sur->verify_top >= 0 && sur->judge_every >= 1, "bad surrogate sizes");
   S.pred.cfg = *sur;
+  S.pred.packed_ready = false;
   S.pred.on = true;
   S.pred.paused = false;
   S.pred.window.clear();

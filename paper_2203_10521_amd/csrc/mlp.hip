@@ -155,6 +155,99 @@ __global__ void k_adam(float* __restrict__ P, float* __restrict__ m, float* __re
   P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: the three layers of 32 rows in one workgroup.  The weights
+// are pre-packed as bfloat16 and transposed ([out][in]) so that the four
+// consecutive inputs a lane feeds one MFMA step are one 8-byte load; the input
+// rows and the first hidden layer sit in LDS as bfloat16, the second hidden
+// layer in float32.  Same rounding points, operands and accumulation order as
+// the layer-by-layer path, hence the same bits.
+// ---------------------------------------------------------------------------
+constexpr int64_t kPacked = (int64_t)kIn * kH + (int64_t)kH * kH;  // bf16 entries
+
+__global__ void k_mlp_pack(const float* __restrict__ P, short* __restrict__ W) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kPacked) return;
+  if (i < (int64_t)kIn * kH) {
+    const int o = (int)(i / kIn), k = (int)(i - (int64_t)o * kIn);
+    W[i] = f2bf(P[oW1 + (int64_t)k * kH + o]);
+  } else {
+    const int64_t j = i - (int64_t)kIn * kH;
+    const int o = (int)(j / kH), k = (int)(j - (int64_t)o * kH);
+    W[i] = f2bf(P[oW2 + (int64_t)k * kH + o]);
+  }
+}
+
+constexpr int kFusedRows = 32;
+constexpr int kH2Pitch = kH + 1;
+
+__global__ void __launch_bounds__(256)
+k_mlp_infer(const float* __restrict__ P, const short* __restrict__ W, const float* __restrict__ X,
+            float* __restrict__ f) {
+  __shared__ short sx[kFusedRows * kIn];
+  __shared__ short sh1[kFusedRows * kH];
+  __shared__ float sh2[kFusedRows * kH2Pitch];
+  const int64_t row0 = (int64_t)blockIdx.x * kFusedRows;
+  for (int i = threadIdx.x; i < kFusedRows * kIn; i += blockDim.x) sx[i] = f2bf(X[row0 * kIn + i]);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 31, kq = (lane >> 5) * 4;
+  const short* W1t = W;
+  const short* W2t = W + (int64_t)kIn * kH;
+  // layer 1: this wave's 64 outputs as two 32 x 32 tiles
+  {
+    const int nA = 64 * wave + r, nB = nA + 32;
+    v16f a0, a1;
+    for (int i = 0; i < 16; ++i) a0[i] = a1[i] = 0.f;
+    for (int k0 = 0; k0 < kIn; k0 += 8) {
+      const v4s x = *reinterpret_cast<const v4s*>(&sx[r * kIn + k0 + kq]);
+      const v4s bA = *reinterpret_cast<const v4s*>(&W1t[(int64_t)nA * kIn + k0 + kq]);
+      const v4s bB = *reinterpret_cast<const v4s*>(&W1t[(int64_t)nB * kIn + k0 + kq]);
+      a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, bA, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, bB, a1, 0, 0, 0);
+    }
+    for (int rr = 0; rr < 16; ++rr) {
+      const int row = 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4);
+      const int cA = 64 * wave + (lane & 31), cB = cA + 32;
+      sh1[row * kH + cA] = f2bf(fmaxf(a0[rr] + P[ob1 + cA], 0.f));
+      sh1[row * kH + cB] = f2bf(fmaxf(a1[rr] + P[ob1 + cB], 0.f));
+    }
+  }
+  __syncthreads();
+  // layer 2
+  {
+    const int nA = 64 * wave + r, nB = nA + 32;
+    v16f a0, a1;
+    for (int i = 0; i < 16; ++i) a0[i] = a1[i] = 0.f;
+    for (int k0 = 0; k0 < kH; k0 += 8) {
+      const v4s h = *reinterpret_cast<const v4s*>(&sh1[r * kH + k0 + kq]);
+      const v4s bA = *reinterpret_cast<const v4s*>(&W2t[(int64_t)nA * kH + k0 + kq]);
+      const v4s bB = *reinterpret_cast<const v4s*>(&W2t[(int64_t)nB * kH + k0 + kq]);
+      a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(h, bA, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(h, bB, a1, 0, 0, 0);
+    }
+    for (int rr = 0; rr < 16; ++rr) {
+      const int row = 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4);
+      const int cA = 64 * wave + (lane & 31), cB = cA + 32;
+      sh2[row * kH2Pitch + cA] = fmaxf(a0[rr] + P[ob2 + cA], 0.f);
+      sh2[row * kH2Pitch + cB] = fmaxf(a1[rr] + P[ob2 + cB], 0.f);
+    }
+  }
+  __syncthreads();
+  // head, one thread per row (the order of k_head)
+  if (threadIdx.x < kFusedRows) {
+    const int row = threadIdx.x;
+    float z = 0.f;
+    for (int c = 0; c < kH; ++c) z = fmaf(bf(sh2[row * kH2Pitch + c]), bf(P[ow3 + c]), z);
+    z += P[ob3];
+    const float* x = X + (row0 + row) * kIn;
+    float occ = 0.f;
+    for (int c = 15; c < 527; ++c) occ += x[c];
+    const float sig = 1.f / (1.f + expf(-z));
+    f[row0 + row] = (1.f - occ / 512.f) + sig - 0.5f;
+  }
+}
+
 struct MlpScratch {
   float* H1;
   float* H2;
@@ -202,13 +295,31 @@ int forward(const float* P, const float* X, int n, MlpScratch& S, float* out_f, 
 
 }  // namespace
 
+int mlp_pack_impl(const float* params, short* packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((unsigned)((kPacked + 255) / 256)), dim3(256), 0, s, params, packed);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+int64_t mlp_packed_entries() { return kPacked; }
+
+int mlp_infer_packed(const float* params, const short* packed, const float* X, int32_t n, float* out_f,
+                     hipStream_t s) {
+  OBBV_ARG(n >= 0 && n % kFusedRows == 0, "n must be a non-negative multiple of 32");
+  if (n == 0) return OBBV_OK;
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)(n / kFusedRows)), dim3(256), 0, s, params, packed, X, out_f);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
 int mlp_forward_impl(const float* params, const float* X, int32_t n, float* out_f, hipStream_t s) {
   OBBV_ARG(params && X && out_f, "NULL argument");
   OBBV_ARG(n >= 0 && n % 32 == 0, "n must be a non-negative multiple of 32");
   if (n == 0) return OBBV_OK;
-  MlpScratch S;
-  OBBV_RET(mlp_scratch(n, S));
-  return forward(params, X, n, S, out_f, nullptr, s);
+  void* pv = nullptr;
+  OBBV_RET(pool_get(kPoolMlp, (size_t)kPacked * 2, &pv));
+  OBBV_RET(mlp_pack_impl(params, (short*)pv, s));
+  return mlp_infer_packed(params, (const short*)pv, X, n, out_f, s);
 }
 
 }  // namespace obbv
