@@ -240,8 +240,10 @@ typedef struct {
                               the last 256 judged candidates above which the rest
                               of the Lloyd iteration evaluates every candidate
                               exactly                                             */
-  int32_t judge_every;     /* every judge_every-th flood round evaluates every
-                              candidate exactly and judges the ranker (>= 1)      */
+  int32_t judge_every;     /* every judge_every-th ranked flood round, a sample of
+                              its candidates is evaluated exactly (on a stream
+                              of the library's own, while the flood goes on) to
+                              judge the ranker (>= 1)                             */
 } obbv_surrogate;
 
 typedef struct {
@@ -278,16 +280,18 @@ int obbv_lloyd_step(obbv_lloyd* st, void* stream);
  * fraction f of every candidate box (a box grown by a popped triangle that no box
  * of its group contains) and of the current boxes, with the predicted change
  * dOBV = max(0, f(grown) V(grown) - f(current) V(current)) (Eq. 12).  In an
- * ordinary round, of the candidates a box receives only the verify_top with the
+ * ranked round, of the candidates a box receives only the verify_top with the
  * smallest predicted change are evaluated exactly, and every triangle goes to
  * the box with the smallest change (exact where evaluated, predicted elsewhere);
- * a round with nothing to verify makes no outer-volume call at all.  Every
- * judge_every-th round evaluates every candidate exactly, decides on the exact
- * values and judges the ranker with them: when the rolling error exceeds
- * max_error the rest of that iteration is exact (counted as a fallback).  The
- * outer volumes of grown boxes, the final boxes of the flood and the parameter
- * update stay exact.  NULL returns to exact evaluation of every candidate.  The
- * structure is copied; its device arrays must stay valid. */
+ * a round with nothing to verify makes no outer-volume call on the caller's
+ * stream.  Every judge_every-th ranked round also sends up to 256 of its
+ * candidates (evenly strided) to an exact evaluation on a second stream; when
+ * it has finished (checked at the start of each round, awaited at the end of the
+ * flood) the errors |predicted - exact| outer fraction enter a rolling mean over
+ * the last 256: above max_error the rest of that iteration is exact (counted as
+ * a fallback).  The outer volumes of grown boxes, the final boxes of the flood
+ * and the parameter update stay exact.  NULL returns to exact evaluation of
+ * every candidate.  The structure is copied; its device arrays must stay valid. */
 int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* surrogate);
 
 /* Host.  Results of the last step (each output nullable, host):
@@ -384,6 +388,15 @@ int64_t obbv_mlp_param_count(void);
  * f = (1 - mean of X[15..526]) + sigmoid(z) - 1/2, z the MLP output.  Products
  * on bfloat16 MFMA with float32 accumulation. */
 int obbv_mlp_forward(const float* params, const float* X, int32_t n, float* out_f, void* stream);
+
+/* Predicted outer fraction of n_boxes boxes in one launch: the input rows of
+ * obbv_sample_features are built on chip and fed to the network of
+ * obbv_mlp_forward; out_f (device or mapped host [n_boxes], any n_boxes >= 0)
+ * receives the same bits as obbv_sample_features followed by obbv_mlp_forward.
+ * `boxes` may be device memory or mapped pinned host memory (each box is read
+ * once).  Used by the Lloyd flood's ranked rounds. */
+int obbv_mlp_rank_boxes(const float* params, const float* volume, int32_t N, const float* frame,
+                        const obbv_box* boxes, int32_t n_boxes, float* out_f, void* stream);
 
 /* One training step on n rows (multiple of 32): forward, mean squared error
  * against target (device [n]), backward, Adam update (lr > 0; step counts from

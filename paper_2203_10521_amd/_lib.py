@@ -78,6 +78,7 @@ SIGNATURES = {
     "obbv_sample_features": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "obbv_mlp_param_count": (ctypes.c_int64, []),
     "obbv_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "obbv_mlp_rank_boxes": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "obbv_mlp_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32,
                                       ctypes.c_float, c_void_p, c_void_p, c_void_p]),
     "obbv_lloyd_create": (c_int32, [ctypes.POINTER(ObbvMesh), ctypes.POINTER(ObbvLloydParams),

@@ -383,6 +383,17 @@ def sample_features(volume, frame, boxes, stream=None):
     return X
 
 
+
+def mlp_rank_boxes(params, volume, frame, boxes, stream=None):
+    """Predicted outer fractions of `boxes` [n, 15] in one launch (inputs sampled
+    from `volume` on chip); the same bits as mlp_forward(sample_features(...))."""
+    _dev(params, torch.float32, "params")
+    _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
+    f = torch.empty(boxes.shape[0], dtype=torch.float32, device=boxes.device)
+    _check(_lib.lib().obbv_mlp_rank_boxes(_ptr(params), _ptr(volume), volume.shape[0], _ptr(frame), _ptr(boxes),
+                                          boxes.shape[0], _ptr(f), _stream(stream)))
+    return f
+
 class OuterVolumePlan:
     """obbv_ov_plan_*: an autotuned, graph-captured evaluation of fixed arrays."""
 

@@ -52,12 +52,16 @@ enum PoolSlot {
   kPoolLists = 6,
   kPoolItems = 7,
   kPoolTiles = 8,
-  kPoolCount = 9
+  kPoolRank = 9,
+  kPoolCount = 10
 };
+// Two sets of the slots: calls that may run at the same time on different
+// streams take their scratch from different sets (slot + set * kPoolCount).
+constexpr int kPoolSets = 2;
 
-// Ensures slot `slot` of the current device holds at least `bytes` and returns it.
-// Growing frees the old block (hipFree waits for the device), so call it only
-// where no queued kernel still reads that slot.
+// Ensures slot `slot` (< kPoolCount * kPoolSets) of the current device holds at
+// least `bytes` and returns it.  Growing frees the old block (hipFree waits for
+// the device), so call it only where no queued kernel still reads that slot.
 int pool_get(int slot, size_t bytes, void** out);
 
 // A ray-test record: 5 float4 = 80 bytes (edge planes, depth plane, clamp,
@@ -89,6 +93,7 @@ struct OvExec {
   int32_t* itile = nullptr;                   // [item_cap] tile of every ray-test work item
   uint32_t* status = nullptr;
   int64_t* publish = nullptr;
+  int pool_base = 0;  // slot offset of the pool set the call's pooled scratch comes from
 };
 int status_word(uint32_t** out);   // device pointer of this device's status word
 

@@ -56,8 +56,10 @@ int fit_impl(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_cluste
 int mlp_forward_impl(const float* params, const float* X, int32_t n, float* out_f, hipStream_t s);
 int mlp_pack_impl(const float* params, short* packed, hipStream_t s);
 int64_t mlp_packed_entries();
-int mlp_infer_packed(const float* params, const short* packed, const float* X, int32_t n, float* out_f,
-                     hipStream_t s);
+int mlp_rank_packed(const float* params, const short* packed, const float* volume, int32_t N, const float* frame,
+                    const obbv_box* boxes, int32_t n, void* scratch, float* out_f, hipStream_t s,
+                    unsigned* done_count, unsigned* done_flag, unsigned seq);
+size_t mlp_rank_scratch_bytes(int32_t n);
 
 namespace {
 
@@ -75,6 +77,12 @@ struct WallTimer {
   void start() { t0 = std::chrono::steady_clock::now(); }
   void stop() { s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
+
+// host-side sections of the flood rounds (measurement only)
+struct FloodTimers {
+  WallTimer pops, cands, rank_post, exact_post, decide, grow, pred_pack, pred_launch, pred_wait;
+};
+static FloodTimers g_ft;
 
 inline float f32_up(double x) {
   float y = (float)x;
@@ -162,9 +170,51 @@ struct Evaluator {
 
   static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-  int eval(const std::vector<HBox>& boxes, const std::vector<uint32_t>& keys, std::vector<double>& out) {
+  // the evaluation between begin() and finish()
+  const std::vector<HBox>* cur_boxes = nullptr;
+  size_t cur_n = 0, cur_nf = 0, o_box = 0, o_key = 0, o_frame = 0, o_bf = 0, o_ctl = 0, o_out = 0;
+  bool cur_shared = false, in_flight = false;
+  int pool_base = 0;  // pool set of the outer-volume scratch (one per concurrent stream)
+
+  // `overlap` (nullable) runs on the host while the device evaluates
+  int eval(const std::vector<HBox>& boxes, const std::vector<uint32_t>& keys, std::vector<double>& out,
+           const std::function<void()>* overlap = nullptr) {
+    OBBV_RET(begin(boxes, keys));
+    if (overlap) (*overlap)();
+    return finish(out);
+  }
+
+  // the device has published the enqueued evaluation (k_finalize's done word)
+  bool published() const {
+    return __atomic_load_n((const int64_t*)(hbuf + o_ctl + 64) + 4, __ATOMIC_ACQUIRE) != 0;
+  }
+  // the enqueued evaluation has finished (no wait)
+  bool ready() const { return !in_flight || published(); }
+
+  int run_call(OvExec* ex) {
+    ex->pool_base = pool_base;
+    double* hout = (double*)(hdev + o_out);  // results go straight to pinned host memory
+    if (cur_shared)
+      return outer_volume_frames(&mesh, (const obbv_box*)(dbuf + o_box), (const uint32_t*)(dbuf + o_key),
+                                 (int32_t)cur_n, &params, (const obbv_box*)(dbuf + o_frame),
+                                 (const int32_t*)(dbuf + o_bf), (int32_t)cur_nf, hout, stream, ex);
+    return outer_volume_exec(&mesh, (const obbv_box*)(dbuf + o_box), (const uint32_t*)(dbuf + o_key),
+                             (int32_t)cur_n, &params, hout, stream, ex);
+  }
+
+  // Stages the boxes and enqueues their evaluation on `stream`; finish() waits
+  // and returns the values.  `boxes` must stay unchanged until finish().  Before
+  // the scratch capacities are known (first call) the evaluation is sized with a
+  // host round trip.
+  int begin(const std::vector<HBox>& boxes, const std::vector<uint32_t>& keys) {
+    if (in_flight) {
+      set_error("internal: evaluation started while another is in flight");
+      return OBBV_ERR_INVALID_ARG;
+    }
     const size_t n = boxes.size();
-    out.assign(n, 0.0);
+    cur_boxes = &boxes;
+    cur_n = n;
+    in_flight = false;
     if (n == 0) return OBBV_OK;
     t_prep.start();
     // Candidates of one box share its centre and axes: group them into frames so
@@ -211,8 +261,14 @@ struct Evaluator {
     }
     const size_t nf = fr.size();
     const bool shared = 2 * nf <= n;
-    const size_t o_box = 0, o_key = al(n * sizeof(obbv_box)), o_frame = o_key + al(n * 4);
-    const size_t o_bf = o_frame + al(nf * sizeof(obbv_box)), o_ctl = o_bf + al(n * 4), o_out = o_ctl + 256;
+    cur_nf = nf;
+    cur_shared = shared;
+    o_box = 0;
+    o_key = al(n * sizeof(obbv_box));
+    o_frame = o_key + al(n * 4);
+    o_bf = o_frame + al(nf * sizeof(obbv_box));
+    o_ctl = o_bf + al(n * 4);
+    o_out = o_ctl + 256;
     const size_t need = o_out + al(n * 8);
     if (need > cap) {
       if (dbuf) {
@@ -259,20 +315,7 @@ struct Evaluator {
     t_prep.stop();
     t_dev.start();
     OBBV_HIP(hipMemcpyAsync(dbuf, hbuf, o_out, hipMemcpyHostToDevice, stream));
-    double* hout = (double*)(hdev + o_out);  // results go straight to pinned host memory
-    uint32_t* dstatus = (uint32_t*)(dbuf + o_ctl);
-    int64_t* pub = (int64_t*)(hdev + o_ctl + 64);
-    const int64_t* hpub = (const int64_t*)(hbuf + o_ctl + 64);
-    auto run = [&](OvExec* ex) -> int {
-      if (shared)
-        return outer_volume_frames(&mesh, (const obbv_box*)(dbuf + o_box), (const uint32_t*)(dbuf + o_key),
-                                   (int32_t)n, &params, (const obbv_box*)(dbuf + o_frame),
-                                   (const int32_t*)(dbuf + o_bf), (int32_t)nf, hout, stream, ex);
-      return outer_volume_exec(&mesh, (const obbv_box*)(dbuf + o_box), (const uint32_t*)(dbuf + o_key), (int32_t)n,
-                               &params, hout, stream, ex);
-    };
-    bool done = false;
-    if (rec_cap > 0) {  // one pass, no round trip; checked afterwards
+    if (rec_cap > 0) {  // one pass, no round trip; checked by finish()
       OvExec ex;
       ex.capped = true;
       ex.recs = (float4*)sbuf;
@@ -281,10 +324,38 @@ struct Evaluator {
       ex.rec_cap = rec_cap;
       ex.bin_cap = bin_cap;
       ex.item_cap = item_cap;
-      ex.status = dstatus;
-      ex.publish = pub;
-      OBBV_RET(run(&ex));
-      OBBV_HIP(hipStreamSynchronize(stream));
+      ex.status = (uint32_t*)(dbuf + o_ctl);
+      ex.publish = (int64_t*)(hdev + o_ctl + 64);
+      OBBV_RET(run_call(&ex));
+      in_flight = true;
+    }
+    return OBBV_OK;
+  }
+
+  int finish(std::vector<double>& out) {
+    const size_t n = cur_n;
+    out.assign(n, 0.0);
+    if (n == 0) return OBBV_OK;
+    bool done = false;
+    if (in_flight) {
+      in_flight = false;
+      // spin on the published done word (no runtime wake-up latency, the host
+      // stays warm); after 10 s without it, wait on the stream, which reports a
+      // failed launch
+      auto t0 = std::chrono::steady_clock::now();
+      for (uint64_t spin = 0; !published(); ++spin) {
+        if ((spin & 4095) == 4095 &&
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > 10.0) {
+          OBBV_HIP(hipStreamSynchronize(stream));
+          if (!published()) {
+            set_error("outer-volume call finished without publishing");
+            return OBBV_ERR_HIP;
+          }
+          break;
+        }
+        __builtin_ia32_pause();
+      }
+      const int64_t* hpub = (const int64_t*)(hbuf + o_ctl + 64);
       const uint32_t st = (uint32_t)hpub[0];
       if (!(st & OBBV_STATUS_OVERFLOW) && hpub[1] <= rec_cap && hpub[2] <= bin_cap && hpub[3] <= item_cap) {
         done = true;
@@ -295,7 +366,7 @@ struct Evaluator {
     }
     if (!done) {  // sized from the device counts; then capacities for the next calls
       OvExec probe;
-      OBBV_RET(run(&probe));
+      OBBV_RET(run_call(&probe));
       OBBV_HIP(hipStreamSynchronize(stream));
       OBBV_RET(grow(probe.n_rec, probe.n_bin, probe.n_items));
     }
@@ -303,7 +374,7 @@ struct Evaluator {
     std::memcpy(out.data(), hbuf + o_out, n * 8);
     evals += (int64_t)n;
     ++calls;
-    if (smp_cap > 0) record(boxes, out);
+    if (smp_cap > 0) record(*cur_boxes, out);
     return OBBV_OK;
   }
 };
@@ -315,8 +386,6 @@ struct Predictor {
   obbv_surrogate cfg{};
   bool on = false;
   hipStream_t stream = nullptr;
-  char* dbuf = nullptr;
-  size_t cap = 0;
   bool paused = false;  // the judge found the ranker off: exact evaluation until the next iteration
   WallTimer t_pred;
   double err_sum = 0.0;
@@ -352,54 +421,126 @@ struct Predictor {
   size_t hcap = 0;
   short* packed = nullptr;  // bfloat16 transposed weights of cfg.mlp_params
   bool packed_ready = false;
+  char* dbuf = nullptr;  // device: bfloat16 input rows and occupancy sums
+  size_t dcap = 0;
+  unsigned* sig_host = nullptr;  // completion flag (mapped host memory) and its device view
+  unsigned* sig_dev = nullptr;
+  unsigned* sig_count = nullptr;  // device: workgroups finished in the current call
+  unsigned sig_seq = 0;
+
+  // Judge: every judge_every-th ranked round, a sample of the round's candidates
+  // is evaluated exactly on a stream of its own (scratch from the second pool
+  // set) while the flood goes on; the errors enter the judge when it finishes.
+  Evaluator jev;
+  hipStream_t jstream = nullptr;
+  std::vector<HBox> jboxes;
+  std::vector<uint32_t> jkeys;
+  std::vector<float> jpred;
+  std::vector<double> jvals;
+  int64_t judged_evals = 0;
+
+  bool judge_busy() const { return jev.in_flight; }
+
+  int judge_begin(const Evaluator& ev, const std::vector<HBox>& cb, const std::vector<uint32_t>& ck,
+                  const std::vector<float>& fp, size_t n) {
+    if (n == 0 || jev.in_flight) return OBBV_OK;
+    if (!jstream) {
+      OBBV_HIP(hipStreamCreateWithFlags(&jstream, hipStreamNonBlocking));
+      jev.stream = jstream;
+      jev.pool_base = kPoolCount;
+    }
+    jev.mesh = ev.mesh;
+    jev.params = ev.params;
+    const size_t stride = (n + kWindow - 1) / kWindow;  // at most one window per judged round
+    jboxes.clear();
+    jkeys.clear();
+    jpred.clear();
+    for (size_t z = 0; z < n; z += stride) {
+      jboxes.push_back(cb[z]);
+      jkeys.push_back(ck[z]);
+      jpred.push_back(fp[z]);
+    }
+    return jev.begin(jboxes, jkeys);
+  }
+
+  // Takes the finished judge evaluation (waits for it with `wait`).
+  int judge_poll(bool wait) {
+    if (!jev.in_flight && jev.cur_n == 0) return OBBV_OK;
+    if (!wait && !jev.ready()) return OBBV_OK;
+    OBBV_RET(jev.finish(jvals));
+    jev.cur_n = 0;
+    judged_evals += (int64_t)jvals.size();
+    for (size_t x = 0; x < jvals.size(); ++x) {
+      const HBox& bx = jboxes[x];
+      const double vb = 8.0 * (double)bx.h[0] * (double)bx.h[1] * (double)bx.h[2];
+      if (vb > 0.0) judge(std::fabs((double)jpred[x] - jvals[x] / vb));
+    }
+    return OBBV_OK;
+  }
 
   ~Predictor() {
+    if (jstream) {
+      (void)hipStreamSynchronize(jstream);
+      (void)hipStreamDestroy(jstream);
+    }
+    if (stream) (void)hipStreamSynchronize(stream);
     if (dbuf) (void)hipFree(dbuf);
     if (hbuf) (void)hipHostFree(hbuf);
     if (packed) (void)hipFree(packed);
+    if (sig_host) (void)hipHostFree(sig_host);
+    if (sig_count) (void)hipFree(sig_count);
   }
 
-  int predict(const std::vector<HBox>& boxes, std::vector<float>& out) {
-    const size_t n = boxes.size();
-    const size_t np = (n + 31) / 32 * 32;
+  // Predicted outer fractions of `boxes`: the boxes are staged in mapped pinned
+  // memory, two launches sample their inputs and run the network, the
+  // predictions land in mapped memory and the last workgroup raises a flag there
+  // that the host spins on.
+  int predict(const std::vector<HBox>& boxes_a, const std::vector<HBox>& boxes_b, std::vector<float>& out,
+              const std::function<void()>* overlap = nullptr) {
+    const size_t na = boxes_a.size(), n = na + boxes_b.size();
     out.assign(n, 0.f);
     if (n == 0) return OBBV_OK;
     t_pred.start();
-    const size_t o_f = (np * sizeof(obbv_box) + 255) & ~(size_t)255;
-    const size_t hneed = o_f + np * 4;
-    const size_t need = o_f + np * 544 * 4 + 1024;
-    if (need > cap || hneed > hcap) {
+    const size_t o_f = (n * sizeof(obbv_box) + 255) & ~(size_t)255;
+    const size_t hneed = o_f + n * 4;
+    if (hneed > hcap) {
       OBBV_HIP(hipStreamSynchronize(stream));
-      if (dbuf) OBBV_HIP(hipFree(dbuf));
       if (hbuf) OBBV_HIP(hipHostFree(hbuf));
-      dbuf = hbuf = hdev = nullptr;
-      cap = hcap = 0;
-      const size_t want = std::max(need * 2, (size_t)1 << 20), hwant = std::max(hneed * 2, (size_t)1 << 16);
-      if (hipMalloc((void**)&dbuf, want) != hipSuccess ||
-          hipHostMalloc((void**)&hbuf, hwant, hipHostMallocDefault) != hipSuccess ||
+      hbuf = hdev = nullptr;
+      hcap = 0;
+      const size_t hwant = std::max(hneed * 2, (size_t)1 << 16);
+      if (hipHostMalloc((void**)&hbuf, hwant, hipHostMallocDefault) != hipSuccess ||
           hipHostGetDevicePointer((void**)&hdev, hbuf, 0) != hipSuccess) {
         (void)hipGetLastError();
         set_error("allocation failed for the ranker buffers");
         return OBBV_ERR_OOM;
       }
-      cap = want;
       hcap = hwant;
     }
-    obbv_box* hb = (obbv_box*)hbuf;
-    for (size_t i = 0; i < np; ++i) {
-      if (i < n) {
-        std::memcpy(hb[i].center, boxes[i].c, 12);
-        std::memcpy(hb[i].axes, boxes[i].Q, 36);
-        std::memcpy(hb[i].half, boxes[i].h, 12);
-      } else {
-        std::memset(&hb[i], 0, sizeof(obbv_box));
+    const size_t dneed = mlp_rank_scratch_bytes((int32_t)n);
+    if (dneed > dcap) {
+      OBBV_HIP(hipStreamSynchronize(stream));
+      if (dbuf) OBBV_HIP(hipFree(dbuf));
+      dbuf = nullptr;
+      dcap = 0;
+      const size_t want = std::max(dneed * 2, (size_t)1 << 20);
+      if (hipMalloc((void**)&dbuf, want) != hipSuccess) {
+        (void)hipGetLastError();
+        dbuf = nullptr;
+        set_error("allocation failed for the ranker inputs");
+        return OBBV_ERR_OOM;
       }
+      dcap = want;
     }
-    obbv_box* db = (obbv_box*)dbuf;
-    float* X = (float*)(dbuf + o_f);
-    OBBV_HIP(hipMemcpyAsync(db, hbuf, np * sizeof(obbv_box), hipMemcpyHostToDevice, stream));
-    const int rc = obbv_sample_features(cfg.volume, cfg.N, cfg.frame, db, (int32_t)np, X, stream);
-    if (rc != OBBV_OK) return rc;
+    g_ft.pred_pack.start();
+    obbv_box* hb = (obbv_box*)hbuf;
+    for (size_t i = 0; i < n; ++i) {
+      const HBox& bx = i < na ? boxes_a[i] : boxes_b[i - na];
+      std::memcpy(hb[i].center, bx.c, 12);
+      std::memcpy(hb[i].axes, bx.Q, 36);
+      std::memcpy(hb[i].half, bx.h, 12);
+    }
+    g_ft.pred_pack.stop();
     if (!packed) {
       if (hipMalloc((void**)&packed, (size_t)mlp_packed_entries() * 2) != hipSuccess) {
         (void)hipGetLastError();
@@ -412,8 +553,40 @@ struct Predictor {
       OBBV_RET(mlp_pack_impl(cfg.mlp_params, packed, stream));
       packed_ready = true;
     }
-    OBBV_RET(mlp_infer_packed(cfg.mlp_params, packed, X, (int32_t)np, (float*)(hdev + o_f), stream));
-    OBBV_HIP(hipStreamSynchronize(stream));
+    if (!sig_host) {  // completion signal: a device counter and a flag in mapped host memory
+      if (hipHostMalloc((void**)&sig_host, 64, hipHostMallocDefault) != hipSuccess ||
+          hipHostGetDevicePointer((void**)&sig_dev, sig_host, 0) != hipSuccess ||
+          hipMalloc((void**)&sig_count, 64) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("allocation failed for the ranker signal");
+        return OBBV_ERR_OOM;
+      }
+      OBBV_HIP(hipMemset(sig_count, 0, 64));
+      __atomic_store_n(sig_host, 0u, __ATOMIC_RELEASE);
+    }
+    const unsigned seq = ++sig_seq;
+    g_ft.pred_launch.start();
+    OBBV_RET(mlp_rank_packed(cfg.mlp_params, packed, cfg.volume, cfg.N, cfg.frame, (const obbv_box*)hdev, (int32_t)n,
+                             dbuf, (float*)(hdev + o_f), stream, sig_count, sig_dev, seq));
+    g_ft.pred_launch.stop();
+    if (overlap) (*overlap)();  // host work for later rounds while the device ranks
+    g_ft.pred_wait.start();
+    // spin on the flag (no runtime wake-up latency); after 10 s without it, wait
+    // on the stream, which reports a failed launch
+    auto t0 = std::chrono::steady_clock::now();
+    for (uint64_t spin = 0; __atomic_load_n(sig_host, __ATOMIC_ACQUIRE) != seq; ++spin) {
+      if ((spin & 4095) == 4095 &&
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > 10.0) {
+        OBBV_HIP(hipStreamSynchronize(stream));
+        if (__atomic_load_n(sig_host, __ATOMIC_ACQUIRE) != seq) {
+          set_error("ranker kernels finished without their completion flag");
+          return OBBV_ERR_HIP;
+        }
+        break;
+      }
+      __builtin_ia32_pause();
+    }
+    g_ft.pred_wait.stop();
     std::memcpy(out.data(), hbuf + o_f, n * 4);
     predicted += (int64_t)n;
     t_pred.stop();
@@ -498,6 +671,24 @@ struct Elements {
   std::vector<int32_t> tri_off, tris;  // CSR: triangles of each element
   std::vector<double> cen;             // [n][3] element centroid
   std::vector<int32_t> adj_off, adj;   // CSR: adjacent elements
+  std::vector<int64_t> vtx_off;        // CSR into vtx (3 doubles per vertex)
+  std::vector<double> vtx;             // the vertices of each element's triangles
+
+  // float64 copies of the vertices of every element's triangles, element by
+  // element (the extent test of a candidate reads one contiguous run)
+  void build_vertices(const HostMesh& M) {
+    vtx_off.assign((size_t)n + 1, 0);
+    vtx.clear();
+    vtx.reserve((size_t)tris.size() * 9);
+    for (int e = 0; e < n; ++e) {
+      for (int x = tri_off[e]; x < tri_off[e + 1]; ++x)
+        for (int k = 0; k < 3; ++k) {
+          const int vi = M.F[3 * tris[x] + k];
+          for (int d = 0; d < 3; ++d) vtx.push_back((double)M.V[3 * vi + d]);
+        }
+      vtx_off[e + 1] = (int64_t)vtx.size();
+    }
+  }
 
   static Elements triangles(const HostMesh& M) {
     Elements E;
@@ -509,9 +700,21 @@ struct Elements {
     E.cen = M.cen;
     E.adj_off = M.adj_off;
     E.adj = M.adj;
+    E.build_vertices(M);
     return E;
   }
 };
+
+// element_extent with the box centre and axes already in float64 (the same
+// arithmetic, from the element's contiguous vertex copies)
+inline void element_extent_fast(const Elements& E, int e, const double c[3], const double Q[9], double out[3]) {
+  out[0] = out[1] = out[2] = 0.0;
+  for (int64_t x = E.vtx_off[e]; x < E.vtx_off[e + 1]; x += 3) {
+    const double p0 = E.vtx[x] - c[0], p1 = E.vtx[x + 1] - c[1], p2 = E.vtx[x + 2] - c[2];
+    for (int r = 0; r < 3; ++r)
+      out[r] = std::max(out[r], std::fabs((p0 * Q[3 * r + 0] + p1 * Q[3 * r + 1]) + p2 * Q[3 * r + 2]));
+  }
+}
 
 // per-axis max over the element's vertices of |Q (v - c)|
 void element_extent(const HostMesh& M, const Elements& E, int e, const HBox& b, double out[3]) {
@@ -655,27 +858,62 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     bool trivial;
     double val;
   };
-  auto round = [&](const std::vector<std::vector<int32_t>>& pops) -> int {
-    std::vector<Cand> cands;
-    std::vector<HBox> cb;       // candidate boxes to evaluate
-    std::vector<uint32_t> ck;   // their jitter keys
-    std::vector<int32_t> cidx;  // their candidate indices
+  // round buffers, reused from round to round
+  std::vector<Cand> cands;
+  std::vector<HBox> cb;        // candidate boxes to evaluate
+  std::vector<uint32_t> ck;    // their jitter keys
+  std::vector<int32_t> cidx;   // their candidate indices
+  std::vector<double> dpred;   // predicted change per candidate
+  std::vector<char> predicted_c, evaluated, keep;
+  std::vector<float> fcand, fp;
+  std::vector<HBox> pb, rb;
+  std::vector<uint32_t> rk;
+  std::vector<int32_t> ri, cur_of((size_t)boxes.size(), -1), touched;
+  std::vector<std::vector<std::pair<double, size_t>>> per_box((size_t)boxes.size());
+  std::vector<std::vector<int32_t>> got((size_t)boxes.size());  // candidate index per receiving box
+  std::vector<double> bc, bQ;  // centres and axes of a group's boxes in float64
+  // `overlap` (the next round's pops) runs once per round, while the device
+  // works if the round makes a device call, else at its end
+  auto round = [&](const std::vector<std::vector<int32_t>>& pops, const std::function<void()>& overlap) -> int {
+    bool overlapped = false;
+    const std::function<void()> overlap_once = [&]() {
+      if (!overlapped) {
+        overlapped = true;
+        overlap();
+      }
+    };
+    g_ft.cands.start();
+    size_t total = 0;
+    for (int g = 0; g < G; ++g) total += pops[g].size() * groups[g].boxes.size();
+    cands.resize(total);
+    cb.resize(total);
+    ck.resize(total);
+    cidx.resize(total);
+    size_t nc = 0, ncb = 0;
     // a box that already contains the element has dOBV = 0, the minimum: then the
     // element's other candidates need no evaluation
     for (int g = 0; g < G; ++g) {
       const Group& gr = groups[g];
       const int b = (int)gr.boxes.size();
+      if (pops[g].empty()) continue;
+      bc.resize((size_t)b * 3);
+      bQ.resize((size_t)b * 9);
+      for (int i = 0; i < b; ++i) {
+        const HBox& bx = boxes[gr.boxes[i]];
+        for (int k = 0; k < 3; ++k) bc[3 * i + k] = bx.c[k];
+        for (int k = 0; k < 9; ++k) bQ[9 * i + k] = bx.Q[k];
+      }
       for (int e : pops[g]) {
-        const size_t first = cands.size();
+        const size_t first = nc;
         bool any_trivial = false;
         for (int i = 0; i < b; ++i) {
           const HBox& bx = boxes[gr.boxes[i]];
-          Cand c;
+          Cand& c = cands[nc++];
           c.e = e;
           c.g = g;
           c.li = i;
           double ext[3];
-          element_extent(M, E, e, bx, ext);
+          element_extent_fast(E, e, &bc[3 * i], &bQ[9 * i], ext);
           for (int r = 0; r < 3; ++r) c.h[r] = f32_up(std::max((double)bx.h[r], ext[r]));
           c.trivial = same_h(c.h, bx.h);
           c.val = 0.0;
@@ -683,43 +921,53 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
             ++cnt.trivial;
             any_trivial = true;
           }
-          cands.push_back(c);
         }
         if (any_trivial) continue;
         for (int i = 0; i < b; ++i) {
-          HBox gb = boxes[gr.boxes[i]];
+          HBox& gb = cb[ncb];
+          gb = boxes[gr.boxes[i]];
           std::memcpy(gb.h, cands[first + i].h, 12);
-          cb.push_back(gb);
-          ck.push_back(slot[gr.boxes[i]]);
-          cidx.push_back((int32_t)(first + i));
+          ck[ncb] = slot[gr.boxes[i]];
+          cidx[ncb] = (int32_t)(first + i);
+          ++ncb;
         }
       }
     }
+    cb.resize(ncb);
+    ck.resize(ncb);
+    cidx.resize(ncb);
+    g_ft.cands.stop();
     // Learned ranking.  The ranker predicts the outer fraction of every candidate
     // and of the current boxes; the predicted change of a move is
     // f(grown) V(grown) - f(current) V(current) (the two predictions share most of
     // their error).  For every receiving box only the verify_top candidates with
     // the smallest predicted change are evaluated exactly; the other candidates
     // are decided on the prediction.
-    std::vector<double> dpred(cands.size(), 0.0);
-    std::vector<char> predicted_c(cands.size(), 0);
-    std::vector<float> fcand;  // prediction of each kept candidate (judge)
+    dpred.assign(cands.size(), 0.0);
+    predicted_c.assign(cands.size(), 0);
+    fcand.clear();  // prediction of each kept candidate (judge)
+    if (pred && pred->on) {  // a finished judge evaluation enters the judge
+      const int64_t before = pred->judged_evals;
+      OBBV_RET(pred->judge_poll(false));
+      cnt.evals += pred->judged_evals - before;
+    }
     const bool ranked = pred && pred->on && !pred->paused && !cidx.empty();
     const bool judge_round = ranked && round_no % std::max(1, pred->cfg.judge_every) == 0;
     ++round_no;
     if (ranked) {
-      std::vector<HBox> pb = cb;
-      std::vector<int32_t> cur_of((size_t)boxes.size(), -1);
+      pb.clear();  // the current boxes, predicted after the candidates
       for (int32_t x : cidx) {
         const int bi = groups[cands[x].g].boxes[cands[x].li];
         if (cur_of[bi] < 0) {
-          cur_of[bi] = (int32_t)pb.size();
+          cur_of[bi] = (int32_t)(cb.size() + pb.size());
           pb.push_back(boxes[bi]);
         }
       }
-      std::vector<float> fp;
-      OBBV_RET(pred->predict(pb, fp));
-      std::vector<std::vector<std::pair<double, size_t>>> per_box((size_t)boxes.size());
+      OBBV_RET(pred->predict(cb, pb, fp, &overlap_once));
+      if (judge_round && !pred->judge_busy()) OBBV_RET(pred->judge_begin(ev, cb, ck, fp, cidx.size()));
+      g_ft.rank_post.start();
+      const size_t top = (size_t)std::max(0, pred->cfg.verify_top);
+      const bool rank_top = top > 0;
       for (size_t z = 0; z < cidx.size(); ++z) {
         const Cand& c = cands[cidx[z]];
         const int bi = groups[c.g].boxes[c.li];
@@ -729,21 +977,22 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         const double d = (double)fp[z] * vg - (double)fp[cur_of[bi]] * vc;
         dpred[cidx[z]] = std::max(d, 0.0);
         predicted_c[cidx[z]] = 1;
-        per_box[bi].push_back({dpred[cidx[z]], z});
+        if (rank_top) per_box[bi].push_back({dpred[cidx[z]], z});
       }
-      // a judge round evaluates every candidate; other rounds the verify_top
-      // smallest predicted changes of every receiving box
-      std::vector<char> keep(cidx.size(), judge_round ? 1 : 0);
-      const size_t top = (size_t)std::max(0, pred->cfg.verify_top);
-      if (!judge_round)
+      for (int32_t x : cidx) cur_of[groups[cands[x].g].boxes[cands[x].li]] = -1;
+      // the verify_top smallest predicted changes of every receiving box are
+      // evaluated exactly
+      keep.assign(cidx.size(), 0);
+      if (rank_top)
         for (auto& v : per_box) {
           if (v.empty()) continue;
           std::sort(v.begin(), v.end());
           for (size_t q = 0; q < std::min(top, v.size()); ++q) keep[v[q].second] = 1;
+          v.clear();
         }
-      std::vector<HBox> rb;
-      std::vector<uint32_t> rk;
-      std::vector<int32_t> ri;
+      rb.clear();
+      rk.clear();
+      ri.clear();
       for (size_t z = 0; z < cidx.size(); ++z)
         if (keep[z]) {
           rb.push_back(cb[z]);
@@ -754,6 +1003,7 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       cb.swap(rb);
       ck.swap(rk);
       cidx.swap(ri);
+      g_ft.rank_post.stop();
     }
     // one device call, if any candidate needs an exact value: the stale boxes
     // (their exact volumes enter the exact changes), then the candidates
@@ -768,7 +1018,7 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       }
       req_boxes.insert(req_boxes.end(), cb.begin(), cb.end());
       req_keys.insert(req_keys.end(), ck.begin(), ck.end());
-      OBBV_RET(ev.eval(req_boxes, req_keys, vals));
+      OBBV_RET(ev.eval(req_boxes, req_keys, vals, &overlap_once));
       cnt.evals += (int64_t)vals.size();
       for (size_t x = 0; x < ns; ++x) {
         obv[stale[x]] = vals[x];
@@ -776,7 +1026,8 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       }
       stale.clear();
     }
-    std::vector<char> evaluated(cands.size(), 0);
+    g_ft.exact_post.start();
+    evaluated.assign(cands.size(), 0);
     for (size_t x = 0; x < cidx.size(); ++x) {
       cands[cidx[x]].val = vals[ns + x];
       evaluated[cidx[x]] = 1;
@@ -788,9 +1039,10 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         if (vb > 0.0) pred->judge(std::fabs((double)fcand[x] - vals[ns + x] / vb));
       }
     }
+    g_ft.exact_post.stop();
     // decisions
-    std::vector<std::vector<int32_t>> got((size_t)boxes.size());  // candidate index per receiving box
-    std::vector<int32_t> touched;
+    g_ft.decide.start();
+    touched.clear();
     size_t ci = 0;
     for (int g = 0; g < G; ++g) {
       const Group& gr = groups[g];
@@ -825,46 +1077,69 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         ci += b;
       }
     }
+    g_ft.decide.stop();
     // grow the receiving boxes to the union
+    g_ft.grow.start();
     for (int bi : touched) {
       float hn[3];
       std::memcpy(hn, cands[got[bi][0]].h, 12);
       for (size_t x = 1; x < got[bi].size(); ++x)
         for (int r = 0; r < 3; ++r) hn[r] = std::max(hn[r], cands[got[bi][x]].h[r]);
-      if (same_h(hn, boxes[bi].h)) continue;
-      std::memcpy(boxes[bi].h, hn, 12);
-      bool found = false;
-      for (int cx : got[bi])
-        if (evaluated[cx] && same_h(cands[cx].h, hn)) {
-          obv[bi] = cands[cx].val;
-          found = true;
-          break;
+      if (!same_h(hn, boxes[bi].h)) {
+        std::memcpy(boxes[bi].h, hn, 12);
+        bool found = false;
+        for (int cx : got[bi])
+          if (evaluated[cx] && same_h(cands[cx].h, hn)) {
+            obv[bi] = cands[cx].val;
+            found = true;
+            break;
+          }
+        if (!found && !is_stale[bi]) {
+          is_stale[bi] = 1;
+          stale.push_back(bi);
         }
-      if (!found && !is_stale[bi]) {
-        is_stale[bi] = 1;
-        stale.push_back(bi);
       }
+      got[bi].clear();
     }
+    g_ft.grow.stop();
+    overlap_once();
     return OBBV_OK;
   };
 
-  std::vector<std::vector<int32_t>> pops((size_t)G);
-  for (;;) {
+  // The pop sequence does not depend on the decisions (a popped element's
+  // neighbours enter the frontier whichever box takes it, and only unassigned
+  // elements are ever in the frontier), so the next round's pops are taken while
+  // the device works on the current round.
+  std::vector<std::vector<int32_t>> pops((size_t)G), next((size_t)G);
+  auto take_pops = [&](std::vector<std::vector<int32_t>>& out) -> bool {
+    g_ft.pops.start();
     bool any = false;
     for (int g = 0; g < G; ++g) {
-      pops[g].clear();
-      while (!heap[g].empty() && (int)pops[g].size() < K) {
+      out[g].clear();
+      while (!heap[g].empty() && (int)out[g].size() < K) {
         const int e = heap[g].top().second;
         heap[g].pop();
-        if (eb[e] < 0) pops[g].push_back(e);
+        if (eb[e] < 0) out[g].push_back(e);
       }
-      any = any || !pops[g].empty();
+      any = any || !out[g].empty();
     }
-    if (!any) break;
-    ++cnt.rounds;
-    OBBV_RET(round(pops));
+    g_ft.pops.stop();
+    return any;
+  };
+  bool any_next = false;
+  const std::function<void()> advance = [&]() {
+    g_ft.pops.start();
     for (int g = 0; g < G; ++g)
       for (int e : pops[g]) push_neighbours(e);
+    g_ft.pops.stop();
+    any_next = take_pops(next);
+  };
+  bool any = take_pops(pops);
+  while (any) {
+    ++cnt.rounds;
+    OBBV_RET(round(pops, advance));
+    pops.swap(next);
+    any = any_next;
   }
   // elements no flood reached: one by one, in index order, all groups in lockstep
   std::vector<std::vector<int32_t>> left((size_t)G);
@@ -881,7 +1156,12 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       if (p < left[g].size()) pops[g].push_back(left[g][p]);
     }
     ++cnt.rounds;
-    OBBV_RET(round(pops));
+    OBBV_RET(round(pops, [] {}));
+  }
+  if (pred && pred->on) {
+    const int64_t before = pred->judged_evals;
+    OBBV_RET(pred->judge_poll(true));
+    cnt.evals += pred->judged_evals - before;
   }
   return flush_stale();
 }
@@ -1065,6 +1345,13 @@ struct LloydState {
             "(host prep %.3f s, device incl. launches %.3f s, %lld overflow repeats); ranker %.3f s\n",
             t_life.s, t_flood.s, t_update.s, (long long)ev.calls, ev.t_prep.s, ev.t_dev.s, (long long)ev.overflows,
             pred.t_pred.s);
+    const FloodTimers& f = g_ft;
+    fprintf(stderr,
+            "[obbv lloyd] flood host: pops %.3f s, candidates %.3f s, ranker post %.3f s, exact post %.3f s, "
+            "decisions %.3f s, growth %.3f s; ranker: pack %.3f s, launch %.3f s, wait %.3f s\n",
+            f.pops.s, f.cands.s, f.rank_post.s, f.exact_post.s, f.decide.s, f.grow.s, f.pred_pack.s, f.pred_launch.s,
+            f.pred_wait.s);
+    g_ft = FloodTimers();
   }
 };
 
@@ -1360,6 +1647,7 @@ int merge_level(LloydState& S, Tree& T, int l) {
     E.tri_off.push_back((int32_t)E.tris.size());
     for (int k = 0; k < 3; ++k) E.cen.push_back((double)U.box[u].c[k]);
   }
+  E.build_vertices(S.M);
   // unit adjacency: a mesh edge joins triangles of the two units
   std::vector<std::vector<int32_t>> nb((size_t)E.n);
   for (int t = 0; t < S.M.nt; ++t) {

@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "box_features.h"
 
 namespace obbv {
 namespace {
@@ -156,97 +157,196 @@ __global__ void k_adam(float* __restrict__ P, float* __restrict__ m, float* __re
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference: the three layers of 32 rows in one workgroup.  The weights
-// are pre-packed as bfloat16 and transposed ([out][in]) so that the four
-// consecutive inputs a lane feeds one MFMA step are one 8-byte load; the input
-// rows and the first hidden layer sit in LDS as bfloat16, the second hidden
-// layer in float32.  Same rounding points, operands and accumulation order as
-// the layer-by-layer path, hence the same bits.
-// ---------------------------------------------------------------------------
+// Fused inference: the network on 32 rows per workgroup.  The weights are
+// pre-packed as bfloat16 in the order the MFMA lanes consume them: for output
+// unit n and lane half q (lanes 32 q .. 32 q + 31 feed inputs 8 k + 4 q .. + 3 of
+// K-step k), entry ((n * 2 + q) * (K / 8) + k) * 4 + j holds W[8 k + 4 q + j][n],
+// so every lane reads one contiguous run of its operands.  The input rows and the
+// first hidden layer sit in LDS as bfloat16, the second hidden layer in float32.
 constexpr int64_t kPacked = (int64_t)kIn * kH + (int64_t)kH * kH;  // bf16 entries
 
 __global__ void k_mlp_pack(const float* __restrict__ P, short* __restrict__ W) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kPacked) return;
-  if (i < (int64_t)kIn * kH) {
-    const int o = (int)(i / kIn), k = (int)(i - (int64_t)o * kIn);
-    W[i] = f2bf(P[oW1 + (int64_t)k * kH + o]);
-  } else {
-    const int64_t j = i - (int64_t)kIn * kH;
-    const int o = (int)(j / kH), k = (int)(j - (int64_t)o * kH);
-    W[i] = f2bf(P[oW2 + (int64_t)k * kH + o]);
-  }
+  const bool first = i < (int64_t)kIn * kH;
+  const int K = first ? kIn : kH;
+  const int64_t e = first ? i : i - (int64_t)kIn * kH;
+  const int j = (int)(e & 3);
+  const int64_t rest = e >> 2;
+  const int k = (int)(rest % (K / 8));
+  const int64_t nq = rest / (K / 8);
+  const int q = (int)(nq & 1), n = (int)(nq >> 1);
+  const int in = 8 * k + 4 * q + j;
+  W[i] = f2bf(P[(first ? oW1 : oW2) + (int64_t)in * kH + n]);
 }
 
 constexpr int kFusedRows = 32;
-constexpr int kH2Pitch = kH + 1;
+static_assert(kFeatIn == kIn, "feature rows and the first layer disagree");
 
-__global__ void __launch_bounds__(256)
-k_mlp_infer(const float* __restrict__ P, const short* __restrict__ W, const float* __restrict__ X,
-            float* __restrict__ f) {
-  __shared__ short sx[kFusedRows * kIn];
-  __shared__ short sh1[kFusedRows * kH];
-  __shared__ float sh2[kFusedRows * kH2Pitch];
-  const int64_t row0 = (int64_t)blockIdx.x * kFusedRows;
-  for (int i = threadIdx.x; i < kFusedRows * kIn; i += blockDim.x) sx[i] = f2bf(X[row0 * kIn + i]);
-  __syncthreads();
+// The network on one tile of kFusedRows rows, by one workgroup of kRowThreads.
+// Layers 1 and 2: bfloat16 rows sx [32][kIn] -> sh1 (bfloat16 [32][kH]) -> the
+// second hidden layer in registers.  Eight waves, wave w computes the 32 x 32
+// output tile of columns 32 w .. 32 w + 31.  A wave's weight operands for both
+// layers (544 + 256 contiguous bytes per lane) are issued before the rows are
+// staged, so the layers wait on one memory latency instead of one per K-step.
+// Head: each lane forms bf16(h2) bf16(w3) for its column and 16 rows; the 32
+// columns of a wave are summed by an xor butterfly (1, 2, 4, 8, 16) within each
+// half-wave, the eight wave sums in order, then the bias:
+// f = (1 - occ / 512) + sigmoid(z) - 1/2.  `stage` fills sx and socc.  Every
+// thread of the block calls this (barriers).
+constexpr int kRowThreads = 512;
+
+template <class Stage>
+__device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ W, Stage stage, short* sx, short* sh1,
+                         float* zp, const float* socc, int64_t row0, int n, float* __restrict__ f) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 31, kq = (lane >> 5) * 4;
-  const short* W1t = W;
-  const short* W2t = W + (int64_t)kIn * kH;
-  // layer 1: this wave's 64 outputs as two 32 x 32 tiles
+  const int nn = 32 * wave + r;  // this lane's weight row (output column)
+  const v4s* w1 = reinterpret_cast<const v4s*>(W) + (int64_t)(2 * nn + (lane >> 5)) * (kIn / 8);
+  const v4s* w2 = reinterpret_cast<const v4s*>(W + (int64_t)kIn * kH) + (int64_t)(2 * nn + (lane >> 5)) * (kH / 8);
+  v4s b1[kIn / 8], b2[kH / 8];
+  for (int k = 0; k < kIn / 8; ++k) b1[k] = w1[k];
+  for (int k = 0; k < kH / 8; ++k) b2[k] = w2[k];
+  __builtin_amdgcn_sched_barrier(0);  // every weight load is in flight before the rows are staged
+  stage();
+  __syncthreads();
+  const int c = 32 * wave + (lane & 31);
   {
-    const int nA = 64 * wave + r, nB = nA + 32;
-    v16f a0, a1;
-    for (int i = 0; i < 16; ++i) a0[i] = a1[i] = 0.f;
-    for (int k0 = 0; k0 < kIn; k0 += 8) {
-      const v4s x = *reinterpret_cast<const v4s*>(&sx[r * kIn + k0 + kq]);
-      const v4s bA = *reinterpret_cast<const v4s*>(&W1t[(int64_t)nA * kIn + k0 + kq]);
-      const v4s bB = *reinterpret_cast<const v4s*>(&W1t[(int64_t)nB * kIn + k0 + kq]);
-      a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, bA, a0, 0, 0, 0);
-      a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, bB, a1, 0, 0, 0);
+    v16f acc;
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    for (int k = 0; k < kIn / 8; ++k) {
+      const v4s x = *reinterpret_cast<const v4s*>(&sx[r * kIn + 8 * k + kq]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, b1[k], acc, 0, 0, 0);
     }
+    const float bias = P[ob1 + c];
     for (int rr = 0; rr < 16; ++rr) {
       const int row = 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4);
-      const int cA = 64 * wave + (lane & 31), cB = cA + 32;
-      sh1[row * kH + cA] = f2bf(fmaxf(a0[rr] + P[ob1 + cA], 0.f));
-      sh1[row * kH + cB] = f2bf(fmaxf(a1[rr] + P[ob1 + cB], 0.f));
+      sh1[row * kH + c] = f2bf(fmaxf(acc[rr] + bias, 0.f));
     }
   }
   __syncthreads();
-  // layer 2
-  {
-    const int nA = 64 * wave + r, nB = nA + 32;
-    v16f a0, a1;
-    for (int i = 0; i < 16; ++i) a0[i] = a1[i] = 0.f;
-    for (int k0 = 0; k0 < kH; k0 += 8) {
-      const v4s h = *reinterpret_cast<const v4s*>(&sh1[r * kH + k0 + kq]);
-      const v4s bA = *reinterpret_cast<const v4s*>(&W2t[(int64_t)nA * kH + k0 + kq]);
-      const v4s bB = *reinterpret_cast<const v4s*>(&W2t[(int64_t)nB * kH + k0 + kq]);
-      a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(h, bA, a0, 0, 0, 0);
-      a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(h, bB, a1, 0, 0, 0);
-    }
-    for (int rr = 0; rr < 16; ++rr) {
-      const int row = 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4);
-      const int cA = 64 * wave + (lane & 31), cB = cA + 32;
-      sh2[row * kH2Pitch + cA] = fmaxf(a0[rr] + P[ob2 + cA], 0.f);
-      sh2[row * kH2Pitch + cB] = fmaxf(a1[rr] + P[ob2 + cB], 0.f);
-    }
+  v16f acc;
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int k = 0; k < kH / 8; ++k) {
+    const v4s h = *reinterpret_cast<const v4s*>(&sh1[r * kH + 8 * k + kq]);
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(h, b2[k], acc, 0, 0, 0);
   }
+  const float bias = P[ob2 + c], w3 = bf(P[ow3 + c]);
+  float v[16];
+  for (int rr = 0; rr < 16; ++rr) v[rr] = bf(fmaxf(acc[rr] + bias, 0.f)) * w3;
+  for (int o = 1; o < 32; o <<= 1)
+    for (int rr = 0; rr < 16; ++rr) v[rr] += __shfl_xor(v[rr], o, 64);
+  if ((lane & 31) == 0)
+    for (int rr = 0; rr < 16; ++rr) zp[wave * kFusedRows + 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4)] = v[rr];
   __syncthreads();
-  // head, one thread per row (the order of k_head)
-  if (threadIdx.x < kFusedRows) {
-    const int row = threadIdx.x;
+  if (threadIdx.x < kFusedRows && row0 + threadIdx.x < n) {
     float z = 0.f;
-    for (int c = 0; c < kH; ++c) z = fmaf(bf(sh2[row * kH2Pitch + c]), bf(P[ow3 + c]), z);
+    for (int w = 0; w < kRowThreads / 64; ++w) z += zp[w * kFusedRows + threadIdx.x];
     z += P[ob3];
-    const float* x = X + (row0 + row) * kIn;
-    float occ = 0.f;
-    for (int c = 15; c < 527; ++c) occ += x[c];
     const float sig = 1.f / (1.f + expf(-z));
-    f[row0 + row] = (1.f - occ / 512.f) + sig - 0.5f;
+    f[row0 + threadIdx.x] = (1.f - socc[threadIdx.x] / 512.f) + sig - 0.5f;
   }
 }
+
+// Network outputs of 32 rows per workgroup.  kFloat: float32 rows X [n][kIn]
+// (n a multiple of 32), rounded to bfloat16 and their occupancy sums taken here;
+// otherwise bfloat16 rows Xb [n][kIn] with their sums in occ [n] (rows >= n read
+// as zero), and the last workgroup to finish raises the host flag (when given).
+template <bool kFloat>
+__global__ void __launch_bounds__(kRowThreads)
+k_mlp_rows(const float* __restrict__ P, const short* __restrict__ W, const float* __restrict__ X,
+           const short* __restrict__ Xb, const float* __restrict__ occ, int n, float* __restrict__ f,
+           unsigned* done_count, unsigned* done_flag, unsigned seq) {
+  __shared__ short sx[kFusedRows * kIn];
+  __shared__ short sh1[kFusedRows * kH];
+  __shared__ float zp[(kRowThreads / 64) * kFusedRows];
+  __shared__ float socc[kFusedRows];
+  const int64_t row0 = (int64_t)blockIdx.x * kFusedRows;
+  auto stage = [&]() {
+    if constexpr (kFloat) {
+      for (int i = threadIdx.x; i < kFusedRows * kIn; i += blockDim.x) sx[i] = f2bf(X[row0 * kIn + i]);
+      const int wave = threadIdx.x >> 6;
+      for (int rw = wave; rw < kFusedRows; rw += kRowThreads / 64) {
+        const float* x = X + (row0 + rw) * kIn;
+        const float o = occ_sum_wave([&](int k) { return x[k]; });
+        if ((threadIdx.x & 63) == 0) socc[rw] = o;
+      }
+    } else {
+      typedef int v4i __attribute__((ext_vector_type(4)));
+      constexpr int kChunks = kIn / 8;  // 16-byte pieces of a row
+      for (int i = threadIdx.x; i < kFusedRows * kChunks; i += blockDim.x) {
+        const int rw = i / kChunks, c = i - rw * kChunks;
+        v4i q = {0, 0, 0, 0};
+        if (row0 + rw < n) q = *reinterpret_cast<const v4i*>(Xb + (row0 + rw) * kIn + 8 * c);
+        *reinterpret_cast<v4i*>(&sx[rw * kIn + 8 * c]) = q;
+      }
+      if (threadIdx.x < kFusedRows) socc[threadIdx.x] = row0 + threadIdx.x < n ? occ[row0 + threadIdx.x] : 0.f;
+    }
+  };
+  mlp_tile(P, W, stage, sx, sh1, zp, socc, row0, n, f);
+  if (done_flag) {  // the last workgroup to finish raises the host-visible flag
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned prev = atomicAdd(done_count, 1u);
+      if (prev == gridDim.x - 1) {
+        atomicExch(done_count, 0u);  // ready for the next call on the stream
+        __threadfence_system();
+        __hip_atomic_store(done_flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  }
+}
+
+// ranker input rows from the occupancy volume, one workgroup per box
+__global__ void k_sample_features(const float* __restrict__ vol, int N, const float* __restrict__ frame,
+                                  const obbv_box* __restrict__ boxes, int n, float* __restrict__ X) {
+  const int b = blockIdx.x;
+  if (b >= n) return;
+  const float* p = reinterpret_cast<const float*>(boxes + b);
+  float* x = X + (int64_t)b * kFeatIn;
+  for (int k = threadIdx.x; k < kFeatIn; k += blockDim.x) x[k] = box_feature(k, p, frame, vol, N);
+}
+
+// Ranker inputs of one box per workgroup (256 threads), for k_mlp_rows<false>:
+// bfloat16 row Xb [b][kIn] and the occupancy sum occ [b].  Thread t computes
+// inputs t, t + 256, t + 512 with their 24 volume reads issued together; the
+// float values equal k_sample_features' and the sum is occ_sum_wave's.  The box
+// may sit in mapped host memory: it is read once.
+constexpr int kRankPerThread = (kIn + 255) / 256;
+
+__global__ void __launch_bounds__(256)
+k_rank_inputs(const float* __restrict__ vol, int N, const float* __restrict__ frame,
+              const obbv_box* __restrict__ boxes, int n, short* __restrict__ Xb, float* __restrict__ occ) {
+  __shared__ float sbox[16];
+  __shared__ float sf[kIn];
+  const int64_t b = blockIdx.x;
+  if (b >= n) return;
+  if (threadIdx.x < 15) sbox[threadIdx.x] = reinterpret_cast<const float*>(boxes)[b * 15 + threadIdx.x];
+  __syncthreads();
+  OccSample smp[kRankPerThread];
+  float v[kRankPerThread][8];
+  for (int m = 0; m < kRankPerThread; ++m) {  // no branches: every read in flight together
+    const int r = min(max((int)threadIdx.x + 256 * m - kFeatOcc0, 0), kFeatOccN - 1);
+    smp[m] = occ_sample_at(r, sbox, frame);
+    for (int c = 0; c < 8; ++c) v[m][c] = occ_corner(vol, N, smp[m], c);
+  }
+  for (int m = 0; m < kRankPerThread; ++m) {
+    const int k = threadIdx.x + 256 * m;
+    if (k >= kIn) break;
+    float x = 0.f;
+    if (k < kFeatOcc0) x = box_param_feature(k, sbox, frame);
+    else if (k < kFeatOcc0 + kFeatOccN) x = occ_blend(smp[m], v[m]);
+    sf[k] = x;
+    Xb[b * kIn + k] = f2bf(x);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const float o = occ_sum_wave([&](int k) { return sf[k]; });
+    if (threadIdx.x == 0) occ[b] = o;
+  }
+}
+
 
 struct MlpScratch {
   float* H1;
@@ -307,7 +407,27 @@ int mlp_infer_packed(const float* params, const short* packed, const float* X, i
                      hipStream_t s) {
   OBBV_ARG(n >= 0 && n % kFusedRows == 0, "n must be a non-negative multiple of 32");
   if (n == 0) return OBBV_OK;
-  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)(n / kFusedRows)), dim3(256), 0, s, params, packed, X, out_f);
+  hipLaunchKernelGGL(k_mlp_rows<true>, dim3((unsigned)(n / kFusedRows)), dim3(kRowThreads), 0, s, params, packed, X,
+                     (const short*)nullptr, (const float*)nullptr, n, out_f, (unsigned*)nullptr, (unsigned*)nullptr,
+                     0u);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+// scratch of mlp_rank_packed: Xb [n][kIn] bfloat16 | occ [n]
+size_t mlp_rank_scratch_bytes(int32_t n) { return (((size_t)n * kIn * 2 + 255) & ~(size_t)255) + (size_t)n * 4; }
+
+int mlp_rank_packed(const float* params, const short* packed, const float* volume, int32_t N, const float* frame,
+                    const obbv_box* boxes, int32_t n, void* scratch, float* out_f, hipStream_t s,
+                    unsigned* done_count, unsigned* done_flag, unsigned seq) {
+  OBBV_ARG(n >= 0 && N >= 1, "bad size");
+  if (n == 0) return OBBV_OK;
+  short* Xb = (short*)scratch;
+  float* occ = (float*)((char*)scratch + (((size_t)n * kIn * 2 + 255) & ~(size_t)255));
+  hipLaunchKernelGGL(k_rank_inputs, dim3((unsigned)n), dim3(256), 0, s, volume, N, frame, boxes, n, Xb, occ);
+  hipLaunchKernelGGL(k_mlp_rows<false>, dim3((unsigned)((n + kFusedRows - 1) / kFusedRows)), dim3(kRowThreads), 0, s,
+                     params, packed, (const float*)nullptr, (const short*)Xb, (const float*)occ, n, out_f, done_count,
+                     done_flag, seq);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
 }
@@ -329,6 +449,33 @@ using namespace obbv;
 extern "C" int obbv_mlp_forward(const float* params, const float* X, int32_t n, float* out_f, void* stream) {
   clear_error();
   return mlp_forward_impl(params, X, n, out_f, (hipStream_t)stream);
+}
+
+extern "C" int obbv_sample_features(const float* volume, int32_t N, const float* frame, const obbv_box* boxes,
+                                    int32_t n_boxes, float* out_X, void* stream) {
+  clear_error();
+  OBBV_ARG(n_boxes >= 0 && N >= 1, "bad size");
+  if (n_boxes == 0) return OBBV_OK;
+  OBBV_ARG(volume && frame && boxes && out_X, "NULL argument");
+  hipLaunchKernelGGL(k_sample_features, dim3((unsigned)n_boxes), dim3(128), 0, (hipStream_t)stream, volume, N, frame,
+                     boxes, n_boxes, out_X);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+
+extern "C" int obbv_mlp_rank_boxes(const float* params, const float* volume, int32_t N, const float* frame,
+                                   const obbv_box* boxes, int32_t n_boxes, float* out_f, void* stream) {
+  clear_error();
+  OBBV_ARG(n_boxes >= 0 && N >= 1, "bad size");
+  if (n_boxes == 0) return OBBV_OK;
+  OBBV_ARG(params && volume && frame && boxes && out_f, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  void* pv = nullptr;
+  void* sc = nullptr;
+  OBBV_RET(pool_get(kPoolMlp, (size_t)kPacked * 2, &pv));
+  OBBV_RET(pool_get(kPoolRank, mlp_rank_scratch_bytes(n_boxes), &sc));
+  OBBV_RET(mlp_pack_impl(params, (short*)pv, s));
+  return mlp_rank_packed(params, (const short*)pv, volume, N, frame, boxes, n_boxes, sc, out_f, s, nullptr, nullptr, 0u);
 }
 
 extern "C" int obbv_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, const float* X,

@@ -1168,7 +1168,7 @@ __global__ void __launch_bounds__(kTestThreads) k_raster(TestArgs a) {
 __global__ void k_or_word(uint32_t* __restrict__ w, uint32_t bits) { atomicOr(w, bits); }
 
 struct Publish {
-  int64_t* out;  // nullable: mapped host memory [status, records, bin entries, work items]
+  int64_t* out;  // nullable: mapped host memory [status, records, bin entries, work items, done]
   const int64_t* rec;
   const int64_t* bin;
   const int64_t* items;
@@ -1180,22 +1180,25 @@ __device__ void finalize_box(const obbv_box* __restrict__ boxes, int b, int R, u
                              double* __restrict__ out_vin_axis, uint32_t* status);
 
 // float64 OBV per box; the last block to finish publishes the call's status bits
-// and totals to the caller's mapped host memory.
+// and totals to the caller's mapped host memory, then out[4] = 1 with a
+// system-scope release: a host that sees it sees every output of the call.
 __global__ void k_finalize(const obbv_box* __restrict__ boxes, int n_boxes, int R, uint32_t axis_mask,
                            const unsigned long long* __restrict__ acc, double* __restrict__ out_obv,
                            double* __restrict__ out_vin_axis, uint32_t* status, Publish pub) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < n_boxes) finalize_box(boxes, b, R, axis_mask, acc, out_obv, out_vin_axis, status);
   if (!pub.out) return;
+  __threadfence_system();
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
     if (atomicAdd(pub.done, 1u) == gridDim.x - 1) {
       __threadfence();
       pub.out[0] = (int64_t)atomicOr(status, 0u);
       pub.out[1] = *pub.rec;
       pub.out[2] = *pub.bin;
       pub.out[3] = *pub.items;
+      __threadfence_system();
+      __hip_atomic_store(pub.out + 4, (int64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }
@@ -1316,6 +1319,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   OBBV_ARG(n_meshes == 1 || box_mesh != nullptr, "box_mesh is required with several meshes");
   OBBV_ARG(params->R >= 1 && params->R <= 32767, "R must be in [1, 32767]");
   OBBV_ARG(params->flags == 0, "flags must be 0");
+  const int pool_base = ex ? ex->pool_base : 0;
   OBBV_ARG(params->tile == 0 || params->tile == 8 || params->tile == 16, "tile must be 0, 8 or 16");
   const uint32_t mask = params->axis_mask ? params->axis_mask : 7u;
   OBBV_ARG(mask <= 7u, "axis_mask has bits above 2");
@@ -1379,7 +1383,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     }
     meta_v = ex->meta;
   } else {
-    OBBV_RET(pool_get(kPoolMeta, off, &meta_v));
+    OBBV_RET(pool_get(pool_base + kPoolMeta, off, &meta_v));
   }
   if (ex) ex->meta_bytes = off;
   char* meta = (char*)meta_v;
@@ -1413,7 +1417,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     items = ex->items;
   } else {
     void* iv = nullptr;
-    OBBV_RET(pool_get(kPoolItems, items_bytes, &iv));
+    OBBV_RET(pool_get(pool_base + kPoolItems, items_bytes, &iv));
     items = (char*)iv;
   }
   if (ex) ex->items_bytes = items_bytes;
@@ -1451,7 +1455,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       bound = pin[3];
     }
     void* lv = nullptr;
-    OBBV_RET(pool_get(kPoolLists, (size_t)std::max<int64_t>(bound, 1) * 48, &lv));
+    OBBV_RET(pool_get(pool_base + kPoolLists, (size_t)std::max<int64_t>(bound, 1) * 48, &lv));
     d_listP = (float4*)lv;
     hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], mask,
                        nch, d_ficnt, (const int32_t*)d_fioff, (const int64_t*)d_foff, d_listP, status);
@@ -1538,8 +1542,8 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       recs_v = ex->recs;
       bins_v = ex->bins;
     } else {
-      OBBV_RET(pool_get(kPoolRecords, (size_t)n_rec * kRecBytes, &recs_v));
-      OBBV_RET(pool_get(kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
+      OBBV_RET(pool_get(pool_base + kPoolRecords, (size_t)n_rec * kRecBytes, &recs_v));
+      OBBV_RET(pool_get(pool_base + kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
     }
     hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
                        d_reccnt, (const int32_t*)d_ioff, d_binoff, d_bincur, (float4*)recs_v, (int32_t*)bins_v);
@@ -1566,7 +1570,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       itile = ex->itile;
     } else {
       void* tv = nullptr;
-      OBBV_RET(pool_get(kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * 4, &tv));
+      OBBV_RET(pool_get(pool_base + kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * 4, &tv));
       itile = (int32_t*)tv;
     }
     ta.item_tile = itile;
@@ -1731,7 +1735,7 @@ extern "C" int obbv_box_features(const obbv_mesh* meshes, int32_t n_meshes, cons
 }
 
 // ---------------------------------------------------------------------------
-// occupancy volume of a mesh and ranker inputs sampled from it
+// occupancy volume of a mesh (the ranker samples its inputs from it)
 // ---------------------------------------------------------------------------
 namespace obbv {
 namespace {
@@ -1764,52 +1768,6 @@ __global__ void k_scatter_volume(const float* __restrict__ occ, int nb, float* _
   vol[((int64_t)(8 * bz + z) * N + (8 * by + y)) * N + (8 * bx + x)] = occ[t];
 }
 
-__device__ inline float vol_at(const float* __restrict__ vol, int N, int x, int y, int z) {
-  if (x < 0 || y < 0 || z < 0 || x >= N || y >= N || z >= N) return 0.f;
-  return vol[((int64_t)z * N + y) * N + x];
-}
-
-// ranker input rows from the occupancy volume: box parameters normalised by the
-// mesh frame, then the volume sampled (trilinear, voxel centres at origin + (i + 1/2) voxel)
-// at the 8 x 8 x 8 sub-cell centres of the box
-__global__ void k_sample_features(const float* __restrict__ vol, int N, const float* __restrict__ frame,
-                                  const obbv_box* __restrict__ boxes, int n, float* __restrict__ X) {
-  const int b = blockIdx.x;
-  if (b >= n) return;
-  const float* p = reinterpret_cast<const float*>(boxes + b);
-  float* x = X + (int64_t)b * 544;
-  for (int k = threadIdx.x; k < 544; k += blockDim.x) {
-    float v = 0.f;
-    if (k < 3) {
-      v = (p[k] - frame[6 + k]) / frame[9];
-    } else if (k < 12) {
-      v = p[k];
-    } else if (k < 15) {
-      v = logf(fmaxf(p[k], 1e-30f) / frame[9]);
-    } else if (k < 527) {
-      const int r = k - 15;
-      const int ix = r / 64, iy = (r / 8) % 8, iz = r % 8;
-      const float l0 = ((ix + 0.5f) / 4.0f - 1.0f) * p[12];
-      const float l1 = ((iy + 0.5f) / 4.0f - 1.0f) * p[13];
-      const float l2 = ((iz + 0.5f) / 4.0f - 1.0f) * p[14];
-      float g[3];
-      for (int d = 0; d < 3; ++d) {
-        const float w = p[d] + l0 * p[3 + d] + l1 * p[6 + d] + l2 * p[9 + d];
-        g[d] = (w - frame[d]) / frame[3 + d] - 0.5f;  // continuous voxel coordinate
-      }
-      const int x0 = (int)floorf(g[0]), y0 = (int)floorf(g[1]), z0 = (int)floorf(g[2]);
-      const float fx = g[0] - x0, fy = g[1] - y0, fz = g[2] - z0;
-      float acc = 0.f;
-      for (int c = 0; c < 8; ++c) {
-        const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
-        const float wgt = (dx ? fx : 1.f - fx) * (dy ? fy : 1.f - fy) * (dz ? fz : 1.f - fz);
-        acc += wgt * vol_at(vol, N, x0 + dx, y0 + dy, z0 + dz);
-      }
-      v = acc;
-    }
-    x[k] = v;
-  }
-}
 }  // namespace
 }  // namespace obbv
 
@@ -1832,19 +1790,6 @@ extern "C" int obbv_occupancy_volume(const obbv_mesh* mesh, int32_t nb, const fl
   obbv_ov_params p{8, 4u, seed, 8, 0u};
   OBBV_RET(outer_volume_impl(mesh, 1, tb, nullptr, nullptr, n, &p, obv, nullptr, nullptr, nullptr, nullptr, s, occ));
   hipLaunchKernelGGL(k_scatter_volume, dim3(ceil_div((int64_t)n * 512, 256)), dim3(256), 0, s, occ, nb, out_volume);
-  OBBV_HIP(hipGetLastError());
-  return OBBV_OK;
-}
-
-extern "C" int obbv_sample_features(const float* volume, int32_t N, const float* frame, const obbv_box* boxes,
-                                    int32_t n_boxes, float* out_X, void* stream) {
-  using namespace obbv;
-  clear_error();
-  OBBV_ARG(n_boxes >= 0 && N >= 1, "bad size");
-  if (n_boxes == 0) return OBBV_OK;
-  OBBV_ARG(volume && frame && boxes && out_X, "NULL argument");
-  hipLaunchKernelGGL(k_sample_features, dim3((unsigned)n_boxes), dim3(128), 0, (hipStream_t)stream, volume, N, frame,
-                     boxes, n_boxes, out_X);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
 }

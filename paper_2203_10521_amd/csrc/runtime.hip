@@ -25,8 +25,8 @@ void clear_error() { g_last_error.clear(); }
 namespace {
 constexpr int kMaxDevices = 64;
 struct DevicePool {
-  void* ptr[kPoolCount] = {};
-  size_t cap[kPoolCount] = {};
+  void* ptr[kPoolCount * kPoolSets] = {};
+  size_t cap[kPoolCount * kPoolSets] = {};
   uint32_t* status = nullptr;
 };
 DevicePool g_pools[kMaxDevices];
@@ -39,6 +39,10 @@ int pool_get(int slot, size_t bytes, void** out) {
   if (dev < 0 || dev >= kMaxDevices) {
     set_error("device index out of range");
     return OBBV_ERR_UNSUPPORTED;
+  }
+  if (slot < 0 || slot >= kPoolCount * kPoolSets) {
+    set_error("scratch slot out of range");
+    return OBBV_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lock(g_pool_mutex);
   DevicePool& p = g_pools[dev];
@@ -307,10 +311,10 @@ extern "C" int obbv_release(void) {
   for (int d = 0; d < kMaxDevices; ++d) {
     DevicePool& p = g_pools[d];
     bool any = p.status != nullptr;
-    for (int k = 0; k < kPoolCount; ++k) any = any || p.ptr[k];
+    for (int k = 0; k < kPoolCount * kPoolSets; ++k) any = any || p.ptr[k];
     if (!any) continue;
     OBBV_HIP(hipSetDevice(d));
-    for (int k = 0; k < kPoolCount; ++k) {
+    for (int k = 0; k < kPoolCount * kPoolSets; ++k) {
       if (p.ptr[k]) OBBV_HIP(hipFree(p.ptr[k]));
       p.ptr[k] = nullptr;
       p.cap[k] = 0;

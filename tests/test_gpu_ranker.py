@@ -120,6 +120,26 @@ def test_ranker_learns_and_ranks_at_least_as_well_as_the_occupancy_mean(api, tra
     assert hit_nn >= hit_occ - 0.1
 
 
+def test_fused_ranking_equals_features_then_forward(api, trained):
+    """One launch (inputs built on chip) gives the bits of the two-step path, for
+    a box count that is not a multiple of the 32-row tile, and none for 0 boxes."""
+    import torch
+    P, _ = trained
+    V, F = synth.noisy_cube_sphere(14, seed=779)
+    Vt, Ft = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+    vol, frame = api.occupancy_volume(Vt, Ft, nb=8, seed=2)
+    for n in (77, 1, 32, 300):
+        B = torch.from_numpy(synth.mixed_boxes(V, n, seed=40 + n)).cuda()
+        fused = api.mlp_rank_boxes(P, vol, frame, B).cpu().numpy()
+        X = api.sample_features(vol, frame, B)
+        pad = (-n) % 32
+        Xp = torch.cat([X, torch.zeros((pad, X.shape[1]), dtype=X.dtype, device=X.device)])
+        two = api.mlp_forward(P, Xp).cpu().numpy()[:n]
+        assert np.array_equal(fused, two), (n, np.abs(fused - two).max())
+    empty = api.mlp_rank_boxes(P, vol, frame, torch.zeros((0, 15), dtype=torch.float32, device="cuda"))
+    assert empty.shape == (0,)
+
+
 def test_ranker_guided_lloyd_close_to_exact_with_fewer_evaluations(api, trained):
     import torch
     from paper_2203_10521_amd import ranker
