@@ -68,6 +68,21 @@ __device__ inline int box_state(const BoxRegs& B) {
   return 0;
 }
 
+// The ray grid of one (box, axis) cast, computed once per call by k_box_sides:
+// half extents of the face (float64 of the float32 extents), cell sizes
+// du = 2 hu / R and their reciprocals, the 1e-6 cell-range margins, the
+// SplitMix64 state of the cast's first u draw, seed + (2 ((key << 32) | (w << 30))
+// + 1) GAMMA (draw (i, j) adds 2 ((i << 15) + j) GAMMA, its v draw one more
+// GAMMA), and the box state (0 = castable; other boxes get no records).
+struct RayFrame {
+  double hu, hv, du, dv, idu, idv;
+  uint64_t s0;
+  float eu, ev;
+  int32_t state;
+  int32_t pad[3];
+};
+static_assert(sizeof(RayFrame) == 80, "RayFrame layout");
+
 // Workgroup k is dispatched to XCD k % 8; give every XCD a contiguous range of
 // logical ids so that tiles of one (box, axis) share that XCD's L2.
 __device__ inline int xcd_remap(int bid, int n) {
@@ -466,10 +481,32 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt) {
 __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, const int32_t* __restrict__ item_cnt,
                             int32_t* __restrict__ side, int32_t* __restrict__ rec_cnt,
                             int32_t* __restrict__ item_off, int TT, int32_t* __restrict__ tile_cnt,
-                            int32_t* __restrict__ bin_cur, unsigned long long* __restrict__ acc) {
+                            int32_t* __restrict__ bin_cur, unsigned long long* __restrict__ acc,
+                            const obbv_box* __restrict__ boxes, const uint32_t* __restrict__ box_key, int R,
+                            uint64_t seed, RayFrame* __restrict__ rframe) {
   const int bw = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (bw >= 3 * n_boxes) return;
+  if (lane == 0 && rframe) {  // the cast's ray grid
+    const int b = bw / 3, w = bw - 3 * b;
+    const BoxRegs B = load_box(boxes, b);
+    const int ua = (w + 1) % 3, va = (w + 2) % 3;
+    const float huf = pick3(B.h, ua), hvf = pick3(B.h, va);
+    RayFrame f;
+    f.hu = huf;
+    f.hv = hvf;
+    f.du = __ddiv_rn(__dmul_rn(2.0, f.hu), (double)R);
+    f.dv = __ddiv_rn(__dmul_rn(2.0, f.hv), (double)R);
+    f.idu = 1.0 / f.du;
+    f.idv = 1.0 / f.dv;
+    f.eu = 1e-6f * huf;
+    f.ev = 1e-6f * hvf;
+    const uint32_t key = box_key ? box_key[b] : (uint32_t)b;
+    f.s0 = seed + (2ull * (((uint64_t)key << 32) | ((uint64_t)w << 30)) + 1ull) * kGamma;
+    f.state = box_state(B);
+    f.pad[0] = f.pad[1] = f.pad[2] = 0;
+    rframe[bw] = f;
+  }
   // counters of this (box, axis) that later passes accumulate into
   for (int k = lane; k < TT; k += 64) {
     tile_cnt[(int64_t)bw * TT + k] = 0;
@@ -809,6 +846,7 @@ struct TestArgs {
   int64_t item_cap;     // planned launches: work items beyond it are skipped
   const int32_t* item_tile;  // [work items] tile of every work item
   int persistent;       // 1: grid-stride over the work items counted on the device
+  const RayFrame* rframe;    // [nbw] ray grid of every (box, axis) cast
 };
 
 // One wave per TE x TE ray tile of one (box, axis); RPL = (TE/8)^2 rays per lane.
@@ -1002,22 +1040,20 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
   const int64_t g = a.item_tile[item];
   const int bw = (int)(g / TT);
   const int tile = (int)(g - (int64_t)bw * TT);
-  const int b = bw / 3, w = bw - 3 * (bw / 3);
+  const int w = bw - 3 * (bw / 3);
   if (!((a.axis_mask >> w) & 1u)) return;
-  const BoxRegs B = load_box(a.boxes, b);
-  if (box_state(B) != 0) return;
-  const int ua = (w + 1) % 3, va = (w + 2) % 3;
-  const float huf = pick3(B.h, ua), hvf = pick3(B.h, va);
-  const double hu = huf, hv = hvf;
-  const double du = __ddiv_rn(__dmul_rn(2.0, hu), (double)a.R);
-  const double dv = __ddiv_rn(__dmul_rn(2.0, hv), (double)a.R);
-  const float eu = 1e-6f * huf, ev = 1e-6f * hvf;
-  const double idu = 1.0 / du, idv = 1.0 / dv;
-  const uint32_t key = a.box_key ? a.box_key[b] : (uint32_t)b;
+  const int lane = threadIdx.x;
+  const int64_t kb = a.bin_off[g] + (item - a.chunk_off[g]) * a.chunk;
+  const int64_t k0 = kb;
+  const int64_t k1 = min(a.bin_off[g + 1], kb + a.chunk);
+  if (k1 > a.bin_cap) return;  // bins past a planned capacity were not written (flagged)
+  // (boxes whose state is not 0 get no records, hence no ray-test work items)
+  const RayFrame rf = a.rframe[bw];
+  const double hu = rf.hu, hv = rf.hv, du = rf.du, dv = rf.dv, idu = rf.idu, idv = rf.idv;
+  const float eu = rf.eu, ev = rf.ev;
   const int ti = tile % a.tpe, tj = tile / a.tpe;
   const int ci_lo = ti * 16, cj_lo = tj * 16;
   const int ci_hi = min(ci_lo + 15, a.R - 1), cj_hi = min(cj_lo + 15, a.R - 1);
-  const int lane = threadIdx.x;
   __shared__ float2 sray[256];
   __shared__ int32_t sacc[256];
   __shared__ int32_t shit[STATS ? 256 : 1];
@@ -1025,16 +1061,21 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
   bool valid[4];
   int32_t racc[4];
   int rhit[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  // Ray r = lane + 64 k sits in cell (ci_lo + lane % 16, cj_lo + lane / 16 + 4 k):
+  // its u draw has state rf.s0 + 2 ((i << 15) + j) GAMMA = z + 8 k GAMMA, where z
+  // is the lane's k = 0 state, and its v draw one GAMMA more.
+  const int i = ci_lo + (lane & 15);
+  const uint32_t t0 = ((uint32_t)i << 15) + (uint32_t)(cj_lo + (lane >> 4));
+  const uint64_t z0 = rf.s0 + (uint64_t)t0 * (2ull * kGamma);
+  auto make_ray = [&](int k) {
     const int r = lane + 64 * k;
-    const int i = ci_lo + (r & 15), j = cj_lo + (r >> 4);
+    const int j = cj_lo + (r >> 4);
     valid[k] = i < a.R && j < a.R;
     ru[k] = rv[k] = 0.f;
     if (valid[k]) {
-      const uint64_t n = ray_counter(key, w, i, j);
-      const double xi = u24(splitmix64_at(a.seed, n));
-      const double eta = u24(splitmix64_at(a.seed, n + 1));
+      const uint64_t zu = z0 + (uint64_t)k * (8ull * kGamma);
+      const double xi = u24(mix64(zu));
+      const double eta = u24(mix64(zu + kGamma));
       ru[k] = (float)__dadd_rn(-hu, __dmul_rn(__dadd_rn((double)i, xi), du));
       rv[k] = (float)__dadd_rn(-hv, __dmul_rn(__dadd_rn((double)j, eta), dv));
     }
@@ -1043,18 +1084,40 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
     if (STATS) shit[r] = 0;
     racc[k] = 0;
     rhit[k] = 0;
-  }
+  };
+  // The item's first kTestThreads records are requested while the rays are
+  // generated: the record ids before the first two rays of every lane, the
+  // records before the last two.
+  // Both loads are unconditional (lanes past the item's records read its last
+  // id, a bad id reads record 0), so the counters of outstanding loads stay exact
+  // and the rays wait only for what they use.  An item holds at least one record.
+  const int idx0 = a.bins[k0 + min((int64_t)lane, k1 - k0 - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+  make_ray(0);
+  make_ray(1);
+  __builtin_amdgcn_sched_barrier(0);
+  // a bad id happens only after a flagged write-pass mismatch
+  const bool have0 = lane < k1 - k0 && (unsigned)idx0 < (unsigned)a.n_rec;
+  const float4* rp0 = a.recs + kRecF4 * (int64_t)(have0 ? idx0 : 0);
+  const float4 p0 = rp0[0], p1 = rp0[1], p2 = rp0[2], p3 = rp0[3], p4 = rp0[4];
+  __builtin_amdgcn_sched_barrier(0);
+  make_ray(2);
+  make_ray(3);
   __syncthreads();
-  const int64_t kb = a.bin_off[g] + (item - a.chunk_off[g]) * a.chunk;
-  const int64_t k0 = kb;
-  const int64_t k1 = min(a.bin_off[g + 1], kb + a.chunk);
   int64_t tests = 0;
-  if (k1 <= a.bin_cap) {  // bins past a planned capacity were not written (flagged)
+  {
     for (int64_t base = k0; base < k1; base += kTestThreads) {
       const int n = (int)min((int64_t)kTestThreads, k1 - base);
       bool have = lane < n, big = false;
       float4 q0, q1, q2, q3, q4;
-      if (have) {
+      if (base == k0) {
+        have = have0;
+        q0 = p0;
+        q1 = p1;
+        q2 = p2;
+        q3 = p3;
+        q4 = p4;
+      } else if (have) {
         const int idx = a.bins[base + lane];
         have = (unsigned)idx < (unsigned)a.n_rec;  // else only after a flagged write-pass mismatch
         if (have) {
@@ -1370,6 +1433,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   const size_t o_tilecnt = take(4 * (size_t)(nbw * TT));  // zeroed by k_box_sides
   const size_t o_bincur = take(4 * (size_t)(nbw * TT));   // zeroed by k_box_sides
   const size_t o_acc = take(8 * (size_t)nbw);             // zeroed by k_box_sides
+  const size_t o_rframe = take(sizeof(RayFrame) * (size_t)nbw);  // written by k_box_sides
   const size_t o_fcnt = take(4 * (size_t)n_frames);
   const size_t o_foff = take(8 * (size_t)(n_frames + 1));
   const size_t scan_bytes =
@@ -1398,6 +1462,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   int32_t* d_tilecnt = (int32_t*)(meta + o_tilecnt);
   int32_t* d_bincur = (int32_t*)(meta + o_bincur);
   unsigned long long* d_acc = (unsigned long long*)(meta + o_acc);
+  RayFrame* d_rframe = (RayFrame*)(meta + o_rframe);
   int32_t* d_blist = sf ? (int32_t*)(meta + o_blist) : nullptr;
   int32_t* d_fcnt = (int32_t*)(meta + o_fcnt);
   int64_t* d_foff = (int64_t*)(meta + o_foff);
@@ -1488,7 +1553,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_box_sides, dim3(ceil_div(nbw, kCullWaves)), dim3(kCullThreads), 0, s,
                      (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, d_ioff, (int)TT,
-                     d_tilecnt, d_bincur, d_acc);
+                     d_tilecnt, d_bincur, d_acc, boxes, box_key, R, params->seed, d_rframe);
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_tile_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_tilecnt);
   OBBV_HIP(hipGetLastError());
@@ -1575,6 +1640,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     }
     ta.item_tile = itile;
     ta.persistent = fixed ? 1 : 0;
+    ta.rframe = d_rframe;
     void* prof_token = nullptr;
     if (profiling_enabled() && !planned) {
       OBBV_RET(profile_counter(&ta.test_counter));
