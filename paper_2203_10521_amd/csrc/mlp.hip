@@ -2,7 +2,8 @@
 // outer fraction) pairs from the exact outer-volume kernel.  The output corrects
 // the occupancy estimate: f = (1 - mean occupancy) + sigmoid(z) - 1/2.
 //
-// Every matrix product runs on MFMA (v_mfma_f32_32x32x8bf16_1k): operands are
+// Every matrix product runs on MFMA (v_mfma_f32_32x32x8bf16_1k in training,
+// v_mfma_f32_32x32x16_bf16 in the fused inference tile): operands are
 // rounded to bfloat16 (round to nearest even) as they are loaded, products are
 // accumulated in float32.  Activations, gradients and the master weights stay in
 // float32 memory; the bfloat16 rounding points are the inputs, the weights, the
@@ -157,13 +158,20 @@ __global__ void k_adam(float* __restrict__ P, float* __restrict__ m, float* __re
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference: the network on 32 rows per workgroup.  The weights are
-// pre-packed as bfloat16 in the order the MFMA lanes consume them: for output
-// unit n and lane half q (lanes 32 q .. 32 q + 31 feed inputs 8 k + 4 q .. + 3 of
-// K-step k), entry ((n * 2 + q) * (K / 8) + k) * 4 + j holds W[8 k + 4 q + j][n],
-// so every lane reads one contiguous run of its operands.  The input rows and the
-// first hidden layer sit in LDS as bfloat16, the second hidden layer in float32.
+// Fused inference: the network on 32 rows per workgroup, on the 32 x 32 x 16
+// bfloat16 MFMA (v_mfma_f32_32x32x16_bf16): lane l holds A[l % 32][8 (l / 32) + j]
+// and B[8 (l / 32) + j][l % 32], j = 0..7, of each K-step of 16; the result
+// layout is that of the 32 x 32 x 8 form.  The weights are pre-packed as bfloat16
+// in the order the lanes consume them: for output unit n and lane half q, entry
+// ((n * 2 + q) * (K / 16) + k) * 8 + j holds W[16 k + 8 q + j][n], so every lane
+// reads one contiguous run of its operands.
 constexpr int64_t kPacked = (int64_t)kIn * kH + (int64_t)kH * kH;  // bf16 entries
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ inline v16f mfma16(const v8s a, const v8s b, const v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 
 __global__ void k_mlp_pack(const float* __restrict__ P, short* __restrict__ W) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,12 +179,12 @@ __global__ void k_mlp_pack(const float* __restrict__ P, short* __restrict__ W) {
   const bool first = i < (int64_t)kIn * kH;
   const int K = first ? kIn : kH;
   const int64_t e = first ? i : i - (int64_t)kIn * kH;
-  const int j = (int)(e & 3);
-  const int64_t rest = e >> 2;
-  const int k = (int)(rest % (K / 8));
-  const int64_t nq = rest / (K / 8);
+  const int j = (int)(e & 7);
+  const int64_t rest = e >> 3;
+  const int k = (int)(rest % (K / 16));
+  const int64_t nq = rest / (K / 16);
   const int q = (int)(nq & 1), n = (int)(nq >> 1);
-  const int in = 8 * k + 4 * q + j;
+  const int in = 16 * k + 8 * q + j;
   W[i] = f2bf(P[(first ? oW1 : oW2) + (int64_t)in * kH + n]);
 }
 
@@ -200,13 +208,13 @@ template <class Stage>
 __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ W, Stage stage, short* sx, short* sh1,
                          float* zp, const float* socc, int64_t row0, int n, float* __restrict__ f) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = lane & 31, kq = (lane >> 5) * 4;
+  const int r = lane & 31, kq = (lane >> 5) * 8;
   const int nn = 32 * wave + r;  // this lane's weight row (output column)
-  const v4s* w1 = reinterpret_cast<const v4s*>(W) + (int64_t)(2 * nn + (lane >> 5)) * (kIn / 8);
-  const v4s* w2 = reinterpret_cast<const v4s*>(W + (int64_t)kIn * kH) + (int64_t)(2 * nn + (lane >> 5)) * (kH / 8);
-  v4s b1[kIn / 8], b2[kH / 8];
-  for (int k = 0; k < kIn / 8; ++k) b1[k] = w1[k];
-  for (int k = 0; k < kH / 8; ++k) b2[k] = w2[k];
+  const v8s* w1 = reinterpret_cast<const v8s*>(W) + (int64_t)(2 * nn + (lane >> 5)) * (kIn / 16);
+  const v8s* w2 = reinterpret_cast<const v8s*>(W + (int64_t)kIn * kH) + (int64_t)(2 * nn + (lane >> 5)) * (kH / 16);
+  v8s b1[kIn / 16], b2[kH / 16];
+  for (int k = 0; k < kIn / 16; ++k) b1[k] = w1[k];
+  for (int k = 0; k < kH / 16; ++k) b2[k] = w2[k];
   __builtin_amdgcn_sched_barrier(0);  // every weight load is in flight before the rows are staged
   stage();
   __syncthreads();
@@ -214,9 +222,9 @@ __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ 
   {
     v16f acc;
     for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-    for (int k = 0; k < kIn / 8; ++k) {
-      const v4s x = *reinterpret_cast<const v4s*>(&sx[r * kIn + 8 * k + kq]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, b1[k], acc, 0, 0, 0);
+    for (int k = 0; k < kIn / 16; ++k) {
+      const v8s x = *reinterpret_cast<const v8s*>(&sx[r * kIn + 16 * k + kq]);
+      acc = mfma16(x, b1[k], acc);
     }
     const float bias = P[ob1 + c];
     for (int rr = 0; rr < 16; ++rr) {
@@ -227,9 +235,9 @@ __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ 
   __syncthreads();
   v16f acc;
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  for (int k = 0; k < kH / 8; ++k) {
-    const v4s h = *reinterpret_cast<const v4s*>(&sh1[r * kH + 8 * k + kq]);
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(h, b2[k], acc, 0, 0, 0);
+  for (int k = 0; k < kH / 16; ++k) {
+    const v8s h = *reinterpret_cast<const v8s*>(&sh1[r * kH + 16 * k + kq]);
+    acc = mfma16(h, b2[k], acc);
   }
   const float bias = P[ob2 + c], w3 = bf(P[ow3 + c]);
   float v[16];
