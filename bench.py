@@ -44,27 +44,37 @@ SEED_MESH = 21
 # HBM traffic of the ray-test kernel per launch on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE, over the ray-test dispatches of one build),
 # each scaled by the same counter's reading for a plain device copy of known size.
-# Valid only for the kernel source it was measured on: any change to the
-# outer-volume source (hash below) reports null until the counters are re-taken.
+# Valid only for the kernel source it was measured on: the hash covers the
+# ray-test kernel's code (from kRasterCells to the end of k_raster); any change
+# there reports null until the counters are re-taken.
 K_TEST_TRAFFIC = {
-    "source_sha256": "01b7b06da4c7e2f043e6599f2a45e2d4d1900105720189abe90088b9db19cbb4",
-    "fetch_bytes_per_launch": 86353544,   # 42,166.2 KiB raw x 2.0 (copy calibration)
-    "write_bytes_per_launch": 630878,     # 616.1 KiB raw x 1.0
+    "source_sha256": "c591a7b702b31c6fce653c8bc2a574905a2e0bbb1c9ff5fc0d4034d43ff427d0",
+    "fetch_bytes_per_launch": 86406080,   # 42,191.858 KiB raw x 1.99993 (copy calibration)
+    "write_bytes_per_launch": 630873,     # 616.087 KiB raw x 1.0
     "profile": "profiles/ray_test_torus_hierarchy_traffic.md",
 }
+RASTER_BEGIN = "constexpr int kRasterCells = 16;"
+RASTER_END = "__global__ void k_or_word("
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def traffic_bytes():
-    if K_TEST_TRAFFIC is None:
-        return None
+def raster_source_sha256():
     src = os.path.join(ROOT, "paper_2203_10521_amd", "csrc", "outer_volume.hip")
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != K_TEST_TRAFFIC["source_sha256"]:
-            return None
+    with open(src) as f:
+        text = f.read()
+    try:
+        region = text[text.index(RASTER_BEGIN):text.index(RASTER_END)]
+    except ValueError:
+        return None
+    return hashlib.sha256(region.encode()).hexdigest()
+
+
+def traffic_bytes():
+    if K_TEST_TRAFFIC is None or raster_source_sha256() != K_TEST_TRAFFIC["source_sha256"]:
+        return None
     return K_TEST_TRAFFIC["fetch_bytes_per_launch"] + K_TEST_TRAFFIC["write_bytes_per_launch"]
 
 

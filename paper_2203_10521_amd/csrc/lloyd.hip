@@ -78,6 +78,13 @@ struct WallTimer {
   void stop() { s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
 
+// Upload of a call's staging area: the device reads the mapped pinned host
+// buffer directly (one launch in the stream, no runtime copy).
+__global__ void k_stage(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 // host-side sections of the flood rounds (measurement only)
 struct FloodTimers {
   WallTimer pops, cands, rank_post, exact_post, decide, grow, pred_pack, pred_launch, pred_wait;
@@ -314,7 +321,12 @@ struct Evaluator {
     std::memset(hbuf + o_ctl, 0, 256);
     t_prep.stop();
     t_dev.start();
-    OBBV_HIP(hipMemcpyAsync(dbuf, hbuf, o_out, hipMemcpyHostToDevice, stream));
+    {
+      const int64_t n16 = (int64_t)(o_out / 16);  // o_out is a multiple of 256
+      const unsigned grid = (unsigned)std::min<int64_t>((n16 + 255) / 256, 64);
+      hipLaunchKernelGGL(k_stage, dim3(grid), dim3(256), 0, stream, (const uint4*)hdev, (uint4*)dbuf, n16);
+      OBBV_HIP(hipGetLastError());
+    }
     if (rec_cap > 0) {  // one pass, no round trip; checked by finish()
       OvExec ex;
       ex.capped = true;

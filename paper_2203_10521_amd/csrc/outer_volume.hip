@@ -728,7 +728,15 @@ __global__ void __launch_bounds__(kCullThreads)
 k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict__ rec_off,
         const int32_t* __restrict__ rec_cnt, const int32_t* __restrict__ item_off,
         const int64_t* __restrict__ bin_off, int32_t* __restrict__ bin_cur, float4* __restrict__ recs,
-        int32_t* __restrict__ bins) {
+        int32_t* __restrict__ bins, const int64_t* __restrict__ chunk_off, int64_t n_tiles,
+        int32_t* __restrict__ item_tile, int64_t item_cap) {
+  if (item_tile) {  // the tile of every ray-test work item (grid-stride over the tiles)
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t c1 = min(chunk_off[t + 1], item_cap);
+      for (int64_t c = chunk_off[t]; c < c1; ++c) item_tile[c] = (int32_t)t;
+    }
+  }
   __shared__ int32_t cnt[kLdsTiles];
   __shared__ int32_t base_pos[kLdsTiles];
   __shared__ int32_t wc[kCullWaves][3];
@@ -857,14 +865,6 @@ struct TestArgs {
 template <int TE, bool STATS, bool STAGE, bool OCC>
 __device__ void test_item(const TestArgs& a, const int64_t item);
 
-// The tile of every work item (one thread per tile writes its chunks' entries).
-__global__ void k_item_tiles(const int64_t* __restrict__ chunk_off, int64_t n_tiles, int32_t* __restrict__ item_tile,
-                             int64_t cap) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const int64_t c1 = min(chunk_off[t + 1], cap);
-  for (int64_t c = chunk_off[t]; c < c1; ++c) item_tile[c] = (int32_t)t;
-}
 
 template <int TE, bool STATS, bool STAGE, bool OCC>
 __global__ void __launch_bounds__(kTestThreads) k_test(TestArgs a) {
@@ -1610,8 +1610,17 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       OBBV_RET(pool_get(pool_base + kPoolRecords, (size_t)n_rec * kRecBytes, &recs_v));
       OBBV_RET(pool_get(pool_base + kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
     }
+    int32_t* itile = nullptr;
+    if (fixed) {
+      itile = ex->itile;
+    } else {
+      void* tv = nullptr;
+      OBBV_RET(pool_get(pool_base + kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * 4, &tv));
+      itile = (int32_t*)tv;
+    }
     hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
-                       d_reccnt, (const int32_t*)d_ioff, d_binoff, d_bincur, (float4*)recs_v, (int32_t*)bins_v);
+                       d_reccnt, (const int32_t*)d_ioff, d_binoff, d_bincur, (float4*)recs_v, (int32_t*)bins_v,
+                       (const int64_t*)d_chunkoff, nbw * TT, n_items > 0 ? itile : (int32_t*)nullptr, n_items);
     OBBV_HIP(hipGetLastError());
     TestArgs ta;
     ta.boxes = boxes;
@@ -1630,14 +1639,6 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     ta.side = d_side;
     ta.bin_cap = fixed ? ex->bin_cap : INT64_MAX;
     ta.item_cap = fixed ? ex->item_cap : INT64_MAX;
-    int32_t* itile = nullptr;
-    if (fixed) {
-      itile = ex->itile;
-    } else {
-      void* tv = nullptr;
-      OBBV_RET(pool_get(pool_base + kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * 4, &tv));
-      itile = (int32_t*)tv;
-    }
     ta.item_tile = itile;
     ta.persistent = fixed ? 1 : 0;
     ta.rframe = d_rframe;
@@ -1659,9 +1660,6 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       if (out_ray_hits) OBBV_HIP(hipMemsetAsync(out_ray_hits, 0, per, s));
     }
     if (n_items > 0) {
-      hipLaunchKernelGGL(k_item_tiles, dim3((unsigned)ceil_div(nbw * TT, 256)), dim3(256), 0, s,
-                         (const int64_t*)d_chunkoff, nbw * TT, itile, n_items);
-      OBBV_HIP(hipGetLastError());
       const bool stage = test_stage_choice();
       const int64_t grid = fixed ? std::min<int64_t>(n_items, 256 * 32) : n_items;
       if (TE == 8)
