@@ -94,7 +94,14 @@ struct OvExec {
   uint32_t* status = nullptr;
   int64_t* publish = nullptr;
   int pool_base = 0;  // slot offset of the pool set the call's pooled scratch comes from
+  // nullable: jitter table (jitter_table) covering every key of the call, built
+  // for this R and seed; the ray-test kernel then reads the draws from it
+  const uint2* jitter = nullptr;
+  int jitter_R = 0;
+  uint64_t jitter_seed = 0;
 };
+// Jitter table of keys [0, n_keys) for ray grids of R x R cells (stream ordered).
+int jitter_table(uint64_t seed, int R, int64_t n_keys, uint2* out, hipStream_t s);
 int status_word(uint32_t** out);   // device pointer of this device's status word
 
 // measurement hooks (obbv_profile_enable / obbv_profile_read)

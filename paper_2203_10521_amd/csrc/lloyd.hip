@@ -142,6 +142,7 @@ struct Evaluator {
   }
 
   ~Evaluator() {
+    if (jtab) (void)hipFree(jtab);
     if (dbuf) (void)hipFree(dbuf);
     if (hbuf) (void)hipHostFree(hbuf);
     if (sbuf) (void)hipFree(sbuf);
@@ -198,8 +199,50 @@ struct Evaluator {
   // the enqueued evaluation has finished (no wait)
   bool ready() const { return !in_flight || published(); }
 
+  // Jitter table of the keys [0, jkeys) at this R and seed (device), so the
+  // ray-test kernel reads the draws instead of recomputing them in every call.
+  uint2* jtab = nullptr;
+  int64_t jkeys = 0;
+  int jR = 0;
+  uint64_t jseed = 0;
+  bool jtab_use = false;
+  static constexpr int64_t kJitterTableBytes = (int64_t)256 << 20;
+
+  int ensure_jitter(const std::vector<uint32_t>& keys) {
+    uint32_t kmax = 0;
+    for (uint32_t k : keys) kmax = std::max(kmax, k);
+    const int R = params.R;
+    const int64_t per_key = 3 * (int64_t)R * R * (int64_t)sizeof(uint2);
+    const int64_t want = ((int64_t)kmax + 64) / 64 * 64;
+    jtab_use = want * per_key <= kJitterTableBytes;
+    if (!jtab_use) return OBBV_OK;
+    if (jtab && want <= jkeys && jR == R && jseed == params.seed) return OBBV_OK;
+    if (jtab) {
+      OBBV_HIP(hipStreamSynchronize(stream));
+      OBBV_HIP(hipFree(jtab));
+      jtab = nullptr;
+      jkeys = 0;
+    }
+    if (hipMalloc((void**)&jtab, (size_t)(want * per_key)) != hipSuccess) {
+      (void)hipGetLastError();
+      jtab = nullptr;
+      jtab_use = false;  // evaluate without the table
+      return OBBV_OK;
+    }
+    OBBV_RET(jitter_table(params.seed, R, want, jtab, stream));
+    jkeys = want;
+    jR = R;
+    jseed = params.seed;
+    return OBBV_OK;
+  }
+
   int run_call(OvExec* ex) {
     ex->pool_base = pool_base;
+    if (jtab_use) {
+      ex->jitter = jtab;
+      ex->jitter_R = jR;
+      ex->jitter_seed = jseed;
+    }
     double* hout = (double*)(hdev + o_out);  // results go straight to pinned host memory
     if (cur_shared)
       return outer_volume_frames(&mesh, (const obbv_box*)(dbuf + o_box), (const uint32_t*)(dbuf + o_key),
@@ -321,6 +364,7 @@ struct Evaluator {
     std::memset(hbuf + o_ctl, 0, 256);
     t_prep.stop();
     t_dev.start();
+    OBBV_RET(ensure_jitter(keys));
     {
       const int64_t n16 = (int64_t)(o_out / 16);  // o_out is a multiple of 256
       const unsigned grid = (unsigned)std::min<int64_t>((n16 + 255) / 256, 64);

@@ -79,7 +79,8 @@ struct RayFrame {
   uint64_t s0;
   float eu, ev;
   int32_t state;
-  int32_t pad[3];
+  uint32_t key;  // the box's jitter key
+  int32_t pad[2];
 };
 static_assert(sizeof(RayFrame) == 80, "RayFrame layout");
 
@@ -504,7 +505,8 @@ __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, 
     const uint32_t key = box_key ? box_key[b] : (uint32_t)b;
     f.s0 = seed + (2ull * (((uint64_t)key << 32) | ((uint64_t)w << 30)) + 1ull) * kGamma;
     f.state = box_state(B);
-    f.pad[0] = f.pad[1] = f.pad[2] = 0;
+    f.key = key;
+    f.pad[0] = f.pad[1] = 0;
     rframe[bw] = f;
   }
   // counters of this (box, axis) that later passes accumulate into
@@ -855,6 +857,7 @@ struct TestArgs {
   const int32_t* item_tile;  // [work items] tile of every work item
   int persistent;       // 1: grid-stride over the work items counted on the device
   const RayFrame* rframe;    // [nbw] ray grid of every (box, axis) cast
+  const uint2* jitter;       // nullable: jitter table [keys][3][R][R] (jitter_table), every key < its rows
 };
 
 // One wave per TE x TE ray tile of one (box, axis); RPL = (TE/8)^2 rays per lane.
@@ -1034,7 +1037,7 @@ __device__ inline bool ray_hit(float u, float v, const float4& r0, const float4&
   return mn >= 0.0f;
 }
 
-template <bool STATS>
+template <bool STATS, bool TAB>
 __device__ void raster_item(const TestArgs& a, const int64_t item) {
   const int TT = a.tpe * a.tpe;
   const int64_t g = a.item_tile[item];
@@ -1064,18 +1067,33 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
   // Ray r = lane + 64 k sits in cell (ci_lo + lane % 16, cj_lo + lane / 16 + 4 k):
   // its u draw has state rf.s0 + 2 ((i << 15) + j) GAMMA = z + 8 k GAMMA, where z
   // is the lane's k = 0 state, and its v draw one GAMMA more.
+  // With a jitter table (TAB) the two draws of every ray are read from it instead
+  // (the same 24-bit values, computed once per key by jitter_table).
   const int i = ci_lo + (lane & 15);
   const uint32_t t0 = ((uint32_t)i << 15) + (uint32_t)(cj_lo + (lane >> 4));
   const uint64_t z0 = rf.s0 + (uint64_t)t0 * (2ull * kGamma);
+  uint2 jq[4];
+  if (TAB) {  // unconditional, clamped reads: the counters of outstanding loads stay exact
+    const uint2* jt = a.jitter + ((int64_t)rf.key * 3 + w) * (int64_t)a.R * a.R;
+    const int ic = min(i, a.R - 1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) jq[k] = jt[(int64_t)min(cj_lo + (lane >> 4) + 4 * k, a.R - 1) * a.R + ic];
+  }
   auto make_ray = [&](int k) {
     const int r = lane + 64 * k;
     const int j = cj_lo + (r >> 4);
     valid[k] = i < a.R && j < a.R;
     ru[k] = rv[k] = 0.f;
     if (valid[k]) {
-      const uint64_t zu = z0 + (uint64_t)k * (8ull * kGamma);
-      const double xi = u24(mix64(zu));
-      const double eta = u24(mix64(zu + kGamma));
+      double xi, eta;
+      if (TAB) {
+        xi = (double)jq[k].x * (1.0 / 16777216.0);
+        eta = (double)jq[k].y * (1.0 / 16777216.0);
+      } else {
+        const uint64_t zu = z0 + (uint64_t)k * (8ull * kGamma);
+        xi = u24(mix64(zu));
+        eta = u24(mix64(zu + kGamma));
+      }
       ru[k] = (float)__dadd_rn(-hu, __dmul_rn(__dadd_rn((double)i, xi), du));
       rv[k] = (float)__dadd_rn(-hv, __dmul_rn(__dadd_rn((double)j, eta), dv));
     }
@@ -1215,17 +1233,30 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
   if (lane == 0 && a.test_counter) atomicAdd(a.test_counter, (unsigned long long)tests);
 }
 
-template <bool STATS>
+template <bool STATS, bool TAB>
 __global__ void __launch_bounds__(kTestThreads) k_raster(TestArgs a) {
   if (!a.persistent) {
-    raster_item<STATS>(a, xcd_remap(blockIdx.x, gridDim.x));
+    raster_item<STATS, TAB>(a, xcd_remap(blockIdx.x, gridDim.x));
     return;
   }
   const int64_t total = min(a.chunk_off[a.n_tiles], a.item_cap);
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    raster_item<STATS>(a, item);
+    raster_item<STATS, TAB>(a, item);
     __syncthreads();  // LDS of the next item
   }
+}
+
+// Jitter table of keys [0, n_keys): entry ((key * 3 + w) * R + j) * R + i holds
+// the top 24 bits of the u and v draws of cell (i, j) of cast axis w.
+__global__ void k_jitter_table(uint64_t seed, int R, int64_t n, uint2* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int i = (int)(e % R), j = (int)((e / R) % R);
+  const int64_t kw = e / ((int64_t)R * R);
+  const int w = (int)(kw % 3);
+  const uint32_t key = (uint32_t)(kw / 3);
+  const uint64_t c = ray_counter(key, w, i, j);
+  out[e] = make_uint2((uint32_t)(splitmix64_at(seed, c) >> 40), (uint32_t)(splitmix64_at(seed, c + 1) >> 40));
 }
 
 __global__ void k_or_word(uint32_t* __restrict__ w, uint32_t bits) { atomicOr(w, bits); }
@@ -1326,9 +1357,11 @@ int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hip
   const dim3 g((unsigned)nblocks), b(kTestThreads);
   if (TE == 16 && !ta.occ && test_raster_choice()) {
     if (stats)
-      hipLaunchKernelGGL((k_raster<true>), g, b, 0, s, ta);
+      hipLaunchKernelGGL((k_raster<true, false>), g, b, 0, s, ta);
+    else if (ta.jitter)
+      hipLaunchKernelGGL((k_raster<false, true>), g, b, 0, s, ta);
     else
-      hipLaunchKernelGGL((k_raster<false>), g, b, 0, s, ta);
+      hipLaunchKernelGGL((k_raster<false, false>), g, b, 0, s, ta);
   } else if (ta.occ && TE == 8)
     hipLaunchKernelGGL((k_test<TE, false, true, true>), g, b, 0, s, ta);
   else if (stats && stage)
@@ -1642,6 +1675,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     ta.item_tile = itile;
     ta.persistent = fixed ? 1 : 0;
     ta.rframe = d_rframe;
+    ta.jitter = ex && ex->jitter && R == ex->jitter_R && params->seed == ex->jitter_seed ? ex->jitter : nullptr;
     void* prof_token = nullptr;
     if (profiling_enabled() && !planned) {
       OBBV_RET(profile_counter(&ta.test_counter));
@@ -1693,6 +1727,15 @@ int outer_volume_exec(const obbv_mesh* mesh, const obbv_box* boxes, const uint32
                       const obbv_ov_params* params, double* out_obv, hipStream_t s, OvExec* ex) {
   return outer_volume_run(mesh, 1, boxes, nullptr, box_key, n_boxes, params, out_obv, nullptr, nullptr, nullptr,
                           nullptr, s, nullptr, ex, nullptr);
+}
+
+int jitter_table(uint64_t seed, int R, int64_t n_keys, uint2* out, hipStream_t s) {
+  OBBV_ARG(R >= 1 && R <= 32767 && n_keys >= 0 && out, "bad jitter table");
+  const int64_t n = n_keys * 3 * (int64_t)R * R;
+  if (n == 0) return OBBV_OK;
+  hipLaunchKernelGGL(k_jitter_table, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, seed, R, n, out);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
 }
 
 int status_or(uint32_t bits, hipStream_t s) {
