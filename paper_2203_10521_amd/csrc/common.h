@@ -90,7 +90,7 @@ struct OvExec {
   int64_t n_rec = 0, n_bin = 0, n_items = 0;  // counts of the last synchronous run
   char* items = nullptr;                      // per-cull-item counts and offsets
   size_t items_cap = 0, items_bytes = 0;
-  int32_t* itile = nullptr;                   // [item_cap] tile of every ray-test work item
+  int4* itile = nullptr;                      // [item_cap] ray-test work items (WorkItem layout)
   uint32_t* status = nullptr;
   int64_t* publish = nullptr;
   int pool_base = 0;  // slot offset of the pool set the call's pooled scratch comes from

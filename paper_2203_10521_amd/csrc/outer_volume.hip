@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kCullThreads = 256;
 constexpr int kTestThreads = 64;
-constexpr int kTestChunk = 256;  // records per ray-test work item
+constexpr int kTestChunk = 512;  // records per ray-test work item (measured best of 64..4096)
 
 struct BoxRegs {
   float Q[9];
@@ -731,12 +731,17 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
         const int32_t* __restrict__ rec_cnt, const int32_t* __restrict__ item_off,
         const int64_t* __restrict__ bin_off, int32_t* __restrict__ bin_cur, float4* __restrict__ recs,
         int32_t* __restrict__ bins, const int64_t* __restrict__ chunk_off, int64_t n_tiles,
-        int32_t* __restrict__ item_tile, int64_t item_cap) {
-  if (item_tile) {  // the tile of every ray-test work item (grid-stride over the tiles)
+        int4* __restrict__ item_tile, int64_t item_cap, int chunk) {
+  if (item_tile) {  // the ray-test work items: tile, record count, first bin entry (grid-stride over the tiles)
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles;
          t += (int64_t)gridDim.x * blockDim.x) {
-      const int64_t c1 = min(chunk_off[t + 1], item_cap);
-      for (int64_t c = chunk_off[t]; c < c1; ++c) item_tile[c] = (int32_t)t;
+      const int64_t c0 = chunk_off[t], c1 = min(chunk_off[t + 1], item_cap);
+      const int64_t b0 = bin_off[t], b1 = bin_off[t + 1];
+      for (int64_t c = c0; c < c1; ++c) {
+        const int64_t k0 = b0 + (c - c0) * chunk;
+        const int cnt = (int)(min(b1, k0 + chunk) - k0);
+        item_tile[c] = make_int4((int)t, cnt, (int)(uint32_t)(uint64_t)k0, (int)(uint32_t)((uint64_t)k0 >> 32));
+      }
     }
   }
   __shared__ int32_t cnt[kLdsTiles];
@@ -854,7 +859,7 @@ struct TestArgs {
   uint32_t axis_mask;
   int64_t bin_cap;      // planned launches: bins beyond it were not written
   int64_t item_cap;     // planned launches: work items beyond it are skipped
-  const int32_t* item_tile;  // [work items] tile of every work item
+  const int4* item_tile;     // [work items] tile, record count, first bin entry (lo, hi) of every work item
   int persistent;       // 1: grid-stride over the work items counted on the device
   const RayFrame* rframe;    // [nbw] ray grid of every (box, axis) cast
   const uint2* jitter;       // nullable: jitter table [keys][3][R][R] (jitter_table), every key < its rows
@@ -885,7 +890,7 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
   constexpr int RPL = NB * NB;
   const int TT = a.tpe * a.tpe;
   // tile of this work item: chunk_off[g] <= item < chunk_off[g + 1]
-  const int64_t g = a.item_tile[item];
+  const int64_t g = a.item_tile[item].x;
   const int bw = (int)(g / TT);
   const int tile = (int)(g - (int64_t)bw * TT);
   const int b = bw / 3, w = bw - 3 * (bw / 3);
@@ -1040,15 +1045,15 @@ __device__ inline bool ray_hit(float u, float v, const float4& r0, const float4&
 template <bool STATS, bool TAB>
 __device__ void raster_item(const TestArgs& a, const int64_t item) {
   const int TT = a.tpe * a.tpe;
-  const int64_t g = a.item_tile[item];
+  const int4 wi = a.item_tile[item];  // tile, record count, first bin entry
+  const int64_t g = wi.x;
   const int bw = (int)(g / TT);
   const int tile = (int)(g - (int64_t)bw * TT);
   const int w = bw - 3 * (bw / 3);
   if (!((a.axis_mask >> w) & 1u)) return;
   const int lane = threadIdx.x;
-  const int64_t kb = a.bin_off[g] + (item - a.chunk_off[g]) * a.chunk;
-  const int64_t k0 = kb;
-  const int64_t k1 = min(a.bin_off[g + 1], kb + a.chunk);
+  const int64_t k0 = (int64_t)(((uint64_t)(uint32_t)wi.w << 32) | (uint32_t)wi.z);
+  const int64_t k1 = k0 + wi.y;
   if (k1 > a.bin_cap) return;  // bins past a planned capacity were not written (flagged)
   // (boxes whose state is not 0 get no records, hence no ray-test work items)
   const RayFrame rf = a.rframe[bw];
@@ -1351,6 +1356,7 @@ int pinned_totals(int64_t** out) {
 namespace {
 
 bool test_raster_choice();
+int test_chunk_choice();
 
 template <int TE>
 int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hipStream_t s) {
@@ -1385,6 +1391,17 @@ bool test_raster_choice() {
   const char* e = getenv("OBBV_TEST_RASTER");
   if (e && *e) return atoi(e) != 0;
   return true;
+}
+
+// Records per ray-test work item: kTestChunk, or OBBV_TEST_CHUNK (64..4096, a
+// multiple of 64) to compare work-item sizes on a device.
+int test_chunk_choice() {
+  const char* e = getenv("OBBV_TEST_CHUNK");
+  if (e && *e) {
+    const int c = atoi(e);
+    if (c >= 64 && c <= 4096 && c % 64 == 0) return c;
+  }
+  return kTestChunk;
 }
 
 bool test_stage_choice() {
@@ -1591,7 +1608,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   hipLaunchKernelGGL(k_tile_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_tilecnt);
   OBBV_HIP(hipGetLastError());
   // bin and work-item offsets of the tiles, record offsets of the (box, axis) pairs
-  const int chunk = kTestChunk;
+  const int chunk = test_chunk_choice();
   {
     const int64_t nt_all = nbw * TT;
     const int64_t nb = ceil_div(nt_all, kScanBlockThreads);
@@ -1643,17 +1660,17 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       OBBV_RET(pool_get(pool_base + kPoolRecords, (size_t)n_rec * kRecBytes, &recs_v));
       OBBV_RET(pool_get(pool_base + kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
     }
-    int32_t* itile = nullptr;
+    int4* itile = nullptr;
     if (fixed) {
       itile = ex->itile;
     } else {
       void* tv = nullptr;
-      OBBV_RET(pool_get(pool_base + kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * 4, &tv));
-      itile = (int32_t*)tv;
+      OBBV_RET(pool_get(pool_base + kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * sizeof(int4), &tv));
+      itile = (int4*)tv;
     }
     hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
                        d_reccnt, (const int32_t*)d_ioff, d_binoff, d_bincur, (float4*)recs_v, (int32_t*)bins_v,
-                       (const int64_t*)d_chunkoff, nbw * TT, n_items > 0 ? itile : (int32_t*)nullptr, n_items);
+                       (const int64_t*)d_chunkoff, nbw * TT, n_items > 0 ? itile : (int4*)nullptr, n_items, chunk);
     OBBV_HIP(hipGetLastError());
     TestArgs ta;
     ta.boxes = boxes;
@@ -2016,7 +2033,7 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   ex.item_cap = (int64_t)std::ceil((double)probe.n_items * headroom) + 64;
   ex.items_cap = probe.items_bytes;
   const size_t bytes = align_up(ex.meta_cap) + align_up((size_t)ex.rec_cap * kRecBytes) + align_up((size_t)ex.bin_cap * 4) +
-                       align_up(ex.items_cap) + align_up((size_t)ex.item_cap * 4);
+                       align_up(ex.items_cap) + align_up((size_t)ex.item_cap * sizeof(int4));
   if (hipMalloc(&P->alloc, bytes) != hipSuccess) {
     (void)hipGetLastError();
     set_error("hipMalloc of the planned scratch failed");
@@ -2026,7 +2043,7 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   ex.recs = (float4*)(ex.meta + align_up(ex.meta_cap));
   ex.bins = (int32_t*)((char*)ex.recs + align_up((size_t)ex.rec_cap * kRecBytes));
   ex.items = (char*)ex.bins + align_up((size_t)ex.bin_cap * 4);
-  ex.itile = (int32_t*)(ex.items + align_up(ex.items_cap));
+  ex.itile = (int4*)(ex.items + align_up(ex.items_cap));
   // the mesh table lives at the start of the meta block (outside the graph)
   std::vector<MeshDev> mh((size_t)n_meshes);
   for (int m = 0; m < n_meshes; ++m)
