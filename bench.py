@@ -110,7 +110,7 @@ def saturated(api, torch, Vt, Ft, boxes, R, seed):
             "achieved_tflops": achieved, "frac": achieved / FP32_PEAK_TFLOPS}
 
 
-def surrogate_comparison(api, torch, Vt, Ft, hp, exact, judge_every=(16,)):
+def surrogate_comparison(api, torch, Vt, Ft, hp, exact, judge_every=(32,)):
     """Train the ranker on exact outer fractions of noisy spheres (not the torus):
     boxes recorded during exact Lloyd iterations plus random boxes around the
     surface; then rebuild the same torus hierarchy with ranker-guided floods."""
@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-saturated", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--judge-every", default="16",
+    ap.add_argument("--judge-every", default="32",
                     help="surrogate: every n-th flood round exact (comma list: the first is reported)")
     ap.add_argument("--iters", type=int, default=HIER["iters"], help="Lloyd iterations per layer")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -285,11 +285,12 @@ int obbv_lloyd_step(obbv_lloyd* st, void* stream);
  * the box with the smallest change (exact where evaluated, predicted elsewhere);
  * a round with nothing to verify makes no outer-volume call on the caller's
  * stream.  Every judge_every-th ranked round also sends up to 256 of its
- * candidates (evenly strided) to an exact evaluation on a second stream; when
- * it has finished (checked at the start of each round, awaited at the end of the
- * flood) the errors |predicted - exact| outer fraction enter a rolling mean over
- * the last 256: above max_error the rest of that iteration is exact (counted as
- * a fallback).  The outer volumes of grown boxes, the final boxes of the flood
+ * candidates (evenly strided) to an exact evaluation on a second stream, which
+ * runs while the flood goes on; at the next such round (or the end of the flood)
+ * its errors |predicted - exact| outer fraction enter a rolling mean over the
+ * last 256: above max_error the rest of that iteration is exact (counted as a
+ * fallback).  The judged rounds and the rounds at which their errors count do
+ * not depend on timing, so a build is reproducible.  The outer volumes of grown boxes, the final boxes of the flood
  * and the parameter update stay exact.  NULL returns to exact evaluation of
  * every candidate.  The structure is copied; its device arrays must stay valid. */
 int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* surrogate);

@@ -53,7 +53,8 @@ enum PoolSlot {
   kPoolItems = 7,
   kPoolTiles = 8,
   kPoolRank = 9,
-  kPoolCount = 10
+  kPoolTileCnt2 = 10,  // zero between calls (each call leaves what it used zero)
+  kPoolCount = 11
 };
 // Two sets of the slots: calls that may run at the same time on different
 // streams take their scratch from different sets (slot + set * kPoolCount).
@@ -63,6 +64,8 @@ constexpr int kPoolSets = 2;
 // least `bytes` and returns it.  Growing frees the old block (hipFree waits for
 // the device), so call it only where no queued kernel still reads that slot.
 int pool_get(int slot, size_t bytes, void** out);
+// As pool_get; a new (grown) block is zeroed before it is returned.
+int pool_get_zeroed(int slot, size_t bytes, void** out);
 
 // A ray-test record: 5 float4 = 80 bytes (edge planes, depth plane, clamp,
 // sign, projected bounding box).

@@ -494,8 +494,7 @@ struct Predictor {
   std::vector<float> jpred;
   std::vector<double> jvals;
   int64_t judged_evals = 0;
-
-  bool judge_busy() const { return jev.in_flight; }
+  double jerr_sum = 0.0, jerr_max = 0.0;  // all judged errors (measurement)
 
   int judge_begin(const Evaluator& ev, const std::vector<HBox>& cb, const std::vector<uint32_t>& ck,
                   const std::vector<float>& fp, size_t n) {
@@ -529,7 +528,12 @@ struct Predictor {
     for (size_t x = 0; x < jvals.size(); ++x) {
       const HBox& bx = jboxes[x];
       const double vb = 8.0 * (double)bx.h[0] * (double)bx.h[1] * (double)bx.h[2];
-      if (vb > 0.0) judge(std::fabs((double)jpred[x] - jvals[x] / vb));
+      if (vb > 0.0) {
+        const double err = std::fabs((double)jpred[x] - jvals[x] / vb);
+        jerr_sum += err;
+        jerr_max = std::max(jerr_max, err);
+        judge(err);
+      }
     }
     return OBBV_OK;
   }
@@ -1002,11 +1006,6 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     dpred.assign(cands.size(), 0.0);
     predicted_c.assign(cands.size(), 0);
     fcand.clear();  // prediction of each kept candidate (judge)
-    if (pred && pred->on) {  // a finished judge evaluation enters the judge
-      const int64_t before = pred->judged_evals;
-      OBBV_RET(pred->judge_poll(false));
-      cnt.evals += pred->judged_evals - before;
-    }
     const bool ranked = pred && pred->on && !pred->paused && !cidx.empty();
     const bool judge_round = ranked && round_no % std::max(1, pred->cfg.judge_every) == 0;
     ++round_no;
@@ -1020,7 +1019,15 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         }
       }
       OBBV_RET(pred->predict(cb, pb, fp, &overlap_once));
-      if (judge_round && !pred->judge_busy()) OBBV_RET(pred->judge_begin(ev, cb, ck, fp, cidx.size()));
+      if (judge_round) {
+        // the previous judge evaluation enters the judge now (waiting for it if
+        // needed), then this round's sample is sent: the judged rounds and the
+        // round at which their errors count are fixed, whatever the timing
+        const int64_t before = pred->judged_evals;
+        OBBV_RET(pred->judge_poll(true));
+        cnt.evals += pred->judged_evals - before;
+        OBBV_RET(pred->judge_begin(ev, cb, ck, fp, cidx.size()));
+      }
       g_ft.rank_post.start();
       const size_t top = (size_t)std::max(0, pred->cfg.verify_top);
       const bool rank_top = top > 0;
@@ -1407,6 +1414,10 @@ struct LloydState {
             "decisions %.3f s, growth %.3f s; ranker: pack %.3f s, launch %.3f s, wait %.3f s\n",
             f.pops.s, f.cands.s, f.rank_post.s, f.exact_post.s, f.decide.s, f.grow.s, f.pred_pack.s, f.pred_launch.s,
             f.pred_wait.s);
+    if (pred.judged_evals > 0)
+      fprintf(stderr, "[obbv lloyd] judge: %lld candidates, mean |f - exact| %.5f, max %.5f, fallbacks %lld\n",
+              (long long)pred.judged_evals, pred.jerr_sum / (double)pred.judged_evals, pred.jerr_max,
+              (long long)pred.fallbacks);
     g_ft = FloodTimers();
   }
 };

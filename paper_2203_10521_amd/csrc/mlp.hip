@@ -190,9 +190,13 @@ __global__ void k_mlp_pack(const float* __restrict__ P, short* __restrict__ W) {
 
 constexpr int kFusedRows = 32;
 static_assert(kFeatIn == kIn, "feature rows and the first layer disagree");
+// LDS row pitches of the tile (bfloat16 entries): 8 more than the row, so the
+// 32 rows a K-step reads fall in different banks (a pitch of 256 entries put
+// every row in the same one)
+constexpr int kInPitch = kIn + 8, kHPitch = kH + 8;
 
 // The network on one tile of kFusedRows rows, by one workgroup of kRowThreads.
-// Layers 1 and 2: bfloat16 rows sx [32][kIn] -> sh1 (bfloat16 [32][kH]) -> the
+// Layers 1 and 2: bfloat16 rows sx [32][kInPitch] -> sh1 (bfloat16 [32][kHPitch]) -> the
 // second hidden layer in registers.  Eight waves, wave w computes the 32 x 32
 // output tile of columns 32 w .. 32 w + 31.  A wave's weight operands for both
 // layers (544 + 256 contiguous bytes per lane) are issued before the rows are
@@ -223,20 +227,20 @@ __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ 
     v16f acc;
     for (int i = 0; i < 16; ++i) acc[i] = 0.f;
     for (int k = 0; k < kIn / 16; ++k) {
-      const v8s x = *reinterpret_cast<const v8s*>(&sx[r * kIn + 16 * k + kq]);
+      const v8s x = *reinterpret_cast<const v8s*>(&sx[r * kInPitch + 16 * k + kq]);
       acc = mfma16(x, b1[k], acc);
     }
     const float bias = P[ob1 + c];
     for (int rr = 0; rr < 16; ++rr) {
       const int row = 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4);
-      sh1[row * kH + c] = f2bf(fmaxf(acc[rr] + bias, 0.f));
+      sh1[row * kHPitch + c] = f2bf(fmaxf(acc[rr] + bias, 0.f));
     }
   }
   __syncthreads();
   v16f acc;
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
   for (int k = 0; k < kH / 16; ++k) {
-    const v8s h = *reinterpret_cast<const v8s*>(&sh1[r * kH + 16 * k + kq]);
+    const v8s h = *reinterpret_cast<const v8s*>(&sh1[r * kHPitch + 16 * k + kq]);
     acc = mfma16(h, b2[k], acc);
   }
   const float bias = P[ob2 + c], w3 = bf(P[ow3 + c]);
@@ -265,14 +269,17 @@ __global__ void __launch_bounds__(kRowThreads)
 k_mlp_rows(const float* __restrict__ P, const short* __restrict__ W, const float* __restrict__ X,
            const short* __restrict__ Xb, const float* __restrict__ occ, int n, float* __restrict__ f,
            unsigned* done_count, unsigned* done_flag, unsigned seq) {
-  __shared__ short sx[kFusedRows * kIn];
-  __shared__ short sh1[kFusedRows * kH];
+  __shared__ short sx[kFusedRows * kInPitch];
+  __shared__ short sh1[kFusedRows * kHPitch];
   __shared__ float zp[(kRowThreads / 64) * kFusedRows];
   __shared__ float socc[kFusedRows];
   const int64_t row0 = (int64_t)blockIdx.x * kFusedRows;
   auto stage = [&]() {
     if constexpr (kFloat) {
-      for (int i = threadIdx.x; i < kFusedRows * kIn; i += blockDim.x) sx[i] = f2bf(X[row0 * kIn + i]);
+      for (int i = threadIdx.x; i < kFusedRows * kIn; i += blockDim.x) {
+        const int rw = i / kIn;
+        sx[rw * kInPitch + (i - rw * kIn)] = f2bf(X[row0 * kIn + i]);
+      }
       const int wave = threadIdx.x >> 6;
       for (int rw = wave; rw < kFusedRows; rw += kRowThreads / 64) {
         const float* x = X + (row0 + rw) * kIn;
@@ -286,7 +293,7 @@ k_mlp_rows(const float* __restrict__ P, const short* __restrict__ W, const float
         const int rw = i / kChunks, c = i - rw * kChunks;
         v4i q = {0, 0, 0, 0};
         if (row0 + rw < n) q = *reinterpret_cast<const v4i*>(Xb + (row0 + rw) * kIn + 8 * c);
-        *reinterpret_cast<v4i*>(&sx[rw * kIn + 8 * c]) = q;
+        *reinterpret_cast<v4i*>(&sx[rw * kInPitch + 8 * c]) = q;
       }
       if (threadIdx.x < kFusedRows) socc[threadIdx.x] = row0 + threadIdx.x < n ? occ[row0 + threadIdx.x] : 0.f;
     }

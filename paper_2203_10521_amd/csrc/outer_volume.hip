@@ -434,11 +434,19 @@ __global__ void k_frame_scan(const int32_t* __restrict__ item_cnt, int n_frames,
 // Which prism(s) the triangle belongs to, per cast axis.
 //   above: projects into the face and reaches above the slab bottom (z_max > -h)
 //   below: projects into the face and reaches below the slab top   (z_min <  h)
+// Tile counters of one work item (one box, 256 triangles, three axes; both
+// sides in the cull pass) are aggregated in LDS when they fit (6 TT resp. 3 TT
+// <= kLdsTiles) and flushed with one global atomic per non-zero tile.
+constexpr int kLdsTiles = 3 * 1024;
+
 __global__ void __launch_bounds__(kCullThreads)
-k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt) {
+k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt, int32_t* __restrict__ tile_cnt2) {
   __shared__ int32_t wc[kCullWaves][6];
+  __shared__ int32_t cnt[kLdsTiles];
   const int64_t total = a.chunk_off[a.n_boxes];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int TT = a.tpe * a.tpe;
+  const bool lds = 6 * TT <= kLdsTiles;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item_box(a.chunk_off, a.n_boxes, item);
     const BoxRegs B = load_box(a.boxes, b);
@@ -447,6 +455,10 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt) {
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
     const bool ok = valid && cull_tri(a, b, M, B, t, P);
+    if (lds) {
+      for (int k = threadIdx.x; k < 6 * TT; k += kCullThreads) cnt[k] = 0;
+      __syncthreads();
+    }
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       bool ka = false, kb = false;
@@ -458,6 +470,22 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt) {
           const float zmax = fmaxf(fmaxf(tr.z[0], tr.z[1]), tr.z[2]);
           ka = zmax > -f.hw;
           kb = zmin < f.hw;
+          if (ka || kb) {  // tile counts of both sides (the mirrored cast negates z only)
+            int ti0, ti1, tj0, tj1;
+            tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
+            for (int tj = tj0; tj <= tj1; ++tj)
+              for (int ti = ti0; ti <= ti1; ++ti) {
+                const int k = tj * a.tpe + ti;
+                if (lds) {
+                  if (ka) atomicAdd(&cnt[(2 * w) * TT + k], 1);
+                  if (kb) atomicAdd(&cnt[(2 * w + 1) * TT + k], 1);
+                } else {
+                  const int64_t base = (int64_t)(b * 3 + w) * 2 * TT;
+                  if (ka) atomicAdd(&tile_cnt2[base + k], 1);
+                  if (kb) atomicAdd(&tile_cnt2[base + TT + k], 1);
+                }
+              }
+          }
         }
       }
       const uint64_t ma = __ballot(ka), mb = __ballot(kb);
@@ -472,6 +500,10 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt) {
       for (int v = 0; v < kCullWaves; ++v) c += wc[v][threadIdx.x];
       item_cnt[6 * item + threadIdx.x] = c;
     }
+    if (lds) {  // [axis][side][tile] of this box: the layout of tile_cnt2
+      for (int k = threadIdx.x; k < 6 * TT; k += kCullThreads)
+        if (cnt[k]) atomicAdd(&tile_cnt2[(int64_t)b * 6 * TT + k], cnt[k]);
+    }
     __syncthreads();
   }
 }
@@ -484,7 +516,7 @@ __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, 
                             int32_t* __restrict__ item_off, int TT, int32_t* __restrict__ tile_cnt,
                             int32_t* __restrict__ bin_cur, unsigned long long* __restrict__ acc,
                             const obbv_box* __restrict__ boxes, const uint32_t* __restrict__ box_key, int R,
-                            uint64_t seed, RayFrame* __restrict__ rframe) {
+                            uint64_t seed, RayFrame* __restrict__ rframe, int32_t* __restrict__ tile_cnt2) {
   const int bw = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (bw >= 3 * n_boxes) return;
@@ -510,10 +542,7 @@ __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, 
     rframe[bw] = f;
   }
   // counters of this (box, axis) that later passes accumulate into
-  for (int k = lane; k < TT; k += 64) {
-    tile_cnt[(int64_t)bw * TT + k] = 0;
-    bin_cur[(int64_t)bw * TT + k] = 0;
-  }
+  for (int k = lane; k < TT; k += 64) bin_cur[(int64_t)bw * TT + k] = 0;
   if (lane == 0) acc[bw] = 0ull;
   const int b = bw / 3, w = bw - 3 * b;
   const int64_t i0 = chunk_off[b], i1 = chunk_off[b + 1];
@@ -531,6 +560,13 @@ __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, 
   if (lane == 0) {
     side[bw] = mirror;
     rec_cnt[bw] = mirror ? dn : up;
+  }
+  // the chosen side's tile counts; both sides' counters are left zero for the next call
+  int32_t* tc = tile_cnt2 + (int64_t)bw * 2 * TT;
+  for (int k = lane; k < TT; k += 64) {
+    tile_cnt[(int64_t)bw * TT + k] = tc[mirror * TT + k];
+    tc[k] = 0;
+    tc[TT + k] = 0;
   }
   int base = 0;
   for (int64_t i = i0; i < i1; i += 64) {
@@ -617,54 +653,7 @@ __device__ inline bool kept(const CastTri& tr, const CastFrame& f) {
   return zmax > -f.hw;
 }
 
-// Tile counters of one work item (one box, 256 triangles, three axes) are
-// aggregated in LDS when they fit (3 * TT <= kLdsTiles) and flushed with one
-// global atomic per non-zero tile.
-constexpr int kLdsTiles = 3 * 1024;
 
-__global__ void __launch_bounds__(kCullThreads)
-k_tile_count(CullArgs a, const int32_t* __restrict__ side, int32_t* __restrict__ tile_cnt) {
-  __shared__ int32_t cnt[kLdsTiles];
-  const int64_t total = a.chunk_off[a.n_boxes];
-  const int TT = a.tpe * a.tpe;
-  const bool lds = 3 * TT <= kLdsTiles;
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const int b = item_box(a.chunk_off, a.n_boxes, item);
-    const BoxRegs B = load_box(a.boxes, b);
-    if (box_state(B) != 0) continue;
-    if (lds) {
-      for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) cnt[k] = 0;
-      __syncthreads();
-    }
-    const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
-    const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
-    float P[3][3];
-    if (cull_tri(a, b, M, B, t, P)) {
-      for (int w = 0; w < 3; ++w) {
-        if (!((a.axis_mask >> w) & 1u)) continue;
-        const int bw = b * 3 + w;
-        const CastFrame f = cast_frame(B, w, a.R);
-        const CastTri tr = cast_tri(P, w, f, side[bw] != 0);
-        if (!kept(tr, f)) continue;
-        int ti0, ti1, tj0, tj1;
-        tile_range(tr, f, a.R, a.TE, ti0, ti1, tj0, tj1);
-        for (int tj = tj0; tj <= tj1; ++tj)
-          for (int ti = ti0; ti <= ti1; ++ti) {
-            if (lds)
-              atomicAdd(&cnt[w * TT + tj * a.tpe + ti], 1);
-            else
-              atomicAdd(&tile_cnt[(int64_t)bw * TT + tj * a.tpe + ti], 1);
-          }
-      }
-    }
-    if (lds) {
-      __syncthreads();
-      for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads)
-        if (cnt[k]) atomicAdd(&tile_cnt[(int64_t)(b * 3 + k / TT) * TT + (k % TT)], cnt[k]);
-      __syncthreads();
-    }
-  }
-}
 
 // The 80-byte test record of a kept triangle in its cast frame.
 //   [0..8]   edge functions E_k(u, v) = A_k u + B_k v + C_k, k = edge (k -> k+1),
@@ -1480,7 +1469,8 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   const size_t o_recoff = take(8 * (size_t)(nbw + 1));
   const size_t o_binoff = take(8 * (size_t)(nbw * TT + 1));
   const size_t o_chunkoff = take(8 * (size_t)(nbw * TT + 1));
-  const size_t o_tilecnt = take(4 * (size_t)(nbw * TT));  // zeroed by k_box_sides
+  const size_t o_tilecnt = take(4 * (size_t)(nbw * TT));  // written by k_box_sides
+  const size_t o_tc2 = take(8 * (size_t)(nbw * TT));  // a plan's two-sided tile counters (unused otherwise)
   const size_t o_bincur = take(4 * (size_t)(nbw * TT));   // zeroed by k_box_sides
   const size_t o_acc = take(8 * (size_t)nbw);             // zeroed by k_box_sides
   const size_t o_rframe = take(sizeof(RayFrame) * (size_t)nbw);  // written by k_box_sides
@@ -1599,13 +1589,21 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   ca.box_list = d_blist;
   const unsigned cull_grid = (unsigned)std::min<int64_t>(items_bound, 256 * 16);
 
-  hipLaunchKernelGGL(k_cull_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_icnt);
+  // both sides' tile counters: zero on entry, left zero by k_box_sides (a plan
+  // keeps its own block in the meta scratch, zeroed at creation)
+  int32_t* d_tc2 = nullptr;
+  if (planned) {
+    d_tc2 = (int32_t*)(meta + o_tc2);
+  } else {
+    void* tcv = nullptr;
+    OBBV_RET(pool_get_zeroed(pool_base + kPoolTileCnt2, 8 * (size_t)nbw * TT, &tcv));
+    d_tc2 = (int32_t*)tcv;
+  }
+  hipLaunchKernelGGL(k_cull_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_icnt, d_tc2);
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_box_sides, dim3(ceil_div(nbw, kCullWaves)), dim3(kCullThreads), 0, s,
                      (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, d_ioff, (int)TT,
-                     d_tilecnt, d_bincur, d_acc, boxes, box_key, R, params->seed, d_rframe);
-  OBBV_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_tile_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_tilecnt);
+                     d_tilecnt, d_bincur, d_acc, boxes, box_key, R, params->seed, d_rframe, d_tc2);
   OBBV_HIP(hipGetLastError());
   // bin and work-item offsets of the tiles, record offsets of the (box, axis) pairs
   const int chunk = test_chunk_choice();
@@ -2039,6 +2037,7 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
     set_error("hipMalloc of the planned scratch failed");
     return OBBV_ERR_OOM;
   }
+  OBBV_HIP(hipMemset(P->alloc, 0, bytes));  // counters that every launch leaves zero start zero
   ex.meta = (char*)P->alloc;
   ex.recs = (float4*)(ex.meta + align_up(ex.meta_cap));
   ex.bins = (int32_t*)((char*)ex.recs + align_up((size_t)ex.rec_cap * kRecBytes));

@@ -33,7 +33,13 @@ DevicePool g_pools[kMaxDevices];
 std::mutex g_pool_mutex;
 }  // namespace
 
-int pool_get(int slot, size_t bytes, void** out) {
+static int pool_get_impl(int slot, size_t bytes, void** out, bool zero);
+
+int pool_get(int slot, size_t bytes, void** out) { return pool_get_impl(slot, bytes, out, false); }
+
+int pool_get_zeroed(int slot, size_t bytes, void** out) { return pool_get_impl(slot, bytes, out, true); }
+
+static int pool_get_impl(int slot, size_t bytes, void** out, bool zero) {
   int dev = 0;
   OBBV_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= kMaxDevices) {
@@ -61,6 +67,12 @@ int pool_get(int slot, size_t bytes, void** out) {
       (void)hipGetLastError();
       set_error("hipMalloc of " + std::to_string(want) + " bytes of scratch failed");
       return OBBV_ERR_OOM;
+    }
+    if (zero && hipMemset(q, 0, want) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(q);
+      set_error("hipMemset of new scratch failed");
+      return OBBV_ERR_HIP;
     }
     p.ptr[slot] = q;
     p.cap[slot] = want;
