@@ -48,9 +48,9 @@ SEED_MESH = 21
 # ray-test kernel's code (from kRasterCells to the end of k_raster); any change
 # there reports null until the counters are re-taken.
 K_TEST_TRAFFIC = {
-    "source_sha256": "c591a7b702b31c6fce653c8bc2a574905a2e0bbb1c9ff5fc0d4034d43ff427d0",
-    "fetch_bytes_per_launch": 86406080,   # 42,191.858 KiB raw x 1.99993 (copy calibration)
-    "write_bytes_per_launch": 630873,     # 616.087 KiB raw x 1.0
+    "source_sha256": "840cb51208d8af72fdf55e90f25112eedfdbacc48f1446ff3f57eeb81b8f79ab",
+    "fetch_bytes_per_launch": 99819415,   # 48,741.554 KiB raw x 1.99993 (copy calibration)
+    "write_bytes_per_launch": 560807,     # 547.663 KiB raw x 1.0
     "profile": "profiles/ray_test_torus_hierarchy_traffic.md",
 }
 RASTER_BEGIN = "constexpr int kRasterCells = 16;"
