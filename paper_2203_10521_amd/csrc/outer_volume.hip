@@ -210,7 +210,8 @@ __device__ inline int item_box(const int64_t* __restrict__ chunk_off, int n_boxe
 struct CullArgs {
   const obbv_box* boxes;
   const int32_t* box_mesh;
-  const MeshDev* meshes;
+  const MeshDev* meshes;  // device mesh table; NULL with a single mesh (then mesh0)
+  MeshDev mesh0;
   const int64_t* chunk_off;
   int n_boxes;
   int R;
@@ -295,7 +296,8 @@ __device__ inline long long block_excl_scan(long long v, long long* wsum, long l
 // the whole mesh), their exclusive scan (chunk_off[0..n_boxes]), the frame use
 // of every box, and the per-call counters that must start at zero.
 __global__ void __launch_bounds__(kScanBlockThreads)
-k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ meshes, int n_meshes, int n_boxes,
+k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ meshes, MeshDev mesh0, int n_meshes,
+             int n_boxes,
              const obbv_box* __restrict__ boxes, const obbv_box* __restrict__ frames,
              const int32_t* __restrict__ box_frame, int n_frames, const int64_t* __restrict__ list_off,
              int32_t* __restrict__ box_list, int64_t* __restrict__ chunk_off, uint32_t* __restrict__ done_counter,
@@ -312,7 +314,7 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
         atomicOr(status, OBBV_STATUS_BAD_INDEX);
         if (box_list) box_list[b] = -1;
       } else {
-        int64_t n = meshes[m].nt;
+        int64_t n = meshes ? meshes[m].nt : mesh0.nt;
         if (box_list) {
           const int f = box_frame[b];
           const bool use = f >= 0 && f < n_frames && inside_frame(boxes[b], frames[f]);
@@ -451,7 +453,7 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt, int32_t* __restrict__ t
     const int b = item_box(a.chunk_off, a.n_boxes, item);
     const BoxRegs B = load_box(a.boxes, b);
     const bool valid = box_state(B) == 0;
-    const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
+    const MeshDev M = a.meshes ? a.meshes[a.box_mesh ? a.box_mesh[b] : 0] : a.mesh0;
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
     const bool ok = valid && cull_tri(a, b, M, B, t, P);
@@ -744,7 +746,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
     const int b = item_box(a.chunk_off, a.n_boxes, item);
     const BoxRegs B = load_box(a.boxes, b);
     const bool valid = box_state(B) == 0;
-    const MeshDev M = a.meshes[a.box_mesh ? a.box_mesh[b] : 0];
+    const MeshDev M = a.meshes ? a.meshes[a.box_mesh ? a.box_mesh[b] : 0] : a.mesh0;
     const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
     const bool ok = valid && cull_tri(a, b, M, B, t, P);
@@ -1531,7 +1533,11 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   int32_t* d_ficnt = (int32_t*)((char*)d_ioff + align_up(12 * (size_t)items_bound));
   int32_t* d_fioff = (int32_t*)((char*)d_ficnt + align_up(4 * (size_t)fitems));
 
-  if (!planned) OBBV_HIP(hipMemcpyAsync(d_mesh, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
+  // the mesh table goes to the device only with several meshes (one mesh travels
+  // in the kernel arguments)
+  if (!planned && n_meshes > 1)
+    OBBV_HIP(hipMemcpyAsync(d_mesh, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
+  const MeshDev* d_meshes = n_meshes > 1 ? (const MeshDev*)d_mesh : nullptr;
 
   float4* d_listP = nullptr;
   if (sf) {  // candidate triangles of every shared frame
@@ -1566,7 +1572,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
                        nch, d_ficnt, (const int32_t*)d_fioff, (const int64_t*)d_foff, d_listP, status);
     OBBV_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_box_chunks, dim3(1), dim3(kScanBlockThreads), 0, s, box_mesh, (const MeshDev*)d_mesh,
+  hipLaunchKernelGGL(k_box_chunks, dim3(1), dim3(kScanBlockThreads), 0, s, box_mesh, d_meshes, mh[0],
                      n_meshes, n_boxes, boxes, sf ? sf->frames : nullptr, sf ? sf->box_frame : nullptr, n_frames,
                      (const int64_t*)d_foff, d_blist, d_choff, d_done, status);
   OBBV_HIP(hipGetLastError());
@@ -1574,7 +1580,8 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   CullArgs ca;
   ca.boxes = boxes;
   ca.box_mesh = box_mesh;
-  ca.meshes = d_mesh;
+  ca.meshes = d_meshes;
+  ca.mesh0 = mh[0];
   ca.chunk_off = d_choff;
   ca.n_boxes = n_boxes;
   ca.R = R;
