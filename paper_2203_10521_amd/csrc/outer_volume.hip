@@ -98,20 +98,60 @@ struct CastFrame {
   int ua, va;
   float hu, hv, hw;
   double du, dv;
+  double idu, idv;  // 1 / du, 1 / dv
   float eu, ev;  // bounding-box margins for binning
 };
 
-__device__ inline CastFrame cast_frame(const BoxRegs& B, int w, int R) {
+// The face rectangle of cast axis w (no cell sizes: enough for projects_into_face).
+__device__ inline CastFrame cast_bounds(const BoxRegs& B, int w) {
   CastFrame f;
   f.ua = (w + 1) % 3;
   f.va = (w + 2) % 3;
   f.hu = pick3(B.h, f.ua);
   f.hv = pick3(B.h, f.va);
   f.hw = pick3(B.h, w);
-  f.du = __ddiv_rn(__dmul_rn(2.0, (double)f.hu), (double)R);
-  f.dv = __ddiv_rn(__dmul_rn(2.0, (double)f.hv), (double)R);
+  f.du = f.dv = f.idu = f.idv = 0.0;
   f.eu = 1e-6f * f.hu;
   f.ev = 1e-6f * f.hv;
+  return f;
+}
+
+__device__ inline CastFrame cast_frame(const BoxRegs& B, int w, int R) {
+  CastFrame f = cast_bounds(B, w);
+  f.du = __ddiv_rn(__dmul_rn(2.0, (double)f.hu), (double)R);
+  f.dv = __ddiv_rn(__dmul_rn(2.0, (double)f.hv), (double)R);
+  f.idu = 1.0 / f.du;
+  f.idv = 1.0 / f.dv;
+  return f;
+}
+
+// cast_frame with the cell sizes of the cast's ray grid table (the same values)
+__device__ inline CastFrame cast_frame_rf(const BoxRegs& B, int w, const RayFrame& rf) {
+  CastFrame f = cast_bounds(B, w);
+  f.du = rf.du;
+  f.dv = rf.dv;
+  f.idu = rf.idu;
+  f.idv = rf.idv;
+  return f;
+}
+
+// The ray grid of cast w of box b (see RayFrame).
+__device__ inline RayFrame make_ray_frame(const BoxRegs& B, int w, uint32_t key, int R, uint64_t seed) {
+  const int ua = (w + 1) % 3, va = (w + 2) % 3;
+  const float huf = pick3(B.h, ua), hvf = pick3(B.h, va);
+  RayFrame f;
+  f.hu = huf;
+  f.hv = hvf;
+  f.du = __ddiv_rn(__dmul_rn(2.0, f.hu), (double)R);
+  f.dv = __ddiv_rn(__dmul_rn(2.0, f.hv), (double)R);
+  f.idu = 1.0 / f.du;
+  f.idv = 1.0 / f.dv;
+  f.eu = 1e-6f * huf;
+  f.ev = 1e-6f * hvf;
+  f.s0 = seed + (2ull * (((uint64_t)key << 32) | ((uint64_t)w << 30)) + 1ull) * kGamma;
+  f.state = box_state(B);
+  f.key = key;
+  f.pad[0] = f.pad[1] = 0;
   return f;
 }
 
@@ -155,10 +195,12 @@ __device__ inline void cell_range(const CastTri& t, const CastFrame& f, int R, i
   const float vmin = fminf(fminf(t.v[0], t.v[1]), t.v[2]);
   const float vmax = fmaxf(fmaxf(t.v[0], t.v[1]), t.v[2]);
   const double hu = f.hu, hv = f.hv;
-  i0 = (int)floor(((double)umin - f.eu + hu) / f.du);
-  i1 = (int)floor(((double)umax + f.eu + hu) / f.du);
-  j0 = (int)floor(((double)vmin - f.ev + hv) / f.dv);
-  j1 = (int)floor(((double)vmax + f.ev + hv) / f.dv);
+  // with reciprocals, as the ray-test kernel takes the range of a record (the
+  // 1e-6 margins dwarf the difference from dividing)
+  i0 = (int)floor(((double)umin - f.eu + hu) * f.idu);
+  i1 = (int)floor(((double)umax + f.eu + hu) * f.idu);
+  j0 = (int)floor(((double)vmin - f.ev + hv) * f.idv);
+  j1 = (int)floor(((double)vmax + f.ev + hv) * f.idv);
   i0 = max(0, min(R - 1, i0));
   i1 = max(0, min(R - 1, i1));
   j0 = max(0, min(R - 1, j0));
@@ -212,6 +254,7 @@ struct CullArgs {
   const int32_t* box_mesh;
   const MeshDev* meshes;  // device mesh table; NULL with a single mesh (then mesh0)
   MeshDev mesh0;
+  const RayFrame* rframe;  // [n_boxes * 3] ray grid of every cast (k_box_chunks)
   const int64_t* chunk_off;
   int n_boxes;
   int R;
@@ -301,9 +344,14 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
              const obbv_box* __restrict__ boxes, const obbv_box* __restrict__ frames,
              const int32_t* __restrict__ box_frame, int n_frames, const int64_t* __restrict__ list_off,
              int32_t* __restrict__ box_list, int64_t* __restrict__ chunk_off, uint32_t* __restrict__ done_counter,
-             uint32_t* status) {
+             uint32_t* status, const uint32_t* __restrict__ box_key, int R, uint64_t seed,
+             RayFrame* __restrict__ rframe) {
   __shared__ long long wsum[kScanBlockThreads / 64];
   if (threadIdx.x == 0 && done_counter) *done_counter = 0u;
+  for (int e = threadIdx.x; e < 3 * n_boxes; e += blockDim.x) {  // the ray grid of every cast
+    const int b = e / 3;
+    rframe[e] = make_ray_frame(load_box(boxes, b), e - 3 * b, box_key ? box_key[b] : (uint32_t)b, R, seed);
+  }
   long long base = 0;
   for (int b0 = 0; b0 < n_boxes; b0 += kScanBlockThreads) {
     const int b = b0 + (int)threadIdx.x;
@@ -360,7 +408,7 @@ k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, uint3
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
         if (!((axis_mask >> w) & 1u)) continue;
-        const CastFrame f = cast_frame(B, w, 1);
+        const CastFrame f = cast_bounds(B, w);
         keep = keep || projects_into_face(cast_tri(P, w, f, false), f);
       }
     }
@@ -465,7 +513,7 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt, int32_t* __restrict__ t
     for (int w = 0; w < 3; ++w) {
       bool ka = false, kb = false;
       if (ok && ((a.axis_mask >> w) & 1u)) {
-        const CastFrame f = cast_frame(B, w, a.R);
+        const CastFrame f = cast_frame_rf(B, w, a.rframe[b * 3 + w]);
         const CastTri tr = cast_tri(P, w, f, false);
         if (projects_into_face(tr, f)) {
           const float zmin = fminf(fminf(tr.z[0], tr.z[1]), tr.z[2]);
@@ -517,32 +565,10 @@ __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, 
                             int32_t* __restrict__ side, int32_t* __restrict__ rec_cnt,
                             int32_t* __restrict__ item_off, int TT, int32_t* __restrict__ tile_cnt,
                             int32_t* __restrict__ bin_cur, unsigned long long* __restrict__ acc,
-                            const obbv_box* __restrict__ boxes, const uint32_t* __restrict__ box_key, int R,
-                            uint64_t seed, RayFrame* __restrict__ rframe, int32_t* __restrict__ tile_cnt2) {
+                            int32_t* __restrict__ tile_cnt2) {
   const int bw = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (bw >= 3 * n_boxes) return;
-  if (lane == 0 && rframe) {  // the cast's ray grid
-    const int b = bw / 3, w = bw - 3 * b;
-    const BoxRegs B = load_box(boxes, b);
-    const int ua = (w + 1) % 3, va = (w + 2) % 3;
-    const float huf = pick3(B.h, ua), hvf = pick3(B.h, va);
-    RayFrame f;
-    f.hu = huf;
-    f.hv = hvf;
-    f.du = __ddiv_rn(__dmul_rn(2.0, f.hu), (double)R);
-    f.dv = __ddiv_rn(__dmul_rn(2.0, f.hv), (double)R);
-    f.idu = 1.0 / f.du;
-    f.idv = 1.0 / f.dv;
-    f.eu = 1e-6f * huf;
-    f.ev = 1e-6f * hvf;
-    const uint32_t key = box_key ? box_key[b] : (uint32_t)b;
-    f.s0 = seed + (2ull * (((uint64_t)key << 32) | ((uint64_t)w << 30)) + 1ull) * kGamma;
-    f.state = box_state(B);
-    f.key = key;
-    f.pad[0] = f.pad[1] = 0;
-    rframe[bw] = f;
-  }
   // counters of this (box, axis) that later passes accumulate into
   for (int k = lane; k < TT; k += 64) bin_cur[(int64_t)bw * TT + k] = 0;
   if (lane == 0) acc[bw] = 0ull;
@@ -759,7 +785,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
     for (int w = 0; w < 3; ++w) {
       bool keep = false;
       if (ok && ((a.axis_mask >> w) & 1u)) {
-        const CastFrame f = cast_frame(B, w, a.R);
+        const CastFrame f = cast_frame_rf(B, w, a.rframe[b * 3 + w]);
         const CastTri tr = cast_tri(P, w, f, side[b * 3 + w] != 0);
         keep = kept(tr, f);
         if (keep && lds) {
@@ -791,7 +817,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
       if (!keep) continue;
       const int bw = b * 3 + w;
       const bool mirror = side[bw] != 0;
-      const CastFrame f = cast_frame(B, w, a.R);
+      const CastFrame f = cast_frame_rf(B, w, a.rframe[b * 3 + w]);
       const CastTri tr = cast_tri(P, w, f, mirror);
       int rank = item_off[3 * item + w] + (int)__popcll(m & ((1ull << lane) - 1ull));
       for (int v = 0; v < wave; ++v) rank += wc[v][w];
@@ -1574,7 +1600,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   }
   hipLaunchKernelGGL(k_box_chunks, dim3(1), dim3(kScanBlockThreads), 0, s, box_mesh, d_meshes, mh[0],
                      n_meshes, n_boxes, boxes, sf ? sf->frames : nullptr, sf ? sf->box_frame : nullptr, n_frames,
-                     (const int64_t*)d_foff, d_blist, d_choff, d_done, status);
+                     (const int64_t*)d_foff, d_blist, d_choff, d_done, status, box_key, R, params->seed, d_rframe);
   OBBV_HIP(hipGetLastError());
 
   CullArgs ca;
@@ -1582,6 +1608,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   ca.box_mesh = box_mesh;
   ca.meshes = d_meshes;
   ca.mesh0 = mh[0];
+  ca.rframe = d_rframe;
   ca.chunk_off = d_choff;
   ca.n_boxes = n_boxes;
   ca.R = R;
@@ -1610,7 +1637,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_box_sides, dim3(ceil_div(nbw, kCullWaves)), dim3(kCullThreads), 0, s,
                      (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, d_ioff, (int)TT,
-                     d_tilecnt, d_bincur, d_acc, boxes, box_key, R, params->seed, d_rframe, d_tc2);
+                     d_tilecnt, d_bincur, d_acc, d_tc2);
   OBBV_HIP(hipGetLastError());
   // bin and work-item offsets of the tiles, record offsets of the (box, axis) pairs
   const int chunk = test_chunk_choice();
