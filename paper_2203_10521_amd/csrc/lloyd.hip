@@ -207,6 +207,12 @@ struct Evaluator {
   uint64_t jseed = 0;
   bool jtab_use = false;
   static constexpr int64_t kJitterTableBytes = (int64_t)256 << 20;
+  // OBBV_JITTER_TABLE=0 turns the table off (the kernel then computes every
+  // draw), so the two paths can be compared bit for bit
+  const bool jtab_allowed = [] {
+    const char* e = getenv("OBBV_JITTER_TABLE");
+    return !(e && *e && atoi(e) == 0);
+  }();
 
   int ensure_jitter(const std::vector<uint32_t>& keys) {
     uint32_t kmax = 0;
@@ -214,7 +220,7 @@ struct Evaluator {
     const int R = params.R;
     const int64_t per_key = 3 * (int64_t)R * R * (int64_t)sizeof(uint2);
     const int64_t want = ((int64_t)kmax + 64) / 64 * 64;
-    jtab_use = want * per_key <= kJitterTableBytes;
+    jtab_use = jtab_allowed && want * per_key <= kJitterTableBytes;
     if (!jtab_use) return OBBV_OK;
     if (jtab && want <= jkeys && jR == R && jseed == params.seed) return OBBV_OK;
     if (jtab) {

@@ -112,3 +112,18 @@ def test_hierarchy_structure_enclosure_and_error(api):
     assert np.allclose(re[used], obv[used], rtol=0, atol=1e-12)
     w = (L - level).astype(np.float64)
     assert abs(np.sum(w * obv) - e[-1]) <= 1e-9 * max(1.0, e[-1])
+
+
+def test_jitter_table_gives_the_same_bits_as_computed_draws(api, monkeypatch):
+    """The Lloyd evaluator reads the ray jitter from a per-key table when the
+    keys are few; with the table turned off the ray-test kernel recomputes
+    every SplitMix64 draw.  Both must give bit-identical hierarchies."""
+    V, F = synth.noisy_cube_sphere(6, seed=21)
+    Vt, Ft = _dev(V, F)
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("OBBV_JITTER_TABLE", flag)
+        out[flag] = api.build_hierarchy(Vt, Ft, levels=3, branching=2, iters=2, sweeps=1, R=16, seed=4,
+                                        pops_per_round=8)
+    for k in ("boxes", "obv", "parent", "tri_node", "e"):
+        assert np.array_equal(out["1"][k], out["0"][k]), k

@@ -166,3 +166,31 @@ def test_ranker_guided_lloyd_close_to_exact_with_fewer_evaluations(api, trained)
     assert out["ranker"]["counters"]["predicted"] > 0
     assert ev_r < ev_x
     assert e_r <= 1.10 * e_x
+
+
+def test_ranker_guided_lloyd_is_deterministic(api, trained):
+    """The asynchronous judge consumes each result at a fixed later round, so
+    two runs of the same ranker-guided Lloyd give identical partitions, boxes
+    and counters however the device and host interleave."""
+    import torch
+    P, _ = trained
+    V, F = synth.noisy_cube_sphere(12, seed=31)
+    Vt, Ft = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+    vol, frame = api.occupancy_volume(Vt, Ft, nb=8, seed=1)
+    centers = np.array([[0.6, 0.2, 0.1], [-0.5, 0.5, 0.0], [0.1, -0.7, -0.4]], np.float32)
+    init = synth.boxes_to_array(centers, np.stack([np.eye(3, dtype=np.float32)] * 3),
+                                np.zeros((3, 3), np.float32))
+    runs = []
+    for _ in range(2):
+        with api.Lloyd(Vt, Ft, R=16, seed=9, pops_per_round=16) as L:
+            L.set_groups(np.zeros(len(F), np.int32), np.zeros(3, np.int32), init)
+            L.set_surrogate(api.Surrogate(P, vol, frame, verify_top=0, max_error=0.2, judge_every=2))
+            for _ in range(2):
+                L.step()
+            runs.append(L.get())
+    a, b = runs
+    assert a["counters"]["predicted"] > 0
+    for k in ("tri_box", "boxes", "obv"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["layer_error"] == b["layer_error"]
+    assert a["counters"] == b["counters"]
