@@ -44,17 +44,16 @@ void clear_error();
 // ---------------------------------------------------------------------------
 enum PoolSlot {
   kPoolMeta = 0,
-  kPoolRecords = 1,
-  kPoolBins = 2,
-  kPoolFit = 3,
-  kPoolMlp = 4,
-  kPoolFeat = 5,
-  kPoolLists = 6,
-  kPoolItems = 7,
-  kPoolTiles = 8,
-  kPoolRank = 9,
-  kPoolTileCnt2 = 10,  // zero between calls (each call leaves what it used zero)
-  kPoolCount = 11
+  kPoolRecords = 1,  // binned records
+  kPoolFit = 2,
+  kPoolMlp = 3,
+  kPoolFeat = 4,
+  kPoolLists = 5,
+  kPoolItems = 6,
+  kPoolTiles = 7,
+  kPoolRank = 8,
+  kPoolTileCnt2 = 9,  // zero between calls (each call leaves what it used zero)
+  kPoolCount = 10
 };
 // Two sets of the slots: calls that may run at the same time on different
 // streams take their scratch from different sets (slot + set * kPoolCount).
@@ -67,9 +66,11 @@ int pool_get(int slot, size_t bytes, void** out);
 // As pool_get; a new (grown) block is zeroed before it is returned.
 int pool_get_zeroed(int slot, size_t bytes, void** out);
 
-// A ray-test record: 5 float4 = 80 bytes (edge planes, depth plane, clamp,
-// sign, projected bounding box).
-constexpr int kRecF4 = 5;
+// A binned ray-test record, one per bin entry: 4 float4 = 64 bytes (edge
+// planes, depth plane, clamp, sign, and the record's cell range inside the tile
+// of its bin).  A tile's entries are contiguous, so a ray-test wave reads one
+// aligned 64-byte line per record with no index indirection.
+constexpr int kRecF4 = 4;
 constexpr int kRecBytes = 16 * kRecF4;
 
 // How one outer-volume evaluation is executed.  Default: scratch is sized from
@@ -87,9 +88,8 @@ struct OvExec {
   bool capped = false;
   char* meta = nullptr;
   size_t meta_cap = 0, meta_bytes = 0;
-  float4* recs = nullptr;
-  int32_t* bins = nullptr;
-  int64_t rec_cap = 0, bin_cap = 0, item_cap = 0;
+  float4* recs = nullptr;                     // [bin_cap] binned records (kRecF4 float4 each)
+  int64_t rec_cap = 0, bin_cap = 0, item_cap = 0;  // records counted per call, bin entries, work items
   int64_t n_rec = 0, n_bin = 0, n_items = 0;  // counts of the last synchronous run
   char* items = nullptr;                      // per-cull-item counts and offsets
   size_t items_cap = 0, items_bytes = 0;
@@ -109,7 +109,10 @@ int status_word(uint32_t** out);   // device pointer of this device's status wor
 
 // measurement hooks (obbv_profile_enable / obbv_profile_read)
 bool profiling_enabled();
-int profile_counter(unsigned long long** out);                  // device test counter
+// device test counter: kProfSlots slots whose sum is the count; a wave adds to
+// one slot, so the waves of a launch do not serialise on one address
+constexpr int kProfSlots = 256;
+int profile_counter(unsigned long long** out);
 int profile_record_begin(hipStream_t s, void** token);            // event before k_test
 int profile_record_end(hipStream_t s, void* token);               // event after k_test
 

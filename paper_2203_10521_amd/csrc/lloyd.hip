@@ -153,7 +153,7 @@ struct Evaluator {
     const int64_t r = std::max(rec_cap, n_rec + n_rec / 2 + 4096);
     const int64_t b = std::max(bin_cap, n_bin + n_bin / 2 + 8192);
     const int64_t it = std::max(item_cap, n_items + n_items / 2 + 256);
-    const size_t need = al((size_t)r * kRecBytes) + al((size_t)b * 4) + al((size_t)it * sizeof(int4));
+    const size_t need = al((size_t)b * kRecBytes) + al((size_t)it * sizeof(int4));
     if (need > scap) {
       if (sbuf) {
         OBBV_HIP(hipStreamSynchronize(stream));
@@ -381,8 +381,7 @@ struct Evaluator {
       OvExec ex;
       ex.capped = true;
       ex.recs = (float4*)sbuf;
-      ex.bins = (int32_t*)(sbuf + al((size_t)rec_cap * kRecBytes));
-      ex.itile = (int4*)(sbuf + al((size_t)rec_cap * kRecBytes) + al((size_t)bin_cap * 4));
+      ex.itile = (int4*)(sbuf + al((size_t)bin_cap * kRecBytes));
       ex.rec_cap = rec_cap;
       ex.bin_cap = bin_cap;
       ex.item_cap = item_cap;

@@ -262,7 +262,7 @@ struct CullArgs {
   int tpe;  // tiles per face edge
   uint32_t axis_mask;
   uint32_t* status;
-  int64_t rec_cap;  // record / bin capacity of the scratch (planned launches)
+  int64_t rec_cap;  // records and bin entries a planned launch was sized for
   int64_t bin_cap;
   // nullable: the triangles a box can see, one list per shared frame, held as
   // their frame-local vertex coordinates (3 float4 per triangle)
@@ -683,14 +683,15 @@ __device__ inline bool kept(const CastTri& tr, const CastFrame& f) {
 
 
 
-// The 80-byte test record of a kept triangle in its cast frame.
+// The 64-byte test record of a kept triangle in its cast frame.
 //   [0..8]   edge functions E_k(u, v) = A_k u + B_k v + C_k, k = edge (k -> k+1),
 //            oriented so that the inside of the projected triangle is E >= 0
 //   [9..11]  depth plane in fixed point: y(u, v) = D u + E v + F equals
 //            kMagic + s (w(u, v) + h) 2^21 / h, s = crossing sign
 //   [12..13] clamp of y to the part of the triangle inside the slab
 //   [14]     crossing sign s (+1 leaving the solid along +w in the cast frame)
-//   [16..19] projected bounding box: u min, u max, v min, v max
+//   [15]     set per bin entry (pack_cells): the triangle's cell range inside the
+//            entry's tile
 // The edge coefficients of an edge shared by two triangles are exact
 // negatives of each other (or equal, when one of them is flipped), so the two
 // triangles classify every ray consistently: the test is watertight.
@@ -735,20 +736,28 @@ __device__ inline void make_record(const CastTri& t, bool mirror, float hw, floa
   out[1] = make_float4(Bc[1], C[1], A[2], Bc[2]);
   out[2] = make_float4(C[2], (float)(K * D), (float)(K * E), (float)(K * (F + h) + (double)kMagic));
   out[3] = make_float4((float)lo, (float)hi, (float)s, 0.0f);
-  out[4] = make_float4(fminf(fminf(t.u[0], t.u[1]), t.u[2]), fmaxf(fmaxf(t.u[0], t.u[1]), t.u[2]),
-                       fminf(fminf(t.v[0], t.v[1]), t.v[2]), fmaxf(fmaxf(t.v[0], t.v[1]), t.v[2]));
+}
+
+// Cell range [i0, i1] x [j0, j1] (cell_range) clipped to the tile whose first
+// cell is (ci, cj), as four 4-bit offsets from that cell (tiles are at most
+// 16 x 16 cells): i0 | i1 << 4 | j0 << 8 | j1 << 12.
+__device__ inline uint32_t pack_cells(int i0, int i1, int j0, int j1, int ci, int cj, int TE) {
+  const int a0 = max(i0, ci) - ci, a1 = min(i1, ci + TE - 1) - ci;
+  const int b0 = max(j0, cj) - cj, b1 = min(j1, cj + TE - 1) - cj;
+  return (uint32_t)a0 | ((uint32_t)a1 << 4) | ((uint32_t)b0 << 8) | ((uint32_t)b1 << 12);
 }
 
 // Bin slots: every (tile) of the work item first counts its entries in LDS,
 // then reserves a contiguous range of its bin with one global atomic; the
 // entries then take positions in that range (their order inside a bin does
-// not matter: the ray sums are exact integers).
+// not matter: the ray sums are exact integers).  Every entry holds its own copy
+// of the record, with the cell range inside its tile.
 __global__ void __launch_bounds__(kCullThreads)
 k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict__ rec_off,
         const int32_t* __restrict__ rec_cnt, const int32_t* __restrict__ item_off,
         const int64_t* __restrict__ bin_off, int32_t* __restrict__ bin_cur, float4* __restrict__ recs,
-        int32_t* __restrict__ bins, const int64_t* __restrict__ chunk_off, int64_t n_tiles,
-        int4* __restrict__ item_tile, int64_t item_cap, int chunk) {
+        const int64_t* __restrict__ chunk_off, int64_t n_tiles, int4* __restrict__ item_tile, int64_t item_cap,
+        int chunk) {
   if (item_tile) {  // the ray-test work items: tile, record count, first bin entry (grid-stride over the tiles)
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -830,7 +839,8 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
         atomicOr(a.status, OBBV_STATUS_OVERFLOW);
         continue;
       }
-      make_record(tr, mirror, f.hw, recs + kRecF4 * slot);
+      float4 rec[kRecF4];
+      make_record(tr, mirror, f.hw, rec);
       int i0, i1, j0, j1;
       cell_range(tr, f, a.R, i0, i1, j0, j1);
       const int ti0 = i0 / a.TE, ti1 = i1 / a.TE, tj0 = j0 / a.TE, tj1 = j1 / a.TE;
@@ -840,13 +850,19 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
           const int64_t tl = tbase + tj * a.tpe + ti;
           const int lt = w * TT + tj * a.tpe + ti;
           const int pos = lds ? base_pos[lt] + atomicAdd(&cnt[lt], 1) : atomicAdd(&bin_cur[tl], 1);
-          const uint32_t entry = (uint32_t)slot;
-          if (bin_off[tl] + pos >= a.bin_cap)
+          const int64_t k = bin_off[tl] + pos;
+          if (k >= a.bin_cap) {
             atomicOr(a.status, OBBV_STATUS_OVERFLOW);
-          else if (bin_off[tl] + pos < bin_off[tl + 1])
-            bins[bin_off[tl] + pos] = (int32_t)entry;
-          else
+          } else if (k < bin_off[tl + 1]) {
+            float4* o = recs + kRecF4 * k;
+            o[0] = rec[0];
+            o[1] = rec[1];
+            o[2] = rec[2];
+            o[3] = make_float4(rec[3].x, rec[3].y, rec[3].z,
+                               __uint_as_float(pack_cells(i0, i1, j0, j1, ti * a.TE, tj * a.TE, a.TE)));
+          } else {
             atomicOr(a.status, OBBV_STATUS_BAD_INDEX);
+          }
         }
     }
     __syncthreads();  // cnt / base_pos / wc are reused by the next item
@@ -860,17 +876,15 @@ struct TestArgs {
   const int64_t* chunk_off;  // [nbw * TT + 1] first work item of each tile
   int64_t n_tiles;
   int chunk;
-  const int32_t* bins;
-  const float4* recs;
+  const float4* recs;        // [bin entries] binned records
   unsigned long long* acc;  // [nbw] per-(box, axis) sum of q
   int32_t* ray_q;           // nullable [nbw][R][R]
   int32_t* ray_hits;        // nullable [nbw][R][R]
-  unsigned long long* test_counter;  // nullable: += rays x binned triangles per tile
+  unsigned long long* test_counter;  // nullable [kProfSlots]: += ray-triangle tests (slot item % kProfSlots)
   float* occ;                        // nullable [n_boxes][8][8][8]: sub-slab inside fractions (R = 8, axis 2)
   const int32_t* side;               // [nbw] mirrored cast flags
   uint64_t seed;
   int n_boxes;
-  int n_rec;
   int R;
   int tpe;
   uint32_t axis_mask;
@@ -981,37 +995,21 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
     for (int64_t base = k0; base < k1; base += kTestThreads) {
       const int n = (int)min((int64_t)kTestThreads, k1 - base);
       if (lane < n) {
-        const int idx = a.bins[base + lane];
-        if ((unsigned)idx < (unsigned)a.n_rec) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) srec[4 * lane + q] = a.recs[kRecF4 * (int64_t)idx + q];
-        } else {  // a record no ray is inside of (only after a flagged write-pass mismatch)
-          srec[4 * lane + 0] = make_float4(0.f, 0.f, -1.f, 0.f);
-          srec[4 * lane + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-          srec[4 * lane + 2] = make_float4(0.f, 0.f, 0.f, kMagic);
-          srec[4 * lane + 3] = make_float4(kMagic, kMagic, 0.f, 0.f);
-        }
+        for (int q = 0; q < 4; ++q) srec[4 * lane + q] = a.recs[kRecF4 * (base + lane) + q];
       }
       __syncthreads();
       for (int j = 0; j < n; ++j) test_record(srec[4 * j + 0], srec[4 * j + 1], srec[4 * j + 2], srec[4 * j + 3]);
       __syncthreads();
     }
   } else {
-    for (int64_t k = k0; k < k1; ++k) {
-      const int idx = a.bins[k];
-      if ((unsigned)idx >= (unsigned)a.n_rec) {  // only after a flagged write-pass mismatch
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) acc[r] += kMagicBits;
-        continue;
-      }
-      test_record(a.recs[kRecF4 * (int64_t)idx + 0], a.recs[kRecF4 * (int64_t)idx + 1],
-                  a.recs[kRecF4 * (int64_t)idx + 2], a.recs[kRecF4 * (int64_t)idx + 3]);
-    }
+    for (int64_t k = k0; k < k1; ++k)
+      test_record(a.recs[kRecF4 * k + 0], a.recs[kRecF4 * k + 1], a.recs[kRecF4 * k + 2], a.recs[kRecF4 * k + 3]);
   }
   const uint32_t nbias = (uint32_t)(k1 - k0) * kMagicBits;
   if (a.test_counter && lane == 0) {
     const int ni = min(TE, a.R - ti * TE), nj = min(TE, a.R - tj * TE);
-    atomicAdd(a.test_counter, (unsigned long long)((k1 - k0) * (int64_t)(ni * nj)));
+    atomicAdd(&a.test_counter[item & (kProfSlots - 1)], (unsigned long long)((k1 - k0) * (int64_t)(ni * nj)));
   }
   int64_t lane_sum = 0;
 #pragma unroll
@@ -1074,8 +1072,7 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
   if (k1 > a.bin_cap) return;  // bins past a planned capacity were not written (flagged)
   // (boxes whose state is not 0 get no records, hence no ray-test work items)
   const RayFrame rf = a.rframe[bw];
-  const double hu = rf.hu, hv = rf.hv, du = rf.du, dv = rf.dv, idu = rf.idu, idv = rf.idv;
-  const float eu = rf.eu, ev = rf.ev;
+  const double hu = rf.hu, hv = rf.hv, du = rf.du, dv = rf.dv;
   const int ti = tile % a.tpe, tj = tile / a.tpe;
   const int ci_lo = ti * 16, cj_lo = tj * 16;
   const int ci_hi = min(ci_lo + 15, a.R - 1), cj_hi = min(cj_lo + 15, a.R - 1);
@@ -1125,22 +1122,16 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
     racc[k] = 0;
     rhit[k] = 0;
   };
-  // The item's first kTestThreads records are requested while the rays are
-  // generated: the record ids before the first two rays of every lane, the
-  // records before the last two.
-  // Both loads are unconditional (lanes past the item's records read its last
-  // id, a bad id reads record 0), so the counters of outstanding loads stay exact
-  // and the rays wait only for what they use.  An item holds at least one record.
-  const int idx0 = a.bins[k0 + min((int64_t)lane, k1 - k0 - 1)];
+  // The item's first kTestThreads records (contiguous, one 64-byte line each)
+  // are requested before the rays are generated.  The load is unconditional
+  // (lanes past the item's records read its last one), so the counters of
+  // outstanding loads stay exact.  An item holds at least one record.
+  const bool have0 = lane < k1 - k0;
+  const float4* rp0 = a.recs + kRecF4 * (k0 + min((int64_t)lane, k1 - k0 - 1));
+  const float4 p0 = rp0[0], p1 = rp0[1], p2 = rp0[2], p3 = rp0[3];
   __builtin_amdgcn_sched_barrier(0);
   make_ray(0);
   make_ray(1);
-  __builtin_amdgcn_sched_barrier(0);
-  // a bad id happens only after a flagged write-pass mismatch
-  const bool have0 = lane < k1 - k0 && (unsigned)idx0 < (unsigned)a.n_rec;
-  const float4* rp0 = a.recs + kRecF4 * (int64_t)(have0 ? idx0 : 0);
-  const float4 p0 = rp0[0], p1 = rp0[1], p2 = rp0[2], p3 = rp0[3], p4 = rp0[4];
-  __builtin_amdgcn_sched_barrier(0);
   make_ray(2);
   make_ray(3);
   __syncthreads();
@@ -1149,37 +1140,25 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
     for (int64_t base = k0; base < k1; base += kTestThreads) {
       const int n = (int)min((int64_t)kTestThreads, k1 - base);
       bool have = lane < n, big = false;
-      float4 q0, q1, q2, q3, q4;
+      float4 q0, q1, q2, q3;
       if (base == k0) {
         have = have0;
         q0 = p0;
         q1 = p1;
         q2 = p2;
         q3 = p3;
-        q4 = p4;
       } else if (have) {
-        const int idx = a.bins[base + lane];
-        have = (unsigned)idx < (unsigned)a.n_rec;  // else only after a flagged write-pass mismatch
-        if (have) {
-          const float4* rp = a.recs + kRecF4 * (int64_t)idx;
-          q0 = rp[0];
-          q1 = rp[1];
-          q2 = rp[2];
-          q3 = rp[3];
-          q4 = rp[4];
-        }
+        const float4* rp = a.recs + kRecF4 * (base + lane);
+        q0 = rp[0];
+        q1 = rp[1];
+        q2 = rp[2];
+        q3 = rp[3];
       }
       if (have) {
-        // the binning's cell range, with reciprocals (the 1e-6 margins dwarf
-        // the difference from dividing)
-        int c0 = (int)floor(((double)q4.x - eu + hu) * idu);
-        int c1 = (int)floor(((double)q4.y + eu + hu) * idu);
-        int d0 = (int)floor(((double)q4.z - ev + hv) * idv);
-        int d1 = (int)floor(((double)q4.w + ev + hv) * idv);
-        c0 = max(ci_lo, max(0, c0));
-        c1 = min(ci_hi, c1);
-        d0 = max(cj_lo, max(0, d0));
-        d1 = min(cj_hi, d1);
+        // the binning's cell range inside this tile, stored with the entry
+        const uint32_t pk = __float_as_uint(q3.w);
+        const int c0 = ci_lo + (int)(pk & 15u), c1 = ci_lo + (int)((pk >> 4) & 15u);
+        const int d0 = cj_lo + (int)((pk >> 8) & 15u), d1 = cj_lo + (int)((pk >> 12) & 15u);
         const int cells = (c1 >= c0 && d1 >= d0) ? (c1 - c0 + 1) * (d1 - d0 + 1) : 0;
         big = cells > kRasterCells;
         if (!big) {
@@ -1252,7 +1231,7 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
     tests += __shfl_xor(tests, off);
   }
   if (lane == 0 && lane_sum != 0) atomicAdd(&a.acc[bw], (unsigned long long)lane_sum);
-  if (lane == 0 && a.test_counter) atomicAdd(a.test_counter, (unsigned long long)tests);
+  if (lane == 0 && a.test_counter) atomicAdd(&a.test_counter[item & (kProfSlots - 1)], (unsigned long long)tests);
 }
 
 template <bool STATS, bool TAB>
@@ -1684,14 +1663,10 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
 
   if (n_rec > 0) {
     void* recs_v = nullptr;
-    void* bins_v = nullptr;
-    if (fixed) {
+    if (fixed)
       recs_v = ex->recs;
-      bins_v = ex->bins;
-    } else {
-      OBBV_RET(pool_get(pool_base + kPoolRecords, (size_t)n_rec * kRecBytes, &recs_v));
-      OBBV_RET(pool_get(pool_base + kPoolBins, (size_t)std::max<int64_t>(n_bin, 1) * 4, &bins_v));
-    }
+    else
+      OBBV_RET(pool_get(pool_base + kPoolRecords, (size_t)std::max<int64_t>(n_bin, 1) * kRecBytes, &recs_v));
     int4* itile = nullptr;
     if (fixed) {
       itile = ex->itile;
@@ -1701,7 +1676,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       itile = (int4*)tv;
     }
     hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
-                       d_reccnt, (const int32_t*)d_ioff, d_binoff, d_bincur, (float4*)recs_v, (int32_t*)bins_v,
+                       d_reccnt, (const int32_t*)d_ioff, d_binoff, d_bincur, (float4*)recs_v,
                        (const int64_t*)d_chunkoff, nbw * TT, n_items > 0 ? itile : (int4*)nullptr, n_items, chunk);
     OBBV_HIP(hipGetLastError());
     TestArgs ta;
@@ -1711,7 +1686,6 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     ta.chunk_off = d_chunkoff;
     ta.n_tiles = nbw * TT;
     ta.chunk = chunk;
-    ta.bins = (const int32_t*)bins_v;
     ta.recs = (const float4*)recs_v;
     ta.acc = d_acc;
     ta.ray_q = out_ray_q;
@@ -1732,7 +1706,6 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     }
     ta.seed = params->seed;
     ta.n_boxes = n_boxes;
-    ta.n_rec = (int)n_rec;
     ta.R = R;
     ta.tpe = tpe;
     ta.axis_mask = mask;
@@ -2064,8 +2037,8 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   ex.bin_cap = (int64_t)std::ceil((double)probe.n_bin * headroom) + 4096;
   ex.item_cap = (int64_t)std::ceil((double)probe.n_items * headroom) + 64;
   ex.items_cap = probe.items_bytes;
-  const size_t bytes = align_up(ex.meta_cap) + align_up((size_t)ex.rec_cap * kRecBytes) + align_up((size_t)ex.bin_cap * 4) +
-                       align_up(ex.items_cap) + align_up((size_t)ex.item_cap * sizeof(int4));
+  const size_t bytes = align_up(ex.meta_cap) + align_up((size_t)ex.bin_cap * kRecBytes) + align_up(ex.items_cap) +
+                       align_up((size_t)ex.item_cap * sizeof(int4));
   if (hipMalloc(&P->alloc, bytes) != hipSuccess) {
     (void)hipGetLastError();
     set_error("hipMalloc of the planned scratch failed");
@@ -2074,8 +2047,7 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   OBBV_HIP(hipMemset(P->alloc, 0, bytes));  // counters that every launch leaves zero start zero
   ex.meta = (char*)P->alloc;
   ex.recs = (float4*)(ex.meta + align_up(ex.meta_cap));
-  ex.bins = (int32_t*)((char*)ex.recs + align_up((size_t)ex.rec_cap * kRecBytes));
-  ex.items = (char*)ex.bins + align_up((size_t)ex.bin_cap * 4);
+  ex.items = (char*)ex.recs + align_up((size_t)ex.bin_cap * kRecBytes);
   ex.itile = (int4*)(ex.items + align_up(ex.items_cap));
   // the mesh table lives at the start of the meta block (outside the graph)
   std::vector<MeshDev> mh((size_t)n_meshes);

@@ -210,7 +210,8 @@ namespace {
 struct ProfState {
   bool enabled = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-  unsigned long long* counter = nullptr;
+  std::vector<hipEvent_t> spare;  // events of earlier reads, reused
+  unsigned long long* counter = nullptr;  // [kProfSlots]
   int counter_dev = -1;
 };
 ProfState g_prof;
@@ -225,8 +226,8 @@ int profile_counter(unsigned long long** out) {
   OBBV_HIP(hipGetDevice(&dev));
   if (!g_prof.counter || g_prof.counter_dev != dev) {
     void* q = nullptr;
-    OBBV_HIP(hipMalloc(&q, 256));
-    OBBV_HIP(hipMemset(q, 0, 256));
+    OBBV_HIP(hipMalloc(&q, kProfSlots * 8));
+    OBBV_HIP(hipMemset(q, 0, kProfSlots * 8));
     g_prof.counter = (unsigned long long*)q;
     g_prof.counter_dev = dev;
   }
@@ -235,9 +236,19 @@ int profile_counter(unsigned long long** out) {
 }
 
 int profile_record_begin(hipStream_t s, void** token) {
-  hipEvent_t a, b;
-  OBBV_HIP(hipEventCreate(&a));
-  OBBV_HIP(hipEventCreate(&b));
+  hipEvent_t ev[2];
+  {
+    std::lock_guard<std::mutex> lock(g_prof_mutex);
+    for (int k = 0; k < 2; ++k) {
+      if (g_prof.spare.empty()) {
+        OBBV_HIP(hipEventCreate(&ev[k]));
+      } else {
+        ev[k] = g_prof.spare.back();
+        g_prof.spare.pop_back();
+      }
+    }
+  }
+  hipEvent_t a = ev[0], b = ev[1];
   OBBV_HIP(hipEventRecord(a, s));
   std::lock_guard<std::mutex> lock(g_prof_mutex);
   g_prof.events.emplace_back(a, b);
@@ -278,16 +289,18 @@ extern "C" int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int
     float ms = 0.f;
     OBBV_HIP(hipEventElapsedTime(&ms, e.first, e.second));
     total += ms;
-    OBBV_HIP(hipEventDestroy(e.first));
-    OBBV_HIP(hipEventDestroy(e.second));
+    g_prof.spare.push_back(e.first);
+    g_prof.spare.push_back(e.second);
   }
   const int64_t n = (int64_t)g_prof.events.size();
   g_prof.events.clear();
   unsigned long long tests = 0;
   if (g_prof.counter) {
     OBBV_HIP(hipDeviceSynchronize());
-    OBBV_HIP(hipMemcpy(&tests, g_prof.counter, 8, hipMemcpyDeviceToHost));
-    OBBV_HIP(hipMemset(g_prof.counter, 0, 8));
+    unsigned long long slots[kProfSlots];
+    OBBV_HIP(hipMemcpy(slots, g_prof.counter, sizeof(slots), hipMemcpyDeviceToHost));
+    for (int k = 0; k < kProfSlots; ++k) tests += slots[k];
+    OBBV_HIP(hipMemset(g_prof.counter, 0, sizeof(slots)));
   }
   if (out_test_ms) *out_test_ms = total;
   if (out_launches) *out_launches = n;
