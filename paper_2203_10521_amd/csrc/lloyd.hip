@@ -87,7 +87,7 @@ __global__ void k_stage(const uint4* __restrict__ src, uint4* __restrict__ dst, 
 
 // host-side sections of the flood rounds (measurement only)
 struct FloodTimers {
-  WallTimer pops, cands, rank_post, exact_post, decide, grow, pred_pack, pred_launch, pred_wait;
+  WallTimer pops, extents, cands, rank_post, exact_post, decide, grow, pred_pack, pred_launch, pred_wait;
 };
 static FloodTimers g_ft;
 
@@ -936,10 +936,39 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
   std::vector<int32_t> ri, cur_of((size_t)boxes.size(), -1), touched;
   std::vector<std::vector<std::pair<double, size_t>>> per_box((size_t)boxes.size());
   std::vector<std::vector<int32_t>> got((size_t)boxes.size());  // candidate index per receiving box
-  std::vector<double> bc, bQ;  // centres and axes of a group's boxes in float64
-  // `overlap` (the next round's pops) runs once per round, while the device
-  // works if the round makes a device call, else at its end
-  auto round = [&](const std::vector<std::vector<int32_t>>& pops, const std::function<void()>& overlap) -> int {
+  // Centres and axes of every group's boxes in float64.  Only the half extents
+  // change during the flood, so an element's extent in a box frame does not
+  // depend on the decisions: the extents of a round's pops are computed while
+  // the device works on the round before.
+  std::vector<std::vector<double>> gbc((size_t)G), gbQ((size_t)G);
+  for (int g = 0; g < G; ++g) {
+    const Group& gr = groups[g];
+    gbc[g].resize(gr.boxes.size() * 3);
+    gbQ[g].resize(gr.boxes.size() * 9);
+    for (size_t i = 0; i < gr.boxes.size(); ++i) {
+      const HBox& bx = boxes[gr.boxes[i]];
+      for (int k = 0; k < 3; ++k) gbc[g][3 * i + k] = bx.c[k];
+      for (int k = 0; k < 9; ++k) gbQ[g][9 * i + k] = bx.Q[k];
+    }
+  }
+  // extents [pop][box of its group][3], pops in group order
+  auto pop_extents = [&](const std::vector<std::vector<int32_t>>& pops, std::vector<double>& out) {
+    g_ft.extents.start();
+    size_t total = 0;
+    for (int g = 0; g < G; ++g) total += pops[g].size() * groups[g].boxes.size();
+    out.resize(total * 3);
+    size_t x = 0;
+    for (int g = 0; g < G; ++g) {
+      const size_t b = groups[g].boxes.size();
+      for (int e : pops[g])
+        for (size_t i = 0; i < b; ++i, x += 3) element_extent_fast(E, e, &gbc[g][3 * i], &gbQ[g][9 * i], &out[x]);
+    }
+    g_ft.extents.stop();
+  };
+  // `overlap` (the next round's pops and their extents) runs once per round,
+  // while the device works if the round makes a device call, else at its end
+  auto round = [&](const std::vector<std::vector<int32_t>>& pops, const std::vector<double>& pext,
+                   const std::function<void()>& overlap) -> int {
     bool overlapped = false;
     const std::function<void()> overlap_once = [&]() {
       if (!overlapped) {
@@ -960,25 +989,16 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     for (int g = 0; g < G; ++g) {
       const Group& gr = groups[g];
       const int b = (int)gr.boxes.size();
-      if (pops[g].empty()) continue;
-      bc.resize((size_t)b * 3);
-      bQ.resize((size_t)b * 9);
-      for (int i = 0; i < b; ++i) {
-        const HBox& bx = boxes[gr.boxes[i]];
-        for (int k = 0; k < 3; ++k) bc[3 * i + k] = bx.c[k];
-        for (int k = 0; k < 9; ++k) bQ[9 * i + k] = bx.Q[k];
-      }
       for (int e : pops[g]) {
         const size_t first = nc;
         bool any_trivial = false;
         for (int i = 0; i < b; ++i) {
           const HBox& bx = boxes[gr.boxes[i]];
+          const double* ext = &pext[3 * nc];
           Cand& c = cands[nc++];
           c.e = e;
           c.g = g;
           c.li = i;
-          double ext[3];
-          element_extent_fast(E, e, &bc[3 * i], &bQ[9 * i], ext);
           for (int r = 0; r < 3; ++r) c.h[r] = f32_up(std::max((double)bx.h[r], ext[r]));
           c.trivial = same_h(c.h, bx.h);
           c.val = 0.0;
@@ -1195,18 +1215,22 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     return any;
   };
   bool any_next = false;
+  std::vector<double> ext, next_ext;
   const std::function<void()> advance = [&]() {
     g_ft.pops.start();
     for (int g = 0; g < G; ++g)
       for (int e : pops[g]) push_neighbours(e);
     g_ft.pops.stop();
     any_next = take_pops(next);
+    pop_extents(next, next_ext);
   };
   bool any = take_pops(pops);
+  pop_extents(pops, ext);
   while (any) {
     ++cnt.rounds;
-    OBBV_RET(round(pops, advance));
+    OBBV_RET(round(pops, ext, advance));
     pops.swap(next);
+    ext.swap(next_ext);
     any = any_next;
   }
   // elements no flood reached: one by one, in index order, all groups in lockstep
@@ -1224,7 +1248,8 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       if (p < left[g].size()) pops[g].push_back(left[g][p]);
     }
     ++cnt.rounds;
-    OBBV_RET(round(pops, [] {}));
+    pop_extents(pops, ext);
+    OBBV_RET(round(pops, ext, [] {}));
   }
   if (pred && pred->on) {
     const int64_t before = pred->judged_evals;
@@ -1415,9 +1440,9 @@ struct LloydState {
             pred.t_pred.s);
     const FloodTimers& f = g_ft;
     fprintf(stderr,
-            "[obbv lloyd] flood host: pops %.3f s, candidates %.3f s, ranker post %.3f s, exact post %.3f s, "
-            "decisions %.3f s, growth %.3f s; ranker: pack %.3f s, launch %.3f s, wait %.3f s\n",
-            f.pops.s, f.cands.s, f.rank_post.s, f.exact_post.s, f.decide.s, f.grow.s, f.pred_pack.s, f.pred_launch.s,
+            "[obbv lloyd] flood host: pops %.3f s, pop extents %.3f s, candidates %.3f s, ranker post %.3f s, "
+            "exact post %.3f s, decisions %.3f s, growth %.3f s; ranker: pack %.3f s, launch %.3f s, wait %.3f s\n",
+            f.pops.s, f.extents.s, f.cands.s, f.rank_post.s, f.exact_post.s, f.decide.s, f.grow.s, f.pred_pack.s, f.pred_launch.s,
             f.pred_wait.s);
     if (pred.judged_evals > 0)
       fprintf(stderr, "[obbv lloyd] judge: %lld candidates, mean |f - exact| %.5f, max %.5f, fallbacks %lld\n",

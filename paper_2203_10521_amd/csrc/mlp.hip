@@ -162,9 +162,11 @@ __global__ void k_adam(float* __restrict__ P, float* __restrict__ m, float* __re
 // bfloat16 MFMA (v_mfma_f32_32x32x16_bf16): lane l holds A[l % 32][8 (l / 32) + j]
 // and B[8 (l / 32) + j][l % 32], j = 0..7, of each K-step of 16; the result
 // layout is that of the 32 x 32 x 8 form.  The weights are pre-packed as bfloat16
-// in the order the lanes consume them: for output unit n and lane half q, entry
-// ((n * 2 + q) * (K / 16) + k) * 8 + j holds W[16 k + 8 q + j][n], so every lane
-// reads one contiguous run of its operands.
+// in the order the lanes consume them: for output unit n, lane half q and K-step
+// k, entry (((n / 32) (K / 16) + k) 64 + 32 q + n % 32) 8 + j holds
+// W[16 k + 8 q + j][n], so the 64 lanes of the wave that computes columns
+// 32 (n / 32) .. read one contiguous kilobyte per K-step (16 cache lines per
+// load instruction instead of 64).
 constexpr int64_t kPacked = (int64_t)kIn * kH + (int64_t)kH * kH;  // bf16 entries
 typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -181,9 +183,10 @@ __global__ void k_mlp_pack(const float* __restrict__ P, short* __restrict__ W) {
   const int64_t e = first ? i : i - (int64_t)kIn * kH;
   const int j = (int)(e & 7);
   const int64_t rest = e >> 3;
-  const int k = (int)(rest % (K / 16));
-  const int64_t nq = rest / (K / 16);
-  const int q = (int)(nq & 1), n = (int)(nq >> 1);
+  const int ln = (int)(rest & 63);  // lane: 32 q + n % 32
+  const int64_t tk = rest >> 6;     // (n / 32) (K / 16) + k
+  const int k = (int)(tk % (K / 16));
+  const int n = 32 * (int)(tk / (K / 16)) + (ln & 31), q = ln >> 5;
   const int in = 16 * k + 8 * q + j;
   W[i] = f2bf(P[(first ? oW1 : oW2) + (int64_t)in * kH + n]);
 }
@@ -208,20 +211,32 @@ constexpr int kInPitch = kIn + 8, kHPitch = kH + 8;
 // thread of the block calls this (barriers).
 constexpr int kRowThreads = 512;
 
-template <class Stage>
-__device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ W, Stage stage, short* sx, short* sh1,
-                         float* zp, const float* socc, int64_t row0, int n, float* __restrict__ f) {
+// `pre` runs before any weight is requested (a stage whose own loads should
+// return first issues them there); kLateW2: the second layer's weights are
+// requested after the rows are staged (a stage that holds many registers of
+// its own), else with the first layer's.  The tile's outputs are f[row0 + t] for
+// t < rows.
+template <bool kLateW2 = false, class Stage, class Pre>
+__device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ W, Stage stage, Pre pre, short* sx,
+                         short* sh1, float* zp, const float* socc, int64_t row0, int rows, float* __restrict__ f) {
+  pre();
+  __builtin_amdgcn_sched_barrier(0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 31, kq = (lane >> 5) * 8;
-  const int nn = 32 * wave + r;  // this lane's weight row (output column)
-  const v8s* w1 = reinterpret_cast<const v8s*>(W) + (int64_t)(2 * nn + (lane >> 5)) * (kIn / 16);
-  const v8s* w2 = reinterpret_cast<const v8s*>(W + (int64_t)kIn * kH) + (int64_t)(2 * nn + (lane >> 5)) * (kH / 16);
+  // this wave's operands: K-step k of lane l at v8s index (wave (K / 16) + k) 64 + l
+  const v8s* w1 = reinterpret_cast<const v8s*>(W) + (int64_t)wave * (kIn / 16) * 64 + lane;
+  const v8s* w2 = reinterpret_cast<const v8s*>(W + (int64_t)kIn * kH) + (int64_t)wave * (kH / 16) * 64 + lane;
   v8s b1[kIn / 16], b2[kH / 16];
-  for (int k = 0; k < kIn / 16; ++k) b1[k] = w1[k];
-  for (int k = 0; k < kH / 16; ++k) b2[k] = w2[k];
-  __builtin_amdgcn_sched_barrier(0);  // every weight load is in flight before the rows are staged
+  for (int k = 0; k < kIn / 16; ++k) b1[k] = w1[64 * k];
+  if (!kLateW2)
+    for (int k = 0; k < kH / 16; ++k) b2[k] = w2[64 * k];
+  __builtin_amdgcn_sched_barrier(0);  // the weight loads are in flight before the rows are staged
   stage();
   __syncthreads();
+  if (kLateW2) {
+    for (int k = 0; k < kH / 16; ++k) b2[k] = w2[64 * k];
+    __builtin_amdgcn_sched_barrier(0);
+  }
   const int c = 32 * wave + (lane & 31);
   {
     v16f acc;
@@ -251,7 +266,7 @@ __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ 
   if ((lane & 31) == 0)
     for (int rr = 0; rr < 16; ++rr) zp[wave * kFusedRows + 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4)] = v[rr];
   __syncthreads();
-  if (threadIdx.x < kFusedRows && row0 + threadIdx.x < n) {
+  if ((int)threadIdx.x < rows) {
     float z = 0.f;
     for (int w = 0; w < kRowThreads / 64; ++w) z += zp[w * kFusedRows + threadIdx.x];
     z += P[ob3];
@@ -298,7 +313,7 @@ k_mlp_rows(const float* __restrict__ P, const short* __restrict__ W, const float
       if (threadIdx.x < kFusedRows) socc[threadIdx.x] = row0 + threadIdx.x < n ? occ[row0 + threadIdx.x] : 0.f;
     }
   };
-  mlp_tile(P, W, stage, sx, sh1, zp, socc, row0, n, f);
+  mlp_tile(P, W, stage, [] {}, sx, sh1, zp, socc, row0, (int)min((int64_t)kFusedRows, n - row0), f);
   if (done_flag) {  // the last workgroup to finish raises the host-visible flag
     __threadfence_system();
     __syncthreads();
@@ -362,6 +377,85 @@ k_rank_inputs(const float* __restrict__ vol, int N, const float* __restrict__ fr
   }
 }
 
+// Ranking of kRankRows boxes per workgroup in one launch: the workgroup computes
+// its boxes' inputs as k_rank_inputs does (the same float values, bfloat16 row
+// and occupancy sum) straight into the tile's LDS rows, the other rows of the
+// 32-row tile are zero, and the network runs as in k_mlp_rows, so the outputs
+// are bitwise those of k_rank_inputs + k_mlp_rows<false>.  The volume reads are
+// requested first, then the first layer's weights.  A workgroup's volume gathers
+// (4,352 per box) and weight loads (401 KB) pass one CU's load pipeline, so few
+// boxes per workgroup spread the gathers over more CUs.  The last workgroup to
+// finish raises the host flag (when given).
+template <int kRankRows>
+__global__ void __launch_bounds__(kRowThreads)
+k_rank_fused(const float* __restrict__ P, const short* __restrict__ W, const float* __restrict__ vol, int N,
+             const float* __restrict__ frame, const obbv_box* __restrict__ boxes, int n, float* __restrict__ f,
+             unsigned* done_count, unsigned* done_flag, unsigned seq) {
+  __shared__ __align__(16) short sx[kFusedRows * kInPitch];
+  __shared__ short sh1[kFusedRows * kHPitch];
+  __shared__ float zp[(kRowThreads / 64) * kFusedRows];
+  __shared__ float socc[kFusedRows];
+  __shared__ float sbox[kRankRows][16];
+  __shared__ float sf[kRankRows][kIn];
+  constexpr int kRankFusedPer = (kRankRows * kIn + kRowThreads - 1) / kRowThreads;
+  const int64_t row0 = (int64_t)blockIdx.x * kRankRows;
+  const int rows = (int)min((int64_t)kRankRows, n - row0);
+  OccSample smp[kRankFusedPer];
+  float v[kRankFusedPer][8];
+  // before the weights: the tile's boxes (they may sit in mapped host memory:
+  // each read once; rows past the last box take the first box and are
+  // discarded), then every volume read of the inputs, so these return first
+  auto pre = [&]() {
+    if (threadIdx.x < kRankRows * 15) {
+      const int rw = threadIdx.x / 15, e = threadIdx.x - 15 * (threadIdx.x / 15);
+      sbox[rw][e] = reinterpret_cast<const float*>(boxes)[(row0 + (rw < rows ? rw : 0)) * 15 + e];
+    }
+    __syncthreads();
+    for (int m = 0; m < kRankFusedPer; ++m) {  // no branches: every read in flight together
+      const int idx = min((int)threadIdx.x + kRowThreads * m, kRankRows * kIn - 1);
+      const int rw = idx / kIn, k = idx - rw * kIn;
+      const int r = min(max(k - kFeatOcc0, 0), kFeatOccN - 1);
+      smp[m] = occ_sample_at(r, sbox[rw], frame);
+      for (int c = 0; c < 8; ++c) v[m][c] = occ_corner(vol, N, smp[m], c);
+    }
+  };
+  auto stage = [&]() {
+    // rows kRankRows.. of the tile are zero
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    constexpr int kChunks = kInPitch / 8;
+    for (int i = threadIdx.x; i < (kFusedRows - kRankRows) * kChunks; i += kRowThreads)
+      *reinterpret_cast<v4i*>(&sx[kRankRows * kInPitch + 8 * i]) = v4i{0, 0, 0, 0};
+    for (int m = 0; m < kRankFusedPer; ++m) {
+      const int idx = threadIdx.x + kRowThreads * m;
+      if (idx >= kRankRows * kIn) break;
+      const int rw = idx / kIn, k = idx - rw * kIn;
+      float x = 0.f;
+      if (k < kFeatOcc0) x = box_param_feature(k, sbox[rw], frame);
+      else if (k < kFeatOcc0 + kFeatOccN) x = occ_blend(smp[m], v[m]);
+      sf[rw][k] = x;
+      sx[rw * kInPitch + k] = rw < rows ? f2bf(x) : (short)0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    if (wave < kRankRows) {
+      const float o = occ_sum_wave([&](int k) { return sf[wave][k]; });
+      if ((threadIdx.x & 63) == 0) socc[wave] = o;
+    }
+  };
+  mlp_tile<true>(P, W, stage, pre, sx, sh1, zp, socc, row0, rows, f);
+  if (done_flag) {  // the last workgroup to finish raises the host-visible flag
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned prev = atomicAdd(done_count, 1u);
+      if (prev == gridDim.x - 1) {
+        atomicExch(done_count, 0u);  // ready for the next call on the stream
+        __threadfence_system();
+        __hip_atomic_store(done_flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  }
+}
 
 struct MlpScratch {
   float* H1;
@@ -429,6 +523,12 @@ int mlp_infer_packed(const float* params, const short* packed, const float* X, i
   return OBBV_OK;
 }
 
+// Rankings of at most kRankOneBoxMax boxes take the one-launch kernel with one
+// box per workgroup, of at most kRankFusedMax with four; every workgroup reads
+// the 401 KB of weights, so larger calls take the two launches.
+constexpr int kRankOneBoxMax = 256;
+constexpr int kRankFusedMax = 1024;
+
 // scratch of mlp_rank_packed: Xb [n][kIn] bfloat16 | occ [n]
 size_t mlp_rank_scratch_bytes(int32_t n) { return (((size_t)n * kIn * 2 + 255) & ~(size_t)255) + (size_t)n * 4; }
 
@@ -437,6 +537,18 @@ int mlp_rank_packed(const float* params, const short* packed, const float* volum
                     unsigned* done_count, unsigned* done_flag, unsigned seq) {
   OBBV_ARG(n >= 0 && N >= 1, "bad size");
   if (n == 0) return OBBV_OK;
+  if (n <= kRankOneBoxMax) {  // one launch, one box per workgroup
+    hipLaunchKernelGGL(k_rank_fused<1>, dim3((unsigned)n), dim3(kRowThreads), 0, s, params, packed, volume, N, frame,
+                       boxes, n, out_f, done_count, done_flag, seq);
+    OBBV_HIP(hipGetLastError());
+    return OBBV_OK;
+  }
+  if (n <= kRankFusedMax) {  // one launch, four boxes per workgroup
+    hipLaunchKernelGGL(k_rank_fused<4>, dim3((unsigned)((n + 3) / 4)), dim3(kRowThreads), 0, s, params, packed, volume,
+                       N, frame, boxes, n, out_f, done_count, done_flag, seq);
+    OBBV_HIP(hipGetLastError());
+    return OBBV_OK;
+  }
   short* Xb = (short*)scratch;
   float* occ = (float*)((char*)scratch + (((size_t)n * kIn * 2 + 255) & ~(size_t)255));
   hipLaunchKernelGGL(k_rank_inputs, dim3((unsigned)n), dim3(256), 0, s, volume, N, frame, boxes, n, Xb, occ);

@@ -121,14 +121,16 @@ def test_ranker_learns_and_ranks_at_least_as_well_as_the_occupancy_mean(api, tra
 
 
 def test_fused_ranking_equals_features_then_forward(api, trained):
-    """One launch (inputs built on chip) gives the bits of the two-step path, for
-    a box count that is not a multiple of the 32-row tile, and none for 0 boxes."""
+    """The ranking entry point gives the bits of features-then-network in each of
+    its forms: one launch with one box per workgroup (up to 256 boxes), one
+    launch with four (up to 1,024, counts that leave a partial workgroup), two
+    launches (more boxes); and nothing for 0 boxes."""
     import torch
     P, _ = trained
     V, F = synth.noisy_cube_sphere(14, seed=779)
     Vt, Ft = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
     vol, frame = api.occupancy_volume(Vt, Ft, nb=8, seed=2)
-    for n in (77, 1, 32, 300):
+    for n in (77, 1, 32, 256, 300, 1023, 1100):
         B = torch.from_numpy(synth.mixed_boxes(V, n, seed=40 + n)).cuda()
         fused = api.mlp_rank_boxes(P, vol, frame, B).cpu().numpy()
         X = api.sample_features(vol, frame, B)
