@@ -23,6 +23,7 @@
 //     local axis, gradient, line search at {8, 4, 2, 1, 0.5} delta along -g,
 //     keep the best if it lowers OBV.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -33,6 +34,7 @@
 #include <numeric>
 #include <queue>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -58,7 +60,7 @@ int mlp_pack_impl(const float* params, short* packed, hipStream_t s);
 int64_t mlp_packed_entries();
 int mlp_rank_packed(const float* params, const short* packed, const float* volume, int32_t N, const float* frame,
                     const obbv_box* boxes, int32_t n, void* scratch, float* out_f, hipStream_t s,
-                    unsigned* done_count, unsigned* done_flag, unsigned seq);
+                    unsigned* done_count, unsigned* done_flag, unsigned seq, const obbv_box* host_boxes);
 size_t mlp_rank_scratch_bytes(int32_t n);
 
 namespace {
@@ -632,7 +634,7 @@ struct Predictor {
     const unsigned seq = ++sig_seq;
     g_ft.pred_launch.start();
     OBBV_RET(mlp_rank_packed(cfg.mlp_params, packed, cfg.volume, cfg.N, cfg.frame, (const obbv_box*)hdev, (int32_t)n,
-                             dbuf, (float*)(hdev + o_f), stream, sig_count, sig_dev, seq));
+                             dbuf, (float*)(hdev + o_f), stream, sig_count, sig_dev, seq, hb));
     g_ft.pred_launch.stop();
     if (overlap) (*overlap)();  // host work for later rounds while the device ranks
     g_ft.pred_wait.start();
@@ -999,7 +1001,8 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
           c.e = e;
           c.g = g;
           c.li = i;
-          for (int r = 0; r < 3; ++r) c.h[r] = f32_up(std::max((double)bx.h[r], ext[r]));
+          // an axis the element does not widen keeps the box's (float) extent
+          for (int r = 0; r < 3; ++r) c.h[r] = ext[r] <= (double)bx.h[r] ? bx.h[r] : f32_up(ext[r]);
           c.trivial = same_h(c.h, bx.h);
           c.val = 0.0;
           if (c.trivial) {
@@ -1320,33 +1323,57 @@ HBox tight_box(const HostMesh& M, const std::vector<int32_t>& verts, const doubl
   return b;
 }
 
+// fn(i) for i in [0, n) on up to eight host threads (each i independent)
+template <class Fn>
+void parallel_for(size_t n, Fn fn) {
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nt = std::min<size_t>({n, (size_t)8, hw});
+  if (nt <= 1) {
+    for (size_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  for (size_t t = 1; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (size_t i = t; i < n; i += nt) fn(i);
+    });
+  for (size_t i = 0; i < n; i += nt) fn(i);
+  for (auto& x : th) x.join();
+}
+
 // Update every box with a non-empty vertex set; returns the accepted OBV per box.
 int update_boxes(const HostMesh& M, const std::vector<std::vector<int32_t>>& verts, std::vector<HBox>& boxes,
                  std::vector<double>& obv, const std::vector<uint32_t>& slot, const std::vector<int32_t>& which,
                  double delta, Evaluator& ev, Counters& cnt) {
   const double steps[5] = {8.0, 4.0, 2.0, 1.0, 0.5};
-  std::vector<HBox> req;
-  std::vector<uint32_t> keys;
-  for (int bi : which) {
+  // the current axes and the six +-delta rotations of every box: 7 tight boxes
+  // each (independent, computed on several host threads)
+  std::vector<HBox> req(which.size() * 7);
+  std::vector<uint32_t> keys(which.size() * 7);
+  parallel_for(req.size(), [&](size_t x) {
+    const int bi = which[x / 7], m = (int)(x % 7);
     double Q[9];
     for (int k = 0; k < 9; ++k) Q[k] = (double)boxes[bi].Q[k];
-    req.push_back(tight_box(M, verts[bi], Q));
-    keys.push_back(slot[bi]);
-    for (int k = 0; k < 3; ++k)
-      for (int sg = 0; sg < 2; ++sg) {
-        double R[9], Q2[9];
-        rot_local(k, sg == 0 ? delta : -delta, R);
-        mat3_mul(R, Q, Q2);
-        req.push_back(tight_box(M, verts[bi], Q2));
-        keys.push_back(slot[bi]);
-      }
-  }
+    if (m == 0) {
+      req[x] = tight_box(M, verts[bi], Q);
+    } else {
+      const int k = (m - 1) / 2, sg = (m - 1) % 2;
+      double R[9], Q2[9];
+      rot_local(k, sg == 0 ? delta : -delta, R);
+      mat3_mul(R, Q, Q2);
+      req[x] = tight_box(M, verts[bi], Q2);
+    }
+    keys[x] = slot[bi];
+  });
   std::vector<double> v1;
   OBBV_RET(ev.eval(req, keys, v1));
   cnt.evals += (int64_t)v1.size();
-  std::vector<HBox> req2;
-  std::vector<uint32_t> keys2;
+  // a line search along the descent direction: 5 rotations per box whose
+  // finite-difference gradient is non-zero
   std::vector<int32_t> has_line;
+  std::vector<std::pair<int32_t, int32_t>> tasks;  // (index into which, step)
+  std::vector<std::array<double, 3>> dir(which.size());
   for (size_t x = 0; x < which.size(); ++x) {
     const double* v = &v1[7 * x];
     double g[3];
@@ -1357,17 +1384,23 @@ int update_boxes(const HostMesh& M, const std::vector<std::vector<int32_t>>& ver
       continue;
     }
     has_line.push_back(1);
+    dir[x] = {-g[0] / gn, -g[1] / gn, -g[2] / gn};
+    for (int si = 0; si < 5; ++si) tasks.push_back({(int32_t)x, si});
+  }
+  std::vector<HBox> req2(tasks.size());
+  std::vector<uint32_t> keys2(tasks.size());
+  parallel_for(tasks.size(), [&](size_t y) {
+    const size_t x = (size_t)tasks[y].first;
+    const double s = steps[tasks[y].second];
     double Q[9];
     for (int k = 0; k < 9; ++k) Q[k] = (double)boxes[which[x]].Q[k];
-    for (double s : steps) {
-      const double r[3] = {s * delta * (-g[0] / gn), s * delta * (-g[1] / gn), s * delta * (-g[2] / gn)};
-      double R[9], Q2[9];
-      rodrigues(r, R);
-      mat3_mul(R, Q, Q2);
-      req2.push_back(tight_box(M, verts[which[x]], Q2));
-      keys2.push_back(slot[which[x]]);
-    }
-  }
+    const double r[3] = {s * delta * dir[x][0], s * delta * dir[x][1], s * delta * dir[x][2]};
+    double R[9], Q2[9];
+    rodrigues(r, R);
+    mat3_mul(R, Q, Q2);
+    req2[y] = tight_box(M, verts[which[x]], Q2);
+    keys2[y] = slot[which[x]];
+  });
   std::vector<double> v2;
   OBBV_RET(ev.eval(req2, keys2, v2));
   cnt.evals += (int64_t)v2.size();

@@ -14,6 +14,8 @@
 // (W[i][o] multiplies input i into output o).
 #include <cmath>
 
+#include <cstring>
+
 #include "common.h"
 #include "box_features.h"
 
@@ -386,11 +388,18 @@ k_rank_inputs(const float* __restrict__ vol, int N, const float* __restrict__ fr
 // (4,352 per box) and weight loads (401 KB) pass one CU's load pipeline, so few
 // boxes per workgroup spread the gathers over more CUs.  The last workgroup to
 // finish raises the host flag (when given).
+// Up to kArgBoxes boxes can travel in the kernel arguments (no read of mapped
+// host memory on the critical path).
+constexpr int kArgBoxes = 32;
+struct RankArgBoxes {
+  float v[kArgBoxes * 15];
+};
+
 template <int kRankRows>
 __global__ void __launch_bounds__(kRowThreads)
 k_rank_fused(const float* __restrict__ P, const short* __restrict__ W, const float* __restrict__ vol, int N,
-             const float* __restrict__ frame, const obbv_box* __restrict__ boxes, int n, float* __restrict__ f,
-             unsigned* done_count, unsigned* done_flag, unsigned seq) {
+             const float* __restrict__ frame, const obbv_box* __restrict__ boxes, RankArgBoxes ab, int use_ab,
+             int n, float* __restrict__ f, unsigned* done_count, unsigned* done_flag, unsigned seq) {
   __shared__ __align__(16) short sx[kFusedRows * kInPitch];
   __shared__ short sh1[kFusedRows * kHPitch];
   __shared__ float zp[(kRowThreads / 64) * kFusedRows];
@@ -402,13 +411,15 @@ k_rank_fused(const float* __restrict__ P, const short* __restrict__ W, const flo
   const int rows = (int)min((int64_t)kRankRows, n - row0);
   OccSample smp[kRankFusedPer];
   float v[kRankFusedPer][8];
-  // before the weights: the tile's boxes (they may sit in mapped host memory:
-  // each read once; rows past the last box take the first box and are
-  // discarded), then every volume read of the inputs, so these return first
+  // before the weights: the tile's boxes (from the arguments, or from `boxes`,
+  // which may sit in mapped host memory: each read once; rows past the last
+  // box take the first box and are discarded), then every volume read of the
+  // inputs, so these return first
   auto pre = [&]() {
     if (threadIdx.x < kRankRows * 15) {
       const int rw = threadIdx.x / 15, e = threadIdx.x - 15 * (threadIdx.x / 15);
-      sbox[rw][e] = reinterpret_cast<const float*>(boxes)[(row0 + (rw < rows ? rw : 0)) * 15 + e];
+      const int64_t at = (row0 + (rw < rows ? rw : 0)) * 15 + e;
+      sbox[rw][e] = use_ab ? ab.v[at] : reinterpret_cast<const float*>(boxes)[at];
     }
     __syncthreads();
     for (int m = 0; m < kRankFusedPer; ++m) {  // no branches: every read in flight together
@@ -442,6 +453,8 @@ k_rank_fused(const float* __restrict__ P, const short* __restrict__ W, const flo
       if ((threadIdx.x & 63) == 0) socc[wave] = o;
     }
   };
+  // the second layer's weights after the stage: requested with the first
+  // layer's, they delay the volume gathers in the CU's load pipeline
   mlp_tile<true>(P, W, stage, pre, sx, sh1, zp, socc, row0, rows, f);
   if (done_flag) {  // the last workgroup to finish raises the host-visible flag
     __threadfence_system();
@@ -534,18 +547,21 @@ size_t mlp_rank_scratch_bytes(int32_t n) { return (((size_t)n * kIn * 2 + 255) &
 
 int mlp_rank_packed(const float* params, const short* packed, const float* volume, int32_t N, const float* frame,
                     const obbv_box* boxes, int32_t n, void* scratch, float* out_f, hipStream_t s,
-                    unsigned* done_count, unsigned* done_flag, unsigned seq) {
+                    unsigned* done_count, unsigned* done_flag, unsigned seq, const obbv_box* host_boxes) {
   OBBV_ARG(n >= 0 && N >= 1, "bad size");
   if (n == 0) return OBBV_OK;
+  RankArgBoxes ab;
+  const int use_ab = host_boxes && n <= kArgBoxes;
+  if (use_ab) std::memcpy(ab.v, host_boxes, (size_t)n * sizeof(obbv_box));
   if (n <= kRankOneBoxMax) {  // one launch, one box per workgroup
     hipLaunchKernelGGL(k_rank_fused<1>, dim3((unsigned)n), dim3(kRowThreads), 0, s, params, packed, volume, N, frame,
-                       boxes, n, out_f, done_count, done_flag, seq);
+                       boxes, ab, use_ab, n, out_f, done_count, done_flag, seq);
     OBBV_HIP(hipGetLastError());
     return OBBV_OK;
   }
   if (n <= kRankFusedMax) {  // one launch, four boxes per workgroup
     hipLaunchKernelGGL(k_rank_fused<4>, dim3((unsigned)((n + 3) / 4)), dim3(kRowThreads), 0, s, params, packed, volume,
-                       N, frame, boxes, n, out_f, done_count, done_flag, seq);
+                       N, frame, boxes, ab, use_ab, n, out_f, done_count, done_flag, seq);
     OBBV_HIP(hipGetLastError());
     return OBBV_OK;
   }
@@ -602,7 +618,8 @@ extern "C" int obbv_mlp_rank_boxes(const float* params, const float* volume, int
   OBBV_RET(pool_get(kPoolMlp, (size_t)kPacked * 2, &pv));
   OBBV_RET(pool_get(kPoolRank, mlp_rank_scratch_bytes(n_boxes), &sc));
   OBBV_RET(mlp_pack_impl(params, (short*)pv, s));
-  return mlp_rank_packed(params, (const short*)pv, volume, N, frame, boxes, n_boxes, sc, out_f, s, nullptr, nullptr, 0u);
+  return mlp_rank_packed(params, (const short*)pv, volume, N, frame, boxes, n_boxes, sc, out_f, s, nullptr, nullptr, 0u,
+                         nullptr);
 }
 
 extern "C" int obbv_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, const float* X,
