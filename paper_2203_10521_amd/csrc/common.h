@@ -73,6 +73,20 @@ int pool_get_zeroed(int slot, size_t bytes, void** out);
 constexpr int kRecF4 = 4;
 constexpr int kRecBytes = 16 * kRecF4;
 
+// A ray-test work item (64 bytes, written by the write pass): up to a chunk of
+// one ray tile's bin entries and the ray grid of the tile's (box, axis) cast,
+// so a ray-test wave needs no further table before its rays and records.
+struct WorkItem {
+  double hu, hv, du, dv;  // half extents of the cast face and cell sizes (u, v)
+  uint64_t s0;            // SplitMix64 state of the u draw of cell (0, 0)
+  int64_t k0;             // first bin entry
+  int32_t count;          // bin entries (at least one)
+  int32_t g;              // tile: ((box * 3 + axis) * tiles per face + tile)
+  uint32_t key;           // the box's jitter key
+  int32_t pad;
+};
+static_assert(sizeof(WorkItem) == 64, "WorkItem layout");
+
 // How one outer-volume evaluation is executed.  Default: scratch is sized from
 // the device counts (one host round trip).  planned: fixed scratch, no round
 // trip, capturable into a HIP graph.  capped: fixed record / bin / work-item
@@ -93,7 +107,7 @@ struct OvExec {
   int64_t n_rec = 0, n_bin = 0, n_items = 0;  // counts of the last synchronous run
   char* items = nullptr;                      // per-cull-item counts and offsets
   size_t items_cap = 0, items_bytes = 0;
-  int4* itile = nullptr;                      // [item_cap] ray-test work items (WorkItem layout)
+  WorkItem* itile = nullptr;                  // [item_cap] ray-test work items
   uint32_t* status = nullptr;
   int64_t* publish = nullptr;
   int pool_base = 0;  // slot offset of the pool set the call's pooled scratch comes from

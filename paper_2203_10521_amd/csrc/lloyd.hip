@@ -155,7 +155,7 @@ struct Evaluator {
     const int64_t r = std::max(rec_cap, n_rec + n_rec / 2 + 4096);
     const int64_t b = std::max(bin_cap, n_bin + n_bin / 2 + 8192);
     const int64_t it = std::max(item_cap, n_items + n_items / 2 + 256);
-    const size_t need = al((size_t)b * kRecBytes) + al((size_t)it * sizeof(int4));
+    const size_t need = al((size_t)b * kRecBytes) + al((size_t)it * sizeof(WorkItem));
     if (need > scap) {
       if (sbuf) {
         OBBV_HIP(hipStreamSynchronize(stream));
@@ -383,7 +383,7 @@ struct Evaluator {
       OvExec ex;
       ex.capped = true;
       ex.recs = (float4*)sbuf;
-      ex.itile = (int4*)(sbuf + al((size_t)bin_cap * kRecBytes));
+      ex.itile = (WorkItem*)(sbuf + al((size_t)bin_cap * kRecBytes));
       ex.rec_cap = rec_cap;
       ex.bin_cap = bin_cap;
       ex.item_cap = item_cap;

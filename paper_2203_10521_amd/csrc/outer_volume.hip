@@ -756,17 +756,29 @@ __global__ void __launch_bounds__(kCullThreads)
 k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict__ rec_off,
         const int32_t* __restrict__ rec_cnt, const int32_t* __restrict__ item_off,
         const int64_t* __restrict__ bin_off, int32_t* __restrict__ bin_cur, float4* __restrict__ recs,
-        const int64_t* __restrict__ chunk_off, int64_t n_tiles, int4* __restrict__ item_tile, int64_t item_cap,
+        const int64_t* __restrict__ chunk_off, int64_t n_tiles, WorkItem* __restrict__ items, int64_t item_cap,
         int chunk) {
-  if (item_tile) {  // the ray-test work items: tile, record count, first bin entry (grid-stride over the tiles)
+  if (items) {  // the ray-test work items (grid-stride over the tiles)
+    const int TT = a.tpe * a.tpe;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles;
          t += (int64_t)gridDim.x * blockDim.x) {
       const int64_t c0 = chunk_off[t], c1 = min(chunk_off[t + 1], item_cap);
+      if (c0 >= c1) continue;
       const int64_t b0 = bin_off[t], b1 = bin_off[t + 1];
+      const RayFrame& rf = a.rframe[t / TT];
+      WorkItem wi;
+      wi.hu = rf.hu;
+      wi.hv = rf.hv;
+      wi.du = rf.du;
+      wi.dv = rf.dv;
+      wi.s0 = rf.s0;
+      wi.g = (int32_t)t;
+      wi.key = rf.key;
+      wi.pad = 0;
       for (int64_t c = c0; c < c1; ++c) {
-        const int64_t k0 = b0 + (c - c0) * chunk;
-        const int cnt = (int)(min(b1, k0 + chunk) - k0);
-        item_tile[c] = make_int4((int)t, cnt, (int)(uint32_t)(uint64_t)k0, (int)(uint32_t)((uint64_t)k0 >> 32));
+        wi.k0 = b0 + (c - c0) * chunk;
+        wi.count = (int32_t)(min(b1, wi.k0 + chunk) - wi.k0);
+        items[c] = wi;
       }
     }
   }
@@ -890,10 +902,10 @@ struct TestArgs {
   uint32_t axis_mask;
   int64_t bin_cap;      // planned launches: bins beyond it were not written
   int64_t item_cap;     // planned launches: work items beyond it are skipped
-  const int4* item_tile;     // [work items] tile, record count, first bin entry (lo, hi) of every work item
+  const WorkItem* items;     // [work items] every ray-test work item
   int persistent;       // 1: grid-stride over the work items counted on the device
-  const RayFrame* rframe;    // [nbw] ray grid of every (box, axis) cast
   const uint2* jitter;       // nullable: jitter table [keys][3][R][R] (jitter_table), every key < its rows
+  int raster_cells;          // records covering more cells of a tile take the wave-wide path
 };
 
 // One wave per TE x TE ray tile of one (box, axis); RPL = (TE/8)^2 rays per lane.
@@ -921,9 +933,9 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
   constexpr int RPL = NB * NB;
   const int TT = a.tpe * a.tpe;
   // tile of this work item: chunk_off[g] <= item < chunk_off[g + 1]
-  const int64_t g = a.item_tile[item].x;
-  const int bw = (int)(g / TT);
-  const int tile = (int)(g - (int64_t)bw * TT);
+  const int g = a.items[item].g;
+  const int bw = g / TT;
+  const int tile = g - bw * TT;
   const int b = bw / 3, w = bw - 3 * (bw / 3);
   if (!((a.axis_mask >> w) & 1u)) return;
   const BoxRegs B = load_box(a.boxes, b);
@@ -1039,11 +1051,11 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
 // Rasterising ray test of 16 x 16-ray tiles.  Each lane takes one record and
 // tests only the rays of the cells its projected bounding box covers (the same
 // conservative cell range the binning used); a record covering more than
-// kRasterCells cells of the tile is tested by the whole wave instead, every lane
-// its four rays.  A crossing inside the triangle adds q = bits(y) - 0x4B400000
+// kRasterCells cells of the tile is tested by the whole wave instead, one covered
+// cell per lane.  A crossing inside the triangle adds q = bits(y) - 0x4B400000
 // (the fixed-point inside length, as in k_test) to its ray's integer sum in LDS,
 // so the sums are exact and independent of the order.
-constexpr int kRasterCells = 16;
+constexpr int kRasterCells = 64;  // default; raster_cells_choice()
 
 __device__ inline bool ray_hit(float u, float v, const float4& r0, const float4& r1, const float4& r2,
                                const float4& r3, int32_t& q) {
@@ -1060,40 +1072,53 @@ __device__ inline bool ray_hit(float u, float v, const float4& r0, const float4&
 template <bool STATS, bool TAB>
 __device__ void raster_item(const TestArgs& a, const int64_t item) {
   const int TT = a.tpe * a.tpe;
-  const int4 wi = a.item_tile[item];  // tile, record count, first bin entry
-  const int64_t g = wi.x;
-  const int bw = (int)(g / TT);
-  const int tile = (int)(g - (int64_t)bw * TT);
+  // the whole item in one request, its (uniform) words moved to scalar
+  // registers before any branch (an item exists only for a tile with bin
+  // entries, so its axis is one the call casts)
+  WorkItem wi;  // ray grid, tile, bin entries
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(a.items + item);
+    uint4 q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = src[k];
+    uint32_t d[16];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      d[4 * k + 0] = __builtin_amdgcn_readfirstlane(q[k].x);
+      d[4 * k + 1] = __builtin_amdgcn_readfirstlane(q[k].y);
+      d[4 * k + 2] = __builtin_amdgcn_readfirstlane(q[k].z);
+      d[4 * k + 3] = __builtin_amdgcn_readfirstlane(q[k].w);
+    }
+    __builtin_memcpy(&wi, d, sizeof(wi));
+  }
+  const int g = wi.g;
+  const int bw = g / TT;
+  const int tile = g - bw * TT;
   const int w = bw - 3 * (bw / 3);
-  if (!((a.axis_mask >> w) & 1u)) return;
   const int lane = threadIdx.x;
-  const int64_t k0 = (int64_t)(((uint64_t)(uint32_t)wi.w << 32) | (uint32_t)wi.z);
-  const int64_t k1 = k0 + wi.y;
+  const int64_t k0 = wi.k0;
+  const int64_t k1 = k0 + wi.count;
   if (k1 > a.bin_cap) return;  // bins past a planned capacity were not written (flagged)
   // (boxes whose state is not 0 get no records, hence no ray-test work items)
-  const RayFrame rf = a.rframe[bw];
-  const double hu = rf.hu, hv = rf.hv, du = rf.du, dv = rf.dv;
+  const double hu = wi.hu, hv = wi.hv, du = wi.du, dv = wi.dv;
   const int ti = tile % a.tpe, tj = tile / a.tpe;
   const int ci_lo = ti * 16, cj_lo = tj * 16;
-  const int ci_hi = min(ci_lo + 15, a.R - 1), cj_hi = min(cj_lo + 15, a.R - 1);
   __shared__ float2 sray[256];
   __shared__ int32_t sacc[256];
   __shared__ int32_t shit[STATS ? 256 : 1];
-  float ru[4], rv[4];
+  __shared__ float4 srec[kTestThreads][kRecF4];  // a chunk's records, for the wave-wide path
   bool valid[4];
-  int32_t racc[4];
-  int rhit[4];
   // Ray r = lane + 64 k sits in cell (ci_lo + lane % 16, cj_lo + lane / 16 + 4 k):
-  // its u draw has state rf.s0 + 2 ((i << 15) + j) GAMMA = z + 8 k GAMMA, where z
+  // its u draw has state s0 + 2 ((i << 15) + j) GAMMA = z + 8 k GAMMA, where z
   // is the lane's k = 0 state, and its v draw one GAMMA more.
   // With a jitter table (TAB) the two draws of every ray are read from it instead
   // (the same 24-bit values, computed once per key by jitter_table).
   const int i = ci_lo + (lane & 15);
   const uint32_t t0 = ((uint32_t)i << 15) + (uint32_t)(cj_lo + (lane >> 4));
-  const uint64_t z0 = rf.s0 + (uint64_t)t0 * (2ull * kGamma);
+  const uint64_t z0 = wi.s0 + (uint64_t)t0 * (2ull * kGamma);
   uint2 jq[4];
   if (TAB) {  // unconditional, clamped reads: the counters of outstanding loads stay exact
-    const uint2* jt = a.jitter + ((int64_t)rf.key * 3 + w) * (int64_t)a.R * a.R;
+    const uint2* jt = a.jitter + ((int64_t)wi.key * 3 + w) * (int64_t)a.R * a.R;
     const int ic = min(i, a.R - 1);
 #pragma unroll
     for (int k = 0; k < 4; ++k) jq[k] = jt[(int64_t)min(cj_lo + (lane >> 4) + 4 * k, a.R - 1) * a.R + ic];
@@ -1102,7 +1127,7 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
     const int r = lane + 64 * k;
     const int j = cj_lo + (r >> 4);
     valid[k] = i < a.R && j < a.R;
-    ru[k] = rv[k] = 0.f;
+    float ru = 0.f, rv = 0.f;
     if (valid[k]) {
       double xi, eta;
       if (TAB) {
@@ -1113,14 +1138,12 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
         xi = u24(mix64(zu));
         eta = u24(mix64(zu + kGamma));
       }
-      ru[k] = (float)__dadd_rn(-hu, __dmul_rn(__dadd_rn((double)i, xi), du));
-      rv[k] = (float)__dadd_rn(-hv, __dmul_rn(__dadd_rn((double)j, eta), dv));
+      ru = (float)__dadd_rn(-hu, __dmul_rn(__dadd_rn((double)i, xi), du));
+      rv = (float)__dadd_rn(-hv, __dmul_rn(__dadd_rn((double)j, eta), dv));
     }
-    sray[r] = make_float2(ru[k], rv[k]);
+    sray[r] = make_float2(ru, rv);
     sacc[r] = 0;
     if (STATS) shit[r] = 0;
-    racc[k] = 0;
-    rhit[k] = 0;
   };
   // The item's first kTestThreads records (contiguous, one 64-byte line each)
   // are requested before the rays are generated.  The load is unconditional
@@ -1160,54 +1183,62 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
         const int c0 = ci_lo + (int)(pk & 15u), c1 = ci_lo + (int)((pk >> 4) & 15u);
         const int d0 = cj_lo + (int)((pk >> 8) & 15u), d1 = cj_lo + (int)((pk >> 12) & 15u);
         const int cells = (c1 >= c0 && d1 >= d0) ? (c1 - c0 + 1) * (d1 - d0 + 1) : 0;
-        big = cells > kRasterCells;
+        big = cells > a.raster_cells;
         if (!big) {
           tests += cells;
-          for (int cj = d0; cj <= d1; ++cj)
-            for (int ci = c0; ci <= c1; ++ci) {
-              const int r = (ci - ci_lo) + 16 * (cj - cj_lo);
-              const float2 p = sray[r];
-              int32_t q;
-              if (ray_hit(p.x, p.y, q0, q1, q2, q3, q)) {
-                atomicAdd(&sacc[r], q);
-                if (STATS) atomicAdd(&shit[r], 1);
-              }
+          // one flat loop over the covered cells (row by row), so the wave runs
+          // as many iterations as its lane with the most cells
+          const int wdt = c1 - c0 + 1;
+          int r = (c0 - ci_lo) + 16 * (d0 - cj_lo), di = 0;
+          for (int t = 0; t < cells; ++t) {
+            const float2 p = sray[r];
+            int32_t q;
+            if (ray_hit(p.x, p.y, q0, q1, q2, q3, q)) {
+              atomicAdd(&sacc[r], q);
+              if (STATS) atomicAdd(&shit[r], 1);
             }
+            ++di;
+            const bool wrap = di == wdt;
+            r += wrap ? 17 - wdt : 1;
+            di = wrap ? 0 : di;
+          }
         }
       }
-      // records covering many cells: the whole wave, every lane its own rays
+      // records covering many cells: the whole wave, one covered cell per lane
+      // (the record read by every lane from LDS)
       uint64_t bm = __ballot(have && big);
+      if (bm) {
+        if (have) {
+          srec[lane][0] = q0;
+          srec[lane][1] = q1;
+          srec[lane][2] = q2;
+          srec[lane][3] = q3;
+        }
+        __syncthreads();
+      }
       while (bm) {
         const int src = __ffsll((long long)bm) - 1;
         bm &= bm - 1;
-        float4 s0, s1, s2, s3;
-        s0.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.x), src));
-        s0.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.y), src));
-        s0.z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.z), src));
-        s0.w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.w), src));
-        s1.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.x), src));
-        s1.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.y), src));
-        s1.z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.z), src));
-        s1.w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.w), src));
-        s2.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.x), src));
-        s2.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.y), src));
-        s2.z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.z), src));
-        s2.w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.w), src));
-        s3.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q3.x), src));
-        s3.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q3.y), src));
-        s3.z = 0.f;
-        s3.w = 0.f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        const float4 s0 = srec[src][0], s1 = srec[src][1], s2 = srec[src][2], s3 = srec[src][3];
+        const uint32_t pk = __float_as_uint(s3.w);
+        const int c0 = (int)(pk & 15u), d0 = (int)((pk >> 8) & 15u);
+        const int wdt = (int)((pk >> 4) & 15u) - c0 + 1, cells = wdt * ((int)((pk >> 12) & 15u) - d0 + 1);
+        // row of covered cell t: floor((t + 1/2) / wdt), exact for t < 256 with
+        // the approximate reciprocal
+        const float iw = __builtin_amdgcn_rcpf((float)wdt);
+        for (int t = lane; t < cells; t += kTestThreads) {
+          const int dj = (int)(((float)t + 0.5f) * iw), di = t - dj * wdt;
+          const int r = (c0 + di) + 16 * (d0 + dj);
+          const float2 p = sray[r];
           int32_t q;
-          const bool in = ray_hit(ru[k], rv[k], s0, s1, s2, s3, q);
-          if (valid[k] && in) {
-            racc[k] += q;
-            if (STATS) ++rhit[k];
+          if (ray_hit(p.x, p.y, s0, s1, s2, s3, q)) {
+            atomicAdd(&sacc[r], q);
+            if (STATS) atomicAdd(&shit[r], 1);
           }
         }
-        tests += lane == 0 ? (int64_t)(ci_hi - ci_lo + 1) * (cj_hi - cj_lo + 1) : 0;
+        tests += lane == 0 ? (int64_t)cells : 0;
       }
+      if (base + kTestThreads < k1) __syncthreads();  // srec is rewritten by the next chunk
     }
   }
   __syncthreads();
@@ -1216,13 +1247,13 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
   for (int k = 0; k < 4; ++k) {
     if (!valid[k]) continue;
     const int r = lane + 64 * k;
-    const int32_t q = sacc[r] + racc[k];
+    const int32_t q = sacc[r];
     lane_sum += q;
     if (STATS) {
       const int i = ci_lo + (r & 15), j = cj_lo + (r >> 4);
       const int64_t o = ((int64_t)bw * a.R + i) * a.R + j;
       if (a.ray_q) atomicAdd(&a.ray_q[o], q);
-      if (a.ray_hits) atomicAdd(&a.ray_hits[o], shit[r] + rhit[k]);
+      if (a.ray_hits) atomicAdd(&a.ray_hits[o], shit[r]);
     }
   }
 #pragma unroll
@@ -1353,6 +1384,7 @@ namespace {
 
 bool test_raster_choice();
 int test_chunk_choice();
+int raster_cells_choice();
 
 template <int TE>
 int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hipStream_t s) {
@@ -1398,6 +1430,17 @@ int test_chunk_choice() {
     if (c >= 64 && c <= 4096 && c % 64 == 0) return c;
   }
   return kTestChunk;
+}
+
+// Cells above which a record of a tile is tested by the whole wave:
+// kRasterCells, or OBBV_RASTER_CELLS (0..256) to compare thresholds on a device.
+int raster_cells_choice() {
+  const char* e = getenv("OBBV_RASTER_CELLS");
+  if (e && *e) {
+    const int c = atoi(e);
+    if (c >= 0 && c <= 256) return c;
+  }
+  return kRasterCells;
 }
 
 bool test_stage_choice() {
@@ -1667,17 +1710,17 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       recs_v = ex->recs;
     else
       OBBV_RET(pool_get(pool_base + kPoolRecords, (size_t)std::max<int64_t>(n_bin, 1) * kRecBytes, &recs_v));
-    int4* itile = nullptr;
+    WorkItem* itile = nullptr;
     if (fixed) {
       itile = ex->itile;
     } else {
       void* tv = nullptr;
-      OBBV_RET(pool_get(pool_base + kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * sizeof(int4), &tv));
-      itile = (int4*)tv;
+      OBBV_RET(pool_get(pool_base + kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * sizeof(WorkItem), &tv));
+      itile = (WorkItem*)tv;
     }
     hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
                        d_reccnt, (const int32_t*)d_ioff, d_binoff, d_bincur, (float4*)recs_v,
-                       (const int64_t*)d_chunkoff, nbw * TT, n_items > 0 ? itile : (int4*)nullptr, n_items, chunk);
+                       (const int64_t*)d_chunkoff, nbw * TT, n_items > 0 ? itile : (WorkItem*)nullptr, n_items, chunk);
     OBBV_HIP(hipGetLastError());
     TestArgs ta;
     ta.boxes = boxes;
@@ -1686,6 +1729,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     ta.chunk_off = d_chunkoff;
     ta.n_tiles = nbw * TT;
     ta.chunk = chunk;
+    ta.raster_cells = raster_cells_choice();
     ta.recs = (const float4*)recs_v;
     ta.acc = d_acc;
     ta.ray_q = out_ray_q;
@@ -1695,9 +1739,8 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     ta.side = d_side;
     ta.bin_cap = fixed ? ex->bin_cap : INT64_MAX;
     ta.item_cap = fixed ? ex->item_cap : INT64_MAX;
-    ta.item_tile = itile;
+    ta.items = itile;
     ta.persistent = fixed ? 1 : 0;
-    ta.rframe = d_rframe;
     ta.jitter = ex && ex->jitter && R == ex->jitter_R && params->seed == ex->jitter_seed ? ex->jitter : nullptr;
     void* prof_token = nullptr;
     if (profiling_enabled() && !planned) {
@@ -2038,7 +2081,7 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   ex.item_cap = (int64_t)std::ceil((double)probe.n_items * headroom) + 64;
   ex.items_cap = probe.items_bytes;
   const size_t bytes = align_up(ex.meta_cap) + align_up((size_t)ex.bin_cap * kRecBytes) + align_up(ex.items_cap) +
-                       align_up((size_t)ex.item_cap * sizeof(int4));
+                       align_up((size_t)ex.item_cap * sizeof(WorkItem));
   if (hipMalloc(&P->alloc, bytes) != hipSuccess) {
     (void)hipGetLastError();
     set_error("hipMalloc of the planned scratch failed");
@@ -2048,7 +2091,7 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   ex.meta = (char*)P->alloc;
   ex.recs = (float4*)(ex.meta + align_up(ex.meta_cap));
   ex.items = (char*)ex.recs + align_up((size_t)ex.bin_cap * kRecBytes);
-  ex.itile = (int4*)(ex.items + align_up(ex.items_cap));
+  ex.itile = (WorkItem*)(ex.items + align_up(ex.items_cap));
   // the mesh table lives at the start of the meta block (outside the graph)
   std::vector<MeshDev> mh((size_t)n_meshes);
   for (int m = 0; m < n_meshes; ++m)
