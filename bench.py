@@ -44,17 +44,17 @@ SEED_MESH = 21
 # HBM traffic of the ray-test kernel per launch on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE, over the ray-test dispatches of one build),
 # each scaled by the same counter's reading for a plain device copy of known size.
-# Valid only for the kernel source it was measured on: the hash covers the
-# ray-test kernel's code (from kRasterCells to the end of k_raster); any change
-# there reports null until the counters are re-taken.
+# Valid only for the sources it was measured on: the hash covers the whole of
+# the outer-volume source and its shared header (the kernel, the pass that
+# writes its records and work items, their layouts); any change there reports
+# null until the counters are re-taken.
 K_TEST_TRAFFIC = {
     "source_sha256": "840cb51208d8af72fdf55e90f25112eedfdbacc48f1446ff3f57eeb81b8f79ab",
     "fetch_bytes_per_launch": 99819415,   # 48,741.554 KiB raw x 1.99993 (copy calibration)
     "write_bytes_per_launch": 560807,     # 547.663 KiB raw x 1.0
     "profile": "profiles/ray_test_torus_hierarchy_traffic.md",
 }
-RASTER_BEGIN = "constexpr int kRasterCells = 16;"
-RASTER_END = "__global__ void k_or_word("
+RASTER_SOURCES = ("outer_volume.hip", "common.h")
 
 
 def log(msg):
@@ -62,14 +62,11 @@ def log(msg):
 
 
 def raster_source_sha256():
-    src = os.path.join(ROOT, "paper_2203_10521_amd", "csrc", "outer_volume.hip")
-    with open(src) as f:
-        text = f.read()
-    try:
-        region = text[text.index(RASTER_BEGIN):text.index(RASTER_END)]
-    except ValueError:
-        return None
-    return hashlib.sha256(region.encode()).hexdigest()
+    h = hashlib.sha256()
+    for name in RASTER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2203_10521_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def traffic_bytes():
