@@ -262,6 +262,7 @@ struct CullArgs {
   int tpe;  // tiles per face edge
   uint32_t axis_mask;
   uint32_t* status;
+  int write_lds;    // write pass: bin slots reserved per tile in LDS (1) or taken one by one (0)
   int64_t rec_cap;  // records and bin entries a planned launch was sized for
   int64_t bin_cap;
   // nullable: the triangles a box can see, one list per shared frame, held as
@@ -664,6 +665,58 @@ k_tiles_scan_top(int64_t* __restrict__ bsum, int64_t nb, int64_t n, int64_t* __r
   if (threadIdx.x == 0) rec_off[nbw] = orr;
 }
 
+// The same offsets for up to kTilesScanOne tiles in one workgroup (one launch
+// instead of three): the counts are staged in LDS (coalesced loads), every
+// thread sums a run of consecutive tiles, one block scan of the run sums, then
+// every thread writes its run's offsets; then the record offsets of the
+// (box, axis) pairs.
+constexpr int kTilesScanOne = 16 * 1024;
+
+__global__ void __launch_bounds__(kScanBlockThreads)
+k_tiles_scan_one(const int32_t* __restrict__ cnt, int64_t n, int chunk, int64_t* __restrict__ bin_off,
+                 int64_t* __restrict__ chunk_off, const int32_t* __restrict__ rec_cnt, int64_t nbw,
+                 int64_t* __restrict__ rec_off) {
+  __shared__ long long wsum[kScanBlockThreads / 64];
+  __shared__ int32_t scnt[kTilesScanOne];
+#pragma unroll
+  for (int k = 0; k < kTilesScanOne / kScanBlockThreads; ++k) {
+    const int i = (int)threadIdx.x + k * kScanBlockThreads;
+    scnt[i] = i < n ? cnt[i] : 0;
+  }
+  __syncthreads();
+  const int per = (int)((n + kScanBlockThreads - 1) / kScanBlockThreads);
+  const int i0 = min((int)threadIdx.x * per, (int)n), i1 = min(i0 + per, (int)n);
+  long long sb = 0, sc = 0;
+  for (int i = i0; i < i1; ++i) {
+    const int c = scnt[i];
+    sb += c;
+    sc += (c + chunk - 1) / chunk;
+  }
+  long long tb = 0, tc = 0;
+  long long ob = block_excl_scan(sb, wsum, tb);
+  long long oc = block_excl_scan(sc, wsum, tc);
+  for (int i = i0; i < i1; ++i) {
+    const int c = scnt[i];
+    bin_off[i] = ob;
+    chunk_off[i] = oc;
+    ob += c;
+    oc += (c + chunk - 1) / chunk;
+  }
+  if (threadIdx.x == 0) {
+    bin_off[n] = tb;
+    chunk_off[n] = tc;
+  }
+  long long orr = 0;
+  for (int64_t j0 = 0; j0 < nbw; j0 += kScanBlockThreads) {
+    const int64_t j = j0 + threadIdx.x;
+    long long t = 0;
+    const long long e = block_excl_scan(j < nbw ? rec_cnt[j] : 0, wsum, t);
+    if (j < nbw) rec_off[j] = orr + e;
+    orr += t;
+  }
+  if (threadIdx.x == 0) rec_off[nbw] = orr;
+}
+
 __global__ void __launch_bounds__(kScanBlockThreads)
 k_tiles_scan_add(int64_t n, const int64_t* __restrict__ bsum, int64_t* __restrict__ bin_off,
                  int64_t* __restrict__ chunk_off) {
@@ -787,7 +840,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
   __shared__ int32_t wc[kCullWaves][3];
   const int64_t total = a.chunk_off[a.n_boxes];
   const int TT = a.tpe * a.tpe;
-  const bool lds = 3 * TT <= kLdsTiles;
+  const bool lds = a.write_lds && 3 * TT <= kLdsTiles;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item_box(a.chunk_off, a.n_boxes, item);
@@ -1385,6 +1438,7 @@ namespace {
 bool test_raster_choice();
 int test_chunk_choice();
 int raster_cells_choice();
+int write_lds_choice();
 
 template <int TE>
 int launch_test(const TestArgs& ta, int64_t nblocks, bool stats, bool stage, hipStream_t s) {
@@ -1441,6 +1495,14 @@ int raster_cells_choice() {
     if (c >= 0 && c <= 256) return c;
   }
   return kRasterCells;
+}
+
+// Write pass bin slots: 1 = per-tile ranges reserved from LDS counts (default),
+// 0 = one global atomic per entry.  OBBV_WRITE_LDS overrides it.
+int write_lds_choice() {
+  const char* e = getenv("OBBV_WRITE_LDS");
+  if (e && *e) return atoi(e) != 0;
+  return 1;
 }
 
 bool test_stage_choice() {
@@ -1626,6 +1688,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   OBBV_HIP(hipGetLastError());
 
   CullArgs ca;
+  ca.write_lds = write_lds_choice();
   ca.boxes = boxes;
   ca.box_mesh = box_mesh;
   ca.meshes = d_meshes;
@@ -1663,7 +1726,11 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   OBBV_HIP(hipGetLastError());
   // bin and work-item offsets of the tiles, record offsets of the (box, axis) pairs
   const int chunk = test_chunk_choice();
-  {
+  if (nbw * TT <= kTilesScanOne) {
+    hipLaunchKernelGGL(k_tiles_scan_one, dim3(1), dim3(kScanBlockThreads), 0, s, (const int32_t*)d_tilecnt, nbw * TT,
+                       chunk, d_binoff, d_chunkoff, (const int32_t*)d_reccnt, nbw, d_recoff);
+    OBBV_HIP(hipGetLastError());
+  } else {
     const int64_t nt_all = nbw * TT;
     const int64_t nb = ceil_div(nt_all, kScanBlockThreads);
     int64_t* bsum = (int64_t*)d_scan;
