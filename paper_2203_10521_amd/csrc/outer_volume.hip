@@ -560,8 +560,9 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt, int32_t* __restrict__ t
 }
 
 // One wave per (box, cast axis): the triangle counts of both half prisms, the
-// side with fewer triangles (mirror flag), its record count, and every item's
-// first record within the (box, axis) (exclusive scan over the box's items).
+// side with fewer triangles (mirror flag), its record count, and (item_off
+// non-null) every item's first record within the (box, axis) (exclusive scan
+// over the box's items).
 __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, const int32_t* __restrict__ item_cnt,
                             int32_t* __restrict__ side, int32_t* __restrict__ rec_cnt,
                             int32_t* __restrict__ item_off, int TT, int32_t* __restrict__ tile_cnt,
@@ -597,6 +598,7 @@ __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, 
     tc[k] = 0;
     tc[TT + k] = 0;
   }
+  if (!item_off) return;
   int base = 0;
   for (int64_t i = i0; i < i1; i += 64) {
     const int v = i + lane < i1 ? item_cnt[6 * (i + lane) + 2 * w + mirror] : 0;
@@ -806,11 +808,9 @@ __device__ inline uint32_t pack_cells(int i0, int i1, int j0, int j1, int ci, in
 // not matter: the ray sums are exact integers).  Every entry holds its own copy
 // of the record, with the cell range inside its tile.
 __global__ void __launch_bounds__(kCullThreads)
-k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict__ rec_off,
-        const int32_t* __restrict__ rec_cnt, const int32_t* __restrict__ item_off,
-        const int64_t* __restrict__ bin_off, int32_t* __restrict__ bin_cur, float4* __restrict__ recs,
-        const int64_t* __restrict__ chunk_off, int64_t n_tiles, WorkItem* __restrict__ items, int64_t item_cap,
-        int chunk) {
+k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict__ bin_off,
+        int32_t* __restrict__ bin_cur, float4* __restrict__ recs, const int64_t* __restrict__ chunk_off,
+        int64_t n_tiles, WorkItem* __restrict__ items, int64_t item_cap, int chunk) {
   if (items) {  // the ray-test work items (grid-stride over the tiles)
     const int TT = a.tpe * a.tpe;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles;
@@ -835,12 +835,15 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
       }
     }
   }
-  __shared__ int32_t cnt[kLdsTiles];
-  __shared__ int32_t base_pos[kLdsTiles];
-  __shared__ int32_t wc[kCullWaves][3];
-  const int64_t total = a.chunk_off[a.n_boxes];
+  // per tile of the item's box (3 TT, dynamic LDS when lds): first bin entry
+  // reserved for the item, end of the tile's bin, entries taken so far
+  extern __shared__ __align__(8) char wdyn[];
   const int TT = a.tpe * a.tpe;
   const bool lds = a.write_lds && 3 * TT <= kLdsTiles;
+  int64_t* base_k = reinterpret_cast<int64_t*>(wdyn);
+  int64_t* lim_k = base_k + 3 * TT;
+  int32_t* cnt = reinterpret_cast<int32_t*>(lim_k + 3 * TT);
+  const int64_t total = a.chunk_off[a.n_boxes];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item_box(a.chunk_off, a.n_boxes, item);
@@ -870,40 +873,30 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
         }
       }
       keepmask |= keep ? (1u << w) : 0u;
-      const uint64_t m = __ballot(keep);
-      if (lane == 0) wc[wave][w] = (int)__popcll(m);
     }
     __syncthreads();
     if (lds) {
-      // reserve one range per non-zero tile
+      // reserve one range per non-zero tile, with the tile's bin start and end
       for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) {
         const int c = cnt[k];
-        base_pos[k] = c ? atomicAdd(&bin_cur[(int64_t)(b * 3 + k / TT) * TT + (k % TT)], c) : 0;
+        if (c) {
+          const int64_t tl = (int64_t)(b * 3 + k / TT) * TT + (k % TT);
+          base_k[k] = bin_off[tl] + atomicAdd(&bin_cur[tl], c);
+          lim_k[k] = bin_off[tl + 1];
+        }
         cnt[k] = 0;
       }
       __syncthreads();
     }
-    // pass 2: records at their deterministic slots, bin entries
+    // pass 2: a record copy per bin entry
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       const bool keep = (keepmask >> w) & 1u;
-      const uint64_t m = __ballot(keep);
       if (!keep) continue;
       const int bw = b * 3 + w;
       const bool mirror = side[bw] != 0;
       const CastFrame f = cast_frame_rf(B, w, a.rframe[b * 3 + w]);
       const CastTri tr = cast_tri(P, w, f, mirror);
-      int rank = item_off[3 * item + w] + (int)__popcll(m & ((1ull << lane) - 1ull));
-      for (int v = 0; v < wave; ++v) rank += wc[v][w];
-      if (rank >= rec_cnt[bw]) {  // count and write passes disagree: never expected
-        atomicOr(a.status, OBBV_STATUS_BAD_INDEX);
-        continue;
-      }
-      const int64_t slot = rec_off[bw] + rank;
-      if (slot >= a.rec_cap) {  // more records than a planned launch was sized for
-        atomicOr(a.status, OBBV_STATUS_OVERFLOW);
-        continue;
-      }
       float4 rec[kRecF4];
       make_record(tr, mirror, f.hw, rec);
       int i0, i1, j0, j1;
@@ -914,11 +907,17 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
         for (int ti = ti0; ti <= ti1; ++ti) {
           const int64_t tl = tbase + tj * a.tpe + ti;
           const int lt = w * TT + tj * a.tpe + ti;
-          const int pos = lds ? base_pos[lt] + atomicAdd(&cnt[lt], 1) : atomicAdd(&bin_cur[tl], 1);
-          const int64_t k = bin_off[tl] + pos;
+          int64_t k, lim;
+          if (lds) {
+            k = base_k[lt] + atomicAdd(&cnt[lt], 1);
+            lim = lim_k[lt];
+          } else {
+            k = bin_off[tl] + atomicAdd(&bin_cur[tl], 1);
+            lim = bin_off[tl + 1];
+          }
           if (k >= a.bin_cap) {
             atomicOr(a.status, OBBV_STATUS_OVERFLOW);
-          } else if (k < bin_off[tl + 1]) {
+          } else if (k < lim) {
             float4* o = recs + kRecF4 * k;
             o[0] = rec[0];
             o[1] = rec[1];
@@ -930,7 +929,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
           }
         }
     }
-    __syncthreads();  // cnt / base_pos / wc are reused by the next item
+    __syncthreads();  // the LDS tile arrays are reused by the next item
   }
 }
 
@@ -1721,7 +1720,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   hipLaunchKernelGGL(k_cull_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_icnt, d_tc2);
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_box_sides, dim3(ceil_div(nbw, kCullWaves)), dim3(kCullThreads), 0, s,
-                     (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, d_ioff, (int)TT,
+                     (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, (int32_t*)nullptr, (int)TT,
                      d_tilecnt, d_bincur, d_acc, d_tc2);
   OBBV_HIP(hipGetLastError());
   // bin and work-item offsets of the tiles, record offsets of the (box, axis) pairs
@@ -1785,9 +1784,10 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
       OBBV_RET(pool_get(pool_base + kPoolTiles, (size_t)std::max<int64_t>(n_items, 1) * sizeof(WorkItem), &tv));
       itile = (WorkItem*)tv;
     }
-    hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_side, d_recoff,
-                       d_reccnt, (const int32_t*)d_ioff, d_binoff, d_bincur, (float4*)recs_v,
-                       (const int64_t*)d_chunkoff, nbw * TT, n_items > 0 ? itile : (WorkItem*)nullptr, n_items, chunk);
+    const size_t write_lds = ca.write_lds && 3 * TT <= kLdsTiles ? (size_t)(3 * TT) * 20 : 0;
+    hipLaunchKernelGGL(k_write, dim3(cull_grid), dim3(kCullThreads), write_lds, s, ca, d_side, d_binoff, d_bincur,
+                       (float4*)recs_v, (const int64_t*)d_chunkoff, nbw * TT,
+                       n_items > 0 ? itile : (WorkItem*)nullptr, n_items, chunk);
     OBBV_HIP(hipGetLastError());
     TestArgs ta;
     ta.boxes = boxes;
