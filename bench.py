@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("box outer-volume evals/s + ray-tri tests/s (% FP32 peak); "
           "Lloyd moves/s surrogate vs exact")
 FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBPS = 8000.0
 FLOP_PER_TEST = 16          # 3 edge functions x 2 FMA + depth plane 2 FMA
 HIER = dict(levels=4, branching=4, iters=20, sweeps=2, R=128, seed=23, pops_per_round=32)
 SEED_MESH = 21
@@ -49,9 +50,9 @@ SEED_MESH = 21
 # writes its records and work items, their layouts); any change there reports
 # null until the counters are re-taken.
 K_TEST_TRAFFIC = {
-    "source_sha256": "840cb51208d8af72fdf55e90f25112eedfdbacc48f1446ff3f57eeb81b8f79ab",
-    "fetch_bytes_per_launch": 99819415,   # 48,741.554 KiB raw x 1.99993 (copy calibration)
-    "write_bytes_per_launch": 560807,     # 547.663 KiB raw x 1.0
+    "source_sha256": "61a7ed744fef91dae2f7037c305751321436e4c05ecc88ede8a458e44bc9f73f",
+    "fetch_bytes_per_launch": 79453949,   # 38,797.129 KiB raw x 1.99993 (copy calibration)
+    "write_bytes_per_launch": 844851,     # 825.050 KiB raw x 1.0
     "profile": "profiles/ray_test_torus_hierarchy_traffic.md",
 }
 RASTER_SOURCES = ("outer_volume.hip", "common.h")
@@ -75,11 +76,14 @@ def traffic_bytes():
     return K_TEST_TRAFFIC["fetch_bytes_per_launch"] + K_TEST_TRAFFIC["write_bytes_per_launch"]
 
 
-def roofline(test_ms, launches, tests):
+def roofline(test_ms, launches, tests, nbytes=0):
+    """Average ray-test launch (ms), tests per launch, their FP32 rate (TFLOP/s)
+    and the algorithmic bytes the launch reads, as a rate (GB/s)."""
     avg_ms = test_ms / max(launches, 1)
     per_launch = tests / max(launches, 1)
     achieved = per_launch * FLOP_PER_TEST / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    return avg_ms, per_launch, achieved
+    gbps = nbytes / max(launches, 1) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return avg_ms, per_launch, achieved, gbps
 
 
 def saturated(api, torch, Vt, Ft, boxes, R, seed):
@@ -99,12 +103,13 @@ def saturated(api, torch, Vt, Ft, boxes, R, seed):
         api.outer_volume(Vt, Ft, Bt, R, seed=seed)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms, n, tests = api.profile_read()
+    ms, n, tests, nbytes = api.profile_read()
     api.profile_enable(False)
-    avg_ms, per_launch, achieved = roofline(ms, n, tests)
+    avg_ms, per_launch, achieved, gbps = roofline(ms, n, tests, nbytes)
     return {"n_boxes": int(len(B)), "evals_per_s": len(B) * reps / dt, "k_test_avg_ms": avg_ms,
             "tests_per_launch": per_launch, "tests_per_s": tests / (ms * 1e-3),
-            "achieved_tflops": achieved, "frac": achieved / FP32_PEAK_TFLOPS}
+            "bytes_per_launch": nbytes / max(n, 1), "achieved_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
+            "achieved_tflops": achieved, "fp32_frac": achieved / FP32_PEAK_TFLOPS}
 
 
 def surrogate_comparison(api, torch, Vt, Ft, hp, exact, judge_every=(32,)):
@@ -226,9 +231,9 @@ def main():
         log(f"timed step done: {out['counters']['evals']} evaluations")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    test_ms, launches, tests = api.profile_read()
+    test_ms, launches, tests, nbytes = api.profile_read()
     api.profile_enable(False)
-    avg_ms, per_launch, achieved = roofline(test_ms, launches, tests)
+    avg_ms, per_launch, achieved, gbps = roofline(test_ms, launches, tests, nbytes)
 
     result = {
         "metric": METRIC,
@@ -256,8 +261,14 @@ def main():
         "k_test_avg_ms": avg_ms,
         "k_test_launches": launches,
         "tests_per_launch": per_launch,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic_bytes()},
+        # the ray-test kernel's algorithmic intensity (16 FLOP per test over the
+        # bytes it must read) is far below the ridge (157.3 TFLOP/s / 8 TB/s):
+        # the memory roof bounds it; its FP32 rate is reported beside it
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": gbps / HBM_PEAK_GBPS, "traffic": traffic_bytes(),
+                     "bytes_per_launch": nbytes / max(launches, 1),
+                     "flop_per_byte": per_launch * FLOP_PER_TEST / max(nbytes / max(launches, 1), 1.0)},
+        "fp32": {"achieved_tflops": achieved, "peak_tflops": FP32_PEAK_TFLOPS, "frac": achieved / FP32_PEAK_TFLOPS},
     }
     log(f"hierarchy: {evals / dt:.0f} evals/s, k_test {avg_ms:.4f} ms avg over {launches} launches")
     if not args.no_surrogate:

@@ -169,15 +169,18 @@ int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, cons
 /* ---- measurement ----------------------------------------------------------- */
 
 /* Host.  enable != 0: every later obbv_outer_volume* call records a pair of HIP
- * events around its ray-test kernel (k_test) on the call's stream and adds the
- * number of ray-triangle tests it performs (rays x binned triangles of each
- * tile) to a device counter.  enable == 0 stops recording. */
+ * events around its ray-test kernel on the call's stream and adds to device
+ * counters the ray-triangle tests it performs (a triangle's record against the
+ * rays of the cells its conservative cell range covers in a tile; every ray of
+ * the tile in the all-rays kernel) and the bytes it must read (a 64-byte work
+ * item per tile chunk, a 64-byte record per bin entry, and with a jitter table
+ * 8 bytes per ray of the item's tile).  enable == 0 stops recording. */
 int obbv_profile_enable(int enable);
 
-/* Synchronous.  Sums the elapsed time of the recorded k_test launches and
- * returns it with the launch count and the test count, then clears the record.
- * Outputs are host pointers, each nullable. */
-int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests);
+/* Synchronous.  Sums the elapsed time of the recorded ray-test launches and
+ * returns it with the launch count, the test count and the byte count, then
+ * clears the record.  Outputs are host pointers, each nullable. */
+int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests, int64_t* out_bytes);
 
 /* ---- planned (graph-replayed) evaluations ------------------------------------ */
 

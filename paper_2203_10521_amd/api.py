@@ -158,17 +158,20 @@ def fit(V, F, tri_cluster, n_clusters, stream=None):
 
 
 def profile_enable(enable=True):
-    """Record HIP events around every later ray-test kernel launch (and count its tests)."""
+    """Record HIP events around every later ray-test kernel launch (and count its
+    tests and the bytes it must read)."""
     _check(_lib.lib().obbv_profile_enable(1 if enable else 0))
 
 
 def profile_read():
-    """(total k_test milliseconds, launches, ray-triangle tests) since the last read."""
+    """(total ray-test milliseconds, launches, ray-triangle tests, algorithmic
+    bytes read) since the last read."""
     ms = ctypes.c_double(0.0)
     n = ctypes.c_int64(0)
     t = ctypes.c_int64(0)
-    _check(_lib.lib().obbv_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(t)))
-    return ms.value, n.value, t.value
+    b = ctypes.c_int64(0)
+    _check(_lib.lib().obbv_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(t), ctypes.byref(b)))
+    return ms.value, n.value, t.value, b.value
 
 
 def _host_ptr(a):

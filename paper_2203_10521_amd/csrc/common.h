@@ -123,8 +123,9 @@ int status_word(uint32_t** out);   // device pointer of this device's status wor
 
 // measurement hooks (obbv_profile_enable / obbv_profile_read)
 bool profiling_enabled();
-// device test counter: kProfSlots slots whose sum is the count; a wave adds to
-// one slot, so the waves of a launch do not serialise on one address
+// device counters: tests in slots [0, kProfSlots), bytes in [kProfSlots,
+// 2 kProfSlots); a count is the sum of its slots, and a wave adds to one slot,
+// so the waves of a launch do not serialise on one address
 constexpr int kProfSlots = 256;
 int profile_counter(unsigned long long** out);
 int profile_record_begin(hipStream_t s, void** token);            // event before k_test

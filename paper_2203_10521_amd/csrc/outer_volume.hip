@@ -944,7 +944,7 @@ struct TestArgs {
   unsigned long long* acc;  // [nbw] per-(box, axis) sum of q
   int32_t* ray_q;           // nullable [nbw][R][R]
   int32_t* ray_hits;        // nullable [nbw][R][R]
-  unsigned long long* test_counter;  // nullable [kProfSlots]: += ray-triangle tests (slot item % kProfSlots)
+  unsigned long long* test_counter;  // nullable [2 kProfSlots]: tests, bytes (slot item % kProfSlots)
   float* occ;                        // nullable [n_boxes][8][8][8]: sub-slab inside fractions (R = 8, axis 2)
   const int32_t* side;               // [nbw] mirrored cast flags
   uint64_t seed;
@@ -1074,6 +1074,8 @@ __device__ void test_item(const TestArgs& a, const int64_t item) {
   if (a.test_counter && lane == 0) {
     const int ni = min(TE, a.R - ti * TE), nj = min(TE, a.R - tj * TE);
     atomicAdd(&a.test_counter[item & (kProfSlots - 1)], (unsigned long long)((k1 - k0) * (int64_t)(ni * nj)));
+    atomicAdd(&a.test_counter[kProfSlots + (item & (kProfSlots - 1))],
+              (unsigned long long)(kRecBytes * (k1 - k0) + (int64_t)sizeof(WorkItem)));
   }
   int64_t lane_sum = 0;
 #pragma unroll
@@ -1314,7 +1316,12 @@ __device__ void raster_item(const TestArgs& a, const int64_t item) {
     tests += __shfl_xor(tests, off);
   }
   if (lane == 0 && lane_sum != 0) atomicAdd(&a.acc[bw], (unsigned long long)lane_sum);
-  if (lane == 0 && a.test_counter) atomicAdd(&a.test_counter[item & (kProfSlots - 1)], (unsigned long long)tests);
+  if (lane == 0 && a.test_counter) {
+    atomicAdd(&a.test_counter[item & (kProfSlots - 1)], (unsigned long long)tests);
+    atomicAdd(&a.test_counter[kProfSlots + (item & (kProfSlots - 1))],
+              (unsigned long long)(kRecBytes * (k1 - k0) + (int64_t)sizeof(WorkItem) +
+                                   (TAB ? 8 * min(16, a.R - ci_lo) * min(16, a.R - cj_lo) : 0)));
+  }
 }
 
 template <bool STATS, bool TAB>

@@ -211,7 +211,7 @@ struct ProfState {
   bool enabled = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   std::vector<hipEvent_t> spare;  // events of earlier reads, reused
-  unsigned long long* counter = nullptr;  // [kProfSlots]
+  unsigned long long* counter = nullptr;  // [2 kProfSlots]
   int counter_dev = -1;
 };
 ProfState g_prof;
@@ -226,8 +226,8 @@ int profile_counter(unsigned long long** out) {
   OBBV_HIP(hipGetDevice(&dev));
   if (!g_prof.counter || g_prof.counter_dev != dev) {
     void* q = nullptr;
-    OBBV_HIP(hipMalloc(&q, kProfSlots * 8));
-    OBBV_HIP(hipMemset(q, 0, kProfSlots * 8));
+    OBBV_HIP(hipMalloc(&q, 2 * kProfSlots * 8));
+    OBBV_HIP(hipMemset(q, 0, 2 * kProfSlots * 8));
     g_prof.counter = (unsigned long long*)q;
     g_prof.counter_dev = dev;
   }
@@ -280,7 +280,8 @@ extern "C" int obbv_profile_enable(int enable) {
   return OBBV_OK;
 }
 
-extern "C" int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests) {
+extern "C" int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests,
+                                 int64_t* out_bytes) {
   clear_error();
   std::lock_guard<std::mutex> lock(g_prof_mutex);
   double total = 0.0;
@@ -294,17 +295,21 @@ extern "C" int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int
   }
   const int64_t n = (int64_t)g_prof.events.size();
   g_prof.events.clear();
-  unsigned long long tests = 0;
+  unsigned long long tests = 0, bytes = 0;
   if (g_prof.counter) {
     OBBV_HIP(hipDeviceSynchronize());
-    unsigned long long slots[kProfSlots];
+    unsigned long long slots[2 * kProfSlots];
     OBBV_HIP(hipMemcpy(slots, g_prof.counter, sizeof(slots), hipMemcpyDeviceToHost));
-    for (int k = 0; k < kProfSlots; ++k) tests += slots[k];
+    for (int k = 0; k < kProfSlots; ++k) {
+      tests += slots[k];
+      bytes += slots[kProfSlots + k];
+    }
     OBBV_HIP(hipMemset(g_prof.counter, 0, sizeof(slots)));
   }
   if (out_test_ms) *out_test_ms = total;
   if (out_launches) *out_launches = n;
   if (out_tests) *out_tests = (int64_t)tests;
+  if (out_bytes) *out_bytes = (int64_t)bytes;
   return OBBV_OK;
 }
 
