@@ -216,14 +216,19 @@ constexpr int kRowThreads = 512;
 // `pre` runs before any weight is requested (a stage whose own loads should
 // return first issues them there); kLateW2: the second layer's weights are
 // requested after the rows are staged (a stage that holds many registers of
-// its own), else with the first layer's.  The tile's outputs are f[row0 + t] for
-// t < rows.
-template <bool kLateW2 = false, class Stage, class Pre>
+// its own), else with the first layer's.  kOneRow: only row 0 of the tile is a
+// real row (the other rows' values are never written out, so they are left
+// uncomputed where the layers allow; row 0 takes the same arithmetic).  The
+// tile's outputs are f[row0 + t] for t < rows.
+template <bool kLateW2 = false, bool kOneRow = false, class Stage, class Pre>
 __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ W, Stage stage, Pre pre, short* sx,
                          short* sh1, float* zp, const float* socc, int64_t row0, int rows, float* __restrict__ f) {
   pre();
   __builtin_amdgcn_sched_barrier(0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = 32 * wave + (lane & 31);
+  // this lane's biases and head weight, requested with the weights
+  const float bias1 = P[ob1 + c], bias2 = P[ob2 + c], w3 = bf(P[ow3 + c]), bias3 = P[ob3];
   const int r = lane & 31, kq = (lane >> 5) * 8;
   // this wave's operands: K-step k of lane l at v8s index (wave (K / 16) + k) 64 + l
   const v8s* w1 = reinterpret_cast<const v8s*>(W) + (int64_t)wave * (kIn / 16) * 64 + lane;
@@ -239,7 +244,6 @@ __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ 
     for (int k = 0; k < kH / 16; ++k) b2[k] = w2[64 * k];
     __builtin_amdgcn_sched_barrier(0);
   }
-  const int c = 32 * wave + (lane & 31);
   {
     v16f acc;
     for (int i = 0; i < 16; ++i) acc[i] = 0.f;
@@ -247,10 +251,13 @@ __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ 
       const v8s x = *reinterpret_cast<const v8s*>(&sx[r * kInPitch + 16 * k + kq]);
       acc = mfma16(x, b1[k], acc);
     }
-    const float bias = P[ob1 + c];
-    for (int rr = 0; rr < 16; ++rr) {
-      const int row = 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4);
-      sh1[row * kHPitch + c] = f2bf(fmaxf(acc[rr] + bias, 0.f));
+    if (kOneRow) {
+      if (lane < 32) sh1[c] = f2bf(fmaxf(acc[0] + bias1, 0.f));
+    } else {
+      for (int rr = 0; rr < 16; ++rr) {
+        const int row = 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4);
+        sh1[row * kHPitch + c] = f2bf(fmaxf(acc[rr] + bias1, 0.f));
+      }
     }
   }
   __syncthreads();
@@ -260,18 +267,23 @@ __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ 
     const v8s h = *reinterpret_cast<const v8s*>(&sh1[r * kHPitch + 16 * k + kq]);
     acc = mfma16(h, b2[k], acc);
   }
-  const float bias = P[ob2 + c], w3 = bf(P[ow3 + c]);
-  float v[16];
-  for (int rr = 0; rr < 16; ++rr) v[rr] = bf(fmaxf(acc[rr] + bias, 0.f)) * w3;
-  for (int o = 1; o < 32; o <<= 1)
-    for (int rr = 0; rr < 16; ++rr) v[rr] += __shfl_xor(v[rr], o, 64);
-  if ((lane & 31) == 0)
-    for (int rr = 0; rr < 16; ++rr) zp[wave * kFusedRows + 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4)] = v[rr];
+  if (kOneRow) {  // row 0 sits in acc[0] of lanes 0..31
+    float v = bf(fmaxf(acc[0] + bias2, 0.f)) * w3;
+    for (int o = 1; o < 32; o <<= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) zp[wave * kFusedRows] = v;
+  } else {
+    float v[16];
+    for (int rr = 0; rr < 16; ++rr) v[rr] = bf(fmaxf(acc[rr] + bias2, 0.f)) * w3;
+    for (int o = 1; o < 32; o <<= 1)
+      for (int rr = 0; rr < 16; ++rr) v[rr] += __shfl_xor(v[rr], o, 64);
+    if ((lane & 31) == 0)
+      for (int rr = 0; rr < 16; ++rr) zp[wave * kFusedRows + 8 * (rr / 4) + 4 * (lane >> 5) + (rr % 4)] = v[rr];
+  }
   __syncthreads();
   if ((int)threadIdx.x < rows) {
     float z = 0.f;
     for (int w = 0; w < kRowThreads / 64; ++w) z += zp[w * kFusedRows + threadIdx.x];
-    z += P[ob3];
+    z += bias3;
     const float sig = 1.f / (1.f + expf(-z));
     f[row0 + threadIdx.x] = (1.f - socc[threadIdx.x] / 512.f) + sig - 0.5f;
   }
@@ -455,7 +467,7 @@ k_rank_fused(const float* __restrict__ P, const short* __restrict__ W, const flo
   };
   // the second layer's weights after the stage: requested with the first
   // layer's, they delay the volume gathers in the CU's load pipeline
-  mlp_tile<true>(P, W, stage, pre, sx, sh1, zp, socc, row0, rows, f);
+  mlp_tile<true, kRankRows == 1>(P, W, stage, pre, sx, sh1, zp, socc, row0, rows, f);
   if (done_flag) {  // the last workgroup to finish raises the host-visible flag
     __threadfence_system();
     __syncthreads();
