@@ -981,11 +981,13 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     g_ft.cands.start();
     size_t total = 0;
     for (int g = 0; g < G; ++g) total += pops[g].size() * groups[g].boxes.size();
-    cands.resize(total);
-    cb.resize(total);
-    ck.resize(total);
-    cidx.resize(total);
-    size_t nc = 0, ncb = 0;
+    cands.resize(total);  // every entry is written below
+    // appended (their capacity is kept from round to round: no re-initialised
+    // elements)
+    cb.clear();
+    ck.clear();
+    cidx.clear();
+    size_t nc = 0;
     // a box that already contains the element has dOBV = 0, the minimum: then the
     // element's other candidates need no evaluation
     for (int g = 0; g < G; ++g) {
@@ -1012,18 +1014,13 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         }
         if (any_trivial) continue;
         for (int i = 0; i < b; ++i) {
-          HBox& gb = cb[ncb];
-          gb = boxes[gr.boxes[i]];
-          std::memcpy(gb.h, cands[first + i].h, 12);
-          ck[ncb] = slot[gr.boxes[i]];
-          cidx[ncb] = (int32_t)(first + i);
-          ++ncb;
+          cb.push_back(boxes[gr.boxes[i]]);
+          std::memcpy(cb.back().h, cands[first + i].h, 12);
+          ck.push_back(slot[gr.boxes[i]]);
+          cidx.push_back((int32_t)(first + i));
         }
       }
     }
-    cb.resize(ncb);
-    ck.resize(ncb);
-    cidx.resize(ncb);
     g_ft.cands.stop();
     // Learned ranking.  The ranker predicts the outer fraction of every candidate
     // and of the current boxes; the predicted change of a move is
