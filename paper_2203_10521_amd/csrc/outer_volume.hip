@@ -250,6 +250,7 @@ __device__ inline int item_box(const int64_t* __restrict__ chunk_off, int n_boxe
 }
 
 struct CullArgs {
+  const int32_t* item_box;  // nullable: the box of every item (else a search of chunk_off)
   const obbv_box* boxes;
   const int32_t* box_mesh;
   const MeshDev* meshes;  // device mesh table; NULL with a single mesh (then mesh0)
@@ -336,6 +337,9 @@ __device__ inline long long block_excl_scan(long long v, long long* wsum, long l
   return before + inc - v;
 }
 
+// Calls of up to this many boxes get an item-to-box table (k_box_chunks).
+constexpr int kItemBoxMax = 4096;
+
 // One block: the number of 256-triangle items of every box (its frame list, or
 // the whole mesh), their exclusive scan (chunk_off[0..n_boxes]), the frame use
 // of every box, and the per-call counters that must start at zero.
@@ -346,8 +350,9 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
              const int32_t* __restrict__ box_frame, int n_frames, const int64_t* __restrict__ list_off,
              int32_t* __restrict__ box_list, int64_t* __restrict__ chunk_off, uint32_t* __restrict__ done_counter,
              uint32_t* status, const uint32_t* __restrict__ box_key, int R, uint64_t seed,
-             RayFrame* __restrict__ rframe) {
+             RayFrame* __restrict__ rframe, int32_t* __restrict__ item_box_tab) {
   __shared__ long long wsum[kScanBlockThreads / 64];
+  __shared__ int32_t sco[kItemBoxMax + 1];  // item offsets of the boxes (with item_box_tab)
   if (threadIdx.x == 0 && done_counter) *done_counter = 0u;
   for (int e = threadIdx.x; e < 3 * n_boxes; e += blockDim.x) {  // the ray grid of every cast
     const int b = e / 3;
@@ -375,10 +380,28 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
     }
     long long total = 0;
     const long long ex = block_excl_scan(nch, wsum, total);
-    if (b < n_boxes) chunk_off[b] = base + ex;
+    if (b < n_boxes) {
+      chunk_off[b] = base + ex;
+      if (item_box_tab) sco[b] = (int32_t)(base + ex);
+    }
     base += total;
   }
   if (threadIdx.x == 0) chunk_off[n_boxes] = base;
+  if (item_box_tab) {  // the box of every item (the cull passes read it instead of searching chunk_off)
+    if (threadIdx.x == 0) sco[n_boxes] = (int32_t)base;
+    __syncthreads();
+    for (int64_t it = threadIdx.x; it < base; it += blockDim.x) {
+      int lo = 0, hi = n_boxes;  // sco[lo] <= it < sco[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sco[mid] <= it)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      item_box_tab[it] = lo;
+    }
+  }
 }
 
 // Per-wave ballot counts of a 256-thread block, summed in LDS: every block
@@ -499,7 +522,7 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt, int32_t* __restrict__ t
   const int TT = a.tpe * a.tpe;
   const bool lds = 6 * TT <= kLdsTiles;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const int b = item_box(a.chunk_off, a.n_boxes, item);
+    const int b = a.item_box ? a.item_box[item] : item_box(a.chunk_off, a.n_boxes, item);
     const BoxRegs B = load_box(a.boxes, b);
     const bool valid = box_state(B) == 0;
     const MeshDev M = a.meshes ? a.meshes[a.box_mesh ? a.box_mesh[b] : 0] : a.mesh0;
@@ -846,7 +869,7 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
   const int64_t total = a.chunk_off[a.n_boxes];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const int b = item_box(a.chunk_off, a.n_boxes, item);
+    const int b = a.item_box ? a.item_box[item] : item_box(a.chunk_off, a.n_boxes, item);
     const BoxRegs B = load_box(a.boxes, b);
     const bool valid = box_state(B) == 0;
     const MeshDev M = a.meshes ? a.meshes[a.box_mesh ? a.box_mesh[b] : 0] : a.mesh0;
@@ -1645,8 +1668,8 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   }
   if (ex) ex->items_bytes = items_bytes;
   int32_t* d_icnt = (int32_t*)items;
-  int32_t* d_ioff = (int32_t*)(items + align_up(24 * (size_t)items_bound));
-  int32_t* d_ficnt = (int32_t*)((char*)d_ioff + align_up(12 * (size_t)items_bound));
+  int32_t* d_itembox = (int32_t*)(items + align_up(24 * (size_t)items_bound));  // [items_bound] box of every item
+  int32_t* d_ficnt = (int32_t*)((char*)d_itembox + align_up(12 * (size_t)items_bound));
   int32_t* d_fioff = (int32_t*)((char*)d_ficnt + align_up(4 * (size_t)fitems));
 
   // the mesh table goes to the device only with several meshes (one mesh travels
@@ -1690,10 +1713,12 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   }
   hipLaunchKernelGGL(k_box_chunks, dim3(1), dim3(kScanBlockThreads), 0, s, box_mesh, d_meshes, mh[0],
                      n_meshes, n_boxes, boxes, sf ? sf->frames : nullptr, sf ? sf->box_frame : nullptr, n_frames,
-                     (const int64_t*)d_foff, d_blist, d_choff, d_done, status, box_key, R, params->seed, d_rframe);
+                     (const int64_t*)d_foff, d_blist, d_choff, d_done, status, box_key, R, params->seed, d_rframe,
+                     n_boxes <= kItemBoxMax && items_bound < ((int64_t)1 << 31) ? d_itembox : (int32_t*)nullptr);
   OBBV_HIP(hipGetLastError());
 
   CullArgs ca;
+  ca.item_box = n_boxes <= kItemBoxMax && items_bound < ((int64_t)1 << 31) ? d_itembox : nullptr;
   ca.write_lds = write_lds_choice();
   ca.boxes = boxes;
   ca.box_mesh = box_mesh;
