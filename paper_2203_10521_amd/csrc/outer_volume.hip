@@ -249,8 +249,18 @@ __device__ inline int item_box(const int64_t* __restrict__ chunk_off, int n_boxe
   return lo;
 }
 
+// A cull work item (256 triangles of one box's list or of the mesh), as
+// k_box_chunks tabulates it: the box, the item's triangle count, and its first
+// triangle: an index into the box's frame list (first >= 0) or mesh triangle
+// -1 - first (first < 0).
+struct ItemInfo {
+  int64_t first;
+  int32_t b;
+  int32_t count;
+};
+
 struct CullArgs {
-  const int32_t* item_box;  // nullable: the box of every item (else a search of chunk_off)
+  const ItemInfo* item_info;  // nullable: every item's box and triangles (else a search of chunk_off)
   const obbv_box* boxes;
   const int32_t* box_mesh;
   const MeshDev* meshes;  // device mesh table; NULL with a single mesh (then mesh0)
@@ -287,6 +297,25 @@ __device__ inline bool cull_tri(const CullArgs& a, int b, const MeshDev& M, cons
   if (l < 0) return t < M.nt && load_tri_local(M, t, B, P, a.status);
   if (t >= (int)(a.list_off[l + 1] - a.list_off[l])) return false;
   const float4* q = a.list_P + 3 * (a.list_off[l] + t);
+  const float4 x = q[0], y = q[1], z = q[2];
+  P[0][0] = x.x;
+  P[0][1] = x.y;
+  P[0][2] = x.z;
+  P[1][0] = x.w;
+  P[1][1] = y.x;
+  P[1][2] = y.y;
+  P[2][0] = y.z;
+  P[2][1] = y.w;
+  P[2][2] = z.x;
+  return true;
+}
+
+// Triangle `tid` of a tabulated item, in the box frame (false past its end).
+__device__ inline bool cull_tri_item(const CullArgs& a, const MeshDev& M, const BoxRegs& B, const ItemInfo& ii,
+                                     int tid, float P[3][3]) {
+  if (tid >= ii.count) return false;
+  if (ii.first < 0) return load_tri_local(M, (int)(-1 - ii.first) + tid, B, P, a.status);
+  const float4* q = a.list_P + 3 * (ii.first + tid);
   const float4 x = q[0], y = q[1], z = q[2];
   P[0][0] = x.x;
   P[0][1] = x.y;
@@ -337,8 +366,8 @@ __device__ inline long long block_excl_scan(long long v, long long* wsum, long l
   return before + inc - v;
 }
 
-// Calls of up to this many boxes get an item-to-box table (k_box_chunks).
-constexpr int kItemBoxMax = 4096;
+// Calls of up to this many boxes get a table of their cull items (k_box_chunks).
+constexpr int kItemBoxMax = 2048;
 
 // One block: the number of 256-triangle items of every box (its frame list, or
 // the whole mesh), their exclusive scan (chunk_off[0..n_boxes]), the frame use
@@ -350,9 +379,13 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
              const int32_t* __restrict__ box_frame, int n_frames, const int64_t* __restrict__ list_off,
              int32_t* __restrict__ box_list, int64_t* __restrict__ chunk_off, uint32_t* __restrict__ done_counter,
              uint32_t* status, const uint32_t* __restrict__ box_key, int R, uint64_t seed,
-             RayFrame* __restrict__ rframe, int32_t* __restrict__ item_box_tab) {
+             RayFrame* __restrict__ rframe, ItemInfo* __restrict__ item_info) {
   __shared__ long long wsum[kScanBlockThreads / 64];
-  __shared__ int32_t sco[kItemBoxMax + 1];  // item offsets of the boxes (with item_box_tab)
+  // with item_info: every box's first item, first triangle (list index, or -1
+  // for the mesh) and triangle count
+  __shared__ int32_t sco[kItemBoxMax + 1];
+  __shared__ int64_t sfirst[kItemBoxMax];
+  __shared__ int32_t sn[kItemBoxMax];
   if (threadIdx.x == 0 && done_counter) *done_counter = 0u;
   for (int e = threadIdx.x; e < 3 * n_boxes; e += blockDim.x) {  // the ray grid of every cast
     const int b = e / 3;
@@ -362,6 +395,7 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
   for (int b0 = 0; b0 < n_boxes; b0 += kScanBlockThreads) {
     const int b = b0 + (int)threadIdx.x;
     long long nch = 0;
+    int64_t first = -1, ntri = 0;
     if (b < n_boxes) {
       const int m = box_mesh ? box_mesh[b] : 0;
       if (m < 0 || m >= n_meshes) {  // out-of-range mesh index: the box sees no triangles
@@ -373,8 +407,12 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
           const int f = box_frame[b];
           const bool use = f >= 0 && f < n_frames && inside_frame(boxes[b], frames[f]);
           box_list[b] = use ? f : -1;
-          if (use) n = list_off[f + 1] - list_off[f];
+          if (use) {
+            first = list_off[f];
+            n = list_off[f + 1] - first;
+          }
         }
+        ntri = n;
         nch = (n + kCullThreads - 1) / kCullThreads;
       }
     }
@@ -382,12 +420,16 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
     const long long ex = block_excl_scan(nch, wsum, total);
     if (b < n_boxes) {
       chunk_off[b] = base + ex;
-      if (item_box_tab) sco[b] = (int32_t)(base + ex);
+      if (item_info) {
+        sco[b] = (int32_t)(base + ex);
+        sfirst[b] = first;
+        sn[b] = (int32_t)ntri;
+      }
     }
     base += total;
   }
   if (threadIdx.x == 0) chunk_off[n_boxes] = base;
-  if (item_box_tab) {  // the box of every item (the cull passes read it instead of searching chunk_off)
+  if (item_info) {  // every item (the cull passes read it instead of searching chunk_off)
     if (threadIdx.x == 0) sco[n_boxes] = (int32_t)base;
     __syncthreads();
     for (int64_t it = threadIdx.x; it < base; it += blockDim.x) {
@@ -399,7 +441,12 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
         else
           hi = mid;
       }
-      item_box_tab[it] = lo;
+      const int64_t t0 = (it - sco[lo]) * (int64_t)kCullThreads;
+      ItemInfo ii;
+      ii.b = lo;
+      ii.count = (int32_t)min((int64_t)kCullThreads, (int64_t)sn[lo] - t0);
+      ii.first = sfirst[lo] >= 0 ? sfirst[lo] + t0 : -1 - t0;
+      item_info[it] = ii;
     }
   }
 }
@@ -522,13 +569,25 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt, int32_t* __restrict__ t
   const int TT = a.tpe * a.tpe;
   const bool lds = 6 * TT <= kLdsTiles;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const int b = a.item_box ? a.item_box[item] : item_box(a.chunk_off, a.n_boxes, item);
+    ItemInfo ii;
+    if (a.item_info) {
+      ii = a.item_info[item];
+    } else {
+      ii.b = item_box(a.chunk_off, a.n_boxes, item);
+      ii.count = -1;
+    }
+    const int b = ii.b;
     const BoxRegs B = load_box(a.boxes, b);
     const bool valid = box_state(B) == 0;
     const MeshDev M = a.meshes ? a.meshes[a.box_mesh ? a.box_mesh[b] : 0] : a.mesh0;
-    const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    const bool ok = valid && cull_tri(a, b, M, B, t, P);
+    bool ok;
+    if (a.item_info) {
+      ok = valid && cull_tri_item(a, M, B, ii, threadIdx.x, P);
+    } else {
+      const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
+      ok = valid && cull_tri(a, b, M, B, t, P);
+    }
     if (lds) {
       for (int k = threadIdx.x; k < 6 * TT; k += kCullThreads) cnt[k] = 0;
       __syncthreads();
@@ -869,13 +928,25 @@ k_write(CullArgs a, const int32_t* __restrict__ side, const int64_t* __restrict_
   const int64_t total = a.chunk_off[a.n_boxes];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const int b = a.item_box ? a.item_box[item] : item_box(a.chunk_off, a.n_boxes, item);
+    ItemInfo ii;
+    if (a.item_info) {
+      ii = a.item_info[item];
+    } else {
+      ii.b = item_box(a.chunk_off, a.n_boxes, item);
+      ii.count = -1;
+    }
+    const int b = ii.b;
     const BoxRegs B = load_box(a.boxes, b);
     const bool valid = box_state(B) == 0;
     const MeshDev M = a.meshes ? a.meshes[a.box_mesh ? a.box_mesh[b] : 0] : a.mesh0;
-    const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
     float P[3][3];
-    const bool ok = valid && cull_tri(a, b, M, B, t, P);
+    bool ok;
+    if (a.item_info) {
+      ok = valid && cull_tri_item(a, M, B, ii, threadIdx.x, P);
+    } else {
+      const int t = (int)(item - a.chunk_off[b]) * kCullThreads + threadIdx.x;
+      ok = valid && cull_tri(a, b, M, B, t, P);
+    }
     // pass 1: kept flags, per-wave record counts, and (in LDS) per-tile entry counts
     if (lds)
       for (int k = threadIdx.x; k < 3 * TT; k += kCullThreads) cnt[k] = 0;
@@ -1652,7 +1723,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   // per-item counts and offsets of the cull passes (every entry is written)
   const int64_t items_bound = (int64_t)n_boxes * ceil_div(std::max(max_nt, 1), kCullThreads);
   const int64_t fitems = sf ? (int64_t)n_frames * ceil_div(std::max(meshes[0].n_triangles, 1), kCullThreads) : 0;
-  const size_t items_bytes = align_up(24 * (size_t)items_bound) + align_up(12 * (size_t)items_bound) +
+  const size_t items_bytes = align_up(24 * (size_t)items_bound) + align_up(sizeof(ItemInfo) * (size_t)items_bound) +
                              2 * align_up(4 * (size_t)fitems);
   char* items = nullptr;
   if (planned) {
@@ -1668,8 +1739,8 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   }
   if (ex) ex->items_bytes = items_bytes;
   int32_t* d_icnt = (int32_t*)items;
-  int32_t* d_itembox = (int32_t*)(items + align_up(24 * (size_t)items_bound));  // [items_bound] box of every item
-  int32_t* d_ficnt = (int32_t*)((char*)d_itembox + align_up(12 * (size_t)items_bound));
+  ItemInfo* d_iteminfo = (ItemInfo*)(items + align_up(24 * (size_t)items_bound));  // [items_bound] every cull item
+  int32_t* d_ficnt = (int32_t*)((char*)d_iteminfo + align_up(sizeof(ItemInfo) * (size_t)items_bound));
   int32_t* d_fioff = (int32_t*)((char*)d_ficnt + align_up(4 * (size_t)fitems));
 
   // the mesh table goes to the device only with several meshes (one mesh travels
@@ -1714,11 +1785,11 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   hipLaunchKernelGGL(k_box_chunks, dim3(1), dim3(kScanBlockThreads), 0, s, box_mesh, d_meshes, mh[0],
                      n_meshes, n_boxes, boxes, sf ? sf->frames : nullptr, sf ? sf->box_frame : nullptr, n_frames,
                      (const int64_t*)d_foff, d_blist, d_choff, d_done, status, box_key, R, params->seed, d_rframe,
-                     n_boxes <= kItemBoxMax && items_bound < ((int64_t)1 << 31) ? d_itembox : (int32_t*)nullptr);
+                     n_boxes <= kItemBoxMax && items_bound < ((int64_t)1 << 31) ? d_iteminfo : (ItemInfo*)nullptr);
   OBBV_HIP(hipGetLastError());
 
   CullArgs ca;
-  ca.item_box = n_boxes <= kItemBoxMax && items_bound < ((int64_t)1 << 31) ? d_itembox : nullptr;
+  ca.item_info = n_boxes <= kItemBoxMax && items_bound < ((int64_t)1 << 31) ? d_iteminfo : nullptr;
   ca.write_lds = write_lds_choice();
   ca.boxes = boxes;
   ca.box_mesh = box_mesh;
