@@ -50,9 +50,9 @@ SEED_MESH = 21
 # writes its records and work items, their layouts); any change there reports
 # null until the counters are re-taken.
 K_TEST_TRAFFIC = {
-    "source_sha256": "61a7ed744fef91dae2f7037c305751321436e4c05ecc88ede8a458e44bc9f73f",
-    "fetch_bytes_per_launch": 79453949,   # 38,797.129 KiB raw x 1.99993 (copy calibration)
-    "write_bytes_per_launch": 844851,     # 825.050 KiB raw x 1.0
+    "source_sha256": "ad37b804f9aa98aefdbffdc88fd4d194853ab4f6e2f9ae71ec3ca40d791634a4",
+    "fetch_bytes_per_launch": 79444926,   # 38,792.755 KiB raw x 1.99993 (copy calibration)
+    "write_bytes_per_launch": 844850,     # 825.049 KiB raw x 1.0
     "profile": "profiles/ray_test_torus_hierarchy_traffic.md",
 }
 RASTER_SOURCES = ("outer_volume.hip", "common.h")
