@@ -3,22 +3,25 @@
 // crossing sum along each ray (Sec. 4.1, Eq. 9 generalised to a line).
 //
 // Pipeline per call (all on one stream):
-//   [k_frame_cull x 2]   boxes grouped by shared centre and axes: the frame-local
-//                        coordinates of the triangles each group can see
-//   k_box_chunks         work list of (box, 256-triangle chunk) items (one block,
-//                        scanned in place)
+//   [k_frame_cull x 2,   boxes grouped by shared centre and axes: the frame-local
+//    k_frame_scan]       coordinates of the triangles each group can see
+//   k_box_chunks         work list of (box, 256-triangle chunk) cull items and a
+//                        table of them (one block), the ray grid of every cast
 //   k_cull_count         per item and cast axis: triangles in the half prism above
-//                        the slab bottom and below the slab top (ballot counts
-//                        summed per block; no shared global counters)
-//   k_box_sides          keep the half prism with fewer triangles (mirror flag);
-//                        per-item record offsets (scan over the box's items)
-//   k_tile_count         per (box, axis, ray tile): number of binned triangles
-//   k_tiles_scan_*       bin, work-item and record offsets (3 kernels); unless the
-//                        scratch is capped or planned, one host sync for sizes
-//   k_write              per kept triangle: an 80-byte test record (edge and depth
-//                        planes, fixed point) + its index in every tile bin
-//   k_test               one wave per ray tile: every ray against its bin
-//   k_finalize           float64 OBV per box
+//                        the slab bottom and below the slab top, and the ray tiles
+//                        each can reach, for both sides (counts summed per block)
+//   k_box_sides          keep the half prism with fewer triangles (mirror flag),
+//                        take that side's tile counts
+//   k_tiles_scan_one     bin, work-item and record offsets (one block for small
+//   (or _block/top/add)  calls, else three kernels); unless the scratch is capped
+//                        or planned, one host sync for sizes
+//   k_write              per kept triangle and ray tile it reaches: a 64-byte test
+//                        record copy (edge and depth planes, fixed point, cell
+//                        range in the tile) in the tile's bin; the 64-byte ray-test
+//                        work items (ray grid, tile, bin range)
+//   k_raster             one wave per work item: every record against the rays of
+//                        the cells it covers (k_test: against every ray of the tile)
+//   k_finalize           float64 OBV per box, publication of the call
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -31,7 +34,7 @@ namespace {
 
 constexpr int kCullThreads = 256;
 constexpr int kTestThreads = 64;
-constexpr int kTestChunk = 512;  // records per ray-test work item (measured best of 64..4096)
+constexpr int kTestChunk = 384;  // records per ray-test work item (measured best of 64..4096)
 
 struct BoxRegs {
   float Q[9];
