@@ -50,9 +50,9 @@ SEED_MESH = 21
 # writes its records and work items, their layouts); any change there reports
 # null until the counters are re-taken.
 K_TEST_TRAFFIC = {
-    "source_sha256": "ad37b804f9aa98aefdbffdc88fd4d194853ab4f6e2f9ae71ec3ca40d791634a4",
-    "fetch_bytes_per_launch": 79444926,   # 38,792.755 KiB raw x 1.99993 (copy calibration)
-    "write_bytes_per_launch": 844850,     # 825.049 KiB raw x 1.0
+    "source_sha256": "7b65f04293212283de72b0551fb889450a5532e4ebc0c58236476abf12a3dd07",
+    "fetch_bytes_per_launch": 80003480,   # 39,065.476 KiB raw x 1.99993 (copy calibration)
+    "write_bytes_per_launch": 875632,     # 855.109 KiB raw x 1.0
     "profile": "profiles/ray_test_torus_hierarchy_traffic.md",
 }
 RASTER_SOURCES = ("outer_volume.hip", "common.h")
