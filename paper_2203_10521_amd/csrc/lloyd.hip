@@ -452,7 +452,7 @@ struct Predictor {
   bool paused = false;  // the judge found the ranker off: exact evaluation until the next iteration
   WallTimer t_pred;
   double err_sum = 0.0;
-  int64_t err_n = 0, predicted = 0, fallbacks = 0;
+  int64_t err_n = 0, predicted = 0, fallbacks = 0, calls = 0;
   static constexpr int kWindow = 256;
 
   // Rolling mean |predicted - exact| outer fraction over the last kWindow verified
@@ -656,6 +656,7 @@ struct Predictor {
     g_ft.pred_wait.stop();
     std::memcpy(out.data(), hbuf + o_f, n * 4);
     predicted += (int64_t)n;
+    ++calls;
     t_pred.stop();
     return OBBV_OK;
   }
@@ -1464,10 +1465,11 @@ struct LloydState {
     if (!getenv("OBBV_LLOYD_TIMING")) return;
     t_life.stop();
     fprintf(stderr,
-            "[obbv lloyd] wall %.3f s: flood %.3f s, parameter update %.3f s; outer-volume calls %lld "
-            "(host prep %.3f s, device incl. launches %.3f s, %lld overflow repeats); ranker %.3f s\n",
-            t_life.s, t_flood.s, t_update.s, (long long)ev.calls, ev.t_prep.s, ev.t_dev.s, (long long)ev.overflows,
-            pred.t_pred.s);
+            "[obbv lloyd] wall %.3f s: flood %.3f s (%lld rounds, %lld ranked), parameter update %.3f s; "
+            "outer-volume calls %lld (host prep %.3f s, device incl. launches %.3f s, %lld overflow repeats); "
+            "ranker %.3f s\n",
+            t_life.s, t_flood.s, (long long)cnt.rounds, (long long)pred.calls, t_update.s, (long long)ev.calls,
+            ev.t_prep.s, ev.t_dev.s, (long long)ev.overflows, pred.t_pred.s);
     const FloodTimers& f = g_ft;
     fprintf(stderr,
             "[obbv lloyd] flood host: pops %.3f s, pop extents %.3f s, candidates %.3f s, ranker post %.3f s, "
