@@ -211,17 +211,22 @@ def test_grouped_candidates_equal_plain_calls(api):
 def test_rasterising_and_all_ray_kernels_agree(api, monkeypatch):
     """The rasterising ray test (each record against the rays of its cells) and
     the all-rays test (each record against every ray of its tile) give the same
-    bits, per box and per ray, for tile 16 and tile 8 calls."""
+    bits, per box and per ray, with the rasterising kernel's per-lane cell loop
+    for records up to 64 cells of a tile and its wave-wide path above, and with
+    either path alone (every record wide; none wide)."""
     V, F = synth.noisy_torus(nu=96, nv=48)
     c, a, h = synth.random_boxes(24, seed=71, center_range=1.0, half_range=(0.1, 0.7))
     Vt, Ft, B = _dev(api, V, F, c, a, h)
     out = {}
-    for mode in ("1", "0"):
+    for mode, cells in (("0", "64"), ("1", "64"), ("1", "0"), ("1", "256")):
         monkeypatch.setenv("OBBV_TEST_RASTER", mode)
+        monkeypatch.setenv("OBBV_RASTER_CELLS", cells)
         r = api.outer_volume_ex(Vt, Ft, B, 48, seed=5, tile=16, rays=True)
-        out[mode] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
-    for k in ("obv", "ray_q", "ray_hits"):
-        assert np.array_equal(out["1"][k], out["0"][k]), k
+        out[(mode, cells)] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
+    ref = out[("0", "64")]
+    for key in (("1", "64"), ("1", "0"), ("1", "256")):
+        for k in ("obv", "ray_q", "ray_hits"):
+            assert np.array_equal(out[key][k], ref[k]), (key, k)
 
 
 def test_validate_mesh(api):
