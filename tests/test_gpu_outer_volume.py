@@ -229,6 +229,22 @@ def test_rasterising_and_all_ray_kernels_agree(api, monkeypatch):
             assert np.array_equal(out[key][k], ref[k]), (key, k)
 
 
+def test_write_pass_slot_strategies_agree(api, monkeypatch):
+    """Bin slots reserved per tile from LDS counts and slots taken one global
+    atomic at a time fill the bins in different orders; the sums are exact
+    integers, so every box and ray gets the same bits."""
+    V, F = synth.noisy_torus(nu=64, nv=32)
+    c, a, h = synth.random_boxes(16, seed=72, center_range=1.0, half_range=(0.1, 0.7))
+    Vt, Ft, B = _dev(api, V, F, c, a, h)
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("OBBV_WRITE_LDS", mode)
+        r = api.outer_volume_ex(Vt, Ft, B, 64, seed=6, tile=16, rays=True)
+        out[mode] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
+    for k in ("obv", "ray_q", "ray_hits"):
+        assert np.array_equal(out["1"][k], out["0"][k]), k
+
+
 def test_validate_mesh(api):
     import torch
     V, F = synth.icosphere(2)
