@@ -645,12 +645,11 @@ k_cull_count(CullArgs a, int32_t* __restrict__ item_cnt, int32_t* __restrict__ t
 }
 
 // One wave per (box, cast axis): the triangle counts of both half prisms, the
-// side with fewer triangles (mirror flag), its record count, and (item_off
-// non-null) every item's first record within the (box, axis) (exclusive scan
-// over the box's items).
+// side with fewer triangles (mirror flag), its record count, and that side's
+// tile counts.
 __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, const int32_t* __restrict__ item_cnt,
-                            int32_t* __restrict__ side, int32_t* __restrict__ rec_cnt,
-                            int32_t* __restrict__ item_off, int TT, int32_t* __restrict__ tile_cnt,
+                            int32_t* __restrict__ side, int32_t* __restrict__ rec_cnt, int TT,
+                            int32_t* __restrict__ tile_cnt,
                             int32_t* __restrict__ bin_cur, unsigned long long* __restrict__ acc,
                             int32_t* __restrict__ tile_cnt2) {
   const int bw = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
@@ -682,14 +681,6 @@ __global__ void k_box_sides(const int64_t* __restrict__ chunk_off, int n_boxes, 
     tile_cnt[(int64_t)bw * TT + k] = tc[mirror * TT + k];
     tc[k] = 0;
     tc[TT + k] = 0;
-  }
-  if (!item_off) return;
-  int base = 0;
-  for (int64_t i = i0; i < i1; i += 64) {
-    const int v = i + lane < i1 ? item_cnt[6 * (i + lane) + 2 * w + mirror] : 0;
-    const int inc = wave_incl_scan(v, lane);
-    if (i + lane < i1) item_off[3 * (i + lane) + w] = base + inc - v;
-    base += __shfl(inc, 63);
   }
 }
 
@@ -1826,7 +1817,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   hipLaunchKernelGGL(k_cull_count, dim3(cull_grid), dim3(kCullThreads), 0, s, ca, d_icnt, d_tc2);
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_box_sides, dim3(ceil_div(nbw, kCullWaves)), dim3(kCullThreads), 0, s,
-                     (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, (int32_t*)nullptr, (int)TT,
+                     (const int64_t*)d_choff, n_boxes, (const int32_t*)d_icnt, d_side, d_reccnt, (int)TT,
                      d_tilecnt, d_bincur, d_acc, d_tc2);
   OBBV_HIP(hipGetLastError());
   // bin and work-item offsets of the tiles, record offsets of the (box, axis) pairs
