@@ -50,9 +50,9 @@ SEED_MESH = 21
 # writes its records and work items, their layouts); any change there reports
 # null until the counters are re-taken.
 K_TEST_TRAFFIC = {
-    "source_sha256": "7b65f04293212283de72b0551fb889450a5532e4ebc0c58236476abf12a3dd07",
-    "fetch_bytes_per_launch": 80003480,   # 39,065.476 KiB raw x 1.99993 (copy calibration)
-    "write_bytes_per_launch": 875632,     # 855.109 KiB raw x 1.0
+    "source_sha256": "67e67bbae71376334d17e7b2d1d43d243ffb5230f762a64715e132cc42ea4a55",
+    "fetch_bytes_per_launch": 80011413,   # 39,069.342 KiB raw x 1.99994 (copy calibration)
+    "write_bytes_per_launch": 875633,     # 855.110 KiB raw x 1.0
     "profile": "profiles/ray_test_torus_hierarchy_traffic.md",
 }
 RASTER_SOURCES = ("outer_volume.hip", "common.h")
