@@ -937,6 +937,8 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
   std::vector<HBox> pb, rb;
   std::vector<uint32_t> rk;
   std::vector<int32_t> ri, cur_of((size_t)boxes.size(), -1), touched;
+  std::vector<uint64_t> rmask;  // containment mask of each pop of the round
+  std::vector<char> in_touched(boxes.size(), 0);
   std::vector<std::vector<std::pair<double, size_t>>> per_box((size_t)boxes.size());
   std::vector<std::vector<int32_t>> got((size_t)boxes.size());  // candidate index per receiving box
   // Centres and axes of every group's boxes in float64.  Only the half extents
@@ -954,24 +956,49 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       for (int k = 0; k < 9; ++k) gbQ[g][9 * i + k] = bx.Q[k];
     }
   }
-  // extents [pop][box of its group][3], pops in group order
-  auto pop_extents = [&](const std::vector<std::vector<int32_t>>& pops, std::vector<double>& out) {
+  // Containment masks: bit i of a pop's mask is set when box i of its group
+  // already contains the element (extent <= half extent on every axis).  Boxes
+  // only grow during the flood, so a set bit stays true; a clear bit can turn
+  // true only for a box that grew after the mask was taken, and the round
+  // re-tests exactly those boxes.  Groups of more than 64 boxes go without.
+  size_t max_group = 0;
+  for (int g = 0; g < G; ++g) max_group = std::max(max_group, groups[g].boxes.size());
+  const bool use_mask = max_group <= 64;
+  // the round in which each box last grew (-1: not during this flood)
+  std::vector<int64_t> grown_at(boxes.size(), -1);
+  auto contains = [](const double* ext, const float h[3]) {
+    return ext[0] <= (double)h[0] && ext[1] <= (double)h[1] && ext[2] <= (double)h[2];
+  };
+  // extents [pop][box of its group][3] and the pops' containment masks, pops in
+  // group order
+  auto pop_extents = [&](const std::vector<std::vector<int32_t>>& pops, std::vector<double>& out,
+                         std::vector<uint64_t>& mask) {
     g_ft.extents.start();
-    size_t total = 0;
-    for (int g = 0; g < G; ++g) total += pops[g].size() * groups[g].boxes.size();
+    size_t total = 0, npop = 0;
+    for (int g = 0; g < G; ++g) {
+      total += pops[g].size() * groups[g].boxes.size();
+      npop += pops[g].size();
+    }
     out.resize(total * 3);
-    size_t x = 0;
+    mask.assign(npop, 0);
+    size_t x = 0, p = 0;
     for (int g = 0; g < G; ++g) {
       const size_t b = groups[g].boxes.size();
-      for (int e : pops[g])
-        for (size_t i = 0; i < b; ++i, x += 3) element_extent_fast(E, e, &gbc[g][3 * i], &gbQ[g][9 * i], &out[x]);
+      for (int e : pops[g]) {
+        uint64_t m = 0;
+        for (size_t i = 0; i < b; ++i, x += 3) {
+          element_extent_fast(E, e, &gbc[g][3 * i], &gbQ[g][9 * i], &out[x]);
+          if (use_mask && contains(&out[x], boxes[groups[g].boxes[i]].h)) m |= 1ull << i;
+        }
+        mask[p++] = m;
+      }
     }
     g_ft.extents.stop();
   };
   // `overlap` (the next round's pops and their extents) runs once per round,
   // while the device works if the round makes a device call, else at its end
   auto round = [&](const std::vector<std::vector<int32_t>>& pops, const std::vector<double>& pext,
-                   const std::function<void()>& overlap) -> int {
+                   const std::vector<uint64_t>& pmask, const std::function<void()>& overlap) -> int {
     bool overlapped = false;
     const std::function<void()> overlap_once = [&]() {
       if (!overlapped) {
@@ -980,26 +1007,49 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       }
     };
     g_ft.cands.start();
+    const int64_t rno = cnt.rounds;
     size_t total = 0;
     for (int g = 0; g < G; ++g) total += pops[g].size() * groups[g].boxes.size();
-    cands.resize(total);  // every entry is written below
+    cands.resize(total);  // at most this many entries are written below
     // appended (their capacity is kept from round to round: no re-initialised
     // elements)
     cb.clear();
     ck.clear();
     cidx.clear();
-    size_t nc = 0;
+    size_t nc = 0, px = 0, p = 0, npop = 0;
+    for (int g = 0; g < G; ++g) npop += pops[g].size();
+    rmask.assign(npop, 0);
     // a box that already contains the element has dOBV = 0, the minimum: then the
-    // element's other candidates need no evaluation
+    // element's other candidates need no evaluation.  Such a pop (a non-zero
+    // containment mask, after re-testing the boxes that grew in the previous
+    // round) takes no candidate entries: its decision is taken from the mask.
     for (int g = 0; g < G; ++g) {
       const Group& gr = groups[g];
       const int b = (int)gr.boxes.size();
+      uint64_t regrown = 0;
+      if (use_mask)
+        for (int i = 0; i < b; ++i) regrown |= grown_at[gr.boxes[i]] == rno - 1 ? 1ull << i : 0ull;
       for (int e : pops[g]) {
+        if (use_mask) {
+          uint64_t m = pmask[p];
+          for (uint64_t t = regrown & ~m; t; t &= t - 1) {
+            const int i = __builtin_ctzll(t);
+            if (contains(&pext[3 * (px + i)], boxes[gr.boxes[i]].h)) m |= 1ull << i;
+          }
+          rmask[p] = m;
+          if (m) {
+            cnt.trivial += __builtin_popcountll(m);
+            px += b;
+            ++p;
+            continue;
+          }
+        }
+        ++p;
         const size_t first = nc;
         bool any_trivial = false;
         for (int i = 0; i < b; ++i) {
           const HBox& bx = boxes[gr.boxes[i]];
-          const double* ext = &pext[3 * nc];
+          const double* ext = &pext[3 * px++];
           Cand& c = cands[nc++];
           c.e = e;
           c.g = g;
@@ -1029,8 +1079,8 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     // their error).  For every receiving box only the verify_top candidates with
     // the smallest predicted change are evaluated exactly; the other candidates
     // are decided on the prediction.
-    dpred.assign(cands.size(), 0.0);
-    predicted_c.assign(cands.size(), 0);
+    dpred.assign(nc, 0.0);
+    predicted_c.assign(nc, 0);
     fcand.clear();  // prediction of each kept candidate (judge)
     const bool ranked = pred && pred->on && !pred->paused && !cidx.empty();
     const bool judge_round = ranked && round_no % std::max(1, pred->cfg.judge_every) == 0;
@@ -1116,7 +1166,7 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       stale.clear();
     }
     g_ft.exact_post.start();
-    evaluated.assign(cands.size(), 0);
+    evaluated.assign(nc, 0);
     for (size_t x = 0; x < cidx.size(); ++x) {
       cands[cidx[x]].val = vals[ns + x];
       evaluated[cidx[x]] = 1;
@@ -1133,10 +1183,32 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     g_ft.decide.start();
     touched.clear();
     size_t ci = 0;
+    p = 0;
     for (int g = 0; g < G; ++g) {
       const Group& gr = groups[g];
       const int b = (int)gr.boxes.size();
       for (int e : pops[g]) {
+        const uint64_t m = rmask[p++];
+        if (m) {  // the containing box nearest the element (first on ties) takes it, unchanged
+          int best = -1;
+          double bdist = 0.0;
+          for (uint64_t t = m; t; t &= t - 1) {
+            const int i = __builtin_ctzll(t);
+            const double dd = dist3(&E.cen[3 * e], boxes[gr.boxes[i]].c);
+            if (best < 0 || dd < bdist) {
+              best = i;
+              bdist = dd;
+            }
+          }
+          const int bi = gr.boxes[best];
+          eb[e] = bi;
+          ++cnt.moves;
+          if (!in_touched[bi]) {
+            in_touched[bi] = 1;
+            touched.push_back(bi);
+          }
+          continue;
+        }
         int best = -1;
         double bd = 0.0, bdist = 0.0;
         for (int i = 0; i < b; ++i) {
@@ -1161,7 +1233,10 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
         const int bi = gr.boxes[best];
         eb[e] = bi;
         ++cnt.moves;
-        if (got[bi].empty()) touched.push_back(bi);
+        if (!in_touched[bi]) {
+          in_touched[bi] = 1;
+          touched.push_back(bi);
+        }
         got[bi].push_back((int32_t)(ci + best));
         ci += b;
       }
@@ -1170,12 +1245,16 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
     // grow the receiving boxes to the union
     g_ft.grow.start();
     for (int bi : touched) {
+      in_touched[bi] = 0;
+      // a box that took only elements it contained keeps its size
+      if (got[bi].empty()) continue;
       float hn[3];
       std::memcpy(hn, cands[got[bi][0]].h, 12);
       for (size_t x = 1; x < got[bi].size(); ++x)
         for (int r = 0; r < 3; ++r) hn[r] = std::max(hn[r], cands[got[bi][x]].h[r]);
       if (!same_h(hn, boxes[bi].h)) {
         std::memcpy(boxes[bi].h, hn, 12);
+        grown_at[bi] = rno;
         bool found = false;
         for (int cx : got[bi])
           if (evaluated[cx] && same_h(cands[cx].h, hn)) {
@@ -1217,21 +1296,23 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
   };
   bool any_next = false;
   std::vector<double> ext, next_ext;
+  std::vector<uint64_t> pmask, next_mask;
   const std::function<void()> advance = [&]() {
     g_ft.pops.start();
     for (int g = 0; g < G; ++g)
       for (int e : pops[g]) push_neighbours(e);
     g_ft.pops.stop();
     any_next = take_pops(next);
-    pop_extents(next, next_ext);
+    pop_extents(next, next_ext, next_mask);
   };
   bool any = take_pops(pops);
-  pop_extents(pops, ext);
+  pop_extents(pops, ext, pmask);
   while (any) {
     ++cnt.rounds;
-    OBBV_RET(round(pops, ext, advance));
+    OBBV_RET(round(pops, ext, pmask, advance));
     pops.swap(next);
     ext.swap(next_ext);
+    pmask.swap(next_mask);
     any = any_next;
   }
   // elements no flood reached: one by one, in index order, all groups in lockstep
@@ -1249,8 +1330,8 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
       if (p < left[g].size()) pops[g].push_back(left[g][p]);
     }
     ++cnt.rounds;
-    pop_extents(pops, ext);
-    OBBV_RET(round(pops, ext, [] {}));
+    pop_extents(pops, ext, pmask);
+    OBBV_RET(round(pops, ext, pmask, [] {}));
   }
   if (pred && pred->on) {
     const int64_t before = pred->judged_evals;
