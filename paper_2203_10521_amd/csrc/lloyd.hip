@@ -60,7 +60,7 @@ int mlp_pack_impl(const float* params, short* packed, hipStream_t s);
 int64_t mlp_packed_entries();
 int mlp_rank_packed(const float* params, const short* packed, const float* volume, int32_t N, const float* frame,
                     const obbv_box* boxes, int32_t n, void* scratch, float* out_f, hipStream_t s,
-                    unsigned* done_count, unsigned* done_flag, unsigned seq, const obbv_box* host_boxes);
+                    unsigned long long* tag, unsigned seq, const obbv_box* host_boxes);
 size_t mlp_rank_scratch_bytes(int32_t n);
 
 namespace {
@@ -486,10 +486,7 @@ struct Predictor {
   bool packed_ready = false;
   char* dbuf = nullptr;  // device: bfloat16 input rows and occupancy sums
   size_t dcap = 0;
-  unsigned* sig_host = nullptr;  // completion flag (mapped host memory) and its device view
-  unsigned* sig_dev = nullptr;
-  unsigned* sig_count = nullptr;  // device: workgroups finished in the current call
-  unsigned sig_seq = 0;
+  unsigned sig_seq = 0;  // call number, in the tag of every prediction word
 
   // Judge: every judge_every-th ranked round, a sample of the round's candidates
   // is evaluated exactly on a stream of its own (scratch from the second pool
@@ -554,14 +551,13 @@ struct Predictor {
     if (dbuf) (void)hipFree(dbuf);
     if (hbuf) (void)hipHostFree(hbuf);
     if (packed) (void)hipFree(packed);
-    if (sig_host) (void)hipHostFree(sig_host);
-    if (sig_count) (void)hipFree(sig_count);
   }
 
   // Predicted outer fractions of `boxes`: the boxes are staged in mapped pinned
-  // memory, two launches sample their inputs and run the network, the
-  // predictions land in mapped memory and the last workgroup raises a flag there
-  // that the host spins on.
+  // memory (and, for a few, in the kernel arguments), one launch (two for many
+  // boxes) samples their inputs and runs the network, and every prediction
+  // lands in mapped memory as one 64-bit word tagged with the call number, which
+  // the host spins on (no completion counter or flag on the device).
   int predict(const std::vector<HBox>& boxes_a, const std::vector<HBox>& boxes_b, std::vector<float>& out,
               const std::function<void()>* overlap = nullptr) {
     const size_t na = boxes_a.size(), n = na + boxes_b.size();
@@ -569,7 +565,7 @@ struct Predictor {
     if (n == 0) return OBBV_OK;
     t_pred.start();
     const size_t o_f = (n * sizeof(obbv_box) + 255) & ~(size_t)255;
-    const size_t hneed = o_f + n * 4;
+    const size_t hneed = o_f + n * 8;
     if (hneed > hcap) {
       OBBV_HIP(hipStreamSynchronize(stream));
       if (hbuf) OBBV_HIP(hipHostFree(hbuf));
@@ -582,6 +578,7 @@ struct Predictor {
         set_error("allocation failed for the ranker buffers");
         return OBBV_ERR_OOM;
       }
+      std::memset(hbuf, 0, hwant);  // no stale tag in the prediction words
       hcap = hwant;
     }
     const size_t dneed = mlp_rank_scratch_bytes((int32_t)n);
@@ -620,41 +617,37 @@ struct Predictor {
       OBBV_RET(mlp_pack_impl(cfg.mlp_params, packed, stream));
       packed_ready = true;
     }
-    if (!sig_host) {  // completion signal: a device counter and a flag in mapped host memory
-      if (hipHostMalloc((void**)&sig_host, 64, hipHostMallocDefault) != hipSuccess ||
-          hipHostGetDevicePointer((void**)&sig_dev, sig_host, 0) != hipSuccess ||
-          hipMalloc((void**)&sig_count, 64) != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("allocation failed for the ranker signal");
-        return OBBV_ERR_OOM;
-      }
-      OBBV_HIP(hipMemset(sig_count, 0, 64));
-      __atomic_store_n(sig_host, 0u, __ATOMIC_RELEASE);
-    }
-    const unsigned seq = ++sig_seq;
+    // a tag no word holds yet (words of earlier calls carry smaller numbers, a
+    // fresh buffer zeros)
+    const unsigned seq = ++sig_seq == 0u ? ++sig_seq : sig_seq;
+    uint64_t* words = reinterpret_cast<uint64_t*>(hbuf + o_f);
     g_ft.pred_launch.start();
     OBBV_RET(mlp_rank_packed(cfg.mlp_params, packed, cfg.volume, cfg.N, cfg.frame, (const obbv_box*)hdev, (int32_t)n,
-                             dbuf, (float*)(hdev + o_f), stream, sig_count, sig_dev, seq, hb));
+                             dbuf, nullptr, stream, reinterpret_cast<unsigned long long*>(hdev + o_f), seq, hb));
     g_ft.pred_launch.stop();
     if (overlap) (*overlap)();  // host work for later rounds while the device ranks
     g_ft.pred_wait.start();
-    // spin on the flag (no runtime wake-up latency); after 10 s without it, wait
-    // on the stream, which reports a failed launch
+    // spin on the tagged words, in order (no runtime wake-up latency); after 10 s
+    // without them, wait on the stream, which reports a failed launch
     auto t0 = std::chrono::steady_clock::now();
-    for (uint64_t spin = 0; __atomic_load_n(sig_host, __ATOMIC_ACQUIRE) != seq; ++spin) {
-      if ((spin & 4095) == 4095 &&
-          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > 10.0) {
-        OBBV_HIP(hipStreamSynchronize(stream));
-        if (__atomic_load_n(sig_host, __ATOMIC_ACQUIRE) != seq) {
-          set_error("ranker kernels finished without their completion flag");
-          return OBBV_ERR_HIP;
+    uint64_t spin = 0;
+    for (size_t i = 0; i < n; ++i) {
+      uint64_t w;
+      while (((w = __atomic_load_n(&words[i], __ATOMIC_ACQUIRE)) >> 32) != seq) {
+        if ((++spin & 4095) == 0 &&
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > 10.0) {
+          OBBV_HIP(hipStreamSynchronize(stream));
+          if ((__atomic_load_n(&words[i], __ATOMIC_ACQUIRE) >> 32) != seq) {
+            set_error("ranker kernels finished without writing every prediction");
+            return OBBV_ERR_HIP;
+          }
         }
-        break;
+        __builtin_ia32_pause();
       }
-      __builtin_ia32_pause();
+      const uint32_t bits = (uint32_t)w;
+      std::memcpy(&out[i], &bits, 4);
     }
     g_ft.pred_wait.stop();
-    std::memcpy(out.data(), hbuf + o_f, n * 4);
     predicted += (int64_t)n;
     ++calls;
     t_pred.stop();

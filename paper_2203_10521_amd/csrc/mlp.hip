@@ -219,10 +219,13 @@ constexpr int kRowThreads = 512;
 // its own), else with the first layer's.  kOneRow: only row 0 of the tile is a
 // real row (the other rows' values are never written out, so they are left
 // uncomputed where the layers allow; row 0 takes the same arithmetic).  The
-// tile's outputs are f[row0 + t] for t < rows.
+// tile's outputs are f[row0 + t] for t < rows, or, with `tag`, the 64-bit words
+// tag[row0 + t] = seq << 32 | bits(f) (one system-scope store each, so a host
+// that reads a word with this call's seq in it has the value as well).
 template <bool kLateW2 = false, bool kOneRow = false, class Stage, class Pre>
 __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ W, Stage stage, Pre pre, short* sx,
-                         short* sh1, float* zp, const float* socc, int64_t row0, int rows, float* __restrict__ f) {
+                         short* sh1, float* zp, const float* socc, int64_t row0, int rows, float* __restrict__ f,
+                         unsigned long long* __restrict__ tag = nullptr, unsigned seq = 0u) {
   pre();
   __builtin_amdgcn_sched_barrier(0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -285,19 +288,24 @@ __device__ void mlp_tile(const float* __restrict__ P, const short* __restrict__ 
     for (int w = 0; w < kRowThreads / 64; ++w) z += zp[w * kFusedRows + threadIdx.x];
     z += bias3;
     const float sig = 1.f / (1.f + expf(-z));
-    f[row0 + threadIdx.x] = (1.f - socc[threadIdx.x] / 512.f) + sig - 0.5f;
+    const float out = (1.f - socc[threadIdx.x] / 512.f) + sig - 0.5f;
+    if (tag)
+      __hip_atomic_store(&tag[row0 + threadIdx.x], ((unsigned long long)seq << 32) | __float_as_uint(out),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    else
+      f[row0 + threadIdx.x] = out;
   }
 }
 
 // Network outputs of 32 rows per workgroup.  kFloat: float32 rows X [n][kIn]
 // (n a multiple of 32), rounded to bfloat16 and their occupancy sums taken here;
 // otherwise bfloat16 rows Xb [n][kIn] with their sums in occ [n] (rows >= n read
-// as zero), and the last workgroup to finish raises the host flag (when given).
+// as zero); with `tag` the outputs go out as tagged words (mlp_tile).
 template <bool kFloat>
 __global__ void __launch_bounds__(kRowThreads)
 k_mlp_rows(const float* __restrict__ P, const short* __restrict__ W, const float* __restrict__ X,
            const short* __restrict__ Xb, const float* __restrict__ occ, int n, float* __restrict__ f,
-           unsigned* done_count, unsigned* done_flag, unsigned seq) {
+           unsigned long long* tag, unsigned seq) {
   __shared__ short sx[kFusedRows * kInPitch];
   __shared__ short sh1[kFusedRows * kHPitch];
   __shared__ float zp[(kRowThreads / 64) * kFusedRows];
@@ -327,19 +335,7 @@ k_mlp_rows(const float* __restrict__ P, const short* __restrict__ W, const float
       if (threadIdx.x < kFusedRows) socc[threadIdx.x] = row0 + threadIdx.x < n ? occ[row0 + threadIdx.x] : 0.f;
     }
   };
-  mlp_tile(P, W, stage, [] {}, sx, sh1, zp, socc, row0, (int)min((int64_t)kFusedRows, n - row0), f);
-  if (done_flag) {  // the last workgroup to finish raises the host-visible flag
-    __threadfence_system();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const unsigned prev = atomicAdd(done_count, 1u);
-      if (prev == gridDim.x - 1) {
-        atomicExch(done_count, 0u);  // ready for the next call on the stream
-        __threadfence_system();
-        __hip_atomic_store(done_flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
-    }
-  }
+  mlp_tile(P, W, stage, [] {}, sx, sh1, zp, socc, row0, (int)min((int64_t)kFusedRows, n - row0), f, tag, seq);
 }
 
 // ranker input rows from the occupancy volume, one workgroup per box
@@ -398,8 +394,9 @@ k_rank_inputs(const float* __restrict__ vol, int N, const float* __restrict__ fr
 // are bitwise those of k_rank_inputs + k_mlp_rows<false>.  The volume reads are
 // requested first, then the first layer's weights.  A workgroup's volume gathers
 // (4,352 per box) and weight loads (401 KB) pass one CU's load pipeline, so few
-// boxes per workgroup spread the gathers over more CUs.  The last workgroup to
-// finish raises the host flag (when given).
+// boxes per workgroup spread the gathers over more CUs.  With `tag` the outputs
+// go out as tagged words (mlp_tile): no completion counter or flag, so a
+// workgroup ends right after its own store.
 // Up to kArgBoxes boxes can travel in the kernel arguments (no read of mapped
 // host memory on the critical path).
 constexpr int kArgBoxes = 32;
@@ -411,7 +408,7 @@ template <int kRankRows>
 __global__ void __launch_bounds__(kRowThreads)
 k_rank_fused(const float* __restrict__ P, const short* __restrict__ W, const float* __restrict__ vol, int N,
              const float* __restrict__ frame, const obbv_box* __restrict__ boxes, RankArgBoxes ab, int use_ab,
-             int n, float* __restrict__ f, unsigned* done_count, unsigned* done_flag, unsigned seq) {
+             int n, float* __restrict__ f, unsigned long long* tag, unsigned seq) {
   __shared__ __align__(16) short sx[kFusedRows * kInPitch];
   __shared__ short sh1[kFusedRows * kHPitch];
   __shared__ float zp[(kRowThreads / 64) * kFusedRows];
@@ -467,19 +464,7 @@ k_rank_fused(const float* __restrict__ P, const short* __restrict__ W, const flo
   };
   // the second layer's weights after the stage: requested with the first
   // layer's, they delay the volume gathers in the CU's load pipeline
-  mlp_tile<true, kRankRows == 1>(P, W, stage, pre, sx, sh1, zp, socc, row0, rows, f);
-  if (done_flag) {  // the last workgroup to finish raises the host-visible flag
-    __threadfence_system();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const unsigned prev = atomicAdd(done_count, 1u);
-      if (prev == gridDim.x - 1) {
-        atomicExch(done_count, 0u);  // ready for the next call on the stream
-        __threadfence_system();
-        __hip_atomic_store(done_flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
-    }
-  }
+  mlp_tile<true, kRankRows == 1>(P, W, stage, pre, sx, sh1, zp, socc, row0, rows, f, tag, seq);
 }
 
 struct MlpScratch {
@@ -542,8 +527,7 @@ int mlp_infer_packed(const float* params, const short* packed, const float* X, i
   OBBV_ARG(n >= 0 && n % kFusedRows == 0, "n must be a non-negative multiple of 32");
   if (n == 0) return OBBV_OK;
   hipLaunchKernelGGL(k_mlp_rows<true>, dim3((unsigned)(n / kFusedRows)), dim3(kRowThreads), 0, s, params, packed, X,
-                     (const short*)nullptr, (const float*)nullptr, n, out_f, (unsigned*)nullptr, (unsigned*)nullptr,
-                     0u);
+                     (const short*)nullptr, (const float*)nullptr, n, out_f, (unsigned long long*)nullptr, 0u);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
 }
@@ -559,7 +543,7 @@ size_t mlp_rank_scratch_bytes(int32_t n) { return (((size_t)n * kIn * 2 + 255) &
 
 int mlp_rank_packed(const float* params, const short* packed, const float* volume, int32_t N, const float* frame,
                     const obbv_box* boxes, int32_t n, void* scratch, float* out_f, hipStream_t s,
-                    unsigned* done_count, unsigned* done_flag, unsigned seq, const obbv_box* host_boxes) {
+                    unsigned long long* tag, unsigned seq, const obbv_box* host_boxes) {
   OBBV_ARG(n >= 0 && N >= 1, "bad size");
   if (n == 0) return OBBV_OK;
   RankArgBoxes ab;
@@ -567,13 +551,13 @@ int mlp_rank_packed(const float* params, const short* packed, const float* volum
   if (use_ab) std::memcpy(ab.v, host_boxes, (size_t)n * sizeof(obbv_box));
   if (n <= kRankOneBoxMax) {  // one launch, one box per workgroup
     hipLaunchKernelGGL(k_rank_fused<1>, dim3((unsigned)n), dim3(kRowThreads), 0, s, params, packed, volume, N, frame,
-                       boxes, ab, use_ab, n, out_f, done_count, done_flag, seq);
+                       boxes, ab, use_ab, n, out_f, tag, seq);
     OBBV_HIP(hipGetLastError());
     return OBBV_OK;
   }
   if (n <= kRankFusedMax) {  // one launch, four boxes per workgroup
     hipLaunchKernelGGL(k_rank_fused<4>, dim3((unsigned)((n + 3) / 4)), dim3(kRowThreads), 0, s, params, packed, volume,
-                       N, frame, boxes, ab, use_ab, n, out_f, done_count, done_flag, seq);
+                       N, frame, boxes, ab, use_ab, n, out_f, tag, seq);
     OBBV_HIP(hipGetLastError());
     return OBBV_OK;
   }
@@ -581,8 +565,7 @@ int mlp_rank_packed(const float* params, const short* packed, const float* volum
   float* occ = (float*)((char*)scratch + (((size_t)n * kIn * 2 + 255) & ~(size_t)255));
   hipLaunchKernelGGL(k_rank_inputs, dim3((unsigned)n), dim3(256), 0, s, volume, N, frame, boxes, n, Xb, occ);
   hipLaunchKernelGGL(k_mlp_rows<false>, dim3((unsigned)((n + kFusedRows - 1) / kFusedRows)), dim3(kRowThreads), 0, s,
-                     params, packed, (const float*)nullptr, (const short*)Xb, (const float*)occ, n, out_f, done_count,
-                     done_flag, seq);
+                     params, packed, (const float*)nullptr, (const short*)Xb, (const float*)occ, n, out_f, tag, seq);
   OBBV_HIP(hipGetLastError());
   return OBBV_OK;
 }
@@ -630,8 +613,7 @@ extern "C" int obbv_mlp_rank_boxes(const float* params, const float* volume, int
   OBBV_RET(pool_get(kPoolMlp, (size_t)kPacked * 2, &pv));
   OBBV_RET(pool_get(kPoolRank, mlp_rank_scratch_bytes(n_boxes), &sc));
   OBBV_RET(mlp_pack_impl(params, (short*)pv, s));
-  return mlp_rank_packed(params, (const short*)pv, volume, N, frame, boxes, n_boxes, sc, out_f, s, nullptr, nullptr, 0u,
-                         nullptr);
+  return mlp_rank_packed(params, (const short*)pv, volume, N, frame, boxes, n_boxes, sc, out_f, s, nullptr, 0u, nullptr);
 }
 
 extern "C" int obbv_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, const float* X,
