@@ -953,10 +953,13 @@ int flood_partition(const HostMesh& M, const Elements& E, const std::vector<Grou
   // already contains the element (extent <= half extent on every axis).  Boxes
   // only grow during the flood, so a set bit stays true; a clear bit can turn
   // true only for a box that grew after the mask was taken, and the round
-  // re-tests exactly those boxes.  Groups of more than 64 boxes go without.
+  // re-tests exactly those boxes.  Groups of more than 64 boxes go without, and
+  // OBBV_FLOOD_MASKS=0 turns the masks off (every pop then builds its candidate
+  // boxes), so the two paths can be compared bit for bit.
   size_t max_group = 0;
   for (int g = 0; g < G; ++g) max_group = std::max(max_group, groups[g].boxes.size());
-  const bool use_mask = max_group <= 64;
+  const char* masks_env = getenv("OBBV_FLOOD_MASKS");
+  const bool use_mask = max_group <= 64 && !(masks_env && *masks_env && atoi(masks_env) == 0);
   // the round in which each box last grew (-1: not during this flood)
   std::vector<int64_t> grown_at(boxes.size(), -1);
   auto contains = [](const double* ext, const float h[3]) {

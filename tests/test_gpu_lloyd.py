@@ -127,3 +127,22 @@ def test_jitter_table_gives_the_same_bits_as_computed_draws(api, monkeypatch):
                                         pops_per_round=8)
     for k in ("boxes", "obv", "parent", "tri_node", "e"):
         assert np.array_equal(out["1"][k], out["0"][k]), k
+
+
+def test_containment_masks_give_the_same_bits_as_candidate_boxes(api, monkeypatch):
+    """The flood decides a pop that a box of its group already contains from a
+    containment mask taken while the device works, re-testing only boxes that
+    grew since; with the masks turned off every pop builds its candidate boxes
+    and the decision loop finds the contained ones.  Both must give
+    bit-identical hierarchies and counters."""
+    V, F = synth.noisy_cube_sphere(8, seed=23)
+    Vt, Ft = _dev(V, F)
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("OBBV_FLOOD_MASKS", flag)
+        out[flag] = api.build_hierarchy(Vt, Ft, levels=3, branching=4, iters=3, sweeps=1, R=16, seed=6,
+                                        pops_per_round=8)
+    for k in ("boxes", "obv", "parent", "tri_node", "e"):
+        assert np.array_equal(out["1"][k], out["0"][k]), k
+    assert out["1"]["counters"] == out["0"]["counters"]
+    assert out["1"]["counters"]["trivial"] > 0
