@@ -122,6 +122,10 @@ struct Evaluator {
   int64_t evals = 0;
   int64_t calls = 0;
   std::vector<HBox> fr;  // frames of the current call (host)
+  // frame grouping buffers, reused from call to call: an open-addressing table
+  // of (centre, axes) keys, each box's key group, and the boxes by group
+  std::vector<int32_t> gslot, gfirst, gid, gcount, gstart, gmem;
+  std::vector<int32_t> box_frame;
   // optional uniform sample (reservoir) of the evaluated (box, outer volume) pairs
   int64_t smp_cap = 0, smp_seen = 0;
   std::vector<HBox> smp_box;
@@ -281,29 +285,50 @@ struct Evaluator {
     // (a frame grows while the sum of its half extents stays within 1.6 times
     // that of its smallest box), so small candidates do not walk the triangles
     // of far-grown ones.
-    std::vector<int32_t> box_frame(n);
+    box_frame.resize(n);
     fr.clear();
     {
-      std::unordered_map<std::string, int32_t> index;
-      std::vector<std::vector<int32_t>> members;
-      std::string key(48, '\0');
+      // key groups in order of first appearance, boxes in index order within
+      // a group (an open-addressing table over the 48 bytes of centre and axes)
+      size_t tsize = 16;
+      while (tsize < 2 * n) tsize <<= 1;
+      gslot.assign(tsize, -1);  // group of a table slot
+      gfirst.clear();           // first box of each group
+      gid.resize(n);
+      auto same_key = [&](size_t x, size_t y) {
+        return std::memcmp(boxes[x].c, boxes[y].c, 12) == 0 && std::memcmp(boxes[x].Q, boxes[y].Q, 36) == 0;
+      };
       for (size_t i = 0; i < n; ++i) {
-        std::memcpy(&key[0], boxes[i].c, 12);
-        std::memcpy(&key[12], boxes[i].Q, 36);
-        auto it = index.find(key);
-        if (it == index.end()) {
-          it = index.emplace(key, (int32_t)members.size()).first;
-          members.emplace_back();
+        uint32_t w[12];
+        std::memcpy(w, boxes[i].c, 12);
+        std::memcpy(w + 3, boxes[i].Q, 36);
+        uint64_t h = 0x9E3779B97F4A7C15ull;
+        for (int k = 0; k < 12; ++k) h = (h ^ w[k]) * 0xFF51AFD7ED558CCDull;
+        size_t t = (size_t)(h ^ (h >> 29)) & (tsize - 1);
+        while (gslot[t] >= 0 && !same_key((size_t)gfirst[gslot[t]], i)) t = (t + 1) & (tsize - 1);
+        if (gslot[t] < 0) {
+          gslot[t] = (int32_t)gfirst.size();
+          gfirst.push_back((int32_t)i);
         }
-        members[it->second].push_back((int32_t)i);
+        gid[i] = gslot[t];
       }
+      const size_t ng = gfirst.size();
+      gcount.assign(ng, 0);
+      for (size_t i = 0; i < n; ++i) ++gcount[gid[i]];
+      gstart.resize(ng + 1);
+      gstart[0] = 0;
+      for (size_t g = 0; g < ng; ++g) gstart[g + 1] = gstart[g] + gcount[g];
+      gmem.resize(n);
+      for (size_t g = 0; g < ng; ++g) gcount[g] = gstart[g];
+      for (size_t i = 0; i < n; ++i) gmem[gcount[gid[i]]++] = (int32_t)i;
       auto size_of = [](const float h[3]) { return (double)h[0] + (double)h[1] + (double)h[2]; };
-      for (auto& mem : members) {
-        std::stable_sort(mem.begin(), mem.end(), [&](int32_t x, int32_t y) {
-          return size_of(boxes[x].h) < size_of(boxes[y].h);
-        });
+      for (size_t g = 0; g < ng; ++g) {
+        int32_t* m0 = gmem.data() + gstart[g];
+        int32_t* m1 = gmem.data() + gstart[g + 1];
+        std::stable_sort(m0, m1, [&](int32_t x, int32_t y) { return size_of(boxes[x].h) < size_of(boxes[y].h); });
         double limit = -1.0;
-        for (int32_t i : mem) {
+        for (const int32_t* it = m0; it != m1; ++it) {
+          const int32_t i = *it;
           const double si = size_of(boxes[i].h);
           if (fr.empty() || limit < 0.0 || !(si <= limit)) {  // NaN sizes start their own frame
             fr.push_back(boxes[i]);
@@ -314,7 +339,6 @@ struct Evaluator {
           }
           box_frame[i] = (int32_t)fr.size() - 1;
         }
-        limit = -1.0;
       }
     }
     const size_t nf = fr.size();
