@@ -245,6 +245,28 @@ def test_write_pass_slot_strategies_agree(api, monkeypatch):
         assert np.array_equal(out["1"][k], out["0"][k]), k
 
 
+def test_work_item_sizes_and_record_loading_agree(api, monkeypatch):
+    """Ray-test work items of 64 or 4096 records instead of the default, and the
+    all-rays kernel's scalar record loads instead of LDS staging, split and
+    load the same bin entries differently; every box and ray gets the same
+    bits."""
+    V, F = synth.noisy_torus(nu=64, nv=32)
+    c, a, h = synth.random_boxes(16, seed=73, center_range=1.0, half_range=(0.1, 0.7))
+    Vt, Ft, B = _dev(api, V, F, c, a, h)
+    out = {}
+    for raster, chunk, stage in (("1", "384", "1"), ("1", "64", "1"), ("1", "4096", "1"), ("0", "384", "1"),
+                                 ("0", "384", "0"), ("0", "64", "0")):
+        monkeypatch.setenv("OBBV_TEST_RASTER", raster)
+        monkeypatch.setenv("OBBV_TEST_CHUNK", chunk)
+        monkeypatch.setenv("OBBV_TEST_STAGE", stage)
+        r = api.outer_volume_ex(Vt, Ft, B, 64, seed=8, tile=16, rays=True)
+        out[(raster, chunk, stage)] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
+    ref = out[("1", "384", "1")]
+    for key, got in out.items():
+        for k in ("obv", "ray_q", "ray_hits"):
+            assert np.array_equal(got[k], ref[k]), (key, k)
+
+
 def test_validate_mesh(api):
     import torch
     V, F = synth.icosphere(2)
