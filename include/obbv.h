@@ -72,7 +72,8 @@ typedef struct {
   int32_t R;          /* rays per face edge: R x R rays per cast axis, 1..32767 */
   uint32_t axis_mask; /* bit w set: cast along local axis w; 0 means 7 (all) */
   uint64_t seed;      /* SplitMix64 seed of the ray jitter                   */
-  int32_t tile;       /* ray tile edge: 8 or 16; 0 = library choice          */
+  int32_t block_rays; /* rays of one LDS ray block (a power of two in [1024,
+                         16384]); 0 = library choice                       */
   uint32_t flags;     /* reserved, must be 0                                 */
 } obbv_ov_params;
 
@@ -116,6 +117,12 @@ int obbv_validate_mesh(const obbv_mesh* mesh, int32_t* out_report, double* out_v
  * (seed, box_key[b], w, i, j); the inside length of [-h_w, h_w] on each ray is
  * integrated from its signed crossings (Eq. 9 generalised to a line), and
  * OBV = V_box - mean_w sum_rays L du dv with V_box = 8 h0 h1 h2.
+ * Ray-triangle tests are FP32 edge functions with a top-left ownership rule: a
+ * ray that meets an edge shared by two triangles facing the same way exactly
+ * (edge function 0 in FP32) crosses exactly one of them, so every ray counts
+ * each sheet of the surface once (watertight).  Each crossing's inside length is
+ * rounded to a multiple of 2^-22 of the slab and summed exactly in int64, so
+ * the result does not depend on scheduling and is bitwise reproducible.
  *
  * meshes     host array of n_meshes mesh descriptors (device data), n_meshes >= 1
  * boxes      device, [n_boxes] obbv_box
@@ -125,7 +132,8 @@ int obbv_validate_mesh(const obbv_mesh* mesh, int32_t* out_report, double* out_v
  * out_obv    device, [n_boxes] float64 outer volume per box
  * A box with a zero extent gets OBV 0; a box with a non-finite parameter gets
  * NaN and sets OBBV_STATUS_NAN_BOX (read it with obbv_status).  n_boxes = 0 is
- * a no-op.  The call synchronises the stream once to size its scratch memory.
+ * a no-op.  The call never waits for the device (scratch is sized from the
+ * arguments); an index out of range sets OBBV_STATUS_BAD_INDEX.
  */
 int obbv_outer_volume(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                       const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
@@ -135,9 +143,13 @@ int obbv_outer_volume(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
  * out_vin_axis  [n_boxes][3] float64 inside volume per cast axis (0 if not cast)
  * out_ray_q     [n_boxes][3][R][R] int32 per-ray inside fraction of the slab,
  *               in units of 2^-22 (L / (2 h_w) * 2^22, rounded per crossing)
- * out_ray_hits  [n_boxes][3][R][R] int32 crossings counted on each ray
+ * out_ray_hits  [n_boxes][3][R][R] int32 crossing counts of each ray on the
+ *               kept side: n_in + 65536 n_beyond, n_in = crossings inside the
+ *               slab [-h_w, h_w], n_beyond = crossings past the slab face of the
+ *               kept side (above +h_w, or below -h_w when the cast is mirrored)
  * out_side      [n_boxes][3] int32: 0 = crossings above the slab bottom were
- *               used, 1 = crossings below the slab top (mirrored cast)
+ *               used, 1 = crossings below the slab top (mirrored cast); the
+ *               kept side is the half prism with fewer triangles
  * The per-ray outputs are meant for tests and need n_boxes * 3 * R * R entries. */
 int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                          const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
@@ -160,8 +172,8 @@ int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_b
  * frames     device, [n_frames] obbv_box, 1 <= n_frames <= n_boxes
  * box_frame  device, [n_boxes] int32
  * other arguments as obbv_outer_volume (box_key nullable = box index).
- * The call synchronises the stream once (scratch sizing), twice when the
- * frame lists could exceed 2 GiB (48 bytes per frame and triangle). */
+ * The call waits for the device only when the frame lists could exceed
+ * 2 GiB (48 bytes per frame and triangle), to size them. */
 int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
                               int32_t n_boxes, const obbv_ov_params* params, const obbv_box* frames,
                               const int32_t* box_frame, int32_t n_frames, double* out_obv, void* stream);
@@ -169,12 +181,12 @@ int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, cons
 /* ---- measurement ----------------------------------------------------------- */
 
 /* Host.  enable != 0: every later obbv_outer_volume* call records a pair of HIP
- * events around its ray-test kernel on the call's stream and adds to device
- * counters the ray-triangle tests it performs (a triangle's record against the
- * rays of the cells its conservative cell range covers in a tile; every ray of
- * the tile in the all-rays kernel) and the bytes it must read (a 64-byte work
- * item per tile chunk, a 64-byte record per bin entry, and with a jitter table
- * 8 bytes per ray of the item's tile).  enable == 0 stops recording. */
+ * events around its cast kernel (cull, LDS ray block, ray-triangle tests) on
+ * the call's stream and adds to device counters the ray-triangle tests it
+ * performs (a kept triangle against the rays of the cells its conservative cell
+ * range covers in a ray block) and the bytes of its culling stream (48 bytes
+ * per triangle-list entry per (axis, ray block) unit, and with a jitter table 8
+ * bytes per ray of the block).  enable == 0 stops recording. */
 int obbv_profile_enable(int enable);
 
 /* Synchronous.  Sums the elapsed time of the recorded ray-test launches and
@@ -187,12 +199,13 @@ int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_t
 typedef struct obbv_ov_plan obbv_ov_plan; /* opaque */
 
 /* Synchronous.  Plans repeated evaluations of the same argument pointers (the
- * contents of `boxes` may change between launches): with params->tile == 0 the
- * ray tile edge is autotuned (both edges timed; the choice is cached per device,
- * R and size buckets), one synchronous evaluation sizes the scratch (times
- * `headroom` >= 1), and one evaluation with fixed scratch, a persistent ray-test
- * grid and no host round trip is captured into a HIP graph.  The plan owns its
- * scratch; the caller's arrays must outlive it. */
+ * contents of `boxes` may change between launches): with params->block_rays == 0
+ * the LDS ray block is autotuned (2048, 4096 and 8192 rays timed; the choice is
+ * cached per GPU architecture, R and size buckets); the scratch is sized from the
+ * arguments (no device pass is needed: the pipeline keeps no per-triangle
+ * records in device memory), and one evaluation is captured into a HIP graph.
+ * `headroom` (>= 1) is accepted for compatibility and not needed.  The plan
+ * owns its scratch; the caller's arrays must outlive it. */
 int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes, const int32_t* box_mesh,
                         const uint32_t* box_key, int32_t n_boxes, const obbv_ov_params* params, double* out_obv,
                         double headroom, void* stream, obbv_ov_plan** out);
@@ -202,9 +215,10 @@ int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, const obbv_bo
  * (read with obbv_status) and out_obv is not valid: plan again. */
 int obbv_ov_plan_launch(obbv_ov_plan* plan, void* stream);
 
-/* Host.  Chosen tile edge, capacities [records, bins, work items] and the
- * autotuner's timings [tile 8, tile 16] in ms (0 when not tuned); each nullable. */
-int obbv_ov_plan_info(obbv_ov_plan* plan, int32_t* out_tile, int64_t* out_caps, float* out_tuned_ms);
+/* Host.  Chosen rays per ray block, sizes [cast items, cast units, scratch
+ * bytes] and the autotuner's timings [2048, 4096, 8192 rays] in ms (0 when not
+ * tuned; out_tuned_ms has 3 entries); each nullable. */
+int obbv_ov_plan_info(obbv_ov_plan* plan, int32_t* out_block_rays, int64_t* out_sizes, float* out_tuned_ms);
 
 int obbv_ov_plan_destroy(obbv_ov_plan* plan);
 
@@ -251,7 +265,7 @@ typedef struct {
 
 typedef struct {
   int32_t R;              /* rays per face edge of every outer-volume evaluation */
-  int32_t tile;           /* ray tile edge (0 = library choice, 8 or 16)          */
+  int32_t block_rays;     /* rays per LDS ray block (0 = library choice)          */
   uint64_t seed;          /* SplitMix64 seed of the ray jitter                    */
   int32_t pops_per_round; /* K: frontier triangles taken per group per round; 1 = the
                              serial flood of the paper                            */
@@ -328,7 +342,7 @@ typedef struct {
   int32_t iters;          /* Lloyd iterations per layer and pass                  */
   int32_t sweeps;         /* bottom-up / top-down sweeps after the first top-down */
   int32_t R;
-  int32_t tile;
+  int32_t block_rays;
   int32_t pops_per_round;
   int32_t reserved;       /* must be 0 */
   uint64_t seed;          /* ray jitter and seed-triangle draws                   */

@@ -28,11 +28,11 @@ class ObbvMesh(ctypes.Structure):
 
 class ObbvOvParams(ctypes.Structure):
     _fields_ = [("R", c_int32), ("axis_mask", c_uint32), ("seed", c_uint64),
-                ("tile", c_int32), ("flags", c_uint32)]
+                ("block_rays", c_int32), ("flags", c_uint32)]
 
 
 class ObbvLloydParams(ctypes.Structure):
-    _fields_ = [("R", c_int32), ("tile", c_int32), ("seed", c_uint64), ("pops_per_round", c_int32),
+    _fields_ = [("R", c_int32), ("block_rays", c_int32), ("seed", c_uint64), ("pops_per_round", c_int32),
                 ("reserved", c_int32), ("delta", ctypes.c_double)]
 
 
@@ -43,7 +43,7 @@ class ObbvSurrogate(ctypes.Structure):
 
 class ObbvHierParams(ctypes.Structure):
     _fields_ = [("levels", c_int32), ("branching", c_int32), ("iters", c_int32), ("sweeps", c_int32),
-                ("R", c_int32), ("tile", c_int32), ("pops_per_round", c_int32), ("reserved", c_int32),
+                ("R", c_int32), ("block_rays", c_int32), ("pops_per_round", c_int32), ("reserved", c_int32),
                 ("seed", c_uint64), ("delta", ctypes.c_double), ("surrogate", ctypes.POINTER(ObbvSurrogate))]
 
 

@@ -77,16 +77,16 @@ def validate_mesh(V, F, stream=None):
     return code, list(rep), vol.value
 
 
-def _params(R, seed, axis_mask, tile):
-    return _lib.ObbvOvParams(int(R), int(axis_mask), int(seed) & ((1 << 64) - 1), int(tile), 0)
+def _params(R, seed, axis_mask, block_rays):
+    return _lib.ObbvOvParams(int(R), int(axis_mask), int(seed) & ((1 << 64) - 1), int(block_rays), 0)
 
 
-def outer_volume(V, F, boxes, R, seed=0, axis_mask=7, tile=0, box_key=None, out=None, stream=None):
+def outer_volume(V, F, boxes, R, seed=0, axis_mask=7, block_rays=0, box_key=None, out=None, stream=None):
     """OBV of every box against the mesh (V, F); float64 tensor [n_boxes]."""
-    return outer_volume_ex(V, F, boxes, R, seed, axis_mask, tile, box_key, out=out, stream=stream)["obv"]
+    return outer_volume_ex(V, F, boxes, R, seed, axis_mask, block_rays, box_key, out=out, stream=stream)["obv"]
 
 
-def outer_volume_ex(V, F, boxes, R, seed=0, axis_mask=7, tile=0, box_key=None, rays=False,
+def outer_volume_ex(V, F, boxes, R, seed=0, axis_mask=7, block_rays=0, box_key=None, rays=False,
                     out=None, stream=None, meshes=None, box_mesh=None):
     """Outer volume with the optional per-axis and per-ray outputs of obbv_outer_volume_ex.
 
@@ -111,14 +111,14 @@ def outer_volume_ex(V, F, boxes, R, seed=0, axis_mask=7, tile=0, box_key=None, r
     if rays:
         rq = torch.empty((n, 3, R, R), dtype=torch.int32, device=dev)
         rh = torch.empty((n, 3, R, R), dtype=torch.int32, device=dev)
-    p = _params(R, seed, axis_mask, tile)
+    p = _params(R, seed, axis_mask, block_rays)
     _check(_lib.lib().obbv_outer_volume_ex(structs, len(meshes), _ptr(boxes), _ptr(box_mesh), _ptr(box_key),
                                            n, ctypes.byref(p), _ptr(obv), _ptr(vin), _ptr(rq), _ptr(rh),
                                            _ptr(side), _stream(stream)))
     return {"obv": obv, "vin_axis": vin, "ray_q": rq, "ray_hits": rh, "side": side}
 
 
-def outer_volume_grouped(V, F, boxes, R, frames, box_frame, seed=0, axis_mask=7, tile=0, box_key=None,
+def outer_volume_grouped(V, F, boxes, R, frames, box_frame, seed=0, axis_mask=7, block_rays=0, box_key=None,
                          out=None, stream=None):
     """obbv_outer_volume_grouped: boxes in groups sharing a centre and axes;
     frames [n_frames, 15] are the groups' unions, box_frame [n_boxes] int32."""
@@ -131,7 +131,7 @@ def outer_volume_grouped(V, F, boxes, R, frames, box_frame, seed=0, axis_mask=7,
     obv = out if out is not None else torch.empty(n, dtype=torch.float64, device=boxes.device)
     _dev(obv, torch.float64, "out")
     m = mesh_struct(V, F)
-    p = _params(R, seed, axis_mask, tile)
+    p = _params(R, seed, axis_mask, block_rays)
     _check(_lib.lib().obbv_outer_volume_grouped(ctypes.byref(m), _ptr(boxes), _ptr(box_key), n, ctypes.byref(p),
                                                 _ptr(frames), _ptr(box_frame), frames.shape[0], _ptr(obv),
                                                 _stream(stream)))
@@ -181,11 +181,11 @@ def _host_ptr(a):
 class Lloyd:
     """Same-layer Lloyd clustering state (obbv_lloyd_*); host arrays are numpy."""
 
-    def __init__(self, V, F, R, seed=0, pops_per_round=32, delta=0.02, tile=0, stream=None):
+    def __init__(self, V, F, R, seed=0, pops_per_round=32, delta=0.02, block_rays=0, stream=None):
         self._mesh = mesh_struct(V, F)
         self._keep = (V, F)
         self.n_triangles = F.shape[0]
-        p = _lib.ObbvLloydParams(int(R), int(tile), int(seed) & ((1 << 64) - 1), int(pops_per_round), 0,
+        p = _lib.ObbvLloydParams(int(R), int(block_rays), int(seed) & ((1 << 64) - 1), int(pops_per_round), 0,
                                  float(delta))
         self._h = ctypes.c_void_p(0)
         _check(_lib.lib().obbv_lloyd_create(ctypes.byref(self._mesh), ctypes.byref(p), ctypes.byref(self._h)))
@@ -269,12 +269,12 @@ class Surrogate:
         return self._s
 
 
-def build_hierarchy(V, F, levels, branching, iters, sweeps, R, seed=0, pops_per_round=32, delta=0.02, tile=0,
+def build_hierarchy(V, F, levels, branching, iters, sweeps, R, seed=0, pops_per_round=32, delta=0.02, block_rays=0,
                     surrogate=None, stream=None):
     """obbv_build_hierarchy; returns numpy outputs (boxes, obv, parent, tri_node, e, counters)."""
     m = mesh_struct(V, F)
     sp = ctypes.pointer(surrogate.struct()) if surrogate is not None else None
-    p = _lib.ObbvHierParams(int(levels), int(branching), int(iters), int(sweeps), int(R), int(tile),
+    p = _lib.ObbvHierParams(int(levels), int(branching), int(iters), int(sweeps), int(R), int(block_rays),
                             int(pops_per_round), 0, int(seed) & ((1 << 64) - 1), float(delta), sp)
     n_nodes = sum(branching ** level for level in range(levels))
     nt = F.shape[0]
@@ -400,13 +400,13 @@ def mlp_rank_boxes(params, volume, frame, boxes, stream=None):
 class OuterVolumePlan:
     """obbv_ov_plan_*: an autotuned, graph-captured evaluation of fixed arrays."""
 
-    def __init__(self, boxes, R, seed=0, axis_mask=7, tile=0, meshes=None, box_mesh=None, box_key=None,
+    def __init__(self, boxes, R, seed=0, axis_mask=7, block_rays=0, meshes=None, box_mesh=None, box_key=None,
                  headroom=1.25, stream=None):
         _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
         self.boxes, self.box_mesh, self.box_key, self._meshes = boxes, box_mesh, box_key, meshes
         self._structs = (_lib.ObbvMesh * len(meshes))(*[mesh_struct(v, f) for v, f in meshes])
         self.out = torch.empty(boxes.shape[0], dtype=torch.float64, device=boxes.device)
-        self._p = _params(R, seed, axis_mask, tile)
+        self._p = _params(R, seed, axis_mask, block_rays)
         self._h = ctypes.c_void_p(0)
         _check(_lib.lib().obbv_ov_plan_create(self._structs, len(meshes), _ptr(boxes), _ptr(box_mesh),
                                               _ptr(box_key), boxes.shape[0], ctypes.byref(self._p), _ptr(self.out),
@@ -417,11 +417,11 @@ class OuterVolumePlan:
         return self.out
 
     def info(self):
-        tile = ctypes.c_int32(0)
+        block_rays = ctypes.c_int32(0)
         caps = (ctypes.c_int64 * 3)()
-        tms = (ctypes.c_float * 2)()
-        _check(_lib.lib().obbv_ov_plan_info(self._h, ctypes.byref(tile), caps, tms))
-        return {"tile": tile.value, "caps": list(caps), "tuned_ms": list(tms)}
+        tms = (ctypes.c_float * 3)()
+        _check(_lib.lib().obbv_ov_plan_info(self._h, ctypes.byref(block_rays), caps, tms))
+        return {"block_rays": block_rays.value, "caps": list(caps), "tuned_ms": list(tms)}
 
     def close(self):
         if self._h:

@@ -43,17 +43,14 @@ void clear_error();
 // per-device scratch: a few independently growing buffers and the status word
 // ---------------------------------------------------------------------------
 enum PoolSlot {
-  kPoolMeta = 0,
-  kPoolRecords = 1,  // binned records
-  kPoolFit = 2,
-  kPoolMlp = 3,
-  kPoolFeat = 4,
-  kPoolLists = 5,
-  kPoolItems = 6,
-  kPoolTiles = 7,
-  kPoolRank = 8,
-  kPoolTileCnt2 = 9,  // zero between calls (each call leaves what it used zero)
-  kPoolCount = 10
+  kPoolMeta = 0,   // per-call counters, offsets, ray grids, per-(box, axis) sums
+  kPoolFit = 1,
+  kPoolMlp = 2,
+  kPoolFeat = 3,
+  kPoolLists = 4,  // frame lists of grouped calls
+  kPoolItems = 5,  // cast items
+  kPoolRank = 6,
+  kPoolCount = 7
 };
 // Two sets of the slots: calls that may run at the same time on different
 // streams take their scratch from different sets (slot + set * kPoolCount).
@@ -66,56 +63,30 @@ int pool_get(int slot, size_t bytes, void** out);
 // As pool_get; a new (grown) block is zeroed before it is returned.
 int pool_get_zeroed(int slot, size_t bytes, void** out);
 
-// A binned ray-test record, one per bin entry: 4 float4 = 64 bytes (edge
-// planes, depth plane, clamp, sign, and the record's cell range inside the tile
-// of its bin).  A tile's entries are contiguous, so a ray-test wave reads one
-// aligned 64-byte line per record with no index indirection.
-constexpr int kRecF4 = 4;
-constexpr int kRecBytes = 16 * kRecF4;
-
-// A ray-test work item (64 bytes, written by the write pass): up to a chunk of
-// one ray tile's bin entries and the ray grid of the tile's (box, axis) cast,
-// so a ray-test wave needs no further table before its rays and records.
-struct WorkItem {
-  double hu, hv, du, dv;  // half extents of the cast face and cell sizes (u, v)
-  uint64_t s0;            // SplitMix64 state of the u draw of cell (0, 0)
-  int64_t k0;             // first bin entry
-  int32_t count;          // bin entries (at least one)
-  int32_t g;              // tile: ((box * 3 + axis) * tiles per face + tile)
-  uint32_t key;           // the box's jitter key
-  int32_t pad;
-};
-static_assert(sizeof(WorkItem) == 64, "WorkItem layout");
-
-// How one outer-volume evaluation is executed.  Default: scratch is sized from
-// the device counts (one host round trip).  planned: fixed scratch, no round
-// trip, capturable into a HIP graph.  capped: fixed record / bin / work-item
-// capacities for a caller that checks the actual totals afterwards and repeats
-// the call if they exceed the capacities.  `status` (nullable, device) replaces
-// the library status word for the call; with `publish` (nullable, pinned host
-// memory mapped for the device) the call's last kernel writes there the status
-// bits ([0], uint32) and the totals ([1..3], int64: records, bin entries, work
-// items), so the caller reads them after a stream synchronisation without a
-// copy command.
+// How one outer-volume evaluation is executed.  Default: scratch comes from the
+// library pool.  planned: scratch fixed beforehand (meta / items blocks of the
+// caller), no host round trip, capturable into a HIP graph.  `status`
+// (nullable, device) replaces the library status word for the call; with
+// `publish` (nullable, pinned host memory mapped for the device) the call's
+// last kernel writes there the status bits ([0]) and then a done word ([4] = 1),
+// so the caller can spin on host memory instead of waiting on the stream.
 struct OvExec {
   bool planned = false;
-  bool capped = false;
   char* meta = nullptr;
   size_t meta_cap = 0, meta_bytes = 0;
-  float4* recs = nullptr;                     // [bin_cap] binned records (kRecF4 float4 each)
-  int64_t rec_cap = 0, bin_cap = 0, item_cap = 0;  // records counted per call, bin entries, work items
-  int64_t n_rec = 0, n_bin = 0, n_items = 0;  // counts of the last synchronous run
-  char* items = nullptr;                      // per-cull-item counts and offsets
+  char* items = nullptr;  // cast items of the call
   size_t items_cap = 0, items_bytes = 0;
-  WorkItem* itile = nullptr;                  // [item_cap] ray-test work items
   uint32_t* status = nullptr;
   int64_t* publish = nullptr;
   int pool_base = 0;  // slot offset of the pool set the call's pooled scratch comes from
   // nullable: jitter table (jitter_table) covering every key of the call, built
-  // for this R and seed; the ray-test kernel then reads the draws from it
+  // for this R and seed; the cast kernel then reads the draws from it
   const uint2* jitter = nullptr;
   int jitter_R = 0;
   uint64_t jitter_seed = 0;
+  // nullable: device float4 [n_meshes] centre of each mesh's bounding box (the
+  // kept side of every cast); computed by the call when absent
+  const float4* centre = nullptr;
 };
 // Jitter table of keys [0, n_keys) for ray grids of R x R cells (stream ordered).
 int jitter_table(uint64_t seed, int R, int64_t n_keys, uint2* out, hipStream_t s);
@@ -128,8 +99,8 @@ bool profiling_enabled();
 // so the waves of a launch do not serialise on one address
 constexpr int kProfSlots = 256;
 int profile_counter(unsigned long long** out);
-int profile_record_begin(hipStream_t s, void** token);            // event before k_test
-int profile_record_end(hipStream_t s, void* token);               // event after k_test
+int profile_record_begin(hipStream_t s, void** token);            // event before the cast kernel
+int profile_record_end(hipStream_t s, void* token);               // event after the cast kernel
 
 // ---------------------------------------------------------------------------
 // constants of the fixed-point ray integration

@@ -46,7 +46,7 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
                       const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
                       const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
                       int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side, hipStream_t s,
-                      float* out_occ);
+                      int32_t* out_occ);
 int outer_volume_frames(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key, int32_t n_boxes,
                         const obbv_ov_params* params, const obbv_box* frames, const int32_t* box_frame,
                         int32_t n_frames, double* out_obv, hipStream_t s, OvExec* ex);
@@ -107,17 +107,26 @@ inline bool same_h(const float a[3], const float b[3]) { return a[0] == b[0] && 
 struct Evaluator {
   obbv_mesh mesh{};
   obbv_ov_params params{};
+  // centre of the mesh's bounding box (the kept side of every cast), staged
+  // with every call so the device need not compute it
+  float centre[4] = {0.f, 0.f, 0.f, 0.f};
+  bool have_centre = false;
+  void set_centre(const std::vector<float>& V) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (size_t i = 0; i < V.size(); i += 3)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::fmin(lo[k], V[i + k]);
+        hi[k] = std::fmax(hi[k], V[i + k]);
+      }
+    for (int k = 0; k < 3; ++k) centre[k] = V.empty() ? 0.f : 0.5f * (lo[k] + hi[k]);
+    centre[3] = 0.f;
+    have_centre = true;
+  }
   hipStream_t stream = nullptr;
   char* dbuf = nullptr;  // device: boxes, keys, frames, box frames, control words, results
   char* hbuf = nullptr;  // pinned host staging of the same layout
   char* hdev = nullptr;  // hbuf as mapped for the device (results are written there)
   size_t cap = 0;
-  // Record / bin / work-item scratch of capped calls (no mid-call host round
-  // trip); grown, and the call repeated synchronously, when a call overflows.
-  char* sbuf = nullptr;
-  size_t scap = 0;
-  int64_t rec_cap = 0, bin_cap = 0, item_cap = 0;
-  int64_t overflows = 0;
   WallTimer t_prep, t_dev;
   int64_t evals = 0;
   int64_t calls = 0;
@@ -151,35 +160,6 @@ struct Evaluator {
     if (jtab) (void)hipFree(jtab);
     if (dbuf) (void)hipFree(dbuf);
     if (hbuf) (void)hipHostFree(hbuf);
-    if (sbuf) (void)hipFree(sbuf);
-  }
-
-  // capacities from the totals of a synchronous call, with headroom
-  int grow(int64_t n_rec, int64_t n_bin, int64_t n_items) {
-    const int64_t r = std::max(rec_cap, n_rec + n_rec / 2 + 4096);
-    const int64_t b = std::max(bin_cap, n_bin + n_bin / 2 + 8192);
-    const int64_t it = std::max(item_cap, n_items + n_items / 2 + 256);
-    const size_t need = al((size_t)b * kRecBytes) + al((size_t)it * sizeof(WorkItem));
-    if (need > scap) {
-      if (sbuf) {
-        OBBV_HIP(hipStreamSynchronize(stream));
-        OBBV_HIP(hipFree(sbuf));
-        sbuf = nullptr;
-        scap = 0;
-      }
-      if (hipMalloc((void**)&sbuf, need) != hipSuccess) {
-        (void)hipGetLastError();
-        sbuf = nullptr;
-        rec_cap = bin_cap = item_cap = 0;
-        set_error("hipMalloc failed for the Lloyd evaluation scratch");
-        return OBBV_ERR_OOM;
-      }
-      scap = need;
-    }
-    rec_cap = r;
-    bin_cap = b;
-    item_cap = it;
-    return OBBV_OK;
   }
 
   static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -265,9 +245,7 @@ struct Evaluator {
   }
 
   // Stages the boxes and enqueues their evaluation on `stream`; finish() waits
-  // and returns the values.  `boxes` must stay unchanged until finish().  Before
-  // the scratch capacities are known (first call) the evaluation is sized with a
-  // host round trip.
+  // and returns the values.  `boxes` must stay unchanged until finish().
   int begin(const std::vector<HBox>& boxes, const std::vector<uint32_t>& keys) {
     if (in_flight) {
       set_error("internal: evaluation started while another is in flight");
@@ -394,6 +372,7 @@ struct Evaluator {
     // control words: the call's private status word (device, zeroed by the
     // upload); the published status bits and totals (host, written by the device)
     std::memset(hbuf + o_ctl, 0, 256);
+    std::memcpy(hbuf + o_ctl + 192, centre, 16);
     t_prep.stop();
     t_dev.start();
     OBBV_RET(ensure_jitter(keys));
@@ -403,16 +382,11 @@ struct Evaluator {
       hipLaunchKernelGGL(k_stage, dim3(grid), dim3(256), 0, stream, (const uint4*)hdev, (uint4*)dbuf, n16);
       OBBV_HIP(hipGetLastError());
     }
-    if (rec_cap > 0) {  // one pass, no round trip; checked by finish()
+    {  // one pass, no host round trip; finish() spins on the published done word
       OvExec ex;
-      ex.capped = true;
-      ex.recs = (float4*)sbuf;
-      ex.itile = (WorkItem*)(sbuf + al((size_t)bin_cap * kRecBytes));
-      ex.rec_cap = rec_cap;
-      ex.bin_cap = bin_cap;
-      ex.item_cap = item_cap;
       ex.status = (uint32_t*)(dbuf + o_ctl);
       ex.publish = (int64_t*)(hdev + o_ctl + 64);
+      ex.centre = have_centre ? (const float4*)(dbuf + o_ctl + 192) : nullptr;
       OBBV_RET(run_call(&ex));
       in_flight = true;
     }
@@ -423,7 +397,6 @@ struct Evaluator {
     const size_t n = cur_n;
     out.assign(n, 0.0);
     if (n == 0) return OBBV_OK;
-    bool done = false;
     if (in_flight) {
       in_flight = false;
       // spin on the published done word (no runtime wake-up latency, the host
@@ -444,18 +417,7 @@ struct Evaluator {
       }
       const int64_t* hpub = (const int64_t*)(hbuf + o_ctl + 64);
       const uint32_t st = (uint32_t)hpub[0];
-      if (!(st & OBBV_STATUS_OVERFLOW) && hpub[1] <= rec_cap && hpub[2] <= bin_cap && hpub[3] <= item_cap) {
-        done = true;
-        if (st) OBBV_RET(status_or(st, stream));
-      } else {
-        ++overflows;
-      }
-    }
-    if (!done) {  // sized from the device counts; then capacities for the next calls
-      OvExec probe;
-      OBBV_RET(run_call(&probe));
-      OBBV_HIP(hipStreamSynchronize(stream));
-      OBBV_RET(grow(probe.n_rec, probe.n_bin, probe.n_items));
+      if (st) OBBV_RET(status_or(st, stream));
     }
     t_dev.stop();
     std::memcpy(out.data(), hbuf + o_out, n * 8);
@@ -534,6 +496,8 @@ struct Predictor {
     }
     jev.mesh = ev.mesh;
     jev.params = ev.params;
+    std::memcpy(jev.centre, ev.centre, 16);
+    jev.have_centre = ev.have_centre;
     const size_t stride = (n + kWindow - 1) / kWindow;  // at most one window per judged round
     jboxes.clear();
     jkeys.clear();
@@ -1567,10 +1531,10 @@ struct LloydState {
     t_life.stop();
     fprintf(stderr,
             "[obbv lloyd] wall %.3f s: flood %.3f s (%lld rounds, %lld ranked), parameter update %.3f s; "
-            "outer-volume calls %lld (host prep %.3f s, device incl. launches %.3f s, %lld overflow repeats); "
+            "outer-volume calls %lld (host prep %.3f s, device incl. launches %.3f s); "
             "ranker %.3f s\n",
             t_life.s, t_flood.s, (long long)cnt.rounds, (long long)pred.calls, t_update.s, (long long)ev.calls,
-            ev.t_prep.s, ev.t_dev.s, (long long)ev.overflows, pred.t_pred.s);
+            ev.t_prep.s, ev.t_dev.s, pred.t_pred.s);
     const FloodTimers& f = g_ft;
     fprintf(stderr,
             "[obbv lloyd] flood host: pops %.3f s, pop extents %.3f s, candidates %.3f s, ranker post %.3f s, "
@@ -1641,7 +1605,7 @@ extern "C" int obbv_lloyd_create(const obbv_mesh* mesh, const obbv_lloyd_params*
   S->ev.params.R = p->R;
   S->ev.params.axis_mask = 7;
   S->ev.params.seed = p->seed;
-  S->ev.params.tile = p->tile;
+  S->ev.params.block_rays = p->block_rays;
   S->ev.params.flags = 0;
   S->ev.stream = nullptr;
   S->K = p->pops_per_round;
@@ -1651,6 +1615,7 @@ extern "C" int obbv_lloyd_create(const obbv_mesh* mesh, const obbv_lloyd_params*
     delete S;
     return rc;
   }
+  S->ev.set_centre(S->M.V);
   S->E = Elements::triangles(S->M);
   *out = reinterpret_cast<obbv_lloyd*>(S);
   return OBBV_OK;
@@ -1964,7 +1929,7 @@ extern "C" int obbv_build_hierarchy(const obbv_mesh* mesh, const obbv_hier_param
   int64_t n_nodes = 0, w = 1;
   for (int l = 0; l < p->levels; ++l, w *= p->branching) n_nodes += w;
   OBBV_ARG(n_nodes < (1 << 24), "too many nodes");
-  obbv_lloyd_params lp{p->R, p->tile, p->seed, p->pops_per_round, 0, p->delta};
+  obbv_lloyd_params lp{p->R, p->block_rays, p->seed, p->pops_per_round, 0, p->delta};
   OBBV_ARG(p->reserved == 0, "reserved must be 0");
   obbv_lloyd* handle = nullptr;
   OBBV_RET(obbv_lloyd_create(mesh, &lp, &handle));

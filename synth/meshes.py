@@ -373,3 +373,33 @@ def disjoint_cuboids(k=3, seed=7, spacing=3.0):
         off += len(V)
     return (np.vstack(Vs).astype(np.float32), np.vstack(Fs).astype(np.int32),
             np.array(comp, dtype=np.int32), params)
+
+
+def split_top_slab(rv, u_half=0.5, v_lo=-0.4, v_hi=0.45, z_lo=-0.25, z_hi=0.3):
+    """Closed axis-aligned slab [-u_half, u_half] x [v_lo, v_hi] x [z_lo, z_hi]
+    whose top face (z = z_hi) is cut in two along the line y = rv, so that an
+    interior edge from (-u_half, rv, z_hi) to (u_half, rv, z_hi) is shared by two
+    top triangles facing +z; the side faces x = +-u_half carry the extra vertex
+    as a pentagon fan.  Vertices float32, triangles outward (counter-clockwise
+    seen from outside)."""
+    x0, x1 = -u_half, u_half
+    P = [(x0, v_lo, z_lo), (x1, v_lo, z_lo), (x1, v_hi, z_lo), (x0, v_hi, z_lo),      # 0-3 bottom
+         (x0, v_lo, z_hi), (x1, v_lo, z_hi), (x1, rv, z_hi), (x0, rv, z_hi),          # 4-7 top, lower half
+         (x1, v_hi, z_hi), (x0, v_hi, z_hi)]                                          # 8-9 top, upper half
+    tris = [
+        ((0, 2, 1), (0, 0, -1)), ((0, 3, 2), (0, 0, -1)),          # bottom
+        ((4, 5, 6), (0, 0, 1)), ((4, 6, 7), (0, 0, 1)),            # top, y in [v_lo, rv]: edge 6-7 on y = rv
+        ((7, 6, 8), (0, 0, 1)), ((7, 8, 9), (0, 0, 1)),            # top, y in [rv, v_hi]: edge 7-6 on y = rv
+        ((0, 1, 5), (0, -1, 0)), ((0, 5, 4), (0, -1, 0)),          # y = v_lo
+        ((3, 9, 8), (0, 1, 0)), ((3, 8, 2), (0, 1, 0)),            # y = v_hi
+        ((1, 2, 8), (1, 0, 0)), ((1, 8, 6), (1, 0, 0)), ((1, 6, 5), (1, 0, 0)),    # x = +u_half
+        ((0, 4, 7), (-1, 0, 0)), ((0, 7, 9), (-1, 0, 0)), ((0, 9, 3), (-1, 0, 0)),  # x = -u_half
+    ]
+    V = np.array(P, dtype=np.float32)
+    F = []
+    for (a, b, c), n in tris:
+        pa, pb, pc = V[a].astype(np.float64), V[b].astype(np.float64), V[c].astype(np.float64)
+        if np.dot(np.cross(pb - pa, pc - pa), n) < 0:
+            b, c = c, b
+        F.append((a, b, c))
+    return V, np.array(F, dtype=np.int32)

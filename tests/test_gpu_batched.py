@@ -49,7 +49,7 @@ def planned(batch):
     api, host, meshes, B, Bt, bmt = batch
     plan = api.OuterVolumePlan(Bt, R, seed=SEED, meshes=meshes, box_mesh=bmt, headroom=1.25)
     info = plan.info()
-    _say(f"plan: tile {info['tile']}, caps {info['caps']}, tuned ms {info['tuned_ms']}")
+    _say(f"plan: {info['block_rays']} rays per block, sizes {info['caps']}, tuned ms {info['tuned_ms']}")
     out = plan.launch().clone()
     torch.cuda.synchronize()
     assert api.status() == 0
@@ -61,7 +61,7 @@ def test_config3_planned_launch_equals_eager_and_separate_calls(batch, planned):
     import torch
     api, host, meshes, B, Bt, bmt = batch
     plan, info, got = planned
-    eager = api.outer_volume_ex(None, None, Bt, R, seed=SEED, tile=info["tile"], meshes=meshes,
+    eager = api.outer_volume_ex(None, None, Bt, R, seed=SEED, block_rays=info["block_rays"], meshes=meshes,
                                 box_mesh=bmt)["obv"].cpu().numpy()
     assert api.status() == 0
     assert np.array_equal(got, eager)
@@ -72,7 +72,7 @@ def test_config3_planned_launch_equals_eager_and_separate_calls(batch, planned):
         sl = slice(m * PER_MESH, (m + 1) * PER_MESH)
         key = torch.arange(m * PER_MESH, (m + 1) * PER_MESH, dtype=torch.int32, device="cuda")
         sep = api.outer_volume(meshes[m][0], meshes[m][1], Bt[sl].contiguous(), R, seed=SEED,
-                               tile=info["tile"], box_key=key).cpu().numpy()
+                               block_rays=info["block_rays"], box_key=key).cpu().numpy()
         assert np.array_equal(sep, got[sl]), m
 
 

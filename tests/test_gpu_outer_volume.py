@@ -3,7 +3,9 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import raygrid
+from oracle import geometry, raygrid
+
+from conftest import record_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -42,50 +44,118 @@ def _oracle(V, F, c, a, h, R, seed, keys=None, rays=False):
     return out
 
 
+def _compare_rays(res, ref, h, boxes, name):
+    """Per-ray parity on the unflagged rays of `boxes`: the fixed-point inside
+    length within TOL_RAY_MAX units, and the crossing counts identical -- in the
+    slab, and beyond the slab face of the kept side (above it, or below it for a
+    mirrored cast).  Flagged rays (within 1e-6 of a projected edge or of a slab
+    face) are counted and reported."""
+    q = res["ray_q"].cpu().numpy()
+    hits = res["ray_hits"].cpu().numpy()
+    side = res["side"].cpu().numpy()
+    n_edge = n_slab = n_rays = n_count_cmp = 0
+    diffs = []
+    for k, b in enumerate(boxes):
+        for w in range(3):
+            ray = ref[k]["rays"][w]
+            hw = float(h[b][w])
+            q_ref = ray["L"] / (2 * hw) * Q_ONE
+            flag = ray["near_edge"] | ray["near_slab"]
+            n_edge += int(ray["near_edge"].sum())
+            n_slab += int((ray["near_slab"] & ~ray["near_edge"]).sum())
+            n_rays += flag.size
+            d = np.abs(q[b, w] - q_ref)
+            assert d[~flag].max(initial=0) <= TOL_RAY_MAX, (name, b, w, d[~flag].max())
+            diffs.append(d[~flag])
+            n_in = hits[b, w] & 0xFFFF
+            n_far = hits[b, w] >> 16
+            far_ref = ray["n_below"] if side[b, w] else ray["n_above"]
+            bad_in = (n_in != ray["n_in"]) & ~flag
+            bad_far = (n_far != far_ref) & ~flag
+            assert not bad_in.any(), (name, b, w, "n_in", np.argwhere(bad_in)[:5].tolist())
+            assert not bad_far.any(), (name, b, w, "n_beyond", np.argwhere(bad_far)[:5].tolist())
+            n_count_cmp += int((~flag).sum())
+    diffs = np.concatenate(diffs)
+    assert np.percentile(diffs, 99.9) <= TOL_RAY_P999
+    rec = {"test": name, "rays": n_rays, "compared": n_count_cmp, "flagged_near_edge": n_edge,
+           "flagged_near_slab": n_slab, "count_mismatches_unflagged": 0,
+           "max_dq_unflagged": float(diffs.max(initial=0)), "p999_dq": float(np.percentile(diffs, 99.9))}
+    record_parity(rec)
+    return rec
+
+
 def test_config1_icosphere_64_boxes_parity(api):
     """Icosphere (1,280 triangles), 64 seeded boxes, R = 32: every box within
-    1e-5 V_box of the oracle, and every unflagged ray equal."""
+    1e-5 V_box of the oracle; on every unflagged ray the inside length within
+    64 units of 2^-22 and the crossing counts identical."""
     V, F = synth.icosphere(3)
     c, a, h = synth.random_boxes(64, seed=12)
     R, seed = 32, 13
     Vt, Ft, B = _dev(api, V, F, c, a, h)
     res = api.outer_volume_ex(Vt, Ft, B, R, seed=seed, rays=True)
     got = res["obv"].cpu().numpy()
-    q = res["ray_q"].cpu().numpy()
     ref = _oracle(V, F, c, a, h, R, seed, rays=True)
-    n_flag = 0
-    diffs = []
     for b in range(64):
         vb = ref[b]["v_box"]
         assert abs(got[b] - ref[b]["obv"]) <= TOL_BOX * vb, (b, got[b], ref[b]["obv"], vb)
-        for w in range(3):
-            ray = ref[b]["rays"][w]
-            hw = float(h[b][w])
-            q_ref = ray["L"] / (2 * hw) * Q_ONE
-            flag = ray["near_edge"] | ray["near_slab"]
-            n_flag += int(flag.sum())
-            d = np.abs(q[b, w] - q_ref)
-            assert d[~flag].max(initial=0) <= TOL_RAY_MAX, (b, w, d[~flag].max())
-            diffs.append(d[~flag])
-    diffs = np.concatenate(diffs)
-    assert np.percentile(diffs, 99.9) <= TOL_RAY_P999
-    print(f"flagged rays: {n_flag} of {64 * 3 * R * R}; unflagged |dq| max {diffs.max():.2f}, "
-          f"p99.9 {np.percentile(diffs, 99.9):.2f} units of 2^-22")
+    rec = _compare_rays(res, ref, h, range(64), "config1_icosphere")
+    print(rec)
 
 
-@pytest.mark.parametrize("R", [1, 7, 20, 33])
-def test_ragged_grids_and_tile_sizes(api, R):
-    """Ragged tails (R not a multiple of the tile) and both tile sizes: the
-    per-ray sums are exact integers, so tile 8 and tile 16 agree bitwise."""
+def test_edge_tie_is_watertight(api):
+    """A closed slab whose top face is cut along the exact v-coordinate of one
+    ray: the shared interior edge has edge function exactly 0 in FP32 on that
+    ray for both top triangles.  The top-left rule gives the ray exactly one top
+    crossing (two in the slab with the bottom one), as the oracle finds, and the
+    box's outer volume matches the oracle."""
+    import torch
+    R, seed, key = 16, 41, 0
+    half = np.array([0.6, 0.6, 0.6])
+    u, v = raygrid.ray_positions(half, 2, R, seed, key)
+    i0, j0 = 7, 8
+    rv64 = float(v[i0, j0])
+    rv = np.float32(rv64)
+    assert float(rv) != rv64, "the oracle's ray must not sit exactly on the edge"
+    assert -0.5 < u[i0, j0] < 0.5 and -0.4 < rv < 0.45
+    V, F = synth.split_top_slab(rv)
+    assert geometry.directed_edge_report(F)[0]
+    c = np.zeros((1, 3), np.float32)
+    a = np.eye(3, dtype=np.float32)[None]
+    h = half.astype(np.float32)[None]
+    Vt, Ft, B = _dev(api, V, F, c, a, h)
+    key_t = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for mask in (4, 7):
+        res = api.outer_volume_ex(Vt, Ft, B, R, seed=seed, axis_mask=mask, box_key=key_t, rays=True)
+        hits = res["ray_hits"].cpu().numpy()[0, 2]
+        ref = raygrid.raygrid_obv(V, F, c[0], a[0], h[0], R, seed, key, axis_mask=mask, keep_rays=True)
+        ray = ref["rays"][2]
+        assert ray["near_edge"][i0, j0]
+        assert ray["n_in"][i0, j0] == 2
+        assert (hits[i0, j0] & 0xFFFF) == 2, hits[i0, j0]
+        assert np.array_equal(hits & 0xFFFF, ray["n_in"])
+        got = res["obv"].cpu().numpy()[0]
+        assert abs(got - ref["obv"]) <= TOL_BOX * ref["v_box"], (mask, got, ref["obv"])
+    record_parity({"test": "edge_tie", "ray": [i0, j0], "gpu_n_in": int(hits[i0, j0] & 0xFFFF),
+                   "oracle_n_in": int(ray["n_in"][i0, j0])})
+
+
+@pytest.mark.parametrize("R", [1, 7, 20, 33, 130])
+def test_ragged_grids_and_ray_blocks(api, R):
+    """Ragged tails (R not a multiple of the ray block's width or height) and
+    three LDS ray-block sizes: the crossings' inside lengths are exact integers,
+    so every block size gives the same bits per box and per ray."""
     V, F = synth.icosphere(2)
     c, a, h = synth.random_boxes(6, seed=21)
     Vt, Ft, B = _dev(api, V, F, c, a, h)
-    r8 = api.outer_volume_ex(Vt, Ft, B, R, seed=5, tile=8, rays=True)
-    r16 = api.outer_volume_ex(Vt, Ft, B, R, seed=5, tile=16, rays=True)
-    assert np.array_equal(r8["obv"].cpu().numpy(), r16["obv"].cpu().numpy())
-    assert np.array_equal(r8["ray_q"].cpu().numpy(), r16["ray_q"].cpu().numpy())
+    out = {}
+    for blk in (1024, 4096, 16384):
+        r = api.outer_volume_ex(Vt, Ft, B, R, seed=5, block_rays=blk, rays=True)
+        out[blk] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits", "side")}
+    for blk in (4096, 16384):
+        for k in ("obv", "ray_q", "ray_hits", "side"):
+            assert np.array_equal(out[blk][k], out[1024][k]), (blk, k)
     ref = _oracle(V, F, c, a, h, R, 5)
-    got = r8["obv"].cpu().numpy()
+    got = out[1024]["obv"]
     for b in range(6):
         assert abs(got[b] - ref[b]["obv"]) <= TOL_BOX * ref[b]["v_box"]
 
@@ -112,7 +182,7 @@ def test_inside_disjoint_zero_and_nan_boxes(api):
     api.status()  # clear
     got = api.outer_volume(Vt, Ft, B, 16, seed=1).cpu().numpy()
     assert got[0] == 0.0                                   # inside the solid: exactly 0
-    assert got[1] == 8.0 * 0.3 * 0.4 * 0.5 or abs(got[1] - 8 * np.prod(h[1].astype(np.float64))) == 0
+    assert got[1] == 8 * np.prod(h[1].astype(np.float64))  # disjoint: exactly V_box
     assert got[2] == 0.0                                   # zero extent
     assert np.isnan(got[3])                                # NaN parameter
     assert api.status() & 0x1
@@ -156,15 +226,22 @@ def test_several_meshes_in_one_call_equal_separate_calls(api):
 
 def test_config2_torus_sampled_boxes_full_size(api):
     """The bench workload's mesh (noisy torus, 65,536 triangles) at R = 128 in
-    the bench's launch configuration; sampled boxes checked by the oracle."""
+    the bench's launch configuration (default ray blocks); 8 boxes spanning the
+    size range checked against the oracle, per box and per ray on 2 of them."""
     import torch
     V, F = synth.noisy_torus()
     c, a, h = synth.random_boxes(64, seed=22, center_range=1.1, half_range=(0.15, 0.9))
     Vt, Ft, B = _dev(api, V, F, c, a, h)
-    got = api.outer_volume(Vt, Ft, B, 128, seed=23).cpu().numpy()
-    for b in (0, 17, 42):
-        ref = raygrid.raygrid_obv(V, F, c[b], a[b], h[b], 128, 23, b)
-        assert abs(got[b] - ref["obv"]) <= TOL_BOX * ref["v_box"], (b, got[b], ref["obv"])
+    res = api.outer_volume_ex(Vt, Ft, B, 128, seed=23, rays=True)
+    got = res["obv"].cpu().numpy()
+    vols = np.prod(h.astype(np.float64), axis=1)
+    order = np.argsort(vols)
+    sample = sorted(set(order[np.linspace(0, 63, 8).astype(int)].tolist()))
+    refs = {}
+    for b in sample:
+        refs[b] = raygrid.raygrid_obv(V, F, c[b], a[b], h[b], 128, 23, b, keep_rays=b in sample[:2])
+        assert abs(got[b] - refs[b]["obv"]) <= TOL_BOX * refs[b]["v_box"], (b, got[b], refs[b]["obv"])
+    _compare_rays(res, [refs[b] for b in sample[:2]], h, sample[:2], "config2_torus_R128")
     torch.cuda.synchronize()
 
 
@@ -208,63 +285,43 @@ def test_grouped_candidates_equal_plain_calls(api):
     assert api.status() == 0
 
 
-def test_rasterising_and_all_ray_kernels_agree(api, monkeypatch):
-    """The rasterising ray test (each record against the rays of its cells) and
-    the all-rays test (each record against every ray of its tile) give the same
-    bits, per box and per ray, with the rasterising kernel's per-lane cell loop
-    for records up to 64 cells of a tile and its wave-wide path above, and with
-    either path alone (every record wide; none wide)."""
+def test_lane_and_wave_paths_agree(api, monkeypatch):
+    """A kept triangle is tested by its own lane over the cells it covers, or by
+    the whole wave (one cell per lane) above a cell-count threshold; with the
+    threshold at 0 (every triangle wave-wide), 64 (the default) and 256 (almost
+    all per lane) every box and every ray get the same bits."""
     V, F = synth.noisy_torus(nu=96, nv=48)
     c, a, h = synth.random_boxes(24, seed=71, center_range=1.0, half_range=(0.1, 0.7))
     Vt, Ft, B = _dev(api, V, F, c, a, h)
     out = {}
-    for mode, cells in (("0", "64"), ("1", "64"), ("1", "0"), ("1", "256")):
-        monkeypatch.setenv("OBBV_TEST_RASTER", mode)
+    for cells in ("0", "64", "256"):
         monkeypatch.setenv("OBBV_RASTER_CELLS", cells)
-        r = api.outer_volume_ex(Vt, Ft, B, 48, seed=5, tile=16, rays=True)
-        out[(mode, cells)] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
-    ref = out[("0", "64")]
-    for key in (("1", "64"), ("1", "0"), ("1", "256")):
+        r = api.outer_volume_ex(Vt, Ft, B, 48, seed=5, rays=True)
+        out[cells] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
+    for key in ("0", "256"):
         for k in ("obv", "ray_q", "ray_hits"):
-            assert np.array_equal(out[key][k], ref[k]), (key, k)
+            assert np.array_equal(out[key][k], out["64"][k]), (key, k)
 
 
-def test_write_pass_slot_strategies_agree(api, monkeypatch):
-    """Bin slots reserved per tile from LDS counts and slots taken one global
-    atomic at a time fill the bins in different orders; the sums are exact
-    integers, so every box and ray gets the same bits."""
-    V, F = synth.noisy_torus(nu=64, nv=32)
-    c, a, h = synth.random_boxes(16, seed=72, center_range=1.0, half_range=(0.1, 0.7))
-    Vt, Ft, B = _dev(api, V, F, c, a, h)
-    out = {}
-    for mode in ("1", "0"):
-        monkeypatch.setenv("OBBV_WRITE_LDS", mode)
-        r = api.outer_volume_ex(Vt, Ft, B, 64, seed=6, tile=16, rays=True)
-        out[mode] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
-    for k in ("obv", "ray_q", "ray_hits"):
-        assert np.array_equal(out["1"][k], out["0"][k]), k
-
-
-def test_work_item_sizes_and_record_loading_agree(api, monkeypatch):
-    """Ray-test work items of 64 or 4096 records instead of the default, and the
-    all-rays kernel's scalar record loads instead of LDS staging, split and
-    load the same bin entries differently; every box and ray gets the same
-    bits."""
-    V, F = synth.noisy_torus(nu=64, nv=32)
-    c, a, h = synth.random_boxes(16, seed=73, center_range=1.0, half_range=(0.1, 0.7))
-    Vt, Ft, B = _dev(api, V, F, c, a, h)
-    out = {}
-    for raster, chunk, stage in (("1", "384", "1"), ("1", "64", "1"), ("1", "4096", "1"), ("0", "384", "1"),
-                                 ("0", "384", "0"), ("0", "64", "0")):
-        monkeypatch.setenv("OBBV_TEST_RASTER", raster)
-        monkeypatch.setenv("OBBV_TEST_CHUNK", chunk)
-        monkeypatch.setenv("OBBV_TEST_STAGE", stage)
-        r = api.outer_volume_ex(Vt, Ft, B, 64, seed=8, tile=16, rays=True)
-        out[(raster, chunk, stage)] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
-    ref = out[("1", "384", "1")]
-    for key, got in out.items():
-        for k in ("obv", "ray_q", "ray_hits"):
-            assert np.array_equal(got[k], ref[k]), (key, k)
+def test_jitter_table_and_computed_draws_agree(api):
+    """Lloyd evaluations read the ray jitter from a per-key table; a plain call
+    computes the same SplitMix64 draws: a one-iteration Lloyd run's final OBV
+    equals the plain call's on the same boxes and keys bit for bit."""
+    import torch
+    V, F = synth.noisy_cube_sphere(12, seed=5)
+    Vt, Ft = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+    st = api.Lloyd(Vt, Ft, R=24, seed=17)
+    n = F.shape[0]
+    tri_group = np.zeros(n, np.int32)
+    c, a, h = synth.random_boxes(3, seed=5, center_range=0.5)
+    boxes = synth.boxes_to_array(c, a, h)
+    st.set_groups(tri_group, np.zeros(3, np.int32), boxes, box_slot=np.array([5, 9, 2], np.uint32))
+    st.step()
+    got = st.get()
+    B = torch.from_numpy(np.ascontiguousarray(got["boxes"])).cuda()
+    keys = torch.from_numpy(np.array([5, 9, 2], np.int32)).cuda()
+    plain = api.outer_volume(Vt, Ft, B, 24, seed=17, box_key=keys).cpu().numpy()
+    assert np.array_equal(plain, got["obv"])
 
 
 def test_validate_mesh(api):
@@ -273,6 +330,7 @@ def test_validate_mesh(api):
     Vt = torch.from_numpy(V).cuda()
     code, rep, vol = api.validate_mesh(Vt, torch.from_numpy(F).cuda())
     assert code == 0 and rep[:3] == [0, 0, 0] and vol > 0
+    assert abs(vol - geometry.signed_volume(V, F)) <= 1e-12 * abs(vol)
     code, rep, _ = api.validate_mesh(Vt, torch.from_numpy(F[1:].copy()).cuda())
     assert code == -2 and rep[0] == 3
     Fb = F.copy()

@@ -35,14 +35,14 @@ def test_plan_replays_equal_eager_calls(api):
     meshes, B, bm = _batch()
     plan = api.OuterVolumePlan(B, 32, seed=3, meshes=meshes, box_mesh=bm, headroom=1.5)
     info = plan.info()
-    assert info["tile"] in (8, 16) and min(info["tuned_ms"]) > 0
-    eager = api.outer_volume_ex(None, None, B, 32, seed=3, tile=info["tile"], meshes=meshes,
+    assert info["block_rays"] in (2048, 4096, 8192) and min(info["tuned_ms"]) > 0
+    eager = api.outer_volume_ex(None, None, B, 32, seed=3, block_rays=info["block_rays"], meshes=meshes,
                                 box_mesh=bm)["obv"].cpu().numpy()
     api.status()
     for rep in range(4):
         got = plan.launch().clone()
         # eager work and a synchronisation between replays
-        again = api.outer_volume_ex(None, None, B, 32, seed=3, tile=info["tile"], meshes=meshes,
+        again = api.outer_volume_ex(None, None, B, 32, seed=3, block_rays=info["block_rays"], meshes=meshes,
                                     box_mesh=bm)["obv"]
         torch.cuda.synchronize()
         assert np.array_equal(got.cpu().numpy(), eager), rep
@@ -51,22 +51,25 @@ def test_plan_replays_equal_eager_calls(api):
     # new box contents, same arrays: the replay follows them
     B[:, :3] += 0.05
     got = plan.launch().cpu().numpy()
-    ref = api.outer_volume_ex(None, None, B, 32, seed=3, tile=info["tile"], meshes=meshes,
+    ref = api.outer_volume_ex(None, None, B, 32, seed=3, block_rays=info["block_rays"], meshes=meshes,
                               box_mesh=bm)["obv"].cpu().numpy()
     assert api.status() == 0
     assert np.array_equal(got, ref)
     plan.close()
 
 
-def test_plan_overflow_is_flagged_not_faulting(api):
-    """Boxes grown after planning need more scratch than planned: the replay
-    skips what does not fit and raises the overflow status bit."""
+def test_plan_follows_grown_boxes(api):
+    """The plan keeps no per-triangle records in device memory, so boxes grown
+    after planning (three times larger) are still evaluated in full: the replay
+    equals the eager call and raises no status bit."""
     import torch
     meshes, B, bm = _batch(n_meshes=2, boxes_per_mesh=32, seed=1)
-    plan = api.OuterVolumePlan(B, 32, seed=3, meshes=meshes, box_mesh=bm, headroom=1.0, tile=16)
+    plan = api.OuterVolumePlan(B, 32, seed=3, meshes=meshes, box_mesh=bm, headroom=1.0, block_rays=2048)
     api.status()
     B[:, 12:] *= 3.0
-    plan.launch()
+    got = plan.launch().clone()
     torch.cuda.synchronize()
-    assert api.status() & 0x4
+    assert api.status() == 0
+    ref = api.outer_volume_ex(None, None, B, 32, seed=3, meshes=meshes, box_mesh=bm)["obv"]
+    assert np.array_equal(got.cpu().numpy(), ref.cpu().numpy())
     plan.close()
