@@ -640,12 +640,14 @@ __device__ inline Rec make_rec(const CastTri& t, bool mirror, float hw) {
       C[k] = __fsub_rn(0.0f, C[k]);
     }
   }
-  // barycentric weight of vertex 0 is E_1 / A2, of vertex 1 is E_2 / A2, of vertex 2 is E_0 / A2
-  const double D = (Ad[1] * t.z[0] + Ad[2] * t.z[1] + Ad[0] * t.z[2]) / t.A2;
-  const double E = (Bd[1] * t.z[0] + Bd[2] * t.z[1] + Bd[0] * t.z[2]) / t.A2;
-  const double F = (Cd[1] * t.z[0] + Cd[2] * t.z[1] + Cd[0] * t.z[2]) / t.A2;
+  // barycentric weight of vertex 0 is E_1 / A2, of vertex 1 is E_2 / A2, of vertex 2 is E_0 / A2;
+  // the fixed-point scale K = s 2^21 / h is folded into the one division
   const double h = hw;
   const double K = (double)s * kHalfQ / h;
+  const double KA = K / t.A2;
+  const double D = (Ad[1] * t.z[0] + Ad[2] * t.z[1] + Ad[0] * t.z[2]) * KA;
+  const double E = (Bd[1] * t.z[0] + Bd[2] * t.z[1] + Bd[0] * t.z[2]) * KA;
+  const double F = (Cd[1] * t.z[0] + Cd[2] * t.z[1] + Cd[0] * t.z[2]) * KA;
   const double zmin = fmin(fmin((double)t.z[0], (double)t.z[1]), (double)t.z[2]);
   const double zmax = fmax(fmax((double)t.z[0], (double)t.z[1]), (double)t.z[2]);
   const double zlo = fmin(fmax(-h, zmin), h);
@@ -667,9 +669,9 @@ __device__ inline Rec make_rec(const CastTri& t, bool mirror, float hw) {
   r.A2 = A[2];
   r.B2 = Bc[2];
   r.C2 = C[2];
-  r.D = (float)(K * D);
-  r.E = (float)(K * E);
-  r.F = (float)(K * (F + h) + (double)kMagic);
+  r.D = (float)D;
+  r.E = (float)E;
+  r.F = (float)(F + K * h + (double)kMagic);
   r.lo = (float)lo;
   r.hi = (float)hi;
   r.s = (float)s;
@@ -949,21 +951,33 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
       // (-hu + (i + xi) du, -hv + (j + eta) dv)
       const int ui0 = s_rng[0], uj0 = s_rng[2];
       const int uw = s_rng[1] - ui0 + 1, nray = uw * (s_rng[3] - uj0 + 1);
-      for (int k = tid; k < nray; k += kCastThreads) {
-        const int dj = k / uw, di = k - dj * uw;
-        const int i = ui0 + di, j = uj0 + dj;
-        double xi, eta;
-        if (TAB) {
-          const uint2 q = a.jitter[((int64_t)rf.key * 3 + w) * a.R * a.R + (int64_t)j * a.R + i];
-          xi = (double)q.x * (1.0 / 16777216.0);
-          eta = (double)q.y * (1.0 / 16777216.0);
-        } else {
-          const uint64_t z = rf.s0 + (uint64_t)(((uint32_t)i << 15) + (uint32_t)j) * (2ull * kGamma);
-          xi = u24(mix64(z));
-          eta = u24(mix64(z + kGamma));
+      for (int k0 = tid; k0 < nray; k0 += 4 * kCastThreads) {
+        // four rays per thread: their jitter is requested (or hashed) before any is used
+        double xi[4], eta[4];
+        int ci[4], cj[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = min(k0 + q * kCastThreads, nray - 1);
+          cj[q] = k / uw;
+          ci[q] = ui0 + k - cj[q] * uw;
+          cj[q] += uj0;
+          if (TAB) {
+            const uint2 jq = a.jitter[((int64_t)rf.key * 3 + w) * a.R * a.R + (int64_t)cj[q] * a.R + ci[q]];
+            xi[q] = (double)jq.x * (1.0 / 16777216.0);
+            eta[q] = (double)jq.y * (1.0 / 16777216.0);
+          } else {
+            const uint64_t z = rf.s0 + (uint64_t)(((uint32_t)ci[q] << 15) + (uint32_t)cj[q]) * (2ull * kGamma);
+            xi[q] = u24(mix64(z));
+            eta[q] = u24(mix64(z + kGamma));
+          }
         }
-        sray[k] = make_float2((float)__dadd_rn(-rf.hu, __dmul_rn(__dadd_rn((double)i, xi), rf.du)),
-                              (float)__dadd_rn(-rf.hv, __dmul_rn(__dadd_rn((double)j, eta), rf.dv)));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = k0 + q * kCastThreads;
+          if (k < nray)
+            sray[k] = make_float2((float)__dadd_rn(-rf.hu, __dmul_rn(__dadd_rn((double)ci[q], xi[q]), rf.du)),
+                                  (float)__dadd_rn(-rf.hv, __dmul_rn(__dadd_rn((double)cj[q], eta[q]), rf.dv)));
+        }
       }
       if (OCC)
         for (int k = tid; k < 512; k += kCastThreads) socc[k] = 0;
