@@ -178,6 +178,23 @@ int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, cons
                               int32_t n_boxes, const obbv_ov_params* params, const obbv_box* frames,
                               const int32_t* box_frame, int32_t n_frames, double* out_obv, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): obbv_outer_volume for one
+ * mesh with every scratch byte in a fixed 32 MiB device array of the library
+ * (one per device, held until the process ends); the call allocates nothing
+ * and never waits for the device.  The caller passes inputs and outputs as for
+ * obbv_outer_volume (box_key nullable = box index); results are bitwise those
+ * of obbv_outer_volume.  out_status (device, nullable): the call ORs its
+ * OBBV_STATUS_* bits there (else into a word of the fixed array, which
+ * obbv_status does not read).  Returns OBBV_ERR_WORKSPACE when the boxes need
+ * more scratch than the array holds (about 16 bytes per box, cast axis and
+ * 4,608 triangles of the mesh, plus 128 bytes per box).  Calls on one device
+ * share the array: calls that overlap in time on one device (different
+ * streams) race and give wrong results; calls ordered on one stream are safe. */
+int obbv_outer_volume_noalloc(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
+                              int32_t n_boxes, const obbv_ov_params* params, double* out_obv,
+                              uint32_t* out_status, void* stream);
+
 /* ---- measurement ----------------------------------------------------------- */
 
 /* Host.  enable != 0: every later obbv_outer_volume* call records a pair of HIP

@@ -62,6 +62,8 @@ SIGNATURES = {
     "obbv_outer_volume_grouped": (c_int32, [ctypes.POINTER(ObbvMesh), c_void_p, c_void_p, c_int32,
                                             ctypes.POINTER(ObbvOvParams), c_void_p, c_void_p, c_int32, c_void_p,
                                             c_void_p]),
+    "obbv_outer_volume_noalloc": (c_int32, [ctypes.POINTER(ObbvMesh), c_void_p, c_void_p, c_int32,
+                                            ctypes.POINTER(ObbvOvParams), c_void_p, c_void_p, c_void_p]),
     "obbv_ov_plan_create": (c_int32, [ctypes.POINTER(ObbvMesh), c_int32, c_void_p, c_void_p, c_void_p, c_int32,
                                       ctypes.POINTER(ObbvOvParams), c_void_p, ctypes.c_double, c_void_p,
                                       ctypes.POINTER(c_void_p)]),

@@ -118,6 +118,24 @@ def outer_volume_ex(V, F, boxes, R, seed=0, axis_mask=7, block_rays=0, box_key=N
     return {"obv": obv, "vin_axis": vin, "ray_q": rq, "ray_hits": rh, "side": side}
 
 
+def outer_volume_noalloc(V, F, boxes, R, seed=0, axis_mask=7, block_rays=0, box_key=None, out=None, status=None,
+                         stream=None):
+    """obbv_outer_volume_noalloc: OBV of every box with the library's fixed
+    scratch array (no device allocation in the call); float64 [n_boxes]."""
+    _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
+    m = mesh_struct(V, F)
+    if box_key is not None:
+        _dev(box_key, torch.int32, "box_key")
+    if status is not None:
+        _dev(status, torch.int32, "status")
+    obv = out if out is not None else torch.empty(boxes.shape[0], dtype=torch.float64, device=boxes.device)
+    _dev(obv, torch.float64, "out")
+    p = _params(R, seed, axis_mask, block_rays)
+    _check(_lib.lib().obbv_outer_volume_noalloc(ctypes.byref(m), _ptr(boxes), _ptr(box_key), boxes.shape[0],
+                                                ctypes.byref(p), _ptr(obv), _ptr(status), _stream(stream)))
+    return obv
+
+
 def outer_volume_grouped(V, F, boxes, R, frames, box_frame, seed=0, axis_mask=7, block_rays=0, box_key=None,
                          out=None, stream=None):
     """obbv_outer_volume_grouped: boxes in groups sharing a centre and axes;

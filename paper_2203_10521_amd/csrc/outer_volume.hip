@@ -30,6 +30,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -1274,7 +1276,11 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   OBBV_ARG(mask <= 7u, "axis_mask has bits above 2");
   OBBV_ARG((int64_t)n_boxes * 6 < (1ll << 31), "too many boxes");
   int max_nt = 0;
-  std::vector<MeshDev> mh((size_t)n_meshes);
+  // the mesh table on the host: a fixed array for a few meshes (no allocation)
+  MeshDev mh_few[4];
+  std::vector<MeshDev> mh_many;
+  if (n_meshes > 4) mh_many.resize((size_t)n_meshes);
+  MeshDev* mh = n_meshes > 4 ? mh_many.data() : mh_few;
   for (int m = 0; m < n_meshes; ++m) {
     OBBV_ARG(meshes[m].n_triangles >= 0 && meshes[m].n_vertices >= 0, "negative mesh size");
     OBBV_ARG(meshes[m].n_triangles == 0 || (meshes[m].triangles && meshes[m].vertices),
@@ -1293,8 +1299,10 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   const CallSizes cs = call_sizes(n_meshes, n_boxes, max_nt, n_frames, meshes[0].n_triangles, bg.nblk, naxes);
 
   uint32_t* status = nullptr;
-  OBBV_RET(status_word(&status));
-  if (ex && ex->status) status = ex->status;
+  if (ex && ex->status)
+    status = ex->status;
+  else
+    OBBV_RET(status_word(&status));
 
   // ---- meta scratch layout (the order of call_sizes) ----
   void* meta_v = nullptr;
@@ -1345,7 +1353,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   // the mesh table goes to the device only with several meshes (one mesh travels
   // in the kernel arguments; a plan keeps its table at the start of its meta block)
   if (!planned && n_meshes > 1)
-    OBBV_HIP(hipMemcpyAsync(d_mesh, mh.data(), sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
+    OBBV_HIP(hipMemcpyAsync(d_mesh, mh, sizeof(MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
   const MeshDev* d_meshes = n_meshes > 1 ? (const MeshDev*)d_mesh : nullptr;
 
   // mesh centres (the kept side of every cast): given by the caller, or from
@@ -1527,6 +1535,79 @@ extern "C" int obbv_outer_volume(const obbv_mesh* meshes, int32_t n_meshes, cons
   obbv::clear_error();
   return obbv::outer_volume_impl(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, params, out_obv,
                                  nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free evaluation: scratch in a fixed device array
+// ---------------------------------------------------------------------------
+namespace obbv {
+namespace {
+// 256 bytes of status word, then the call's meta block and cast items.  Each
+// device holds its own copy until the process ends.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+std::mutex g_noalloc_mutex;
+char* g_noalloc_ptr[64] = {};  // device address of `scratch` on each device (host code must not use the name)
+
+int noalloc_scratch(char** out) {
+  int dev = 0;
+  OBBV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) {
+    set_error("device index out of range");
+    return OBBV_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+      return OBBV_ERR_HIP;
+    }
+    g_noalloc_ptr[dev] = (char*)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return OBBV_OK;
+}
+}  // namespace
+}  // namespace obbv
+
+extern "C" int obbv_outer_volume_noalloc(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
+                                         int32_t n_boxes, const obbv_ov_params* params, double* out_obv,
+                                         uint32_t* out_status, void* stream) {
+  using namespace obbv;
+  clear_error();
+  OBBV_ARG(mesh && params, "NULL argument");
+  OBBV_ARG(n_boxes >= 0, "n_boxes < 0");
+  if (n_boxes == 0) return OBBV_OK;
+  OBBV_ARG(params->R >= 1 && params->R <= 32767, "R must be in [1, 32767]");
+  OBBV_ARG(params->block_rays == 0 || (params->block_rays >= 1024 && params->block_rays <= kBlockRaysMax &&
+                                       (params->block_rays & (params->block_rays - 1)) == 0),
+           "block_rays must be 0 or a power of two in [1024, 16384]");
+  const uint32_t mask = params->axis_mask ? params->axis_mask : 7u;
+  OBBV_ARG(mask <= 7u, "axis_mask has bits above 2");
+  OBBV_ARG(mesh->n_triangles >= 0, "negative mesh size");
+  const int naxes = (int)((mask & 1u) + ((mask >> 1) & 1u) + ((mask >> 2) & 1u));
+  const BlockGeom bg = block_geom(params->R, block_rays_choice(params->block_rays));
+  const CallSizes cs = call_sizes(1, n_boxes, mesh->n_triangles, 0, mesh->n_triangles, bg.nblk, naxes);
+  const size_t need = 256 + align_up(cs.meta) + align_up(cs.items);
+  if (need > kNoAllocScratchBytes) {
+    set_error("obbv_outer_volume_noalloc: the call needs " + std::to_string(need) + " bytes of scratch, more than the " +
+              std::to_string(kNoAllocScratchBytes) + " bytes of the fixed array (fewer boxes per call)");
+    return OBBV_ERR_WORKSPACE;
+  }
+  char* base = nullptr;
+  OBBV_RET(noalloc_scratch(&base));
+  OvExec ex;
+  ex.planned = true;
+  ex.status = out_status ? out_status : (uint32_t*)base;
+  ex.meta = base + 256;
+  ex.meta_cap = align_up(cs.meta);
+  ex.items = ex.meta + ex.meta_cap;
+  ex.items_cap = align_up(cs.items);
+  return outer_volume_run(mesh, 1, boxes, nullptr, box_key, n_boxes, params, out_obv, nullptr, nullptr, nullptr,
+                          nullptr, (hipStream_t)stream, nullptr, &ex, nullptr);
 }
 
 // ---------------------------------------------------------------------------

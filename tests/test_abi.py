@@ -63,3 +63,20 @@ def test_argument_errors_before_any_device_call(L):
 
 def test_version(L):
     assert L.obbv_version().startswith(b"obbv")
+
+
+def test_noalloc_rejects_oversized_calls_before_any_device_call(L):
+    """The allocation-free entry point checks its fixed scratch size on the host:
+    a call whose cast items would not fit returns OBBV_ERR_WORKSPACE (-5) with a
+    message, before it touches the device; bad parameters return -1."""
+    from paper_2203_10521_amd import _lib
+    m = _lib.ObbvMesh(ctypes.c_void_p(16), ctypes.c_void_p(16), 3, 2_000_000)
+    p = _lib.ObbvOvParams(32, 7, 1, 0, 0)
+    rc = L.obbv_outer_volume_noalloc(ctypes.byref(m), ctypes.c_void_p(16), None, 1_000_000, ctypes.byref(p),
+                                     ctypes.c_void_p(16), None, None)
+    assert rc == -5
+    assert b"scratch" in L.obbv_last_error()
+    bad = _lib.ObbvOvParams(0, 7, 1, 0, 0)
+    assert L.obbv_outer_volume_noalloc(ctypes.byref(m), ctypes.c_void_p(16), None, 1, ctypes.byref(bad),
+                                       ctypes.c_void_p(16), None, None) == -1
+    assert L.obbv_outer_volume_noalloc(ctypes.byref(m), None, None, 0, ctypes.byref(p), None, None, None) == 0
