@@ -383,6 +383,20 @@ int obbv_build_hierarchy(const obbv_mesh* mesh, const obbv_hier_params* params, 
                          int32_t* out_parent, int32_t* out_tri_node, double* out_e, int64_t* out_counters,
                          void* stream);
 
+/* ---- top-down OBB tree (comparison baseline) ------------------------------ */
+
+/* Synchronous.  The top-down covariance-box tree the paper compares its
+ * hierarchy with (Sec. 5, Fig. 6: OBB-tree style builders): the root box is the
+ * covariance box of all triangles (obbv_fit); every node's triangles are ordered
+ * by the projection of their centroids (float64) on the longest axis of the
+ * node's box (ties by triangle index) and cut into `branching` parts of equal
+ * count (part = rank * branching / count), each again fitted, down to `levels`
+ * layers (root included, 1..12; branching 2..64).  Node numbering, outputs and
+ * layouts as obbv_build_hierarchy: out_boxes [n_nodes][15], out_parent
+ * [n_nodes], out_tri_node [levels][n_triangles] (host, each nullable). */
+int obbv_build_obb_tree(const obbv_mesh* mesh, int32_t levels, int32_t branching, float* out_boxes,
+                        int32_t* out_parent, int32_t* out_tri_node, void* stream);
+
 /* ---- learned ranker of candidate boxes -------------------------------------- */
 
 /* Occupancy features of boxes: for every box, 8 x 8 rays along local axis 2

@@ -95,6 +95,8 @@ SIGNATURES = {
     "obbv_lloyd_take_records": (c_int32, [c_void_p, ctypes.c_int64, c_void_p, c_void_p,
                                           ctypes.POINTER(ctypes.c_int64)]),
     "obbv_lloyd_destroy": (c_int32, [c_void_p]),
+    "obbv_build_obb_tree": (c_int32, [ctypes.POINTER(ObbvMesh), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                      c_void_p]),
     "obbv_build_hierarchy": (c_int32, [ctypes.POINTER(ObbvMesh), ctypes.POINTER(ObbvHierParams), c_void_p,
                                        c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
 }

@@ -287,6 +287,19 @@ class Surrogate:
         return self._s
 
 
+def build_obb_tree(V, F, levels, branching, stream=None):
+    """obbv_build_obb_tree: the top-down covariance-box tree (numpy outputs)."""
+    m = mesh_struct(V, F)
+    n_nodes = sum(branching ** l for l in range(levels))
+    nt = F.shape[0]
+    boxes = np.empty((n_nodes, BOX_FLOATS), np.float32)
+    parent = np.empty(n_nodes, np.int32)
+    tri_node = np.empty((levels, nt), np.int32)
+    _check(_lib.lib().obbv_build_obb_tree(ctypes.byref(m), int(levels), int(branching), _host_ptr(boxes),
+                                          _host_ptr(parent), _host_ptr(tri_node), _stream(stream)))
+    return {"boxes": boxes, "parent": parent, "tri_node": tri_node}
+
+
 def build_hierarchy(V, F, levels, branching, iters, sweeps, R, seed=0, pops_per_round=32, delta=0.02, block_rays=0,
                     surrogate=None, stream=None):
     """obbv_build_hierarchy; returns numpy outputs (boxes, obv, parent, tri_node, e, counters)."""

@@ -28,6 +28,16 @@ def init_params(seed=0):
             "w3": 0.1 * he(256, 1)[:, 0], "b3": np.zeros(1)}
 
 
+def occupancy_params(seed=0):
+    """A ranker whose network output is 0 for every input (output layer zero):
+    through the same machinery it predicts the occupancy estimate
+    1 - mean occupancy, the heuristic the learned ranker must beat."""
+    p = init_params(seed)
+    p["w3"] = np.zeros(256)
+    p["b3"] = np.zeros(1)
+    return torch.from_numpy(api.mlp_pack(p)).cuda()
+
+
 def make_dataset(meshes, boxes, R=64, seed=0, nb=16):
     """Ranker inputs and targets for every (mesh, box set) pair.
 

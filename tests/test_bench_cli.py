@@ -19,10 +19,20 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_traffic_is_reported_only_for_the_profiled_kernel_source():
     sys.path.insert(0, ROOT)
     import bench
-    sha = bench.raster_source_sha256()
+    sha = bench.cast_source_sha256()
     assert sha is not None and len(sha) == 64
     t = bench.traffic_bytes()
-    if sha == bench.K_TEST_TRAFFIC["source_sha256"]:
-        assert t == bench.K_TEST_TRAFFIC["fetch_bytes_per_launch"] + bench.K_TEST_TRAFFIC["write_bytes_per_launch"]
+    rec = bench.K_CAST_TRAFFIC
+    if rec is not None and sha == rec["source_sha256"]:
+        assert t == rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     else:
         assert t is None
+
+
+def test_kernel_rates_are_algorithmic_flop_over_launch_time():
+    sys.path.insert(0, ROOT)
+    import bench
+    # 2 launches of 1 ms each, 1e9 tests: 5e8 tests per launch x 16 FLOP / 1 ms = 8 TFLOP/s
+    avg_ms, per_launch, tflops, gbps = bench.kernel_rates(2.0, 2, 1_000_000_000, 2_000_000_000)
+    assert avg_ms == 1.0 and per_launch == 5e8
+    assert abs(tflops - 8.0) < 1e-9 and abs(gbps - 1000.0) < 1e-9
