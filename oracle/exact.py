@@ -88,6 +88,11 @@ def triangle_inside_contribution(pa, pb, pc, hu, hv, hw):
         poly = clip_polygon(poly, g)
         if len(poly) < 3:
             return 0
+    if all(p[2] == hw for p in poly):
+        # lying in the plane w = +h_w: both closed half-spaces below would keep
+        # it, but it is one piece, inside over the whole slab
+        a, _ = fan_integrals(poly)
+        return s * 2 * hw * a
     top = clip_polygon(poly, lambda p: p[2] - hw)
     mid = clip_polygon(clip_polygon(poly, lambda p: hw - p[2]), lambda p: p[2] + hw)
     total = 0

@@ -187,3 +187,22 @@ def test_eq5_sum_of_obv_bounds_union_outer_volume():
     outside = winding_number(V, F, pts) < 0.5
     omv = np.prod(hi - lo) * np.mean(in_union & outside)
     assert s >= omv - 4 * np.prod(hi - lo) * np.sqrt(0.25 / n)
+
+
+def test_faces_in_the_box_faces_count_once():
+    """Mesh faces lying exactly in the planes of the box faces (aligned cuboids
+    and their bounding or tight boxes): the inside volume is the closed form
+    along every cast axis, in float64 and in exact rationals."""
+    parts = [synth.cuboid((0.5, 0.25, 0.375), c) for c in [(-3, 0.75, 0), (-3, -0.75, 0), (3, 0.75, 0)]]
+    V = np.vstack([p[0] for p in parts])
+    F = np.vstack([p[1] + 8 * k for k, p in enumerate(parts)])
+    v_one = 1.0 * 0.5 * 0.75
+    cases = [([0.0, 0.0, 0.0], [3.5, 1.0, 0.375], 3 * v_one),       # bounding box of all three
+             ([-3.0, 0.0, 0.0], [0.5, 1.0, 0.375], 2 * v_one),      # bounding box of the pair
+             ([3.0, 0.75, 0.0], [0.5, 0.25, 0.375], v_one),         # tight box of one cuboid
+             ([3.0, 0.75, 0.0], [0.25, 0.25, 0.375], v_one / 2)]    # half of it, sharing 5 faces
+    for c, h, vin in cases:
+        got = exact.inside_volume(V, F, c, np.eye(3), h)
+        assert np.allclose(got, vin, rtol=0, atol=1e-15), (c, h, got)
+        for w in range(3):
+            assert exact.inside_volume_exact(V, F, c, np.eye(3).tolist(), h, axis=w) == Fraction(vin)
