@@ -101,98 +101,166 @@ def _centroids(V, F):
     return ((T[:, 0] + T[:, 1]) + T[:, 2]) / 3.0
 
 
-def flood_partition(V, F, adj, group, centers, axes, slots, evaluate, K=32):
-    """Bulk-synchronous flood of the triangles `group` into len(centers) boxes.
+class Elements:
+    """What a flood distributes among boxes: single triangles (the same-layer
+    clustering, Sec. 4.2.1) or units of several triangles (the bottom-up merge
+    of Sec. 4.2.2 regroups the child boxes of a layer).  Per element: the
+    float64 coordinates of its triangles' vertices, a centroid and its
+    edge-adjacent elements; ``tris`` lists its triangles."""
+
+    def __init__(self, verts, cen, adj, tris):
+        self.verts = verts
+        self.cen = np.asarray(cen, np.float64)
+        self.adj = adj
+        self.tris = tris
+        self.n = len(verts)
+
+    def extent(self, e, c, Q):
+        """max over the element's vertices of |Q (v - c)| per local axis (float64)."""
+        P = project(self.verts[e] - np.asarray(c, np.float64), Q)
+        return np.abs(P).max(axis=0)
+
+
+def triangle_elements(V, F, adj=None):
+    V64 = np.asarray(V).astype(np.float64)
+    F = np.asarray(F)
+    return Elements([V64[f] for f in F], _centroids(np.asarray(V), F), adjacency(F) if adj is None else adj,
+                    [np.array([t]) for t in range(len(F))])
+
+
+def unit_elements(V, F, tri_adj, unit_tris, unit_centres):
+    """Units of triangles as elements: the centroid of a unit is its box centre;
+    two units are adjacent when a mesh edge joins a triangle of each."""
+    V64 = np.asarray(V).astype(np.float64)
+    F = np.asarray(F)
+    unit_of = {}
+    for e, ts in enumerate(unit_tris):
+        for t in ts:
+            unit_of[int(t)] = e
+    adj = []
+    for e, ts in enumerate(unit_tris):
+        nb = set()
+        for t in ts:
+            for t2 in tri_adj[int(t)]:
+                u = unit_of.get(t2, -1)
+                if u >= 0 and u != e:
+                    nb.add(u)
+        adj.append(sorted(nb))
+    verts = [V64[F[np.asarray(ts)].reshape(-1)] for ts in unit_tris]
+    cen = np.asarray(unit_centres, np.float32).astype(np.float64)
+    return Elements(verts, cen, adj, [np.asarray(ts) for ts in unit_tris])
+
+
+def box_volume(h):
+    h = np.asarray(h, np.float64)
+    return float(8.0 * h[0] * h[1] * h[2])
+
+
+def flood(E, group, centers, axes, slots, evaluate, K=32, follow=None, tie=2e-5):
+    """Bulk-synchronous flood of the elements `group` into len(centers) boxes.
 
     evaluate(list of (slot, c, Q, h)) -> float64 array of OBV.
-    Returns (assign: dict t -> box index, boxes: list of (c, Q, h), obv array,
-    counters dict).
+
+    ``follow`` (optional, element -> box index) names the choice another
+    implementation took.  Where the two best moves of an element differ in dOBV
+    by less than ``tie`` times the larger grown box volume (the estimator's
+    noise), either choice is correct; the flood then takes the named one and
+    counts it in ``counters["ties"]``.  Every value it uses is still its own.
+
+    Returns (assign: dict element -> box index, boxes: list of (c, Q, h), obv
+    array, counters dict).
     """
-    V = np.asarray(V)
-    F = np.asarray(F)
     b = len(centers)
-    group = [int(t) for t in group]
+    group = [int(e) for e in group]
     in_group = set(group)
-    m = _centroids(V, F)
     C = np.asarray(centers, np.float32).astype(np.float64)
-    dist = {t: np.linalg.norm(m[t] - C, axis=1) for t in group}
-    key = {t: float(dist[t].min()) for t in group}
+    dist = {e: np.linalg.norm(E.cen[e] - C, axis=1) for e in group}
+    key = {e: float(dist[e].min()) for e in group}
     assign = {}
     boxes = []
     chosen = set()
     for i in range(b):
-        cand = [t for t in group if t not in chosen]
-        s = min(cand, key=lambda t: (float(dist[t][i]), t))
+        cand = [e for e in group if e not in chosen]
+        s = min(cand, key=lambda e: (float(dist[e][i]), e))
         chosen.add(s)
         assign[s] = i
-        boxes.append(make_box(centers[i], axes[i], tri_extent(V, F, s, np.float32(centers[i]),
-                                                              np.float32(axes[i]))))
+        c32, Q32 = np.float32(centers[i]), np.asarray(axes[i], np.float32)
+        boxes.append(make_box(c32, Q32, E.extent(s, c32.astype(np.float64), Q32.astype(np.float64))))
     obv = np.array(evaluate([(slots[i], *boxes[i]) for i in range(b)]), dtype=np.float64)
-    counters = {"rounds": 0, "evals": b, "trivial": 0, "moves": 0}
+    counters = {"rounds": 0, "evals": b, "trivial": 0, "moves": 0, "ties": 0}
     heap = []
     queued = set(assign)
     for s in list(assign):
-        for n in adj[s]:
+        for n in E.adj[s]:
             if n in in_group and n not in queued:
                 queued.add(n)
                 heapq.heappush(heap, (key[n], n))
 
     def decide(pops):
-        """Evaluate the (t, box) candidates of this round against the current boxes.
+        """Evaluate the (e, box) candidates of this round against the current boxes.
 
-        A box that already contains t has dOBV = 0, the smallest possible value,
-        so when one exists t goes to the nearest such box and the other boxes
-        of t need no evaluation.
+        A box that already contains e has dOBV = 0, the smallest possible value,
+        so when one exists e goes to the nearest such box and the other boxes
+        of e need no evaluation.
         """
         grown = {}
         req = []
-        for t in pops:
+        for e in pops:
             trivial_any = False
             for i in range(b):
                 c, Q, h = boxes[i]
-                h2 = f32_up(np.maximum(h.astype(np.float64), tri_extent(V, F, t, c, Q)))
-                grown[(t, i)] = h2
+                ext = E.extent(e, c.astype(np.float64), Q.astype(np.float64))
+                h2 = f32_up(np.maximum(h.astype(np.float64), ext))
+                grown[(e, i)] = h2
                 if np.array_equal(h2, h):
                     counters["trivial"] += 1
                     trivial_any = True
             if not trivial_any:
-                req += [(t, i) for i in range(b)]
-        vals = evaluate([(slots[i], boxes[i][0], boxes[i][1], grown[(t, i)]) for t, i in req]) if req else []
+                req += [(e, i) for i in range(b)]
+        vals = evaluate([(slots[i], boxes[i][0], boxes[i][1], grown[(e, i)]) for e, i in req]) if req else []
         counters["evals"] += len(req)
         dval = {k: v for k, v in zip(req, vals)}
         choice = {}
-        for t in pops:
+        for e in pops:
             best = None
             for i in range(b):
-                if (t, i) in dval:
-                    d = abs(dval[(t, i)] - obv[i])
-                elif np.array_equal(grown[(t, i)], boxes[i][2]):
+                if (e, i) in dval:
+                    d = abs(dval[(e, i)] - obv[i])
+                elif np.array_equal(grown[(e, i)], boxes[i][2]):
                     d = 0.0
                 else:
-                    continue          # not evaluated: another box contains t
-                k = (d, float(dist[t][i]), i)
+                    continue          # not evaluated: another box contains e
+                k = (d, float(dist[e][i]), i)
                 if best is None or k < best:
                     best = k
-            choice[t] = best[2]
+            pick = best[2]
+            f = None if follow is None else follow(e)
+            if f is not None and f != pick and 0 <= f < b and (e, f) in dval:
+                df = abs(dval[(e, f)] - obv[f])
+                vb = max(box_volume(grown[(e, f)]), box_volume(grown[(e, pick)]))
+                if df != best[0] and abs(df - best[0]) <= tie * vb:
+                    pick = f
+                    counters["ties"] += 1
+            choice[e] = pick
         return choice, grown, dval
 
     def apply(choice, grown, dval):
         per_box = {}
-        for t, i in choice.items():
-            assign[t] = i
-            per_box.setdefault(i, []).append(t)
+        for e, i in choice.items():
+            assign[e] = i
+            per_box.setdefault(i, []).append(e)
             counters["moves"] += 1
         extra = []
-        for i, ts in per_box.items():
+        for i, es in per_box.items():
             c, Q, h = boxes[i]
-            hs = [grown[(t, i)] for t in ts]
+            hs = [grown[(e, i)] for e in es]
             hn = hs[0]
             for x in hs[1:]:
                 hn = np.maximum(hn, x)
             if np.array_equal(hn, h):
                 continue
             boxes[i] = (c, Q, hn)
-            same = [t for t in ts if np.array_equal(grown[(t, i)], hn) and (t, i) in dval]
+            same = [e for e in es if np.array_equal(grown[(e, i)], hn) and (e, i) in dval]
             if same:
                 obv[i] = dval[(same[0], i)]
             else:
@@ -206,25 +274,30 @@ def flood_partition(V, F, adj, group, centers, axes, slots, evaluate, K=32):
     while heap:
         pops = []
         while heap and len(pops) < K:
-            _, t = heapq.heappop(heap)
-            if t not in assign:
-                pops.append(t)
+            _, e = heapq.heappop(heap)
+            if e not in assign:
+                pops.append(e)
         if not pops:
             break
         counters["rounds"] += 1
         choice, grown, dval = decide(pops)
         apply(choice, grown, dval)
-        for t in pops:
-            for n in adj[t]:
+        for e in pops:
+            for n in E.adj[e]:
                 if n in in_group and n not in assign and n not in queued:
                     queued.add(n)
                     heapq.heappush(heap, (key[n], n))
-    # triangles the flood cannot reach
-    for t in sorted(group):
-        if t not in assign:
-            choice, grown, dval = decide([t])
+    # elements the flood cannot reach
+    for e in sorted(group):
+        if e not in assign:
+            choice, grown, dval = decide([e])
             apply(choice, grown, dval)
     return assign, boxes, obv, counters
+
+
+def flood_partition(V, F, adj, group, centers, axes, slots, evaluate, K=32, follow=None, tie=2e-5):
+    """The flood over single triangles (see ``flood``)."""
+    return flood(triangle_elements(V, F, adj), group, centers, axes, slots, evaluate, K, follow, tie)
 
 
 def serial_flood(V, F, adj, group, centers, axes, slots, evaluate):
@@ -312,9 +385,15 @@ def rodrigues(r):
     return np.eye(3) + np.sin(th) * Kx + (1 - np.cos(th)) * (Kx @ Kx)
 
 
-def update_box(V, F, tris, Q, slot, evaluate, delta=0.02, steps=(8.0, 4.0, 2.0, 1.0, 0.5)):
+def update_box(V, F, tris, Q, slot, evaluate, delta=0.02, steps=(8.0, 4.0, 2.0, 1.0, 0.5),
+               follow_box=None, tie=2e-5, counters=None):
     """Step 2 of the Lloyd iteration for one box: tight box, FD gradient over the
-    three rotation angles, line search along -gradient; returns (box, obv, accepted)."""
+    three rotation angles, line search along -gradient; returns (box, obv, accepted).
+
+    ``follow_box`` (optional (c, Q, h)) is the box another implementation kept.
+    Where the candidate nearest to it scores within ``tie`` times the box volume
+    of this update's own choice, either is correct and the update takes that
+    candidate (counted in ``counters["ties"]``)."""
     Q = np.asarray(Q, np.float32).astype(np.float64)
     base = tight_box(V, F, tris, Q)
     cands = [base]
@@ -324,15 +403,28 @@ def update_box(V, F, tris, Q, slot, evaluate, delta=0.02, steps=(8.0, 4.0, 2.0, 
     vals = np.asarray(evaluate([(slot, *bx) for bx in cands]), dtype=np.float64)
     g = np.array([(vals[1 + 2 * k] - vals[2 + 2 * k]) / (2 * delta) for k in range(3)])
     gn = float(np.linalg.norm(g))
-    if gn == 0.0:
-        return base, float(vals[0]), False
-    d = -g / gn
-    line = [tight_box(V, F, tris, rodrigues(s * delta * d) @ Q) for s in steps]
-    lv = np.asarray(evaluate([(slot, *bx) for bx in line]), dtype=np.float64)
-    j = int(np.argmin(lv))
-    if lv[j] < vals[0]:
-        return line[j], float(lv[j]), True
-    return base, float(vals[0]), False
+    options = [(base, float(vals[0]), False)]
+    pick = 0
+    if gn != 0.0:
+        d = -g / gn
+        line = [tight_box(V, F, tris, rodrigues(s * delta * d) @ Q) for s in steps]
+        lv = np.asarray(evaluate([(slot, *bx) for bx in line]), dtype=np.float64)
+        options += [(line[j], float(lv[j]), True) for j in range(len(steps))]
+        j = int(np.argmin(lv))
+        if lv[j] < vals[0]:
+            pick = 1 + j
+    if follow_box is not None:
+        fc, fQ, fh = (np.asarray(x, np.float64).reshape(-1) for x in follow_box)
+        gap = [max(np.abs(bx[0] - fc).max(), np.abs(bx[1].reshape(-1) - fQ).max(), np.abs(bx[2] - fh).max())
+               for bx, _, _ in options]
+        near = int(np.argmin(gap))
+        if near != pick:
+            vb = max(box_volume(options[near][0][2]), box_volume(options[pick][0][2]))
+            if abs(options[near][1] - options[pick][1]) <= tie * vb:
+                pick = near
+                if counters is not None:
+                    counters["ties"] = counters.get("ties", 0) + 1
+    return options[pick]
 
 
 # ---------------------------------------------------------------------------

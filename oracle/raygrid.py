@@ -107,6 +107,41 @@ def eq9_outside_length(t_hits, signs, t_e):
     return float(t_e - np.sum(s[keep] * np.minimum(t[keep], t_e)))
 
 
+def integrate_rays(ray, depth, sign, n_rays, h, tol):
+    """Per-ray quantities of crossings sorted by (ray, depth), all rays at once.
+
+    The parity length of a ray adds, in depth order, the length of every inside
+    segment of [-h, h] between consecutive in-slab crossings (the ray starts
+    inside when an odd number of crossings lies below -h), then the last
+    segment up to +h: the sums of ``parity_inside_length`` term by term and in
+    its order.  The signed length is ``signed_inside_length``.
+    """
+    below = depth < -h
+    above = depth > h
+    inn = ~below & ~above
+    n_below = np.bincount(ray[below], minlength=n_rays).astype(np.int64)
+    n_in = np.bincount(ray[inn], minlength=n_rays).astype(np.int64)
+    n_above = np.bincount(ray[above], minlength=n_rays).astype(np.int64)
+    near_slab = np.bincount(ray[np.abs(np.abs(depth) - h) < tol], minlength=n_rays) > 0
+    L_sgn = np.bincount(ray, weights=sign * (np.clip(depth, -h, h) + h), minlength=n_rays).astype(np.float64)
+    # in-slab crossings: rank within the ray and the previous position
+    r_in, d_in = ray[inn], depth[inn]
+    first = np.ones(len(r_in), dtype=bool)
+    first[1:] = r_in[1:] != r_in[:-1]
+    start = np.maximum.accumulate(np.where(first, np.arange(len(r_in)), 0)) if len(r_in) else np.zeros(0, int)
+    rank = np.arange(len(r_in)) - start
+    prev = np.where(first, -h, np.concatenate([[-h], d_in[:-1]]))
+    was_inside = (n_below[r_in] + rank) % 2 == 1
+    L_par = np.bincount(r_in[was_inside], weights=(d_in - prev)[was_inside],
+                        minlength=n_rays).astype(np.float64)
+    # the last segment: inside after all in-slab crossings
+    last = np.full(n_rays, -h)
+    last[r_in] = d_in            # crossings are in depth order: the last write wins
+    tail = (n_below + n_in) % 2 == 1
+    L_par[tail] += h - last[tail]
+    return L_par, L_sgn, n_below, n_in, n_above, near_slab
+
+
 def cast_axis(P, F, half, w, R, seed, box_key, tol=1e-6, keep_depths=False):
     """All rays of one cast axis.  Returns a dict of per-ray [R, R] arrays."""
     ua, va = face_axes(w)
@@ -180,23 +215,9 @@ def cast_axis(P, F, half, w, R, seed, box_key, tol=1e-6, keep_depths=False):
         hs = np.zeros(0)
     order = np.lexsort((hwv, hr))
     hr, hwv, hs = hr[order], hwv[order], hs[order]
-    L_par = np.zeros(R * R)
-    L_sgn = np.zeros(R * R)
-    n_below = np.zeros(R * R, dtype=np.int64)
-    n_in = np.zeros(R * R, dtype=np.int64)
-    n_above = np.zeros(R * R, dtype=np.int64)
-    near_slab = np.zeros(R * R, dtype=bool)
+    L_par, L_sgn, n_below, n_in, n_above, near_slab = integrate_rays(hr, hwv, hs, R * R, hw, tol)
     bounds = np.searchsorted(hr, np.arange(R * R + 1))
     depths = [hwv[bounds[r]:bounds[r + 1]] for r in range(R * R)] if keep_depths else None
-    for r in np.nonzero(bounds[1:] > bounds[:-1])[0]:
-        d = hwv[bounds[r]:bounds[r + 1]]
-        sg = hs[bounds[r]:bounds[r + 1]]
-        L_par[r] = parity_inside_length(d, hw)
-        L_sgn[r] = signed_inside_length(d, sg, hw)
-        n_below[r] = int(np.sum(d < -hw))
-        n_in[r] = int(np.sum((d >= -hw) & (d <= hw)))
-        n_above[r] = int(np.sum(d > hw))
-        near_slab[r] = bool(np.any(np.abs(np.abs(d) - hw) < tol))
     V_in = float(L_par.sum() * du * dv)
     return {
         "V_in": V_in,
@@ -217,13 +238,22 @@ def raygrid_obv(V, F, center, axes, half, R, seed, box_key=0, axis_mask=7, tol=1
     v_box = float(8.0 * h[0] * h[1] * h[2])
     per_axis = {}
     rays = {}
+    # local bounds of every triangle: a triangle whose projection misses the face
+    # rectangle of an axis (by more than the candidate-cell margin) meets none of
+    # its rays, so it is left out of that axis before the per-cell work
+    p0, p1, p2 = P[F[:, 0]], P[F[:, 1]], P[F[:, 2]]
+    lo = np.minimum(np.minimum(p0, p1), p2)
+    hi = np.maximum(np.maximum(p0, p1), p2)
     for w in range(3):
         if not (axis_mask >> w) & 1:
             continue
         if v_box == 0.0:
             per_axis[w] = 0.0
             continue
-        res = cast_axis(P, F, h, w, R, seed, box_key, tol)
+        ua, va = face_axes(w)
+        near = ((hi[:, ua] >= -h[ua] - 2 * tol) & (lo[:, ua] <= h[ua] + 2 * tol)
+                & (hi[:, va] >= -h[va] - 2 * tol) & (lo[:, va] <= h[va] + 2 * tol))
+        res = cast_axis(P, F[near], h, w, R, seed, box_key, tol)
         per_axis[w] = res["V_in"]
         if keep_rays:
             rays[w] = res
