@@ -66,22 +66,23 @@ class Hierarchy:
     """State of the build, with the plain steps of Sec. 4.2.2 as methods.
 
     ``evaluate`` maps a list of (key, c, Q, h) to OBV values.  ``follow``
-    (optional) names the choices of another implementation, used only on
-    near-ties (see ``lloyd.flood``): follow.element(level, kind, index) and
-    follow.box(level, j)."""
+    (optional) names the choices of another implementation, taken only where
+    they are as valid as this build's own (near-ties of the flood,
+    ``lloyd.flood``; updates within the estimate's noise, ``lloyd.update_box``):
+    follow.element(level, kind, index) and follow.box(level, j)."""
 
     def __init__(self, V, F, levels, branching, evaluate, seed, K=32, delta=0.02, iters=1, follow=None,
-                 tie=2e-5):
+                 tie=2e-5, eps=1e-5):
         self.V = np.asarray(V)
         self.F = np.asarray(F, np.int64)
         self.nt = len(self.F)
         self.L, self.b = levels, branching
         self.evaluate, self.seed, self.K, self.delta, self.iters = evaluate, seed, K, delta, iters
-        self.follow, self.tie = follow, tie
+        self.follow, self.tie, self.eps = follow, tie, eps
         self.adj = ol.adjacency(self.F)
         self.tri_E = ol.triangle_elements(self.V, self.F, self.adj)
         self.cen = ol._centroids(self.V, self.F)
-        self.counters = {"ties": 0, "evals": 0}
+        self.counters = {"ties": 0, "update_ties": 0, "evals": 0}
         self.trace = []
         self.lv = []
 
@@ -125,7 +126,7 @@ class Hierarchy:
                 continue
             fb = fol.box(level, j) if fol is not None else None
             bx, v, _ = ol.update_box(self.V, self.F, sorted(tris[j]), boxes[j][1], slot[j], self._ev, self.delta,
-                                     follow_box=fb, tie=self.tie, counters=self.counters)
+                                     follow_box=fb, tie=self.tie, eps=self.eps, counters=self.counters)
             boxes[j] = bx
             obv[j] = v
         return eb, tris
@@ -290,10 +291,10 @@ class FollowArrays:
 
 
 def build(V, F, levels, branching, evaluate, seed, iters=1, sweeps=1, K=32, delta=0.02, follow_top_down=None,
-          follow_sweeps=None, tie=2e-5):
+          follow_sweeps=None, tie=2e-5, eps=1e-5):
     """Top-down build and ``sweeps`` sweeps.  Returns (hierarchy, e history,
     layer-major arrays after the top-down build)."""
-    H = Hierarchy(V, F, levels, branching, evaluate, seed, K, delta, iters, follow_top_down, tie)
+    H = Hierarchy(V, F, levels, branching, evaluate, seed, K, delta, iters, follow_top_down, tie, eps)
     e = [H.top_down()]
     top_down = H.arrays()
     H.follow = follow_sweeps

@@ -385,15 +385,36 @@ def rodrigues(r):
     return np.eye(3) + np.sin(th) * Kx + (1 - np.cos(th)) * (Kx @ Kx)
 
 
+def rotation_vector(Rm):
+    """Axis times angle of a rotation matrix (log map; angles well below pi)."""
+    c = np.clip((np.trace(Rm) - 1.0) / 2.0, -1.0, 1.0)
+    th = float(np.arccos(c))
+    if th == 0.0:
+        return np.zeros(3)
+    w = np.array([Rm[2, 1] - Rm[1, 2], Rm[0, 2] - Rm[2, 0], Rm[1, 0] - Rm[0, 1]])
+    return th * w / (2.0 * np.sin(th))
+
+
 def update_box(V, F, tris, Q, slot, evaluate, delta=0.02, steps=(8.0, 4.0, 2.0, 1.0, 0.5),
-               follow_box=None, tie=2e-5, counters=None):
+               follow_box=None, tie=2e-5, eps=1e-5, counters=None):
     """Step 2 of the Lloyd iteration for one box: tight box, FD gradient over the
     three rotation angles, line search along -gradient; returns (box, obv, accepted).
 
-    ``follow_box`` (optional (c, Q, h)) is the box another implementation kept.
-    Where the candidate nearest to it scores within ``tie`` times the box volume
-    of this update's own choice, either is correct and the update takes that
-    candidate (counted in ``counters["ties"]``)."""
+    ``follow_box`` (optional (c, Q, h)) is the box another implementation kept
+    whose outer-volume estimates agree with these to ``eps`` of the box volume.
+    Its finite-difference gradient then differs by at most sqrt(3) eps V / delta
+    per component, so its descent direction by at most
+    kappa = 2 sqrt(3) eps V / (delta |g|) (plus float32 rounding of the axes):
+    the update is ill-conditioned where |g| is small.  The named box is taken
+    when it is valid under that bound:
+    it is this oracle's tight box for its own axes; its axes are the current
+    ones or a rotation of them by one of the line-search steps about a direction
+    within kappa of -g / |g|; and its outer volume (evaluated here) agrees with
+    this update's value at the same step to tie V plus the first-order change
+    2 s delta |g| |d' - d|, with the choice among candidates a near-tie (within
+    tie V, plus the same direction allowance) when it differs from this one.
+    Taken boxes are counted in ``counters["update_ties"]``.
+    """
     Q = np.asarray(Q, np.float32).astype(np.float64)
     base = tight_box(V, F, tris, Q)
     cands = [base]
@@ -405,6 +426,8 @@ def update_box(V, F, tris, Q, slot, evaluate, delta=0.02, steps=(8.0, 4.0, 2.0, 
     gn = float(np.linalg.norm(g))
     options = [(base, float(vals[0]), False)]
     pick = 0
+    d = np.zeros(3)
+    lv = np.zeros(0)
     if gn != 0.0:
         d = -g / gn
         line = [tight_box(V, F, tris, rodrigues(s * delta * d) @ Q) for s in steps]
@@ -413,18 +436,44 @@ def update_box(V, F, tris, Q, slot, evaluate, delta=0.02, steps=(8.0, 4.0, 2.0, 
         j = int(np.argmin(lv))
         if lv[j] < vals[0]:
             pick = 1 + j
-    if follow_box is not None:
-        fc, fQ, fh = (np.asarray(x, np.float64).reshape(-1) for x in follow_box)
-        gap = [max(np.abs(bx[0] - fc).max(), np.abs(bx[1].reshape(-1) - fQ).max(), np.abs(bx[2] - fh).max())
-               for bx, _, _ in options]
-        near = int(np.argmin(gap))
-        if near != pick:
-            vb = max(box_volume(options[near][0][2]), box_volume(options[pick][0][2]))
-            if abs(options[near][1] - options[pick][1]) <= tie * vb:
-                pick = near
-                if counters is not None:
-                    counters["ties"] = counters.get("ties", 0) + 1
-    return options[pick]
+    if follow_box is None:
+        return options[pick]
+    fc, fQ, fh = (np.asarray(x, np.float64) for x in follow_box)
+    fQ = fQ.reshape(3, 3)
+    row = np.concatenate([fc, fQ.reshape(-1), fh])
+
+    def gap(bx):
+        return float(np.max(np.abs(np.concatenate([bx[0], bx[1].reshape(-1), bx[2]]).astype(np.float64) - row)))
+
+    if gap(options[pick][0]) <= 1e-6:
+        return options[pick]
+    mine = tight_box(V, F, tris, fQ)
+    if gap(mine) > 1e-6:
+        return options[pick]                 # not the tight box of its own axes
+    vbox = max(box_volume(mine[2]), box_volume(options[pick][0][2]))
+    v_f = float(np.asarray(evaluate([(slot, *mine)]), dtype=np.float64)[0])
+    r = rotation_vector(fQ @ Q.T)
+    th = float(np.linalg.norm(r))
+    kappa = (2.0 * np.sqrt(3.0) * eps * vbox / (delta * gn) if gn > 0 else np.inf)
+    if th < 1e-6:                            # the named box kept the current axes
+        allow = tie * vbox + (2.0 * max(steps) * delta * gn * min(kappa, 2.0) if pick else 0.0)
+        ok = abs(v_f - vals[0]) <= tie * vbox and (pick == 0 or vals[0] - options[pick][1] <= allow)
+    else:
+        jf = int(np.argmin([abs(th - s * delta) for s in steps]))
+        s_f = steps[jf]
+        dd = float(np.linalg.norm(r / th - d)) if gn > 0 else np.inf
+        round_off = 1e-6 / (s_f * delta)
+        ok = gn > 0 and abs(th - s_f * delta) <= 1e-3 * s_f * delta and dd <= kappa + round_off
+        if ok:
+            drift = 2.0 * s_f * delta * gn * dd
+            ok = abs(v_f - lv[jf]) <= tie * vbox + drift and v_f <= vals[0] + tie * vbox
+            if ok and 1 + jf != pick:
+                ok = abs(lv[jf] - options[pick][1]) <= tie * vbox + drift
+    if not ok:
+        return options[pick]
+    if counters is not None:
+        counters["update_ties"] = counters.get("update_ties", 0) + 1
+    return (mine, v_f, th >= 1e-6)
 
 
 # ---------------------------------------------------------------------------

@@ -118,9 +118,9 @@ def test_hierarchy_structure_enclosure_and_weighted_error():
 
 
 def test_following_another_build_changes_nothing_beyond_the_tie_tolerance():
-    """The near-tie rule only picks between choices whose outer volumes agree
-    within the tolerance: with tolerance 0 any named choices are ignored, and
-    naming the build's own choices reproduces it with no tie taken."""
+    """Named choices are taken only where they are as valid as the build's own:
+    with both tolerances 0 another build's choices are ignored, and naming the
+    build's own choices reproduces it with nothing taken."""
     V, F = synth.noisy_cube_sphere(4, seed=103)
     ev = _raygrid_eval(V, F)
     H0, e0, td0 = hierarchy.build(V, F, 3, 2, ev, 1, iters=1, sweeps=1, K=8)
@@ -128,11 +128,13 @@ def test_following_another_build_changes_nothing_beyond_the_tie_tolerance():
     _, _, other = hierarchy.build(V, F, 3, 2, ev, 2, iters=1, sweeps=0, K=8)
     fol = hierarchy.FollowArrays(other, 3, 2)
     H1, e1, _ = hierarchy.build(V, F, 3, 2, ev, 1, iters=1, sweeps=1, K=8, follow_top_down=fol,
-                                follow_sweeps=fol, tie=0.0)
+                                follow_sweeps=fol, tie=0.0, eps=0.0)
     H2, e2, _ = hierarchy.build(V, F, 3, 2, ev, 1, iters=1, sweeps=1, K=8,
                                 follow_top_down=hierarchy.FollowArrays(td0, 3, 2),
                                 follow_sweeps=hierarchy.FollowArrays(A0, 3, 2))
-    assert e1 == e0 and e2 == e0 and H1.counters["ties"] == 0 and H2.counters["ties"] == 0
+    assert e1 == e0 and e2 == e0
+    for H in (H1, H2):
+        assert H.counters["ties"] == 0 and H.counters["update_ties"] == 0
     for k in A0:
         assert np.array_equal(H1.arrays()[k], A0[k]) and np.array_equal(H2.arrays()[k], A0[k]), k
 

@@ -107,3 +107,37 @@ def test_layer_weights_example():
     assert lloyd.layer_weights(2) == [2.0, 1.0]
     assert lloyd.layer_weights(4) == [4.0, 3.0, 2.0, 1.0]
     assert lloyd.hierarchy_error([[1.0], [0.5, 0.25]], [2.0, 1.0]) == 2.75
+
+
+def test_update_takes_a_twin_within_noise_but_not_another_rotation():
+    """The parameter update is an argmin over noisy estimates: a twin update
+    whose evaluator differs by 5e-7 of the box volume per call is accepted as
+    valid (the gradient-noise bound covers it), while the same step taken about
+    a direction at right angles to the descent direction is rejected."""
+    V, F = synth.noisy_cube_sphere(4, seed=3)
+    tris = list(range(0, len(F), 3))
+    ev = _raygrid_eval(V, F, R=8)
+    rng = np.random.default_rng(1)
+
+    def noisy(items):
+        return [v + 5e-7 * lloyd.box_volume(h) * rng.standard_normal() for v, (_, _, _, h) in zip(ev(items), items)]
+
+    Q = (lloyd.rot_local(0, 0.3) @ lloyd.rot_local(2, 0.2)).astype(np.float32)
+    mine = lloyd.update_box(V, F, tris, Q, 4, ev)
+    twin = lloyd.update_box(V, F, tris, Q, 4, noisy)
+    assert np.abs(twin[0][1] - mine[0][1]).max() > 1e-6       # the noise turned the step
+    cnt = {}
+    got = lloyd.update_box(V, F, tris, Q, 4, ev, follow_box=twin[0], counters=cnt)
+    assert cnt["update_ties"] == 1
+    assert np.array_equal(got[0][1], twin[0][1]) and np.array_equal(got[0][2], twin[0][2])
+    assert abs(got[1] - mine[1]) <= 2e-5 * lloyd.box_volume(mine[0][2])
+    # a step of the chosen length about an axis orthogonal to the descent direction
+    r = lloyd.rotation_vector(mine[0][1].astype(np.float64) @ Q.astype(np.float64).T)
+    assert np.linalg.norm(r) > 0
+    perp = np.cross(r, [0.3, -0.5, 0.8])
+    perp *= np.linalg.norm(r) / np.linalg.norm(perp)
+    wrong = lloyd.tight_box(V, F, tris, lloyd.rodrigues(perp) @ Q.astype(np.float64))
+    cnt = {}
+    got = lloyd.update_box(V, F, tris, Q, 4, ev, follow_box=wrong, counters=cnt)
+    assert cnt.get("update_ties", 0) == 0
+    assert np.array_equal(got[0][1], mine[0][1]) and got[1] == mine[1]
