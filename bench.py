@@ -56,7 +56,10 @@ SEED_MESH = 21
 # known size.  Valid only for the sources it was measured on (the hash covers
 # the outer-volume source and its shared header): any change there reports null
 # until the counters are re-taken.
-K_CAST_TRAFFIC = None
+K_CAST_TRAFFIC = {"source_sha256": "82bf3626576d23999fceeabfe9196faa9567cf6d1df566e34293c0a13b494581",
+                  "fetch_bytes_per_launch": 66088794, "write_bytes_per_launch": 81977,
+                  "fetch_kib_raw": 32270.98, "write_kib_raw": 80.06,
+                  "copy_factor_fetch": 1.99993, "copy_factor_write": 1.00000}
 CAST_SOURCES = ("outer_volume.hip", "common.h")
 
 
@@ -434,6 +437,10 @@ def main():
                      "frac": tflops / FP32_PEAK_TFLOPS, "traffic": traffic_bytes(),
                      "kernel": "k_cast", "flop_per_test": FLOP_PER_TEST,
                      "peak_nonpacked": FP32_NONPACKED_TFLOPS, "frac_nonpacked": tflops / FP32_NONPACKED_TFLOPS},
+        "hbm_traffic": (None if traffic_bytes() is None else
+                        {"bytes_per_launch": traffic_bytes(), "ratio_to_algorithmic": traffic_bytes() / algo_bytes,
+                         "gbps_at_cast_avg": traffic_bytes() / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None,
+                         "source": "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"}),
         "culling_stream": {"bytes_per_launch": nbytes / max(launches, 1), "achieved_gbps": gbps,
                            "peak_gbps": HBM_PEAK_GBPS, "frac": gbps / HBM_PEAK_GBPS,
                            "algorithmic_bytes_per_launch": algo_bytes,
