@@ -65,3 +65,25 @@ def test_fit_rotated_cuboid_exact_axes(api):
     for i in range(3):
         assert abs(abs(Q[i] @ a[0][i].astype(np.float64)) - 1) < 1e-6
     assert np.allclose(b[12:], half, rtol=1e-5)
+
+
+def test_fit_is_bitwise_independent_of_triangle_order(api):
+    """Exact integer sums: the same clusters give bit-identical boxes and
+    eigenvalues on a repeat, and with the triangles listed in another order
+    (37 clusters interleaved at random, so every wave adds into several)."""
+    import torch
+    V, F = synth.noisy_torus(nu=128, nv=64)
+    g = np.random.default_rng(3)
+    cl = g.integers(-1, 37, size=len(F)).astype(np.int32)
+    Vt = torch.from_numpy(V).cuda()
+
+    def run(order):
+        b, e = api.fit(Vt, torch.from_numpy(F[order]).cuda(), torch.from_numpy(cl[order]).cuda(), 37)
+        return b.cpu().numpy(), e.cpu().numpy()
+
+    ident = np.arange(len(F))
+    b0, e0 = run(ident)
+    for order in (ident, g.permutation(len(F)), ident[::-1].copy()):
+        b1, e1 = run(order)
+        assert np.array_equal(b0.view(np.uint32), b1.view(np.uint32))
+        assert np.array_equal(e0.view(np.uint64), e1.view(np.uint64))
