@@ -23,9 +23,12 @@ Other objects of the line:
                 triangle helix's 5,461-node covariance tree (R 256 -> 32)
   obb_tree      per-layer sum of OBV of the built hierarchy vs the top-down
                 covariance tree (the paper's Fig. 6 comparison)
-  surrogate     the ranker trained on noisy spheres, then the same hierarchy with
-                network-ranked floods, occupancy-mean-ranked floods, and
-                network-ranked floods verifying the top 4 per box
+  surrogate     the ranker trained on 1.05 M exact outer fractions of the batched
+                workload's spheres 0-223, validated on 224-255 against the
+                occupancy estimate (MAE, top-1 of flood-candidate groups); then
+                the same hierarchy, and 2 Lloyd iterations on 16 held-out
+                spheres, with network-ranked floods, occupancy-mean-ranked
+                floods, and network-ranked floods verifying the top 4 per box
   cpu_baseline  the CPU oracle on a bounded sample of the hierarchy's boxes
 """
 import argparse
@@ -142,8 +145,8 @@ def leg_config1(api, torch):
 
 def leg_config3(api, torch):
     import synth
-    t0 = time.perf_counter()
-    host = synth.noisy_sphere_batch(256, seed=3)
+    host = config3_meshes()
+    gen_s = _CONFIG3["generation_s"]
     meshes, boxes, bm = [], [], []
     for m, (V, F) in enumerate(host):
         meshes.append((torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()))
@@ -152,7 +155,6 @@ def leg_config3(api, torch):
         bm += [m] * 64
     Bt = torch.from_numpy(np.concatenate(boxes)).cuda()
     bmt = torch.from_numpy(np.array(bm, np.int32)).cuda()
-    gen_s = time.perf_counter() - t0
     plan = api.OuterVolumePlan(Bt, 64, seed=33, meshes=meshes, box_mesh=bmt)
     info = plan.info()
     # the plan is a graph: time its replays with events on the stream
@@ -235,33 +237,118 @@ def obb_tree_comparison(api, torch, Vt, Ft, out, hp):
             "e_obb_tree": float(sum(x * y for x, y in zip(w, tr)))}
 
 
-def surrogate_comparison(api, torch, Vt, Ft, hp, exact, judge_every=32):
-    """Train the ranker on exact outer fractions of noisy spheres (not the torus):
-    boxes recorded during exact Lloyd iterations plus random boxes around the
-    surface; then rebuild the same torus hierarchy with network-ranked floods,
-    with occupancy-mean-ranked floods (the same machinery, network output 0),
-    and with network-ranked floods that verify the 4 best candidates per box."""
+_CONFIG3 = {}
+
+
+def config3_meshes():
+    """The batched workload's 256 noisy spheres (generated once per run)."""
+    import synth
+    if "host" not in _CONFIG3:
+        t0 = time.perf_counter()
+        _CONFIG3["host"] = synth.noisy_sphere_batch(256, seed=3)
+        _CONFIG3["generation_s"] = time.perf_counter() - t0
+    return _CONFIG3["host"]
+
+
+def ranker_eval_set(api, torch, V, F, seed, n_single, n_groups=64):
+    """Random boxes around a mesh, then flood-candidate groups (a base box and 8
+    copies grown by one more triangle each): inputs, exact fractions and OBVs."""
     import synth
     from paper_2203_10521_amd import ranker
+    Vt, Ft = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+    base, cand = synth.flood_candidates(V, F, n_groups, seed=seed)
+    B = torch.from_numpy(np.concatenate([synth.mixed_boxes(V, n_single, seed=seed + 1), base,
+                                         cand.reshape(-1, 15)])).cuda()
+    X, t, _ = ranker.make_dataset([(Vt, Ft)], [B], R=64, seed=1, nb=16)
+    obv = api.outer_volume(Vt, Ft, B, 64, seed=1)
+    return X, t, obv, B, n_single, len(base)
+
+
+def lloyd_held_out(api, torch, host, ids, surrogates):
+    """Two Lloyd iterations on each held-out mesh (8 k-means groups x 4 boxes,
+    R = 64) per evaluation mode: moves per second and the summed layer error."""
+    from paper_2203_10521_amd import ranker
+    res = {name: {"moves": 0, "seconds": 0.0, "layer_error": 0.0, "evals": 0} for name in surrogates}
+    for m in ids:
+        V, F = host[m]
+        Vt, Ft = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+        grp = ranker._kmeans_groups(V, F, 8, seed=m)
+        fitted, _ = api.fit(Vt, Ft, torch.from_numpy(grp).cuda(), 8)
+        fitted = fitted.cpu().numpy()
+        g = np.random.default_rng(m)
+        cen = V.astype(np.float64)[F].mean(axis=1)
+        init, bg = [], []
+        for j in range(8):
+            tris = np.nonzero(grp == j)[0]
+            for t in g.choice(tris, size=min(4, len(tris)), replace=False):
+                b = fitted[j].copy()
+                b[:3] = cen[t]
+                b[12:] = 0.0
+                init.append(b)
+                bg.append(j)
+        vol, frame = api.occupancy_volume(Vt, Ft, nb=16, seed=1)
+        for name, sur in surrogates.items():
+            with api.Lloyd(Vt, Ft, R=64, seed=m, pops_per_round=32) as L:
+                L.set_groups(grp, np.array(bg, np.int32), np.array(init, np.float32))
+                if sur is not None:
+                    L.set_surrogate(api.Surrogate(sur[0], vol, frame, verify_top=sur[1], max_error=0.05,
+                                                  judge_every=32))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(2):
+                    L.step()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                out = L.get()
+            r = res[name]
+            r["moves"] += out["counters"]["moves"]
+            r["evals"] += out["counters"]["evals"]
+            r["seconds"] += dt
+            r["layer_error"] += out["layer_error"]
+    for name, r in res.items():
+        r["moves_per_s"] = r["moves"] / r["seconds"]
+    for name, r in res.items():
+        if name != "exact":
+            r["speedup"] = r["moves_per_s"] / res["exact"]["moves_per_s"]
+            r["e_ratio"] = r["layer_error"] / res["exact"]["layer_error"]
+    return res
+
+
+def surrogate_comparison(api, torch, Vt, Ft, hp, exact, judge_every=32):
+    """Train the ranker on 1.05 M exact outer fractions of the batched workload's
+    noisy spheres 0-223 (4,096 random boxes and 64 flood-candidate groups of 9
+    boxes per mesh), validate on spheres 224-255 against the occupancy
+    estimate, then: the torus hierarchy with network-ranked floods,
+    occupancy-mean-ranked floods (the same machinery, network output 0) and
+    network-ranked floods verifying the 4 best candidates per box; and two
+    Lloyd iterations on 16 held-out spheres (240-255) under each mode."""
+    from paper_2203_10521_amd import ranker
+    host = config3_meshes()
     t0 = time.perf_counter()
-    meshes, boxes = [], []
-    for k in range(8):
-        V, F = synth.noisy_cube_sphere(16 + 6 * k, seed=500 + k)
-        meshes.append((torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()))
-        rec = ranker.lloyd_boxes(V, F, R=64, seed=700 + k, n_groups=16, iters=2, cap=8192)
-        mixed = synth.mixed_boxes(V, 16384 - len(rec), seed=600 + k)
-        boxes.append(torch.from_numpy(np.concatenate([rec, mixed])).cuda())
-    X, t, _ = ranker.make_dataset(meshes, boxes, R=64, seed=1, nb=16)
-    n_val = boxes[-1].shape[0]          # the last sphere is held out for validation
-    P, losses = ranker.train(X[:-n_val], t[:-n_val], steps=3000, batch=4096, lr=2e-3, seed=0)
+    Xs, ts = [], []
+    for m in range(224):
+        X, t, *_ = ranker_eval_set(api, torch, *host[m], seed=100 + m, n_single=4096)
+        Xs.append(X)
+        ts.append(t)
+    X, t = torch.cat(Xs), torch.cat(ts)
+    del Xs, ts
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    P, losses = ranker.train(X, t, steps=3000, batch=4096, lr=1e-3, seed=0)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    err_nn = (ranker.predict(P, X[-n_val:]) - t[-n_val:]).abs()
-    err_occ = (ranker.occupancy_heuristic(X[-n_val:]) - t[-n_val:]).abs()
+    n_pairs = int(X.shape[0])
+    del X, t
+    val = ranker.summarise_metrics([ranker.ranking_metrics(P, *ranker_eval_set(api, torch, *host[m], seed=900 + m,
+                                                                                 n_single=1024))
+                                    for m in range(224, 256)])
+    log(f"ranker validation: network MAE {val['network']['mae']:.5f} top-1 {val['network']['top1']:.3f}; "
+        f"occupancy mean MAE {val['occupancy_mean']['mae']:.5f} top-1 {val['occupancy_mean']['top1']:.3f}")
     vol, frame = api.occupancy_volume(Vt, Ft, nb=16, seed=1)
+    occ = ranker.occupancy_params()
     runs = {}
-    for name, params, verify in (("network", P, 0), ("occupancy_mean", ranker.occupancy_params(), 0),
-                                 ("network_verify_top4", P, 4)):
+    for name, params, verify in (("network", P, 0), ("occupancy_mean", occ, 0), ("network_verify_top4", P, 4)):
         sur = api.Surrogate(params, vol, frame, verify_top=verify, max_error=0.05, judge_every=judge_every)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -273,15 +360,20 @@ def surrogate_comparison(api, torch, Vt, Ft, hp, exact, judge_every=32):
                       "exact_evals": c["evals"], "predictions": c["predicted"], "fallbacks": c["fallbacks"],
                       "build_s": dt}
         log(f"surrogate {name}: {runs[name]['speedup']:.2f}x exact moves/s, e ratio {runs[name]['e_ratio']:.4f}")
+    held = lloyd_held_out(api, torch, host, range(240, 256),
+                          {"exact": None, "network": (P, 0), "occupancy_mean": (occ, 0),
+                           "network_verify_top4": (P, 4)})
     res = dict(runs["network"])
     res.update({"judge_every": judge_every, "exact_moves_per_s": exact["moves_per_s"],
                 "exact_final_e": exact["final_e"], "exact_evals_without_ranker": exact["evals"],
                 "occupancy_mean": runs["occupancy_mean"], "network_verify_top4": runs["network_verify_top4"],
-                "train": {"samples": int(X.shape[0] - n_val), "steps": 3000, "seconds": train_s,
-                          "final_loss": losses[-1][1], "val_mae": float(err_nn.mean()),
-                          "occupancy_mean_val_mae": float(err_occ.mean()),
-                          "data": "8 noisy cube-spheres (n = 16..58), 16,384 boxes each (exact-Lloyd "
-                                  "recorded + random around the surface); the last sphere held out"}})
+                "held_out_config3_lloyd": held,
+                "validation": val,
+                "train": {"pairs": n_pairs, "steps": 3000, "batch": 4096, "data_s": data_s, "train_s": train_s,
+                          "final_loss": losses[-1][1],
+                          "data": "noisy spheres 0-223 of the batched workload (256 spheres, log-normal "
+                                  "triangle counts); per sphere 4,096 random boxes around it + 64 flood-candidate "
+                                  "groups (a base box and 8 one-triangle growths); validation: spheres 224-255"}})
     return res
 
 

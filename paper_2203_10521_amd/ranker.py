@@ -15,8 +15,9 @@ PARAMS = 544 * 256 + 256 + 256 * 256 + 256 + 256 + 1
 
 
 def init_params(seed=0):
-    """He-uniform weights (first-layer rows past the 527 real inputs zero, the output
-    layer scaled by 0.1 so that training starts near the occupancy estimate), zero biases."""
+    """He-uniform hidden weights (first-layer rows past the 527 real inputs zero),
+    zero biases and a zero output layer: the untrained network predicts exactly
+    the occupancy estimate 1 - mean occupancy, and training learns the correction."""
     g = np.random.default_rng(seed)
 
     def he(n_in, n_out):
@@ -25,17 +26,14 @@ def init_params(seed=0):
     W1 = he(544, 256)
     W1[527:] = 0.0
     return {"W1": W1, "b1": np.zeros(256), "W2": he(256, 256), "b2": np.zeros(256),
-            "w3": 0.1 * he(256, 1)[:, 0], "b3": np.zeros(1)}
+            "w3": np.zeros(256), "b3": np.zeros(1)}
 
 
 def occupancy_params(seed=0):
-    """A ranker whose network output is 0 for every input (output layer zero):
-    through the same machinery it predicts the occupancy estimate
-    1 - mean occupancy, the heuristic the learned ranker must beat."""
-    p = init_params(seed)
-    p["w3"] = np.zeros(256)
-    p["b3"] = np.zeros(1)
-    return torch.from_numpy(api.mlp_pack(p)).cuda()
+    """A ranker whose network output is 0 for every input (output layer zero, as
+    before training): through the same machinery it predicts the occupancy
+    estimate 1 - mean occupancy, the heuristic the learned ranker must beat."""
+    return torch.from_numpy(api.mlp_pack(init_params(seed))).cuda()
 
 
 def make_dataset(meshes, boxes, R=64, seed=0, nb=16):
@@ -139,3 +137,49 @@ def predict(P, X):
 def occupancy_heuristic(X):
     """Outer fraction estimated as 1 - mean of the 512 sampled occupancies."""
     return 1.0 - X[:, 15:527].mean(dim=1)
+
+
+def ranking_metrics(P, X, t, obv, boxes, n_single, n_groups, k=8):
+    """Prediction error and ranking quality on one mesh's evaluation set.
+
+    Rows [0, n_single) are single boxes; then n_groups base boxes; then the
+    n_groups x k candidates grown from them (in group order).  A candidate's
+    change is f V(candidate) - f V(base) with f the predicted outer fraction;
+    the exact change uses the exact outer volumes `obv`.  Returns sums over the
+    mesh for the network P (None: skipped) and for 1 - mean occupancy:
+    absolute errors of all rows and of the candidates, top-1 hits (the
+    predicted best candidate of a group is the exact best) and correctly
+    ordered candidate pairs."""
+    vb = 8.0 * boxes[:, 12].double() * boxes[:, 13].double() * boxes[:, 14].double()
+    b0, c0 = n_single, n_single + n_groups
+    exact = obv[c0:].reshape(n_groups, k) - obv[b0:c0, None]
+    iu = torch.triu_indices(k, k, 1, device=X.device)
+    ex_pair = torch.sign(exact[:, iu[0]] - exact[:, iu[1]])
+    out = {"rows": int(t.shape[0]), "candidates": int(n_groups * k), "groups": int(n_groups),
+           "pairs": int((ex_pair != 0).sum().item())}
+    preds = {"occupancy_mean": occupancy_heuristic(X)}
+    if P is not None:
+        preds["network"] = predict(P, X)
+    for name, f in preds.items():
+        err = (f - t).abs()
+        ch = (f[c0:].double() * vb[c0:]).reshape(n_groups, k) - (f[b0:c0].double() * vb[b0:c0])[:, None]
+        pr_pair = torch.sign(ch[:, iu[0]] - ch[:, iu[1]])
+        out[name] = {"abs_err": float(err.sum().item()), "cand_abs_err": float(err[c0:].sum().item()),
+                     "top1": int((ch.argmin(dim=1) == exact.argmin(dim=1)).sum().item()),
+                     "pairs_ok": int(((pr_pair == ex_pair) & (ex_pair != 0)).sum().item())}
+    return out
+
+
+def summarise_metrics(per_mesh):
+    """Means over meshes of ranking_metrics sums: MAE, candidate MAE, top-1 rate,
+    pair accuracy, for each predictor."""
+    tot = {k: sum(m[k] for m in per_mesh) for k in ("rows", "candidates", "groups", "pairs")}
+    res = {}
+    for name in ("network", "occupancy_mean"):
+        if name not in per_mesh[0]:
+            continue
+        s = {k: sum(m[name][k] for m in per_mesh) for k in ("abs_err", "cand_abs_err", "top1", "pairs_ok")}
+        res[name] = {"mae": s["abs_err"] / tot["rows"], "candidate_mae": s["cand_abs_err"] / tot["candidates"],
+                     "top1": s["top1"] / tot["groups"], "pair_accuracy": s["pairs_ok"] / max(tot["pairs"], 1)}
+    res.update(tot)
+    return res

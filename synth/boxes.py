@@ -73,3 +73,40 @@ def mixed_boxes(V, n, seed, surface_frac=0.5):
     qs = _uniform_quaternions(rng, n)
     axes = np.stack([quat_to_axes(q) for q in qs]) if n else np.zeros((0, 3, 3))
     return boxes_to_array(np.vstack([c_s, c_r]), axes, np.vstack([h_s, h_r]))
+
+
+def _f32_up(x):
+    y = np.asarray(x, np.float64).astype(np.float32)
+    return np.where(y.astype(np.float64) < x, np.nextafter(y, np.float32(np.inf)), y).astype(np.float32)
+
+
+def flood_candidates(V, F, n_groups, seed, k=8, patch=48, reach=6):
+    """Candidate boxes as a flood meets them: n_groups base boxes, each with k
+    grown copies.  A base box has a uniform random rotation, its centre at the
+    centroid of a random triangle, and half extents enclosing (symmetrically
+    about that centre) the `patch` triangles whose centroids are nearest to it;
+    candidate j encloses the base's triangles plus one more triangle, drawn from
+    the next reach x k nearest, that lies partly outside the base box.  Returns
+    float32 (base [G, 15], candidates [G, k, 15]); groups without k such
+    triangles are skipped."""
+    rng = np.random.default_rng(seed)
+    V = np.asarray(V, np.float64)
+    T = V[np.asarray(F)]
+    cen = T.mean(axis=1)
+    qs = _uniform_quaternions(rng, n_groups)
+    base, cand = [], []
+    for g in range(n_groups):
+        Q = quat_to_axes(qs[g])
+        s = int(rng.integers(0, len(cen)))
+        c = cen[s].astype(np.float32).astype(np.float64)
+        near = np.argsort(np.linalg.norm(cen - c, axis=1))[:patch + reach * k]
+        loc = np.abs((T[near] - c) @ Q.T).max(axis=1)          # [n, 3] extents per triangle
+        h = _f32_up(loc[:patch].max(axis=0))
+        grows = [int(i) for i in range(patch, len(near)) if np.any(_f32_up(np.maximum(loc[i], h)) != h)]
+        if len(grows) < k:
+            continue
+        pick = rng.choice(grows, size=k, replace=False)
+        base.append(np.concatenate([c.astype(np.float32), Q.reshape(-1).astype(np.float32), h]))
+        cand.append([np.concatenate([c.astype(np.float32), Q.reshape(-1).astype(np.float32),
+                                     _f32_up(np.maximum(loc[i], h))]) for i in pick])
+    return np.array(base, np.float32).reshape(-1, 15), np.array(cand, np.float32).reshape(-1, k, 15)
