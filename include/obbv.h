@@ -96,11 +96,16 @@ int obbv_release(void);
 
 /* Synchronous.  Validates a mesh for the closed-solid requirement (Sec. 6):
  * indices in [0, n_vertices), every directed edge once with its reverse once,
- * enclosed volume sum(det[a, b, c]) / 6 > 0.
+ * enclosed volume sum(det[a, b, c]) / 6 > 0.  Runs on the device: the edges go
+ * through a hash table of undirected edges counting both directions; the
+ * volume terms are summed exactly in 64-bit fixed point (one power-of-two scale
+ * per mesh, from its largest |coordinate|), so the result does not depend on
+ * thread order.
  * out_report (host, nullable, 4 entries): [0] number of directed edges without
- * exactly one reverse, [1] number of repeated directed edges, [2] number of
- * out-of-range indices, [3] unused (0).  *out_volume (host, nullable): the
- * signed enclosed volume (float64).
+ * exactly one reverse (an edge (a, a) has none), [1] number of repeated
+ * directed edges, [2] number of out-of-range indices, [3] unused (0).
+ * *out_volume (host, nullable): the signed enclosed volume (float64; 0 when an
+ * index is out of range).
  * Returns OBBV_OK, OBBV_ERR_MESH_NOT_CLOSED, OBBV_ERR_MESH_NOT_ORIENTED or
  * OBBV_ERR_INVALID_ARG. */
 int obbv_validate_mesh(const obbv_mesh* mesh, int32_t* out_report, double* out_volume,

@@ -50,7 +50,8 @@ enum PoolSlot {
   kPoolLists = 4,  // frame lists of grouped calls
   kPoolItems = 5,  // cast items
   kPoolRank = 6,
-  kPoolCount = 7
+  kPoolMesh = 7,   // mesh validation: edge table and counters
+  kPoolCount = 8
 };
 // Two sets of the slots: calls that may run at the same time on different
 // streams take their scratch from different sets (slot + set * kPoolCount).

@@ -359,70 +359,3 @@ extern "C" int obbv_release(void) {
 // ---------------------------------------------------------------------------
 // C ABI: mesh validation (synchronous, host side)
 // ---------------------------------------------------------------------------
-extern "C" int obbv_validate_mesh(const obbv_mesh* mesh, int32_t* out_report, double* out_volume,
-                                  void* stream) {
-  clear_error();
-  OBBV_ARG(mesh != nullptr, "mesh is NULL");
-  OBBV_ARG(mesh->n_triangles >= 0 && mesh->n_vertices >= 0, "negative mesh size");
-  OBBV_ARG(mesh->n_triangles == 0 || (mesh->triangles && mesh->vertices), "mesh pointers are NULL");
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t nt = mesh->n_triangles, nv = mesh->n_vertices;
-  std::vector<int32_t> F((size_t)nt * 3);
-  std::vector<float> V((size_t)nv * 3);
-  if (nt) OBBV_HIP(hipMemcpyAsync(F.data(), mesh->triangles, F.size() * 4, hipMemcpyDeviceToHost, s));
-  if (nv) OBBV_HIP(hipMemcpyAsync(V.data(), mesh->vertices, V.size() * 4, hipMemcpyDeviceToHost, s));
-  OBBV_HIP(hipStreamSynchronize(s));
-  int32_t bad_index = 0;
-  for (int32_t x : F)
-    if (x < 0 || x >= nv) ++bad_index;
-  int32_t report[4] = {0, 0, bad_index, 0};
-  double vol = 0.0;
-  if (bad_index == 0 && nt > 0) {
-    std::vector<uint64_t> e;
-    e.reserve((size_t)nt * 3);
-    for (int64_t t = 0; t < nt; ++t)
-      for (int k = 0; k < 3; ++k) {
-        uint32_t a = (uint32_t)F[3 * t + k], b = (uint32_t)F[3 * t + (k + 1) % 3];
-        e.push_back(((uint64_t)a << 32) | b);
-      }
-    std::sort(e.begin(), e.end());
-    int32_t repeated = 0, unmatched = 0;
-    for (size_t i = 0; i < e.size(); ++i) {
-      if (i + 1 < e.size() && e[i + 1] == e[i]) ++repeated;
-      uint64_t rev = (e[i] << 32) | (e[i] >> 32);
-      auto range = std::equal_range(e.begin(), e.end(), rev);
-      if (range.second - range.first != 1) ++unmatched;
-    }
-    report[0] = unmatched;
-    report[1] = repeated;
-    for (int64_t t = 0; t < nt; ++t) {
-      const float* a = &V[3 * (size_t)F[3 * t + 0]];
-      const float* b = &V[3 * (size_t)F[3 * t + 1]];
-      const float* c = &V[3 * (size_t)F[3 * t + 2]];
-      double bc0 = (double)b[1] * c[2] - (double)b[2] * c[1];
-      double bc1 = (double)b[2] * c[0] - (double)b[0] * c[2];
-      double bc2 = (double)b[0] * c[1] - (double)b[1] * c[0];
-      vol += (double)a[0] * bc0 + (double)a[1] * bc1 + (double)a[2] * bc2;
-    }
-    vol /= 6.0;
-  }
-  if (out_report) std::memcpy(out_report, report, sizeof(report));
-  if (out_volume) *out_volume = vol;
-  if (bad_index) {
-    set_error("triangle index out of range");
-    return OBBV_ERR_INVALID_ARG;
-  }
-  if (report[1]) {
-    set_error("a directed edge occurs more than once (inconsistent orientation)");
-    return OBBV_ERR_MESH_NOT_ORIENTED;
-  }
-  if (report[0]) {
-    set_error("a directed edge has no reverse edge (mesh not closed)");
-    return OBBV_ERR_MESH_NOT_CLOSED;
-  }
-  if (nt > 0 && !(vol > 0.0)) {
-    set_error("enclosed volume is not positive (triangles not outward oriented)");
-    return OBBV_ERR_MESH_NOT_ORIENTED;
-  }
-  return OBBV_OK;
-}

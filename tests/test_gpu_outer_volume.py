@@ -324,7 +324,25 @@ def test_jitter_table_and_computed_draws_agree(api):
     assert np.array_equal(plain, got["obv"])
 
 
+def _edge_report(F, nv):
+    """Brute-force counts of the validation report: directed edges whose reverse
+    does not occur exactly once, repeats of a directed edge, bad indices."""
+    from collections import Counter
+    F = np.asarray(F, np.int64)
+    bad = int(((F < 0) | (F >= nv)).sum())
+    edges = Counter()
+    for a, b, c in F.tolist():
+        for u, v in ((a, b), (b, c), (c, a)):
+            edges[(u, v)] += 1
+    unmatched = sum(m for (u, v), m in edges.items() if u == v or edges.get((v, u), 0) != 1)
+    repeated = sum(m - 1 for m in edges.values())
+    return [unmatched, repeated, bad]
+
+
 def test_validate_mesh(api):
+    """Device edge table and exact volume sum: reports equal to brute-force
+    counts on closed, open, flipped and bad-index meshes; the volume matches
+    the oracle's sum of det / 6 and is bit-identical for any triangle order."""
     import torch
     V, F = synth.icosphere(2)
     Vt = torch.from_numpy(V).cuda()
@@ -332,10 +350,25 @@ def test_validate_mesh(api):
     assert code == 0 and rep[:3] == [0, 0, 0] and vol > 0
     assert abs(vol - geometry.signed_volume(V, F)) <= 1e-12 * abs(vol)
     code, rep, _ = api.validate_mesh(Vt, torch.from_numpy(F[1:].copy()).cuda())
-    assert code == -2 and rep[0] == 3
+    assert code == -2 and rep[:3] == _edge_report(F[1:], len(V)) and rep[0] == 3
     Fb = F.copy()
     Fb[5] = Fb[5][[0, 2, 1]]
     code, rep, _ = api.validate_mesh(Vt, torch.from_numpy(Fb).cuda())
-    assert code == -3 and rep[1] > 0
+    assert code == -3 and rep[:3] == _edge_report(Fb, len(V)) and rep[1] == 3
     code, _, vol = api.validate_mesh(Vt, torch.from_numpy(F[:, [0, 2, 1]].copy()).cuda())
     assert code == -3 and vol < 0
+    Fi = F.copy()
+    Fi[7, 1] = len(V) + 3
+    Fi[9, 0] = -1
+    code, rep, _ = api.validate_mesh(Vt, torch.from_numpy(Fi).cuda())
+    assert code == -1 and rep[2] == 2
+    # bigger meshes: volume against the oracle, bit-identical under permutation
+    g = np.random.default_rng(0)
+    for V, F in (synth.noisy_torus(), synth.noisy_cube_sphere(60, seed=4)):
+        Vt = torch.from_numpy(V).cuda()
+        code, rep, vol = api.validate_mesh(Vt, torch.from_numpy(F).cuda())
+        assert code == 0 and rep[:3] == [0, 0, 0]
+        ref = geometry.signed_volume(V, F)
+        assert abs(vol - ref) <= 1e-12 * abs(ref), (vol, ref)
+        _, _, vol2 = api.validate_mesh(Vt, torch.from_numpy(F[g.permutation(len(F))].copy()).cuda())
+        assert vol2 == vol
