@@ -315,6 +315,23 @@ int obbv_lloyd_set_groups(obbv_lloyd* st, int32_t n_boxes, const int32_t* tri_gr
  * rotation gradient, line search, kept if OBV drops). */
 int obbv_lloyd_step(obbv_lloyd* st, void* stream);
 
+/* Synchronous, like obbv_lloyd_step.  The adjustment of Sec. 4.2.1 (third step:
+ * when the iteration stalls in a local minimum, the least important box is
+ * adjusted and the result kept only if the error drops), for every group with
+ * two boxes or more.  Reading of importance: the number of triangles a box
+ * holds; ties go to the box with the larger outer volume, then the higher box
+ * index.  The least important box moves to the centroid of the triangle
+ * farthest from the centre of the group's box with the largest outer volume
+ * (ties: lower box index, lower triangle index) and takes that box's axes; one
+ * Lloyd iteration of the adjusted groups follows (as obbv_lloyd_step), and a
+ * group keeps it only if the sum of its boxes' outer volumes is lower than
+ * before, else its boxes, outer volumes and assignments are restored.  Groups
+ * that were not adjusted are left unchanged.  Call after obbv_lloyd_step; the
+ * caller decides when the iteration has stalled.
+ * out_accepted (host, nullable, [number of groups]): 1 kept, 0 undone, -1 not
+ * adjusted (fewer than two boxes, or the worst box holds no triangle). */
+int obbv_lloyd_adjust(obbv_lloyd* st, int32_t* out_accepted, void* stream);
+
 /* Host.  With a non-NULL surrogate, later flood rounds predict the outer
  * fraction f of every candidate box (a box grown by a popped triangle that no box
  * of its group contains) and of the current boxes, with the predicted change

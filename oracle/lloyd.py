@@ -23,6 +23,9 @@ Parameter update (step 2): tight box for the current axes, then a finite
 difference gradient of OBV over the three rotation angles (+-delta about each
 local axis) and a steepest-descent line search; the best candidate is kept if
 it lowers OBV.
+Adjustment (step 3, for a stalled iteration): the least important box (fewest
+triangles) is re-seeded inside the worst-fitting box; kept only if the group's
+error drops (``adjust``).
 
 Boxes are stored as float32 (centre and axes rounded to nearest, half extents
 rounded up so the box still encloses), as the HIP path stores them; OBV values
@@ -479,21 +482,72 @@ def update_box(V, F, tris, Q, slot, evaluate, delta=0.02, steps=(8.0, 4.0, 2.0, 
 # ---------------------------------------------------------------------------
 # one Lloyd iteration of a group, and the hierarchy weights
 # ---------------------------------------------------------------------------
-def lloyd_iteration(V, F, adj, group, centers, axes, slots, evaluate, K=32):
-    """Partition then update every box; returns (clusters, boxes, obv, layer error)."""
-    assign, boxes, obv, cnt = flood_partition(V, F, adj, group, centers, axes, slots, evaluate, K)
+def lloyd_iteration(V, F, adj, group, centers, axes, slots, evaluate, K=32, follow=None, follow_boxes=None,
+                    tie=2e-5, counters=None):
+    """Partition then update every box; returns (clusters, boxes, obv, layer error, flood counters).
+    ``follow`` / ``follow_boxes`` (optional) name another implementation's
+    choices, taken only where they are as valid as this one's (see ``flood`` and
+    ``update_box``)."""
+    assign, boxes, obv, cnt = flood_partition(V, F, adj, group, centers, axes, slots, evaluate, K, follow, tie)
     b = len(centers)
-    clusters = [[t for t, i in assign.items() if i == k] for k in range(b)]
+    clusters = [sorted(t for t, i in assign.items() if i == k) for k in range(b)]
     out_boxes, out_obv = [], []
     for k in range(b):
         if not clusters[k]:
             out_boxes.append(boxes[k])
             out_obv.append(float(obv[k]))
             continue
-        bx, v, _ = update_box(V, F, clusters[k], boxes[k][1], slots[k], evaluate)
+        fb = follow_boxes(k) if follow_boxes is not None else None
+        bx, v, _ = update_box(V, F, clusters[k], boxes[k][1], slots[k], evaluate, follow_box=fb, tie=tie,
+                              counters=counters)
         out_boxes.append(bx)
         out_obv.append(v)
     return clusters, out_boxes, np.array(out_obv), float(np.sum(out_obv)), cnt
+
+
+# ---------------------------------------------------------------------------
+# adjustment (Sec. 4.2.1, third step)
+# ---------------------------------------------------------------------------
+def least_important(clusters, obv):
+    """The box of least importance: the fewest triangles; ties go to the larger
+    outer volume, then to the higher index."""
+    return min(range(len(clusters)), key=lambda i: (len(clusters[i]), -float(obv[i]), -i))
+
+
+def adjust(V, F, adj, group, clusters, boxes, obv, slots, evaluate, K=32, follow=None, follow_boxes=None,
+           tie=2e-5, counters=None):
+    """One adjustment of a group's boxes, for when the Lloyd iteration stalls.
+
+    The least important box is re-seeded where the group fits worst: its centre
+    moves to the centroid of the triangle farthest from the centre of the box
+    with the largest outer volume (ties: lower index; farthest: ties to the lower
+    triangle index), and it takes that box's axes.  One Lloyd iteration then
+    runs from the adjusted centres and axes; its result is kept if the group's
+    error (sum of OBV) is lower than before, else the group is left as it was.
+
+    Returns (accepted, clusters, boxes, obv, error)."""
+    b = len(boxes)
+    e0 = float(np.sum(obv))
+    if b < 2:
+        return False, clusters, boxes, obv, e0
+    j = least_important(clusters, obv)
+    w = min((i for i in range(b) if i != j), key=lambda i: (-float(obv[i]), i))
+    if not clusters[w]:
+        return False, clusters, boxes, obv, e0
+    cen = _centroids(np.asarray(V), np.asarray(F))
+    cw = np.asarray(boxes[w][0], np.float32).astype(np.float64)
+    tw = np.asarray(sorted(clusters[w]))
+    d = np.linalg.norm(cen[tw] - cw, axis=1)
+    t = int(tw[np.flatnonzero(d == d.max())[0]])
+    centers = [np.asarray(bx[0], np.float32) for bx in boxes]
+    axes = [np.asarray(bx[1], np.float32) for bx in boxes]
+    centers[j] = cen[t].astype(np.float32)
+    axes[j] = np.asarray(boxes[w][1], np.float32).copy()
+    c2, b2, o2, e2, _ = lloyd_iteration(V, F, adj, group, centers, axes, slots, evaluate, K, follow, follow_boxes,
+                                        tie, counters)
+    if e2 < e0:
+        return True, c2, b2, o2, e2
+    return False, clusters, boxes, obv, e0
 
 
 def layer_weights(n_levels):

@@ -88,6 +88,7 @@ SIGNATURES = {
                                     ctypes.POINTER(c_void_p)]),
     "obbv_lloyd_set_groups": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "obbv_lloyd_step": (c_int32, [c_void_p, c_void_p]),
+    "obbv_lloyd_adjust": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "obbv_lloyd_set_surrogate": (c_int32, [c_void_p, ctypes.POINTER(ObbvSurrogate)]),
     "obbv_lloyd_get": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double_p,
                                  ctypes.POINTER(ctypes.c_int64)]),

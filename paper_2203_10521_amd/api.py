@@ -216,11 +216,19 @@ class Lloyd:
         boxes = np.ascontiguousarray(boxes, dtype=np.float32).reshape(-1, BOX_FLOATS)
         slot = None if box_slot is None else np.ascontiguousarray(box_slot, dtype=np.uint32)
         self.n_boxes = boxes.shape[0]
+        self.n_groups = int(box_group.max()) + 1 if len(box_group) else 0
         _check(_lib.lib().obbv_lloyd_set_groups(self._h, self.n_boxes, _host_ptr(tri_group), _host_ptr(box_group),
                                                 _host_ptr(boxes), _host_ptr(slot)))
 
     def step(self):
         _check(_lib.lib().obbv_lloyd_step(self._h, _stream(self._stream)))
+
+    def adjust(self):
+        """One adjustment of every group (obbv_lloyd_adjust): per group 1 kept,
+        0 undone, -1 not adjusted."""
+        acc = np.empty(self.n_groups, np.int32)
+        _check(_lib.lib().obbv_lloyd_adjust(self._h, _host_ptr(acc), _stream(self._stream)))
+        return acc
 
     def get(self):
         tri_box = np.empty(self.n_triangles, np.int32)

@@ -1589,6 +1589,97 @@ static int lloyd_iterate(LloydState& S) {
   return OBBV_OK;
 }
 
+// One adjustment of every group with two boxes or more (Sec. 4.2.1, third
+// step): the least important box (fewest triangles; ties: larger outer volume,
+// then higher index) moves to the centroid of the triangle farthest from the
+// centre of the group's box with the largest outer volume (ties: lower index;
+// farthest: ties to the lower triangle), with that box's axes; one Lloyd
+// iteration of the adjusted groups follows, and each group keeps its result
+// only if its error (sum of its boxes' outer volumes) drops.
+static int lloyd_adjust(LloydState& S, int32_t* out_accepted) {
+  const int G = (int)S.groups.size();
+  std::vector<int64_t> cnt(S.boxes.size(), 0);
+  for (int t = 0; t < S.M.nt; ++t)
+    if (S.tri_box[t] >= 0) ++cnt[S.tri_box[t]];
+  const std::vector<HBox> boxes0 = S.boxes;
+  const std::vector<double> obv0 = S.obv;
+  const std::vector<int32_t> tri_box0 = S.tri_box;
+  std::vector<int> state(G, -1);  // -1 not adjusted, 0 undone, 1 kept
+  std::vector<double> e0(G, 0.0);
+  std::vector<Group> adjusted;
+  for (int g = 0; g < G; ++g) {
+    const Group& gr = S.groups[g];
+    const int b = (int)gr.boxes.size();
+    if (b < 2 || gr.elems.empty()) continue;
+    for (int bi : gr.boxes) e0[g] += cnt[bi] > 0 ? S.obv[bi] : 0.0;
+    int j = 0;
+    for (int i = 1; i < b; ++i) {
+      const int bi = gr.boxes[i], bj = gr.boxes[j];
+      if (cnt[bi] < cnt[bj] || (cnt[bi] == cnt[bj] && (S.obv[bi] > S.obv[bj] || (S.obv[bi] == S.obv[bj]))))
+        j = i;
+    }
+    int w = -1;
+    for (int i = 0; i < b; ++i)
+      if (i != j && (w < 0 || S.obv[gr.boxes[i]] > S.obv[gr.boxes[w]])) w = i;
+    const int bw = gr.boxes[w];
+    if (cnt[bw] == 0) continue;
+    int far = -1;
+    double fd = -1.0;
+    for (int e : gr.elems) {
+      if (S.tri_box[e] != bw) continue;  // elements are the group's triangles
+      const double d = dist3(&S.M.cen[3 * (size_t)e], S.boxes[bw].c);
+      if (d > fd || (d == fd && e < far)) {
+        fd = d;
+        far = e;
+      }
+    }
+    HBox& bj = S.boxes[gr.boxes[j]];
+    for (int k = 0; k < 3; ++k) bj.c[k] = (float)S.M.cen[3 * (size_t)far + k];
+    std::memcpy(bj.Q, S.boxes[bw].Q, 36);
+    state[g] = 0;
+    adjusted.push_back(gr);
+  }
+  if (!adjusted.empty()) {
+    std::vector<Group> all;
+    all.swap(S.groups);
+    S.groups = adjusted;
+    const int rc = lloyd_iterate(S);
+    S.groups.swap(all);
+    OBBV_RET(rc);
+    // triangles of the groups that were not adjusted keep their boxes
+    for (int g = 0; g < G; ++g)
+      if (state[g] < 0)
+        for (int e : S.groups[g].elems) S.tri_box[e] = tri_box0[e];
+    for (int g = 0; g < G; ++g) {
+      if (state[g] < 0) continue;
+      const Group& gr = S.groups[g];
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (int e : gr.elems)
+        if (S.tri_box[e] >= 0) ++cnt[S.tri_box[e]];
+      double e1 = 0.0;
+      for (int bi : gr.boxes) e1 += cnt[bi] > 0 ? S.obv[bi] : 0.0;
+      if (e1 < e0[g]) {
+        state[g] = 1;
+        continue;
+      }
+      for (int bi : gr.boxes) {
+        S.boxes[bi] = boxes0[bi];
+        S.obv[bi] = obv0[bi];
+      }
+      for (int e : gr.elems) S.tri_box[e] = tri_box0[e];
+    }
+    // boxes of groups that were not adjusted are untouched by the iteration
+    S.layer_error = 0.0;
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int t = 0; t < S.M.nt; ++t)
+      if (S.tri_box[t] >= 0) ++cnt[S.tri_box[t]];
+    for (size_t bi = 0; bi < S.boxes.size(); ++bi) S.layer_error += cnt[bi] > 0 ? S.obv[bi] : 0.0;
+  }
+  if (out_accepted)
+    for (int g = 0; g < G; ++g) out_accepted[g] = state[g];
+  return OBBV_OK;
+}
+
 }  // namespace obbv
 
 using namespace obbv;
@@ -1660,6 +1751,16 @@ extern "C" int obbv_lloyd_step(obbv_lloyd* st, void* stream) {
   S.ev.stream = (hipStream_t)stream;
   S.pred.stream = (hipStream_t)stream;
   return lloyd_iterate(S);
+}
+
+extern "C" int obbv_lloyd_adjust(obbv_lloyd* st, int32_t* out_accepted, void* stream) {
+  clear_error();
+  OBBV_ARG(st, "NULL state");
+  LloydState& S = *reinterpret_cast<LloydState*>(st);
+  OBBV_ARG(!S.groups.empty(), "obbv_lloyd_set_groups was not called");
+  S.ev.stream = (hipStream_t)stream;
+  S.pred.stream = (hipStream_t)stream;
+  return lloyd_adjust(S, out_accepted);
 }
 
 extern "C" int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* sur) {

@@ -147,3 +147,98 @@ def test_hierarchy_top_down_and_one_sweep_match_the_oracle(api):
                    "trace": [[t[0], t[1], t[4]] for t in H.trace], "max_box_gap": max(g1[0], g2[0]),
                    "max_obv_gap_rel": max(g1[1], g2[1]), "e_oracle": e, "e_device": [float(x) for x in sw["e"]]})
     assert H.counters["ties"] <= 8
+
+
+def _pack(centers, axes):
+    n = len(centers)
+    return synth.boxes_to_array(np.asarray(centers), np.asarray(axes), np.zeros((n, 3), np.float32))
+
+
+def _follows(out, bxs):
+    local = {int(j): i for i, j in enumerate(bxs)}
+    row = out["boxes"]
+    return (lambda e: local.get(int(out["tri_box"][e])),
+            lambda k: (row[bxs[k], :3], row[bxs[k], 3:12].reshape(3, 3), row[bxs[k], 12:]))
+
+
+def _check_group(out, bxs, clusters, boxes, obv, ref_tri, gaps):
+    for i, j in enumerate(bxs):
+        ref_tri[clusters[i]] = j
+        c, Q, h = boxes[i]
+        got = out["boxes"][j]
+        gaps[0] = max(gaps[0], _box_gap(np.concatenate([c, Q.reshape(-1), h]), got))
+        gaps[1] = max(gaps[1], abs(out["obv"][j] - obv[i]) / max(ol.box_volume(h), 1e-30))
+
+
+@pytest.mark.timeout(900)
+def test_adjustment_matches_the_oracle(api):
+    """The adjustment step (Sec. 4.2.1, third step) from the same states as the
+    oracle.  Stalled cuboids (two boxes in one cuboid, one over the other two):
+    two adjustments kept, a third undone, the same partitions and boxes.  The
+    8 x 4 torus groups after one K = 32 iteration: the same kept / undone flag
+    per group, partition, boxes and outer volumes (1e-5)."""
+    import torch
+    counters = {"ties": 0}
+    # stalled cuboids
+    V, F, comp, params = synth.disjoint_cuboids(3, seed=7, spacing=3.0)
+    cen = V[F].astype(np.float64).mean(1)
+    t0, t1 = np.nonzero(comp == 0)[0], np.nonzero(comp == 1)[0]
+    centers = np.array([cen[t0[0]], cen[t0[-1]], cen[t1[0]]], np.float32)
+    axes = np.array([params[0][1], params[0][1], params[1][1]], np.float32)
+    R, seed, K = 16, 3, 4
+    Vt, Ft = _dev(V, F)
+    outs, flags = [], []
+    with api.Lloyd(Vt, Ft, R=R, seed=seed, pops_per_round=K) as L:
+        L.set_groups(np.zeros(len(F), np.int32), np.zeros(3, np.int32), _pack(centers, axes), [0, 1, 2])
+        L.step()
+        outs.append(L.get())
+        for _ in range(3):
+            flags.append(int(L.adjust()[0]))
+            outs.append(L.get())
+    assert flags == [1, 1, 0]
+    adj = ol.adjacency(F)
+    group, bxs = range(len(F)), np.arange(3)
+    with RaygridPool(V, F, R, seed, workers=1) as ev:
+        fol, folb = _follows(outs[0], bxs)
+        state = ol.lloyd_iteration(V, F, adj, group, centers, axes, [0, 1, 2], ev, K, fol, folb, TIE, counters)[:3]
+        for k in range(3):
+            fol, folb = _follows(outs[k + 1], bxs)
+            acc, *nxt = ol.adjust(V, F, adj, group, *state, [0, 1, 2], ev, K, fol, folb, TIE, counters)
+            assert int(acc) == flags[k]
+            state = nxt[:3]
+            ref_tri, gaps = np.full(len(F), -1), [0.0, 0.0]
+            _check_group(outs[k + 1], bxs, state[0], state[1], state[2], ref_tri, gaps)
+            assert np.array_equal(outs[k + 1]["tri_box"], ref_tri), k
+            assert gaps[0] <= 1e-5 and gaps[1] <= 1e-5, (k, gaps)
+    assert sorted(sorted(set(comp[outs[3]["tri_box"] == j])) for j in range(3)) == [[0], [1], [2]]
+    # torus groups
+    V, F, tri_group, B, box_group = _torus_groups()
+    slots = (7 + 3 * np.arange(len(B))).astype(np.uint32)
+    R, seed, K = 16, 9, 32
+    Vt, Ft = _dev(V, F)
+    with api.Lloyd(Vt, Ft, R=R, seed=seed, pops_per_round=K) as L:
+        L.set_groups(tri_group, box_group, B, slots)
+        L.step()
+        pre = L.get()
+        acc = L.adjust()
+        post = L.get()
+    E = ol.triangle_elements(V, F)
+    adj = E.adj
+    ref_tri, gaps = np.full(len(F), -1), [0.0, 0.0]
+    with RaygridPool(V, F, R, seed) as ev:
+        for g in range(8):
+            bxs = np.nonzero(box_group == g)[0]
+            elems = np.nonzero(tri_group == g)[0]
+            fol, folb = _follows(pre, bxs)
+            state = ol.lloyd_iteration(V, F, adj, elems, B[bxs, :3], B[bxs, 3:12].reshape(-1, 3, 3), slots[bxs], ev,
+                                       K, fol, folb, TIE, counters)[:3]
+            fol, folb = _follows(post, bxs)
+            a, cl, bx, obv, _ = ol.adjust(V, F, adj, elems, *state, slots[bxs], ev, K, fol, folb, TIE, counters)
+            assert int(a) == int(acc[g]), g
+            _check_group(post, bxs, cl, bx, obv, ref_tri, gaps)
+    record_parity({"test": "lloyd_adjustment_cuboids_and_torus_8x4", "kept": int((acc == 1).sum()),
+                   "undone": int((acc == 0).sum()), "ties": counters["ties"],
+                   "update_ties": counters.get("update_ties", 0), "max_box_gap": gaps[0],
+                   "max_obv_gap_rel": gaps[1]})
+    assert np.array_equal(post["tri_box"], ref_tri)
+    assert gaps[0] <= 1e-5 and gaps[1] <= 1e-5

@@ -141,3 +141,67 @@ def test_update_takes_a_twin_within_noise_but_not_another_rotation():
     got = lloyd.update_box(V, F, tris, Q, 4, ev, follow_box=wrong, counters=cnt)
     assert cnt.get("update_ties", 0) == 0
     assert np.array_equal(got[0][1], mine[0][1]) and got[1] == mine[1]
+
+
+def _stalled_cuboids():
+    """Three disjoint cuboids; two boxes start in cuboid 0 and one in cuboid 1,
+    so no flood reaches cuboid 2 and the partition mixes cuboids 1 and 2."""
+    V, F, comp, params = synth.disjoint_cuboids(3, seed=7, spacing=3.0)
+    cen = V[F].astype(np.float64).mean(1)
+    t0, t1 = np.nonzero(comp == 0)[0], np.nonzero(comp == 1)[0]
+    centers = np.array([cen[t0[0]], cen[t0[-1]], cen[t1[0]]], np.float32)
+    axes = np.array([params[0][1], params[0][1], params[1][1]], np.float32)
+    return V, F, comp, centers, axes
+
+
+def test_adjustment_reseeds_a_redundant_box():
+    """Sec. 4.2.1, third step: plain iterations keep two boxes in one cuboid and
+    one box over the other two; each adjustment moves the least important box
+    (fewest triangles) into the worst-fitting box and is kept because the error
+    drops; after two, every box holds exactly one cuboid; a third is undone and
+    leaves the state as it was."""
+    V, F, comp, centers, axes = _stalled_cuboids()
+    adj = lloyd.adjacency(F)
+    ev = _exact_eval(V, F)
+    group, slots = range(len(F)), [0, 1, 2]
+    cl, bx, obv, e, _ = lloyd.lloyd_iteration(V, F, adj, group, centers, axes, slots, ev, K=4)
+    c2, b2, o2, e2, _ = lloyd.lloyd_iteration(V, F, adj, group, [b[0] for b in bx], [b[1] for b in bx], slots, ev,
+                                              K=4)
+    assert sorted(sorted(set(comp[c])) for c in c2) == [[0], [0], [1, 2]]
+    assert lloyd.least_important(cl, obv) in (0, 1)
+    state = (cl, bx, obv, e)
+    errors = [e]
+    for k in range(2):
+        acc, *state = lloyd.adjust(V, F, adj, group, *state[:3], slots, ev, K=4)
+        assert acc and state[3] < errors[-1]
+        errors.append(state[3])
+    assert sorted(sorted(set(comp[c])) for c in state[0]) == [[0], [1], [2]]
+    acc, c3, b3, o3, e3 = lloyd.adjust(V, F, adj, group, *state[:3], slots, ev, K=4)
+    assert not acc and c3 is state[0] and b3 is state[1] and o3 is state[2] and e3 == state[3]
+
+
+def test_adjustment_is_kept_only_when_the_error_drops():
+    """Iterations and adjustments alternating on a noisy sphere: every kept
+    adjustment lowers the group's error, every undone one returns the state
+    unchanged, so the error after each adjustment never exceeds the error before."""
+    V, F = synth.noisy_cube_sphere(4, seed=12)
+    adj = lloyd.adjacency(F)
+    ev = _raygrid_eval(V, F, R=6)
+    g = np.random.default_rng(2)
+    cen = V[F].astype(np.float64).mean(1)
+    centers = cen[g.choice(len(F), 4, replace=False)].astype(np.float32)
+    axes = np.stack([np.eye(3, dtype=np.float32)] * 4)
+    group, slots = range(len(F)), [3, 4, 5, 6]
+    cl, bx, obv, e, _ = lloyd.lloyd_iteration(V, F, adj, group, centers, axes, slots, ev, K=8)
+    outcomes = []
+    for _ in range(3):
+        acc, cl2, bx2, obv2, e2 = lloyd.adjust(V, F, adj, group, cl, bx, obv, slots, ev, K=8)
+        assert e2 <= e
+        if acc:
+            assert e2 < e
+        else:
+            assert cl2 is cl and e2 == e
+        outcomes.append(acc)
+        cl, bx, obv, e, _ = lloyd.lloyd_iteration(V, F, adj, group, [b[0] for b in bx2], [b[1] for b in bx2], slots,
+                                                  ev, K=8)
+    assert len(outcomes) == 3
