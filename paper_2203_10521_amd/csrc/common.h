@@ -88,7 +88,17 @@ struct OvExec {
   // nullable: device float4 [n_meshes] centre of each mesh's bounding box (the
   // kept side of every cast); computed by the call when absent
   const float4* centre = nullptr;
+  // nullable: span bounds of the (single) mesh (span_table), reused from call to
+  // call; computed by the call when absent
+  const float4* spans = nullptr;
+  const float4* span_runs = nullptr;
 };
+// Span bounds table of a mesh for repeated single-mesh outer-volume calls:
+// its size in bytes (0: the mesh needs none), its computation (stream ordered)
+// and the run bounds inside it.
+size_t span_table_size(int64_t nt);
+int span_table(const obbv_mesh* m, float4* table, hipStream_t s);
+const float4* span_runs_of(const float4* table, int64_t nt);
 // Jitter table of keys [0, n_keys) for ray grids of R x R cells (stream ordered).
 int jitter_table(uint64_t seed, int R, int64_t n_keys, uint2* out, hipStream_t s);
 int status_word(uint32_t** out);   // device pointer of this device's status word

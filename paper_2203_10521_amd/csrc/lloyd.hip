@@ -156,7 +156,26 @@ struct Evaluator {
     }
   }
 
+  // span bounds of the mesh (reused by every call; the mesh does not change
+  // during the state's life); the judge's evaluator borrows the table
+  float4* spans = nullptr;
+  bool spans_done = false, owns_spans = false;
+  int ensure_spans() {
+    if (spans_done) return OBBV_OK;
+    spans_done = true;
+    const size_t bytes = span_table_size(mesh.n_triangles);
+    if (!bytes) return OBBV_OK;
+    if (hipMalloc((void**)&spans, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      spans = nullptr;  // every call then computes its own
+      return OBBV_OK;
+    }
+    owns_spans = true;
+    return span_table(&mesh, spans, stream);
+  }
+
   ~Evaluator() {
+    if (owns_spans && spans) (void)hipFree(spans);
     if (jtab) (void)hipFree(jtab);
     if (dbuf) (void)hipFree(dbuf);
     if (hbuf) (void)hipHostFree(hbuf);
@@ -376,6 +395,7 @@ struct Evaluator {
     t_prep.stop();
     t_dev.start();
     OBBV_RET(ensure_jitter(keys));
+    OBBV_RET(ensure_spans());
     {
       const int64_t n16 = (int64_t)(o_out / 16);  // o_out is a multiple of 256
       const unsigned grid = (unsigned)std::min<int64_t>((n16 + 255) / 256, 64);
@@ -387,6 +407,8 @@ struct Evaluator {
       ex.status = (uint32_t*)(dbuf + o_ctl);
       ex.publish = (int64_t*)(hdev + o_ctl + 64);
       ex.centre = have_centre ? (const float4*)(dbuf + o_ctl + 192) : nullptr;
+      ex.spans = spans;
+      ex.span_runs = spans ? span_runs_of(spans, mesh.n_triangles) : nullptr;
       OBBV_RET(run_call(&ex));
       in_flight = true;
     }
@@ -496,6 +518,8 @@ struct Predictor {
     }
     jev.mesh = ev.mesh;
     jev.params = ev.params;
+    jev.spans = ev.spans;  // borrowed (the judge never frees it)
+    jev.spans_done = true;
     std::memcpy(jev.centre, ev.centre, 16);
     jev.have_centre = ev.have_centre;
     const size_t stride = (n + kWindow - 1) / kWindow;  // at most one window per judged round

@@ -9,10 +9,18 @@
 //   [k_frame_cull x 2,   boxes grouped by shared centre and axes: per (group,
 //    k_frame_scan]       cast axis), the frame-local coordinates of the triangles
 //                        in the group's kept half prism
+//   k_span_bounds        single-mesh calls on meshes of more than one cast item
+//                        (unless the caller has them): the bounding box of every
+//                        span of 256 consecutive triangles and of every run of 18
+//                        spans (one cast item); spans the kept half prism of a
+//                        cast cannot reach are skipped below (meshes whose
+//                        triangle order follows the surface -- grids, strips --
+//                        give tight spans; any order gives the same results)
 //   k_box_chunks         one block: the triangle list of every (box, axis) (its
 //                        group's list or the whole mesh) cut into cast items of
-//                        kCastTris entries, the ray grid of every cast, and the
-//                        per-call counters set to zero
+//                        kCastTris entries (whole-mesh runs whose bounds miss the
+//                        cast's kept half prism are left out), the ray grid of
+//                        every cast, and the per-call counters set to zero
 //   k_cast               persistent workgroups take (item, ray block) units from
 //                        a device queue: the item's triangles are culled against
 //                        the box's kept half prism and the block, the survivors
@@ -44,10 +52,13 @@ constexpr int kCastThreads = 768;    // 12 waves: three per SIMD, one workgroup 
 constexpr int kCastWaves = kCastThreads / 64;
 constexpr int kCastTris = 4608;      // triangle-list entries per cast item (6 cull steps; 384 per wave)
 constexpr int kBigCap = 64;          // records queued for the wave-wide test per round
-constexpr int kRasterCells = 64;     // records covering more cells take the wave-wide test
+constexpr int kRasterCells = 512;    // records covering more cells take the wave-wide test
 constexpr int kBlockRaysDefault = 16384;  // rays of one LDS ray block (float2 each): a whole
                                           // face up to R = 128
 constexpr int kBlockRaysMax = 16384;
+constexpr int kSpanTris = 256;                     // triangles per span (bounds table)
+constexpr int kSpansPerItem = kCastTris / kSpanTris;  // 18
+static_assert(kCastTris % kSpanTris == 0 && kSpansPerItem <= 64, "spans of an item fit one wave");
 
 struct BoxRegs {
   float Q[9];
@@ -253,6 +264,117 @@ __device__ inline bool cast_mirror(const BoxRegs& B, int w, const float4& cm) {
   return d < 0.f;
 }
 
+// Whether a world-space box [lo, hi] may hold a triangle that cast axis w of box
+// B keeps (the triangle projects into the face rectangle, margins included, and
+// reaches above -h_w on the kept side): separating-axis test on the three box
+// axes with a margin of 1e-4 of the magnitudes involved -- far above the float32
+// rounding of this test and of the kernels' local transforms (both a few units
+// of 2^-24 of the same magnitudes) -- so a span the test rejects holds no
+// triangle the cull would keep.  Non-finite bounds pass.
+__device__ inline bool span_may_cast(const BoxRegs& B, int w, bool mirror, const float4& lo, const float4& hi) {
+  if (lo.x > hi.x || lo.y > hi.y || lo.z > hi.z) return false;  // no valid triangle
+  // bounds relative to the box centre first (rounding relative to |x - c|, as
+  // in the kernels' transforms), then centre and half size
+  const float l0 = lo.x - B.c[0], l1 = lo.y - B.c[1], l2 = lo.z - B.c[2];
+  const float u0 = hi.x - B.c[0], u1 = hi.y - B.c[1], u2 = hi.z - B.c[2];
+  const float m0 = 0.5f * (l0 + u0), m1 = 0.5f * (l1 + u1), m2 = 0.5f * (l2 + u2);
+  const float r0 = 0.5f * (u0 - l0), r1 = 0.5f * (u1 - l1), r2 = 0.5f * (u2 - l2);
+  const float a0 = fabsf(m0) + r0, a1 = fabsf(m1) + r1, a2 = fabsf(m2) + r2;
+  float P[3], rad[3];
+#pragma unroll
+  for (int row = 0; row < 3; ++row) {
+    const float q0 = B.Q[3 * row], q1 = B.Q[3 * row + 1], q2 = B.Q[3 * row + 2];
+    P[row] = q0 * m0 + q1 * m1 + q2 * m2;
+    rad[row] = fabsf(q0) * r0 + fabsf(q1) * r1 + fabsf(q2) * r2 +
+               1e-4f * (fabsf(q0) * a0 + fabsf(q1) * a1 + fabsf(q2) * a2);
+  }
+  const int ua = (w + 1) % 3, va = (w + 2) % 3;
+  const float pu = pick3(P, ua), pv = pick3(P, va), pw = pick3(P, w);
+  const float ru = pick3(rad, ua), rv = pick3(rad, va), rw = pick3(rad, w);
+  const float mu = pick3(B.h, ua) * 1.0001f, mv = pick3(B.h, va) * 1.0001f, hw = pick3(B.h, w);
+  if (pu - ru > mu || pu + ru < -mu || pv - rv > mv || pv + rv < -mv) return false;
+  const float zmax = (mirror ? -pw : pw) + rw;
+  return !(zmax < -hw * 1.0001f);
+}
+
+// Bounds of every span of kSpanTris triangles and of every run of
+// kSpansPerItem spans (a whole-mesh cast item): one block of 4 waves per run,
+// each wave one span at a time.  Triangles with an out-of-range index are
+// flagged and left out; a span with a non-finite vertex gets infinite bounds.
+__global__ void __launch_bounds__(256)
+k_span_bounds(MeshDev M, float4* __restrict__ spans, float4* __restrict__ runs, uint32_t* status) {
+  __shared__ float red[4][6];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int run = blockIdx.x;
+  const int64_t n_spans = ((int64_t)M.nt + kSpanTris - 1) / kSpanTris;
+  float rlo[3] = {INFINITY, INFINITY, INFINITY}, rhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int sp = wave; sp < kSpansPerItem; sp += 4) {
+    const int64_t span = (int64_t)run * kSpansPerItem + sp;
+    if (span >= n_spans) break;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    for (int k = lane; k < kSpanTris; k += 64) {
+      const int64_t t = span * kSpanTris + k;
+      if (t >= M.nt) break;
+      const int32_t* f = M.F + 3 * t;
+      const int idx[3] = {f[0], f[1], f[2]};
+      if ((unsigned)idx[0] >= (unsigned)M.nv || (unsigned)idx[1] >= (unsigned)M.nv ||
+          (unsigned)idx[2] >= (unsigned)M.nv) {
+        atomicOr(status, OBBV_STATUS_BAD_INDEX);
+        continue;
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const float x = M.V[3 * (int64_t)idx[j] + d];
+          bad = bad || !isfinite(x);
+          lo[d] = fminf(lo[d], x);
+          hi[d] = fmaxf(hi[d], x);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = fminf(lo[d], __shfl_xor(lo[d], off));
+        hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], off));
+      }
+    if (__any(bad))
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = -INFINITY;
+        hi[d] = INFINITY;
+      }
+    if (lane == 0) {
+      spans[2 * span] = make_float4(lo[0], lo[1], lo[2], 0.f);
+      spans[2 * span + 1] = make_float4(hi[0], hi[1], hi[2], 0.f);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      rlo[d] = fminf(rlo[d], lo[d]);
+      rhi[d] = fmaxf(rhi[d], hi[d]);
+    }
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      red[wave][d] = rlo[d];
+      red[wave][3 + d] = rhi[d];
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fminf(fminf(red[0][d], red[1][d]), fminf(red[2][d], red[3][d]));
+      hi[d] = fmaxf(fmaxf(red[0][3 + d], red[1][3 + d]), fmaxf(red[2][3 + d], red[3][3 + d]));
+    }
+    runs[2 * run] = make_float4(lo[0], lo[1], lo[2], 0.f);
+    runs[2 * run + 1] = make_float4(hi[0], hi[1], hi[2], 0.f);
+  }
+}
+
 // Centre of each mesh's bounding box (xyz, w unused): one block per mesh.
 __global__ void __launch_bounds__(256)
 k_mesh_centre(const MeshDev* __restrict__ meshes, MeshDev mesh0, int n_meshes, float4* __restrict__ out) {
@@ -439,7 +561,8 @@ __device__ inline bool kept(const CastTri& tr, const CastFrame& f) {
 __global__ void __launch_bounds__(kCullThreads)
 k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, const float4* __restrict__ centre,
              uint32_t axis_mask, int nch, int32_t* __restrict__ item_cnt, const int32_t* __restrict__ item_off,
-             const int64_t* __restrict__ list_off, float4* __restrict__ list_P, uint32_t* status) {
+             const int64_t* __restrict__ list_off, float4* __restrict__ list_P, uint32_t* status,
+             const float4* __restrict__ spans) {
   __shared__ int32_t wc[3][kCullWaves];
   const int64_t total = (int64_t)n_frames * nch;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -449,13 +572,20 @@ k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, const
     const int ch = (int)(fc - (int64_t)fr * nch);
     const int t = ch * kCullThreads + threadIdx.x;
     const BoxRegs B = load_box(frames, fr);
+    // the axes whose kept half prism the chunk (one span) may reach
+    uint32_t reach = axis_mask;
+    if (spans) {
+      const float4 lo = spans[2 * ch], hi = spans[2 * ch + 1];
+      for (int w = 0; w < 3; ++w)
+        if (((reach >> w) & 1u) && !span_may_cast(B, w, cast_mirror(B, w, cm), lo, hi)) reach &= ~(1u << w);
+    }
     float P[3][3];
-    const bool ok = box_state(B) == 0 && t < M.nt && load_tri_local(M, t, B, P, status);
+    const bool ok = reach != 0u && box_state(B) == 0 && t < M.nt && load_tri_local(M, t, B, P, status);
     uint64_t mk[3];
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       bool keep = false;
-      if (ok && ((axis_mask >> w) & 1u)) {
+      if (ok && ((reach >> w) & 1u)) {
         const CastFrame f = cast_bounds(B, w);
         keep = kept(cast_tri(P, w, f, cast_mirror(B, w, cm)), f);
       }
@@ -549,7 +679,8 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
              const int64_t* __restrict__ list_off, int64_t* __restrict__ chunk_off, uint32_t* status,
              const uint32_t* __restrict__ box_key, int R, uint64_t seed, RayFrame* __restrict__ rframe,
              ItemInfo* __restrict__ items, int64_t item_cap, unsigned long long* __restrict__ acc,
-             unsigned long long* __restrict__ ctl) {
+             unsigned long long* __restrict__ ctl, const float4* __restrict__ runs,
+             const float4* __restrict__ centre) {
   __shared__ long long wsum[kScanBlockThreads / 64];
   if (threadIdx.x < 4) ctl[threadIdx.x] = 0ull;
   for (int e = threadIdx.x; e < 3 * n_boxes; e += blockDim.x) {
@@ -563,7 +694,9 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
     const int pr = p0 + (int)threadIdx.x;
     long long nch = 0;
     int64_t first = 0, ntri = 0;
-    bool list = false;
+    bool list = false, culled = false, mirror = false;
+    uint64_t rmask = 0;  // runs kept (the first 64)
+    BoxRegs Bx;
     if (pr < npairs) {
       const int b = pr / 3, w = pr - 3 * b;
       const int m = box_mesh ? box_mesh[b] : 0;
@@ -581,20 +714,49 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
         }
         ntri = n;
         nch = (n + kCastTris - 1) / kCastTris;
+        if (!list && runs && !meshes) {  // whole mesh: only the runs the kept half prism may reach
+          Bx = load_box(boxes, b);
+          mirror = cast_mirror(Bx, w, centre[0]);
+          culled = true;
+          long long c = 0;
+          const long long nr = (n + kCastTris - 1) / kCastTris;
+          for (long long r = 0; r < nr; ++r) {
+            const bool hit = span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1]);
+            if (r < 64 && hit) rmask |= 1ull << r;
+            c += hit ? 1 : 0;
+          }
+          nch = c;
+        }
       }
     }
     long long total = 0;
     const long long ex = block_excl_scan(nch, wsum, total);
     if (pr < npairs) {
       chunk_off[pr] = base + ex;
-      for (long long c = 0; c < nch; ++c) {
-        const long long it = base + ex + c;
-        if (it >= item_cap) break;
-        ItemInfo ii;
-        ii.bw3 = pr;
-        ii.count = (int32_t)min((int64_t)kCastTris, ntri - c * kCastTris);
-        ii.first = list ? first + c * kCastTris : -1 - c * kCastTris;
-        items[it] = ii;
+      if (culled) {
+        const int w = pr - 3 * (pr / 3);
+        long long c = 0;
+        for (long long r = 0; c < nch; ++r) {
+          if (r < 64 ? !((rmask >> r) & 1ull) : !span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1]))
+            continue;
+          const long long it = base + ex + c++;
+          if (it >= item_cap) break;
+          ItemInfo ii;
+          ii.bw3 = pr;
+          ii.count = (int32_t)min((int64_t)kCastTris, ntri - r * kCastTris);
+          ii.first = -1 - r * kCastTris;
+          items[it] = ii;
+        }
+      } else {
+        for (long long c = 0; c < nch; ++c) {
+          const long long it = base + ex + c;
+          if (it >= item_cap) break;
+          ItemInfo ii;
+          ii.bw3 = pr;
+          ii.count = (int32_t)min((int64_t)kCastTris, ntri - c * kCastTris);
+          ii.first = list ? first + c * kCastTris : -1 - c * kCastTris;
+          items[it] = ii;
+        }
       }
     }
     base += total;
@@ -750,6 +912,7 @@ struct CastArgs {
   int32_t* ray_hits;         // nullable [n_boxes][3][R][R]: crossings in the slab + 65536 x beyond it
   int32_t* occ;              // nullable [n_boxes][8][8][8]: sub-slab inside lengths in 2^-19 of a sub-slab
   unsigned long long* test_counter;  // nullable [2 kProfSlots]: tests, bytes
+  const float4* spans;       // nullable: span bounds of mesh 0 (single-mesh calls)
 };
 
 // Per-ray outputs of one crossing (tests and ray features only).
@@ -853,6 +1016,7 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
   __shared__ int32_t s_rng[4];
   __shared__ long long s_red[kCastWaves];
   __shared__ long long s_tests[kCastWaves];
+  __shared__ int32_t s_read[kCastWaves];  // list entries read per wave (profiling)
   __shared__ unsigned long long s_unit;
   __shared__ int32_t socc[OCC ? 512 : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -894,20 +1058,34 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
     constexpr int kSlice = kCastTris / kCastWaves;  // entries a wave culls at most
     int n_mine = 0;                                  // survivors of this wave (uniform in the wave)
     int ri0 = 0x7fffffff, ri1 = -1, rj0 = 0x7fffffff, rj1 = -1;
+    // spans of a whole-mesh item that the cast's kept half prism may reach (a
+    // wave's 64 entries lie in one span: the test is uniform in the wave)
+    uint64_t smask = ~0ull;
+    if (a.spans && ii.first < 0) {
+      const int64_t sp0 = (-1 - ii.first) / kSpanTris;
+      const int nsp = (ii.count + kSpanTris - 1) / kSpanTris;
+      const bool reach =
+          lane < nsp && span_may_cast(B, w, mirror, a.spans[2 * (sp0 + lane)], a.spans[2 * (sp0 + lane) + 1]);
+      smask = __ballot(reach);
+    }
+    int n_read = 0;
     {
       const int e0 = wave * 64 + lane;
       bool oka = false, okb = false;
       TriPk Ta{}, Tb{};
-      if (e0 < ii.count) Ta = item_tri_pk(a.la, M, B, ii, e0, oka);
-      if (e0 + kCastThreads < ii.count) Tb = item_tri_pk(a.la, M, B, ii, e0 + kCastThreads, okb);
+      if (e0 < ii.count && ((smask >> (e0 / kSpanTris)) & 1ull)) Ta = item_tri_pk(a.la, M, B, ii, e0, oka);
+      if (e0 + kCastThreads < ii.count && ((smask >> ((e0 + kCastThreads) / kSpanTris)) & 1ull))
+        Tb = item_tri_pk(a.la, M, B, ii, e0 + kCastThreads, okb);
       for (int e = e0; e - lane < ii.count; e += kCastThreads) {
         float P[3][3];
         unpack_tri(Ta, P);
         const bool ok = oka;
+        n_read += (e < ii.count && ((smask >> (e / kSpanTris)) & 1ull)) ? 1 : 0;
         Ta = Tb;
         oka = okb;
         okb = false;
-        if (e + 2 * kCastThreads < ii.count) Tb = item_tri_pk(a.la, M, B, ii, e + 2 * kCastThreads, okb);
+        const int en = e + 2 * kCastThreads;
+        if (en < ii.count && ((smask >> (en / kSpanTris)) & 1ull)) Tb = item_tri_pk(a.la, M, B, ii, en, okb);
         bool keep = false;
         if (ok) {
           const CastTri tr = cast_tri(P, w, f, mirror);
@@ -929,6 +1107,11 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
       }
     }
     if (lane == 0) s_wcnt[wave] = n_mine;
+    if (a.test_counter) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) n_read += __shfl_xor(n_read, off);
+      if (lane == 0) s_read[wave] = n_read;
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       ri0 = min(ri0, __shfl_xor(ri0, off));
@@ -1005,7 +1188,12 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
           int slot = kBigCap;
           if (cells > a.raster_cells) slot = atomicAdd(&s_nbig[par], 1);
           if (cells <= a.raster_cells) {
-            acc += raster_lane<STATS, OCC, int32_t>(a, r, i0, i1, j0, j1, ui0, uj0, uw, bw3, sray, socc);
+            // a record's crossings share one sign and are at most 2^22 each: an
+            // int32 sum holds fewer than 512 of them
+            if (cells < 512)
+              acc += raster_lane<STATS, OCC, int32_t>(a, r, i0, i1, j0, j1, ui0, uj0, uw, bw3, sray, socc);
+            else
+              acc += raster_lane<STATS, OCC, long long>(a, r, i0, i1, j0, j1, ui0, uj0, uw, bw3, sray, socc);
             tests += cells;
           } else if (slot < kBigCap) {
             store_big(sbig[slot], r, i0, i1, j0, j1);
@@ -1045,9 +1233,11 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
       }
       if (sum) atomicAdd(&a.acc[bw3], (unsigned long long)sum);
       if (a.test_counter) {
+        long long n_read_all = 0;
+        for (int v = 0; v < kCastWaves; ++v) n_read_all += s_read[v];
         const int slot = (int)(u & (kProfSlots - 1));
         atomicAdd(&a.test_counter[slot], (unsigned long long)nt);
-        atomicAdd(&a.test_counter[kProfSlots + slot], (unsigned long long)(48ll * ii.count));
+        atomicAdd(&a.test_counter[kProfSlots + slot], (unsigned long long)(48ll * n_read_all));
       }
     }
     if (OCC && n_surv > 0) {
@@ -1170,12 +1360,12 @@ int pinned_totals(int64_t** out) {
 }
 
 // Cells above which a record is tested wave-wide: kRasterCells, or
-// OBBV_RASTER_CELLS (0..256) to compare thresholds on a device (same bits).
+// OBBV_RASTER_CELLS (0..16384) to compare thresholds on a device (same bits).
 int raster_cells_choice() {
   const char* e = getenv("OBBV_RASTER_CELLS");
   if (e && *e) {
     const int c = atoi(e);
-    if (c >= 0 && c <= 256) return c;
+    if (c >= 0 && c <= kBlockRaysMax) return c;
   }
   return kRasterCells;
 }
@@ -1190,6 +1380,18 @@ int block_rays_choice(int requested) {
   }
   return kBlockRaysDefault;
 }
+
+// Span culling of whole-mesh casts: on unless OBBV_SPAN_CULL=0 (same bits either way).
+bool span_cull_choice() {
+  const char* e = getenv("OBBV_SPAN_CULL");
+  return !(e && *e && atoi(e) == 0);
+}
+
+int64_t n_spans_of(int64_t nt) { return (nt + kSpanTris - 1) / kSpanTris; }
+int64_t n_runs_of(int64_t nt) { return (nt + kCastTris - 1) / kCastTris; }
+// span bounds table of a single-mesh call: 2 float4 per span and per run
+bool spans_apply(int n_meshes, int64_t nt0) { return n_meshes == 1 && nt0 > kCastTris; }
+size_t span_table_bytes(int64_t nt) { return 32 * (size_t)(n_spans_of(nt) + n_runs_of(nt)); }
 
 struct BlockGeom {
   int BC, BR, nbc, nblk;
@@ -1250,10 +1452,27 @@ CallSizes call_sizes(int n_meshes, int n_boxes, int max_nt, int n_frames, int nt
   take(4 * 3 * (size_t)n_frames);            // (frame, axis) list counts
   take(8 * (size_t)(3 * n_frames + 1));      // (frame, axis) list offsets
   take(exclusive_scan_scratch_bytes(3 * n_frames));
+  if (spans_apply(n_meshes, nt0)) take(span_table_bytes(nt0));  // span bounds
   c.meta = off;
   c.items = align_up(sizeof(ItemInfo) * (size_t)c.item_cap) + 2 * align_up(4 * (size_t)fitems);
   return c;
 }
+
+// Span bounds of a mesh for repeated single-mesh calls (see k_span_bounds):
+// bytes of the table (0 when the mesh has one cast item or less) and its launch.
+size_t span_table_size(int64_t nt) { return spans_apply(1, nt) ? span_table_bytes(nt) : 0; }
+int span_table(const obbv_mesh* m, float4* table, hipStream_t s) {
+  const int64_t nt = m->n_triangles;
+  if (!spans_apply(1, nt)) return OBBV_OK;
+  uint32_t* status = nullptr;
+  OBBV_RET(status_word(&status));
+  const MeshDev M{m->vertices, m->triangles, m->n_vertices, m->n_triangles};
+  hipLaunchKernelGGL(k_span_bounds, dim3((unsigned)n_runs_of(nt)), dim3(256), 0, s, M, table, table + 2 * n_spans_of(nt),
+                     status);
+  OBBV_HIP(hipGetLastError());
+  return OBBV_OK;
+}
+const float4* span_runs_of(const float4* table, int64_t nt) { return table + 2 * n_spans_of(nt); }
 
 int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                      const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
@@ -1336,6 +1555,8 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   int64_t* d_foff = (int64_t*)take(8 * (size_t)(3 * n_frames + 1));
   void* d_scan = take(exclusive_scan_scratch_bytes(3 * n_frames));
   const size_t scan_bytes = exclusive_scan_scratch_bytes(3 * n_frames);
+  const int64_t nt0 = meshes[0].n_triangles;
+  float4* d_spans = spans_apply(n_meshes, nt0) ? (float4*)take(span_table_bytes(nt0)) : nullptr;
 
   char* items = nullptr;
   if (planned) {
@@ -1364,6 +1585,22 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     OBBV_HIP(hipGetLastError());
   }
 
+  // span bounds: given by the caller (same mesh for every call), or from the mesh
+  const float4* spans = nullptr;
+  const float4* runs = nullptr;
+  if (spans_apply(n_meshes, nt0) && span_cull_choice()) {
+    if (ex && ex->spans) {
+      spans = ex->spans;
+      runs = ex->span_runs;
+    } else {
+      hipLaunchKernelGGL(k_span_bounds, dim3((unsigned)n_runs_of(nt0)), dim3(256), 0, s, mh[0], d_spans,
+                         d_spans + 2 * n_spans_of(nt0), status);
+      OBBV_HIP(hipGetLastError());
+      spans = d_spans;
+      runs = d_spans + 2 * n_spans_of(nt0);
+    }
+  }
+
   float4* d_listP = nullptr;
   if (sf) {  // per (frame, axis): the triangles of the frame's kept half prism
     const int nt = meshes[0].n_triangles;
@@ -1371,7 +1608,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     const unsigned fgrid = (unsigned)std::min<int64_t>((int64_t)n_frames * nch, 256 * 16);
     hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], centre,
                        mask, nch, d_ficnt, (const int32_t*)nullptr, (const int64_t*)nullptr, (float4*)nullptr,
-                       status);
+                       status, spans);
     OBBV_HIP(hipGetLastError());
     const int ngroups = 3 * n_frames;
     if ((int64_t)ngroups * nch <= ((int64_t)1 << 20)) {  // one block: item and list offsets
@@ -1396,13 +1633,13 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     OBBV_RET(pool_get(pool_base + kPoolLists, (size_t)std::max<int64_t>(bound, 1) * 48, &lv));
     d_listP = (float4*)lv;
     hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], centre,
-                       mask, nch, d_ficnt, (const int32_t*)d_fioff, (const int64_t*)d_foff, d_listP, status);
+                       mask, nch, d_ficnt, (const int32_t*)d_fioff, (const int64_t*)d_foff, d_listP, status, spans);
     OBBV_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_box_chunks, dim3(1), dim3(kScanBlockThreads), 0, s, box_mesh, d_meshes, mh[0], n_meshes,
                      n_boxes, mask, boxes, sf ? sf->frames : nullptr, sf ? sf->box_frame : nullptr, n_frames,
                      (const int64_t*)d_foff, d_choff, status, box_key, R, params->seed, d_rframe, d_items,
-                     cs.item_cap, d_acc, d_ctl);
+                     cs.item_cap, d_acc, d_ctl, runs, centre);
   OBBV_HIP(hipGetLastError());
 
   ListArgs la;
@@ -1432,6 +1669,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   ca.ray_hits = out_ray_hits;
   ca.occ = out_occ;
   ca.test_counter = nullptr;
+  ca.spans = spans;
   const bool stats = out_ray_q || out_ray_hits;
   if (stats) {
     const size_t per = (size_t)n_boxes * 3 * R * R * 4;

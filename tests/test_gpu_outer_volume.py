@@ -288,19 +288,24 @@ def test_grouped_candidates_equal_plain_calls(api):
 def test_lane_and_wave_paths_agree(api, monkeypatch):
     """A kept triangle is tested by its own lane over the cells it covers, or by
     the whole wave (one cell per lane) above a cell-count threshold; with the
-    threshold at 0 (every triangle wave-wide), 64 (the default) and 256 (almost
-    all per lane) every box and every ray get the same bits."""
+    threshold at 0 (every triangle wave-wide), 64, 512 (the default) and 16384
+    (every triangle per lane, those of 512 cells or more with 64-bit sums) every
+    box and every ray get the same bits.  The coarse mesh and small boxes give
+    triangles covering hundreds of cells."""
     V, F = synth.noisy_torus(nu=96, nv=48)
     c, a, h = synth.random_boxes(24, seed=71, center_range=1.0, half_range=(0.1, 0.7))
-    Vt, Ft, B = _dev(api, V, F, c, a, h)
-    out = {}
-    for cells in ("0", "64", "256"):
-        monkeypatch.setenv("OBBV_RASTER_CELLS", cells)
-        r = api.outer_volume_ex(Vt, Ft, B, 48, seed=5, rays=True)
-        out[cells] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
-    for key in ("0", "256"):
-        for k in ("obv", "ray_q", "ray_hits"):
-            assert np.array_equal(out[key][k], out["64"][k]), (key, k)
+    Vc, Fc = synth.noisy_torus(nu=24, nv=12)
+    c2, a2, h2 = synth.random_boxes(16, seed=72, center_range=1.0, half_range=(0.05, 0.25))
+    for (VV, FF, cc, aa, hh, R) in ((V, F, c, a, h, 48), (Vc, Fc, c2, a2, h2, 96)):
+        Vt, Ft, B = _dev(api, VV, FF, cc, aa, hh)
+        out = {}
+        for cells in ("0", "64", "512", "16384"):
+            monkeypatch.setenv("OBBV_RASTER_CELLS", cells)
+            r = api.outer_volume_ex(Vt, Ft, B, R, seed=5, rays=True)
+            out[cells] = {k: r[k].cpu().numpy() for k in ("obv", "ray_q", "ray_hits")}
+        for key in ("0", "64", "16384"):
+            for k in ("obv", "ray_q", "ray_hits"):
+                assert np.array_equal(out[key][k], out["512"][k]), (R, key, k)
 
 
 def test_jitter_table_and_computed_draws_agree(api):
@@ -372,3 +377,52 @@ def test_validate_mesh(api):
         assert abs(vol - ref) <= 1e-12 * abs(ref), (vol, ref)
         _, _, vol2 = api.validate_mesh(Vt, torch.from_numpy(F[g.permutation(len(F))].copy()).cuda())
         assert vol2 == vol
+
+
+def test_span_culling_gives_the_same_bits(api, monkeypatch):
+    """Whole-mesh casts skip the runs and spans of 256 triangles whose bounds
+    miss the cast's kept half prism.  The skipped triangles are ones the cull
+    would drop, so the results are bit-identical with the culling off
+    (OBBV_SPAN_CULL=0): on a mesh in surface order (tight spans) and on the same
+    mesh with its triangles shuffled (loose spans), for small boxes near the
+    surface and large random ones, in one call and through a plan."""
+    import torch
+    V, F = synth.noisy_torus()
+    g = np.random.default_rng(5)
+    F_shuffled = F[g.permutation(len(F))].copy()
+    c, a, h = synth.random_boxes(48, seed=8, center_range=1.2, half_range=(0.02, 0.12))
+    c2, a2, h2 = synth.random_boxes(16, seed=9, center_range=1.0, half_range=(0.2, 0.9))
+    B = torch.from_numpy(np.concatenate([synth.boxes_to_array(c, a, h), synth.boxes_to_array(c2, a2, h2)])).cuda()
+    Vt = torch.from_numpy(V).cuda()
+    for FF in (F, F_shuffled):
+        Ft = torch.from_numpy(FF).cuda()
+        out = {}
+        for flag in ("1", "0"):
+            monkeypatch.setenv("OBBV_SPAN_CULL", flag)
+            api.status()
+            out[flag] = api.outer_volume(Vt, Ft, B, 24, seed=4).cpu().numpy()
+            assert api.status() == 0
+        assert np.array_equal(out["1"], out["0"])
+    monkeypatch.setenv("OBBV_SPAN_CULL", "1")
+    plan = api.OuterVolumePlan(B, 24, seed=4, meshes=[(Vt, torch.from_numpy(F).cuda())], block_rays=2048)
+    got = plan.launch().clone().cpu().numpy()
+    ref = api.outer_volume(Vt, torch.from_numpy(F).cuda(), B, 24, seed=4, block_rays=2048).cpu().numpy()
+    plan.close()
+    assert np.array_equal(got, ref)
+
+
+def test_span_culling_far_from_the_origin(api, monkeypatch):
+    """The same comparison with the mesh and boxes moved 3,000 units from the
+    origin (float32 coordinates then carry about 2.4e-4 of absolute rounding):
+    the span test's margins stay relative to the local magnitudes."""
+    import torch
+    V, F = synth.noisy_torus(nu=128, nv=64)
+    shift = np.array([3000.0, -2000.0, 1000.0], np.float32)
+    c, a, h = synth.random_boxes(32, seed=18, center_range=1.2, half_range=(0.02, 0.3))
+    B = torch.from_numpy(synth.boxes_to_array((c + shift).astype(np.float32), a, h)).cuda()
+    Vt, Ft = torch.from_numpy((V + shift).astype(np.float32)).cuda(), torch.from_numpy(F).cuda()
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("OBBV_SPAN_CULL", flag)
+        out[flag] = api.outer_volume(Vt, Ft, B, 20, seed=6).cpu().numpy()
+    assert np.array_equal(out["1"], out["0"])
