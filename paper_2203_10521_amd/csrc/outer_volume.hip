@@ -51,7 +51,6 @@ constexpr int kCullThreads = 256;
 constexpr int kCastThreads = 768;    // 12 waves: three per SIMD, one workgroup per CU
 constexpr int kCastWaves = kCastThreads / 64;
 constexpr int kCastTris = 4608;      // triangle-list entries per cast item (6 cull steps; 384 per wave)
-constexpr int kBigCap = 64;          // records queued for the wave-wide test per round
 constexpr int kRasterCells = 512;    // records covering more cells take the wave-wide test
 constexpr int kBlockRaysDefault = 16384;  // rays of one LDS ray block (float2 each): a whole
                                           // face up to R = 128
@@ -856,43 +855,34 @@ __device__ inline bool rec_hit(const Rec& r, float u, float v, float& y) {
           (int)(__float_as_int(e2) >= r.t2)) != 0;
 }
 
-// A record queued for the wave-wide test: 5 float4 in LDS (planes, clamp, sign,
-// tie thresholds, the cell range inside the unit's ray block).
-__device__ inline void store_big(float4* q, const Rec& r, int i0, int i1, int j0, int j1) {
-  q[0] = make_float4(r.A0, r.B0, r.C0, r.A1);
-  q[1] = make_float4(r.B1, r.C1, r.A2, r.B2);
-  q[2] = make_float4(r.C2, r.D, r.E, r.F);
-  q[3] = make_float4(r.lo, r.hi, r.s, __int_as_float(r.t0 | (r.t1 << 1) | (r.t2 << 2)));
-  q[4] = make_float4(__int_as_float(i0), __int_as_float(i1), __int_as_float(j0), __int_as_float(j1));
-}
-
-__device__ inline Rec load_big(const float4* q, int& i0, int& i1, int& j0, int& j1) {
-  const float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
-  Rec r;
-  r.A0 = a.x;
-  r.B0 = a.y;
-  r.C0 = a.z;
-  r.A1 = a.w;
-  r.B1 = b.x;
-  r.C1 = b.y;
-  r.A2 = b.z;
-  r.B2 = b.w;
-  r.C2 = c.x;
-  r.D = c.y;
-  r.E = c.z;
-  r.F = c.w;
-  r.lo = d.x;
-  r.hi = d.y;
-  r.s = d.z;
-  const int t = __float_as_int(d.w);
-  r.t0 = t & 1;
-  r.t1 = (t >> 1) & 1;
-  r.t2 = (t >> 2) & 1;
-  i0 = __float_as_int(e.x);
-  i1 = __float_as_int(e.y);
-  j0 = __float_as_int(e.z);
-  j1 = __float_as_int(e.w);
-  return r;
+// Lane src's record and cell range, in every lane of the wave (for the
+// wave-wide test).
+__device__ inline Rec shfl_rec(const Rec& r, int i0, int i1, int j0, int j1, int src, int& o0, int& o1, int& p0,
+                               int& p1) {
+  Rec o;
+  o.A0 = __shfl(r.A0, src);
+  o.B0 = __shfl(r.B0, src);
+  o.C0 = __shfl(r.C0, src);
+  o.A1 = __shfl(r.A1, src);
+  o.B1 = __shfl(r.B1, src);
+  o.C1 = __shfl(r.C1, src);
+  o.A2 = __shfl(r.A2, src);
+  o.B2 = __shfl(r.B2, src);
+  o.C2 = __shfl(r.C2, src);
+  o.D = __shfl(r.D, src);
+  o.E = __shfl(r.E, src);
+  o.F = __shfl(r.F, src);
+  o.lo = __shfl(r.lo, src);
+  o.hi = __shfl(r.hi, src);
+  o.s = __shfl(r.s, src);
+  o.t0 = __shfl(r.t0, src);
+  o.t1 = __shfl(r.t1, src);
+  o.t2 = __shfl(r.t2, src);
+  o0 = __shfl(i0, src);
+  o1 = __shfl(i1, src);
+  p0 = __shfl(j0, src);
+  p1 = __shfl(j1, src);
+  return o;
 }
 
 struct CastArgs {
@@ -1003,15 +993,15 @@ __device__ inline int32_t raster_wave(const CastArgs& a, const Rec& r, int i0, i
 //      survivors are compacted into an LDS list (wave ballots + a workgroup
 //      prefix) and their cell ranges merged into one bounding cell range;
 //   B. the rays of that range only are generated into LDS;
-//   C. rounds of one survivor per thread: its planes in registers, then its
-//      covered cells per lane (or, for records covering many cells, the whole
-//      wave from an LDS queue, one cell per lane).
+//   C. each wave draws chunks of 64 survivors from a shared cursor: one
+//      survivor per lane, its planes in registers, its covered cells per lane
+//      (or, for records covering many cells, by the whole wave, one cell per
+//      lane), with no barrier until the unit's sums.
 template <bool STATS, bool OCC, bool TAB>
 __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
   extern __shared__ float2 sray[];  // rays of the survivors' cell range inside the unit's block (u, v)
   __shared__ int32_t sidx[kCastTris];
-  __shared__ float4 sbig[kBigCap][5];
-  __shared__ int32_t s_nbig[2];
+  __shared__ int32_t s_cursor;  // next survivor of the test phase
   __shared__ int32_t s_wcnt[kCastWaves];
   __shared__ int32_t s_rng[4];
   __shared__ long long s_red[kCastWaves];
@@ -1023,14 +1013,10 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
   const int64_t n_items = a.chunk_off[3 * a.n_boxes];
   const int per_item = a.nblk;
   const unsigned long long n_units = (unsigned long long)n_items * (unsigned long long)per_item;
-  if (tid < 2) s_nbig[tid] = 0;
-  // s_nbig[par] is zero at the start of every round: a round takes its counter,
-  // clears the other one (last read before the round's first barrier) and hands
-  // it on; par carries over from unit to unit
-  int par = 0;
   for (;;) {
     if (tid == 0) {
       s_unit = atomicAdd(a.queue, 1ull);
+      s_cursor = 0;
       s_rng[0] = 0x7fffffff;
       s_rng[1] = -1;
       s_rng[2] = 0x7fffffff;
@@ -1169,50 +1155,51 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
       if (TAB && a.test_counter && tid == 0)
         atomicAdd(&a.test_counter[kProfSlots + (int)(u & (kProfSlots - 1))], (unsigned long long)(8ll * nray));
       __syncthreads();
-      // C. rounds of one survivor per thread
-      for (int r0 = 0; r0 < n_surv; r0 += kCastThreads) {
-        if (r0 + tid < n_surv) {
-          int x = r0 + tid, v = 0;  // survivor r0 + tid: entry x of the slice of wave v
+      // C. each wave takes chunks of 64 survivors from a cursor: a lane tests its
+      // survivor over the cells it covers; survivors covering more than
+      // raster_cells cells are then tested by the whole wave, one cell per lane
+      // (the record broadcast from its lane).  Waves run independently until
+      // the sums.
+      for (;;) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_cursor, 64);
+        base = __shfl(base, 0);
+        if (base >= n_surv) break;
+        const int k = base + lane;
+        const bool have = k < n_surv;
+        Rec r{};
+        int i0 = 0, i1 = -1, j0 = 0, j1 = -1, cells = 0;
+        if (have) {
+          int x = k, v = 0;  // survivor k: entry x of the slice of wave v
           for (int c = s_wcnt[0]; x >= c && v < kCastWaves - 1; c = s_wcnt[++v]) x -= c;
           float P[3][3];
           item_tri(a.la, M, B, ii, sidx[v * kSlice + x], P);  // succeeded in the cull
           const CastTri tr = cast_tri(P, w, f, mirror);
-          int i0, i1, j0, j1;
           cell_range(tr, f, a.R, i0, i1, j0, j1);
           i0 = max(i0, ci0);
           i1 = min(i1, ci1);
           j0 = max(j0, cj0);
           j1 = min(j1, cj1);
-          const Rec r = make_rec(tr, mirror, f.hw);
-          const int cells = (i1 - i0 + 1) * (j1 - j0 + 1);
-          int slot = kBigCap;
-          if (cells > a.raster_cells) slot = atomicAdd(&s_nbig[par], 1);
-          if (cells <= a.raster_cells) {
-            // a record's crossings share one sign and are at most 2^22 each: an
-            // int32 sum holds fewer than 512 of them
-            if (cells < 512)
-              acc += raster_lane<STATS, OCC, int32_t>(a, r, i0, i1, j0, j1, ui0, uj0, uw, bw3, sray, socc);
-            else
-              acc += raster_lane<STATS, OCC, long long>(a, r, i0, i1, j0, j1, ui0, uj0, uw, bw3, sray, socc);
-            tests += cells;
-          } else if (slot < kBigCap) {
-            store_big(sbig[slot], r, i0, i1, j0, j1);
-          } else {  // the wave-wide queue is full this round: the lane tests it alone
+          r = make_rec(tr, mirror, f.hw);
+          cells = (i1 - i0 + 1) * (j1 - j0 + 1);
+        }
+        const bool wide = have && cells > a.raster_cells;
+        if (have && !wide) {
+          // a record's crossings share one sign and are at most 2^22 each: an
+          // int32 sum holds fewer than 512 of them
+          if (cells < 512)
+            acc += raster_lane<STATS, OCC, int32_t>(a, r, i0, i1, j0, j1, ui0, uj0, uw, bw3, sray, socc);
+          else
             acc += raster_lane<STATS, OCC, long long>(a, r, i0, i1, j0, j1, ui0, uj0, uw, bw3, sray, socc);
-            tests += cells;
-          }
+          tests += cells;
         }
-        __syncthreads();
-        const int nb = min(s_nbig[par], kBigCap);
-        if (tid == 0) s_nbig[par ^ 1] = 0;
-        for (int q = wave; q < nb; q += kCastWaves) {
-          int i0, i1, j0, j1;
-          const Rec r = load_big(sbig[q], i0, i1, j0, j1);
-          acc += raster_wave<STATS, OCC>(a, r, i0, i1, j0, j1, ui0, uj0, uw, bw3, sray, socc, lane);
-          tests += lane == 0 ? (long long)(i1 - i0 + 1) * (j1 - j0 + 1) : 0ll;
+        for (uint64_t wm = __ballot(wide); wm; wm &= wm - 1) {
+          const int src = __ffsll((unsigned long long)wm) - 1;
+          int wi0, wi1, wj0, wj1;
+          const Rec rw = shfl_rec(r, i0, i1, j0, j1, src, wi0, wi1, wj0, wj1);
+          acc += raster_wave<STATS, OCC>(a, rw, wi0, wi1, wj0, wj1, ui0, uj0, uw, bw3, sray, socc, lane);
+          tests += lane == 0 ? (long long)(wi1 - wi0 + 1) * (wj1 - wj0 + 1) : 0ll;
         }
-        __syncthreads();
-        par ^= 1;
       }
     }
 #pragma unroll
@@ -1683,7 +1670,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   }
   // persistent workgroups: as many as stay resident (LDS bound) across the 256 CUs
   // one 12-wave workgroup per CU (three waves per SIMD); more when the ray block is small
-  const size_t lds_static = sizeof(int32_t) * kCastTris + sizeof(float4) * 5 * kBigCap + 1024;
+  const size_t lds_static = sizeof(int32_t) * kCastTris + 1024;
   const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(1, (160 * 1024) / (bg.lds + lds_static)));
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cs.units, 256 * per_cu));
   if (out_occ)
