@@ -51,6 +51,7 @@ constexpr int kCullThreads = 256;
 constexpr int kCastThreads = 768;    // 12 waves: three per SIMD, one workgroup per CU
 constexpr int kCastWaves = kCastThreads / 64;
 constexpr int kCastTris = 4608;      // triangle-list entries per cast item (6 cull steps; 384 per wave)
+constexpr int kRayBatch = 8;        // rays a thread generates at once in the ray phase
 constexpr int kRasterCells = 512;    // records covering more cells take the wave-wide test
 constexpr int kBlockRaysDefault = 16384;  // rays of one LDS ray block (float2 each): a whole
                                           // face up to R = 128
@@ -1122,12 +1123,12 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
       // (-hu + (i + xi) du, -hv + (j + eta) dv)
       const int ui0 = s_rng[0], uj0 = s_rng[2];
       const int uw = s_rng[1] - ui0 + 1, nray = uw * (s_rng[3] - uj0 + 1);
-      for (int k0 = tid; k0 < nray; k0 += 4 * kCastThreads) {
-        // four rays per thread: their jitter is requested (or hashed) before any is used
-        double xi[4], eta[4];
-        int ci[4], cj[4];
+      for (int k0 = tid; k0 < nray; k0 += kRayBatch * kCastThreads) {
+        // kRayBatch rays per thread: their jitter is requested (or hashed) before any is used
+        double xi[kRayBatch], eta[kRayBatch];
+        int ci[kRayBatch], cj[kRayBatch];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kRayBatch; ++q) {
           const int k = min(k0 + q * kCastThreads, nray - 1);
           cj[q] = k / uw;
           ci[q] = ui0 + k - cj[q] * uw;
@@ -1143,7 +1144,7 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
           }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kRayBatch; ++q) {
           const int k = k0 + q * kCastThreads;
           if (k < nray)
             sray[k] = make_float2((float)__dadd_rn(-rf.hu, __dmul_rn(__dadd_rn((double)ci[q], xi[q]), rf.du)),
@@ -1160,20 +1161,31 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
       // raster_cells cells are then tested by the whole wave, one cell per lane
       // (the record broadcast from its lane).  Waves run independently until
       // the sums.
-      for (;;) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&s_cursor, 64);
-        base = __shfl(base, 0);
-        if (base >= n_surv) break;
+      // The next chunk's triangles are requested before the current chunk is
+      // tested.
+      auto fetch = [&](int k, TriPk& t) {
+        int x = k, v = 0;  // survivor k: entry x of the slice of wave v
+        for (int c = s_wcnt[0]; x >= c && v < kCastWaves - 1; c = s_wcnt[++v]) x -= c;
+        bool ok;
+        t = item_tri_pk(a.la, M, B, ii, sidx[v * kSlice + x], ok);  // succeeded in the cull
+      };
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&s_cursor, 64);
+      base = __shfl(base, 0);
+      TriPk Tn{};
+      if (base + lane < n_surv) fetch(base + lane, Tn);
+      while (base < n_surv) {
         const int k = base + lane;
         const bool have = k < n_surv;
+        const TriPk Tc = Tn;
+        if (lane == 0) base = atomicAdd(&s_cursor, 64);
+        base = __shfl(base, 0);
+        if (base + lane < n_surv) fetch(base + lane, Tn);
         Rec r{};
         int i0 = 0, i1 = -1, j0 = 0, j1 = -1, cells = 0;
         if (have) {
-          int x = k, v = 0;  // survivor k: entry x of the slice of wave v
-          for (int c = s_wcnt[0]; x >= c && v < kCastWaves - 1; c = s_wcnt[++v]) x -= c;
           float P[3][3];
-          item_tri(a.la, M, B, ii, sidx[v * kSlice + x], P);  // succeeded in the cull
+          unpack_tri(Tc, P);
           const CastTri tr = cast_tri(P, w, f, mirror);
           cell_range(tr, f, a.R, i0, i1, j0, j1);
           i0 = max(i0, ci0);
