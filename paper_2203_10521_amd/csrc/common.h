@@ -51,7 +51,8 @@ enum PoolSlot {
   kPoolItems = 5,  // cast items
   kPoolRank = 6,
   kPoolMesh = 7,   // mesh validation: edge table and counters
-  kPoolCount = 8
+  kPoolFrameCnt = 8,  // (frame, axis) list counters of one-pass grouped calls (zero between calls)
+  kPoolCount = 9
 };
 // Two sets of the slots: calls that may run at the same time on different
 // streams take their scratch from different sets (slot + set * kPoolCount).

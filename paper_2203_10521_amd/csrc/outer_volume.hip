@@ -558,6 +558,45 @@ __device__ inline bool kept(const CastTri& tr, const CastFrame& f) {
 // grouped per (frame, axis).  With item_off NULL the pass writes each item's
 // count of such triangles; otherwise it writes their frame-local coordinates at
 // list_off[frame * 3 + axis] + item_off[item] + rank (in triangle order).
+// The triangles of (frame fr, 256-triangle chunk ch) kept along each axis:
+// mk[w] is the wave's ballot, wc[w][wave] its count; P the thread's triangle in
+// frame-local coordinates.
+__device__ inline void frame_keep(const obbv_box* __restrict__ frames, int fr, int ch, const MeshDev& M,
+                                  const float4& cm, uint32_t axis_mask, const float4* __restrict__ spans,
+                                  uint32_t* status, float P[3][3], uint64_t mk[3], int32_t (*wc)[kCullWaves]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = ch * kCullThreads + threadIdx.x;
+  const BoxRegs B = load_box(frames, fr);
+  // the axes whose kept half prism the chunk (one span) may reach
+  uint32_t reach = axis_mask;
+  if (spans) {
+    const float4 lo = spans[2 * ch], hi = spans[2 * ch + 1];
+    for (int w = 0; w < 3; ++w)
+      if (((reach >> w) & 1u) && !span_may_cast(B, w, cast_mirror(B, w, cm), lo, hi)) reach &= ~(1u << w);
+  }
+  const bool ok = reach != 0u && box_state(B) == 0 && t < M.nt && load_tri_local(M, t, B, P, status);
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    bool keep = false;
+    if (ok && ((reach >> w) & 1u)) {
+      const CastFrame f = cast_bounds(B, w);
+      keep = kept(cast_tri(P, w, f, cast_mirror(B, w, cm)), f);
+    }
+    mk[w] = __ballot(keep);
+    if (lane == 0) wc[w][wave] = (int)__popcll(mk[w]);
+  }
+}
+
+__device__ inline void store_tri(float4* q, const float P[3][3]) {
+  q[0] = make_float4(P[0][0], P[0][1], P[0][2], P[1][0]);
+  q[1] = make_float4(P[1][1], P[1][2], P[2][0], P[2][1]);
+  q[2] = make_float4(P[2][2], 0.f, 0.f, 0.f);
+}
+
+// Two passes (lists sized exactly): with item_off NULL the pass writes each
+// item's count of kept triangles; otherwise it writes their frame-local
+// coordinates at list_off[frame * 3 + axis] + item_off[item] + rank (in
+// triangle order).
 __global__ void __launch_bounds__(kCullThreads)
 k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, const float4* __restrict__ centre,
              uint32_t axis_mask, int nch, int32_t* __restrict__ item_cnt, const int32_t* __restrict__ item_off,
@@ -570,28 +609,9 @@ k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, const
   for (int64_t fc = blockIdx.x; fc < total; fc += gridDim.x) {
     const int fr = (int)(fc / nch);
     const int ch = (int)(fc - (int64_t)fr * nch);
-    const int t = ch * kCullThreads + threadIdx.x;
-    const BoxRegs B = load_box(frames, fr);
-    // the axes whose kept half prism the chunk (one span) may reach
-    uint32_t reach = axis_mask;
-    if (spans) {
-      const float4 lo = spans[2 * ch], hi = spans[2 * ch + 1];
-      for (int w = 0; w < 3; ++w)
-        if (((reach >> w) & 1u) && !span_may_cast(B, w, cast_mirror(B, w, cm), lo, hi)) reach &= ~(1u << w);
-    }
     float P[3][3];
-    const bool ok = reach != 0u && box_state(B) == 0 && t < M.nt && load_tri_local(M, t, B, P, status);
     uint64_t mk[3];
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      bool keep = false;
-      if (ok && ((reach >> w) & 1u)) {
-        const CastFrame f = cast_bounds(B, w);
-        keep = kept(cast_tri(P, w, f, cast_mirror(B, w, cm)), f);
-      }
-      mk[w] = __ballot(keep);
-      if (lane == 0) wc[w][wave] = (int)__popcll(mk[w]);
-    }
+    frame_keep(frames, fr, ch, M, cm, axis_mask, spans, status, P, mk, wc);
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
@@ -605,14 +625,52 @@ k_frame_cull(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, const
       } else if ((mk[w] >> lane) & 1ull) {
         int pos = item_off[item] + (int)__popcll(mk[w] & ((1ull << lane) - 1ull));
         for (int v = 0; v < wave; ++v) pos += wc[w][v];
-        if (pos < item_off[item] + item_cnt[item]) {
-          float4* q = list_P + 3 * (list_off[fr * 3 + w] + pos);
-          q[0] = make_float4(P[0][0], P[0][1], P[0][2], P[1][0]);
-          q[1] = make_float4(P[1][1], P[1][2], P[2][0], P[2][1]);
-          q[2] = make_float4(P[2][2], 0.f, 0.f, 0.f);
-        } else {  // count and write passes disagree: never expected
+        if (pos < item_off[item] + item_cnt[item])
+          store_tri(list_P + 3 * (list_off[fr * 3 + w] + pos), P);
+        else  // count and write passes disagree: never expected
           atomicOr(status, OBBV_STATUS_BAD_INDEX);
-        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One pass: the kept triangles of every axis are appended to list (frame,
+// axis), a segment of seg entries from (frame * 3 + axis) * seg, at positions
+// taken from the list's counter list_cnt (zero before the pass).  Entries of a
+// list follow the blocks' arrival order; the cast's sums are exact integers, so
+// no result depends on it.
+__global__ void __launch_bounds__(kCullThreads)
+k_frame_list(const obbv_box* __restrict__ frames, int n_frames, MeshDev M, const float4* __restrict__ centre,
+             uint32_t axis_mask, int nch, int64_t seg, int32_t* __restrict__ list_cnt, float4* __restrict__ list_P,
+             uint32_t* status, const float4* __restrict__ spans) {
+  __shared__ int32_t wc[3][kCullWaves];
+  __shared__ int32_t base[3];
+  const int64_t total = (int64_t)n_frames * nch;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float4 cm = centre[0];
+  for (int64_t fc = blockIdx.x; fc < total; fc += gridDim.x) {
+    const int fr = (int)(fc / nch);
+    const int ch = (int)(fc - (int64_t)fr * nch);
+    float P[3][3];
+    uint64_t mk[3];
+    frame_keep(frames, fr, ch, M, cm, axis_mask, spans, status, P, mk, wc);
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      int c = 0;
+      for (int v = 0; v < kCullWaves; ++v) c += wc[threadIdx.x][v];
+      base[threadIdx.x] = c ? atomicAdd(&list_cnt[fr * 3 + threadIdx.x], c) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      if ((mk[w] >> lane) & 1ull) {
+        int pos = base[w] + (int)__popcll(mk[w] & ((1ull << lane) - 1ull));
+        for (int v = 0; v < wave; ++v) pos += wc[w][v];
+        if (pos < seg)
+          store_tri(list_P + 3 * (((int64_t)fr * 3 + w) * seg + pos), P);
+        else  // a list holds each triangle once at most: never expected
+          atomicOr(status, OBBV_STATUS_BAD_INDEX);
       }
     }
     __syncthreads();
@@ -671,12 +729,14 @@ __global__ void k_frame_scan(const int32_t* __restrict__ item_cnt, int n_frames,
 // that axis when the box may use its frame, else the whole mesh; boxes that
 // cannot be cast get none --, their offsets chunk_off[0..3 n_boxes], the ray
 // grid of every cast, and the per-call counters that must start at zero
-// (per-(box, axis) sums, unit queue, finished blocks).
+// (per-(box, axis) sums, unit queue, finished blocks; the one-pass frame list
+// counters once read).
 __global__ void __launch_bounds__(kScanBlockThreads)
 k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ meshes, MeshDev mesh0, int n_meshes,
              int n_boxes, uint32_t axis_mask, const obbv_box* __restrict__ boxes,
              const obbv_box* __restrict__ frames, const int32_t* __restrict__ box_frame, int n_frames,
-             const int64_t* __restrict__ list_off, int64_t* __restrict__ chunk_off, uint32_t* status,
+             const int64_t* __restrict__ list_off, int32_t* __restrict__ list_cnt, int64_t list_seg,
+             int64_t* __restrict__ chunk_off, uint32_t* status,
              const uint32_t* __restrict__ box_key, int R, uint64_t seed, RayFrame* __restrict__ rframe,
              ItemInfo* __restrict__ items, int64_t item_cap, unsigned long long* __restrict__ acc,
              unsigned long long* __restrict__ ctl, const float4* __restrict__ runs,
@@ -707,8 +767,13 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
         if (frames) {
           const int f = box_frame[b];
           if (f >= 0 && f < n_frames && inside_frame(boxes[b], frames[f])) {
-            first = list_off[f * 3 + w];
-            n = list_off[f * 3 + w + 1] - first;
+            if (list_cnt) {
+              first = ((int64_t)f * 3 + w) * list_seg;
+              n = list_cnt[f * 3 + w];
+            } else {
+              first = list_off[f * 3 + w];
+              n = list_off[f * 3 + w + 1] - first;
+            }
             list = true;
           }
         }
@@ -764,6 +829,10 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
   if (threadIdx.x == 0) {
     chunk_off[npairs] = base < item_cap ? base : item_cap;
     if (base > item_cap) atomicOr(status, OBBV_STATUS_OVERFLOW);
+  }
+  if (list_cnt) {  // one-pass list counters start the next call at zero
+    __syncthreads();
+    for (int g = threadIdx.x; g < 3 * n_frames; g += blockDim.x) list_cnt[g] = 0;
   }
 }
 
@@ -1601,43 +1670,55 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   }
 
   float4* d_listP = nullptr;
+  int32_t* d_lcnt = nullptr;  // one-pass list counters
+  int64_t seg = 0;
   if (sf) {  // per (frame, axis): the triangles of the frame's kept half prism
     const int nt = meshes[0].n_triangles;
     const int nch = ceil_div(std::max(nt, 1), kCullThreads);
     const unsigned fgrid = (unsigned)std::min<int64_t>((int64_t)n_frames * nch, 256 * 16);
-    hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], centre,
-                       mask, nch, d_ficnt, (const int32_t*)nullptr, (const int64_t*)nullptr, (float4*)nullptr,
-                       status, spans);
-    OBBV_HIP(hipGetLastError());
     const int ngroups = 3 * n_frames;
-    if ((int64_t)ngroups * nch <= ((int64_t)1 << 20)) {  // one block: item and list offsets
-      hipLaunchKernelGGL(k_frame_scan, dim3(1), dim3(kScanBlockThreads), 0, s, (const int32_t*)d_ficnt, ngroups,
-                         nch, d_fioff, d_fcnt, d_foff);
+    if ((int64_t)ngroups * std::max(nt, 1) * 48 <= ((int64_t)1 << 31)) {
+      // one pass: every list gets room for the whole mesh
+      seg = std::max(nt, 1);
+      void* cv = nullptr;
+      OBBV_RET(pool_get_zeroed(pool_base + kPoolFrameCnt, 4 * (size_t)ngroups, &cv));
+      d_lcnt = (int32_t*)cv;
+      void* lv = nullptr;
+      OBBV_RET(pool_get(pool_base + kPoolLists, (size_t)ngroups * seg * 48, &lv));
+      d_listP = (float4*)lv;
+      hipLaunchKernelGGL(k_frame_list, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], centre,
+                         mask, nch, seg, d_lcnt, d_listP, status, spans);
       OBBV_HIP(hipGetLastError());
-    } else {
-      hipLaunchKernelGGL(k_frame_scan, dim3(ceil_div(ngroups, kCullWaves)), dim3(kCullThreads), 0, s,
-                         (const int32_t*)d_ficnt, ngroups, nch, d_fioff, d_fcnt, (int64_t*)nullptr);
+    } else {  // large: count, scan, size the lists exactly (one host round trip), write
+      hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], centre,
+                         mask, nch, d_ficnt, (const int32_t*)nullptr, (const int64_t*)nullptr, (float4*)nullptr,
+                         status, spans);
       OBBV_HIP(hipGetLastError());
-      OBBV_RET(exclusive_scan_i32_to_i64(d_fcnt, d_foff, ngroups, d_scan, scan_bytes, s));
-    }
-    int64_t bound = (int64_t)ngroups * nt;
-    if (bound * 48 > ((int64_t)1 << 31)) {  // large: size the lists exactly (one host round trip)
+      if ((int64_t)ngroups * nch <= ((int64_t)1 << 20)) {  // one block: item and list offsets
+        hipLaunchKernelGGL(k_frame_scan, dim3(1), dim3(kScanBlockThreads), 0, s, (const int32_t*)d_ficnt, ngroups,
+                           nch, d_fioff, d_fcnt, d_foff);
+        OBBV_HIP(hipGetLastError());
+      } else {
+        hipLaunchKernelGGL(k_frame_scan, dim3(ceil_div(ngroups, kCullWaves)), dim3(kCullThreads), 0, s,
+                           (const int32_t*)d_ficnt, ngroups, nch, d_fioff, d_fcnt, (int64_t*)nullptr);
+        OBBV_HIP(hipGetLastError());
+        OBBV_RET(exclusive_scan_i32_to_i64(d_fcnt, d_foff, ngroups, d_scan, scan_bytes, s));
+      }
       int64_t* pin = nullptr;
       OBBV_RET(pinned_totals(&pin));
       OBBV_HIP(hipMemcpyAsync(pin + 3, d_foff + ngroups, 8, hipMemcpyDeviceToHost, s));
       OBBV_HIP(hipStreamSynchronize(s));
-      bound = pin[3];
+      void* lv = nullptr;
+      OBBV_RET(pool_get(pool_base + kPoolLists, (size_t)std::max<int64_t>(pin[3], 1) * 48, &lv));
+      d_listP = (float4*)lv;
+      hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], centre,
+                         mask, nch, d_ficnt, (const int32_t*)d_fioff, (const int64_t*)d_foff, d_listP, status, spans);
+      OBBV_HIP(hipGetLastError());
     }
-    void* lv = nullptr;
-    OBBV_RET(pool_get(pool_base + kPoolLists, (size_t)std::max<int64_t>(bound, 1) * 48, &lv));
-    d_listP = (float4*)lv;
-    hipLaunchKernelGGL(k_frame_cull, dim3(fgrid), dim3(kCullThreads), 0, s, sf->frames, n_frames, mh[0], centre,
-                       mask, nch, d_ficnt, (const int32_t*)d_fioff, (const int64_t*)d_foff, d_listP, status, spans);
-    OBBV_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_box_chunks, dim3(1), dim3(kScanBlockThreads), 0, s, box_mesh, d_meshes, mh[0], n_meshes,
                      n_boxes, mask, boxes, sf ? sf->frames : nullptr, sf ? sf->box_frame : nullptr, n_frames,
-                     (const int64_t*)d_foff, d_choff, status, box_key, R, params->seed, d_rframe, d_items,
+                     (const int64_t*)d_foff, d_lcnt, seg, d_choff, status, box_key, R, params->seed, d_rframe, d_items,
                      cs.item_cap, d_acc, d_ctl, runs, centre);
   OBBV_HIP(hipGetLastError());
 
