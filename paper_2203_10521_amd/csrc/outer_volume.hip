@@ -742,6 +742,8 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
              unsigned long long* __restrict__ ctl, const float4* __restrict__ runs,
              const float4* __restrict__ centre) {
   __shared__ long long wsum[kScanBlockThreads / 64];
+  __shared__ unsigned long long s_rm[kScanBlockThreads];  // runs kept (the first 64) of a whole-mesh cast
+  __shared__ uint8_t s_cul[kScanBlockThreads];            // the pair is a whole-mesh cast with span runs
   if (threadIdx.x < 4) ctl[threadIdx.x] = 0ull;
   for (int e = threadIdx.x; e < 3 * n_boxes; e += blockDim.x) {
     const int b = e / 3;
@@ -783,15 +785,33 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
           Bx = load_box(boxes, b);
           mirror = cast_mirror(Bx, w, centre[0]);
           culled = true;
-          long long c = 0;
-          const long long nr = (n + kCastTris - 1) / kCastTris;
-          for (long long r = 0; r < nr; ++r) {
-            const bool hit = span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1]);
-            if (r < 64 && hit) rmask |= 1ull << r;
-            c += hit ? 1 : 0;
-          }
-          nch = c;
         }
+      }
+    }
+    if (runs && !meshes) {
+      // the first 64 runs of every whole-mesh cast of these pairs, one (pair,
+      // run) test per thread, into bit r of s_rm[pair - p0]
+      const long long nr = (mesh0.nt + kCastTris - 1) / kCastTris;
+      const int nr64 = (int)min(nr, 64ll);
+      const int npc = min(kScanBlockThreads, npairs - p0);
+      s_rm[threadIdx.x] = 0ull;
+      s_cul[threadIdx.x] = culled ? 1 : 0;
+      __syncthreads();
+      for (int k = threadIdx.x; k < npc * nr64; k += blockDim.x) {
+        const int q = k / nr64, r = k - q * nr64;
+        if (!s_cul[q]) continue;
+        const int p = p0 + q, b = p / 3, w = p - 3 * b;
+        const BoxRegs Bk = load_box(boxes, b);
+        if (span_may_cast(Bk, w, cast_mirror(Bk, w, centre[0]), runs[2 * r], runs[2 * r + 1]))
+          atomicOr(&s_rm[q], 1ull << r);
+      }
+      __syncthreads();
+      if (culled) {
+        const int w = pr - 3 * (pr / 3);
+        rmask = s_rm[threadIdx.x];
+        long long c = __popcll(rmask);
+        for (long long r = 64; r < nr; ++r) c += span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1]) ? 1 : 0;
+        nch = c;
       }
     }
     long long total = 0;
@@ -1450,6 +1470,14 @@ int block_rays_choice(int requested) {
 }
 
 // Span culling of whole-mesh casts: on unless OBBV_SPAN_CULL=0 (same bits either way).
+// Frame lists of grouped calls: one pass into fixed segments while they fit in
+// 2 GB, else two passes sized exactly; OBBV_FRAME_LISTS=2 takes the two-pass
+// build at any size (same bits).
+bool frame_lists_two_pass(int64_t bytes_one_pass) {
+  const char* e = getenv("OBBV_FRAME_LISTS");
+  return bytes_one_pass > ((int64_t)1 << 31) || (e && *e && atoi(e) == 2);
+}
+
 bool span_cull_choice() {
   const char* e = getenv("OBBV_SPAN_CULL");
   return !(e && *e && atoi(e) == 0);
@@ -1677,7 +1705,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
     const int nch = ceil_div(std::max(nt, 1), kCullThreads);
     const unsigned fgrid = (unsigned)std::min<int64_t>((int64_t)n_frames * nch, 256 * 16);
     const int ngroups = 3 * n_frames;
-    if ((int64_t)ngroups * std::max(nt, 1) * 48 <= ((int64_t)1 << 31)) {
+    if (!frame_lists_two_pass((int64_t)ngroups * std::max(nt, 1) * 48)) {
       // one pass: every list gets room for the whole mesh
       seg = std::max(nt, 1);
       void* cv = nullptr;

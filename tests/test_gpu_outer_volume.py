@@ -245,11 +245,16 @@ def test_config2_torus_sampled_boxes_full_size(api):
     torch.cuda.synchronize()
 
 
-def test_grouped_candidates_equal_plain_calls(api):
+@pytest.mark.parametrize("lists", ["1", "2"])
+def test_grouped_candidates_equal_plain_calls(api, monkeypatch, lists):
     """Boxes grouped by shared centre and axes (Lloyd candidates: a box grown in
     several ways) give bitwise the plain call's results; boxes whose group frame
     does not contain them (other axes, larger extent, bad index) fall back to
-    the whole mesh and still agree."""
+    the whole mesh and still agree.  Both frame-list builds: one pass into
+    fixed segments (list order follows the blocks' arrival) and two passes
+    sized exactly (OBBV_FRAME_LISTS=2); repeated calls check that the one-pass
+    counters start every call at zero."""
+    monkeypatch.setenv("OBBV_FRAME_LISTS", lists)
     import torch
     V, F = synth.noisy_torus()
     g = np.random.default_rng(12)
