@@ -91,7 +91,7 @@ __global__ void k_stage(const uint4* __restrict__ src, uint4* __restrict__ dst, 
 struct FloodTimers {
   WallTimer pops, extents, cands, rank_post, exact_post, decide, grow, pred_pack, pred_launch, pred_wait;
 };
-static FloodTimers g_ft;
+static thread_local FloodTimers g_ft;  // per host thread (floods may run on two)
 
 inline float f32_up(double x) {
   float y = (float)x;
@@ -1548,9 +1548,40 @@ struct LloydState {
   Predictor pred;
   WallTimer t_flood, t_update, t_life;
   int64_t n_calls0 = 0;
+  // second evaluator, on a stream and scratch set of its own, for floods whose
+  // groups are split over two host threads
+  Evaluator ev2;
+  hipStream_t stream2 = nullptr;
+
+  int ensure_ev2() {
+    OBBV_RET(ev.ensure_spans());
+    if (!stream2) {
+      OBBV_HIP(hipStreamCreateWithFlags(&stream2, hipStreamNonBlocking));
+      ev2.stream = stream2;
+      ev2.pool_base = kPoolCount;
+    }
+    ev2.mesh = ev.mesh;
+    ev2.params = ev.params;
+    ev2.spans = ev.spans;  // borrowed (made once, never replaced)
+    ev2.spans_done = true;
+    std::memcpy(ev2.centre, ev.centre, 16);
+    ev2.have_centre = ev.have_centre;
+    // the second stream starts after the work enqueued so far on the first
+    hipEvent_t e;
+    OBBV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const hipError_t r1 = hipEventRecord(e, ev.stream);
+    const hipError_t r2 = r1 == hipSuccess ? hipStreamWaitEvent(stream2, e, 0) : r1;
+    (void)hipEventDestroy(e);
+    OBBV_HIP(r2);
+    return OBBV_OK;
+  }
 
   LloydState() { t_life.start(); }
   ~LloydState() {
+    if (stream2) {
+      (void)hipStreamSynchronize(stream2);
+      (void)hipStreamDestroy(stream2);
+    }
     if (!getenv("OBBV_LLOYD_TIMING")) return;
     t_life.stop();
     fprintf(stderr,
@@ -1573,6 +1604,75 @@ struct LloydState {
   }
 };
 
+// Host threads a flood of independent groups is split over: 2, or 1 with
+// OBBV_FLOOD_STREAMS=1 (same bits: the flood of a group reads and writes only
+// its own elements and boxes, and a box's outer volume does not depend on the
+// call that evaluates it).
+static int flood_streams_choice() {
+  const char* e = getenv("OBBV_FLOOD_STREAMS");
+  return (e && *e && atoi(e) == 1) ? 1 : 2;
+}
+
+// The flood of `groups`: without the ranker and with two groups or more, the
+// groups are split into two halves of about equal element counts, flooded on
+// two host threads with an evaluator (stream, scratch) each, so that one half's
+// device work overlaps the other's host work and fills the CUs the other's
+// calls leave idle.
+static int flood_split(LloydState& S, const std::vector<Group>& groups, PartitionIO io) {
+  const bool split = groups.size() >= 2 && !S.pred.on && S.ev.smp_cap == 0 && flood_streams_choice() == 2;
+  if (!split) return flood_partition(S.M, S.E, groups, io, S.K, S.ev, S.cnt, &S.pred);
+  std::vector<int> order(groups.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return groups[a].elems.size() > groups[b].elems.size(); });
+  std::vector<char> second(groups.size(), 0);
+  size_t wa = 0, wb = 0;
+  for (int g : order) {
+    if (wb < wa) {
+      second[g] = 1;
+      wb += groups[g].elems.size();
+    } else {
+      wa += groups[g].elems.size();
+    }
+  }
+  std::vector<Group> ga, gb;
+  for (size_t g = 0; g < groups.size(); ++g) (second[g] ? gb : ga).push_back(groups[g]);
+  OBBV_RET(S.ensure_ev2());
+  std::vector<int32_t> eb2;
+  PartitionIO io2{io.boxes, io.obv, io.slot, &eb2};
+  Counters c2;
+  int rc2 = OBBV_OK;
+  std::string err2;
+  int dev = 0;
+  OBBV_HIP(hipGetDevice(&dev));
+  std::thread th([&] {
+    if (hipSetDevice(dev) != hipSuccess) {
+      rc2 = OBBV_ERR_HIP;
+      err2 = "hipSetDevice failed in the second flood thread";
+      return;
+    }
+    rc2 = flood_partition(S.M, S.E, gb, io2, S.K, S.ev2, c2, nullptr);
+    if (rc2 != OBBV_OK) err2 = obbv_last_error();
+  });
+  const int rc1 = flood_partition(S.M, S.E, ga, io, S.K, S.ev, S.cnt, nullptr);
+  th.join();
+  if (rc2 != OBBV_OK) {
+    set_error(err2);
+    return rc2;
+  }
+  OBBV_RET(rc1);
+  std::vector<int32_t>& eb = *io.elem_box;
+  for (const Group& g : gb)
+    for (int e : g.elems) eb[e] = eb2[e];
+  S.cnt.evals += c2.evals;
+  S.cnt.rounds += c2.rounds;
+  S.cnt.trivial += c2.trivial;
+  S.cnt.moves += c2.moves;
+  S.ev.calls += S.ev2.calls;
+  S.ev2.calls = 0;
+  return OBBV_OK;
+}
+
 // One Lloyd iteration (partition + parameter update) of every group.
 static int lloyd_iterate(LloydState& S) {
   S.pred.paused = false;  // a judge fallback lasts for one iteration
@@ -1583,7 +1683,7 @@ static int lloyd_iterate(LloydState& S) {
   for (const Group& g : S.groups)
     if (g.boxes.size() > 1) flood_groups.push_back(g);
   S.t_flood.start();
-  OBBV_RET(flood_partition(S.M, S.E, flood_groups, io, S.K, S.ev, S.cnt, &S.pred));
+  OBBV_RET(flood_split(S, flood_groups, io));
   S.t_flood.stop();
   for (const Group& g : S.groups)
     if (g.boxes.size() == 1)
@@ -2009,7 +2109,7 @@ int merge_level(LloydState& S, Tree& T, int l) {
   for (const Group& g : S.groups)
     if (g.boxes.size() > 1) fg.push_back(g);
   S.pred.paused = false;
-  OBBV_RET(flood_partition(S.M, S.E, fg, io, S.K, S.ev, S.cnt, &S.pred));
+  OBBV_RET(flood_split(S, fg, io));
   for (const Group& g : S.groups)
     if (g.boxes.size() == 1)
       for (int e : g.elems) eb[e] = g.boxes[0];
