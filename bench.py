@@ -12,9 +12,13 @@ flood pops per group per round.  One step = one complete obbv_build_hierarchy.
 
 Other objects of the line:
   roofline      the cast kernel (cull, LDS rays, FP32 ray-triangle tests): 16
-                FLOP per test the kernel performs over its average launch time
-                (HIP events on the library stream), against the FP32 vector peak;
-                `traffic` = its HBM bytes per launch from rocprofv3 counters
+                FLOP per test the kernel performs, over the time during which a
+                cast launch runs (HIP events around every launch, on the stream
+                it is launched on; the floods of independent groups run on two
+                streams whose launches overlap, so the launch intervals are
+                merged), against the FP32 vector peak; the per-launch average
+                beside it; `traffic` = its HBM bytes per launch from rocprofv3
+                counters
   culling_stream  the bytes the cast kernel streams per launch (48 B per
                 triangle-list entry per unit) as a rate against HBM, next to the
                 algorithmic bytes of the calls (36 B per triangle + 68 B per box)
@@ -491,9 +495,13 @@ def main():
         log(f"timed step done: {out['counters']['evals']} evaluations")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    cast_ms, launches, tests, nbytes = api.profile_read()
+    cast_ms, launches, tests, nbytes, busy_ms = api.profile_read(busy=True)
     api.profile_enable(False)
-    avg_ms, per_launch, tflops, gbps = kernel_rates(cast_ms, launches, tests, nbytes)
+    avg_ms, per_launch, tflops_launch, gbps_launch = kernel_rates(cast_ms, launches, tests, nbytes)
+    # rates while the cast kernel runs: the launches of the two flood streams
+    # overlap, so the tests are divided by the union of the launch intervals
+    tflops = tests * FLOP_PER_TEST / (busy_ms * 1e-3) / 1e12 if busy_ms > 0 else 0.0
+    gbps = nbytes / (busy_ms * 1e-3) / 1e9 if busy_ms > 0 else 0.0
     boxes_per_call = evals / max(launches, 1)
     algo_bytes = F.shape[0] * 36 + 68 * boxes_per_call
 
@@ -519,21 +527,25 @@ def main():
         "evals_per_step": evals / args.steps,
         "moves_per_s": moves / dt,
         "hierarchy_error": out["e"].tolist(),
-        "tests_per_s": tests / (cast_ms * 1e-3) if cast_ms > 0 else None,
+        "tests_per_s": tests / (busy_ms * 1e-3) if busy_ms > 0 else None,
         "cast_avg_ms": avg_ms,
+        "cast_busy_ms_per_step": busy_ms / args.steps,
+        "cast_sum_ms_per_step": cast_ms / args.steps,
         "cast_launches": launches,
         "tests_per_launch": per_launch,
         # the cast kernel's work is FP32 ray-triangle tests: 16 FLOP each, graded
         # against the FP32 vector peak (packed; the non-packed ceiling beside it)
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / FP32_PEAK_TFLOPS, "traffic": traffic_bytes(),
-                     "kernel": "k_cast", "flop_per_test": FLOP_PER_TEST,
+                     "kernel": "k_cast", "flop_per_test": FLOP_PER_TEST, "time": "union of launch intervals",
+                     "achieved_per_launch": tflops_launch, "frac_per_launch": tflops_launch / FP32_PEAK_TFLOPS,
                      "peak_nonpacked": FP32_NONPACKED_TFLOPS, "frac_nonpacked": tflops / FP32_NONPACKED_TFLOPS},
         "hbm_traffic": (None if traffic_bytes() is None else
                         {"bytes_per_launch": traffic_bytes(), "ratio_to_algorithmic": traffic_bytes() / algo_bytes,
                          "gbps_at_cast_avg": traffic_bytes() / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None,
                          "source": "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"}),
         "culling_stream": {"bytes_per_launch": nbytes / max(launches, 1), "achieved_gbps": gbps,
+                           "achieved_gbps_per_launch": gbps_launch,
                            "peak_gbps": HBM_PEAK_GBPS, "frac": gbps / HBM_PEAK_GBPS,
                            "algorithmic_bytes_per_launch": algo_bytes,
                            "ratio_to_algorithmic": (nbytes / max(launches, 1)) / algo_bytes,

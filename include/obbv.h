@@ -212,9 +212,13 @@ int obbv_outer_volume_noalloc(const obbv_mesh* mesh, const obbv_box* boxes, cons
 int obbv_profile_enable(int enable);
 
 /* Synchronous.  Sums the elapsed time of the recorded ray-test launches and
- * returns it with the launch count, the test count and the byte count, then
- * clears the record.  Outputs are host pointers, each nullable. */
-int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests, int64_t* out_bytes);
+ * returns it with the launch count, the test count and the byte count, and the
+ * time during which at least one recorded launch ran (out_busy_ms: the union of
+ * the launches' intervals, which is less than the sum when launches on several
+ * streams overlap), then clears the record.  Outputs are host pointers, each
+ * nullable. */
+int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests, int64_t* out_bytes,
+                      double* out_busy_ms);
 
 /* ---- planned (graph-replayed) evaluations ------------------------------------ */
 

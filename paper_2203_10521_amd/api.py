@@ -181,15 +181,19 @@ def profile_enable(enable=True):
     _check(_lib.lib().obbv_profile_enable(1 if enable else 0))
 
 
-def profile_read():
+def profile_read(busy=False):
     """(total ray-test milliseconds, launches, ray-triangle tests, algorithmic
-    bytes read) since the last read."""
+    bytes read) since the last read; with busy=True a fifth value, the
+    milliseconds during which at least one ray-test launch ran (launches on
+    several streams overlap)."""
     ms = ctypes.c_double(0.0)
     n = ctypes.c_int64(0)
     t = ctypes.c_int64(0)
     b = ctypes.c_int64(0)
-    _check(_lib.lib().obbv_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(t), ctypes.byref(b)))
-    return ms.value, n.value, t.value, b.value
+    u = ctypes.c_double(0.0)
+    _check(_lib.lib().obbv_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(t), ctypes.byref(b),
+                                        ctypes.byref(u)))
+    return (ms.value, n.value, t.value, b.value, u.value) if busy else (ms.value, n.value, t.value, b.value)
 
 
 def _host_ptr(a):

@@ -1548,40 +1548,46 @@ struct LloydState {
   Predictor pred;
   WallTimer t_flood, t_update, t_life;
   int64_t n_calls0 = 0;
-  // second evaluator, on a stream and scratch set of its own, for floods whose
-  // groups are split over two host threads
-  Evaluator ev2;
-  hipStream_t stream2 = nullptr;
+  // more evaluators, each on a stream and scratch set of its own, for floods
+  // whose groups are split over several host threads
+  static constexpr int kFloodParts = kPoolSets;
+  Evaluator evx[kFloodParts - 1];
+  hipStream_t streamx[kFloodParts - 1] = {};
 
-  int ensure_ev2() {
+  int ensure_evx(int parts) {
     OBBV_RET(ev.ensure_spans());
-    if (!stream2) {
-      OBBV_HIP(hipStreamCreateWithFlags(&stream2, hipStreamNonBlocking));
-      ev2.stream = stream2;
-      ev2.pool_base = kPoolCount;
-    }
-    ev2.mesh = ev.mesh;
-    ev2.params = ev.params;
-    ev2.spans = ev.spans;  // borrowed (made once, never replaced)
-    ev2.spans_done = true;
-    std::memcpy(ev2.centre, ev.centre, 16);
-    ev2.have_centre = ev.have_centre;
-    // the second stream starts after the work enqueued so far on the first
     hipEvent_t e;
     OBBV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    const hipError_t r1 = hipEventRecord(e, ev.stream);
-    const hipError_t r2 = r1 == hipSuccess ? hipStreamWaitEvent(stream2, e, 0) : r1;
+    hipError_t r = hipEventRecord(e, ev.stream);
+    for (int k = 0; k < parts - 1 && r == hipSuccess; ++k) {
+      Evaluator& x = evx[k];
+      if (!streamx[k]) {
+        r = hipStreamCreateWithFlags(&streamx[k], hipStreamNonBlocking);
+        if (r != hipSuccess) break;
+        x.stream = streamx[k];
+        x.pool_base = (k + 1) * kPoolCount;
+      }
+      x.mesh = ev.mesh;
+      x.params = ev.params;
+      x.spans = ev.spans;  // borrowed (made once, never replaced)
+      x.spans_done = true;
+      std::memcpy(x.centre, ev.centre, 16);
+      x.have_centre = ev.have_centre;
+      // the stream starts after the work enqueued so far on the first
+      r = hipStreamWaitEvent(streamx[k], e, 0);
+    }
     (void)hipEventDestroy(e);
-    OBBV_HIP(r2);
+    OBBV_HIP(r);
     return OBBV_OK;
   }
 
   LloydState() { t_life.start(); }
   ~LloydState() {
-    if (stream2) {
-      (void)hipStreamSynchronize(stream2);
-      (void)hipStreamDestroy(stream2);
-    }
+    for (hipStream_t& x : streamx)
+      if (x) {
+        (void)hipStreamSynchronize(x);
+        (void)hipStreamDestroy(x);
+      }
     if (!getenv("OBBV_LLOYD_TIMING")) return;
     t_life.stop();
     fprintf(stderr,
@@ -1604,72 +1610,78 @@ struct LloydState {
   }
 };
 
-// Host threads a flood of independent groups is split over: 2, or 1 with
-// OBBV_FLOOD_STREAMS=1 (same bits: the flood of a group reads and writes only
-// its own elements and boxes, and a box's outer volume does not depend on the
-// call that evaluates it).
+// Host threads a flood of independent groups is split over (OBBV_FLOOD_STREAMS,
+// 1 to 4, default 4: the device's hardware queues per process).  The bits do not depend on it: the flood of a group
+// reads and writes only its own elements and boxes, and a box's outer volume
+// does not depend on the call that evaluates it.
 static int flood_streams_choice() {
   const char* e = getenv("OBBV_FLOOD_STREAMS");
-  return (e && *e && atoi(e) == 1) ? 1 : 2;
+  if (e && *e) return std::max(1, std::min(LloydState::kFloodParts, atoi(e)));
+  return LloydState::kFloodParts;
 }
 
 // The flood of `groups`: without the ranker and with two groups or more, the
-// groups are split into two halves of about equal element counts, flooded on
-// two host threads with an evaluator (stream, scratch) each, so that one half's
-// device work overlaps the other's host work and fills the CUs the other's
-// calls leave idle.
+// groups are split into parts of about equal element counts (largest group
+// first, into the lightest part; groups keep their order inside a part),
+// flooded on host threads with an evaluator (stream, scratch set) each, so that
+// one part's device work overlaps another's host work and fills the CUs
+// another's calls leave idle.
 static int flood_split(LloydState& S, const std::vector<Group>& groups, PartitionIO io) {
-  const bool split = groups.size() >= 2 && !S.pred.on && S.ev.smp_cap == 0 && flood_streams_choice() == 2;
-  if (!split) return flood_partition(S.M, S.E, groups, io, S.K, S.ev, S.cnt, &S.pred);
+  const int parts = std::min<int>(flood_streams_choice(), (int)groups.size());
+  if (parts < 2 || S.pred.on || S.ev.smp_cap != 0)
+    return flood_partition(S.M, S.E, groups, io, S.K, S.ev, S.cnt, &S.pred);
   std::vector<int> order(groups.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return groups[a].elems.size() > groups[b].elems.size(); });
-  std::vector<char> second(groups.size(), 0);
-  size_t wa = 0, wb = 0;
+  std::vector<int> part_of(groups.size(), 0);
+  std::vector<size_t> load((size_t)parts, 0);
   for (int g : order) {
-    if (wb < wa) {
-      second[g] = 1;
-      wb += groups[g].elems.size();
-    } else {
-      wa += groups[g].elems.size();
-    }
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    part_of[g] = k;
+    load[k] += groups[g].elems.size();
   }
-  std::vector<Group> ga, gb;
-  for (size_t g = 0; g < groups.size(); ++g) (second[g] ? gb : ga).push_back(groups[g]);
-  OBBV_RET(S.ensure_ev2());
-  std::vector<int32_t> eb2;
-  PartitionIO io2{io.boxes, io.obv, io.slot, &eb2};
-  Counters c2;
-  int rc2 = OBBV_OK;
-  std::string err2;
+  std::vector<std::vector<Group>> pg((size_t)parts);
+  for (size_t g = 0; g < groups.size(); ++g) pg[part_of[g]].push_back(groups[g]);
+  OBBV_RET(S.ensure_evx(parts));
+  const int nx = parts - 1;
+  std::vector<std::vector<int32_t>> ebx((size_t)nx);
+  std::vector<Counters> cx((size_t)nx);
+  std::vector<int> rcx((size_t)nx, OBBV_OK);
+  std::vector<std::string> errx((size_t)nx);
   int dev = 0;
   OBBV_HIP(hipGetDevice(&dev));
-  std::thread th([&] {
-    if (hipSetDevice(dev) != hipSuccess) {
-      rc2 = OBBV_ERR_HIP;
-      err2 = "hipSetDevice failed in the second flood thread";
-      return;
+  std::vector<std::thread> th;
+  for (int k = 0; k < nx; ++k)
+    th.emplace_back([&, k] {
+      if (hipSetDevice(dev) != hipSuccess) {
+        rcx[k] = OBBV_ERR_HIP;
+        errx[k] = "hipSetDevice failed in a flood thread";
+        return;
+      }
+      PartitionIO iok{io.boxes, io.obv, io.slot, &ebx[k]};
+      rcx[k] = flood_partition(S.M, S.E, pg[k + 1], iok, S.K, S.evx[k], cx[k], nullptr);
+      if (rcx[k] != OBBV_OK) errx[k] = obbv_last_error();
+    });
+  const int rc0 = flood_partition(S.M, S.E, pg[0], io, S.K, S.ev, S.cnt, nullptr);
+  for (std::thread& t : th) t.join();
+  for (int k = 0; k < nx; ++k)
+    if (rcx[k] != OBBV_OK) {
+      set_error(errx[k]);
+      return rcx[k];
     }
-    rc2 = flood_partition(S.M, S.E, gb, io2, S.K, S.ev2, c2, nullptr);
-    if (rc2 != OBBV_OK) err2 = obbv_last_error();
-  });
-  const int rc1 = flood_partition(S.M, S.E, ga, io, S.K, S.ev, S.cnt, nullptr);
-  th.join();
-  if (rc2 != OBBV_OK) {
-    set_error(err2);
-    return rc2;
-  }
-  OBBV_RET(rc1);
+  OBBV_RET(rc0);
   std::vector<int32_t>& eb = *io.elem_box;
-  for (const Group& g : gb)
-    for (int e : g.elems) eb[e] = eb2[e];
-  S.cnt.evals += c2.evals;
-  S.cnt.rounds += c2.rounds;
-  S.cnt.trivial += c2.trivial;
-  S.cnt.moves += c2.moves;
-  S.ev.calls += S.ev2.calls;
-  S.ev2.calls = 0;
+  for (int k = 0; k < nx; ++k) {
+    for (const Group& g : pg[k + 1])
+      for (int e : g.elems) eb[e] = ebx[k][e];
+    S.cnt.evals += cx[k].evals;
+    S.cnt.rounds += cx[k].rounds;
+    S.cnt.trivial += cx[k].trivial;
+    S.cnt.moves += cx[k].moves;
+    S.ev.calls += S.evx[k].calls;
+    S.evx[k].calls = 0;
+  }
   return OBBV_OK;
 }
 

@@ -281,18 +281,37 @@ extern "C" int obbv_profile_enable(int enable) {
 }
 
 extern "C" int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests,
-                                 int64_t* out_bytes) {
+                                 int64_t* out_bytes, double* out_busy_ms) {
   clear_error();
   std::lock_guard<std::mutex> lock(g_prof_mutex);
   double total = 0.0;
+  // launch intervals from the first launch's start event, merged into the busy time
+  std::vector<std::pair<double, double>> iv;
+  iv.reserve(g_prof.events.size());
   for (auto& e : g_prof.events) {
     OBBV_HIP(hipEventSynchronize(e.second));
-    float ms = 0.f;
+    float ms = 0.f, t0 = 0.f;
     OBBV_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+    OBBV_HIP(hipEventElapsedTime(&t0, g_prof.events.front().first, e.first));
     total += ms;
+    iv.emplace_back((double)t0, (double)t0 + (double)ms);
+  }
+  for (auto& e : g_prof.events) {
     g_prof.spare.push_back(e.first);
     g_prof.spare.push_back(e.second);
   }
+  std::sort(iv.begin(), iv.end());
+  double busy = 0.0, lo = 0.0, hi = -1.0;
+  for (const auto& x : iv) {
+    if (x.first > hi) {
+      if (hi > lo) busy += hi - lo;
+      lo = x.first;
+      hi = x.second;
+    } else {
+      hi = std::max(hi, x.second);
+    }
+  }
+  if (hi > lo) busy += hi - lo;
   const int64_t n = (int64_t)g_prof.events.size();
   g_prof.events.clear();
   unsigned long long tests = 0, bytes = 0;
@@ -310,6 +329,7 @@ extern "C" int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int
   if (out_launches) *out_launches = n;
   if (out_tests) *out_tests = (int64_t)tests;
   if (out_bytes) *out_bytes = (int64_t)bytes;
+  if (out_busy_ms) *out_busy_ms = busy;
   return OBBV_OK;
 }
 

@@ -148,21 +148,25 @@ def test_containment_masks_give_the_same_bits_as_candidate_boxes(api, monkeypatc
     assert out["1"]["counters"]["trivial"] > 0
 
 
-def test_flood_on_two_streams_gives_the_same_bits(api, monkeypatch):
+def test_flood_on_several_streams_gives_the_same_bits(api, monkeypatch):
     """Floods of two or more independent groups (the children of different
-    parents) run as two halves on two host threads, each with its own
-    evaluator and stream; with OBBV_FLOOD_STREAMS=1 one thread floods every
-    group in shared rounds.  The hierarchies are bit-identical and so are the
-    counters, except rounds (the halves count their rounds separately)."""
+    parents) run in parts of about equal size on host threads, each with its
+    own evaluator and stream (OBBV_FLOOD_STREAMS parts, default 4); with 1, one
+    thread floods every group in shared rounds.  The hierarchies are
+    bit-identical and so are the counters, except rounds (the parts count their
+    rounds separately)."""
     V, F = synth.noisy_cube_sphere(8, seed=29)
     Vt, Ft = _dev(V, F)
     out = {}
-    for flag in ("2", "1"):
+    for flag in ("1", "2", "4"):
         monkeypatch.setenv("OBBV_FLOOD_STREAMS", flag)
         out[flag] = api.build_hierarchy(Vt, Ft, levels=3, branching=4, iters=3, sweeps=1, R=16, seed=9,
                                         pops_per_round=8)
-    for k in ("boxes", "obv", "parent", "tri_node", "e"):
-        assert np.array_equal(out["2"][k], out["1"][k]), k
-    c2, c1 = dict(out["2"]["counters"]), dict(out["1"]["counters"])
-    assert c2.pop("rounds") >= c1.pop("rounds")
-    assert c2 == c1
+    c1 = dict(out["1"]["counters"])
+    r1 = c1.pop("rounds")
+    for flag in ("2", "4"):
+        for k in ("boxes", "obv", "parent", "tri_node", "e"):
+            assert np.array_equal(out[flag][k], out["1"][k]), (flag, k)
+        c = dict(out[flag]["counters"])
+        assert c.pop("rounds") >= r1
+        assert c == c1
