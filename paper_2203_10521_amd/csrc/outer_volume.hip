@@ -1033,19 +1033,33 @@ __device__ inline Acc raster_lane(const CastArgs& a, const Rec& r, int i0, int i
   const int wdt = i1 - i0 + 1, cells = wdt * (j1 - j0 + 1);
   int idx = (i0 - ci0) + (j0 - cj0) * bw, di = 0;
   Acc sum = 0;
-  for (int t = 0; t < cells; ++t) {
-    const float2 p = sray[idx];
+  // two cells per step: both rays are read from LDS before either is tested
+  auto test = [&](const float2 p, int at) {
     float y;
     if (rec_hit(r, p.x, p.y, y)) {
       const int32_t q = (int32_t)(__float_as_uint(__builtin_amdgcn_fmed3f(y, r.lo, r.hi)) - kMagicBits);
       sum += q;
-      if (STATS || OCC) note_hit<STATS, OCC>(a, r, y, q, idx, ci0, cj0, bw, bw3, socc);
+      if (STATS || OCC) note_hit<STATS, OCC>(a, r, y, q, at, ci0, cj0, bw, bw3, socc);
     }
+  };
+  auto step = [&](int& at) {
     ++di;
     const bool wrap = di == wdt;
-    idx += wrap ? bw - wdt + 1 : 1;
+    at += wrap ? bw - wdt + 1 : 1;
     di = wrap ? 0 : di;
+  };
+  int t = 0;
+  for (; t + 1 < cells; t += 2) {
+    int idx1 = idx;
+    step(idx1);
+    const float2 p0 = sray[idx], p1 = sray[idx1];
+    int idx2 = idx1;
+    step(idx2);
+    test(p0, idx);
+    test(p1, idx1);
+    idx = idx2;
   }
+  if (t < cells) test(sray[idx], idx);
   return sum;
 }
 
