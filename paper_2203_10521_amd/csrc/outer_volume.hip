@@ -1717,7 +1717,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   if (sf) {  // per (frame, axis): the triangles of the frame's kept half prism
     const int nt = meshes[0].n_triangles;
     const int nch = ceil_div(std::max(nt, 1), kCullThreads);
-    const unsigned fgrid = (unsigned)std::min<int64_t>((int64_t)n_frames * nch, 256 * 16);
+    const unsigned fgrid = (unsigned)std::min<int64_t>((int64_t)n_frames * nch, 256 * 64);
     const int ngroups = 3 * n_frames;
     if (!frame_lists_two_pass((int64_t)ngroups * std::max(nt, 1) * 48)) {
       // one pass: every list gets room for the whole mesh
