@@ -1226,16 +1226,26 @@ __global__ void __launch_bounds__(kCastThreads) k_cast(CastArgs a) {
       // (-hu + (i + xi) du, -hv + (j + eta) dv)
       const int ui0 = s_rng[0], uj0 = s_rng[2];
       const int uw = s_rng[1] - ui0 + 1, nray = uw * (s_rng[3] - uj0 + 1);
+      // ray k = j uw + i of the range; a thread's rays are kCastThreads apart:
+      // (i, j) advance by (si, sj) with a carry (no division per ray)
+      const int sj = kCastThreads / uw, si = kCastThreads - sj * uw;
+      int rj = tid / uw, ri = tid - rj * uw;
       for (int k0 = tid; k0 < nray; k0 += kRayBatch * kCastThreads) {
         // kRayBatch rays per thread: their jitter is requested (or hashed) before any is used
         double xi[kRayBatch], eta[kRayBatch];
         int ci[kRayBatch], cj[kRayBatch];
 #pragma unroll
         for (int q = 0; q < kRayBatch; ++q) {
-          const int k = min(k0 + q * kCastThreads, nray - 1);
-          cj[q] = k / uw;
-          ci[q] = ui0 + k - cj[q] * uw;
-          cj[q] += uj0;
+          // rays past the range read the last one's draws (in bounds, not stored)
+          const bool in = k0 + q * kCastThreads < nray;
+          ci[q] = ui0 + (in ? ri : uw - 1);
+          cj[q] = uj0 + (in ? rj : nray / uw - 1);
+          ri += si;
+          rj += sj;
+          if (ri >= uw) {
+            ri -= uw;
+            ++rj;
+          }
           if (TAB) {
             const uint2 jq = a.jitter[((int64_t)rf.key * 3 + w) * a.R * a.R + (int64_t)cj[q] * a.R + ci[q]];
             xi[q] = (double)jq.x * (1.0 / 16777216.0);
