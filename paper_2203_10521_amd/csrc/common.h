@@ -56,7 +56,7 @@ enum PoolSlot {
 };
 // Two sets of the slots: calls that may run at the same time on different
 // streams take their scratch from different sets (slot + set * kPoolCount).
-constexpr int kPoolSets = 4;
+constexpr int kPoolSets = 8;
 
 // Ensures slot `slot` (< kPoolCount * kPoolSets) of the current device holds at
 // least `bytes` and returns it.  Growing frees the old block (hipFree waits for

@@ -458,6 +458,8 @@ struct Predictor {
   bool on = false;
   hipStream_t stream = nullptr;
   bool paused = false;  // the judge found the ranker off: exact evaluation until the next iteration
+  int judge_set = 1;    // pool set of the judge's exact evaluations
+  int64_t cfg_gen = 0;  // configuration generation (flood-part predictors follow the state's)
   WallTimer t_pred;
   double err_sum = 0.0;
   int64_t err_n = 0, predicted = 0, fallbacks = 0, calls = 0;
@@ -514,7 +516,7 @@ struct Predictor {
     if (!jstream) {
       OBBV_HIP(hipStreamCreateWithFlags(&jstream, hipStreamNonBlocking));
       jev.stream = jstream;
-      jev.pool_base = kPoolCount;
+      jev.pool_base = judge_set * kPoolCount;
     }
     jev.mesh = ev.mesh;
     jev.params = ev.params;
@@ -1550,8 +1552,12 @@ struct LloydState {
   int64_t n_calls0 = 0;
   // more evaluators, each on a stream and scratch set of its own, for floods
   // whose groups are split over several host threads
-  static constexpr int kFloodParts = kPoolSets;
+  // pool sets: 0 the flood's evaluator, 1-3 the other parts' evaluators, 4 the
+  // judge of the state's predictor, 5-7 the judges of the other parts' predictors
+  static constexpr int kFloodParts = 4;
+  static_assert(2 * kFloodParts <= kPoolSets, "a pool set per evaluator and per judge");
   Evaluator evx[kFloodParts - 1];
+  Predictor predx[kFloodParts - 1];
   hipStream_t streamx[kFloodParts - 1] = {};
 
   int ensure_evx(int parts) {
@@ -1581,12 +1587,17 @@ struct LloydState {
     return OBBV_OK;
   }
 
-  LloydState() { t_life.start(); }
+  LloydState() {
+    t_life.start();
+    pred.judge_set = kFloodParts;
+    for (int k = 0; k < kFloodParts - 1; ++k) predx[k].judge_set = kFloodParts + 1 + k;
+  }
   ~LloydState() {
-    for (hipStream_t& x : streamx)
-      if (x) {
-        (void)hipStreamSynchronize(x);
-        (void)hipStreamDestroy(x);
+    for (int k = 0; k < kFloodParts - 1; ++k)
+      if (streamx[k]) {
+        (void)hipStreamSynchronize(streamx[k]);
+        predx[k].stream = nullptr;  // its destructor runs after the stream is gone
+        (void)hipStreamDestroy(streamx[k]);
       }
     if (!getenv("OBBV_LLOYD_TIMING")) return;
     t_life.stop();
@@ -1620,16 +1631,15 @@ static int flood_streams_choice() {
   return LloydState::kFloodParts;
 }
 
-// The flood of `groups`: without the ranker and with two groups or more, the
-// groups are split into parts of about equal element counts (largest group
+// The flood of `groups`: with two groups or more, the groups are split into
+// parts of about equal element counts (largest group
 // first, into the lightest part; groups keep their order inside a part),
 // flooded on host threads with an evaluator (stream, scratch set) each, so that
 // one part's device work overlaps another's host work and fills the CUs
 // another's calls leave idle.
 static int flood_split(LloydState& S, const std::vector<Group>& groups, PartitionIO io) {
   const int parts = std::min<int>(flood_streams_choice(), (int)groups.size());
-  if (parts < 2 || S.pred.on || S.ev.smp_cap != 0)
-    return flood_partition(S.M, S.E, groups, io, S.K, S.ev, S.cnt, &S.pred);
+  if (parts < 2 || S.ev.smp_cap != 0) return flood_partition(S.M, S.E, groups, io, S.K, S.ev, S.cnt, &S.pred);
   std::vector<int> order(groups.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
@@ -1645,6 +1655,23 @@ static int flood_split(LloydState& S, const std::vector<Group>& groups, Partitio
   for (size_t g = 0; g < groups.size(); ++g) pg[part_of[g]].push_back(groups[g]);
   OBBV_RET(S.ensure_evx(parts));
   const int nx = parts - 1;
+  // with the ranker on, every part has a predictor of its own (same network and
+  // settings; its own stream, staging, judge window and judge scratch set)
+  for (int k = 0; k < nx && S.pred.on; ++k) {
+    Predictor& P = S.predx[k];
+    if (P.cfg_gen != S.pred.cfg_gen) {
+      P.cfg = S.pred.cfg;
+      P.cfg_gen = S.pred.cfg_gen;
+      P.packed_ready = false;
+      P.window.clear();
+      P.wpos = 0;
+      P.err_sum = 0.0;
+      P.err_n = 0;
+    }
+    P.on = true;
+    P.paused = S.pred.paused;
+    P.stream = S.streamx[k];
+  }
   std::vector<std::vector<int32_t>> ebx((size_t)nx);
   std::vector<Counters> cx((size_t)nx);
   std::vector<int> rcx((size_t)nx, OBBV_OK);
@@ -1660,10 +1687,10 @@ static int flood_split(LloydState& S, const std::vector<Group>& groups, Partitio
         return;
       }
       PartitionIO iok{io.boxes, io.obv, io.slot, &ebx[k]};
-      rcx[k] = flood_partition(S.M, S.E, pg[k + 1], iok, S.K, S.evx[k], cx[k], nullptr);
+      rcx[k] = flood_partition(S.M, S.E, pg[k + 1], iok, S.K, S.evx[k], cx[k], S.pred.on ? &S.predx[k] : nullptr);
       if (rcx[k] != OBBV_OK) errx[k] = obbv_last_error();
     });
-  const int rc0 = flood_partition(S.M, S.E, pg[0], io, S.K, S.ev, S.cnt, nullptr);
+  const int rc0 = flood_partition(S.M, S.E, pg[0], io, S.K, S.ev, S.cnt, &S.pred);
   for (std::thread& t : th) t.join();
   for (int k = 0; k < nx; ++k)
     if (rcx[k] != OBBV_OK) {
@@ -1681,6 +1708,16 @@ static int flood_split(LloydState& S, const std::vector<Group>& groups, Partitio
     S.cnt.moves += cx[k].moves;
     S.ev.calls += S.evx[k].calls;
     S.evx[k].calls = 0;
+    Predictor& P = S.predx[k];
+    S.pred.predicted += P.predicted;
+    S.pred.fallbacks += P.fallbacks;
+    S.pred.calls += P.calls;
+    S.pred.judged_evals += P.judged_evals;
+    S.pred.jerr_sum += P.jerr_sum;
+    S.pred.jerr_max = std::max(S.pred.jerr_max, P.jerr_max);
+    S.pred.t_pred.s += P.t_pred.s;
+    P.predicted = P.fallbacks = P.calls = P.judged_evals = 0;
+    P.jerr_sum = P.jerr_max = P.t_pred.s = 0.0;
   }
   return OBBV_OK;
 }
@@ -1911,6 +1948,7 @@ extern "C" int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* su
   OBBV_ARG(sur->N >= 1 && sur->verify_top >= 0 && sur->judge_every >= 1, "bad surrogate sizes");
   S.pred.cfg = *sur;
   S.pred.packed_ready = false;
+  ++S.pred.cfg_gen;
   S.pred.on = true;
   S.pred.paused = false;
   S.pred.window.clear();
