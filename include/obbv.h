@@ -183,6 +183,27 @@ int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, cons
                               int32_t n_boxes, const obbv_ov_params* params, const obbv_box* frames,
                               const int32_t* box_frame, int32_t n_frames, double* out_obv, void* stream);
 
+/* Exact outer volume (Sec. 3, Eq. 4), the evaluator without quadrature or
+ * jitter: for every box, V_box minus the volume of the solid inside it, found
+ * by the divergence theorem along the box's local axis `axis` (0, 1 or 2) in
+ * float64.  Each triangle's projection on the face perpendicular to `axis` is
+ * clipped to the face rectangle, split by the two slab planes and its depth,
+ * clamped to the slab, integrated over the pieces, with the sign of the
+ * projected triangle's orientation.  Exact up to float64 rounding on closed,
+ * consistently oriented meshes (the value is the same along every axis);
+ * summed in a fixed order (bitwise deterministic).
+ *
+ * mesh     host struct, device arrays (as obbv_outer_volume)
+ * boxes    device, [n_boxes] obbv_box, 0 <= n_boxes <= 65,535
+ * out_obv  device, [n_boxes] float64
+ * A box with a zero extent gets OBV 0; a box with a non-finite parameter or a
+ * negative extent gets NaN and sets OBBV_STATUS_NAN_BOX; a triangle with an
+ * out-of-range index sets OBBV_STATUS_BAD_INDEX and counts as absent.  Work is
+ * O(n_boxes x n_triangles); scratch 8 bytes per box and 4,096 triangles.
+ * Stream ordered. */
+int obbv_outer_volume_exact(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t axis,
+                            double* out_obv, void* stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): obbv_outer_volume for one
  * mesh with every scratch byte in a fixed 32 MiB device array of the library

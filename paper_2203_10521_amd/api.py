@@ -118,6 +118,19 @@ def outer_volume_ex(V, F, boxes, R, seed=0, axis_mask=7, block_rays=0, box_key=N
     return {"obv": obv, "vin_axis": vin, "ray_q": rq, "ray_hits": rh, "side": side}
 
 
+def outer_volume_exact(V, F, boxes, axis=0, out=None, stream=None):
+    """obbv_outer_volume_exact: exact OBV of every box along local axis `axis`
+    (clipped-prism integral in float64); float64 tensor [n_boxes]."""
+    _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
+    n = boxes.shape[0]
+    m = mesh_struct(V, F)
+    obv = out if out is not None else torch.empty(n, dtype=torch.float64, device=boxes.device)
+    _dev(obv, torch.float64, "out")
+    _check(_lib.lib().obbv_outer_volume_exact(ctypes.byref(m), _ptr(boxes), n, int(axis), _ptr(obv),
+                                              _stream(stream)))
+    return obv
+
+
 def outer_volume_noalloc(V, F, boxes, R, seed=0, axis_mask=7, block_rays=0, box_key=None, out=None, status=None,
                          stream=None):
     """obbv_outer_volume_noalloc: OBV of every box with the library's fixed

@@ -52,10 +52,11 @@ enum PoolSlot {
   kPoolRank = 6,
   kPoolMesh = 7,   // mesh validation: edge table and counters
   kPoolFrameCnt = 8,  // (frame, axis) list counters of one-pass grouped calls (zero between calls)
-  kPoolCount = 9
+  kPoolExact = 9,     // per-(box, triangle chunk) partial sums of the exact evaluator
+  kPoolCount = 10
 };
-// Two sets of the slots: calls that may run at the same time on different
-// streams take their scratch from different sets (slot + set * kPoolCount).
+// Sets of the slots: calls that may run at the same time on different streams
+// take their scratch from different sets (slot + set * kPoolCount).
 constexpr int kPoolSets = 8;
 
 // Ensures slot `slot` (< kPoolCount * kPoolSets) of the current device holds at
