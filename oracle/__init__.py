@@ -9,10 +9,12 @@ written from the paper's statement of the problem:
                  integration along each ray (Sec. 4.1, Eq. 9 generalised);
 * ``fit``     -- area-weighted covariance OBB of a triangle cluster;
 * ``rng``     -- SplitMix64, the counter-based generator both sides implement
-                 from its publication to draw the ray jitter.
+                 from its publication to draw the ray jitter;
+* ``collision`` -- synthetic sphere queries against a box hierarchy (tests and
+                 hits), the stand-in for the paper's collision experiment.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  It shares no code with the HIP library
 and never imports it; inputs come from ``synth`` or from the caller.
 """
-from . import rng, geometry, exact, raygrid, fit  # noqa: F401
+from . import rng, geometry, exact, raygrid, fit, collision  # noqa: F401
