@@ -27,6 +27,11 @@ Other objects of the line:
                 triangle helix's 5,461-node covariance tree (R 256 -> 32)
   obb_tree      per-layer sum of OBV of the built hierarchy vs the top-down
                 covariance tree (the paper's Fig. 6 comparison)
+  exact_evaluator  the exact clipped-prism evaluator on the hierarchy's boxes:
+                calls per second and the estimator's deviation from it
+  collision_queries  synthetic sphere queries against the built hierarchy and
+                the covariance tree: sphere-box tests per query (the paper's
+                collision experiment counts such tests)
   surrogate     the ranker trained on 1.05 M exact outer fractions of the batched
                 workload's spheres 0-223, validated on 224-255 against the
                 occupancy estimate (MAE, top-1 of flood-candidate groups); then
@@ -145,6 +150,65 @@ def leg_config1(api, torch):
     B = torch.from_numpy(synth.boxes_to_array(c, a, h)).cuda()
     res = timed_profile(api, torch, lambda: api.outer_volume(Vt, Ft, B, 32, seed=13), 50)
     return leg_object(64, 50, *res, workload="icosphere 1,280 triangles, 64 random boxes, R=32")
+
+
+def exact_evaluator_leg(api, torch, Vt, Ft, boxes, R, seed):
+    """The exact evaluator (clipped-prism integral, float64) on the built
+    hierarchy's boxes against the torus, next to the estimator of the hot path
+    on the same boxes: calls per second and the estimator's deviation."""
+    B = torch.from_numpy(np.ascontiguousarray(boxes)).cuda()
+    n = B.shape[0]
+    api.outer_volume_exact(Vt, Ft, B, axis=0)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ex = api.outer_volume_exact(Vt, Ft, B, axis=0)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    est = api.outer_volume(Vt, Ft, B, R, seed=seed)
+    torch.cuda.synchronize()
+    e, x = est.cpu().numpy(), ex.cpu().numpy()
+    h = boxes[:, 12:15].astype(np.float64)
+    vb = 8.0 * h[:, 0] * h[:, 1] * h[:, 2]
+    ok = vb > 0
+    dev = np.abs(e - x)[ok] / vb[ok]
+    return {"n_boxes": int(n), "ms_per_call": 1e3 * dt, "evals_per_s": n / dt,
+            "pair_tests_per_s": n * int(Ft.shape[0]) / dt,
+            "estimator_R": R, "estimator_dev_mean": float(dev.mean()), "estimator_dev_max": float(dev.max()),
+            "workload": "the built torus hierarchy's boxes, 65,536 triangles, cast axis 0, float64"}
+
+
+def collision_leg(api, torch, V, Vt, Ft, out, hp, n_spheres=65536):
+    """Synthetic collision queries (the stand-in for the paper's collision
+    experiment): the same spheres against the built hierarchy and the top-down
+    covariance tree; sphere-box tests per query and queries per second."""
+    import synth
+    L, b = hp["levels"], hp["branching"]
+    tree = api.build_obb_tree(Vt, Ft, L, b)
+    S = torch.from_numpy(synth.query_spheres(V, n_spheres, seed=77)).cuda()
+    res = {}
+    for name, boxes, tri_node in (("hierarchy", out["boxes"], out["tri_node"]),
+                                  ("obb_tree", tree["boxes"], tree["tri_node"])):
+        used = np.zeros(len(boxes), np.uint8)
+        ids = tri_node[tri_node >= 0]
+        used[ids] = 1
+        B = torch.from_numpy(np.ascontiguousarray(boxes)).cuda()
+        U = torch.from_numpy(used).cuda()
+        api.collision_queries(B, L, b, S, node_used=U)
+        torch.cuda.synchronize()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tests, hits = api.collision_queries(B, L, b, S, node_used=U)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"tests_per_query": float(tests.double().mean()), "hits_per_query": float(hits.double().mean()),
+                     "queries_per_s": n_spheres / dt}
+    res["tests_ratio"] = res["hierarchy"]["tests_per_query"] / res["obb_tree"]["tests_per_query"]
+    res["workload"] = (f"{n_spheres} spheres, centres uniform in the torus's bounding box grown by 20 %, radii "
+                       "log-uniform in 1-20 % of its diagonal; 4 levels, branching 4")
+    return res
 
 
 def leg_config3(api, torch):
@@ -555,6 +619,8 @@ def main():
     if not args.no_legs:
         log("tree comparison, config 1 / 3 / 4 legs")
         result["obb_tree"] = obb_tree_comparison(api, torch, Vt, Ft, out, hp)
+        result["exact_evaluator"] = exact_evaluator_leg(api, torch, Vt, Ft, out["boxes"], hp["R"], hp["seed"])
+        result["collision_queries"] = collision_leg(api, torch, V, Vt, Ft, out, hp)
         result["legs"] = {"config1": leg_config1(api, torch), "config3": leg_config3(api, torch),
                           "config4": leg_config4(api, torch)}
     if not args.no_surrogate:

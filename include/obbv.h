@@ -204,6 +204,28 @@ int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, cons
 int obbv_outer_volume_exact(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t axis,
                             double* out_obv, void* stream);
 
+/* Synthetic collision queries, the stand-in for the paper's collision
+ * experiment (Sec. 5: colliders against a model's hierarchy, counting
+ * bounding-volume tests).  For every sphere the hierarchy is descended from
+ * the root: a node is tested against the sphere (float64: the squared distance
+ * from the centre to the box in its frame, sum_k max(|Q_k . (x - c)| - h_k,
+ * 0)^2, against r^2); when the sphere overlaps it and it has children, they are
+ * tested in order; an overlapped leaf is a hit.  Unused nodes are not tested.
+ *
+ * nodes      device, [n_nodes] obbv_box in level order: level l holds
+ *            branching^l nodes, node j of level l has children branching*j ..
+ *            branching*j + branching - 1 of level l + 1 (the layout of
+ *            obbv_build_hierarchy and obbv_build_obb_tree)
+ * node_used  device, [n_nodes] uint8, nullable (every node used)
+ * levels     1..16; branching 1..64
+ * spheres    device, [n_spheres][4] float32 (centre xyz, radius), 16-byte aligned
+ * out_tests  device, [n_spheres] int32: sphere-box tests of each query
+ * out_hits   device, [n_spheres] int32: overlapped leaves of each query
+ * Stream ordered; no scratch. */
+int obbv_collision_queries(const obbv_box* nodes, const uint8_t* node_used, int32_t levels, int32_t branching,
+                           const float* spheres, int32_t n_spheres, int32_t* out_tests, int32_t* out_hits,
+                           void* stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): obbv_outer_volume for one
  * mesh with every scratch byte in a fixed 32 MiB device array of the library

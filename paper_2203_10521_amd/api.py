@@ -131,6 +131,26 @@ def outer_volume_exact(V, F, boxes, axis=0, out=None, stream=None):
     return obv
 
 
+def collision_queries(nodes, levels, branching, spheres, node_used=None, stream=None):
+    """obbv_collision_queries: (tests, hits) int32 tensors [n_spheres] of sphere
+    queries descending a level-order box hierarchy."""
+    _dev(nodes, torch.float32, "nodes", (BOX_FLOATS,))
+    _dev(spheres, torch.float32, "spheres", (4,))
+    n_nodes = sum(int(branching) ** lv for lv in range(int(levels)))
+    if nodes.shape[0] != n_nodes:
+        raise ValueError(f"nodes must hold the {n_nodes} nodes of {levels} levels of branching {branching}")
+    if node_used is not None:
+        _dev(node_used, torch.uint8, "node_used")
+        if node_used.shape != (n_nodes,):
+            raise ValueError(f"node_used must have shape [{n_nodes}]")
+    n = spheres.shape[0]
+    tests = torch.empty(n, dtype=torch.int32, device=spheres.device)
+    hits = torch.empty(n, dtype=torch.int32, device=spheres.device)
+    _check(_lib.lib().obbv_collision_queries(_ptr(nodes), _ptr(node_used), int(levels), int(branching),
+                                             _ptr(spheres), n, _ptr(tests), _ptr(hits), _stream(stream)))
+    return tests, hits
+
+
 def outer_volume_noalloc(V, F, boxes, R, seed=0, axis_mask=7, block_rays=0, box_key=None, out=None, status=None,
                          stream=None):
     """obbv_outer_volume_noalloc: OBV of every box with the library's fixed

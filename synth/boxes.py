@@ -110,3 +110,17 @@ def flood_candidates(V, F, n_groups, seed, k=8, patch=48, reach=6):
         cand.append([np.concatenate([c.astype(np.float32), Q.reshape(-1).astype(np.float32),
                                      _f32_up(np.maximum(loc[i], h))]) for i in pick])
     return np.array(base, np.float32).reshape(-1, 15), np.array(cand, np.float32).reshape(-1, k, 15)
+
+
+def query_spheres(V, n, seed, r_lo=0.01, r_hi=0.2):
+    """[n, 4] float32 spheres (centre, radius) for collision queries: centres
+    uniform in the mesh's bounding box grown by 20 % on every side, radii
+    log-uniform in [r_lo, r_hi] times the box diagonal."""
+    V = np.asarray(V, np.float64)
+    lo, hi = V.min(axis=0), V.max(axis=0)
+    pad = 0.2 * (hi - lo)
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(lo - pad, hi + pad, size=(n, 3))
+    diag = float(np.linalg.norm(hi - lo))
+    r = np.exp(rng.uniform(np.log(r_lo), np.log(r_hi), size=n)) * diag
+    return np.concatenate([c, r[:, None]], axis=1).astype(np.float32)
