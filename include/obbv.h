@@ -204,6 +204,30 @@ int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, cons
 int obbv_outer_volume_exact(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t axis,
                             double* out_obv, void* stream);
 
+/* The paper's central-projection estimator of the outer volume (Sec. 4.1,
+ * Eq. 9-10): rays leave the box centre through the pixel centres of a
+ * 6 x m x m cube map in the box frame; each pixel is a cone of directions of
+ * its exact solid angle W.  A ray's crossings of the mesh (watertight test,
+ * one owner for points on a shared edge) give the cone's outer volume
+ * (r_e^3 - sum_k s_k min(r_k, r_e)^3) W / 3, r_e the distance at which the ray
+ * leaves the box, r_k the crossing distances, s_k = +1 where the ray leaves the
+ * solid and -1 where it enters (crossings beyond the box count as reaching
+ * it); OBV is the sum over the cones.  A box inside the solid gives 0 exactly;
+ * the estimate tends to the exact outer volume as m grows.  float64, fixed
+ * summation order (bitwise deterministic).
+ *
+ * mesh     host struct, device arrays (as obbv_outer_volume)
+ * boxes    device, [n_boxes] obbv_box, 0 <= n_boxes <= 65,535
+ * m        pixels per cube-map face side, 1..256
+ * out_obv  device, [n_boxes] float64
+ * A box with a non-finite parameter or a negative extent gets NaN and sets
+ * OBBV_STATUS_NAN_BOX; a triangle with an out-of-range index sets
+ * OBBV_STATUS_BAD_INDEX and counts as absent.  Work is O(n_boxes x 6 m^2 x
+ * n_triangles) (every triangle is tested against every ray); scratch 8 bytes
+ * per box and 256 rays.  Stream ordered. */
+int obbv_outer_volume_central(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t m,
+                              double* out_obv, void* stream);
+
 /* Synthetic collision queries, the stand-in for the paper's collision
  * experiment (Sec. 5: colliders against a model's hierarchy, counting
  * bounding-volume tests).  For every sphere the hierarchy is descended from

@@ -74,6 +74,7 @@ SIGNATURES = {
     "obbv_profile_enable": (c_int32, [c_int32]),
     "obbv_collision_queries": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_int32, c_void_p,
                                          c_void_p, c_void_p]),
+    "obbv_outer_volume_central": (c_int32, [ctypes.POINTER(ObbvMesh), c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "obbv_outer_volume_exact": (c_int32, [ctypes.POINTER(ObbvMesh), c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "obbv_profile_read": (c_int32, [c_double_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_int64), c_double_p]),

@@ -131,6 +131,19 @@ def outer_volume_exact(V, F, boxes, axis=0, out=None, stream=None):
     return obv
 
 
+def outer_volume_central(V, F, boxes, m, out=None, stream=None):
+    """obbv_outer_volume_central: the central-projection estimate of every box's
+    OBV with a 6 x m x m cube map; float64 tensor [n_boxes]."""
+    _dev(boxes, torch.float32, "boxes", (BOX_FLOATS,))
+    n = boxes.shape[0]
+    mm = mesh_struct(V, F)
+    obv = out if out is not None else torch.empty(n, dtype=torch.float64, device=boxes.device)
+    _dev(obv, torch.float64, "out")
+    _check(_lib.lib().obbv_outer_volume_central(ctypes.byref(mm), _ptr(boxes), n, int(m), _ptr(obv),
+                                                _stream(stream)))
+    return obv
+
+
 def collision_queries(nodes, levels, branching, spheres, node_used=None, stream=None):
     """obbv_collision_queries: (tests, hits) int32 tensors [n_spheres] of sphere
     queries descending a level-order box hierarchy."""

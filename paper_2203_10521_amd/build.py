@@ -33,9 +33,16 @@ def hipcc():
     return exe
 
 
+# Sources whose float64 arithmetic follows an oracle's order of operations one
+# rounding at a time: no fused multiply-adds anywhere in the translation unit
+# (the rounded-operation intrinsics are plain operators the compiler may fuse).
+NO_CONTRACT = {"exact.hip", "central.hip", "collision.hip"}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
+    extra = ["-ffp-contract=off"] if os.path.basename(src) in NO_CONTRACT else []
+    cmd = [hipcc(), *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l
                     and "warning generated" not in l and "warnings generated" not in l)

@@ -9,6 +9,9 @@
 
 #include "common.h"
 
+// Built with -ffp-contract=off (build.py): every operation rounds on its own,
+// in the order the oracle follows.
+
 namespace obbv {
 namespace {
 

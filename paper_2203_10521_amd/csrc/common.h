@@ -53,7 +53,8 @@ enum PoolSlot {
   kPoolMesh = 7,   // mesh validation: edge table and counters
   kPoolFrameCnt = 8,  // (frame, axis) list counters of one-pass grouped calls (zero between calls)
   kPoolExact = 9,     // per-(box, triangle chunk) partial sums of the exact evaluator
-  kPoolCount = 10
+  kPoolCentral = 10,  // per-(box, ray chunk) partial sums of the central-projection estimator
+  kPoolCount = 11
 };
 // Sets of the slots: calls that may run at the same time on different streams
 // take their scratch from different sets (slot + set * kPoolCount).
