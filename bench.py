@@ -28,7 +28,8 @@ Other objects of the line:
   obb_tree      per-layer sum of OBV of the built hierarchy vs the top-down
                 covariance tree (the paper's Fig. 6 comparison)
   exact_evaluator  the exact clipped-prism evaluator on the hierarchy's boxes:
-                calls per second and the estimator's deviation from it
+                calls per second and the deviation from it of the hot path's
+                estimator and of the paper's central-projection estimator
   collision_queries  synthetic sphere queries against the built hierarchy and
                 the covariance tree: sphere-box tests per query (the paper's
                 collision experiment counts such tests)
@@ -173,9 +174,21 @@ def exact_evaluator_leg(api, torch, Vt, Ft, boxes, R, seed):
     vb = 8.0 * h[:, 0] * h[:, 1] * h[:, 2]
     ok = vb > 0
     dev = np.abs(e - x)[ok] / vb[ok]
+    # the paper's central-projection estimator on the same boxes (cube map 6 x 32 x 32)
+    m = 32
+    api.outer_volume_central(Vt, Ft, B[:1], m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cp = api.outer_volume_central(Vt, Ft, B, m)
+    torch.cuda.synchronize()
+    dtc = time.perf_counter() - t0
+    cdev = np.abs(cp.cpu().numpy() - x)[ok] / vb[ok]
     return {"n_boxes": int(n), "ms_per_call": 1e3 * dt, "evals_per_s": n / dt,
             "pair_tests_per_s": n * int(Ft.shape[0]) / dt,
             "estimator_R": R, "estimator_dev_mean": float(dev.mean()), "estimator_dev_max": float(dev.max()),
+            "central_m": m, "central_ms_per_call": 1e3 * dtc, "central_evals_per_s": n / dtc,
+            "central_ray_tests_per_s": n * 6 * m * m * int(Ft.shape[0]) / dtc,
+            "central_dev_mean": float(cdev.mean()), "central_dev_max": float(cdev.max()),
             "workload": "the built torus hierarchy's boxes, 65,536 triangles, cast axis 0, float64"}
 
 
