@@ -78,3 +78,44 @@ def test_collision_all_nodes_used_and_edge_sizes(api, hierarchies):
     assert t0.numel() == 0 and h0.numel() == 0
     with pytest.raises(ValueError):
         api.collision_queries(torch.from_numpy(boxes[:-1].copy()).cuda(), L, b, torch.from_numpy(S).cuda())
+
+
+def test_collision_on_random_nested_trees(api):
+    """Random trees whose children lie inside their parents, some nodes unused,
+    3 to 4 levels and branching 2 to 5: every query's tests and hits equal the
+    oracle's."""
+    import torch
+    rng = np.random.default_rng(4)
+    I3 = np.eye(3)
+    for levels, b in ((3, 5), (4, 2), (4, 3)):
+        rows = [np.concatenate([[0.0, 0.0, 0.0], I3.reshape(-1), [1.0, 1.0, 1.0]])]
+        used = [True]
+        base, n = 0, 1
+        for l in range(1, levels):
+            for j in range(n):
+                pc, ph = rows[base + j][0:3], rows[base + j][12:15]
+                for k in range(b):
+                    lo = pc[0] - ph[0] + 2 * ph[0] * k / b
+                    hx = ph[0] / b * rng.uniform(0.4, 1.0)
+                    cx = lo + ph[0] / b
+                    hy, hz = ph[1] * rng.uniform(0.3, 1.0), ph[2] * rng.uniform(0.3, 1.0)
+                    cy = pc[1] + rng.uniform(-(ph[1] - hy), ph[1] - hy)
+                    cz = pc[2] + rng.uniform(-(ph[2] - hz), ph[2] - hz)
+                    rows.append(np.concatenate([[cx, cy, cz], I3.reshape(-1), [hx, hy, hz]]))
+                    used.append(bool(used[base + j]) and rng.uniform() > 0.15)
+            base += n
+            n *= b
+        flat = np.array(rows, np.float32)
+        u = np.array(used, np.uint8)
+        S = np.concatenate([rng.uniform(-1.3, 1.3, (500, 3)), rng.uniform(0.0, 0.5, (500, 1))], axis=1)
+        S = S.astype(np.float32)
+        tests, hits = api.collision_queries(torch.from_numpy(flat).cuda(), levels, b, torch.from_numpy(S).cuda(),
+                                            node_used=torch.from_numpy(u).cuda())
+        bl = collision.boxes_by_level(flat.astype(np.float64), levels, b)
+        ul, base = [], 0
+        for l in range(levels):
+            ul.append([bool(x) for x in u[base:base + b ** l]])
+            base += b ** l
+        ot, oh = collision.queries(levels, b, bl, ul, S.astype(np.float64))
+        assert np.array_equal(tests.cpu().numpy(), np.array(ot, np.int32)), (levels, b)
+        assert np.array_equal(hits.cpu().numpy(), np.array(oh, np.int32)), (levels, b)

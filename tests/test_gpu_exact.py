@@ -126,3 +126,27 @@ def test_estimator_converges_to_the_exact_evaluator(api):
         if R == 128:
             assert np.all(np.abs(est - ex) <= 5e-3 * vb)
     assert err[128] < err[32]
+
+
+def test_exact_evaluator_faces_in_the_box_planes(api):
+    """A cuboid solid and boxes whose faces lie exactly in the solid's face
+    planes (the slab's top or bottom plane holds mesh triangles, and face
+    rectangles share edges with them): the device follows the oracle's rule for
+    pieces lying in the top plane and both give the exact volume of the
+    intersection of the two boxes."""
+    V, F = synth.cuboid(half=(0.5, 0.375, 0.25), center=(0.0, 0.0, 0.0))
+    I3 = np.eye(3, dtype=np.float32)
+    c = np.array([[0.0, 0.0, 0.125], [0.25, 0.0, 0.0], [0.0, -0.125, -0.125], [0.125, 0.125, 0.0]], np.float32)
+    h = np.array([[0.25, 0.25, 0.125], [0.25, 0.375, 0.25], [0.5, 0.25, 0.125], [0.375, 0.25, 0.5]], np.float32)
+    a = np.repeat(I3[None], len(c), axis=0)
+    B = _t(synth.boxes_to_array(c, a, h))
+    lo_s, hi_s = np.array([-0.5, -0.375, -0.25]), np.array([0.5, 0.375, 0.25])
+    for w in range(3):
+        got = api.outer_volume_exact(_t(V), _t(F), B, axis=w).cpu().numpy()
+        for i in range(len(c)):
+            lo = np.maximum(c[i] - h[i], lo_s)
+            hi = np.minimum(c[i] + h[i], hi_s)
+            inter = float(np.prod(np.clip(hi - lo, 0.0, None)))
+            want = exact.box_volume(h[i]) - inter
+            assert abs(got[i] - want) <= 1e-12, (w, i, got[i], want)
+            assert abs(got[i] - exact.obv(V, F, c[i], a[i], h[i].astype(np.float64), axis=w)) <= 1e-12
