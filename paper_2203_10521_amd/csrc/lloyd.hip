@@ -34,6 +34,7 @@
 #include <numeric>
 #include <queue>
 #include <string>
+#include <stdexcept>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -1687,8 +1688,13 @@ static int flood_split(LloydState& S, const std::vector<Group>& groups, Partitio
         return;
       }
       PartitionIO iok{io.boxes, io.obv, io.slot, &ebx[k]};
-      rcx[k] = flood_partition(S.M, S.E, pg[k + 1], iok, S.K, S.evx[k], cx[k], S.pred.on ? &S.predx[k] : nullptr);
-      if (rcx[k] != OBBV_OK) errx[k] = obbv_last_error();
+      try {  // nothing may leave a thread: a failure becomes the part's return code
+        rcx[k] = flood_partition(S.M, S.E, pg[k + 1], iok, S.K, S.evx[k], cx[k], S.pred.on ? &S.predx[k] : nullptr);
+        if (rcx[k] != OBBV_OK) errx[k] = obbv_last_error();
+      } catch (const std::exception& ex) {
+        rcx[k] = OBBV_ERR_OOM;
+        errx[k] = std::string("flood thread: ") + ex.what();
+      }
     });
   const int rc0 = flood_partition(S.M, S.E, pg[0], io, S.K, S.ev, S.cnt, &S.pred);
   for (std::thread& t : th) t.join();
