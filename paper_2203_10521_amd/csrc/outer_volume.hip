@@ -6,9 +6,11 @@
 //   k_mesh_centre        centre of every mesh's bounding box (unless the caller
 //                        gives it): every cast keeps the half prism on the far
 //                        side of its box from it
-//   [k_frame_cull x 2,   boxes grouped by shared centre and axes: per (group,
-//    k_frame_scan]       cast axis), the frame-local coordinates of the triangles
-//                        in the group's kept half prism
+//   [k_frame_list]       boxes grouped by shared centre and axes: per (group,
+//                        cast axis), the frame-local coordinates of the triangles
+//                        in the group's kept half prism, in one pass into
+//                        fixed segments (lists beyond 2 GB: k_frame_cull
+//                        counts, k_frame_scan sizes, k_frame_cull fills)
 //   k_span_bounds        single-mesh calls on meshes of more than one cast item
 //                        (unless the caller has them): the bounding box of every
 //                        span of 256 consecutive triangles and of every run of 18
@@ -28,9 +30,11 @@
 //                        with their bounding cell range; the jittered rays of that
 //                        range go to LDS; each lane builds one survivor's FP32
 //                        edge and depth planes in registers and tests the rays of
-//                        the cells its projected bounding box covers (records
-//                        covering many cells are queued in LDS and tested
-//                        wave-wide); the exact integer inside lengths are summed
+//                        the cells its projected bounding box covers (waves
+//                        take chunks of 64 survivors from an LDS cursor;
+//                        records covering many cells are broadcast from their
+//                        lane and tested by the whole wave, one cell per lane);
+//                        the exact integer inside lengths are summed
 //                        per lane, per workgroup, then into the (box, axis) int64
 //                        sum
 //   k_finalize           float64 OBV per box, publication of the call
