@@ -16,6 +16,12 @@
  * - The caller owns every buffer it passes and the library never frees caller
  *   memory.  Scratch memory is a per-device library pool, grown on demand and
  *   returned to HIP by obbv_release().
+ * - Calls that take scratch from the pool share it: on one device, issue them
+ *   on one stream (or order them), from one host thread at a time.  Calls that
+ *   overlap in time (several streams, several threads) race on the pool.  A
+ *   planned launch (obbv_ov_plan_launch) uses only its plan's memory; the
+ *   Lloyd driver splits its floods over streams of its own with a separate
+ *   part of the pool for each.
  * - Meshes are closed, consistently oriented triangle meshes (Sec. 6 of the paper:
  *   the method handles solid models only): every directed edge (a, b) occurs
  *   once and its reverse (b, a) once; triangles are counter-clockwise seen from
@@ -43,9 +49,11 @@ extern "C" {
                                            enclosed volume is not positive       */
 #define OBBV_ERR_DEGENERATE (-4)      /* nothing to compute (e.g. empty cluster) */
 #define OBBV_ERR_WORKSPACE (-5)       /* scratch limit exceeded                  */
-#define OBBV_ERR_OOM (-6)             /* hipMalloc failed                        */
+#define OBBV_ERR_OOM (-6)             /* hipMalloc or a host allocation failed   */
 #define OBBV_ERR_HIP (-7)             /* a HIP runtime call failed               */
 #define OBBV_ERR_UNSUPPORTED (-8)     /* option not available on this device     */
+#define OBBV_ERR_INTERNAL (-9)        /* unexpected host-side failure (a thread
+                                         that could not start, ...)              */
 
 /* ---- device status word bits (obbv_status) ---------------------------- */
 #define OBBV_STATUS_NAN_BOX 0x1u      /* a box had a non-finite parameter        */

@@ -222,7 +222,13 @@ int outer_volume_central(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n
 
 }  // namespace obbv
 
+static int obbv_outer_volume_central_body(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t m,
+                                         double* out_obv, void* stream);
 extern "C" int obbv_outer_volume_central(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t m,
+                                         double* out_obv, void* stream) {
+  return obbv::guarded([&] { return obbv_outer_volume_central_body(mesh, boxes, n_boxes, m, out_obv, stream); });
+}
+static int obbv_outer_volume_central_body(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t m,
                                          double* out_obv, void* stream) {
   obbv::clear_error();
   return obbv::outer_volume_central(mesh, boxes, n_boxes, m, out_obv, (hipStream_t)stream);

@@ -101,7 +101,15 @@ int collision_queries(const obbv_box* nodes, const uint8_t* node_used, int32_t l
 
 }  // namespace obbv
 
+static int obbv_collision_queries_body(const obbv_box* nodes, const uint8_t* node_used, int32_t levels,
+                                      int32_t branching, const float* spheres, int32_t n_spheres, int32_t* out_tests,
+                                      int32_t* out_hits, void* stream);
 extern "C" int obbv_collision_queries(const obbv_box* nodes, const uint8_t* node_used, int32_t levels,
+                                      int32_t branching, const float* spheres, int32_t n_spheres, int32_t* out_tests,
+                                      int32_t* out_hits, void* stream) {
+  return obbv::guarded([&] { return obbv_collision_queries_body(nodes, node_used, levels, branching, spheres, n_spheres, out_tests, out_hits, stream); });
+}
+static int obbv_collision_queries_body(const obbv_box* nodes, const uint8_t* node_used, int32_t levels,
                                       int32_t branching, const float* spheres, int32_t n_spheres, int32_t* out_tests,
                                       int32_t* out_hits, void* stream) {
   obbv::clear_error();

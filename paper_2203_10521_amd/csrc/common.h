@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 
 #include "obbv.h"
@@ -32,6 +34,33 @@ void clear_error();
       return OBBV_ERR_INVALID_ARG;                                              \
     }                                                                           \
   } while (0)
+
+// Runs the body of a C entry point: a C++ exception (a failed host
+// allocation, a thread that could not start) becomes an error code and a
+// message, so that no exception crosses the C ABI.
+template <class F>
+int guarded(F&& body) noexcept {
+  const char* msg = "internal error";
+  int code = OBBV_ERR_INTERNAL;
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    msg = "host memory allocation failed";
+    code = OBBV_ERR_OOM;
+  } catch (const std::exception& e) {
+    try {
+      set_error(std::string("internal error: ") + e.what());
+      return OBBV_ERR_INTERNAL;
+    } catch (...) {
+    }
+  } catch (...) {
+  }
+  try {
+    set_error(msg);
+  } catch (...) {
+  }
+  return code;
+}
 
 #define OBBV_RET(call)                                                          \
   do {                                                                          \

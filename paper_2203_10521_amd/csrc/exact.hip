@@ -239,7 +239,13 @@ int outer_volume_exact(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_b
 
 }  // namespace obbv
 
+static int obbv_outer_volume_exact_body(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t axis,
+                                       double* out_obv, void* stream);
 extern "C" int obbv_outer_volume_exact(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t axis,
+                                       double* out_obv, void* stream) {
+  return obbv::guarded([&] { return obbv_outer_volume_exact_body(mesh, boxes, n_boxes, axis, out_obv, stream); });
+}
+static int obbv_outer_volume_exact_body(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n_boxes, int32_t axis,
                                        double* out_obv, void* stream) {
   obbv::clear_error();
   return obbv::outer_volume_exact(mesh, boxes, n_boxes, axis, out_obv, (hipStream_t)stream);

@@ -473,7 +473,13 @@ int fit_impl(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_cluste
 
 }  // namespace obbv
 
+static int obbv_fit_body(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters,
+                        obbv_box* out_boxes, double* out_eigvals, void* stream);
 extern "C" int obbv_fit(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters,
+                        obbv_box* out_boxes, double* out_eigvals, void* stream) {
+  return obbv::guarded([&] { return obbv_fit_body(mesh, tri_cluster, n_clusters, out_boxes, out_eigvals, stream); });
+}
+static int obbv_fit_body(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_clusters,
                         obbv_box* out_boxes, double* out_eigvals, void* stream) {
   obbv::clear_error();
   return obbv::fit_impl(mesh, tri_cluster, n_clusters, out_boxes, out_eigvals, (hipStream_t)stream);

@@ -35,6 +35,8 @@
 #include <queue>
 #include <string>
 #include <stdexcept>
+#include <exception>
+#include <mutex>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -1422,14 +1424,29 @@ void parallel_for(size_t n, Fn fn) {
     for (size_t i = 0; i < n; ++i) fn(i);
     return;
   }
+  // an exception of any share (or a thread that cannot start) is rethrown
+  // here once every started thread has been joined
   std::vector<std::thread> th;
   th.reserve(nt - 1);
-  for (size_t t = 1; t < nt; ++t)
-    th.emplace_back([&, t] {
+  std::exception_ptr err;
+  std::mutex mu;
+  auto run = [&](size_t t) {
+    try {
       for (size_t i = t; i < n; i += nt) fn(i);
-    });
-  for (size_t i = 0; i < n; i += nt) fn(i);
+    } catch (...) {
+      std::lock_guard<std::mutex> lock(mu);
+      if (!err) err = std::current_exception();
+    }
+  };
+  try {
+    for (size_t t = 1; t < nt; ++t) th.emplace_back(run, t);
+  } catch (...) {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!err) err = std::current_exception();
+  }
+  run(0);
   for (auto& x : th) x.join();
+  if (err) std::rethrow_exception(err);
 }
 
 // Update every box with a non-empty vertex set; returns the accepted OBV per box.
@@ -1680,27 +1697,38 @@ static int flood_split(LloydState& S, const std::vector<Group>& groups, Partitio
   int dev = 0;
   OBBV_HIP(hipGetDevice(&dev));
   std::vector<std::thread> th;
+  struct Joiner {  // every started thread is joined, also when this frame unwinds
+    std::vector<std::thread>& t;
+    ~Joiner() {
+      for (std::thread& x : t)
+        if (x.joinable()) x.join();
+    }
+  } joiner{th};
   for (int k = 0; k < nx; ++k)
     th.emplace_back([&, k] {
-      if (hipSetDevice(dev) != hipSuccess) {
-        rcx[k] = OBBV_ERR_HIP;
-        errx[k] = "hipSetDevice failed in a flood thread";
-        return;
-      }
-      PartitionIO iok{io.boxes, io.obv, io.slot, &ebx[k]};
       try {  // nothing may leave a thread: a failure becomes the part's return code
+        if (hipSetDevice(dev) != hipSuccess) {
+          rcx[k] = OBBV_ERR_HIP;
+          errx[k] = "hipSetDevice failed in a flood thread";
+          return;
+        }
+        PartitionIO iok{io.boxes, io.obv, io.slot, &ebx[k]};
         rcx[k] = flood_partition(S.M, S.E, pg[k + 1], iok, S.K, S.evx[k], cx[k], S.pred.on ? &S.predx[k] : nullptr);
         if (rcx[k] != OBBV_OK) errx[k] = obbv_last_error();
-      } catch (const std::exception& ex) {
+      } catch (const std::bad_alloc&) {
         rcx[k] = OBBV_ERR_OOM;
-        errx[k] = std::string("flood thread: ") + ex.what();
+      } catch (...) {
+        rcx[k] = OBBV_ERR_INTERNAL;
       }
     });
   const int rc0 = flood_partition(S.M, S.E, pg[0], io, S.K, S.ev, S.cnt, &S.pred);
-  for (std::thread& t : th) t.join();
+  for (std::thread& t : th) t.join();  // (an exception above is joined by `joiner`)
   for (int k = 0; k < nx; ++k)
     if (rcx[k] != OBBV_OK) {
-      set_error(errx[k]);
+      if (!errx[k].empty())
+        set_error(errx[k]);
+      else
+        set_error(rcx[k] == OBBV_ERR_OOM ? "flood thread: host memory allocation failed" : "flood thread: internal error");
       return rcx[k];
     }
   OBBV_RET(rc0);
@@ -1863,7 +1891,11 @@ static int lloyd_adjust(LloydState& S, int32_t* out_accepted) {
 
 using namespace obbv;
 
+static int obbv_lloyd_create_body(const obbv_mesh* mesh, const obbv_lloyd_params* p, obbv_lloyd** out);
 extern "C" int obbv_lloyd_create(const obbv_mesh* mesh, const obbv_lloyd_params* p, obbv_lloyd** out) {
+  return obbv::guarded([&] { return obbv_lloyd_create_body(mesh, p, out); });
+}
+static int obbv_lloyd_create_body(const obbv_mesh* mesh, const obbv_lloyd_params* p, obbv_lloyd** out) {
   clear_error();
   OBBV_ARG(mesh && p && out, "NULL argument");
   OBBV_ARG(p->R >= 1 && p->R <= 32767, "R must be in [1, 32767]");
@@ -1891,7 +1923,13 @@ extern "C" int obbv_lloyd_create(const obbv_mesh* mesh, const obbv_lloyd_params*
   return OBBV_OK;
 }
 
+static int obbv_lloyd_set_groups_body(obbv_lloyd* st, int32_t n_boxes, const int32_t* tri_group,
+                                     const int32_t* box_group, const float* boxes, const uint32_t* box_slot);
 extern "C" int obbv_lloyd_set_groups(obbv_lloyd* st, int32_t n_boxes, const int32_t* tri_group,
+                                     const int32_t* box_group, const float* boxes, const uint32_t* box_slot) {
+  return obbv::guarded([&] { return obbv_lloyd_set_groups_body(st, n_boxes, tri_group, box_group, boxes, box_slot); });
+}
+static int obbv_lloyd_set_groups_body(obbv_lloyd* st, int32_t n_boxes, const int32_t* tri_group,
                                      const int32_t* box_group, const float* boxes, const uint32_t* box_slot) {
   clear_error();
   OBBV_ARG(st && tri_group && box_group && boxes, "NULL argument");
@@ -1922,7 +1960,11 @@ extern "C" int obbv_lloyd_set_groups(obbv_lloyd* st, int32_t n_boxes, const int3
   return OBBV_OK;
 }
 
+static int obbv_lloyd_step_body(obbv_lloyd* st, void* stream);
 extern "C" int obbv_lloyd_step(obbv_lloyd* st, void* stream) {
+  return obbv::guarded([&] { return obbv_lloyd_step_body(st, stream); });
+}
+static int obbv_lloyd_step_body(obbv_lloyd* st, void* stream) {
   clear_error();
   OBBV_ARG(st, "NULL state");
   LloydState& S = *reinterpret_cast<LloydState*>(st);
@@ -1932,7 +1974,11 @@ extern "C" int obbv_lloyd_step(obbv_lloyd* st, void* stream) {
   return lloyd_iterate(S);
 }
 
+static int obbv_lloyd_adjust_body(obbv_lloyd* st, int32_t* out_accepted, void* stream);
 extern "C" int obbv_lloyd_adjust(obbv_lloyd* st, int32_t* out_accepted, void* stream) {
+  return obbv::guarded([&] { return obbv_lloyd_adjust_body(st, out_accepted, stream); });
+}
+static int obbv_lloyd_adjust_body(obbv_lloyd* st, int32_t* out_accepted, void* stream) {
   clear_error();
   OBBV_ARG(st, "NULL state");
   LloydState& S = *reinterpret_cast<LloydState*>(st);
@@ -1942,7 +1988,11 @@ extern "C" int obbv_lloyd_adjust(obbv_lloyd* st, int32_t* out_accepted, void* st
   return lloyd_adjust(S, out_accepted);
 }
 
+static int obbv_lloyd_set_surrogate_body(obbv_lloyd* st, const obbv_surrogate* sur);
 extern "C" int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* sur) {
+  return obbv::guarded([&] { return obbv_lloyd_set_surrogate_body(st, sur); });
+}
+static int obbv_lloyd_set_surrogate_body(obbv_lloyd* st, const obbv_surrogate* sur) {
   clear_error();
   OBBV_ARG(st, "NULL state");
   LloydState& S = *reinterpret_cast<LloydState*>(st);
@@ -1964,7 +2014,13 @@ extern "C" int obbv_lloyd_set_surrogate(obbv_lloyd* st, const obbv_surrogate* su
   return OBBV_OK;
 }
 
+static int obbv_lloyd_get_body(obbv_lloyd* st, int32_t* tri_box, float* boxes, double* obv, double* layer_error,
+                              int64_t* counters);
 extern "C" int obbv_lloyd_get(obbv_lloyd* st, int32_t* tri_box, float* boxes, double* obv, double* layer_error,
+                              int64_t* counters) {
+  return obbv::guarded([&] { return obbv_lloyd_get_body(st, tri_box, boxes, obv, layer_error, counters); });
+}
+static int obbv_lloyd_get_body(obbv_lloyd* st, int32_t* tri_box, float* boxes, double* obv, double* layer_error,
                               int64_t* counters) {
   // counters: [0] evaluations, [1] rounds, [2] no-evaluation candidates, [3] moves,
   // [4] ranker predictions, [5] ranker fallbacks
@@ -1991,7 +2047,11 @@ extern "C" int obbv_lloyd_get(obbv_lloyd* st, int32_t* tri_box, float* boxes, do
   return OBBV_OK;
 }
 
+static int obbv_lloyd_record_body(obbv_lloyd* st, int64_t cap);
 extern "C" int obbv_lloyd_record(obbv_lloyd* st, int64_t cap) {
+  return obbv::guarded([&] { return obbv_lloyd_record_body(st, cap); });
+}
+static int obbv_lloyd_record_body(obbv_lloyd* st, int64_t cap) {
   clear_error();
   OBBV_ARG(st, "NULL state");
   OBBV_ARG(cap >= 0, "cap must be >= 0");
@@ -2003,7 +2063,11 @@ extern "C" int obbv_lloyd_record(obbv_lloyd* st, int64_t cap) {
   return OBBV_OK;
 }
 
+static int obbv_lloyd_take_records_body(obbv_lloyd* st, int64_t max_n, float* boxes, double* obv, int64_t* n_out);
 extern "C" int obbv_lloyd_take_records(obbv_lloyd* st, int64_t max_n, float* boxes, double* obv, int64_t* n_out) {
+  return obbv::guarded([&] { return obbv_lloyd_take_records_body(st, max_n, boxes, obv, n_out); });
+}
+static int obbv_lloyd_take_records_body(obbv_lloyd* st, int64_t max_n, float* boxes, double* obv, int64_t* n_out) {
   clear_error();
   OBBV_ARG(st && n_out, "NULL argument");
   LloydState& S = *reinterpret_cast<LloydState*>(st);
@@ -2022,7 +2086,11 @@ extern "C" int obbv_lloyd_take_records(obbv_lloyd* st, int64_t max_n, float* box
   return OBBV_OK;
 }
 
+static int obbv_lloyd_destroy_body(obbv_lloyd* st);
 extern "C" int obbv_lloyd_destroy(obbv_lloyd* st) {
+  return obbv::guarded([&] { return obbv_lloyd_destroy_body(st); });
+}
+static int obbv_lloyd_destroy_body(obbv_lloyd* st) {
   clear_error();
   delete reinterpret_cast<LloydState*>(st);
   return OBBV_OK;
@@ -2199,7 +2267,15 @@ int merge_level(LloydState& S, Tree& T, int l) {
 }  // namespace
 }  // namespace obbv
 
+static int obbv_build_hierarchy_body(const obbv_mesh* mesh, const obbv_hier_params* p, float* out_boxes,
+                                    double* out_obv, int32_t* out_parent, int32_t* out_tri_node, double* out_e,
+                                    int64_t* out_counters, void* stream);
 extern "C" int obbv_build_hierarchy(const obbv_mesh* mesh, const obbv_hier_params* p, float* out_boxes,
+                                    double* out_obv, int32_t* out_parent, int32_t* out_tri_node, double* out_e,
+                                    int64_t* out_counters, void* stream) {
+  return obbv::guarded([&] { return obbv_build_hierarchy_body(mesh, p, out_boxes, out_obv, out_parent, out_tri_node, out_e, out_counters, stream); });
+}
+static int obbv_build_hierarchy_body(const obbv_mesh* mesh, const obbv_hier_params* p, float* out_boxes,
                                     double* out_obv, int32_t* out_parent, int32_t* out_tri_node, double* out_e,
                                     int64_t* out_counters, void* stream) {
   clear_error();

@@ -123,7 +123,13 @@ k_volume(const float* __restrict__ V, const int32_t* __restrict__ F, int64_t nt,
 
 using namespace obbv;
 
+static int obbv_validate_mesh_body(const obbv_mesh* mesh, int32_t* out_report, double* out_volume,
+                                  void* stream);
 extern "C" int obbv_validate_mesh(const obbv_mesh* mesh, int32_t* out_report, double* out_volume,
+                                  void* stream) {
+  return obbv::guarded([&] { return obbv_validate_mesh_body(mesh, out_report, out_volume, stream); });
+}
+static int obbv_validate_mesh_body(const obbv_mesh* mesh, int32_t* out_report, double* out_volume,
                                   void* stream) {
   clear_error();
   OBBV_ARG(mesh != nullptr, "mesh is NULL");

@@ -584,12 +584,22 @@ int mlp_forward_impl(const float* params, const float* X, int32_t n, float* out_
 
 using namespace obbv;
 
+static int obbv_mlp_forward_body(const float* params, const float* X, int32_t n, float* out_f, void* stream);
 extern "C" int obbv_mlp_forward(const float* params, const float* X, int32_t n, float* out_f, void* stream) {
+  return obbv::guarded([&] { return obbv_mlp_forward_body(params, X, n, out_f, stream); });
+}
+static int obbv_mlp_forward_body(const float* params, const float* X, int32_t n, float* out_f, void* stream) {
   clear_error();
   return mlp_forward_impl(params, X, n, out_f, (hipStream_t)stream);
 }
 
+static int obbv_sample_features_body(const float* volume, int32_t N, const float* frame, const obbv_box* boxes,
+                                    int32_t n_boxes, float* out_X, void* stream);
 extern "C" int obbv_sample_features(const float* volume, int32_t N, const float* frame, const obbv_box* boxes,
+                                    int32_t n_boxes, float* out_X, void* stream) {
+  return obbv::guarded([&] { return obbv_sample_features_body(volume, N, frame, boxes, n_boxes, out_X, stream); });
+}
+static int obbv_sample_features_body(const float* volume, int32_t N, const float* frame, const obbv_box* boxes,
                                     int32_t n_boxes, float* out_X, void* stream) {
   clear_error();
   OBBV_ARG(n_boxes >= 0 && N >= 1, "bad size");
@@ -601,7 +611,13 @@ extern "C" int obbv_sample_features(const float* volume, int32_t N, const float*
   return OBBV_OK;
 }
 
+static int obbv_mlp_rank_boxes_body(const float* params, const float* volume, int32_t N, const float* frame,
+                                   const obbv_box* boxes, int32_t n_boxes, float* out_f, void* stream);
 extern "C" int obbv_mlp_rank_boxes(const float* params, const float* volume, int32_t N, const float* frame,
+                                   const obbv_box* boxes, int32_t n_boxes, float* out_f, void* stream) {
+  return obbv::guarded([&] { return obbv_mlp_rank_boxes_body(params, volume, N, frame, boxes, n_boxes, out_f, stream); });
+}
+static int obbv_mlp_rank_boxes_body(const float* params, const float* volume, int32_t N, const float* frame,
                                    const obbv_box* boxes, int32_t n_boxes, float* out_f, void* stream) {
   clear_error();
   OBBV_ARG(n_boxes >= 0 && N >= 1, "bad size");
@@ -616,7 +632,15 @@ extern "C" int obbv_mlp_rank_boxes(const float* params, const float* volume, int
   return mlp_rank_packed(params, (const short*)pv, volume, N, frame, boxes, n_boxes, sc, out_f, s, nullptr, 0u, nullptr);
 }
 
+static int obbv_mlp_train_step_body(float* params, float* adam_m, float* adam_v, int32_t step, const float* X,
+                                   const float* target, int32_t n, float lr, float* out_loss, float* out_grad,
+                                   void* stream);
 extern "C" int obbv_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, const float* X,
+                                   const float* target, int32_t n, float lr, float* out_loss, float* out_grad,
+                                   void* stream) {
+  return obbv::guarded([&] { return obbv_mlp_train_step_body(params, adam_m, adam_v, step, X, target, n, lr, out_loss, out_grad, stream); });
+}
+static int obbv_mlp_train_step_body(float* params, float* adam_m, float* adam_v, int32_t step, const float* X,
                                    const float* target, int32_t n, float lr, float* out_loss, float* out_grad,
                                    void* stream) {
   clear_error();

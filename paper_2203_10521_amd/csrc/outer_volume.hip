@@ -39,6 +39,7 @@
 //                        sum
 //   k_finalize           float64 OBV per box, publication of the call
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -1457,21 +1458,27 @@ __device__ void finalize_box(const obbv_box* __restrict__ boxes, int b, int R, u
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct HostPinned {
-  int64_t* p = nullptr;
-};
-HostPinned g_pinned[64];
+// Pinned host words for totals read back by the host, one block per device and
+// scratch-pool set (calls that may run at the same time use different sets).
+int64_t* g_pinned[64][kPoolSets] = {};
+std::mutex g_pinned_mutex;
 
-int pinned_totals(int64_t** out) {
+int pinned_totals(int pool_base, int64_t** out) {
   int dev = 0;
   OBBV_HIP(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64) return OBBV_ERR_UNSUPPORTED;
-  if (!g_pinned[dev].p) {
+  const int set = pool_base / kPoolCount;
+  if (dev < 0 || dev >= 64) {
+    set_error("device index out of range");
+    return OBBV_ERR_UNSUPPORTED;
+  }
+  OBBV_ARG(set >= 0 && set < kPoolSets, "scratch-pool set out of range");
+  std::lock_guard<std::mutex> lock(g_pinned_mutex);
+  if (!g_pinned[dev][set]) {
     void* q = nullptr;
     OBBV_HIP(hipHostMalloc(&q, 64, hipHostMallocDefault));
-    g_pinned[dev].p = (int64_t*)q;
+    g_pinned[dev][set] = (int64_t*)q;
   }
-  *out = g_pinned[dev].p;
+  *out = g_pinned[dev][set];
   return OBBV_OK;
 }
 
@@ -1532,13 +1539,19 @@ BlockGeom block_geom(int R, int block_rays) {
   return g;
 }
 
+constexpr int kMaxDevicesCast = 64;
+
 template <bool STATS, bool OCC, bool TAB>
 int launch_cast(const CastArgs& ca, unsigned grid, size_t lds, hipStream_t s) {
-  static bool attr_set = false;  // per instantiation: allow the largest dynamic block
-  if (!attr_set) {
+  // per instantiation and device: allow the largest dynamic block (calls on
+  // several host threads may both set it; the setting is idempotent)
+  static std::atomic<bool> attr_set[kMaxDevicesCast];
+  int dev = 0;
+  OBBV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevicesCast || !attr_set[dev].load(std::memory_order_acquire)) {
     OBBV_HIP(hipFuncSetAttribute((const void*)k_cast<STATS, OCC, TAB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)(kBlockRaysMax * sizeof(float2))));
-    attr_set = true;
+    if (dev >= 0 && dev < kMaxDevicesCast) attr_set[dev].store(true, std::memory_order_release);
   }
   hipLaunchKernelGGL((k_cast<STATS, OCC, TAB>), dim3(grid), dim3(kCastThreads), lds, s, ca);
   OBBV_HIP(hipGetLastError());
@@ -1761,7 +1774,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
         OBBV_RET(exclusive_scan_i32_to_i64(d_fcnt, d_foff, ngroups, d_scan, scan_bytes, s));
       }
       int64_t* pin = nullptr;
-      OBBV_RET(pinned_totals(&pin));
+      OBBV_RET(pinned_totals(pool_base, &pin));
       OBBV_HIP(hipMemcpyAsync(pin + 3, d_foff + ngroups, 8, hipMemcpyDeviceToHost, s));
       OBBV_HIP(hipStreamSynchronize(s));
       void* lv = nullptr;
@@ -1881,7 +1894,17 @@ int outer_volume_impl(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box*
 
 }  // namespace obbv
 
+static int obbv_outer_volume_grouped_body(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
+                                         int32_t n_boxes, const obbv_ov_params* params, const obbv_box* frames,
+                                         const int32_t* box_frame, int32_t n_frames, double* out_obv,
+                                         void* stream);
 extern "C" int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
+                                         int32_t n_boxes, const obbv_ov_params* params, const obbv_box* frames,
+                                         const int32_t* box_frame, int32_t n_frames, double* out_obv,
+                                         void* stream) {
+  return obbv::guarded([&] { return obbv_outer_volume_grouped_body(mesh, boxes, box_key, n_boxes, params, frames, box_frame, n_frames, out_obv, stream); });
+}
+static int obbv_outer_volume_grouped_body(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
                                          int32_t n_boxes, const obbv_ov_params* params, const obbv_box* frames,
                                          const int32_t* box_frame, int32_t n_frames, double* out_obv,
                                          void* stream) {
@@ -1893,7 +1916,19 @@ extern "C" int obbv_outer_volume_grouped(const obbv_mesh* mesh, const obbv_box* 
                                    (hipStream_t)stream, nullptr);
 }
 
+static int obbv_outer_volume_ex_body(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                    const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                                    const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
+                                    int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side,
+                                    void* stream);
 extern "C" int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                    const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                                    const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
+                                    int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side,
+                                    void* stream) {
+  return obbv::guarded([&] { return obbv_outer_volume_ex_body(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, params, out_obv, out_vin_axis, out_ray_q, out_ray_hits, out_side, stream); });
+}
+static int obbv_outer_volume_ex_body(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                                     const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
                                     const obbv_ov_params* params, double* out_obv, double* out_vin_axis,
                                     int32_t* out_ray_q, int32_t* out_ray_hits, int32_t* out_side,
@@ -1903,7 +1938,15 @@ extern "C" int obbv_outer_volume_ex(const obbv_mesh* meshes, int32_t n_meshes, c
                                  out_vin_axis, out_ray_q, out_ray_hits, out_side, (hipStream_t)stream, nullptr);
 }
 
+static int obbv_outer_volume_body(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                 const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                                 const obbv_ov_params* params, double* out_obv, void* stream);
 extern "C" int obbv_outer_volume(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                 const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                                 const obbv_ov_params* params, double* out_obv, void* stream) {
+  return obbv::guarded([&] { return obbv_outer_volume_body(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, params, out_obv, stream); });
+}
+static int obbv_outer_volume_body(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                                  const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
                                  const obbv_ov_params* params, double* out_obv, void* stream) {
   obbv::clear_error();
@@ -1947,7 +1990,15 @@ int noalloc_scratch(char** out) {
 }  // namespace
 }  // namespace obbv
 
+static int obbv_outer_volume_noalloc_body(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
+                                         int32_t n_boxes, const obbv_ov_params* params, double* out_obv,
+                                         uint32_t* out_status, void* stream);
 extern "C" int obbv_outer_volume_noalloc(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
+                                         int32_t n_boxes, const obbv_ov_params* params, double* out_obv,
+                                         uint32_t* out_status, void* stream) {
+  return obbv::guarded([&] { return obbv_outer_volume_noalloc_body(mesh, boxes, box_key, n_boxes, params, out_obv, out_status, stream); });
+}
+static int obbv_outer_volume_noalloc_body(const obbv_mesh* mesh, const obbv_box* boxes, const uint32_t* box_key,
                                          int32_t n_boxes, const obbv_ov_params* params, double* out_obv,
                                          uint32_t* out_status, void* stream) {
   using namespace obbv;
@@ -2017,7 +2068,15 @@ __global__ void k_features(const obbv_box* __restrict__ boxes, const int32_t* __
 }  // namespace
 }  // namespace obbv
 
+static int obbv_box_features_body(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                 const int32_t* box_mesh, int32_t n_boxes, const float* mesh_frame, uint64_t seed,
+                                 float* out_X, void* stream);
 extern "C" int obbv_box_features(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                 const int32_t* box_mesh, int32_t n_boxes, const float* mesh_frame, uint64_t seed,
+                                 float* out_X, void* stream) {
+  return obbv::guarded([&] { return obbv_box_features_body(meshes, n_meshes, boxes, box_mesh, n_boxes, mesh_frame, seed, out_X, stream); });
+}
+static int obbv_box_features_body(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                                  const int32_t* box_mesh, int32_t n_boxes, const float* mesh_frame, uint64_t seed,
                                  float* out_X, void* stream) {
   using namespace obbv;
@@ -2077,7 +2136,13 @@ __global__ void k_scatter_volume(const int32_t* __restrict__ occ, int nb, float*
 }  // namespace
 }  // namespace obbv
 
+static int obbv_occupancy_volume_body(const obbv_mesh* mesh, int32_t nb, const float* frame, uint64_t seed,
+                                     float* out_volume, void* stream);
 extern "C" int obbv_occupancy_volume(const obbv_mesh* mesh, int32_t nb, const float* frame, uint64_t seed,
+                                     float* out_volume, void* stream) {
+  return obbv::guarded([&] { return obbv_occupancy_volume_body(mesh, nb, frame, seed, out_volume, stream); });
+}
+static int obbv_occupancy_volume_body(const obbv_mesh* mesh, int32_t nb, const float* frame, uint64_t seed,
                                      float* out_volume, void* stream) {
   using namespace obbv;
   clear_error();
@@ -2166,7 +2231,17 @@ int time_block(OvPlanState& P, int block, hipStream_t s, float* ms) {
 }  // namespace
 }  // namespace obbv
 
+static int obbv_ov_plan_create_body(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                   const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                                   const obbv_ov_params* params, double* out_obv, double headroom, void* stream,
+                                   obbv_ov_plan** out);
 extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
+                                   const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
+                                   const obbv_ov_params* params, double* out_obv, double headroom, void* stream,
+                                   obbv_ov_plan** out) {
+  return obbv::guarded([&] { return obbv_ov_plan_create_body(meshes, n_meshes, boxes, box_mesh, box_key, n_boxes, params, out_obv, headroom, stream, out); });
+}
+static int obbv_ov_plan_create_body(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* boxes,
                                    const int32_t* box_mesh, const uint32_t* box_key, int32_t n_boxes,
                                    const obbv_ov_params* params, double* out_obv, double headroom, void* stream,
                                    obbv_ov_plan** out) {
@@ -2272,7 +2347,11 @@ extern "C" int obbv_ov_plan_create(const obbv_mesh* meshes, int32_t n_meshes, co
   return OBBV_OK;
 }
 
+static int obbv_ov_plan_launch_body(obbv_ov_plan* plan, void* stream);
 extern "C" int obbv_ov_plan_launch(obbv_ov_plan* plan, void* stream) {
+  return obbv::guarded([&] { return obbv_ov_plan_launch_body(plan, stream); });
+}
+static int obbv_ov_plan_launch_body(obbv_ov_plan* plan, void* stream) {
   using namespace obbv;
   clear_error();
   OBBV_ARG(plan, "NULL plan");
@@ -2281,7 +2360,11 @@ extern "C" int obbv_ov_plan_launch(obbv_ov_plan* plan, void* stream) {
   return OBBV_OK;
 }
 
+static int obbv_ov_plan_info_body(obbv_ov_plan* plan, int32_t* out_block_rays, int64_t* out_caps, float* out_tuned_ms);
 extern "C" int obbv_ov_plan_info(obbv_ov_plan* plan, int32_t* out_block_rays, int64_t* out_caps, float* out_tuned_ms) {
+  return obbv::guarded([&] { return obbv_ov_plan_info_body(plan, out_block_rays, out_caps, out_tuned_ms); });
+}
+static int obbv_ov_plan_info_body(obbv_ov_plan* plan, int32_t* out_block_rays, int64_t* out_caps, float* out_tuned_ms) {
   using namespace obbv;
   clear_error();
   OBBV_ARG(plan, "NULL plan");
@@ -2297,7 +2380,11 @@ extern "C" int obbv_ov_plan_info(obbv_ov_plan* plan, int32_t* out_block_rays, in
   return OBBV_OK;
 }
 
+static int obbv_ov_plan_destroy_body(obbv_ov_plan* plan);
 extern "C" int obbv_ov_plan_destroy(obbv_ov_plan* plan) {
+  return obbv::guarded([&] { return obbv_ov_plan_destroy_body(plan); });
+}
+static int obbv_ov_plan_destroy_body(obbv_ov_plan* plan) {
   using namespace obbv;
   clear_error();
   if (!plan) return OBBV_OK;

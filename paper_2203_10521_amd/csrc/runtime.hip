@@ -270,7 +270,11 @@ int profile_record_end(hipStream_t s, void* token) {
 
 using namespace obbv;
 
+static int obbv_profile_enable_body(int enable);
 extern "C" int obbv_profile_enable(int enable) {
+  return obbv::guarded([&] { return obbv_profile_enable_body(enable); });
+}
+static int obbv_profile_enable_body(int enable) {
   clear_error();
   g_prof.enabled = enable != 0;
   if (g_prof.enabled) {
@@ -280,7 +284,13 @@ extern "C" int obbv_profile_enable(int enable) {
   return OBBV_OK;
 }
 
+static int obbv_profile_read_body(double* out_test_ms, int64_t* out_launches, int64_t* out_tests,
+                                 int64_t* out_bytes, double* out_busy_ms);
 extern "C" int obbv_profile_read(double* out_test_ms, int64_t* out_launches, int64_t* out_tests,
+                                 int64_t* out_bytes, double* out_busy_ms) {
+  return obbv::guarded([&] { return obbv_profile_read_body(out_test_ms, out_launches, out_tests, out_bytes, out_busy_ms); });
+}
+static int obbv_profile_read_body(double* out_test_ms, int64_t* out_launches, int64_t* out_tests,
                                  int64_t* out_bytes, double* out_busy_ms) {
   clear_error();
   std::lock_guard<std::mutex> lock(g_prof_mutex);
@@ -340,7 +350,11 @@ extern "C" const char* obbv_version(void) { return "obbv 0.1.0 (gfx950)"; }
 
 extern "C" const char* obbv_last_error(void) { return g_last_error.c_str(); }
 
+static int obbv_status_body(void* stream, uint32_t* out_flags);
 extern "C" int obbv_status(void* stream, uint32_t* out_flags) {
+  return obbv::guarded([&] { return obbv_status_body(stream, out_flags); });
+}
+static int obbv_status_body(void* stream, uint32_t* out_flags) {
   clear_error();
   hipStream_t s = (hipStream_t)stream;
   uint32_t* st = nullptr;
@@ -353,7 +367,11 @@ extern "C" int obbv_status(void* stream, uint32_t* out_flags) {
   return OBBV_OK;
 }
 
+static int obbv_release_body(void);
 extern "C" int obbv_release(void) {
+  return obbv::guarded([&] { return obbv_release_body(); });
+}
+static int obbv_release_body(void) {
   clear_error();
   int cur = 0;
   OBBV_HIP(hipGetDevice(&cur));

@@ -19,7 +19,13 @@ int fit_impl(const obbv_mesh* mesh, const int32_t* tri_cluster, int32_t n_cluste
 
 using namespace obbv;
 
+static int obbv_build_obb_tree_body(const obbv_mesh* mesh, int32_t levels, int32_t branching, float* out_boxes,
+                                   int32_t* out_parent, int32_t* out_tri_node, void* stream);
 extern "C" int obbv_build_obb_tree(const obbv_mesh* mesh, int32_t levels, int32_t branching, float* out_boxes,
+                                   int32_t* out_parent, int32_t* out_tri_node, void* stream) {
+  return obbv::guarded([&] { return obbv_build_obb_tree_body(mesh, levels, branching, out_boxes, out_parent, out_tri_node, stream); });
+}
+static int obbv_build_obb_tree_body(const obbv_mesh* mesh, int32_t levels, int32_t branching, float* out_boxes,
                                    int32_t* out_parent, int32_t* out_tri_node, void* stream) {
   clear_error();
   OBBV_ARG(mesh != nullptr, "mesh is NULL");
