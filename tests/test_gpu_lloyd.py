@@ -162,9 +162,15 @@ def test_flood_on_several_streams_gives_the_same_bits(api, monkeypatch):
         monkeypatch.setenv("OBBV_FLOOD_STREAMS", flag)
         out[flag] = api.build_hierarchy(Vt, Ft, levels=3, branching=4, iters=3, sweeps=1, R=16, seed=9,
                                         pops_per_round=8)
+    # four streams with the frame lists built in two passes (each pass reads a
+    # list total back through the host word of its own scratch set)
+    monkeypatch.setenv("OBBV_FLOOD_STREAMS", "4")
+    monkeypatch.setenv("OBBV_FRAME_LISTS", "2")
+    out["4, two-pass lists"] = api.build_hierarchy(Vt, Ft, levels=3, branching=4, iters=3, sweeps=1, R=16, seed=9,
+                                                   pops_per_round=8)
     c1 = dict(out["1"]["counters"])
     r1 = c1.pop("rounds")
-    for flag in ("2", "4"):
+    for flag in ("2", "4", "4, two-pass lists"):
         for k in ("boxes", "obv", "parent", "tri_node", "e"):
             assert np.array_equal(out[flag][k], out["1"][k]), (flag, k)
         c = dict(out[flag]["counters"])
