@@ -193,7 +193,6 @@ def exact_evaluator_leg(api, torch, Vt, Ft, boxes, R, seed):
             "pair_tests_per_s": n * int(Ft.shape[0]) / dt,
             "estimator_R": R, "estimator_dev_mean": float(dev.mean()), "estimator_dev_max": float(dev.max()),
             "central_m": m, "central_ms_per_call": 1e3 * dtc, "central_evals_per_s": n / dtc,
-            "central_ray_tests_per_s": n * 6 * m * m * int(Ft.shape[0]) / dtc,
             "central_dev_mean": float(cdev.mean()), "central_dev_max": float(cdev.max()),
             "workload": "the built torus hierarchy's boxes, 65,536 triangles, cast axis 0, float64"}
 

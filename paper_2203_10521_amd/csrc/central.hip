@@ -12,6 +12,7 @@
 // function equal to 0 passes only on a top-left edge).  float64 throughout,
 // one fixed order of operations; sums in a fixed order.
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -41,10 +42,11 @@ __device__ inline bool topleft(double px, double py, double qx, double qy) {
 __device__ inline double pick(const double v[3], int k) { return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]); }
 
 __global__ void __launch_bounds__(kCentralThreads)
-k_central_partial(const obbv_box* __restrict__ boxes, MeshDev M, int m, int n_chunks, double* __restrict__ part,
-                  uint32_t* status) {
+k_central_partial(const obbv_box* __restrict__ boxes, MeshDev M, int m, int n_chunks, int cull,
+                  double* __restrict__ part, uint32_t* status) {
   __shared__ double sT[12][kCentralTile];  // A, B, C (box frame), outward normal
-  __shared__ int32_t sOk[kCentralTile];
+  __shared__ int32_t sIdx[kCentralTile];   // the tile's triangles that may be hit, in triangle order
+  __shared__ int32_t sWc[kCentralTile / 64];
   __shared__ double red[kCentralThreads];
   const int chunk = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   const float* bp = reinterpret_cast<const float*>(boxes + b);
@@ -100,6 +102,29 @@ k_central_partial(const obbv_box* __restrict__ boxes, MeshDev M, int m, int n_ch
     Sy = __ddiv_rn(pick(d, ky), pick(d, kz));
     Sz = __ddiv_rn(1.0, pick(d, kz));
   }
+  // The block's rays lie in the pyramid of directions over its pixels of one
+  // face (a in [a_lo, a_hi] along face axis + 1, b in [b_lo, b_hi] along axis
+  // + 2, sigma = +-x[axis] > 0), half a pixel inside its sides.  A triangle
+  // whose three vertices lie beyond one side (or behind the centre) by more
+  // than 1e-9 of their coordinates holds no point of any ray at t > 0, so it
+  // adds no crossing and is skipped: the sum is unchanged, bit for bit.
+  // Blocks spanning two faces cull nothing.
+  const int p0 = chunk * kCentralThreads, p1 = min(p0 + kCentralThreads, n_rays) - 1;
+  const int mm = m * m;
+  const bool pyr = cull != 0 && ok && p0 / mm == p1 / mm;
+  const int pface = p0 / mm, paxis = pface / 2;
+  const double psg = (pface & 1) ? -1.0 : 1.0;
+  double a_lo = 0.0, a_hi = 0.0, b_lo = 0.0, b_hi = 0.0;
+  if (pyr) {
+    const int r0 = p0 - pface * mm, r1 = p1 - pface * mm;
+    const int i0 = r0 / m, i1 = r1 / m;
+    const int j0 = i0 == i1 ? r0 - i0 * m : 0, j1 = i0 == i1 ? r1 - i1 * m : m - 1;
+    const double md = (double)m;
+    a_lo = __dadd_rn(-1.0, __ddiv_rn(2.0 * i0, md));
+    a_hi = __dadd_rn(-1.0, __ddiv_rn(2.0 * (i1 + 1), md));
+    b_lo = __dadd_rn(-1.0, __ddiv_rn(2.0 * j0, md));
+    b_hi = __dadd_rn(-1.0, __ddiv_rn(2.0 * (j1 + 1), md));
+  }
   double sum = 0.0;  // sum_k s_k min(r_k, r_e)^3, crossings in triangle order
   for (int t0 = 0; t0 < M.nt; t0 += kCentralTile) {
     __syncthreads();
@@ -130,15 +155,40 @@ k_central_partial(const obbv_box* __restrict__ boxes, MeshDev M, int m, int n_ch
           sT[10][tid] = __dsub_rn(__dmul_rn(e1[2], e2[0]), __dmul_rn(e1[0], e2[2]));
           sT[11][tid] = __dsub_rn(__dmul_rn(e1[0], e2[1]), __dmul_rn(e1[1], e2[0]));
           good = 1;
+          if (pyr) {
+            // sides of the pyramid (value > 0: outside), and behind the centre
+            int out = 0x1f;
+            for (int q = 0; q < 3; ++q) {
+              const double sg = __dmul_rn(psg, pick(L[q], paxis));
+              const double xa = pick(L[q], (paxis + 1) % 3), xb = pick(L[q], (paxis + 2) % 3);
+              const double tol = __dmul_rn(1e-9, __dadd_rn(__dadd_rn(fabs(sg), fabs(xa)), fabs(xb)));
+              int o = 0;
+              if (-sg > tol) o |= 1;
+              if (__dsub_rn(xa, __dmul_rn(a_hi, sg)) > tol) o |= 2;
+              if (__dsub_rn(__dmul_rn(a_lo, sg), xa) > tol) o |= 4;
+              if (__dsub_rn(xb, __dmul_rn(b_hi, sg)) > tol) o |= 8;
+              if (__dsub_rn(__dmul_rn(b_lo, sg), xb) > tol) o |= 16;
+              out &= o;
+            }
+            if (out) good = 0;
+          }
         }
       }
-      sOk[tid] = good;
+      // compact the tile's kept triangles, in triangle order
+      const uint64_t mk = __ballot(good != 0);
+      const int lane = tid & 63, wv = tid >> 6;
+      if (lane == 0) sWc[wv] = (int)__popcll(mk);
+      __syncthreads();
+      int pos = (int)__popcll(mk & ((1ull << lane) - 1ull));
+      for (int v = 0; v < wv; ++v) pos += sWc[v];
+      if (good) sIdx[pos] = tid;
     }
     __syncthreads();
     if (!ray) continue;
-    const int nt = min(kCentralTile, M.nt - t0);
-    for (int k = 0; k < nt; ++k) {
-      if (!sOk[k]) continue;
+    int nk = 0;
+    for (int v = 0; v < kCentralTile / 64; ++v) nk += sWc[v];
+    for (int kk = 0; kk < nk; ++kk) {
+      const int k = sIdx[kk];
       const double Akz = sT[kz][k], Bkz = sT[3 + kz][k], Ckz = sT[6 + kz][k];
       const double Ax = __dsub_rn(sT[kx][k], __dmul_rn(Sx, Akz)), Ay = __dsub_rn(sT[ky][k], __dmul_rn(Sy, Akz));
       const double Bx = __dsub_rn(sT[3 + kx][k], __dmul_rn(Sx, Bkz)), By = __dsub_rn(sT[3 + ky][k], __dmul_rn(Sy, Bkz));
@@ -211,8 +261,11 @@ int outer_volume_central(const obbv_mesh* mesh, const obbv_box* boxes, int32_t n
   void* p = nullptr;
   OBBV_RET(pool_get(kPoolCentral, sizeof(double) * (size_t)n_boxes * n_chunks, &p));
   double* part = (double*)p;
+  // OBBV_CENTRAL_CULL=0 tests every triangle against every ray (same bits)
+  const char* e = getenv("OBBV_CENTRAL_CULL");
+  const int cull = (e && *e && atoi(e) == 0) ? 0 : 1;
   hipLaunchKernelGGL(k_central_partial, dim3((unsigned)n_chunks, (unsigned)n_boxes), dim3(kCentralThreads), 0, s,
-                     boxes, M, m, n_chunks, part, status);
+                     boxes, M, m, n_chunks, cull, part, status);
   OBBV_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_central_final, dim3((unsigned)ceil_div(n_boxes, 128)), dim3(128), 0, s, boxes, n_boxes,
                      n_chunks, (const double*)part, out_obv, status);

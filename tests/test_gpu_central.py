@@ -29,11 +29,14 @@ def _t(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-@pytest.mark.parametrize("m", [3, 8])
+@pytest.mark.parametrize("m", [3, 8, 16, 32])
 def test_central_estimator_matches_the_oracle(api, m):
     """Random boxes over the icosphere plus a box inside the solid (exactly 0),
     one far away and one holding the whole mesh, across more than one tile of
-    triangles and a ragged last ray chunk: |gpu - oracle| <= 1e-11 (V_box + 1)."""
+    triangles and a ragged last ray chunk: |gpu - oracle| <= 1e-11 (V_box + 1).
+    With m = 3 and 8 every ray block spans two cube faces (no culling); with
+    m = 16 a block is one face and with m = 32 a quarter of one, where the
+    triangles outside the block's pyramid of directions are skipped."""
     V, F = synth.icosphere(3)
     c, a, h = synth.random_boxes(10, seed=23, center_range=0.8, half_range=(0.1, 0.7))
     c = np.concatenate([c, [[0.05, 0.0, -0.02], [4.0, 0.0, 0.0], [0.0, 0.0, 0.0]]]).astype(np.float32)
@@ -77,3 +80,23 @@ def test_central_estimator_converges_and_flags(api):
     assert err[32] < err[8] and err[32] < 2e-3
     again = api.outer_volume_central(Vt, Ft, B, 32).cpu().numpy()
     assert np.array_equal(again, est, equal_nan=True)
+
+
+@pytest.mark.parametrize("m", [16, 24, 32])
+def test_central_culling_gives_the_same_bits(api, monkeypatch, m):
+    """Skipping the triangles that lie outside a ray block's pyramid of
+    directions (OBBV_CENTRAL_CULL, on by default) changes no bit of the
+    estimate: 65,536 triangles of the noisy torus, boxes of several sizes
+    around it (m = 24 mixes blocks inside one face and blocks spanning two)."""
+    V, F = synth.noisy_torus()
+    c, a, h = synth.random_boxes(12, seed=31, center_range=1.1, half_range=(0.05, 0.8))
+    B = _t(synth.boxes_to_array(c, a, h))
+    Vt, Ft = _t(V), _t(F)
+    api.status()  # clear what earlier calls left
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("OBBV_CENTRAL_CULL", flag)
+        out[flag] = api.outer_volume_central(Vt, Ft, B, m).cpu().numpy()
+    assert api.status() == 0
+    assert np.array_equal(out["1"].view(np.int64), out["0"].view(np.int64)), m
+    assert np.all(np.isfinite(out["1"]))
