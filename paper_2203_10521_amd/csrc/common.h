@@ -124,6 +124,12 @@ struct OvExec {
   // call; computed by the call when absent
   const float4* spans = nullptr;
   const float4* span_runs = nullptr;
+  // smaller cast items for calls that run alone: a call whose default items
+  // would give fewer than split_below cast units takes items of item_tris
+  // entries (a multiple of 256 dividing the default) instead, so that it
+  // leaves fewer compute units idle; 0 = never.  The results do not change.
+  int item_tris = 0;
+  int split_below = 0;
 };
 // Span bounds table of a mesh for repeated single-mesh outer-volume calls:
 // its size in bytes (0: the mesh needs none), its computation (stream ordered)

@@ -191,6 +191,8 @@ struct Evaluator {
   size_t cur_n = 0, cur_nf = 0, o_box = 0, o_key = 0, o_frame = 0, o_bf = 0, o_ctl = 0, o_out = 0;
   bool cur_shared = false, in_flight = false;
   int pool_base = 0;  // pool set of the outer-volume scratch (one per concurrent stream)
+  int item_tris = 0;    // smaller cast items for its calls with few units (0: never)
+  int split_below = 0;  // the unit count below which a call takes them
 
   // `overlap` (nullable) runs on the host while the device evaluates
   int eval(const std::vector<HBox>& boxes, const std::vector<uint32_t>& keys, std::vector<double>& out,
@@ -252,6 +254,8 @@ struct Evaluator {
 
   int run_call(OvExec* ex) {
     ex->pool_base = pool_base;
+    ex->item_tris = item_tris;
+    ex->split_below = item_tris ? split_below : 0;
     if (jtab_use) {
       ex->jitter = jtab;
       ex->jitter_R = jR;
@@ -1649,6 +1653,26 @@ static int flood_streams_choice() {
   return LloydState::kFloodParts;
 }
 
+// The calls of a flood that runs on one stream run alone on the device; those
+// with few cast units take smaller cast items: OBBV_ALONE_ITEM_TRIS entries (0:
+// never; else 768, 1536 or 2304), by default 1536.  The bits do not depend on it.
+static int alone_item_tris() {
+  const char* e = getenv("OBBV_ALONE_ITEM_TRIS");
+  if (e && *e) {
+    const int v = atoi(e);
+    if (v == 0 || v == 768 || v == 1536 || v == 2304) return v;
+  }
+  return 1536;
+}
+
+// ... and the cast-unit count below which such a call takes them:
+// OBBV_ALONE_SPLIT_BELOW, by default 128.
+static int alone_split_below() {
+  const char* e = getenv("OBBV_ALONE_SPLIT_BELOW");
+  if (e && *e) return std::max(0, atoi(e));
+  return 128;
+}
+
 // The flood of `groups`: with two groups or more, the groups are split into
 // parts of about equal element counts (largest group
 // first, into the lightest part; groups keep their order inside a part),
@@ -1657,7 +1681,15 @@ static int flood_streams_choice() {
 // another's calls leave idle.
 static int flood_split(LloydState& S, const std::vector<Group>& groups, PartitionIO io) {
   const int parts = std::min<int>(flood_streams_choice(), (int)groups.size());
-  if (parts < 2 || S.ev.smp_cap != 0) return flood_partition(S.M, S.E, groups, io, S.K, S.ev, S.cnt, &S.pred);
+  if (parts < 2 || S.ev.smp_cap != 0) {
+    // a flood on one stream: its calls run alone on the device, so those with
+    // few cast units take smaller items (more units for idle compute units)
+    S.ev.item_tris = alone_item_tris();
+    S.ev.split_below = alone_split_below();
+    const int rc = flood_partition(S.M, S.E, groups, io, S.K, S.ev, S.cnt, &S.pred);
+    S.ev.item_tris = 0;
+    return rc;
+  }
   std::vector<int> order(groups.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),

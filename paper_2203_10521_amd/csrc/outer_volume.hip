@@ -745,7 +745,7 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
              const uint32_t* __restrict__ box_key, int R, uint64_t seed, RayFrame* __restrict__ rframe,
              ItemInfo* __restrict__ items, int64_t item_cap, unsigned long long* __restrict__ acc,
              unsigned long long* __restrict__ ctl, const float4* __restrict__ runs,
-             const float4* __restrict__ centre) {
+             const float4* __restrict__ centre, int item_small, int split_below, int nblk) {
   __shared__ long long wsum[kScanBlockThreads / 64];
   __shared__ unsigned long long s_rm[kScanBlockThreads];  // runs kept (the first 64) of a whole-mesh cast
   __shared__ uint8_t s_cul[kScanBlockThreads];            // the pair is a whole-mesh cast with span runs
@@ -759,7 +759,7 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
   const int npairs = 3 * n_boxes;
   for (int p0 = 0; p0 < npairs; p0 += kScanBlockThreads) {
     const int pr = p0 + (int)threadIdx.x;
-    long long nch = 0;
+    long long nch = 0, nch_s = 0;  // items of the default size and of item_small entries
     int64_t first = 0, ntri = 0;
     bool list = false, culled = false, mirror = false;
     uint64_t rmask = 0;  // runs kept (the first 64)
@@ -786,6 +786,7 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
         }
         ntri = n;
         nch = (n + kCastTris - 1) / kCastTris;
+        nch_s = (n + item_small - 1) / item_small;
         if (!list && runs && !meshes) {  // whole mesh: only the runs the kept half prism may reach
           Bx = load_box(boxes, b);
           mirror = cast_mirror(Bx, w, centre[0]);
@@ -811,16 +812,30 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
           atomicOr(&s_rm[q], 1ull << r);
       }
       __syncthreads();
-      if (culled) {
+      if (culled) {  // items: the kept runs (each cut into pieces of item_small entries)
         const int w = pr - 3 * (pr / 3);
         rmask = s_rm[threadIdx.x];
-        long long c = __popcll(rmask);
-        for (long long r = 64; r < nr; ++r) c += span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1]) ? 1 : 0;
+        long long c = 0, cs = 0;
+        for (long long r = 0; r < nr; ++r)
+          if (r < 64 ? ((rmask >> r) & 1ull) != 0 : span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1])) {
+            ++c;
+            cs += (min((int64_t)kCastTris, ntri - r * kCastTris) + item_small - 1) / item_small;
+          }
         nch = c;
+        nch_s = cs;
       }
     }
     long long total = 0;
-    const long long ex = block_excl_scan(nch, wsum, total);
+    long long ex = block_excl_scan(nch, wsum, total);
+    // a call whose default items give fewer than split_below units takes items
+    // of item_small entries instead (more units for the compute units it would
+    // leave idle); decided on the whole call, so only with one block of pairs
+    int item_tris = kCastTris;
+    if (item_small < kCastTris && npairs <= kScanBlockThreads && total * nblk < split_below) {
+      item_tris = item_small;
+      nch = nch_s;
+      ex = block_excl_scan(nch, wsum, total);
+    }
     if (pr < npairs) {
       chunk_off[pr] = base + ex;
       if (culled) {
@@ -829,13 +844,16 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
         for (long long r = 0; c < nch; ++r) {
           if (r < 64 ? !((rmask >> r) & 1ull) : !span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1]))
             continue;
-          const long long it = base + ex + c++;
-          if (it >= item_cap) break;
-          ItemInfo ii;
-          ii.bw3 = pr;
-          ii.count = (int32_t)min((int64_t)kCastTris, ntri - r * kCastTris);
-          ii.first = -1 - r * kCastTris;
-          items[it] = ii;
+          const int64_t run_n = min((int64_t)kCastTris, ntri - r * kCastTris);
+          for (int64_t q = 0; q < run_n && c < nch; q += item_tris) {
+            const long long it = base + ex + c++;
+            if (it >= item_cap) break;
+            ItemInfo ii;
+            ii.bw3 = pr;
+            ii.count = (int32_t)min((int64_t)item_tris, run_n - q);
+            ii.first = -1 - (r * kCastTris + q);
+            items[it] = ii;
+          }
         }
       } else {
         for (long long c = 0; c < nch; ++c) {
@@ -843,8 +861,8 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
           if (it >= item_cap) break;
           ItemInfo ii;
           ii.bw3 = pr;
-          ii.count = (int32_t)min((int64_t)kCastTris, ntri - c * kCastTris);
-          ii.first = list ? first + c * kCastTris : -1 - c * kCastTris;
+          ii.count = (int32_t)min((int64_t)item_tris, ntri - c * item_tris);
+          ii.first = list ? first + c * item_tris : -1 - c * item_tris;
           items[it] = ii;
         }
       }
@@ -1573,9 +1591,10 @@ struct CallSizes {
   int64_t item_cap = 0, units = 0;
 };
 
-CallSizes call_sizes(int n_meshes, int n_boxes, int max_nt, int n_frames, int nt0, int nblk, int naxes) {
+CallSizes call_sizes(int n_meshes, int n_boxes, int max_nt, int n_frames, int nt0, int nblk, int naxes,
+                     int item_tris = kCastTris) {
   CallSizes c;
-  c.item_cap = (int64_t)n_boxes * naxes * std::max(1, (max_nt + kCastTris - 1) / kCastTris);
+  c.item_cap = (int64_t)n_boxes * naxes * std::max(1, (max_nt + item_tris - 1) / item_tris);
   c.units = c.item_cap * nblk;
   const int64_t fitems = n_frames ? 3ll * n_frames * ((std::max(nt0, 1) + kCullThreads - 1) / kCullThreads) : 0;
   size_t off = 0;
@@ -1652,7 +1671,10 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   const int n_frames = sf ? sf->n_frames : 0;
   const int naxes = (int)((mask & 1u) + ((mask >> 1) & 1u) + ((mask >> 2) & 1u));
   const BlockGeom bg = block_geom(R, block_rays_choice(params->block_rays));
-  const CallSizes cs = call_sizes(n_meshes, n_boxes, max_nt, n_frames, meshes[0].n_triangles, bg.nblk, naxes);
+  const int item_tris = ex && ex->item_tris ? ex->item_tris : kCastTris;
+  OBBV_ARG(item_tris % kSpanTris == 0 && kCastTris % item_tris == 0, "item_tris must be a multiple of 256 dividing 4608");
+  const CallSizes cs =
+      call_sizes(n_meshes, n_boxes, max_nt, n_frames, meshes[0].n_triangles, bg.nblk, naxes, item_tris);
 
   uint32_t* status = nullptr;
   if (ex && ex->status)
@@ -1788,7 +1810,7 @@ int outer_volume_run(const obbv_mesh* meshes, int32_t n_meshes, const obbv_box* 
   hipLaunchKernelGGL(k_box_chunks, dim3(1), dim3(kScanBlockThreads), 0, s, box_mesh, d_meshes, mh[0], n_meshes,
                      n_boxes, mask, boxes, sf ? sf->frames : nullptr, sf ? sf->box_frame : nullptr, n_frames,
                      (const int64_t*)d_foff, d_lcnt, seg, d_choff, status, box_key, R, params->seed, d_rframe, d_items,
-                     cs.item_cap, d_acc, d_ctl, runs, centre);
+                     cs.item_cap, d_acc, d_ctl, runs, centre, item_tris, ex ? ex->split_below : 0, bg.nblk);
   OBBV_HIP(hipGetLastError());
 
   ListArgs la;

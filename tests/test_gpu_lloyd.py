@@ -176,3 +176,26 @@ def test_flood_on_several_streams_gives_the_same_bits(api, monkeypatch):
         c = dict(out[flag]["counters"])
         assert c.pop("rounds") >= r1
         assert c == c1
+
+
+def test_smaller_items_for_calls_that_run_alone_give_the_same_bits(api, monkeypatch):
+    """Calls of a flood on one stream that would have few cast units take
+    smaller cast items (OBBV_ALONE_ITEM_TRIS entries below
+    OBBV_ALONE_SPLIT_BELOW units).  With every flood on one stream and the
+    threshold above any call's units, every call of the floods is split; the
+    hierarchies and counters are bit-identical to unsplit calls.  12,288
+    triangles: whole-mesh casts cut their span-culled runs into pieces, and
+    grouped casts their frame lists."""
+    V, F = synth.noisy_cube_sphere(32, seed=33)
+    Vt, Ft = _dev(V, F)
+    monkeypatch.setenv("OBBV_FLOOD_STREAMS", "1")
+    monkeypatch.setenv("OBBV_ALONE_SPLIT_BELOW", str(1 << 30))
+    out = {}
+    for items in ("0", "768", "1536", "2304"):
+        monkeypatch.setenv("OBBV_ALONE_ITEM_TRIS", items)
+        out[items] = api.build_hierarchy(Vt, Ft, levels=3, branching=4, iters=3, sweeps=1, R=32, seed=12,
+                                         pops_per_round=8)
+    for items in ("768", "1536", "2304"):
+        for k in ("boxes", "obv", "parent", "tri_node", "e"):
+            assert np.array_equal(out[items][k], out["0"][k]), (items, k)
+        assert out[items]["counters"] == out["0"]["counters"]
