@@ -786,7 +786,7 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
         }
         ntri = n;
         nch = (n + kCastTris - 1) / kCastTris;
-        nch_s = (n + item_small - 1) / item_small;
+        nch_s = item_small < kCastTris ? (n + item_small - 1) / item_small : nch;
         if (!list && runs && !meshes) {  // whole mesh: only the runs the kept half prism may reach
           Bx = load_box(boxes, b);
           mirror = cast_mirror(Bx, w, centre[0]);
@@ -815,14 +815,17 @@ k_box_chunks(const int32_t* __restrict__ box_mesh, const MeshDev* __restrict__ m
       if (culled) {  // items: the kept runs (each cut into pieces of item_small entries)
         const int w = pr - 3 * (pr / 3);
         rmask = s_rm[threadIdx.x];
-        long long c = 0, cs = 0;
-        for (long long r = 0; r < nr; ++r)
-          if (r < 64 ? ((rmask >> r) & 1ull) != 0 : span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1])) {
-            ++c;
-            cs += (min((int64_t)kCastTris, ntri - r * kCastTris) + item_small - 1) / item_small;
-          }
+        long long c = __popcll(rmask);
+        for (long long r = 64; r < nr; ++r) c += span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1]) ? 1 : 0;
         nch = c;
-        nch_s = cs;
+        nch_s = c;
+        if (item_small < kCastTris) {
+          long long cs = 0;
+          for (long long r = 0; r < nr; ++r)
+            if (r < 64 ? ((rmask >> r) & 1ull) != 0 : span_may_cast(Bx, w, mirror, runs[2 * r], runs[2 * r + 1]))
+              cs += ((int)min((int64_t)kCastTris, ntri - r * kCastTris) + item_small - 1) / item_small;
+          nch_s = cs;
+        }
       }
     }
     long long total = 0;
