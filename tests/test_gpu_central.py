@@ -82,6 +82,39 @@ def test_central_estimator_converges_and_flags(api):
     assert np.array_equal(again, est, equal_nan=True)
 
 
+def test_central_estimator_edge_cases(api):
+    """No boxes: nothing to do, no error.  A mesh without triangles: every cone
+    lies outside, and the estimate is the cones' total volume (the oracle's, a
+    little above V_box).  A flat box: exactly 0.  A triangle whose index is past
+    the vertex count is skipped and sets OBBV_STATUS_BAD_INDEX: the estimate is
+    the oracle's without that triangle."""
+    V, F = synth.icosphere(2)
+    c = np.array([[0.1, 0.0, 0.05], [0.1, 0.0, 0.05], [-0.3, 0.2, 0.1]], np.float32)
+    a = np.repeat(np.eye(3, dtype=np.float32)[None], 3, axis=0)
+    h = np.array([[0.5, 0.4, 0.3], [0.5, 0.0, 0.3], [0.6, 0.5, 0.7]], np.float32)
+    B = _t(synth.boxes_to_array(c, a, h))
+    m = 4
+    api.status()
+    none = api.outer_volume_central(_t(V), _t(F), B[:0], m)
+    assert none.shape == (0,) and api.status() == 0
+    empty = api.outer_volume_central(_t(V), _t(F[:0]), B, m).cpu().numpy()
+    assert api.status() == 0
+    for i in (0, 2):
+        want = central.obv(V, F[:0], c[i], a[i], h[i], m)
+        assert abs(empty[i] - want) <= TOL_REL * (exact.box_volume(h[i]) + 1.0), (i, empty[i], want)
+    assert empty[1] == 0.0
+    Fb = F.copy()
+    Fb[7, 1] = len(V) + 5
+    got = api.outer_volume_central(_t(V), _t(Fb), B, m).cpu().numpy()
+    assert api.status() & 0x2
+    keep = np.ones(len(F), bool)
+    keep[7] = False
+    for i in (0, 2):
+        want = central.obv(V, F[keep], c[i], a[i], h[i], m)
+        assert abs(got[i] - want) <= TOL_REL * (exact.box_volume(h[i]) + 1.0), (i, got[i], want)
+    assert got[1] == 0.0
+
+
 @pytest.mark.parametrize("m", [16, 24, 32])
 def test_central_culling_gives_the_same_bits(api, monkeypatch, m):
     """Skipping the triangles that lie outside a ray block's pyramid of
