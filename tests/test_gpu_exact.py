@@ -94,6 +94,23 @@ def test_exact_evaluator_special_boxes_and_determinism(api):
     assert np.array_equal(again, r[2], equal_nan=True)
 
 
+def test_exact_evaluator_empty_inputs(api):
+    """No boxes: nothing to do, no error.  A mesh without triangles: nothing
+    of any box is inside, so OBV = V_box = 8 h0 h1 h2 exactly, on every axis."""
+    V, F = synth.icosphere(1)
+    c, a, h = _boxes_around(V, 5, seed=3)
+    B = _t(synth.boxes_to_array(c, a, h))
+    api.status()
+    none = api.outer_volume_exact(_t(V), _t(F), B[:0], axis=0)
+    assert none.shape == (0,)
+    hd = h.astype(np.float64)
+    vb = 8.0 * hd[:, 0] * hd[:, 1] * hd[:, 2]
+    for w in range(3):
+        got = api.outer_volume_exact(_t(V), _t(F[:0]), B, axis=w).cpu().numpy()
+        assert np.array_equal(got, vb), w
+    assert api.status() == 0
+
+
 def test_exact_evaluator_flags_bad_indices(api):
     """A triangle index past the vertex count sets OBBV_STATUS_BAD_INDEX and the
     triangle counts as absent (the result equals the mesh without it)."""
