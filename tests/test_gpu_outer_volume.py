@@ -190,6 +190,10 @@ def test_inside_disjoint_zero_and_nan_boxes(api):
     assert abs(got[4] - ref[0]["obv"]) <= TOL_BOX * ref[0]["v_box"]
     empty = api.outer_volume(Vt, Ft, B[:0], 16, seed=1)
     assert empty.shape == (0,)
+    # a mesh without triangles: nothing is inside any box
+    bare = api.outer_volume(Vt, Ft[:0], B[:3], 16, seed=1).cpu().numpy()
+    assert bare[0] == 8 * np.prod(h[0].astype(np.float64)) and bare[1] == 8 * np.prod(h[1].astype(np.float64))
+    assert bare[2] == 0.0
     torch.cuda.synchronize()
 
 
