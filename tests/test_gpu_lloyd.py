@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 import synth
+from conftest import record_parity
 from oracle import lloyd as olloyd
 from oracle import raygrid
 
@@ -199,3 +200,50 @@ def test_smaller_items_for_calls_that_run_alone_give_the_same_bits(api, monkeypa
         for k in ("boxes", "obv", "parent", "tri_node", "e"):
             assert np.array_equal(out[items][k], out["0"][k]), (items, k)
         assert out[items]["counters"] == out["0"]["counters"]
+
+
+@pytest.mark.timeout(300)
+def test_bench_hierarchy_full_size_properties_and_sampled_parity(api):
+    """The timed workload at full size and in the same launch configuration
+    (noisy torus of 65,536 triangles, 4 levels of branching 4, 20 Lloyd
+    iterations per level, 2 sweeps, R = 128, 32 pops per round, floods on four
+    streams): Definition 1 structure, every node's box encloses its triangles,
+    e never increases, the returned OBVs are what the device gives for the
+    returned boxes (keys = node ids) and their Eq. 7 sum is e; three sampled
+    nodes (the root, one of level 1, one of level 3) match the oracle within
+    1e-5 of their box volume."""
+    import torch
+    V, F = synth.noisy_torus()
+    Vt, Ft = _dev(V, F)
+    L, b, R, seed = 4, 4, 128, 23
+    out = api.build_hierarchy(Vt, Ft, levels=L, branching=b, iters=20, sweeps=2, R=R, seed=seed,
+                              pops_per_round=32)
+    boxes, obv, parent, tri_node, e = out["boxes"], out["obv"], out["parent"], out["tri_node"], out["e"]
+    n_nodes = sum(b ** lv for lv in range(L))
+    assert boxes.shape == (n_nodes, 15)
+    assert np.all(tri_node[0] == 0) and np.all(tri_node >= 0)
+    for lv in range(1, L):
+        assert np.array_equal(parent[tri_node[lv]], tri_node[lv - 1])
+    used = np.array([(tri_node == n).any() for n in range(n_nodes)])
+    for node in np.nonzero(used)[0]:
+        tris = np.nonzero((tri_node == node).any(axis=0))[0]
+        bx = boxes[node].astype(np.float64)
+        idx = np.unique(F[tris])
+        loc = (V[idx].astype(np.float64) - bx[:3]) @ bx[3:12].reshape(3, 3).T
+        assert np.all(np.abs(loc) <= bx[12:] * (1 + 1e-6) + 1e-6), node
+    assert np.all(np.diff(e) <= 0)
+    key = torch.from_numpy(np.arange(n_nodes, dtype=np.int32)).cuda()
+    re = api.outer_volume(Vt, Ft, torch.from_numpy(boxes).cuda(), R, seed=seed, box_key=key).cpu().numpy()
+    assert np.allclose(re[used], obv[used], rtol=0, atol=1e-12)
+    level = np.concatenate([[lv] * b ** lv for lv in range(L)])
+    assert abs(np.sum((L - level) * obv) - e[-1]) <= 1e-9 * max(1.0, e[-1])
+    worst = 0.0
+    for node in (0, 1 + int(np.argmax(used[1:1 + b])), 1 + b + b * b + int(np.argmax(used[1 + b + b * b:]))):
+        bx = boxes[node].astype(np.float32)
+        ref = raygrid.raygrid_obv(V, F, bx[:3], bx[3:12].reshape(3, 3), bx[12:], R, seed, node)
+        vb = 8.0 * np.prod(bx[12:].astype(np.float64))
+        err = abs(obv[node] - ref["obv"]) / vb
+        worst = max(worst, err)
+        assert err <= 1e-5, (node, obv[node], ref["obv"])
+    record_parity({"test": "bench_hierarchy_full_size", "nodes": int(used.sum()), "e": float(e[-1]),
+                   "sampled_max_err_rel": worst})
